@@ -1,0 +1,231 @@
+/*
+ * ofdft.h - C ABI of libofdft.so, an orbital-free DFT energy/potential engine
+ * for one AMD MI355X (gfx950).
+ *
+ * The method is that of Shao, Jiang, Mi, Genova and Pavanello, "DFTpy: An
+ * efficient and object-oriented platform for orbital-free DFT simulations"
+ * (arXiv:2002.02985).  The library evaluates, on a periodic real-space grid,
+ *
+ *   E[rho] = T_TF + T_vW + T_NL + E_H + int v_ext rho  (+ E_ion)
+ *
+ * (eq. "efunc" without exchange-correlation) and its functional derivative
+ * v = dE/drho (eqs. "euler", "euler2a"), where T_NL is the Wang-Teter
+ * functional (eq. "WT") or the density-dependent-kernel functional evaluated
+ * with linear splines over k_F knots (steps s1-s4 of Section
+ * "New-generation nonlocal KEDFs"), and minimises E over phi = sqrt(rho) at
+ * fixed electron count (eq. "euler2", Section "Density optimization
+ * strategies").
+ *
+ * Conventions
+ *   Units: Hartree atomic units (Ha, Bohr).
+ *   Grid: n[0] x n[1] x n[2] points, C order (index i2 fastest); point
+ *     (i0,i1,i2) sits at r = sum_d (i_d / n_d) a_d, a_d = lattice[d][:].
+ *     Every n[d] must be one of the supported FFT lengths (products of 2 and
+ *     3 listed by ofdft_supported_length()), n[2] even.
+ *   Integrals: int f = (V/N) sum_r f(r).  Fourier coefficients:
+ *     f(G) = (1/N) sum_r f(r) exp(-i G.r); the inverse of a half spectrum is
+ *     Re sum_half c(m2) X exp(i G.r), c = 1 on the m2 = 0 and m2 = n2/2
+ *     planes, 2 elsewhere; Nyquist frequencies take the negative sign.
+ *   Fields on the host are double, C order.  Fields passed as device
+ *     pointers (the _dev calls) have the grid's field type: double for
+ *     OFDFT_FP64 grids, float for OFDFT_MIXED grids.
+ *
+ * Ownership and errors
+ *   Handles are created and owned by the library and released by the
+ *   matching _destroy call (NULL is accepted and ignored).  Host arrays
+ *   belong to the caller; they are read or written during the call only and
+ *   never retained.  Device pointers are borrowed for the duration of the
+ *   call on the given stream; the call returns after the stream work it
+ *   enqueued has completed.  A grid handle is not thread-safe.
+ *   No function aborts: each returns an ofdft_status, and
+ *   ofdft_last_error() gives a message for the calling thread.
+ *   Non-finite or negative densities give OFDFT_EINVAL.
+ */
+#ifndef OFDFT_H
+#define OFDFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OFDFT_ABI_VERSION 1
+
+typedef struct ofdft_ctx ofdft_ctx;
+typedef struct ofdft_grid ofdft_grid;
+
+typedef enum {
+    OFDFT_OK = 0,
+    OFDFT_PENDING = 1,
+    OFDFT_EINVAL = -1,      /* bad argument, unsupported size, non-finite input */
+    OFDFT_ENOMEM = -2,      /* device or host allocation failed                 */
+    OFDFT_EDEVICE = -3,     /* HIP runtime error                                */
+    OFDFT_ENOCONV = -4,     /* iteration budget exhausted (result still filled) */
+    OFDFT_ECANCELLED = -5,
+    OFDFT_ENOTFOUND = -6
+} ofdft_status;
+
+/* energy terms (bitmask) */
+enum {
+    OFDFT_TERM_TF = 1,        /* Thomas-Fermi  C_TF int rho^(5/3)                    */
+    OFDFT_TERM_VW = 2,        /* von Weizsaecker  (lambda/2) int |grad sqrt(rho)|^2  */
+    OFDFT_TERM_HARTREE = 4,   /* 2 pi V sum_{G!=0} |rho(G)|^2 / G^2                  */
+    OFDFT_TERM_EXT = 8,       /* int v_ext rho with the local pseudopotential, + E_ion */
+    OFDFT_TERM_WT = 16,       /* Wang-Teter nonlocal functional (eqs. "nl2", "WT")    */
+    OFDFT_TERM_SPLINE = 32    /* density-dependent kernel with k_F splines (s1-s4)    */
+};
+enum { OFDFT_KNOTS_LOG = 0, OFDFT_KNOTS_LIN = 1 };
+enum { OFDFT_NL_S3S4 = 0, OFDFT_NL_EXACT = 1 };
+enum { OFDFT_FP64 = 0, OFDFT_MIXED = 1 };
+
+/* Cell: lattice vectors as rows (Bohr), grid, atoms.  pos is natoms x 3
+ * Cartesian Bohr; species[a] indexes Z[] (valence charge) and rc[] (radius of
+ * the local pseudopotential v(G) = -4 pi Z exp(-G^2 rc^2 / 4) / G^2, i.e.
+ * -Z erf(r/rc)/r, with the non-Coulomb G = 0 value pi Z rc^2). */
+typedef struct {
+    double lattice[3][3];
+    int32_t n[3];
+    int32_t natoms;
+    const double *pos;
+    const int32_t *species;
+    int32_t nspecies;
+    const double *Z;
+    const double *rc;
+    double nelec;
+} ofdft_cell_desc;
+
+/* Functional.  alpha and beta are the exponents of eq. "nl2"; the GPU path
+ * requires alpha == beta.  kf_wt <= 0 selects (3 pi^2 nelec / V)^(1/3) for
+ * the Wang-Teter kernel.  Spline knots (step s1): nk values from kf_min to
+ * kf_max, geometric (LOG) or arithmetic (LIN), both ends included.
+ * nl_mode S3S4 interpolates the per-knot potentials (steps s3, s4 as
+ * printed); EXACT returns the functional derivative of the spline energy.
+ * rho_floor (default 1e-12) bounds rho^(alpha-1) and 1/sqrt(rho). */
+typedef struct {
+    uint32_t terms;
+    double lambda_vw;
+    double alpha, beta;
+    double kf_wt;
+    int32_t nk;
+    double kf_min, kf_max;
+    int32_t knot_spacing;
+    int32_t nl_mode;
+    int32_t precision;
+    double rho_floor;
+} ofdft_functional_desc;
+
+/* Energies (Ha).  mu = int v rho / int rho; resid_norm = sqrt(mean(R^2)) with
+ * R = dE/dphi - 2 mu phi (the residual of eq. "euler2"). */
+typedef struct {
+    double e_tf, e_vw, e_h, e_ext, e_nl, e_ion, e_total;
+    double mu, nelec_int, resid_norm;
+} ofdft_energy;
+
+int ofdft_abi_version(void);
+const char *ofdft_last_error(void);
+/* 1 if n is an FFT length the library has kernels for, else 0. */
+int ofdft_supported_length(int32_t n);
+
+ofdft_status ofdft_ctx_create(int device, ofdft_ctx **out);
+void ofdft_ctx_destroy(ofdft_ctx *ctx);
+
+/* Builds the grid: reciprocal vectors, twiddle tables, the ionic structure
+ * factor and v_ext(G) (exact direct sum over atoms, separable phases), the
+ * Ewald energy E_ion, and device buffers for one density.  The descriptors
+ * are copied. */
+ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
+                               const ofdft_functional_desc *func, ofdft_grid **out);
+void ofdft_grid_destroy(ofdft_grid *grid);
+/* Pre-allocates workspace for batched calls of up to nbatch densities. */
+ofdft_status ofdft_grid_reserve(ofdft_grid *grid, int32_t nbatch);
+/* Bytes of device memory the grid currently holds. */
+uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid);
+
+/* Resident density (N doubles, C order), kept on the device in the grid's
+ * field type; used by energy_potential(NULL, ...), forces and optimize. */
+ofdft_status ofdft_set_density(ofdft_grid *grid, const double *rho_host);
+ofdft_status ofdft_get_density(ofdft_grid *grid, double *rho_host);
+
+/* Energy and potential for rho (host, N doubles) or, if rho is NULL, the
+ * resident density.  v_out (host, N doubles, may be NULL) receives
+ * v = dE/drho; e_out must not be NULL. */
+ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host,
+                                    double *v_out_host, ofdft_energy *e_out);
+
+/* Device variant: d_rho and d_v (may be NULL) are device arrays of N values
+ * of the grid's field type, hip_stream a hipStream_t (NULL = the context's
+ * own stream). */
+ofdft_status ofdft_energy_potential_dev(ofdft_grid *grid, const void *d_rho, void *d_v,
+                                        void *hip_stream, ofdft_energy *e_out);
+
+/* Batched device variant: nbatch densities of the same cell, stored
+ * back to back (nbatch x N values); d_v likewise (may be NULL);
+ * e_out has nbatch entries.  Every step of the evaluation runs for the whole
+ * batch in each kernel launch. */
+ofdft_status ofdft_energy_potential_batch_dev(ofdft_grid *grid, int32_t nbatch,
+                                              const void *d_rho, void *d_v,
+                                              void *hip_stream, ofdft_energy *e_out);
+
+/* The 3D FFT pair on the grid (the transforms behind every reciprocal-space
+ * term): forward d_out = r2c(d_in) as n0 x n1 x (n2/2+1) interleaved complex
+ * values, normalised by 1/N; inverse d_out = Re sum_half c X exp(iG.r)
+ * (unnormalised).  Device arrays of the grid's field type, nbatch fields. */
+ofdft_status ofdft_fft_r2c_dev(ofdft_grid *grid, int32_t nbatch, const void *d_in,
+                               void *d_out, void *hip_stream);
+ofdft_status ofdft_fft_c2r_dev(ofdft_grid *grid, int32_t nbatch, const void *d_in,
+                               void *d_out, void *hip_stream);
+
+/* Forces on the ions (Ha/Bohr, natoms x 3 doubles) for the resident density:
+ * Hellmann-Feynman electron-ion term -d/dR int v_ext rho at fixed rho plus
+ * the Ewald ion-ion term. */
+ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host);
+
+/* Density optimisation (Section "Density optimization strategies"):
+ * nonlinear conjugate gradients (Polak-Ribiere, restarted on loss of
+ * descent) on phi = sqrt(rho) with the update phi cos(t) + p sin(t),
+ * p orthogonal to phi and normalised to N_e, and a strong-Wolfe line search
+ * over t in FP64.  Starts from the resident density (warm start) and leaves
+ * the optimised density resident.  Converged when sqrt(mean(R^2)) < tol;
+ * OFDFT_ENOCONV (with the result filled in) when max_iter is reached. */
+typedef struct {
+    double tol;
+    int32_t max_iter;
+    int32_t method;   /* 0: CG (Polak-Ribiere+) */
+    int32_t warm;     /* reserved */
+} ofdft_opt_params;
+typedef struct {
+    ofdft_energy e;
+    int32_t iters, evals;
+    double final_resid;
+} ofdft_opt_result;
+ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params,
+                            ofdft_opt_result *result);
+
+/* Per-pass timing of the evaluation pipeline (a profiling aid): when
+ * enabled, every kernel launch of the passes below is bracketed by HIP events
+ * recorded on the stream it is launched on, and the elapsed times are summed
+ * per pass.  Enabling resets the counters. */
+enum {
+    OFDFT_PASS_ROW_FWD = 0,   /* prologue + axis-2 r2c                          */
+    OFDFT_PASS_COL1_FWD,      /* axis-1 forward c2c                             */
+    OFDFT_PASS_COL0_G,        /* axis-0 c2c with the reciprocal-space terms     */
+    OFDFT_PASS_COL1_INV,      /* axis-1 inverse c2c                             */
+    OFDFT_PASS_ROW_INV,       /* axis-2 c2r + combine of the potential          */
+    OFDFT_PASS_KNOT_INV,      /* spline: omega_i multiply + axis-0 inverse      */
+    OFDFT_PASS_KNOT_COL1,     /* spline: axis-1 inverse of the knot spectra     */
+    OFDFT_PASS_KNOT_ROW,      /* spline: axis-2 c2r + interpolation over k_F    */
+    OFDFT_PASS_EXACT_FWD,     /* spline EXACT: transforms of rho^a L_i          */
+    OFDFT_PASS_EXACT_ACC,     /* spline EXACT: sum_i omega_i F[rho^a L_i]       */
+    OFDFT_PASS_FINALIZE,      /* FP64 reductions                                */
+    OFDFT_PASS_OTHER,         /* optimiser vector kernels                       */
+    OFDFT_NPASS
+};
+ofdft_status ofdft_profile_enable(ofdft_grid *grid, int32_t on);
+ofdft_status ofdft_profile_read(ofdft_grid *grid, int32_t pass, double *total_ms,
+                                int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFDFT_H */

@@ -1,0 +1,1389 @@
+// C ABI of libofdft.so: handles, grid set-up, the evaluation pipeline, forces
+// and the density optimiser.  Host code; all field work runs in the HIP
+// kernels declared in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ofdft.h"
+#include "kernels.hpp"
+
+using namespace ofdft;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+static ofdft_status fail(ofdft_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? OFDFT_ENOMEM : OFDFT_EDEVICE,             \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+#define ST_TRY(expr)                                                                          \
+    do {                                                                                      \
+        ofdft_status s_ = (expr);                                                             \
+        if (s_ != OFDFT_OK) return s_;                                                        \
+    } while (0)
+
+static const double PI = 3.14159265358979323846264338327950288;
+static const double C_TF = 2.8712340001881918;
+
+// ---------------------------------------------------------------- handles
+struct ofdft_ctx {
+    int device;
+    hipStream_t stream;
+};
+
+enum Pass {
+    PS_ROW_FWD = 0,
+    PS_COL1_FWD,
+    PS_COL0_G,
+    PS_COL1_INV,
+    PS_ROW_INV,
+    PS_KNOT_INV,
+    PS_KNOT_COL1,
+    PS_KNOT_ROW,
+    PS_EXACT_FWD,
+    PS_EXACT_ACC,
+    PS_FINALIZE,
+    PS_OTHER,
+    NPASS
+};
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;       // pairs
+    std::vector<int> kind;
+    double ms[NPASS] = {0};
+    long long count[NPASS] = {0};
+};
+
+struct ofdft_grid {
+    ofdft_ctx *ctx = nullptr;
+    // copies of the descriptors
+    double lattice[3][3];
+    int n[3];
+    int natoms = 0;
+    std::vector<double> pos;
+    std::vector<int> species;
+    std::vector<int> species_order;   // sorted position -> original atom index
+    std::vector<double> Z, rc;
+    double nelec = 0;
+    ofdft_functional_desc func;
+    bool fp64 = true;
+    size_t fsz = 8;
+    Geom geom;
+    double V = 0, dv = 0;
+    Knots knots;
+    double kf_wt = 0;
+    double e_ion = 0;
+    // device tables
+    void *tw0 = nullptr, *tw1 = nullptr, *twM = nullptr, *twN = nullptr;
+    void *vext = nullptr;
+    double *ph0 = nullptr, *ph1 = nullptr, *ph2 = nullptr;
+    int *d_spec_off = nullptr, *d_atom_species = nullptr;
+    double *d_Z = nullptr, *d_rc = nullptr;
+    // workspace
+    int cap = 0;
+    void *spec = nullptr;    // 4 * cap * Nh complex
+    void *kspec = nullptr;   // MAXKB * cap * Nh complex (spline)
+    void *acc1 = nullptr, *acc2 = nullptr;   // cap * N
+    void *stage_in = nullptr, *stage_out = nullptr;   // cap * N (host API staging)
+    double *part = nullptr;
+    int pstride = 0;
+    double *sums = nullptr;
+    int *d_count = nullptr;
+    double *h_sums = nullptr;   // pinned
+    // resident density and optimiser vectors (N each)
+    void *rho = nullptr;
+    void *opt[9] = {nullptr};
+    size_t bytes = 0;
+    Timer timer;
+};
+
+// ---------------------------------------------------------------- helpers
+static bool is_supported(int L) { return length_supported(L); }
+
+static ofdft_status dmalloc(ofdft_grid *g, void **p, size_t bytes)
+{
+    if (*p) return OFDFT_OK;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(OFDFT_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " +
+                                      hipGetErrorString(e));
+    }
+    g->bytes += bytes;
+    return OFDFT_OK;
+}
+
+static void dfree(void *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+static std::vector<T> to_type(const double *src, size_t n)
+{
+    std::vector<T> v(n);
+    for (size_t i = 0; i < n; ++i) v[i] = (T)src[i];
+    return v;
+}
+
+// twiddle table exp(-2 pi i n / L) for n < cnt, built in FP64, stored as field type
+static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt)
+{
+    std::vector<double> t(2 * (size_t)cnt);
+    for (int i = 0; i < cnt; ++i) {
+        const double a = 2.0 * PI * (double)i / (double)L;
+        t[2 * i] = std::cos(a);
+        t[2 * i + 1] = -std::sin(a);
+    }
+    ST_TRY(dmalloc(g, dst, (size_t)cnt * 2 * g->fsz));
+    if (g->fp64) {
+        HIP_TRY(hipMemcpy(*dst, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+    } else {
+        auto f = to_type<float>(t.data(), t.size());
+        HIP_TRY(hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    }
+    return OFDFT_OK;
+}
+
+static int freq_host(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// ---------------------------------------------------------------- Ewald (host, FP64)
+// E_ion = 1/2 sum' Z_a Z_b erfc(a r)/r + (2 pi / V) sum_{G!=0} e^{-G^2/4a^2}/G^2 |S(G)|^2
+//         - a/sqrt(pi) sum Z^2 - pi Q^2 / (2 V a^2),  S(G) = sum Z_a e^{iG.R_a}
+// and its forces; point charges in a neutralising background.
+struct EwaldSetup {
+    double a, rcut, gcut;
+    std::vector<double> L;   // lattice translations (x,y,z) within reach
+    std::vector<double> G;   // reciprocal vectors (x,y,z,|G|^2), G != 0, |G| <= gcut
+};
+
+static EwaldSetup ewald_setup(const ofdft_grid *g)
+{
+    EwaldSetup e;
+    const int na = g->natoms;
+    e.a = std::sqrt(PI) * std::pow((double)std::max(na, 1) / (g->V * g->V), 1.0 / 6.0) * 2.0;
+    e.rcut = 6.6 / e.a;
+    e.gcut = 2.0 * e.a * 6.6;
+    // images: planes of lattice points perpendicular to b_d are 2 pi/|b_d| apart
+    int nmax[3], gmax[3];
+    for (int d = 0; d < 3; ++d) {
+        const double bn = std::sqrt(g->geom.b[d][0] * g->geom.b[d][0] + g->geom.b[d][1] * g->geom.b[d][1] +
+                                    g->geom.b[d][2] * g->geom.b[d][2]);
+        const double an = std::sqrt(g->lattice[d][0] * g->lattice[d][0] + g->lattice[d][1] * g->lattice[d][1] +
+                                    g->lattice[d][2] * g->lattice[d][2]);
+        nmax[d] = (int)std::ceil(e.rcut * bn / (2 * PI)) + 1;
+        gmax[d] = (int)std::ceil(e.gcut * an / (2 * PI)) + 1;
+    }
+    for (int i = -nmax[0]; i <= nmax[0]; ++i)
+        for (int j = -nmax[1]; j <= nmax[1]; ++j)
+            for (int k = -nmax[2]; k <= nmax[2]; ++k)
+                for (int c = 0; c < 3; ++c)
+                    e.L.push_back(i * g->lattice[0][c] + j * g->lattice[1][c] + k * g->lattice[2][c]);
+    for (int i = -gmax[0]; i <= gmax[0]; ++i)
+        for (int j = -gmax[1]; j <= gmax[1]; ++j)
+            for (int k = -gmax[2]; k <= gmax[2]; ++k) {
+                if (!i && !j && !k) continue;
+                double v[3];
+                for (int c = 0; c < 3; ++c)
+                    v[c] = i * g->geom.b[0][c] + j * g->geom.b[1][c] + k * g->geom.b[2][c];
+                const double g2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                if (g2 > e.gcut * e.gcut) continue;
+                e.G.insert(e.G.end(), {v[0], v[1], v[2], g2});
+            }
+    return e;
+}
+
+static double ewald_energy_host(const ofdft_grid *g, std::vector<double> *forces)
+{
+    const int na = g->natoms;
+    if (forces) forces->assign(3 * (size_t)na, 0.0);
+    if (na == 0) return 0.0;
+    const EwaldSetup e = ewald_setup(g);
+    const double a = e.a;
+    std::vector<double> q(na);
+    double Q = 0, Q2 = 0;
+    for (int i = 0; i < na; ++i) {
+        q[i] = g->Z[g->species[i]];
+        Q += q[i];
+        Q2 += q[i] * q[i];
+    }
+    const size_t nL = e.L.size() / 3;
+    double ereal = 0.0;
+    for (int i = 0; i < na; ++i) {
+        for (int j = 0; j < na; ++j) {
+            const double dx0 = g->pos[3 * i] - g->pos[3 * j];
+            const double dy0 = g->pos[3 * i + 1] - g->pos[3 * j + 1];
+            const double dz0 = g->pos[3 * i + 2] - g->pos[3 * j + 2];
+            for (size_t l = 0; l < nL; ++l) {
+                const double dx = dx0 - e.L[3 * l], dy = dy0 - e.L[3 * l + 1], dz = dz0 - e.L[3 * l + 2];
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < 1e-20 || r2 > e.rcut * e.rcut) continue;
+                const double r = std::sqrt(r2);
+                const double ec = std::erfc(a * r);
+                ereal += 0.5 * q[i] * q[j] * ec / r;
+                if (forces) {
+                    const double mag = q[i] * q[j] *
+                                       (ec / r2 + 2.0 * a / std::sqrt(PI) * std::exp(-a * a * r2) / r) / r;
+                    (*forces)[3 * i] += mag * dx;
+                    (*forces)[3 * i + 1] += mag * dy;
+                    (*forces)[3 * i + 2] += mag * dz;
+                }
+            }
+        }
+    }
+    double erec = 0.0;
+    const size_t nG = e.G.size() / 4;
+    std::vector<double> cr(na), ci(na);
+    for (size_t k = 0; k < nG; ++k) {
+        const double *G = &e.G[4 * k];
+        double sr = 0, si = 0;
+        for (int i = 0; i < na; ++i) {
+            const double ph = G[0] * g->pos[3 * i] + G[1] * g->pos[3 * i + 1] + G[2] * g->pos[3 * i + 2];
+            cr[i] = std::cos(ph);
+            ci[i] = std::sin(ph);
+            sr += q[i] * cr[i];
+            si += q[i] * ci[i];
+        }
+        const double w = std::exp(-G[3] / (4 * a * a)) / G[3];
+        erec += 2.0 * PI / g->V * w * (sr * sr + si * si);
+        if (forces) {
+            // F_i = (4 pi / V) w q_i G Im[e^{iG.R_i} conj S]
+            for (int i = 0; i < na; ++i) {
+                const double im = ci[i] * sr - cr[i] * si;
+                const double f = 4.0 * PI / g->V * w * q[i] * im;
+                (*forces)[3 * i] += f * G[0];
+                (*forces)[3 * i + 1] += f * G[1];
+                (*forces)[3 * i + 2] += f * G[2];
+            }
+        }
+    }
+    return ereal + erec - a / std::sqrt(PI) * Q2 - PI * Q * Q / (2 * g->V * a * a);
+}
+
+// ---------------------------------------------------------------- timing
+static void timer_start(ofdft_grid *g, hipStream_t s, int kind, hipEvent_t &e0)
+{
+    if (!g->timer.on) return;
+    (void)kind;
+    (void)hipEventCreate(&e0);
+    (void)hipEventRecord(e0, s);
+}
+
+static void timer_stop(ofdft_grid *g, hipStream_t s, int kind, hipEvent_t e0)
+{
+    if (!g->timer.on) return;
+    hipEvent_t e1;
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e1, s);
+    g->timer.ev.push_back(e0);
+    g->timer.ev.push_back(e1);
+    g->timer.kind.push_back(kind);
+}
+
+static void timer_collect(ofdft_grid *g)
+{
+    Timer &t = g->timer;
+    for (size_t i = 0; i < t.kind.size(); ++i) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(t.ev[2 * i + 1]);
+        if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) == hipSuccess) {
+            t.ms[t.kind[i]] += ms;
+            t.count[t.kind[i]] += 1;
+        }
+        (void)hipEventDestroy(t.ev[2 * i]);
+        (void)hipEventDestroy(t.ev[2 * i + 1]);
+    }
+    t.ev.clear();
+    t.kind.clear();
+}
+
+#define TIMED(kind, stmt)                                                                     \
+    do {                                                                                      \
+        hipEvent_t e0_ = nullptr;                                                             \
+        timer_start(g, s, kind, e0_);                                                         \
+        hipError_t r_ = (stmt);                                                               \
+        timer_stop(g, s, kind, e0_);                                                          \
+        if (r_ != hipSuccess)                                                                 \
+            return fail(OFDFT_EDEVICE, std::string(#stmt) + ": " + hipGetErrorString(r_));    \
+    } while (0)
+
+// ---------------------------------------------------------------- workspace
+static int max_pstride(const ofdft_grid *g)
+{
+    const Geom &G = g->geom;
+    int rb, c0, c1;
+    if (g->fp64) {
+        rb = row_blocks<double>(G);
+        c0 = col_blocks<double>(G.n0, (long long)G.n1 * G.n2h);
+        c1 = col_blocks<double>(G.n1, (long long)G.n0 * G.n2h);
+    } else {
+        rb = row_blocks<float>(G);
+        c0 = col_blocks<float>(G.n0, (long long)G.n1 * G.n2h);
+        c1 = col_blocks<float>(G.n1, (long long)G.n0 * G.n2h);
+    }
+    return std::max({rb, c0, c1, dots_blocks(G.N), 1});
+}
+
+static ofdft_status reserve(ofdft_grid *g, int nb)
+{
+    if (nb <= g->cap) return OFDFT_OK;
+    // drop the old workspace
+    dfree(g->spec);
+    dfree(g->kspec);
+    dfree(g->acc1);
+    dfree(g->acc2);
+    dfree(g->stage_in);
+    dfree(g->stage_out);
+    dfree(reinterpret_cast<void *&>(g->part));
+    dfree(reinterpret_cast<void *&>(g->sums));
+    if (g->h_sums) (void)hipHostFree(g->h_sums);
+    g->h_sums = nullptr;
+    g->bytes = 0;   // recounted below together with the fixed tables
+    const Geom &G = g->geom;
+    const size_t cbytes = 2 * g->fsz;
+    const bool spline = g->func.terms & OFDFT_TERM_SPLINE;
+    ST_TRY(dmalloc(g, &g->spec, 4 * (size_t)nb * G.Nh * cbytes));
+    if (spline) {
+        ST_TRY(dmalloc(g, &g->kspec, (size_t)MAXKB * nb * G.Nh * cbytes));
+        ST_TRY(dmalloc(g, &g->acc1, (size_t)nb * G.N * g->fsz));
+        if (g->func.nl_mode == OFDFT_NL_EXACT)
+            ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
+    }
+    g->pstride = max_pstride(g);
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->part),
+                   (size_t)nb * NSLOT * g->pstride * sizeof(double)));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->sums), (size_t)nb * NSLOT * sizeof(double)));
+    HIP_TRY(hipHostMalloc((void **)&g->h_sums, (size_t)nb * NSLOT * sizeof(double)));
+    g->cap = nb;
+    return OFDFT_OK;
+}
+
+// ---------------------------------------------------------------- evaluation
+struct Layout {
+    int s_rho = -1, s_phi = -1, s_rhob = -1, s_h = -1;
+    int nfwd = 0, ninv = 0;
+};
+
+static Layout layout_of(const ofdft_grid *g)
+{
+    Layout l;
+    const uint32_t t = g->func.terms;
+    int idx = 0;
+    if (t & (OFDFT_TERM_HARTREE | OFDFT_TERM_EXT)) l.s_rho = idx++;
+    if (t & OFDFT_TERM_VW) l.s_phi = idx++;
+    if (t & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) l.s_rhob = idx++;
+    l.nfwd = idx;
+    l.ninv = (t & OFDFT_TERM_SPLINE) ? idx - 1 : idx;
+    if ((t & OFDFT_TERM_SPLINE) && g->func.nl_mode == OFDFT_NL_EXACT) l.s_h = idx++;
+    return l;
+}
+
+template <typename T>
+static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data, int nfb, int nbatch,
+                             int inv, const int *ops, int kind)
+{
+    const Geom &G = g->geom;
+    ColArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.data = data;
+    a.src = data;
+    a.fstride = G.Nh;
+    a.nbatch = nbatch;
+    a.inv = inv;
+    a.g = G;
+    a.part = g->part;
+    a.pstride = g->pstride;
+    a.vext = g->vext;
+    a.use_h = (g->func.terms & OFDFT_TERM_HARTREE) ? 1 : 0;
+    a.use_ext = (g->func.terms & OFDFT_TERM_EXT) ? 1 : 0;
+    a.lambda_vw = g->func.lambda_vw;
+    a.kf_wt = g->kf_wt;
+    int L;
+    if (axis == 1) {
+        L = G.n1;
+        a.ncols = (long long)G.n0 * G.n2h;
+        a.inner = G.n2h;
+        a.outer_stride = (long long)G.n1 * G.n2h;
+        a.elem_stride = G.n2h;
+        a.tw = g->tw1;
+    } else {
+        L = G.n0;
+        a.ncols = (long long)G.n1 * G.n2h;
+        a.inner = a.ncols;
+        a.outer_stride = 0;
+        a.elem_stride = (long long)G.n1 * G.n2h;
+        a.tw = g->tw0;
+        if (ops)
+            for (int f = 0; f < 4; ++f) a.op[f] = ops[f];   // ops has 4 entries
+    }
+    int nbk = 0;
+    TIMED(kind, launch_col<T>(L, nfb, a, nbk, s));
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
+                              void *d_g, hipStream_t s, ofdft_energy *e_out, double *bad_out)
+{
+    ST_TRY(reserve(g, nb));
+    const Geom &G = g->geom;
+    const Layout l = layout_of(g);
+    const uint32_t terms = g->func.terms;
+    const bool spline = terms & OFDFT_TERM_SPLINE;
+    const bool exact = spline && g->func.nl_mode == OFDFT_NL_EXACT;
+    const long long fs = (long long)nb * G.Nh;   // stride between field slots
+    char *spec = (char *)g->spec;
+    const size_t cb = 2 * sizeof(T);
+    auto slot_ptr = [&](int sl) { return (void *)(spec + (size_t)sl * fs * cb); };
+
+    // 1. prologue + axis-2 r2c of rho, phi, rho^beta
+    RowFwdArgs rf;
+    std::memset(&rf, 0, sizeof(rf));
+    rf.in = d_in;
+    rf.out = g->spec;
+    rf.out_fstride = fs;
+    rf.nfields = l.nfwd;
+    if (l.s_rho >= 0) rf.kind[l.s_rho] = FK_RHO;
+    if (l.s_phi >= 0) rf.kind[l.s_phi] = FK_PHI;
+    if (l.s_rhob >= 0) rf.kind[l.s_rhob] = FK_RHOB;
+    rf.in_is_phi = in_is_phi;
+    rf.beta = g->func.beta;
+    rf.alpha = g->func.alpha;
+    rf.knots = g->knots;
+    rf.partials = 1;
+    rf.part = g->part;
+    rf.pstride = g->pstride;
+    rf.twM = g->twM;
+    rf.twN = g->twN;
+    int nb_row = 0;
+    TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
+
+    int nb_col0 = 0;
+    if (l.nfwd > 0) {
+        // 2. axis 1 forward
+        ST_TRY(col_pass<T>(g, s, 1, g->spec, l.nfwd * nb, nb, 0, nullptr, PS_COL1_FWD));
+        // 3. axis 0: forward, reciprocal-space term, inverse
+        int ops[4] = {0, 0, 0, 0};
+        if (l.s_rho >= 0) ops[l.s_rho] = GO_HEXT;
+        if (l.s_phi >= 0) ops[l.s_phi] = GO_VW;
+        if (l.s_rhob >= 0) ops[l.s_rhob] = spline ? GO_SCALE : GO_WT;
+        ST_TRY(col_pass<T>(g, s, 0, g->spec, l.nfwd * nb, nb, 0, ops, PS_COL0_G));
+        nb_col0 = col_blocks<T>(G.n0, (long long)G.n1 * G.n2h);
+    }
+
+    // spline loop over knot batches (steps s2-s4)
+    if (spline) {
+        const int nk = g->knots.nk;
+        for (int k0 = 0; k0 < nk; k0 += MAXKB) {
+            const int K = std::min(MAXKB, nk - k0);
+            KnotArgs ka;
+            std::memset(&ka, 0, sizeof(ka));
+            ka.src = slot_ptr(l.s_rhob);
+            ka.dst = g->kspec;
+            ka.fstride = G.Nh;
+            ka.ncols = (long long)G.n1 * G.n2h;
+            ka.knot0 = k0;
+            ka.K = K;
+            ka.nbatch = nb;
+            ka.knots = g->knots;
+            ka.tw = g->tw0;
+            ka.g = G;
+            TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
+            ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1));
+            RowInvArgs ri;
+            std::memset(&ri, 0, sizeof(ri));
+            ri.spec = g->kspec;
+            ri.spec_fstride = fs;
+            ri.nfields = K;
+            ri.mode = EP_KNOTS;
+            ri.in = d_in;
+            ri.in_is_phi = in_is_phi;
+            ri.exact = exact;
+            ri.spline = 1;
+            ri.acc1 = g->acc1;
+            ri.acc2 = g->acc2;
+            ri.acc_init = (k0 == 0);
+            ri.knot0 = k0;
+            ri.knots = g->knots;
+            ri.nbatch = nb;
+            ri.twM = g->twM;
+            ri.twN = g->twN;
+            ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
+            int nbk = 0;
+            TIMED(PS_KNOT_ROW, launch_row_inv<T>(G, ri, nbk, s));
+            if (exact) {
+                // f_i = rho^a L_i(k~): r2c, axis 1, then axis 0 with omega_i, summed into H
+                RowFwdArgs ef = rf;
+                ef.out = g->kspec;
+                ef.out_fstride = fs;
+                ef.nfields = K;
+                for (int f = 0; f < K; ++f) ef.kind[f] = FK_KNOT;
+                ef.knot0 = k0;
+                ef.partials = 0;
+                int nbe = 0;
+                TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
+                ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD));
+                KnotArgs kc = ka;
+                kc.src = g->kspec;
+                kc.dst = slot_ptr(l.s_h);
+                kc.accumulate = (k0 > 0);
+                TIMED(PS_EXACT_ACC, launch_knot_acc<T>(kc, s));
+            }
+        }
+        if (exact) {
+            ST_TRY(col_pass<T>(g, s, 0, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
+            ST_TRY(col_pass<T>(g, s, 1, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
+        }
+    }
+
+    // 4. axis 1 inverse of the fields that return to real space
+    if (l.ninv > 0) ST_TRY(col_pass<T>(g, s, 1, g->spec, l.ninv * nb, nb, 1, nullptr, PS_COL1_INV));
+
+    // 5. axis-2 c2r and the final combine
+    RowInvArgs rc;
+    std::memset(&rc, 0, sizeof(rc));
+    rc.spec = g->spec;
+    rc.spec_fstride = fs;
+    rc.mode = EP_COMBINE;
+    rc.in = d_in;
+    rc.in_is_phi = in_is_phi;
+    rc.fld_hext = l.s_rho;
+    rc.fld_vw = l.s_phi;
+    rc.fld_wt = (terms & OFDFT_TERM_WT) ? l.s_rhob : -1;
+    rc.fld_a = l.s_h;
+    rc.use_tf = (terms & OFDFT_TERM_TF) ? 1 : 0;
+    rc.spline = spline;
+    rc.exact = exact;
+    rc.lambda_vw = g->func.lambda_vw;
+    rc.alpha = g->func.alpha;
+    rc.floor = g->func.rho_floor;
+    rc.acc1 = g->acc1;
+    rc.acc2 = g->acc2;
+    rc.knots = g->knots;
+    rc.v_out = d_v;
+    rc.g_out = d_g;
+    rc.part = g->part;
+    rc.pstride = g->pstride;
+    rc.nbatch = nb;
+    rc.twM = g->twM;
+    rc.twN = g->twN;
+    int nb_inv = 0;
+    TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));
+
+    // 6. fixed-order FP64 sums
+    int cnt[NSLOT] = {0};
+    cnt[SL_RHO] = cnt[SL_TF] = cnt[SL_BAD] = nb_row;
+    cnt[SL_H] = cnt[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
+    cnt[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
+    cnt[SL_NL] = cnt[SL_GPHI] = cnt[SL_GG] = cnt[SL_PHIPHI] = nb_inv;
+    HIP_TRY(hipMemcpyAsync(g->d_count, cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
+    TIMED(PS_FINALIZE, launch_finalize(g->part, g->pstride, g->d_count, nb, g->sums, s));
+    HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, (size_t)nb * NSLOT * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    timer_collect(g);
+
+    double bad = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double *S = g->h_sums + (size_t)b * NSLOT;
+        ofdft_energy e;
+        std::memset(&e, 0, sizeof(e));
+        e.nelec_int = g->dv * S[SL_RHO];
+        if (terms & OFDFT_TERM_TF) e.e_tf = C_TF * g->dv * S[SL_TF];
+        if (terms & OFDFT_TERM_VW) e.e_vw = 0.5 * g->func.lambda_vw * g->V * S[SL_VW];
+        if (terms & OFDFT_TERM_HARTREE) e.e_h = 2.0 * PI * g->V * S[SL_H];
+        if (terms & OFDFT_TERM_EXT) {
+            e.e_ext = g->V * S[SL_EXT];
+            e.e_ion = g->e_ion;
+        }
+        if (terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) e.e_nl = g->dv * S[SL_NL];
+        e.e_total = e.e_tf + e.e_vw + e.e_h + e.e_ext + e.e_nl + e.e_ion;
+        const double spp = S[SL_PHIPHI];
+        e.mu = spp > 0 ? S[SL_GPHI] / (2.0 * spp) : 0.0;
+        const double r2 = spp > 0 ? S[SL_GG] - S[SL_GPHI] * S[SL_GPHI] / spp : S[SL_GG];
+        e.resid_norm = std::sqrt(std::max(0.0, r2) / (double)G.N);
+        bad += S[SL_BAD];
+        if (e_out) e_out[b] = e;
+    }
+    if (bad_out) *bad_out = bad;
+    return OFDFT_OK;
+}
+
+static ofdft_status eval_dispatch(ofdft_grid *g, int nb, const void *d_in, int in_is_phi,
+                                  void *d_v, void *d_g, hipStream_t s, ofdft_energy *e_out)
+{
+    double bad = 0.0;
+    ofdft_status st = g->fp64 ? eval_impl<double>(g, nb, d_in, in_is_phi, d_v, d_g, s, e_out, &bad)
+                              : eval_impl<float>(g, nb, d_in, in_is_phi, d_v, d_g, s, e_out, &bad);
+    if (st != OFDFT_OK) return st;
+    if (bad > 0)
+        return fail(OFDFT_EINVAL, "input density has " + std::to_string((long long)bad) +
+                                      " non-finite or negative values");
+    return OFDFT_OK;
+}
+
+// ---------------------------------------------------------------- FFT pair
+template <typename T>
+static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_out, bool fwd,
+                             hipStream_t s)
+{
+    ST_TRY(reserve(g, nb));
+    const Geom &G = g->geom;
+    if (fwd) {
+        RowFwdArgs rf;
+        std::memset(&rf, 0, sizeof(rf));
+        rf.in = d_in;
+        rf.out = d_out;
+        rf.out_fstride = 0;
+        rf.nfields = 1;
+        rf.kind[0] = FK_RAW;
+        rf.twM = g->twM;
+        rf.twN = g->twN;
+        rf.knots = g->knots;
+        int nbk = 0;
+        TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nbk, s));
+        ST_TRY(col_pass<T>(g, s, 1, d_out, nb, nb, 0, nullptr, PS_COL1_FWD));
+        int ops[4] = {GO_SCALE, 0, 0, 0};
+        ST_TRY(col_pass<T>(g, s, 0, d_out, nb, nb, 0, ops, PS_COL0_G));
+    } else {
+        // inverse: copy the spectrum into the workspace so the caller's input survives
+        HIP_TRY(hipMemcpyAsync(g->spec, d_in, (size_t)nb * G.Nh * 2 * sizeof(T),
+                               hipMemcpyDeviceToDevice, s));
+        ST_TRY(col_pass<T>(g, s, 0, g->spec, nb, nb, 1, nullptr, PS_COL0_G));
+        ST_TRY(col_pass<T>(g, s, 1, g->spec, nb, nb, 1, nullptr, PS_COL1_INV));
+        RowInvArgs ri;
+        std::memset(&ri, 0, sizeof(ri));
+        ri.spec = g->spec;
+        ri.spec_fstride = 0;
+        ri.nfields = 1;
+        ri.mode = EP_STORE;
+        ri.out = d_out;
+        ri.nbatch = nb;
+        ri.twM = g->twM;
+        ri.twN = g->twN;
+        ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
+        int nbk = 0;
+        TIMED(PS_ROW_INV, launch_row_inv<T>(G, ri, nbk, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    timer_collect(g);
+    return OFDFT_OK;
+}
+
+// ---------------------------------------------------------------- grid set-up
+static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_desc *f)
+{
+    if (!c || !f) return fail(OFDFT_EINVAL, "null descriptor");
+    for (int d = 0; d < 3; ++d)
+        if (!is_supported(c->n[d]))
+            return fail(OFDFT_EINVAL, "grid size " + std::to_string(c->n[d]) +
+                                          " on axis " + std::to_string(d) + " is not supported");
+    if (c->n[2] % 2 != 0 || !is_supported(c->n[2] / 2))
+        return fail(OFDFT_EINVAL, "n[2] must be even with n[2]/2 a supported length");
+    if (c->natoms < 0 || (c->natoms > 0 && (!c->pos || !c->species)))
+        return fail(OFDFT_EINVAL, "bad atom arrays");
+    if (c->natoms > 0 && (c->nspecies <= 0 || !c->Z || !c->rc))
+        return fail(OFDFT_EINVAL, "bad species arrays");
+    for (int a = 0; a < c->natoms; ++a) {
+        if (c->species[a] < 0 || c->species[a] >= c->nspecies)
+            return fail(OFDFT_EINVAL, "species index out of range");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(c->pos[3 * a + k])) return fail(OFDFT_EINVAL, "non-finite position");
+    }
+    if (!(c->nelec > 0)) return fail(OFDFT_EINVAL, "nelec must be positive");
+    const uint32_t all = OFDFT_TERM_TF | OFDFT_TERM_VW | OFDFT_TERM_HARTREE | OFDFT_TERM_EXT |
+                         OFDFT_TERM_WT | OFDFT_TERM_SPLINE;
+    if (f->terms & ~all) return fail(OFDFT_EINVAL, "unknown term bits");
+    if ((f->terms & OFDFT_TERM_WT) && (f->terms & OFDFT_TERM_SPLINE))
+        return fail(OFDFT_EINVAL, "WT and SPLINE are exclusive");
+    if ((f->terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) && f->alpha != f->beta)
+        return fail(OFDFT_EINVAL, "the GPU path requires alpha == beta");
+    if ((f->terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) && !(f->alpha > 0.5))
+        return fail(OFDFT_EINVAL, "alpha must exceed 1/2");
+    if (f->terms & OFDFT_TERM_SPLINE) {
+        if (f->nk < 1 || f->nk > MAXKNOTS) return fail(OFDFT_EINVAL, "nk out of range");
+        if (!(f->kf_min > 0) || !(f->kf_max >= f->kf_min) || (f->nk > 1 && !(f->kf_max > f->kf_min)))
+            return fail(OFDFT_EINVAL, "bad knot range");
+        if (f->nl_mode != OFDFT_NL_S3S4 && f->nl_mode != OFDFT_NL_EXACT)
+            return fail(OFDFT_EINVAL, "bad nl_mode");
+    }
+    if (f->precision != OFDFT_FP64 && f->precision != OFDFT_MIXED)
+        return fail(OFDFT_EINVAL, "bad precision");
+    if (!(f->rho_floor > 0)) return fail(OFDFT_EINVAL, "rho_floor must be positive");
+    return OFDFT_OK;
+}
+
+static void grid_free(ofdft_grid *g)
+{
+    dfree(g->tw0);
+    dfree(g->tw1);
+    dfree(g->twM);
+    dfree(g->twN);
+    dfree(g->vext);
+    dfree(reinterpret_cast<void *&>(g->ph0));
+    dfree(reinterpret_cast<void *&>(g->ph1));
+    dfree(reinterpret_cast<void *&>(g->ph2));
+    dfree(reinterpret_cast<void *&>(g->d_spec_off));
+    dfree(reinterpret_cast<void *&>(g->d_atom_species));
+    dfree(reinterpret_cast<void *&>(g->d_Z));
+    dfree(reinterpret_cast<void *&>(g->d_rc));
+    dfree(reinterpret_cast<void *&>(g->d_count));
+    dfree(g->spec);
+    dfree(g->kspec);
+    dfree(g->acc1);
+    dfree(g->acc2);
+    dfree(g->stage_in);
+    dfree(g->stage_out);
+    dfree(reinterpret_cast<void *&>(g->part));
+    dfree(reinterpret_cast<void *&>(g->sums));
+    dfree(g->rho);
+    for (auto &p : g->opt) dfree(p);
+    if (g->h_sums) (void)hipHostFree(g->h_sums);
+    g->h_sums = nullptr;
+    for (hipEvent_t e : g->timer.ev) (void)hipEventDestroy(e);
+    g->timer.ev.clear();
+}
+
+static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const ofdft_functional_desc *f)
+{
+    std::memcpy(g->lattice, c->lattice, sizeof(g->lattice));
+    for (int d = 0; d < 3; ++d) g->n[d] = c->n[d];
+    g->natoms = c->natoms;
+    g->pos.assign(c->pos, c->pos + 3 * (size_t)c->natoms);
+    g->species.assign(c->species, c->species + c->natoms);
+    g->Z.assign(c->Z, c->Z + std::max(c->nspecies, 0));
+    g->rc.assign(c->rc, c->rc + std::max(c->nspecies, 0));
+    g->nelec = c->nelec;
+    g->func = *f;
+    g->fp64 = f->precision == OFDFT_FP64;
+    g->fsz = g->fp64 ? 8 : 4;
+
+    // geometry: b_j with a_i . b_j = 2 pi delta_ij  (b = 2 pi inv(A)^T)
+    const double(*A)[3] = g->lattice;
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(std::fabs(det) > 0)) return fail(OFDFT_EINVAL, "singular lattice");
+    g->V = std::fabs(det);
+    double cof[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof[i][j] = A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1];
+        }
+    Geom &G = g->geom;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G.b[i][j] = 2.0 * PI * cof[i][j] / det;
+    G.n0 = c->n[0];
+    G.n1 = c->n[1];
+    G.n2 = c->n[2];
+    G.m = c->n[2] / 2;
+    G.n2h = G.m + 1;
+    G.N = (long long)G.n0 * G.n1 * G.n2;
+    G.Nh = (long long)G.n0 * G.n1 * G.n2h;
+    G.invN = 1.0 / (double)G.N;
+    g->dv = g->V / (double)G.N;
+
+    // knots (step s1): geometric or arithmetic, both ends included
+    std::memset(&g->knots, 0, sizeof(g->knots));
+    if (f->terms & OFDFT_TERM_SPLINE) {
+        Knots &K = g->knots;
+        K.nk = f->nk;
+        K.log_spacing = f->knot_spacing == OFDFT_KNOTS_LOG;
+        for (int i = 0; i < f->nk; ++i) {
+            const double u = f->nk > 1 ? (double)i / (double)(f->nk - 1) : 0.0;
+            K.k[i] = K.log_spacing ? f->kf_min * std::pow(f->kf_max / f->kf_min, u)
+                                   : f->kf_min + (f->kf_max - f->kf_min) * u;
+        }
+        if (f->nk > 1)
+            K.inv_span = K.log_spacing ? (f->nk - 1) / std::log(K.k[f->nk - 1] / K.k[0])
+                                       : (f->nk - 1) / (K.k[f->nk - 1] - K.k[0]);
+    }
+    g->kf_wt = f->kf_wt > 0 ? f->kf_wt : std::cbrt(3.0 * PI * PI * g->nelec / g->V);
+
+    // twiddles
+    ST_TRY(upload_twiddles(g, &g->tw0, G.n0, G.n0));
+    ST_TRY(upload_twiddles(g, &g->tw1, G.n1, G.n1));
+    ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m));
+    ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1));
+
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_count), NSLOT * sizeof(int)));
+
+    // ionic structure factor tables and v_ext(G)
+    const int na = g->natoms;
+    const int ns = (int)g->Z.size();
+    if (na > 0) {
+        // fractional coordinates s = R . inv(A) ; inv(A) = cof^T / det
+        std::vector<double> fr(3 * (size_t)na);
+        for (int a = 0; a < na; ++a)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0;
+                for (int i = 0; i < 3; ++i) s += g->pos[3 * a + i] * cof[j][i] / det;
+                fr[3 * a + j] = s - std::floor(s);
+            }
+        // atoms sorted by species
+        std::vector<int> order(na);
+        for (int a = 0; a < na; ++a) order[a] = a;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return g->species[x] < g->species[y]; });
+        std::vector<int> off(ns + 1, 0);
+        for (int a = 0; a < na; ++a) off[g->species[a] + 1]++;
+        for (int s = 0; s < ns; ++s) off[s + 1] += off[s];
+        const int nax[3] = {G.n0, G.n1, G.n2h};
+        double **tabs[3] = {&g->ph0, &g->ph1, &g->ph2};
+        for (int d = 0; d < 3; ++d) {
+            // separate tables in sorted order (for v_ext) are the same tables; forces index
+            // atoms in their original order, so the tables are stored in original order and
+            // the species-sorted v_ext kernel uses the permutation below
+            std::vector<double> t(2 * (size_t)na * nax[d]);
+            for (int a = 0; a < na; ++a) {
+                const int src = order[a];
+                for (int i = 0; i < nax[d]; ++i) {
+                    const int m = (d == 2) ? ((i == G.m) ? -G.m : i) : freq_host(i, nax[d]);
+                    double x = (double)m * fr[3 * src + d];
+                    x -= std::nearbyint(x);
+                    const double ang = -2.0 * PI * x;
+                    t[2 * ((size_t)a * nax[d] + i)] = std::cos(ang);
+                    t[2 * ((size_t)a * nax[d] + i) + 1] = std::sin(ang);
+                }
+            }
+            ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]), t.size() * sizeof(double)));
+            HIP_TRY(hipMemcpy(*tabs[d], t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        }
+        std::vector<int> sorted_species(na);
+        for (int a = 0; a < na; ++a) sorted_species[a] = g->species[order[a]];
+        g->species_order = order;
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_spec_off), (ns + 1) * sizeof(int)));
+        HIP_TRY(hipMemcpy(g->d_spec_off, off.data(), (ns + 1) * sizeof(int), hipMemcpyHostToDevice));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_atom_species), na * sizeof(int)));
+        HIP_TRY(hipMemcpy(g->d_atom_species, sorted_species.data(), na * sizeof(int),
+                          hipMemcpyHostToDevice));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_Z), ns * sizeof(double)));
+        HIP_TRY(hipMemcpy(g->d_Z, g->Z.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_rc), ns * sizeof(double)));
+        HIP_TRY(hipMemcpy(g->d_rc, g->rc.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+    }
+    ST_TRY(dmalloc(g, &g->vext, (size_t)G.Nh * 2 * g->fsz));
+    hipStream_t s = g->ctx->stream;
+    if (na > 0) {
+        hipError_t e = g->fp64 ? launch_vext<double>(G, na, g->d_spec_off, ns, g->ph0, g->ph1, g->ph2,
+                                                     g->d_Z, g->d_rc, g->V, g->vext, s)
+                               : launch_vext<float>(G, na, g->d_spec_off, ns, g->ph0, g->ph1, g->ph2,
+                                                    g->d_Z, g->d_rc, g->V, g->vext, s);
+        HIP_TRY(e);
+    } else {
+        HIP_TRY(hipMemsetAsync(g->vext, 0, (size_t)G.Nh * 2 * g->fsz, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    g->e_ion = (f->terms & OFDFT_TERM_EXT) ? ewald_energy_host(g, nullptr) : 0.0;
+    ST_TRY(dmalloc(g, &g->rho, (size_t)G.N * g->fsz));
+    return OFDFT_OK;
+}
+
+// ---------------------------------------------------------------- host<->device fields
+static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, size_t n, hipStream_t s)
+{
+    if (g->fp64) {
+        HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, s));
+    } else {
+        auto f = to_type<float>(src, n);
+        HIP_TRY(hipMemcpyAsync(dst, f.data(), n * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return OFDFT_OK;
+}
+
+static ofdft_status download_field(ofdft_grid *g, double *dst, const void *src, size_t n, hipStream_t s)
+{
+    if (g->fp64) {
+        HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        std::vector<float> f(n);
+        HIP_TRY(hipMemcpyAsync(f.data(), src, n * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t i = 0; i < n; ++i) dst[i] = f[i];
+    }
+    return OFDFT_OK;
+}
+
+static hipStream_t pick_stream(ofdft_grid *g, void *hs)
+{
+    return hs ? (hipStream_t)hs : g->ctx->stream;
+}
+
+// ---------------------------------------------------------------- optimiser
+// Vectors: 0 phi, 1 p (search direction on the sphere), 2 d (raw direction),
+// 3 R (residual), 4 R_prev, 5 g (dE/dphi at phi), 6 phi trial, 7 g trial.
+enum { V_PHI = 0, V_P, V_D, V_R, V_RP, V_G, V_PT, V_GT, NVEC = 8 };
+
+struct OptState {
+    ofdft_grid *g;
+    hipStream_t s;
+    long long N;
+};
+
+template <typename T>
+static ofdft_status dots(OptState &o, int nd, const void *x0, const void *y0, const void *x1,
+                         const void *y1, const void *x2, const void *y2, double *out)
+{
+    ofdft_grid *g = o.g;
+    hipStream_t s = o.s;
+    int nbk = 0;
+    TIMED(PS_OTHER, launch_dots<T>(o.N, nd, x0, y0, x1, y1, x2, y2, nullptr, nullptr, g->part,
+                                   g->pstride, nbk, s));
+    int cnt[NSLOT] = {0};
+    for (int d = 0; d < nd; ++d) cnt[SL_AUX0 + d] = nbk;
+    HIP_TRY(hipMemcpyAsync(g->d_count, cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_finalize(g->part, g->pstride, g->d_count, 1, g->sums, s));
+    HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, NSLOT * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    timer_collect(g);
+    for (int d = 0; d < nd; ++d) out[d] = g->h_sums[SL_AUX0 + d];
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status lincomb(OptState &o, void *z, double a, const void *x, double b, const void *y)
+{
+    ofdft_grid *g = o.g;
+    hipStream_t s = o.s;
+    TIMED(PS_OTHER, launch_lincomb<T>(o.N, z, a, x, b, y, s));
+    return OFDFT_OK;
+}
+
+static double cubic_min(double a, double fa, double da, double b, double fb, double db, bool &ok)
+{
+    const double d1 = da + db - 3.0 * (fa - fb) / (a - b);
+    const double disc = d1 * d1 - da * db;
+    ok = false;
+    if (disc < 0) return 0;
+    const double d2 = (b > a ? 1.0 : -1.0) * std::sqrt(disc);
+    const double den = db - da + 2.0 * d2;
+    if (den == 0) return 0;
+    ok = true;
+    return b - (b - a) * (db + d2 - d1) / den;
+}
+
+template <typename T>
+static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, ofdft_opt_result *res)
+{
+    hipStream_t s = g->ctx->stream;
+    const Geom &G = g->geom;
+    OptState o{g, s, G.N};
+    ST_TRY(reserve(g, 1));
+    for (int i = 0; i < NVEC; ++i) ST_TRY(dmalloc(g, &g->opt[i], (size_t)G.N * sizeof(T)));
+    void **v = g->opt;
+    const double dv = g->dv, ne = g->nelec;
+    const int max_iter = prm->max_iter;
+    const double tol = prm->tol;
+    std::memset(res, 0, sizeof(*res));
+
+    // phi = sqrt(rho_resident), normalised to N_e
+    {
+        // square root through the plain kernels: phi = sqrt(max(rho, 0)) is computed by the
+        // forward pass when the input is rho, but the optimiser needs phi as a vector.
+        std::vector<double> h((size_t)G.N);
+        ST_TRY(download_field(g, h.data(), g->rho, (size_t)G.N, s));
+        for (auto &x : h) x = std::sqrt(std::max(x, 0.0));
+        ST_TRY(upload_field(g, v[V_PHI], h.data(), (size_t)G.N, s));
+    }
+    double pp;
+    ST_TRY(dots<T>(o, 1, v[V_PHI], v[V_PHI], nullptr, nullptr, nullptr, nullptr, &pp));
+    if (!(pp > 0)) return fail(OFDFT_EINVAL, "resident density is zero");
+    ST_TRY(lincomb<T>(o, v[V_PHI], std::sqrt(ne / (dv * pp)), v[V_PHI], 0.0, nullptr));
+
+    ofdft_energy E;
+    ST_TRY(eval_dispatch(g, 1, v[V_PHI], 1, nullptr, v[V_G], s, &E));
+    int evals = 1, iter = 0;
+    bool have_prev = false, converged = false;
+    double kappa = -1.0, theta_prev = -1.0;
+    const double c1 = 1e-4, c2 = 0.1;
+    for (iter = 0; iter < max_iter; ++iter) {
+        if (E.resid_norm < tol) {
+            converged = true;
+            break;
+        }
+        // R = g - 2 mu phi
+        ST_TRY(lincomb<T>(o, v[V_R], 1.0, v[V_G], -2.0 * E.mu, v[V_PHI]));
+        double dd[3];
+        if (have_prev) {
+            ST_TRY(dots<T>(o, 3, v[V_R], v[V_R], v[V_R], v[V_RP], v[V_RP], v[V_RP], dd));
+            const double beta = std::max(0.0, (dd[0] - dd[1]) / dd[2]);
+            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], beta, v[V_D]));
+        } else {
+            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], 0.0, nullptr));
+        }
+        double q[3];
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            ST_TRY(dots<T>(o, 3, v[V_D], v[V_R], v[V_D], v[V_PHI], v[V_PHI], v[V_PHI], q));
+            if (q[0] >= 0.0 && attempt == 0) {   // not a descent direction: restart
+                ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], 0.0, nullptr));
+                continue;
+            }
+            break;
+        }
+        // p = d - (<d,phi>/<phi,phi>) phi, scaled to <p,p> dv = N_e
+        ST_TRY(lincomb<T>(o, v[V_P], 1.0, v[V_D], -q[1] / q[2], v[V_PHI]));
+        double pq[2];
+        ST_TRY(dots<T>(o, 2, v[V_P], v[V_P], v[V_G], v[V_P], nullptr, nullptr, pq));
+        if (!(pq[0] > 0)) break;
+        const double sc = std::sqrt(ne / (dv * pq[0]));
+        ST_TRY(lincomb<T>(o, v[V_P], sc, v[V_P], 0.0, nullptr));
+        const double d0 = dv * pq[1] * sc;   // dE/dtheta at 0
+        if (!(d0 < 0)) break;
+
+        double theta0 = (kappa > 0) ? std::min(1.0, std::max(1e-12, -d0 / kappa))
+                                    : (theta_prev > 0 ? theta_prev : 0.1);
+        const double f0 = E.e_total;
+        const double eps_f = 1e-14 * std::max(1.0, std::fabs(f0));
+        // trial evaluation at theta: phi_t = phi cos + p sin; returns E and dE/dtheta
+        double last_theta = -1.0;
+        ofdft_energy Et;
+        auto trial = [&](double th, double &f, double &df) -> ofdft_status {
+            ST_TRY(lincomb<T>(o, v[V_PT], std::cos(th), v[V_PHI], std::sin(th), v[V_P]));
+            ST_TRY(eval_dispatch(g, 1, v[V_PT], 1, nullptr, v[V_GT], s, &Et));
+            ++evals;
+            double gd[2];
+            ST_TRY(dots<T>(o, 2, v[V_GT], v[V_PHI], v[V_GT], v[V_P], nullptr, nullptr, gd));
+            f = Et.e_total;
+            df = dv * (-std::sin(th) * gd[0] + std::cos(th) * gd[1]);
+            last_theta = th;
+            return OFDFT_OK;
+        };
+        auto decrease_ok = [&](double a, double fa, double da) {
+            return fa <= f0 + c1 * a * d0 || (fa <= f0 + eps_f && da <= (2 * c1 - 1) * d0);
+        };
+        // strong-Wolfe search: bracket, then zoom with safeguarded cubic steps
+        double a_lo = 0.0, f_lo = f0, d_lo = d0, a_hi = 0, f_hi = 0, d_hi = 0;
+        double a = theta0, best_a = -1, best_f = 1e300;
+        bool done = false, zoom = false;
+        int budget = 20;
+        double fa = 0, da = 0;
+        for (int k = 0; k < budget && !done && !zoom; ++k) {
+            ST_TRY(trial(a, fa, da));
+            if (fa < best_f) { best_f = fa; best_a = a; }
+            if (!decrease_ok(a, fa, da) || (k > 0 && fa > f_lo + eps_f)) {
+                a_hi = a; f_hi = fa; d_hi = da; zoom = true; break;
+            }
+            if (std::fabs(da) <= -c2 * d0) { done = true; break; }
+            if (da >= 0) {
+                a_hi = a_lo; f_hi = f_lo; d_hi = d_lo;
+                a_lo = a; f_lo = fa; d_lo = da;
+                zoom = true;
+                break;
+            }
+            bool ok;
+            double an = cubic_min(a_lo, f_lo, d_lo, a, fa, da, ok);
+            if (!ok || an <= a * 1.1 || an > a * 4.0) an = 2.0 * a;
+            a_lo = a; f_lo = fa; d_lo = da;
+            a = an;
+        }
+        if (zoom) {
+            for (int k = 0; k < budget && !done; ++k) {
+                const double lo = std::min(a_lo, a_hi), hi = std::max(a_lo, a_hi);
+                bool ok;
+                double an = cubic_min(a_lo, f_lo, d_lo, a_hi, f_hi, d_hi, ok);
+                if (!ok || !(an > lo && an < hi)) an = 0.5 * (a_lo + a_hi);
+                else an = std::min(std::max(an, lo + 0.01 * (hi - lo)), hi - 0.01 * (hi - lo));
+                a = an;
+                ST_TRY(trial(a, fa, da));
+                if (fa < best_f) { best_f = fa; best_a = a; }
+                if (!decrease_ok(a, fa, da) || fa > f_lo + eps_f) {
+                    a_hi = a; f_hi = fa; d_hi = da;
+                } else {
+                    if (std::fabs(da) <= -c2 * d0) { done = true; break; }
+                    if (da * (a_hi - a_lo) >= 0) { a_hi = a_lo; f_hi = f_lo; d_hi = d_lo; }
+                    a_lo = a; f_lo = fa; d_lo = da;
+                }
+            }
+        }
+        if (!done) {
+            // fall back to the best point seen
+            if (!(best_f <= f0 + eps_f)) break;
+            if (best_a != last_theta) ST_TRY(trial(best_a, fa, da));
+            a = best_a;
+        }
+        kappa = (da - d0) / a;
+        theta_prev = a;
+        // accept: phi <- phi_t, g <- g_t, R_prev <- R
+        std::swap(v[V_PHI], v[V_PT]);
+        std::swap(v[V_G], v[V_GT]);
+        std::swap(v[V_R], v[V_RP]);
+        have_prev = true;
+        E = Et;
+    }
+    if (!converged && E.resid_norm < tol) converged = true;
+    // leave the optimised density resident: rho = phi^2
+    {
+        std::vector<double> h((size_t)G.N);
+        ST_TRY(download_field(g, h.data(), v[V_PHI], (size_t)G.N, s));
+        for (auto &x : h) x = x * x;
+        ST_TRY(upload_field(g, g->rho, h.data(), (size_t)G.N, s));
+    }
+    res->e = E;
+    res->iters = iter;
+    res->evals = evals;
+    res->final_resid = E.resid_norm;
+    if (!converged) return fail(OFDFT_ENOCONV, "optimisation did not reach the tolerance");
+    return OFDFT_OK;
+}
+
+// ================================================================ C ABI
+extern "C" {
+
+int ofdft_abi_version(void) { return OFDFT_ABI_VERSION; }
+
+const char *ofdft_last_error(void) { return g_last_error.c_str(); }
+
+int ofdft_supported_length(int32_t n) { return is_supported(n) ? 1 : 0; }
+
+ofdft_status ofdft_ctx_create(int device, ofdft_ctx **out)
+{
+    if (!out) return fail(OFDFT_EINVAL, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(OFDFT_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    ofdft_ctx *c = new (std::nothrow) ofdft_ctx;
+    if (!c) return fail(OFDFT_ENOMEM, "host allocation failed");
+    c->device = device;
+    hipError_t e = hipStreamCreate(&c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(OFDFT_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return OFDFT_OK;
+}
+
+void ofdft_ctx_destroy(ofdft_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
+                               const ofdft_functional_desc *func, ofdft_grid **out)
+{
+    if (!ctx || !out) return fail(OFDFT_EINVAL, "null argument");
+    *out = nullptr;
+    ST_TRY(validate(cell, func));
+    HIP_TRY(hipSetDevice(ctx->device));
+    ofdft_grid *g = new (std::nothrow) ofdft_grid;
+    if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
+    g->ctx = ctx;
+    ofdft_status st = grid_setup(g, cell, func);
+    if (st == OFDFT_OK) st = reserve(g, 1);
+    if (st != OFDFT_OK) {
+        grid_free(g);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return OFDFT_OK;
+}
+
+void ofdft_grid_destroy(ofdft_grid *grid)
+{
+    if (!grid) return;
+    (void)hipSetDevice(grid->ctx->device);
+    (void)hipStreamSynchronize(grid->ctx->stream);
+    grid_free(grid);
+    delete grid;
+}
+
+ofdft_status ofdft_grid_reserve(ofdft_grid *grid, int32_t nbatch)
+{
+    if (!grid || nbatch < 1) return fail(OFDFT_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return reserve(grid, nbatch);
+}
+
+uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
+{
+    if (!grid) return 0;
+    const Geom &G = grid->geom;
+    uint64_t b = 0;
+    b += (uint64_t)(2 * G.n0 + 2 * G.n1 + 2 * G.m + 2 * (G.m + 1)) * grid->fsz;    // twiddles
+    b += (uint64_t)G.Nh * 2 * grid->fsz;                                              // v_ext
+    b += (uint64_t)grid->natoms * (G.n0 + G.n1 + G.n2h) * 16;                         // phases
+    b += (uint64_t)G.N * grid->fsz;                                                   // resident rho
+    const uint64_t cap = (uint64_t)grid->cap;
+    b += 4 * cap * G.Nh * 2 * grid->fsz;
+    if (grid->kspec) b += (uint64_t)MAXKB * cap * G.Nh * 2 * grid->fsz;
+    if (grid->acc1) b += cap * G.N * grid->fsz;
+    if (grid->acc2) b += cap * G.N * grid->fsz;
+    b += cap * NSLOT * (uint64_t)grid->pstride * 8;
+    for (auto p : grid->opt)
+        if (p) b += (uint64_t)G.N * grid->fsz;
+    return b;
+}
+
+ofdft_status ofdft_set_density(ofdft_grid *grid, const double *rho_host)
+{
+    if (!grid || !rho_host) return fail(OFDFT_EINVAL, "null argument");
+    const long long N = grid->geom.N;
+    for (long long i = 0; i < N; ++i)
+        if (!std::isfinite(rho_host[i]) || rho_host[i] < 0)
+            return fail(OFDFT_EINVAL, "density has non-finite or negative values");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return upload_field(grid, grid->rho, rho_host, (size_t)N, grid->ctx->stream);
+}
+
+ofdft_status ofdft_get_density(ofdft_grid *grid, double *rho_host)
+{
+    if (!grid || !rho_host) return fail(OFDFT_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return download_field(grid, rho_host, grid->rho, (size_t)grid->geom.N, grid->ctx->stream);
+}
+
+ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host, double *v_out_host,
+                                    ofdft_energy *e_out)
+{
+    if (!grid || !e_out) return fail(OFDFT_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    const size_t N = (size_t)grid->geom.N;
+    hipStream_t s = grid->ctx->stream;
+    if (rho_host) {
+        for (size_t i = 0; i < N; ++i)
+            if (!std::isfinite(rho_host[i]) || rho_host[i] < 0)
+                return fail(OFDFT_EINVAL, "density has non-finite or negative values");
+        ST_TRY(dmalloc(grid, &grid->stage_in, N * grid->fsz));
+        ST_TRY(upload_field(grid, grid->stage_in, rho_host, N, s));
+    }
+    const void *d_in = rho_host ? grid->stage_in : grid->rho;
+    void *d_v = nullptr;
+    if (v_out_host) {
+        ST_TRY(dmalloc(grid, &grid->stage_out, N * grid->fsz));
+        d_v = grid->stage_out;
+    }
+    ST_TRY(eval_dispatch(grid, 1, d_in, 0, d_v, nullptr, s, e_out));
+    if (v_out_host) ST_TRY(download_field(grid, v_out_host, d_v, N, s));
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_energy_potential_dev(ofdft_grid *grid, const void *d_rho, void *d_v,
+                                        void *hip_stream, ofdft_energy *e_out)
+{
+    return ofdft_energy_potential_batch_dev(grid, 1, d_rho, d_v, hip_stream, e_out);
+}
+
+ofdft_status ofdft_energy_potential_batch_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
+                                              void *d_v, void *hip_stream, ofdft_energy *e_out)
+{
+    if (!grid || !d_rho || !e_out || nbatch < 1) return fail(OFDFT_EINVAL, "bad argument");
+    if (nbatch > 65535) return fail(OFDFT_EINVAL, "nbatch too large");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return eval_dispatch(grid, nbatch, d_rho, 0, d_v, nullptr, pick_stream(grid, hip_stream), e_out);
+}
+
+ofdft_status ofdft_fft_r2c_dev(ofdft_grid *grid, int32_t nbatch, const void *d_in, void *d_out,
+                               void *hip_stream)
+{
+    if (!grid || !d_in || !d_out || nbatch < 1 || nbatch > 65535)
+        return fail(OFDFT_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    hipStream_t s = pick_stream(grid, hip_stream);
+    return grid->fp64 ? fft_impl<double>(grid, nbatch, d_in, d_out, true, s)
+                      : fft_impl<float>(grid, nbatch, d_in, d_out, true, s);
+}
+
+ofdft_status ofdft_fft_c2r_dev(ofdft_grid *grid, int32_t nbatch, const void *d_in, void *d_out,
+                               void *hip_stream)
+{
+    if (!grid || !d_in || !d_out || nbatch < 1 || nbatch > 65535)
+        return fail(OFDFT_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    hipStream_t s = pick_stream(grid, hip_stream);
+    return grid->fp64 ? fft_impl<double>(grid, nbatch, d_in, d_out, false, s)
+                      : fft_impl<float>(grid, nbatch, d_in, d_out, false, s);
+}
+
+ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
+{
+    if (!grid || !f_out_host) return fail(OFDFT_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    const int na = grid->natoms;
+    if (na == 0) return OFDFT_OK;
+    ofdft_grid *g = grid;
+    hipStream_t s = g->ctx->stream;
+    ST_TRY(reserve(g, 1));
+    // rho(G) of the resident density into the workspace spectrum
+    ofdft_status st = g->fp64 ? fft_impl<double>(g, 1, g->rho, g->spec, true, s)
+                              : fft_impl<float>(g, 1, g->rho, g->spec, true, s);
+    ST_TRY(st);
+    double *d_f = nullptr;
+    HIP_TRY(hipMalloc((void **)&d_f, 3 * (size_t)na * sizeof(double)));
+    hipError_t e = g->fp64 ? launch_forces<double>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
+                                                   g->ph2, g->d_Z, g->d_rc, g->spec, d_f, s)
+                           : launch_forces<float>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
+                                                  g->ph2, g->d_Z, g->d_rc, g->spec, d_f, s);
+    std::vector<double> fs(3 * (size_t)na);
+    if (e == hipSuccess) e = hipMemcpyAsync(fs.data(), d_f, fs.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_f);
+    HIP_TRY(e);
+    std::vector<double> fe;
+    (void)ewald_energy_host(g, &fe);
+    for (int a = 0; a < na; ++a) {
+        const int orig = g->species_order[a];
+        for (int k = 0; k < 3; ++k) f_out_host[3 * orig + k] = fs[3 * a + k] + fe[3 * orig + k];
+    }
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, ofdft_opt_result *result)
+{
+    if (!grid || !params || !result) return fail(OFDFT_EINVAL, "null argument");
+    if (!(params->tol > 0) || params->max_iter < 0) return fail(OFDFT_EINVAL, "bad parameters");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return grid->fp64 ? optimize_impl<double>(grid, params, result)
+                      : optimize_impl<float>(grid, params, result);
+}
+
+// per-pass timing with HIP events on the launch stream
+ofdft_status ofdft_profile_enable(ofdft_grid *grid, int32_t on)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null argument");
+    grid->timer.on = on != 0;
+    for (int i = 0; i < NPASS; ++i) {
+        grid->timer.ms[i] = 0;
+        grid->timer.count[i] = 0;
+    }
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_profile_read(ofdft_grid *grid, int32_t pass, double *total_ms, int64_t *launches)
+{
+    if (!grid || pass < 0 || pass >= NPASS || !total_ms || !launches)
+        return fail(OFDFT_EINVAL, "bad argument");
+    *total_ms = grid->timer.ms[pass];
+    *launches = grid->timer.count[pass];
+    return OFDFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,233 @@
+// Device-side FFT building blocks for gfx950: radix-2/3/4/8 butterflies in
+// registers and Stockham autosort stages on pencils staged in LDS.
+//
+// Every reciprocal-space term of the orbital-free energy (Hartree, the
+// von Weizsaecker Laplacian, the nonlocal kernels of eqs. "nl2"/"WT" and the
+// per-knot convolutions of step s3) is a 3D FFT round trip; the paper runs
+// them through FFTW on one CPU core.  Here a workgroup of NT threads loads P
+// pencils of length L into LDS, runs log_R(L) Stockham stages in place
+// (all loads of a stage are held in registers across a barrier before the
+// stores), and writes them back.  L and the radix sequence are compile-time
+// so every index is a constant-divisor operation.
+//
+// Forward transforms use exp(-2 pi i nk/L), inverse exp(+2 pi i nk/L); no
+// scaling is applied.  Twiddles W_L^n come from a table built in FP64 on the
+// host and rounded to the field type.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ofdft {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a)
+{
+    if constexpr (INV) return {-a.y, a.x};
+    else return {a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- plans
+struct Plan {
+    int n;
+    int r[16];
+};
+
+// radices for a length-L transform: as many 8s as possible (an 8*2 tail is
+// rewritten as 4*4), then 4 or 2, then 3s.
+constexpr Plan make_plan(int L)
+{
+    Plan p{0, {}};
+    int m = L;
+    int twos = 0;
+    while (m % 2 == 0) { m /= 2; ++twos; }
+    int threes = 0;
+    while (m % 3 == 0) { m /= 3; ++threes; }
+    int e8 = twos / 3, rem = twos % 3;
+    if (rem == 1 && e8 > 0) { --e8; p.r[p.n++] = 4; p.r[p.n++] = 4; rem = 0; }
+    for (int i = 0; i < e8; ++i) p.r[p.n++] = 8;
+    if (rem == 2) p.r[p.n++] = 4;
+    if (rem == 1) p.r[p.n++] = 2;
+    for (int i = 0; i < threes; ++i) p.r[p.n++] = 3;
+    return p;
+}
+
+constexpr bool plan_ok(int L)
+{
+    // only lengths made of 2s and 3s
+    int m = L;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1 && L >= 2;
+}
+
+// ---------------------------------------------------------------- butterflies
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T> *a)
+{
+    if constexpr (R == 2) {
+        cpx<T> t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    } else if constexpr (R == 3) {
+        const T h = T(-0.5);
+        const T s = INV ? T(0.86602540378443864676372317075294)
+                        : T(-0.86602540378443864676372317075294);
+        cpx<T> t = cadd(a[1], a[2]);
+        cpx<T> d = csub(a[1], a[2]);
+        cpx<T> m = {a[0].x + h * t.x, a[0].y + h * t.y};
+        // s * i * d
+        cpx<T> sd = {-s * d.y, s * d.x};
+        a[0] = cadd(a[0], t);
+        a[1] = cadd(m, sd);
+        a[2] = csub(m, sd);
+    } else if constexpr (R == 4) {
+        cpx<T> t0 = cadd(a[0], a[2]);
+        cpx<T> t1 = csub(a[0], a[2]);
+        cpx<T> t2 = cadd(a[1], a[3]);
+        cpx<T> t3 = mul_mi<T, INV>(csub(a[1], a[3]));
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, t3);
+        a[3] = csub(t1, t3);
+    } else if constexpr (R == 8) {
+        const T r2 = T(0.70710678118654752440084436210485);
+        cpx<T> e[4] = {a[0], a[2], a[4], a[6]};
+        cpx<T> o[4] = {a[1], a[3], a[5], a[7]};
+        dft<T, 4, INV>(e);
+        dft<T, 4, INV>(o);
+        // o[k] *= W8^k (forward W8 = (1 - i)/sqrt2, inverse conjugate)
+        cpx<T> o1, o3;
+        if constexpr (INV) {
+            o1 = {r2 * (o[1].x - o[1].y), r2 * (o[1].x + o[1].y)};
+            o3 = {-r2 * (o[3].x + o[3].y), r2 * (o[3].x - o[3].y)};
+        } else {
+            o1 = {r2 * (o[1].x + o[1].y), r2 * (o[1].y - o[1].x)};
+            o3 = {r2 * (o[3].y - o[3].x), -r2 * (o[3].x + o[3].y)};
+        }
+        cpx<T> o2 = mul_mi<T, INV>(o[2]);
+        a[0] = cadd(e[0], o[0]);
+        a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], o1);
+        a[5] = csub(e[1], o1);
+        a[2] = cadd(e[2], o2);
+        a[6] = csub(e[2], o2);
+        a[3] = cadd(e[3], o3);
+        a[7] = csub(e[3], o3);
+    }
+}
+
+// ---------------------------------------------------------------- LDS layout
+// ROW layout: element n of pencil p at buf[p * L + n], butterflies j-fastest
+//   (used for the contiguous axis, whose pencils are rows in memory).
+// COL layout: element n of pencil p at buf[n * P + p], pencils fastest
+//   (used for strided axes: a tile of P adjacent columns).
+template <bool ROW, int L, int P>
+__device__ __forceinline__ int lidx(int n, int p)
+{
+    if constexpr (ROW) return p * L + n;
+    else return n * P + p;
+}
+
+// One Stockham stage of radix R after NS points have been combined.
+// Input element (j + r L/R) of every pencil is twiddled by W_{NS R}^{r (j mod NS)},
+// transformed, and stored at (j / NS) NS R + (j mod NS) + s NS.
+template <typename T, int L, int R, int NS, bool INV, int P, int NT, bool ROW>
+__device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *__restrict__ tw,
+                                               int tid)
+{
+    constexpr int NBF = L / R;
+    constexpr int TOT = NBF * P;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    cpx<T> v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            const int j = ROW ? (b % NBF) : (b / P);
+            const int p = ROW ? (b / NBF) : (b % P);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<ROW, L, P>(j + r * NBF, p)];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            const int j = ROW ? (b % NBF) : (b / P);
+            const int p = ROW ? (b / NBF) : (b % P);
+            const int k = j % NS;
+            if constexpr (NS > 1) {
+                constexpr int STEP = L / (NS * R);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cpx<T> w = tw[r * k * STEP];
+                    if constexpr (INV) w.y = -w.y;
+                    v[q][r] = cmul(v[q][r], w);
+                }
+            }
+            dft<T, R, INV>(v[q]);
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lidx<ROW, L, P>(base + r * NS, p)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int L, bool INV, int P, int NT, bool ROW, int S, int NS>
+__device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *__restrict__ tw, int tid)
+{
+    constexpr Plan pl = make_plan(L);
+    if constexpr (S < pl.n) {
+        constexpr int R = pl.r[S];
+        stockham_stage<T, L, R, NS, INV, P, NT, ROW>(buf, tw, tid);
+        fft_stages<T, L, INV, P, NT, ROW, S + 1, NS * R>(buf, tw, tid);
+    }
+}
+
+// Transform P pencils of length L held in LDS (layout per ROW), in place.
+// Caller must __syncthreads() after filling buf; returns after a barrier.
+template <typename T, int L, bool INV, int P, int NT, bool ROW>
+__device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *__restrict__ tw, int tid)
+{
+    static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
+    fft_stages<T, L, INV, P, NT, ROW, 0, 1>(buf, tw, tid);
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic workgroup sum of one double per thread (fixed tree order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *red, int tid)
+{
+    red[tid] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace ofdft

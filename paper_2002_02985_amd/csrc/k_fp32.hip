@@ -1,0 +1,5 @@
+// FFT-pass kernels instantiated for FP32 fields (the mixed-precision path).
+#include "kernels_impl.hpp"
+namespace ofdft {
+OFDFT_INSTANTIATE_LAUNCHERS(float)
+}

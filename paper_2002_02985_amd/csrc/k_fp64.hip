@@ -1,0 +1,5 @@
+// FFT-pass kernels instantiated for FP64 fields (the plain FP64 path).
+#include "kernels_impl.hpp"
+namespace ofdft {
+OFDFT_INSTANTIATE_LAUNCHERS(double)
+}

@@ -1,0 +1,253 @@
+// Non-FFT kernels: fixed-order FP64 reductions, the ionic structure factor
+// and local pseudopotential v_ext(G), electron-ion forces, and the vector
+// operations of the density optimiser.
+#include "kernels_impl.hpp"
+
+namespace ofdft {
+
+static const int SUPPORTED[] = {2,  3,  4,  6,  8,   9,   12,  16,  18,  24,  27,  32,  36,  48,  54,
+                                64, 72, 81, 96, 108, 128, 144, 162, 192, 216, 256, 288, 384, 512, 1024};
+
+bool length_supported(int L)
+{
+    for (int v : SUPPORTED)
+        if (v == L) return true;
+    return false;
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ __launch_bounds__(NT) void k_finalize(const double *part, int pstride, const int *count,
+                                                 double *sums)
+{
+    __shared__ double red[NT];
+    const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+    const double *p = part + ((long long)b * NSLOT + s) * pstride;
+    const int n = count[s];
+    double acc = 0.0;
+    for (int i = tid; i < n; i += NT) acc += p[i];
+    acc = block_sum<NT>(acc, red, tid);
+    if (tid == 0) sums[b * NSLOT + s] = acc;
+}
+
+hipError_t launch_finalize(const double *part, int pstride, const int *count_dev, int nbatch,
+                           double *sums, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(NSLOT, nbatch), dim3(NT), 0, s, part, pstride, count_dev,
+                       sums);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- v_ext(G)
+// v_ext(G) = (1/V) sum_s v_s(|G|) sum_{a in s} e^{-i G.R_a}; the phase is the
+// product of per-axis tables ph_d[a][i] = exp(-2 pi i m_d(i) s_{a,d}) (s the
+// fractional coordinates), built in FP64 with exact argument reduction.
+// One block per (i0, i1) row of the half spectrum; atoms are grouped by species.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_vext(Geom g, int natoms, const int *spec_off,
+                                             int nspecies, const double *ph0, const double *ph1,
+                                             const double *ph2, const double *Z,
+                                             const double *rc, double inv_vol, cpx<T> *vext)
+{
+    const int row = blockIdx.x;
+    const int i0 = row / g.n1, i1 = row % g.n1;
+    const int m0 = freq(i0, g.n0), m1 = freq(i1, g.n1);
+    for (int k2 = threadIdx.x; k2 < g.n2h; k2 += NT) {
+        const int m2 = (k2 == g.m) ? -g.m : k2;
+        const double G2 = gvec2<double>(g, m0, m1, m2);
+        double vr = 0.0, vi = 0.0;
+        for (int s = 0; s < nspecies; ++s) {
+            double sr = 0.0, si = 0.0;
+            for (int a = spec_off[s]; a < spec_off[s + 1]; ++a) {
+                const double *p0 = ph0 + 2 * ((long long)a * g.n0 + i0);
+                const double *p1 = ph1 + 2 * ((long long)a * g.n1 + i1);
+                const double *p2 = ph2 + 2 * ((long long)a * g.n2h + k2);
+                const double ar = p0[0] * p1[0] - p0[1] * p1[1];
+                const double ai = p0[0] * p1[1] + p0[1] * p1[0];
+                sr += ar * p2[0] - ai * p2[1];
+                si += ar * p2[1] + ai * p2[0];
+            }
+            const double z = Z[s], r = rc[s];
+            const double vs = G2 > 0.0 ? -4.0 * PI_D * z * exp(-G2 * r * r * 0.25) / G2
+                                       : PI_D * z * r * r;
+            vr += vs * sr;
+            vi += vs * si;
+        }
+        vext[(long long)row * g.n2h + k2] = {T(vr * inv_vol), T(vi * inv_vol)};
+    }
+}
+
+template <typename T>
+hipError_t launch_vext(const Geom &g, int natoms, const int *spec_off, int nspecies,
+                       const double *ph0, const double *ph1, const double *ph2, const double *Z,
+                       const double *rc, double volume, void *vext, hipStream_t s)
+{
+    (void)natoms;
+    hipLaunchKernelGGL((k_vext<T>), dim3(g.n0 * g.n1), dim3(NT), 0, s, g, natoms, spec_off,
+                       nspecies, ph0, ph1, ph2, Z, rc, 1.0 / volume, (cpx<T> *)vext);
+    return hipGetLastError();
+}
+template hipError_t launch_vext<float>(const Geom &, int, const int *, int, const double *,
+                                       const double *, const double *, const double *,
+                                       const double *, double, void *, hipStream_t);
+template hipError_t launch_vext<double>(const Geom &, int, const int *, int, const double *,
+                                        const double *, const double *, const double *,
+                                        const double *, double, void *, hipStream_t);
+
+// ---------------------------------------------------------------- forces
+// F_a = sum_half c(m2) G v_{s(a)}(|G|) Im[e^{i G.R_a} rho(G)], the exact
+// derivative -d/dR_a of int v_ext rho = V sum_half c Re[conj(v_ext(G)) rho(G)].
+// One block per atom; its phase tables are staged in LDS.
+constexpr int FORCE_MAXTAB = 2 * 1024 + 513;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_forces(Geom g, const int *atom_species,
+                                               const double *ph0, const double *ph1,
+                                               const double *ph2, const double *Z,
+                                               const double *rc, const cpx<T> *rho_g,
+                                               double *f_out)
+{
+    __shared__ double tab[2 * FORCE_MAXTAB];
+    __shared__ double red[NT];
+    const int a = blockIdx.x, tid = threadIdx.x;
+    const int ntab = g.n0 + g.n1 + g.n2h;
+    for (int i = tid; i < g.n0; i += NT) {
+        tab[2 * i] = ph0[2 * ((long long)a * g.n0 + i)];
+        tab[2 * i + 1] = ph0[2 * ((long long)a * g.n0 + i) + 1];
+    }
+    for (int i = tid; i < g.n1; i += NT) {
+        tab[2 * (g.n0 + i)] = ph1[2 * ((long long)a * g.n1 + i)];
+        tab[2 * (g.n0 + i) + 1] = ph1[2 * ((long long)a * g.n1 + i) + 1];
+    }
+    for (int i = tid; i < g.n2h; i += NT) {
+        tab[2 * (g.n0 + g.n1 + i)] = ph2[2 * ((long long)a * g.n2h + i)];
+        tab[2 * (g.n0 + g.n1 + i) + 1] = ph2[2 * ((long long)a * g.n2h + i) + 1];
+    }
+    (void)ntab;
+    __syncthreads();
+    const int s = atom_species[a];
+    const double z = Z[s], r = rc[s];
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (long long e = tid; e < g.Nh; e += NT) {
+        const int k2 = (int)(e % g.n2h);
+        const long long row = e / g.n2h;
+        const int i1 = (int)(row % g.n1), i0 = (int)(row / g.n1);
+        const int m0 = freq(i0, g.n0), m1 = freq(i1, g.n1);
+        const int m2 = (k2 == g.m) ? -g.m : k2;
+        const double gx = m0 * g.b[0][0] + m1 * g.b[1][0] + m2 * g.b[2][0];
+        const double gy = m0 * g.b[0][1] + m1 * g.b[1][1] + m2 * g.b[2][1];
+        const double gz = m0 * g.b[0][2] + m1 * g.b[1][2] + m2 * g.b[2][2];
+        const double G2 = gx * gx + gy * gy + gz * gz;
+        if (G2 == 0.0) continue;
+        const double *p0 = tab + 2 * i0;
+        const double *p1 = tab + 2 * (g.n0 + i1);
+        const double *p2 = tab + 2 * (g.n0 + g.n1 + k2);
+        // tables hold exp(-i G.R); the force needs exp(+i G.R) = conj
+        const double ar = p0[0] * p1[0] - p0[1] * p1[1];
+        const double ai = p0[0] * p1[1] + p0[1] * p1[0];
+        const double er = ar * p2[0] - ai * p2[1];
+        const double ei = -(ar * p2[1] + ai * p2[0]);
+        const cpx<T> rg = rho_g[e];
+        const double im = er * (double)rg.y + ei * (double)rg.x;
+        const double vs = -4.0 * PI_D * z * exp(-G2 * r * r * 0.25) / G2;
+        const double w = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
+        const double sc = w * vs * im;
+        fx += sc * gx;
+        fy += sc * gy;
+        fz += sc * gz;
+    }
+    fx = block_sum<NT>(fx, red, tid);
+    fy = block_sum<NT>(fy, red, tid);
+    fz = block_sum<NT>(fz, red, tid);
+    if (tid == 0) {
+        f_out[3 * a + 0] = fx;
+        f_out[3 * a + 1] = fy;
+        f_out[3 * a + 2] = fz;
+    }
+}
+
+template <typename T>
+hipError_t launch_forces(const Geom &g, int natoms, const int *atom_species, const double *ph0,
+                         const double *ph1, const double *ph2, const double *Z, const double *rc,
+                         const void *rho_g, double *f_out, hipStream_t s)
+{
+    if (g.n0 + g.n1 + g.n2h > FORCE_MAXTAB) return hipErrorInvalidValue;
+    if (natoms <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_forces<T>), dim3(natoms), dim3(NT), 0, s, g, atom_species, ph0, ph1, ph2,
+                       Z, rc, (const cpx<T> *)rho_g, f_out);
+    return hipGetLastError();
+}
+template hipError_t launch_forces<float>(const Geom &, int, const int *, const double *,
+                                         const double *, const double *, const double *,
+                                         const double *, const void *, double *, hipStream_t);
+template hipError_t launch_forces<double>(const Geom &, int, const int *, const double *,
+                                          const double *, const double *, const double *,
+                                          const double *, const void *, double *, hipStream_t);
+
+// ---------------------------------------------------------------- vectors
+constexpr int DOT_ITEMS = 8;
+
+int dots_blocks(long long n) { return (int)((n + (long long)NT * DOT_ITEMS - 1) / (NT * DOT_ITEMS)); }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dots(long long n, int nd, const T *x0, const T *y0,
+                                             const T *x1, const T *y1, const T *x2, const T *y2,
+                                             const T *x3, const T *y3, double *part, int pstride)
+{
+    __shared__ double red[NT];
+    const int tid = threadIdx.x;
+    const long long base = (long long)blockIdx.x * NT * DOT_ITEMS;
+    const T *xs[4] = {x0, x1, x2, x3};
+    const T *ys[4] = {y0, y1, y2, y3};
+    for (int d = 0; d < nd; ++d) {
+        double acc = 0.0;
+        for (int it = 0; it < DOT_ITEMS; ++it) {
+            const long long i = base + (long long)it * NT + tid;
+            if (i < n) acc += (double)xs[d][i] * (double)ys[d][i];
+        }
+        acc = block_sum<NT>(acc, red, tid);
+        if (tid == 0) part[(long long)(SL_AUX0 + d) * pstride + blockIdx.x] = acc;
+    }
+}
+
+template <typename T>
+hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,
+                       const void *y1, const void *x2, const void *y2, const void *x3,
+                       const void *y3, double *part, int pstride, int &nblocks, hipStream_t s)
+{
+    nblocks = dots_blocks(n);
+    if (nblocks > pstride || nd < 1 || nd > 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_dots<T>), dim3(nblocks), dim3(NT), 0, s, n, nd, (const T *)x0,
+                       (const T *)y0, (const T *)x1, (const T *)y1, (const T *)x2, (const T *)y2,
+                       (const T *)x3, (const T *)y3, part, pstride);
+    return hipGetLastError();
+}
+template hipError_t launch_dots<float>(long long, int, const void *, const void *, const void *,
+                                       const void *, const void *, const void *, const void *,
+                                       const void *, double *, int, int &, hipStream_t);
+template hipError_t launch_dots<double>(long long, int, const void *, const void *, const void *,
+                                        const void *, const void *, const void *, const void *,
+                                        const void *, double *, int, int &, hipStream_t);
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lincomb(long long n, T *z, double a, const T *x, double b,
+                                                const T *y)
+{
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i < n) z[i] = T(a * (double)x[i] + (y ? b * (double)y[i] : 0.0));
+}
+
+template <typename T>
+hipError_t launch_lincomb(long long n, void *z, double a, const void *x, double b, const void *y,
+                          hipStream_t s)
+{
+    const long long nb = (n + NT - 1) / NT;
+    hipLaunchKernelGGL((k_lincomb<T>), dim3((unsigned)nb), dim3(NT), 0, s, n, (T *)z, a,
+                       (const T *)x, b, (const T *)y);
+    return hipGetLastError();
+}
+template hipError_t launch_lincomb<float>(long long, void *, double, const void *, double,
+                                          const void *, hipStream_t);
+template hipError_t launch_lincomb<double>(long long, void *, double, const void *, double,
+                                           const void *, hipStream_t);
+
+}  // namespace ofdft

@@ -1,0 +1,169 @@
+// Host-visible launch interface of the HIP kernels.  Every launcher checks
+// its shapes against the kernel's compile-time tiling before it launches and
+// returns hipErrorInvalidValue for a length it has no kernel for.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ofdft {
+
+// partial-sum slots (FP64), one row of per-workgroup partials per slot
+enum Slot {
+    SL_RHO = 0,     // sum rho
+    SL_TF,          // sum rho^(5/3)
+    SL_H,           // sum_half c |rho(G)|^2 / G^2
+    SL_EXT,         // sum_half c Re[conj(v_ext(G)) rho(G)]
+    SL_VW,          // sum_half c G^2 |phi(G)|^2
+    SL_NL,          // sum rho^alpha Phi  (or rho^alpha v1 for the spline)
+    SL_GPHI,        // sum g phi
+    SL_GG,          // sum g^2
+    SL_PHIPHI,      // sum phi^2
+    SL_BAD,         // count of non-finite or negative inputs
+    SL_AUX0,        // slots for vector reductions
+    SL_AUX1,
+    SL_AUX2,
+    SL_AUX3,
+    NSLOT
+};
+
+// field kinds of the forward (prologue) kernel
+enum FieldKind { FK_RHO = 0, FK_PHI = 1, FK_RHOB = 2, FK_RAW = 3, FK_KNOT = 4 };
+// reciprocal-space operations of the axis-0 kernel
+enum GOp { GO_NONE = 0, GO_HEXT = 1, GO_VW = 2, GO_WT = 3, GO_SCALE = 4 };
+// epilogues of the inverse row kernel
+enum EpiMode { EP_STORE = 0, EP_COMBINE = 1, EP_KNOTS = 2 };
+
+constexpr int MAXKNOTS = 64;
+constexpr int MAXKB = 8;     // knots per batch of the spline loop
+
+struct Geom {
+    int n0, n1, n2, m, n2h;
+    long long N, Nh;            // real points, half-spectrum points per field
+    double b[3][3];             // reciprocal vectors (rows)
+    double invN;
+};
+
+struct Knots {
+    int nk;
+    int log_spacing;
+    double inv_span;            // (nk-1)/ln(k_N/k_1)  or  (nk-1)/(k_N-k_1)
+    double k[MAXKNOTS];
+};
+
+// forward row pass: axis-2 r2c of up to 4 fields derived pointwise from the
+// input (rho or phi), plus FP64 partials of the prologue.
+struct RowFwdArgs {
+    const void *in;             // nbatch x N (field type)
+    void *out;                  // spectra: out + f * out_fstride + b * Nh
+    long long out_fstride;
+    int nfields;
+    int kind[MAXKB];
+    int in_is_phi;
+    double beta;                // exponent of FK_RHOB
+    double alpha;               // exponent of FK_KNOT (rho^alpha L_i)
+    int knot0;                  // FK_KNOT: knot index of field f is knot0 + f
+    Knots knots;
+    int partials;               // accumulate SL_RHO, SL_TF, SL_BAD
+    double *part;               // [nbatch][NSLOT][pstride]
+    int pstride;
+    const void *twM;            // W_M^n, n < M
+    const void *twN;            // W_{n2}^k, k <= M
+};
+
+// strided column pass along axis 1 or 0 (c2c), optionally with a fused
+// reciprocal-space operation between a forward and an inverse transform
+struct ColArgs {
+    void *data;                 // out; field fb at data + fb * fstride
+    const void *src;            // in (may equal data)
+    long long fstride;
+    long long ncols, inner, outer_stride, elem_stride;
+    int inv;                    // direction when the field's op is GO_NONE
+    int nbatch;                 // field = blockIdx.y / nbatch
+    int op[MAXKB];              // per field op (axis 0 only; zero elsewhere)
+    const void *vext;           // half spectrum, field type (GO_HEXT)
+    int use_h, use_ext;
+    double lambda_vw;
+    double kf_wt;               // GO_WT kernel Fermi wavevector
+    double *part;
+    int pstride;
+    const void *tw;             // W_L^n
+    Geom g;
+};
+
+// axis-0 spline kernels: per-knot inverse of omega_i rho^b(G), and the EXACT
+// accumulation H += sum_i omega_i F[rho^a L_i]
+struct KnotArgs {
+    const void *src;            // inv: nbatch arrays; acc: K x nbatch arrays
+    void *dst;                  // inv: K x nbatch arrays; acc: nbatch arrays (H)
+    long long fstride;
+    long long ncols;
+    int knot0, K, nbatch;
+    int accumulate;             // acc: 0 overwrite H, 1 add into H
+    Knots knots;
+    const void *tw;
+    Geom g;
+};
+
+// inverse row pass: axis-2 c2r of up to 4 fields, then a plain store, the
+// final combine of the potential, or the spline knot accumulation.
+struct RowInvArgs {
+    const void *spec;           // field f of batch b at spec + f * spec_fstride + b * Nh
+    long long spec_fstride;
+    int nfields;
+    int mode;
+    void *out;                  // EP_STORE: field f of batch b at out + (f * nbatch + b) * N
+    const void *in;             // rho or phi (EP_COMBINE / EP_KNOTS)
+    int in_is_phi;
+    int fld_hext, fld_vw, fld_wt, fld_a;   // field index or -1
+    int use_tf, spline, exact;
+    double lambda_vw, alpha, floor;
+    void *acc1, *acc2;          // spline accumulators sum L_i Phi_i, sum L_i' Phi_i
+    int acc_init;               // EP_KNOTS: first knot batch overwrites
+    int knot0;
+    Knots knots;
+    void *v_out, *g_out;        // optional outputs (nbatch x N)
+    double *part;
+    int pstride;
+    int nbatch;
+    const void *twM, *twN;
+};
+
+bool length_supported(int L);
+
+// launchers (T = float or double)
+template <typename T> hipError_t launch_row_fwd(const Geom &g, int nbatch, const RowFwdArgs &a, int &nblocks, hipStream_t s);
+template <typename T> hipError_t launch_col(int L, int nfb, const ColArgs &a, int &nblocks, hipStream_t s);
+template <typename T> hipError_t launch_knot_inv(const KnotArgs &a, hipStream_t s);
+template <typename T> hipError_t launch_knot_acc(const KnotArgs &a, hipStream_t s);
+template <typename T> hipError_t launch_row_inv(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
+template <typename T> int row_blocks(const Geom &g);
+template <typename T> int col_blocks(int L, long long ncols);
+
+// FP64 reductions: sums[b][s] = sum_{i < count[s]} part[b][s][i]
+hipError_t launch_finalize(const double *part, int pstride, const int *count_dev, int nbatch,
+                           double *sums, hipStream_t s);
+
+// ionic structure factor and v_ext(G), electron-ion forces
+template <typename T>
+hipError_t launch_vext(const Geom &g, int natoms, const int *spec_off, int nspecies,
+                       const double *ph0, const double *ph1, const double *ph2,
+                       const double *Z, const double *rc, double volume, void *vext,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_forces(const Geom &g, int natoms, const int *atom_species,
+                         const double *ph0, const double *ph1, const double *ph2,
+                         const double *Z, const double *rc, const void *rho_g, double *f_out,
+                         hipStream_t s);
+
+// vector kernels (optimizer): up to 4 dot products into part slots
+template <typename T>
+hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,
+                       const void *y1, const void *x2, const void *y2, const void *x3,
+                       const void *y3, double *part, int pstride, int &nblocks, hipStream_t s);
+// z = a x + b y
+template <typename T>
+hipError_t launch_lincomb(long long n, void *z, double a, const void *x, double b, const void *y,
+                          hipStream_t s);
+int dots_blocks(long long n);
+
+}  // namespace ofdft

@@ -1,0 +1,866 @@
+// HIP kernels of the orbital-free DFT evaluation (templated on the field
+// type T = float | double and on the FFT length).  Included by the
+// per-precision translation units, which instantiate the launchers.
+//
+// One energy+potential evaluation is five field passes plus a reduction:
+//   1. row_fwd   axis-2 r2c of rho, phi and rho^beta computed pointwise from
+//                the input (Thomas-Fermi partials fused);
+//   2. col       axis-1 forward c2c;
+//   3. col       axis-0 forward c2c, reciprocal-space term (Hartree + local
+//                pseudopotential, von Weizsaecker Laplacian, Wang-Teter
+//                kernel), axis-0 inverse c2c -- per field, with the
+//                reciprocal-space energy partials;
+//   4. col       axis-1 inverse c2c;
+//   5. row_inv   axis-2 c2r of all fields and the final combine of the
+//                potential v = dE/drho and of g = dE/dphi, with the
+//                nonlocal energy and chemical-potential partials;
+//   6. finalize  fixed-order FP64 sums of the per-workgroup partials.
+// The spline functional adds, per batch of knots, an axis-0 kernel that
+// applies omega_i(|G|) and inverts, the axis-1 inverse, and an axis-2 c2r
+// that interpolates over k_F at every point (steps s2-s4).
+#pragma once
+#include <cmath>
+
+#include "fft_core.hpp"
+#include "kernels.hpp"
+
+namespace ofdft {
+
+constexpr int NT = 256;
+constexpr double PI_D = 3.14159265358979323846264338327950288;
+constexpr double THREE_PI2 = 29.608813203268075856503472999628;  // 3 pi^2
+constexpr double C_TF_D = 2.8712340001881918;   // (3/10)(3 pi^2)^(2/3)
+constexpr double C_WT_D = 2.2969872001505534;   // (6/25)(3 pi^2)^(2/3)
+
+template <typename T> struct Cfg;
+template <> struct Cfg<float> {
+    static constexpr int COL_ELEMS = 4096;
+    static constexpr int ROW_ELEMS = 2048;
+};
+template <> struct Cfg<double> {
+    static constexpr int COL_ELEMS = 2048;
+    static constexpr int ROW_ELEMS = 1024;
+};
+
+constexpr int pow2_floor(int x)
+{
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+template <typename T, int L> constexpr int col_P()
+{
+    int p = pow2_floor(Cfg<T>::COL_ELEMS / L);
+    if (p < 4) p = 4;
+    if (p > NT) p = NT;
+    return p;
+}
+template <typename T, int M> constexpr int row_P()
+{
+    int p = pow2_floor(Cfg<T>::ROW_ELEMS / M);
+    return p < 1 ? 1 : p;
+}
+
+// ---------------------------------------------------------------- math
+__device__ __forceinline__ float d_cbrt(float x) { return cbrtf(x); }
+__device__ __forceinline__ double d_cbrt(double x) { return cbrt(x); }
+__device__ __forceinline__ float d_pow(float x, float e) { return powf(x, e); }
+__device__ __forceinline__ double d_pow(double x, double e) { return pow(x, e); }
+__device__ __forceinline__ float d_log(float x) { return logf(x); }
+__device__ __forceinline__ double d_log(double x) { return log(x); }
+__device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ bool d_finite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool d_finite(double x) { return isfinite(x); }
+
+// Lindhard kernel shape G_NL(eta) = 1/F - 3 eta^2 - 1 with
+// F = 1/2 + (1 - eta^2)/(4 eta) ln|(1 + eta)/(1 - eta)| (the G_NL formula of
+// the nonlocal-KEDF section).  The logarithm is taken as log1p of
+// 2 eta/(1 - eta) or 2/(eta - 1); from eta = 1.6 on, 1/F - 3 eta^2 is summed
+// as a series in x = 1/eta^2 so that nothing cancels:
+//   F = x P(x),  P = sum_{n>=1} x^(n-1)/((2n-1)(2n+1)),
+//   3 eta^2 F = 1 + x S(x),  S = sum_{n>=2} 3 x^(n-2)/((2n-1)(2n+1)),
+//   G = -1 - S/P.
+template <typename T>
+__device__ __forceinline__ T gnl_dev(T eta)
+{
+    if (!(eta > T(0))) return T(0);
+    if (eta < T(1)) {
+        T F = T(0.5) + (T(1) - eta) * (T(1) + eta) / (T(4) * eta) *
+                           d_log1p(T(2) * eta / (T(1) - eta));
+        return T(1) / F - T(3) * eta * eta - T(1);
+    }
+    if (eta == T(1)) return T(-2);
+    if (eta < T(1.6)) {
+        T F = T(0.5) - (eta - T(1)) * (eta + T(1)) / (T(4) * eta) *
+                           d_log1p(T(2) / (eta - T(1)));
+        return T(1) / F - T(3) * eta * eta - T(1);
+    }
+    const T x = T(1) / (eta * eta);
+    constexpr int NTERM = sizeof(T) == 8 ? 40 : 18;
+    T P = T(0), S = T(0);
+#pragma unroll
+    for (int n = NTERM; n >= 1; --n) P = P * x + T(1.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
+#pragma unroll
+    for (int n = NTERM; n >= 2; --n) S = S * x + T(3.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
+    return T(-1) - S / P;
+}
+
+// k_F = (3 pi^2 rho)^(1/3), clamped to the knot range; bracket j and linear
+// weight t on the knots (step s4).  An exact knot belongs to the segment on
+// its right; the last knot to the last segment with t = 1.
+template <typename T>
+__device__ __forceinline__ void knot_bracket(T rho, const Knots &kn, int &j, T &t, bool &inside,
+                                             T &kf)
+{
+    kf = d_cbrt(T(THREE_PI2) * rho);
+    const int nk = kn.nk;
+    const T k1 = T(kn.k[0]), kN = T(kn.k[nk - 1]);
+    inside = kf > k1 && kf < kN;
+    const T kt = kf < k1 ? k1 : (kf > kN ? kN : kf);
+    if (nk == 1) {
+        j = 0;
+        t = T(0);
+        return;
+    }
+    T s = kn.log_spacing ? T(kn.inv_span) * d_log(kt / k1) : T(kn.inv_span) * (kt - k1);
+    int jj = (int)floor(s);
+    jj = jj < 0 ? 0 : (jj > nk - 2 ? nk - 2 : jj);
+    if (kt < T(kn.k[jj]) && jj > 0) jj -= 1;
+    else if (jj < nk - 2 && kt >= T(kn.k[jj + 1])) jj += 1;
+    j = jj;
+    const T kj = T(kn.k[jj]), kj1 = T(kn.k[jj + 1]);
+    t = (kt - kj) / (kj1 - kj);
+}
+
+// signed grid frequency of index i on an axis of n points (Nyquist negative)
+__device__ __forceinline__ int freq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+template <typename T>
+__device__ __forceinline__ T gvec2(const Geom &g, int m0, int m1, int m2)
+{
+    const T gx = T(m0) * T(g.b[0][0]) + T(m1) * T(g.b[1][0]) + T(m2) * T(g.b[2][0]);
+    const T gy = T(m0) * T(g.b[0][1]) + T(m1) * T(g.b[1][1]) + T(m2) * T(g.b[2][1]);
+    const T gz = T(m0) * T(g.b[0][2]) + T(m1) * T(g.b[1][2]) + T(m2) * T(g.b[2][2]);
+    return gx * gx + gy * gy + gz * gz;
+}
+
+__device__ __forceinline__ double *part_ptr(double *part, int b, int slot, int pstride)
+{
+    return part + ((long long)b * NSLOT + slot) * pstride;
+}
+
+// ================================================================ row forward
+template <typename T>
+__device__ __forceinline__ T field_value(int kind, T v, int in_is_phi, T beta, T alpha,
+                                         int knot, const Knots &kn)
+{
+    const T rho = in_is_phi ? v * v : (v > T(0) ? v : T(0));
+    switch (kind) {
+    case FK_RHO: return in_is_phi ? v * v : v;
+    case FK_PHI: return in_is_phi ? v : d_sqrt(rho);
+    case FK_RHOB: return rho > T(0) ? d_pow(rho, beta) : T(0);
+    case FK_KNOT: {
+        int j;
+        T t, kf;
+        bool inside;
+        knot_bracket(rho, kn, j, t, inside, kf);
+        T L = kn.nk == 1 ? T(1) : (j == knot ? T(1) - t : (j + 1 == knot ? t : T(0)));
+        return L == T(0) ? T(0) : L * (rho > T(0) ? d_pow(rho, alpha) : T(0));
+    }
+    default: return v;
+    }
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
+{
+    constexpr int P = row_P<T, M>();
+    constexpr int PAIRS = P * M;
+    constexpr int PER = (PAIRS + NT - 1) / NT;
+    __shared__ cpx<T> buf[PAIRS];
+    __shared__ double red[NT];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const long long nrows = (long long)g.n0 * g.n1;
+    const long long r0 = (long long)blockIdx.x * P;
+    const T *in = (const T *)a.in + (long long)b * g.N;
+    const cpx<T> *twM = (const cpx<T> *)a.twM;
+    const cpx<T> *twN = (const cpx<T> *)a.twN;
+
+    cpx<T> x[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NT;
+        x[q] = {T(0), T(0)};
+        if (idx < PAIRS) {
+            const int p = idx / M, n = idx % M;
+            const long long row = r0 + p;
+            if (row < nrows) x[q] = ((const cpx<T> *)(in + row * g.n2))[n];
+        }
+    }
+    if (a.partials) {
+        double s_rho = 0.0, s_tf = 0.0, bad = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < PAIRS && r0 + idx / M < nrows) {
+                const T vv[2] = {x[q].x, x[q].y};
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const T v = vv[c];
+                    const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
+                    if (!ok) {
+                        bad += 1.0;
+                        continue;
+                    }
+                    const T rho = a.in_is_phi ? v * v : v;
+                    const T cr = d_cbrt(rho);
+                    s_rho += (double)rho;
+                    s_tf += (double)(rho * cr * cr);
+                }
+            }
+        }
+        s_rho = block_sum<NT>(s_rho, red, tid);
+        s_tf = block_sum<NT>(s_tf, red, tid);
+        bad = block_sum<NT>(bad, red, tid);
+        if (tid == 0) {
+            part_ptr(a.part, b, SL_RHO, a.pstride)[blockIdx.x] = s_rho;
+            part_ptr(a.part, b, SL_TF, a.pstride)[blockIdx.x] = s_tf;
+            part_ptr(a.part, b, SL_BAD, a.pstride)[blockIdx.x] = bad;
+        }
+    }
+    const T beta = T(a.beta), alpha = T(a.alpha);
+    for (int f = 0; f < a.nfields; ++f) {
+        const int kind = a.kind[f];
+        const int knot = a.knot0 + f;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < PAIRS)
+                buf[idx] = {field_value<T>(kind, x[q].x, a.in_is_phi, beta, alpha, knot, a.knots),
+                            field_value<T>(kind, x[q].y, a.in_is_phi, beta, alpha, knot, a.knots)};
+        }
+        __syncthreads();
+        lds_fft<T, M, false, P, NT, true>(buf, twM, tid);
+        // unpack the half-length complex transform into the r2c half spectrum:
+        // X[k] = (Z[k] + conj Z[M-k])/2 - i W^k (Z[k] - conj Z[M-k])/2
+        cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh;
+        constexpr int OUTS = P * (M + 1);
+        for (int o = tid; o < OUTS; o += NT) {
+            const int p = o / (M + 1), k = o % (M + 1);
+            const long long row = r0 + p;
+            if (row < nrows) {
+                const cpx<T> zk = buf[p * M + (k == M ? 0 : k)];
+                const cpx<T> zm = cconj(buf[p * M + (k == 0 ? 0 : M - k)]);
+                const cpx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
+                const cpx<T> d = {T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y)};
+                const cpx<T> wd = cmul(twN[k], d);
+                out[row * g.n2h + k] = {e.x + wd.y, e.y - wd.x};
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ================================================================ columns
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_col(ColArgs a)
+{
+    constexpr int P = col_P<T, L>();
+    constexpr int RSTEP = NT / P;
+    static_assert(NT % P == 0, "tile width must divide the block");
+    __shared__ cpx<T> buf[L * P];
+    __shared__ double red[NT];
+    const int tid = threadIdx.x;
+    const int fb = blockIdx.y;
+    const int p = tid % P;
+    const long long c = (long long)blockIdx.x * P + p;
+    const bool cvalid = c < a.ncols;
+    const long long cbase = cvalid ? (c / a.inner) * a.outer_stride + (c % a.inner) : 0;
+    const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
+    cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
+    const cpx<T> *tw = (const cpx<T> *)a.tw;
+
+    for (int n = tid / P; n < L; n += RSTEP)
+        buf[n * P + p] = cvalid ? src[cbase + n * a.elem_stride] : cpx<T>{T(0), T(0)};
+    __syncthreads();
+    const int field = fb / a.nbatch;
+    const int b = fb % a.nbatch;
+    const int op = field < MAXKB ? a.op[field] : GO_NONE;
+    if (op == GO_NONE) {
+        if (a.inv) lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
+        else lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+    } else {
+        // axis 0: element n is i0, column c is (i1, k2)
+        lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+        const Geom &g = a.g;
+        const int i1 = cvalid ? (int)(c / g.n2h) : 0;
+        const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+        const int m1 = freq(i1, g.n1);
+        const int m2 = (k2 == g.m) ? -g.m : k2;
+        const double wgt = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
+        const T invN = T(g.invN);
+        const cpx<T> *vx = (const cpx<T> *)a.vext;
+        const T fourpi = T(4.0 * PI_D);
+        double s0 = 0.0, s1 = 0.0;
+        for (int n = tid / P; n < L; n += RSTEP) {
+            if (!cvalid) continue;
+            const int m0 = freq(n, L);
+            const T G2 = gvec2<T>(g, m0, m1, m2);
+            const cpx<T> F = cscale(buf[n * P + p], invN);
+            cpx<T> o = {T(0), T(0)};
+            if (op == GO_HEXT) {
+                const cpx<T> v = vx[(long long)n * g.n1 * g.n2h + c];
+                if (G2 > T(0)) {
+                    const T ih = T(1) / G2;
+                    s0 += wgt * (double)((F.x * F.x + F.y * F.y) * ih);
+                    if (a.use_h) o = cscale(F, fourpi * ih);
+                }
+                if (a.use_ext) {
+                    s1 += wgt * (double)(v.x * F.x + v.y * F.y);
+                    o = cadd(o, v);
+                }
+            } else if (op == GO_VW) {
+                s0 += wgt * (double)(G2 * (F.x * F.x + F.y * F.y));
+                o = cscale(F, T(a.lambda_vw) * G2);
+            } else if (op == GO_WT) {
+                const T eta = d_sqrt(G2) / (T(2) * T(a.kf_wt));
+                o = cscale(F, T(C_WT_D) * gnl_dev<T>(eta));
+            } else {  // GO_SCALE
+                o = F;
+            }
+            buf[n * P + p] = o;
+        }
+        if (op == GO_HEXT || op == GO_VW) {
+            s0 = block_sum<NT>(s0, red, tid);
+            s1 = block_sum<NT>(s1, red, tid);
+            if (tid == 0) {
+                if (op == GO_HEXT) {
+                    part_ptr(a.part, b, SL_H, a.pstride)[blockIdx.x] = s0;
+                    part_ptr(a.part, b, SL_EXT, a.pstride)[blockIdx.x] = s1;
+                } else {
+                    part_ptr(a.part, b, SL_VW, a.pstride)[blockIdx.x] = s0;
+                }
+            }
+        }
+        __syncthreads();
+        if (op != GO_SCALE) lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
+    }
+    if (cvalid)
+        for (int n = tid / P; n < L; n += RSTEP) dst[cbase + n * a.elem_stride] = buf[n * P + p];
+}
+
+// ================================================================ spline, axis 0
+// Step s2/s3: for knots i = knot0 .. knot0+K-1, Phi_i(G) = omega_i(|G|) rho^b(G)
+// with omega_i = C_WT G_NL(|G| / (2 k_i)), then the axis-0 inverse.
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
+{
+    constexpr int P = col_P<T, L>();
+    constexpr int RSTEP = NT / P;
+    constexpr int PER = (L + RSTEP - 1) / RSTEP;
+    __shared__ cpx<T> buf[L * P];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const int p = tid % P;
+    const long long c = (long long)blockIdx.x * P + p;
+    const bool cvalid = c < a.ncols;
+    const Geom &g = a.g;
+    const long long es = (long long)g.n1 * g.n2h;
+    const cpx<T> *src = (const cpx<T> *)a.src + b * a.fstride;
+    const cpx<T> *tw = (const cpx<T> *)a.tw;
+    const int i1 = cvalid ? (int)(c / g.n2h) : 0;
+    const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+    const int m1 = freq(i1, g.n1);
+    const int m2 = (k2 == g.m) ? -g.m : k2;
+    cpx<T> xs[PER];
+    T gn[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int n = tid / P + q * RSTEP;
+        xs[q] = {T(0), T(0)};
+        gn[q] = T(0);
+        if (n < L && cvalid) {
+            xs[q] = src[c + n * es];
+            gn[q] = d_sqrt(gvec2<T>(g, freq(n, L), m1, m2));
+        }
+    }
+    for (int kk = 0; kk < a.K; ++kk) {
+        const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int n = tid / P + q * RSTEP;
+            if (n < L) buf[n * P + p] = cscale(xs[q], T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k));
+        }
+        __syncthreads();
+        lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
+        cpx<T> *dst = (cpx<T> *)a.dst + ((long long)kk * a.nbatch + b) * a.fstride;
+        if (cvalid)
+            for (int n = tid / P; n < L; n += RSTEP) dst[c + n * es] = buf[n * P + p];
+        __syncthreads();
+    }
+}
+
+// EXACT mode: H(G) (+)= sum_{kk} omega_{knot0+kk}(|G|) F[rho^a L_i](G), where the
+// K inputs have had the axis-2 r2c and axis-1 forward passes; this kernel does
+// the axis-0 forward transform and the normalisation.
+template <typename T, int L>
+__global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
+{
+    constexpr int P = col_P<T, L>();
+    constexpr int RSTEP = NT / P;
+    constexpr int PER = (L + RSTEP - 1) / RSTEP;
+    __shared__ cpx<T> buf[L * P];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const int p = tid % P;
+    const long long c = (long long)blockIdx.x * P + p;
+    const bool cvalid = c < a.ncols;
+    const Geom &g = a.g;
+    const long long es = (long long)g.n1 * g.n2h;
+    const cpx<T> *tw = (const cpx<T> *)a.tw;
+    const int i1 = cvalid ? (int)(c / g.n2h) : 0;
+    const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+    const int m1 = freq(i1, g.n1);
+    const int m2 = (k2 == g.m) ? -g.m : k2;
+    const T invN = T(g.invN);
+    cpx<T> acc[PER];
+    T gn[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int n = tid / P + q * RSTEP;
+        acc[q] = {T(0), T(0)};
+        gn[q] = (n < L && cvalid) ? d_sqrt(gvec2<T>(g, freq(n, L), m1, m2)) : T(0);
+    }
+    for (int kk = 0; kk < a.K; ++kk) {
+        const cpx<T> *src = (const cpx<T> *)a.src + ((long long)kk * a.nbatch + b) * a.fstride;
+        for (int n = tid / P; n < L; n += RSTEP)
+            buf[n * P + p] = cvalid ? src[c + n * es] : cpx<T>{T(0), T(0)};
+        __syncthreads();
+        lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+        const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int n = tid / P + q * RSTEP;
+            if (n < L) {
+                const T w = T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k) * invN;
+                const cpx<T> v = buf[n * P + p];
+                acc[q].x += w * v.x;
+                acc[q].y += w * v.y;
+            }
+        }
+        __syncthreads();
+    }
+    cpx<T> *dst = (cpx<T> *)a.dst + (long long)b * a.fstride;
+    if (cvalid) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int n = tid / P + q * RSTEP;
+            if (n < L) {
+                cpx<T> v = acc[q];
+                if (a.accumulate) v = cadd(v, dst[c + n * es]);
+                dst[c + n * es] = v;
+            }
+        }
+    }
+}
+
+// ================================================================ row inverse
+// c2r of one half-spectrum row block into buf (z[n] = f[2n] + i f[2n+1]):
+// Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), k < M, with
+// the imaginary parts of X[0] and X[M] dropped (Re of the inverse).
+template <typename T, int M, int P>
+__device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__ spec,
+                                         long long r0, long long nrows, int n2h,
+                                         const cpx<T> *__restrict__ twM,
+                                         const cpx<T> *__restrict__ twN, int tid)
+{
+    constexpr int PAIRS = P * M;
+    for (int o = tid; o < PAIRS; o += NT) {
+        const int p = o / M, k = o % M;
+        const long long row = r0 + p;
+        cpx<T> z = {T(0), T(0)};
+        if (row < nrows) {
+            const cpx<T> *x = spec + row * n2h;
+            cpx<T> xk = x[k];
+            cpx<T> xm = x[M - k];
+            if (k == 0) {
+                xk.y = T(0);
+                xm.y = T(0);
+            }
+            const cpx<T> s = {xk.x + xm.x, xk.y - xm.y};   // X[k] + conj X[M-k]
+            const cpx<T> d = {xk.x - xm.x, xk.y + xm.y};   // X[k] - conj X[M-k]
+            const cpx<T> dw = cmul(d, cconj(twN[k]));
+            z = {s.x - dw.y, s.y + dw.x};                  // s + i dw
+        }
+        buf[o] = z;
+    }
+    __syncthreads();
+    lds_fft<T, M, true, P, NT, true>(buf, twM, tid);
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
+{
+    constexpr int P = row_P<T, M>();
+    constexpr int PAIRS = P * M;
+    constexpr int PER = (PAIRS + NT - 1) / NT;
+    __shared__ cpx<T> buf[PAIRS];
+    __shared__ double red[NT];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.y;
+    const long long nrows = (long long)g.n0 * g.n1;
+    const long long r0 = (long long)blockIdx.x * P;
+    const cpx<T> *twM = (const cpx<T> *)a.twM;
+    const cpx<T> *twN = (const cpx<T> *)a.twN;
+    auto spec_of = [&](int f) {
+        return (const cpx<T> *)a.spec + f * a.spec_fstride + (long long)b * g.Nh;
+    };
+    auto pair_of = [&](int q, long long &off) {
+        const int idx = tid + q * NT;
+        if (idx >= PAIRS) return false;
+        const int p = idx / M, n = idx % M;
+        const long long row = r0 + p;
+        if (row >= nrows) return false;
+        off = row * g.n2 + 2 * n;
+        return true;
+    };
+
+    if (a.mode == EP_STORE) {
+        for (int f = 0; f < a.nfields; ++f) {
+            c2r_rows<T, M, P>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
+            T *out = (T *)a.out + ((long long)f * a.nbatch + b) * g.N;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                long long off;
+                if (pair_of(q, off)) *(cpx<T> *)(out + off) = buf[tid + q * NT];
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    // input density (rho or phi) for this block's pairs
+    const T *in = (const T *)a.in + (long long)b * g.N;
+    cpx<T> xin[PER];
+    bool valid[PER];
+    long long offs[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        valid[q] = pair_of(q, offs[q]);
+        xin[q] = valid[q] ? *(const cpx<T> *)(in + offs[q]) : cpx<T>{T(0), T(0)};
+    }
+
+    if (a.mode == EP_KNOTS) {
+        // step s4 for this batch of knots: v1 += L_i Phi_i, v2 += L_i' Phi_i
+        int jj[PER][2];
+        T tt[PER][2];
+        cpx<T> v1[PER], v2[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const T vv[2] = {xin[q].x, xin[q].y};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T rho = a.in_is_phi ? vv[c] * vv[c] : (vv[c] > T(0) ? vv[c] : T(0));
+                T kf;
+                bool inside;
+                knot_bracket(rho, a.knots, jj[q][c], tt[q][c], inside, kf);
+            }
+            v1[q] = {T(0), T(0)};
+            v2[q] = {T(0), T(0)};
+        }
+        for (int f = 0; f < a.nfields; ++f) {
+            c2r_rows<T, M, P>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
+            const int i = a.knot0 + f;
+            const int nk = a.knots.nk;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (!valid[q]) continue;
+                const cpx<T> z = buf[tid + q * NT];
+                const T ph[2] = {z.x, z.y};
+                T w1[2], w2[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int j = jj[q][c];
+                    const T t = tt[q][c];
+                    if (nk == 1) {
+                        w1[c] = T(1);
+                        w2[c] = T(0);
+                    } else {
+                        const T idk = T(1.0 / (a.knots.k[j + 1] - a.knots.k[j]));
+                        w1[c] = (j == i) ? T(1) - t : ((j + 1 == i) ? t : T(0));
+                        w2[c] = (j == i) ? -idk : ((j + 1 == i) ? idk : T(0));
+                    }
+                }
+                v1[q].x += w1[0] * ph[0];
+                v1[q].y += w1[1] * ph[1];
+                v2[q].x += w2[0] * ph[0];
+                v2[q].y += w2[1] * ph[1];
+            }
+            __syncthreads();
+        }
+        T *acc1 = (T *)a.acc1 + (long long)b * g.N;
+        T *acc2 = a.exact ? (T *)a.acc2 + (long long)b * g.N : nullptr;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (!valid[q]) continue;
+            cpx<T> s1 = v1[q];
+            if (!a.acc_init) s1 = cadd(s1, *(cpx<T> *)(acc1 + offs[q]));
+            *(cpx<T> *)(acc1 + offs[q]) = s1;
+            if (acc2) {
+                cpx<T> s2 = v2[q];
+                if (!a.acc_init) s2 = cadd(s2, *(cpx<T> *)(acc2 + offs[q]));
+                *(cpx<T> *)(acc2 + offs[q]) = s2;
+            }
+        }
+        return;
+    }
+
+    // EP_COMBINE: v = dE/drho and g = dE/dphi from all terms
+    cpx<T> fh[PER], fl[PER], fw[PER], fa[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) fh[q] = fl[q] = fw[q] = fa[q] = {T(0), T(0)};
+    const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+    for (int s = 0; s < 4; ++s) {
+        if (flds[s] < 0) continue;
+        c2r_rows<T, M, P>(buf, spec_of(flds[s]), r0, nrows, g.n2h, twM, twN, tid);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < PAIRS) {
+                const cpx<T> z = buf[idx];
+                if (s == 0) fh[q] = z;
+                else if (s == 1) fl[q] = z;
+                else if (s == 2) fw[q] = z;
+                else fa[q] = z;
+            }
+        }
+        __syncthreads();
+    }
+    const T *acc1 = a.spline ? (const T *)a.acc1 + (long long)b * g.N : nullptr;
+    const T *acc2 = (a.spline && a.exact) ? (const T *)a.acc2 + (long long)b * g.N : nullptr;
+    T *vout = a.v_out ? (T *)a.v_out + (long long)b * g.N : nullptr;
+    T *gout = a.g_out ? (T *)a.g_out + (long long)b * g.N : nullptr;
+    const T alpha = T(a.alpha);
+    const T floor_rho = T(a.floor);
+    const T floor_phi = d_sqrt(floor_rho);
+    double s_nl = 0.0, s_gphi = 0.0, s_gg = 0.0, s_pp = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        if (!valid[q]) continue;
+        cpx<T> a1 = {T(0), T(0)}, a2 = {T(0), T(0)};
+        if (acc1) a1 = *(const cpx<T> *)(acc1 + offs[q]);
+        if (acc2) a2 = *(const cpx<T> *)(acc2 + offs[q]);
+        const T xv[2] = {xin[q].x, xin[q].y};
+        const T hv[2] = {fh[q].x, fh[q].y};
+        const T lv[2] = {fl[q].x, fl[q].y};
+        const T wv[2] = {fw[q].x, fw[q].y};
+        const T av[2] = {fa[q].x, fa[q].y};
+        const T s1v[2] = {a1.x, a1.y};
+        const T s2v[2] = {a2.x, a2.y};
+        T vo[2], go[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T phi, rho;
+            if (a.in_is_phi) {
+                phi = xv[c];
+                rho = phi * phi;
+            } else {
+                rho = xv[c] > T(0) ? xv[c] : T(0);
+                phi = d_sqrt(rho);
+            }
+            const T aphi = phi < T(0) ? -phi : phi;
+            const T sgn = phi < T(0) ? T(-1) : T(1);
+            const T rho_s = rho > floor_rho ? rho : floor_rho;
+            const T phi_s = sgn * (aphi > floor_phi ? aphi : floor_phi);
+            T v = hv[c];          // v_H + v_ext
+            T gphi = T(2) * phi * v;
+            if (a.use_tf) {
+                const T cr = d_cbrt(rho);
+                const T vt = T(5.0 / 3.0 * C_TF_D) * cr * cr;
+                v += vt;
+                gphi += T(2) * phi * vt;
+            }
+            // von Weizsaecker: lv = -lambda nabla^2 phi
+            v += T(0.5) * lv[c] / phi_s;
+            gphi += lv[c];
+            // nonlocal: rho^(alpha-1) floored in v; phi rho^(alpha-1) = sgn |phi|^(2 alpha - 1) in g
+            const T ra1 = d_pow(rho_s, alpha - T(1));
+            const T fa_ = aphi > T(0) ? sgn * d_pow(aphi, T(2) * alpha - T(1)) : T(0);
+            const T ra = rho > T(0) ? d_pow(rho, alpha) : T(0);
+            if (a.fld_wt >= 0) {
+                v += T(2) * alpha * ra1 * wv[c];
+                gphi += T(4) * alpha * fa_ * wv[c];
+                s_nl += (double)(ra * wv[c]);
+            }
+            if (a.spline) {
+                s_nl += (double)(ra * s1v[c]);
+                if (!a.exact) {
+                    v += T(2) * alpha * ra1 * s1v[c];
+                    gphi += T(4) * alpha * fa_ * s1v[c];
+                } else {
+                    T kf, t;
+                    int j;
+                    bool inside;
+                    knot_bracket(rho, a.knots, j, t, inside, kf);
+                    const T dk = inside ? kf * T(1.0 / 3.0) : T(0);   // rho dk~/drho
+                    v += alpha * ra1 * (s1v[c] + av[c]) + ra * (dk / rho_s) * s2v[c];
+                    gphi += T(2) * (alpha * fa_ * (s1v[c] + av[c]) + fa_ * dk * s2v[c]);
+                }
+            }
+            vo[c] = v;
+            go[c] = gphi;
+            s_gphi += (double)gphi * (double)phi;
+            s_gg += (double)gphi * (double)gphi;
+            s_pp += (double)phi * (double)phi;
+        }
+        if (vout) *(cpx<T> *)(vout + offs[q]) = {vo[0], vo[1]};
+        if (gout) *(cpx<T> *)(gout + offs[q]) = {go[0], go[1]};
+    }
+    s_nl = block_sum<NT>(s_nl, red, tid);
+    s_gphi = block_sum<NT>(s_gphi, red, tid);
+    s_gg = block_sum<NT>(s_gg, red, tid);
+    s_pp = block_sum<NT>(s_pp, red, tid);
+    if (tid == 0) {
+        part_ptr(a.part, b, SL_NL, a.pstride)[blockIdx.x] = s_nl;
+        part_ptr(a.part, b, SL_GPHI, a.pstride)[blockIdx.x] = s_gphi;
+        part_ptr(a.part, b, SL_GG, a.pstride)[blockIdx.x] = s_gg;
+        part_ptr(a.part, b, SL_PHIPHI, a.pstride)[blockIdx.x] = s_pp;
+    }
+}
+
+// ================================================================ launchers
+#define OFDFT_LENGTHS(X) \
+    X(2) X(3) X(4) X(6) X(8) X(9) X(12) X(16) X(18) X(24) X(27) X(32) X(36) X(48) X(54) \
+    X(64) X(72) X(81) X(96) X(108) X(128) X(144) X(162) X(192) X(216) X(256) X(288) X(384) \
+    X(512) X(1024)
+
+template <typename T, int M>
+hipError_t row_fwd_go(const Geom &g, int nbatch, const RowFwdArgs &a, int &nblocks, hipStream_t s)
+{
+    constexpr int P = row_P<T, M>();
+    const long long nrows = (long long)g.n0 * g.n1;
+    nblocks = (int)((nrows + P - 1) / P);
+    if (a.partials && nblocks > a.pstride) return hipErrorInvalidValue;
+    if (a.nfields < 0 || a.nfields > MAXKB) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nbatch);
+    hipLaunchKernelGGL((k_row_fwd<T, M>), grid, dim3(NT), 0, s, a, g);
+    return hipGetLastError();
+}
+
+template <typename T, int M>
+hipError_t row_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s)
+{
+    constexpr int P = row_P<T, M>();
+    const long long nrows = (long long)g.n0 * g.n1;
+    nblocks = (int)((nrows + P - 1) / P);
+    if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
+    dim3 grid(nblocks, a.nbatch);
+    hipLaunchKernelGGL((k_row_inv<T, M>), grid, dim3(NT), 0, s, a, g);
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
+{
+    constexpr int P = col_P<T, L>();
+    nblocks = (int)((a.ncols + P - 1) / P);
+    bool has_part = false;
+    for (int f = 0; f < MAXKB; ++f) has_part |= (a.op[f] == GO_HEXT || a.op[f] == GO_VW);
+    if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
+    dim3 grid(nblocks, nfb);
+    hipLaunchKernelGGL((k_col<T, L>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t knot_inv_go(const KnotArgs &a, hipStream_t s)
+{
+    constexpr int P = col_P<T, L>();
+    dim3 grid((unsigned)((a.ncols + P - 1) / P), a.nbatch);
+    hipLaunchKernelGGL((k_knot_inv<T, L>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
+{
+    constexpr int P = col_P<T, L>();
+    dim3 grid((unsigned)((a.ncols + P - 1) / P), a.nbatch);
+    hipLaunchKernelGGL((k_knot_acc<T, L>), grid, dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+#define OFDFT_INSTANTIATE_LAUNCHERS(T)                                                          \
+    template <> hipError_t launch_row_fwd<T>(const Geom &g, int nbatch, const RowFwdArgs &a,   \
+                                             int &nb, hipStream_t s)                           \
+    {                                                                                          \
+        switch (g.m) {                                                                         \
+            OFDFT_LENGTHS(OFDFT_CASE_ROWF_##T)                                                 \
+        default: return hipErrorInvalidValue;                                                  \
+        }                                                                                      \
+    }                                                                                          \
+    template <> hipError_t launch_row_inv<T>(const Geom &g, const RowInvArgs &a, int &nb,      \
+                                             hipStream_t s)                                    \
+    {                                                                                          \
+        switch (g.m) {                                                                         \
+            OFDFT_LENGTHS(OFDFT_CASE_ROWI_##T)                                                 \
+        default: return hipErrorInvalidValue;                                                  \
+        }                                                                                      \
+    }                                                                                          \
+    template <> hipError_t launch_col<T>(int L, int nfb, const ColArgs &a, int &nb,            \
+                                         hipStream_t s)                                        \
+    {                                                                                          \
+        switch (L) {                                                                           \
+            OFDFT_LENGTHS(OFDFT_CASE_COL_##T)                                                  \
+        default: return hipErrorInvalidValue;                                                  \
+        }                                                                                      \
+    }                                                                                          \
+    template <> hipError_t launch_knot_inv<T>(const KnotArgs &a, hipStream_t s)                \
+    {                                                                                          \
+        switch (a.g.n0) {                                                                      \
+            OFDFT_LENGTHS(OFDFT_CASE_KI_##T)                                                   \
+        default: return hipErrorInvalidValue;                                                  \
+        }                                                                                      \
+    }                                                                                          \
+    template <> hipError_t launch_knot_acc<T>(const KnotArgs &a, hipStream_t s)                \
+    {                                                                                          \
+        switch (a.g.n0) {                                                                      \
+            OFDFT_LENGTHS(OFDFT_CASE_KA_##T)                                                   \
+        default: return hipErrorInvalidValue;                                                  \
+        }                                                                                      \
+    }                                                                                          \
+    template <> int row_blocks<T>(const Geom &g)                                               \
+    {                                                                                          \
+        switch (g.m) {                                                                         \
+            OFDFT_LENGTHS(OFDFT_CASE_RB_##T)                                                   \
+        default: return 0;                                                                     \
+        }                                                                                      \
+    }                                                                                          \
+    template <> int col_blocks<T>(int L, long long ncols)                                      \
+    {                                                                                          \
+        switch (L) {                                                                           \
+            OFDFT_LENGTHS(OFDFT_CASE_CB_##T)                                                   \
+        default: return 0;                                                                     \
+        }                                                                                      \
+    }
+
+#define OFDFT_CASE_ROWF_float(L) case L: return row_fwd_go<float, L>(g, nbatch, a, nb, s);
+#define OFDFT_CASE_ROWF_double(L) case L: return row_fwd_go<double, L>(g, nbatch, a, nb, s);
+#define OFDFT_CASE_ROWI_float(L) case L: return row_inv_go<float, L>(g, a, nb, s);
+#define OFDFT_CASE_ROWI_double(L) case L: return row_inv_go<double, L>(g, a, nb, s);
+#define OFDFT_CASE_COL_float(L) case L: return col_go<float, L>(nfb, a, nb, s);
+#define OFDFT_CASE_COL_double(L) case L: return col_go<double, L>(nfb, a, nb, s);
+#define OFDFT_CASE_KI_float(L) case L: return knot_inv_go<float, L>(a, s);
+#define OFDFT_CASE_KI_double(L) case L: return knot_inv_go<double, L>(a, s);
+#define OFDFT_CASE_KA_float(L) case L: return knot_acc_go<float, L>(a, s);
+#define OFDFT_CASE_KA_double(L) case L: return knot_acc_go<double, L>(a, s);
+#define OFDFT_CASE_RB_float(L) case L: return (int)(((long long)g.n0 * g.n1 + row_P<float, L>() - 1) / row_P<float, L>());
+#define OFDFT_CASE_RB_double(L) case L: return (int)(((long long)g.n0 * g.n1 + row_P<double, L>() - 1) / row_P<double, L>());
+#define OFDFT_CASE_CB_float(L) case L: return (int)((ncols + col_P<float, L>() - 1) / col_P<float, L>());
+#define OFDFT_CASE_CB_double(L) case L: return (int)((ncols + col_P<double, L>() - 1) / col_P<double, L>());
+
+}  // namespace ofdft

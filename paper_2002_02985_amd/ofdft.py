@@ -1,0 +1,317 @@
+"""ctypes binding of libofdft.so (argument marshalling only).
+
+Every function named ``ofdft_*`` here calls the C entry point of the same name
+declared in ``include/ofdft.h``; all computation happens in the library's HIP
+kernels.  ``load()`` raises if the library has not been built -- there is no
+fallback.  Device arrays are passed as raw pointers (e.g. ``tensor.data_ptr()``
+of a torch tensor on the GPU) together with a HIP stream handle.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libofdft.so")
+
+OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOCONV, ECANCELLED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
+TERM_TF, TERM_VW, TERM_HARTREE, TERM_EXT, TERM_WT, TERM_SPLINE = 1, 2, 4, 8, 16, 32
+KNOTS_LOG, KNOTS_LIN = 0, 1
+NL_S3S4, NL_EXACT = 0, 1
+FP64, MIXED = 0, 1
+PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
+              "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
+
+
+class CellDesc(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_double * 9), ("n", ctypes.c_int32 * 3),
+                ("natoms", ctypes.c_int32), ("pos", ctypes.POINTER(ctypes.c_double)),
+                ("species", ctypes.POINTER(ctypes.c_int32)), ("nspecies", ctypes.c_int32),
+                ("Z", ctypes.POINTER(ctypes.c_double)), ("rc", ctypes.POINTER(ctypes.c_double)),
+                ("nelec", ctypes.c_double)]
+
+
+class FunctionalDesc(ctypes.Structure):
+    _fields_ = [("terms", ctypes.c_uint32), ("lambda_vw", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("kf_wt", ctypes.c_double), ("nk", ctypes.c_int32), ("kf_min", ctypes.c_double),
+                ("kf_max", ctypes.c_double), ("knot_spacing", ctypes.c_int32),
+                ("nl_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rho_floor", ctypes.c_double)]
+
+
+class Energy(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in
+                ("e_tf", "e_vw", "e_h", "e_ext", "e_nl", "e_ion", "e_total", "mu", "nelec_int",
+                 "resid_norm")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class OptParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("warm", ctypes.c_int32)]
+
+
+class OptResult(ctypes.Structure):
+    _fields_ = [("e", Energy), ("iters", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("final_resid", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_DP = ctypes.POINTER(ctypes.c_double)
+_SIGS = {
+    "ofdft_abi_version": (ctypes.c_int, []),
+    "ofdft_last_error": (ctypes.c_char_p, []),
+    "ofdft_supported_length": (ctypes.c_int, [ctypes.c_int32]),
+    "ofdft_ctx_create": (ctypes.c_int, [ctypes.c_int, _PP]),
+    "ofdft_ctx_destroy": (None, [_P]),
+    "ofdft_grid_create": (ctypes.c_int, [_P, ctypes.POINTER(CellDesc),
+                                         ctypes.POINTER(FunctionalDesc), _PP]),
+    "ofdft_grid_destroy": (None, [_P]),
+    "ofdft_grid_reserve": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_device_bytes": (ctypes.c_uint64, [_P]),
+    "ofdft_set_density": (ctypes.c_int, [_P, _DP]),
+    "ofdft_get_density": (ctypes.c_int, [_P, _DP]),
+    "ofdft_energy_potential": (ctypes.c_int, [_P, _DP, _DP, ctypes.POINTER(Energy)]),
+    "ofdft_energy_potential_dev": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(Energy)]),
+    "ofdft_energy_potential_batch_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P,
+                                                        ctypes.POINTER(Energy)]),
+    "ofdft_fft_r2c_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "ofdft_fft_c2r_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "ofdft_forces": (ctypes.c_int, [_P, _DP]),
+    "ofdft_optimize": (ctypes.c_int, [_P, ctypes.POINTER(OptParams), ctypes.POINTER(OptResult)]),
+    "ofdft_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_profile_read": (ctypes.c_int, [_P, ctypes.c_int32, _DP,
+                                          ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libofdft.so; raises OSError if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise OSError("libofdft.so not found at %s: run paper_2002_02985_amd/build.py" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class OfdftError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ofdft status %d: %s" % (status, msg))
+        self.status = status
+
+
+def check(status):
+    if status not in (OK,):
+        raise OfdftError(status, load().ofdft_last_error().decode())
+    return status
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+# ------------------------------------------------------------------ C names
+def ofdft_abi_version():
+    return load().ofdft_abi_version()
+
+
+def ofdft_supported_length(n):
+    return bool(load().ofdft_supported_length(int(n)))
+
+
+def ofdft_ctx_create(device=0):
+    h = ctypes.c_void_p()
+    check(load().ofdft_ctx_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def ofdft_ctx_destroy(ctx):
+    load().ofdft_ctx_destroy(ctx)
+
+
+def make_cell_desc(cell):
+    """CellDesc from a workloads dict; returns (desc, keepalive arrays)."""
+    lat = np.ascontiguousarray(cell["lattice"], dtype=np.float64).reshape(9)
+    pos = np.ascontiguousarray(cell["pos"], dtype=np.float64).reshape(-1)
+    spc = np.ascontiguousarray(cell["species"], dtype=np.int32).reshape(-1)
+    Z = np.ascontiguousarray(cell["Z"], dtype=np.float64)
+    rc = np.ascontiguousarray(cell["rc"], dtype=np.float64)
+    d = CellDesc()
+    d.lattice[:] = list(lat)
+    d.n[:] = [int(x) for x in cell["n"]]
+    d.natoms = len(spc)
+    d.pos = _dptr(pos)
+    d.species = spc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.nspecies = len(Z)
+    d.Z = _dptr(Z)
+    d.rc = _dptr(rc)
+    d.nelec = float(cell["nelec"])
+    return d, (lat, pos, spc, Z, rc)
+
+
+def make_functional_desc(terms, precision=FP64, lambda_vw=1.0, alpha=5.0 / 6.0, beta=5.0 / 6.0,
+                         kf_wt=0.0, nk=32, kf_min=0.1, kf_max=3.0, knot_spacing=KNOTS_LOG,
+                         nl_mode=NL_S3S4, rho_floor=1e-12):
+    f = FunctionalDesc()
+    f.terms = int(terms)
+    f.lambda_vw = lambda_vw
+    f.alpha = alpha
+    f.beta = beta
+    f.kf_wt = kf_wt
+    f.nk = nk
+    f.kf_min = kf_min
+    f.kf_max = kf_max
+    f.knot_spacing = knot_spacing
+    f.nl_mode = nl_mode
+    f.precision = precision
+    f.rho_floor = rho_floor
+    return f
+
+
+def ofdft_grid_create(ctx, cell_desc, func_desc):
+    h = ctypes.c_void_p()
+    check(load().ofdft_grid_create(ctx, ctypes.byref(cell_desc), ctypes.byref(func_desc),
+                                   ctypes.byref(h)))
+    return h
+
+
+def ofdft_grid_destroy(grid):
+    load().ofdft_grid_destroy(grid)
+
+
+def ofdft_grid_reserve(grid, nbatch):
+    check(load().ofdft_grid_reserve(grid, int(nbatch)))
+
+
+def ofdft_grid_device_bytes(grid):
+    return int(load().ofdft_grid_device_bytes(grid))
+
+
+def ofdft_set_density(grid, rho):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    check(load().ofdft_set_density(grid, _dptr(rho)))
+
+
+def ofdft_get_density(grid, shape):
+    out = np.empty(shape, dtype=np.float64)
+    check(load().ofdft_get_density(grid, _dptr(out)))
+    return out
+
+
+def ofdft_energy_potential(grid, rho=None, want_v=True, shape=None):
+    e = Energy()
+    rp = None
+    if rho is not None:
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        rp = _dptr(rho)
+        shape = rho.shape
+    v = np.empty(shape, dtype=np.float64) if want_v else None
+    check(load().ofdft_energy_potential(grid, rp, _dptr(v) if want_v else None, ctypes.byref(e)))
+    return e, v
+
+
+def ofdft_energy_potential_dev(grid, d_rho, d_v, stream):
+    e = Energy()
+    check(load().ofdft_energy_potential_dev(grid, d_rho, d_v, stream, ctypes.byref(e)))
+    return e
+
+
+def ofdft_energy_potential_batch_dev(grid, nbatch, d_rho, d_v, stream):
+    es = (Energy * int(nbatch))()
+    check(load().ofdft_energy_potential_batch_dev(grid, int(nbatch), d_rho, d_v, stream, es))
+    return list(es)
+
+
+def ofdft_fft_r2c_dev(grid, nbatch, d_in, d_out, stream):
+    check(load().ofdft_fft_r2c_dev(grid, int(nbatch), d_in, d_out, stream))
+
+
+def ofdft_fft_c2r_dev(grid, nbatch, d_in, d_out, stream):
+    check(load().ofdft_fft_c2r_dev(grid, int(nbatch), d_in, d_out, stream))
+
+
+def ofdft_forces(grid, natoms):
+    f = np.empty((natoms, 3), dtype=np.float64)
+    check(load().ofdft_forces(grid, _dptr(f)))
+    return f
+
+
+def ofdft_optimize(grid, tol=1e-7, max_iter=1000, method=0, allow_noconv=False):
+    p = OptParams(tol=tol, max_iter=max_iter, method=method, warm=0)
+    r = OptResult()
+    st = load().ofdft_optimize(grid, ctypes.byref(p), ctypes.byref(r))
+    if not (st == OK or (allow_noconv and st == ENOCONV)):
+        check(st)
+    return r, st
+
+
+def ofdft_profile_enable(grid, on=True):
+    check(load().ofdft_profile_enable(grid, 1 if on else 0))
+
+
+def ofdft_profile_read(grid, pass_id):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(load().ofdft_profile_read(grid, int(pass_id), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ------------------------------------------------------------------ convenience
+class Grid:
+    """Owns a context and a grid for one cell/functional."""
+
+    def __init__(self, cell, terms, precision=FP64, device=0, ctx=None, **func_kw):
+        self.cell = cell
+        self.shape = tuple(int(x) for x in cell["n"])
+        self.natoms = len(cell["species"])
+        self._own_ctx = ctx is None
+        self.ctx = ofdft_ctx_create(device) if ctx is None else ctx
+        cd, self._keep = make_cell_desc(cell)
+        fd = make_functional_desc(terms, precision=precision, **func_kw)
+        self.fp64 = precision == FP64
+        self.handle = ofdft_grid_create(self.ctx, cd, fd)
+
+    @property
+    def field_dtype(self):
+        return np.float64 if self.fp64 else np.float32
+
+    def close(self):
+        if self.handle:
+            ofdft_grid_destroy(self.handle)
+            self.handle = None
+        if self._own_ctx and self.ctx:
+            ofdft_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def energy_potential(self, rho=None, want_v=True):
+        return ofdft_energy_potential(self.handle, rho, want_v, self.shape)
+
+    def set_density(self, rho):
+        ofdft_set_density(self.handle, rho)
+
+    def get_density(self):
+        return ofdft_get_density(self.handle, self.shape)
+
+    def forces(self):
+        return ofdft_forces(self.handle, self.natoms)
+
+    def optimize(self, tol=1e-7, max_iter=1000, allow_noconv=False):
+        return ofdft_optimize(self.handle, tol, max_iter, allow_noconv=allow_noconv)

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (stated per result):
+* FP64 path: relative 1e-10 in every energy term, 1e-9 Ha absolute in the
+  potential, 1e-8 Ha/Bohr in forces; FFTs to 1e-12 of the spectrum's scale.
+* Mixed path (FP32 fields, FP64 reductions): |dE| <= 1e-5 Ha per atom,
+  max |dv| <= 1e-4 Ha on points with rho >= 1e-6, forces <= 1e-4 Ha/Bohr;
+  FFTs to 2e-6 of the spectrum's scale.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cell as OC
+from oracle import functionals as OF
+from oracle.ewald import ewald_energy, forces as oracle_forces
+from oracle.fourier import c2r as o_c2r, r2c as o_r2c
+from paper_2002_02985_amd import ofdft
+from paper_2002_02985_amd import workloads as W
+from tests.gpu_helpers import eval_batch, fft_c2r, fft_r2c
+from tests.oracle_helpers import make_cell, smooth_density
+
+pytestmark = pytest.mark.gpu
+
+LOCAL = ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT
+ENERGY_KEYS = ("e_tf", "e_vw", "e_h", "e_ext", "e_nl", "e_ion", "e_total")
+
+
+def oracle_func(terms, **kw):
+    return OC.Functional(terms=int(terms), **kw)
+
+
+def box(n, L=(9.0, 10.0, 11.0), natoms=3, seed=0, Z=2.0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, size=(natoms, 3)) * np.array(L)
+    return {"lattice": np.diag(L), "n": n, "pos": pos, "species": np.zeros(natoms, np.int32),
+            "Z": np.array([Z]), "rc": np.array([1.0]), "nelec": Z * natoms}
+
+
+def varied_rho(cell_d, seed=1, amp=0.9, rho0=0.03):
+    c = make_cell(cell_d)
+    return smooth_density(c, seed=seed, amp=amp, nmodes=3, rho0=rho0)
+
+
+def compare(e_gpu, v_gpu, ro, rho, natoms, fp64, label=""):
+    if fp64:
+        for k in ENERGY_KEYS:
+            ref = getattr(ro, k)
+            assert abs(e_gpu[k] - ref) <= 1e-10 * max(1.0, abs(ref)), (label, k, e_gpu[k], ref)
+        assert abs(e_gpu["mu"] - ro.mu) <= 1e-10 * max(1.0, abs(ro.mu))
+        np.testing.assert_allclose(v_gpu, ro.v, rtol=0, atol=1e-9, err_msg=label)
+    else:
+        tol = 1e-5 * max(natoms, 1)
+        for k in ENERGY_KEYS:
+            assert abs(e_gpu[k] - getattr(ro, k)) <= tol, (label, k, e_gpu[k], getattr(ro, k))
+        mask = rho >= 1e-6
+        err = np.abs(v_gpu - ro.v)[mask].max()
+        assert err <= 1e-4, (label, err)
+    # the mixed path rounds the input density to FP32 (relative 6e-8 per value)
+    tol_n = 1e-9 if fp64 else 1e-7
+    assert abs(e_gpu["nelec_int"] - ro.nelec_int) <= tol_n * ro.nelec_int
+
+
+# ------------------------------------------------------------------ FFT
+FFT_SHAPES = [(12, 18, 16), (24, 16, 12), (6, 4, 4), (32, 32, 32), (18, 27, 54), (96, 96, 96)]
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+@pytest.mark.parametrize("shape", FFT_SHAPES)
+def test_fft_pair_against_oracle(shape, prec):
+    print("case fft", shape, prec, flush=True)
+    cell = box(shape)
+    rng = np.random.default_rng(sum(shape))
+    nb = 2
+    f = rng.standard_normal((nb,) + shape)
+    with ofdft.Grid(cell, ofdft.TERM_TF, precision=prec) as g:
+        X = fft_r2c(g, f)
+        ref = np.stack([o_r2c(f[b]) for b in range(nb)])
+        scale = np.abs(ref).max()
+        tol = 1e-12 if prec == ofdft.FP64 else 2e-6
+        assert np.abs(X - ref).max() <= tol * scale
+        # inverse of the oracle spectrum (with imaginary parts on the
+        # self-conjugate planes, which the inverse must drop)
+        spec = ref.copy()
+        spec[:, 0, 0, 0] += 0.3j
+        back = fft_c2r(g, spec)
+        rref = np.stack([o_c2r(spec[b], shape) for b in range(nb)])
+        assert np.abs(back - rref).max() <= tol * np.abs(rref).max() * 4
+
+
+# ------------------------------------------------------------------ energies
+def c1_cell():
+    cell, rho = W.config_c1()
+    return cell, rho
+
+
+CASES = {
+    "c1_local": (lambda: c1_cell(), LOCAL, {}),
+    "c1_wt": (lambda: c1_cell(), LOCAL | ofdft.TERM_WT, {}),
+    "box_tf_only": (lambda: (box((12, 18, 16)), None), ofdft.TERM_TF, {}),
+    "box_hartree_only": (lambda: (box((12, 18, 16)), None), ofdft.TERM_HARTREE, {}),
+    "box_wt": (lambda: (box((24, 16, 12)), None), ofdft.TERM_VW | ofdft.TERM_WT, {}),
+    "box_spline_s3s4": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_SPLINE,
+                        dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    "box_spline_exact": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_SPLINE,
+                         dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT)),
+    "box_spline_lin_exact": (lambda: (box((18, 16, 24)), None), ofdft.TERM_SPLINE,
+                             dict(nk=13, kf_min=0.4, kf_max=1.9, knot_spacing=ofdft.KNOTS_LIN,
+                                  nl_mode=ofdft.NL_EXACT)),
+}
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_energy_potential_parity(name, prec):
+    print("case energy", name, prec, flush=True)
+    mk, terms, kw = CASES[name]
+    cell, rho = mk()
+    if rho is None:
+        rho = varied_rho(cell)
+    oc = make_cell(cell)
+    ro = OF.energy_potential(oc, oracle_func(terms, **kw), rho=rho)
+    with ofdft.Grid(cell, terms, precision=prec, **kw) as g:
+        e, v = g.energy_potential(rho)
+        compare(e.as_dict(), v, ro, rho, len(cell["species"]), prec == ofdft.FP64, name)
+        # resident-density path gives the same numbers
+        g.set_density(rho)
+        e2, _ = g.energy_potential(None, want_v=False)
+        assert e2.e_total == e.e_total
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_batch_matches_single(prec):
+    cell, _ = c1_cell()
+    rhos = [varied_rho(cell, seed=s, amp=0.5, rho0=12 / 7.65 ** 3) for s in range(3)]
+    terms = LOCAL | ofdft.TERM_WT
+    with ofdft.Grid(cell, terms, precision=prec) as g:
+        es, vs = eval_batch(g, rhos)
+        for b, rho in enumerate(rhos):
+            e1, v1 = g.energy_potential(rho)
+            for k in ENERGY_KEYS + ("mu", "resid_norm"):
+                assert es[b][k] == getattr(e1, k), (b, k)
+            assert np.array_equal(vs[b], v1.astype(vs.dtype)) if prec == ofdft.FP64 else \
+                np.abs(vs[b] - v1).max() == 0.0
+
+
+def test_input_validation():
+    cell, rho = c1_cell()
+    with ofdft.Grid(cell, LOCAL) as g:
+        bad = rho.copy()
+        bad[3, 4, 5] = -1.0
+        with pytest.raises(ofdft.OfdftError) as ei:
+            g.energy_potential(bad)
+        assert ei.value.status == ofdft.EINVAL
+        bad[3, 4, 5] = np.nan
+        with pytest.raises(ofdft.OfdftError):
+            g.energy_potential(bad)
+    bad_cell = dict(cell)
+    bad_cell["n"] = (30, 32, 32)
+    with pytest.raises(ofdft.OfdftError) as ei:
+        ofdft.Grid(bad_cell, LOCAL)
+    assert ei.value.status == ofdft.EINVAL
+
+
+# ------------------------------------------------------------------ forces
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_forces_parity(prec):
+    cell = W.al_fcc_cell(1, (24, 24, 24), jitter=0.15, seed=21)
+    oc = make_cell(cell)
+    rho = smooth_density(oc, seed=8)
+    ro = OF.energy_potential(oc, OC.Functional(terms=OC.EXT), rho=rho)
+    ref = oracle_forces(oc, ro.rho_g)
+    with ofdft.Grid(cell, LOCAL, precision=prec) as g:
+        g.set_density(rho)
+        F = g.forces()
+    tol = 1e-8 if prec == ofdft.FP64 else 1e-4
+    assert np.abs(F - ref).max() <= tol, np.abs(F - ref).max()
+
+
+# ------------------------------------------------------------------ optimiser
+def test_optimize_c1_fp64_matches_oracle_minimum():
+    from oracle.optimize import optimize as o_opt
+    cell, rho = c1_cell()
+    oc = make_cell(cell)
+    func = OC.Functional(terms=int(LOCAL))
+    ref = o_opt(oc, func, np.sqrt(rho), tol=1e-7, max_iter=500, vext=OF.vext_g(oc),
+                e_ion=ewald_energy(oc))
+    assert ref.converged
+    with ofdft.Grid(cell, LOCAL) as g:
+        g.set_density(rho)
+        r, st = g.optimize(tol=1e-7, max_iter=500)
+        assert st == ofdft.OK
+        rho_gpu = g.get_density()
+    assert r.final_resid < 1e-7
+    assert abs(r.e.e_total - ref.result.e_total) < 1e-9
+    assert abs(oc.dv * rho_gpu.sum() - cell["nelec"]) < 1e-10
+    np.testing.assert_allclose(rho_gpu, ref.phi ** 2, atol=1e-6)
