@@ -1,0 +1,238 @@
+"""Benchmark: orbital-free DFT energy+potential evaluations on one MI355X.
+
+Workload: fcc Al, 3x3x3 conventional cells (108 atoms, a = 22.95 Bohr) on a
+96^3 grid with the Wang-Teter nonlocal functional (alpha = beta = 5/6, kernel
+at the cell's average k_F) + von Weizsaecker + Thomas-Fermi + Hartree + the
+local pseudopotential (Z = 3, rc = 1 Bohr).  One step evaluates the energy
+and the potential of 200 seeded densities (Gaussian superposition times
+1 + 0.01 noise, seeds 1000..1199) in one batched call of the mixed-precision
+path (FP32 fields and FFTs, FP64 reductions).  The same batch is also run on
+the plain FP64 path; the line reports both, the energy difference per atom
+between them, p50/p99 step latency, the roofline of the dominant kernel and
+the oracle's CPU throughput on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NDENS = 200
+N_GRID = (96, 96, 96)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=4,
+                    help="densities evaluated by the oracle for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 256 MiB first (counter calibration)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(name, nb, N, Nh, nfields, w):
+    """Algorithmic HBM bytes of one launch of a pass: each input array read
+    once, each output written once (w = bytes per real)."""
+    cw = 2 * w
+    if name == "row_fwd":
+        return nb * N * w + nfields * nb * Nh * cw
+    if name in ("col1_fwd", "col0_g", "col1_inv"):
+        extra = Nh * cw if name == "col0_g" else 0        # v_ext(G), read once
+        return 2 * nfields * nb * Nh * cw + extra
+    if name == "row_inv":
+        return nfields * nb * Nh * cw + 2 * nb * N * w    # spectra + input in, v out
+    return 0
+
+
+def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile):
+    terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
+             ofdft.TERM_WT)
+    dt = torch.float64 if precision == ofdft.FP64 else torch.float32
+    g = ofdft.Grid(cell, terms, precision=precision)
+    ofdft.ofdft_grid_reserve(g.handle, NDENS)
+    x = torch.empty((NDENS,) + N_GRID, dtype=dt, device="cuda:0")
+    for b in range(NDENS):
+        x[b].copy_(torch.from_numpy(dens[b]))
+    v = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    for _ in range(warmup):
+        es = ofdft.ofdft_energy_potential_batch_dev(g.handle, NDENS, x.data_ptr(), v.data_ptr(), sh)
+    torch.cuda.synchronize()
+    if profile:
+        ofdft.ofdft_profile_enable(g.handle, True)
+    lat = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        es = ofdft.ofdft_energy_potential_batch_dev(g.handle, NDENS, x.data_ptr(), v.data_ptr(), sh)
+        lat.append(time.perf_counter() - s0)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = t_start.elapsed_time(t_end)
+    passes = {}
+    if profile:
+        for i, name in enumerate(ofdft.PASS_NAMES):
+            ms, n = ofdft.ofdft_profile_read(g.handle, i)
+            if n:
+                passes[name] = (ms, n)
+        ofdft.ofdft_profile_enable(g.handle, False)
+    energies = np.array([e.e_total for e in es])
+    dev_bytes = ofdft.ofdft_grid_device_bytes(g.handle)
+    g.close()
+    del x, v
+    torch.cuda.empty_cache()
+    return {"wall": wall, "gpu_ms": gpu_ms, "lat": lat, "energies": energies, "passes": passes,
+            "dev_bytes": dev_bytes}
+
+
+def cpu_baseline(cell, dens, nsample):
+    from oracle import cell as OC
+    from oracle import functionals as OF
+    from oracle.ewald import ewald_energy
+    from tests.oracle_helpers import make_cell
+    oc = make_cell(cell)
+    func = OC.Functional(terms=OC.TF | OC.VW | OC.HARTREE | OC.EXT | OC.WT)
+    vx = OF.vext_g(oc)
+    ei = ewald_energy(oc)
+    out = []
+    t0 = time.perf_counter()
+    for b in range(nsample):
+        r = OF.energy_potential(oc, func, rho=dens[b], vext=vx, e_ion=ei)
+        out.append(r.e_total)
+    t = time.perf_counter() - t0
+    return t, np.array(out)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+              "(per-GPU throughput is the single-GPU figure)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
+
+    log("generating %d densities on %s" % (NDENS, N_GRID))
+    cell, dens = W.config_c2(N_GRID, NDENS)
+    natoms = len(cell["species"])
+    N = int(np.prod(N_GRID))
+    Nh = N_GRID[0] * N_GRID[1] * (N_GRID[2] // 2 + 1)
+
+    log("mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps))
+    mixed = run_gpu_batch(ofdft, torch, cell, dens, ofdft.MIXED, args.steps, args.warmup, True)
+    fp64 = None
+    if not args.no_fp64:
+        log("fp64 path")
+        fp64 = run_gpu_batch(ofdft, torch, cell, dens, ofdft.FP64, max(3, args.steps // 2),
+                             args.warmup, True)
+
+    ms_step = mixed["wall"] * 1e3 / args.steps
+    value = NDENS * N / (ms_step * 1e-3) / 1e9
+    lat = np.array(mixed["lat"]) * 1e3
+
+    # dominant kernel of the mixed path
+    nfields = 3
+    best = None
+    for name, (ms, n) in mixed["passes"].items():
+        if best is None or ms > best[1]:
+            best = (name, ms, n)
+    name, ms, n = best
+    avg_ms = ms / n
+    nbytes = pass_bytes(name, NDENS, N, Nh, nfields, 4)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 4)}
+    passes_out = {}
+    for k, (pms, pn) in mixed["passes"].items():
+        b = pass_bytes(k, NDENS, N, Nh, nfields, 4)
+        passes_out[k] = {"avg_ms": round(pms / pn, 4), "launches": pn,
+                         "GB/s": round(b / (pms / pn * 1e-3) / 1e9, 1) if b else None}
+
+    line = {
+        "metric": "energy+potential evals/s (Gpts/s) mixed vs FP64 at dE<=1e-5 Ha/atom; p50/p99",
+        "value": round(value, 3),
+        "unit": "Gpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "gpu_event_ms_per_step": round(mixed["gpu_ms"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fcc Al 3x3x3 (108 atoms, a=22.95 Bohr), 96^3 grid, "
+                               "WT+vW+TF+Hartree+local pseudopotential, 200 seeded densities "
+                               "per step, mixed precision (FP32 fields, FP64 reductions)",
+                   "grid": list(N_GRID), "densities_per_step": NDENS, "natoms": natoms},
+        "evals_per_s": round(NDENS / (ms_step * 1e-3), 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "per_density_p50": round(float(np.percentile(lat, 50)) / NDENS, 4)},
+        "passes": passes_out,
+        "device_bytes": mixed["dev_bytes"],
+        "roofline": roof,
+    }
+    if fp64 is not None:
+        ms64 = fp64["wall"] * 1e3 / max(3, args.steps // 2)
+        dE = np.abs(mixed["energies"] - fp64["energies"]) / natoms
+        line["fp64"] = {"value": round(NDENS * N / (ms64 * 1e-3) / 1e9, 3), "unit": "Gpts/s",
+                        "ms_per_step": round(ms64, 3)}
+        line["mixed_vs_fp64"] = {"max_dE_per_atom": float(dE.max()),
+                                 "speedup": round(ms64 / ms_step, 3),
+                                 "within_1e-5": bool(dE.max() <= 1e-5)}
+
+    if not args.no_cpu:
+        log("oracle CPU baseline on %d densities" % args.cpu_sample)
+        t, e_or = cpu_baseline(cell, dens, args.cpu_sample)
+        line["cpu_baseline"] = {"value": round(args.cpu_sample * N / t / 1e9, 6), "unit": "Gpts/s",
+                                "cores": 1, "kind": "oracle",
+                                "sample": "%d of the 200 densities, one FP64 evaluation each "
+                                          "(%.1f s)" % (args.cpu_sample, t)}
+        ref = fp64["energies"][:args.cpu_sample] if fp64 is not None else None
+        line["oracle_check"] = {
+            "max_dE_per_atom_mixed": float(np.max(np.abs(mixed["energies"][:args.cpu_sample] - e_or)) / natoms),
+            "max_rel_dE_fp64": (float(np.max(np.abs(ref - e_or) / np.abs(e_or))) if ref is not None else None)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,6 +88,8 @@ struct ofdft_grid {
     Geom geom;
     double V = 0, dv = 0;
     Knots knots;
+    std::vector<double> knot_host;
+    double *d_knots = nullptr;
     double kf_wt = 0;
     double e_ion = 0;
     // device tables
@@ -339,7 +341,7 @@ static int max_pstride(const ofdft_grid *g)
         c0 = col_blocks<float>(G.n0, (long long)G.n1 * G.n2h);
         c1 = col_blocks<float>(G.n1, (long long)G.n0 * G.n2h);
     }
-    return std::max({rb, c0, c1, dots_blocks(G.N), 1});
+    return std::max({rb, c0, c1, dots_blocks(G.N), G.n0, 1});
 }
 
 static ofdft_status reserve(ofdft_grid *g, int nb)
@@ -473,13 +475,18 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     rf.pstride = g->pstride;
     rf.twM = g->twM;
     rf.twN = g->twN;
+    rf.tw1 = g->tw1;
+    // grids whose (i1, k2) plane fits in LDS fuse passes 1+2 and 4+5
+    const bool plane = plane_supported<T>(G.n1, G.m);
     int nb_row = 0;
-    TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
+    if (plane) TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nb_row, s));
+    else TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
 
     int nb_col0 = 0;
     if (l.nfwd > 0) {
         // 2. axis 1 forward
-        ST_TRY(col_pass<T>(g, s, 1, g->spec, l.nfwd * nb, nb, 0, nullptr, PS_COL1_FWD));
+        if (!plane)
+            ST_TRY(col_pass<T>(g, s, 1, g->spec, l.nfwd * nb, nb, 0, nullptr, PS_COL1_FWD));
         // 3. axis 0: forward, reciprocal-space term, inverse
         int ops[4] = {0, 0, 0, 0};
         if (l.s_rho >= 0) ops[l.s_rho] = GO_HEXT;
@@ -507,7 +514,8 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
             ka.tw = g->tw0;
             ka.g = G;
             TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
-            ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1));
+            if (!plane)
+                ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1));
             RowInvArgs ri;
             std::memset(&ri, 0, sizeof(ri));
             ri.spec = g->kspec;
@@ -526,9 +534,11 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
             ri.nbatch = nb;
             ri.twM = g->twM;
             ri.twN = g->twN;
+            ri.tw1 = g->tw1;
             ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
             int nbk = 0;
-            TIMED(PS_KNOT_ROW, launch_row_inv<T>(G, ri, nbk, s));
+            if (plane) TIMED(PS_KNOT_ROW, launch_plane_inv<T>(G, ri, nbk, s));
+            else TIMED(PS_KNOT_ROW, launch_row_inv<T>(G, ri, nbk, s));
             if (exact) {
                 // f_i = rho^a L_i(k~): r2c, axis 1, then axis 0 with omega_i, summed into H
                 RowFwdArgs ef = rf;
@@ -539,8 +549,12 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
                 ef.knot0 = k0;
                 ef.partials = 0;
                 int nbe = 0;
-                TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
-                ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD));
+                if (plane) {
+                    TIMED(PS_EXACT_FWD, launch_plane_fwd<T>(G, nb, ef, nbe, s));
+                } else {
+                    TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
+                    ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD));
+                }
                 KnotArgs kc = ka;
                 kc.src = g->kspec;
                 kc.dst = slot_ptr(l.s_h);
@@ -550,12 +564,14 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
         }
         if (exact) {
             ST_TRY(col_pass<T>(g, s, 0, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
-            ST_TRY(col_pass<T>(g, s, 1, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
+            if (!plane)
+                ST_TRY(col_pass<T>(g, s, 1, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
         }
     }
 
     // 4. axis 1 inverse of the fields that return to real space
-    if (l.ninv > 0) ST_TRY(col_pass<T>(g, s, 1, g->spec, l.ninv * nb, nb, 1, nullptr, PS_COL1_INV));
+    if (l.ninv > 0 && !plane)
+        ST_TRY(col_pass<T>(g, s, 1, g->spec, l.ninv * nb, nb, 1, nullptr, PS_COL1_INV));
 
     // 5. axis-2 c2r and the final combine
     RowInvArgs rc;
@@ -585,8 +601,10 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     rc.nbatch = nb;
     rc.twM = g->twM;
     rc.twN = g->twN;
+    rc.tw1 = g->tw1;
     int nb_inv = 0;
-    TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));
+    if (plane) TIMED(PS_ROW_INV, launch_plane_inv<T>(G, rc, nb_inv, s));
+    else TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));
 
     // 6. fixed-order FP64 sums
     int cnt[NSLOT] = {0};
@@ -657,10 +675,15 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         rf.kind[0] = FK_RAW;
         rf.twM = g->twM;
         rf.twN = g->twN;
+        rf.tw1 = g->tw1;
         rf.knots = g->knots;
         int nbk = 0;
-        TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nbk, s));
-        ST_TRY(col_pass<T>(g, s, 1, d_out, nb, nb, 0, nullptr, PS_COL1_FWD));
+        if (plane_supported<T>(G.n1, G.m)) {
+            TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nbk, s));
+        } else {
+            TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nbk, s));
+            ST_TRY(col_pass<T>(g, s, 1, d_out, nb, nb, 0, nullptr, PS_COL1_FWD));
+        }
         int ops[4] = {GO_SCALE, 0, 0, 0};
         ST_TRY(col_pass<T>(g, s, 0, d_out, nb, nb, 0, ops, PS_COL0_G));
     } else {
@@ -668,7 +691,8 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         HIP_TRY(hipMemcpyAsync(g->spec, d_in, (size_t)nb * G.Nh * 2 * sizeof(T),
                                hipMemcpyDeviceToDevice, s));
         ST_TRY(col_pass<T>(g, s, 0, g->spec, nb, nb, 1, nullptr, PS_COL0_G));
-        ST_TRY(col_pass<T>(g, s, 1, g->spec, nb, nb, 1, nullptr, PS_COL1_INV));
+        const bool plane = plane_supported<T>(G.n1, G.m);
+        if (!plane) ST_TRY(col_pass<T>(g, s, 1, g->spec, nb, nb, 1, nullptr, PS_COL1_INV));
         RowInvArgs ri;
         std::memset(&ri, 0, sizeof(ri));
         ri.spec = g->spec;
@@ -679,9 +703,11 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         ri.nbatch = nb;
         ri.twM = g->twM;
         ri.twN = g->twN;
+        ri.tw1 = g->tw1;
         ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
         int nbk = 0;
-        TIMED(PS_ROW_INV, launch_row_inv<T>(G, ri, nbk, s));
+        if (plane) TIMED(PS_ROW_INV, launch_plane_inv<T>(G, ri, nbk, s));
+        else TIMED(PS_ROW_INV, launch_row_inv<T>(G, ri, nbk, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     timer_collect(g);
@@ -746,6 +772,7 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_Z));
     dfree(reinterpret_cast<void *&>(g->d_rc));
     dfree(reinterpret_cast<void *&>(g->d_count));
+    dfree(reinterpret_cast<void *&>(g->d_knots));
     dfree(g->spec);
     dfree(g->kspec);
     dfree(g->acc1);
@@ -808,14 +835,19 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
         Knots &K = g->knots;
         K.nk = f->nk;
         K.log_spacing = f->knot_spacing == OFDFT_KNOTS_LOG;
+        std::vector<double> &k = g->knot_host;
+        k.resize(f->nk);
         for (int i = 0; i < f->nk; ++i) {
             const double u = f->nk > 1 ? (double)i / (double)(f->nk - 1) : 0.0;
-            K.k[i] = K.log_spacing ? f->kf_min * std::pow(f->kf_max / f->kf_min, u)
-                                   : f->kf_min + (f->kf_max - f->kf_min) * u;
+            k[i] = K.log_spacing ? f->kf_min * std::pow(f->kf_max / f->kf_min, u)
+                                 : f->kf_min + (f->kf_max - f->kf_min) * u;
         }
         if (f->nk > 1)
-            K.inv_span = K.log_spacing ? (f->nk - 1) / std::log(K.k[f->nk - 1] / K.k[0])
-                                       : (f->nk - 1) / (K.k[f->nk - 1] - K.k[0]);
+            K.inv_span = K.log_spacing ? (f->nk - 1) / std::log(k[f->nk - 1] / k[0])
+                                       : (f->nk - 1) / (k[f->nk - 1] - k[0]);
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_knots), k.size() * sizeof(double)));
+        HIP_TRY(hipMemcpy(g->d_knots, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice));
+        K.k = g->d_knots;
     }
     g->kf_wt = f->kf_wt > 0 ? f->kf_wt : std::cbrt(3.0 * PI * PI * g->nelec / g->V);
 

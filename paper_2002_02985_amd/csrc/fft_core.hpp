@@ -135,36 +135,43 @@ __device__ __forceinline__ void dft(cpx<T> *a)
 }
 
 // ---------------------------------------------------------------- LDS layout
-// ROW layout: element n of pencil p at buf[p * L + n], butterflies j-fastest
-//   (used for the contiguous axis, whose pencils are rows in memory).
-// COL layout: element n of pencil p at buf[n * P + p], pencils fastest
-//   (used for strided axes: a tile of P adjacent columns).
-template <bool ROW, int L, int P>
+// Element n of pencil p lives at buf[n * ES + p * PS]; butterflies are
+// assigned pencil-fastest.  Column kernels use ES = P, PS = 1 (a tile of P
+// adjacent columns); row kernels use ES = P + 1, PS = 1 so that the
+// row-ordered global loads, which walk n across lanes, also hit distinct
+// banks.  The plane kernels keep one padded buffer with odd A and run their
+// row transforms with (ES, PS) = (A, 1) and their column transforms with
+// (1, A): consecutive lanes then step by 1 or by the odd A, both free of bank
+// conflicts, and no transpose is needed between the two axes.
+template <int ES, int PS>
 __device__ __forceinline__ int lidx(int n, int p)
 {
-    if constexpr (ROW) return p * L + n;
-    else return n * P + p;
+    return n * ES + p * PS;
 }
 
 // One Stockham stage of radix R after NS points have been combined.
 // Input element (j + r L/R) of every pencil is twiddled by W_{NS R}^{r (j mod NS)},
 // transformed, and stored at (j / NS) NS R + (j mod NS) + s NS.
-template <typename T, int L, int R, int NS, bool INV, int P, int NT, bool ROW>
-__device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *__restrict__ tw,
+template <typename T, int L, int R, int NS, bool INV, int P, int NT, int ES, int PS>
+__device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
                                                int tid)
 {
     constexpr int NBF = L / R;
     constexpr int TOT = NBF * P;
     constexpr int PER = (TOT + NT - 1) / NT;
+    // an opaque copy of the thread index: the index arithmetic of this stage
+    // is recomputed here instead of being hoisted out of callers' loops and
+    // held in registers across the whole kernel
+    asm volatile("" : "+v"(tid));
     cpx<T> v[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const int b = tid + q * NT;
         if (TOT % NT == 0 || b < TOT) {
-            const int j = ROW ? (b % NBF) : (b / P);
-            const int p = ROW ? (b / NBF) : (b % P);
+            const int j = b / P;
+            const int p = b % P;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<ROW, L, P>(j + r * NBF, p)];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<ES, PS>(j + r * NBF, p)];
         }
     }
     __syncthreads();
@@ -172,8 +179,8 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *__rest
     for (int q = 0; q < PER; ++q) {
         const int b = tid + q * NT;
         if (TOT % NT == 0 || b < TOT) {
-            const int j = ROW ? (b % NBF) : (b / P);
-            const int p = ROW ? (b / NBF) : (b % P);
+            const int j = b / P;
+            const int p = b % P;
             const int k = j % NS;
             if constexpr (NS > 1) {
                 constexpr int STEP = L / (NS * R);
@@ -187,47 +194,70 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *__rest
             dft<T, R, INV>(v[q]);
             const int base = (j / NS) * NS * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lidx<ROW, L, P>(base + r * NS, p)] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[lidx<ES, PS>(base + r * NS, p)] = v[q][r];
         }
     }
     __syncthreads();
 }
 
-template <typename T, int L, bool INV, int P, int NT, bool ROW, int S, int NS>
-__device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *__restrict__ tw, int tid)
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS>
+__device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
     constexpr Plan pl = make_plan(L);
     if constexpr (S < pl.n) {
         constexpr int R = pl.r[S];
-        stockham_stage<T, L, R, NS, INV, P, NT, ROW>(buf, tw, tid);
-        fft_stages<T, L, INV, P, NT, ROW, S + 1, NS * R>(buf, tw, tid);
+        stockham_stage<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid);
+        fft_stages<T, L, INV, P, NT, ES, PS, S + 1, NS * R>(buf, tw, tid);
     }
 }
 
-// Transform P pencils of length L held in LDS (layout per ROW), in place.
-// Caller must __syncthreads() after filling buf; returns after a barrier.
-template <typename T, int L, bool INV, int P, int NT, bool ROW>
-__device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *__restrict__ tw, int tid)
+// Transform P pencils of length L held in LDS (buf[n * ES + p * PS]), in
+// place.  Caller must __syncthreads() after filling buf; returns after a
+// barrier.
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS = 1>
+__device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
-    fft_stages<T, L, INV, P, NT, ROW, 0, 1>(buf, tw, tid);
+    fft_stages<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid);
 }
 
 // ---------------------------------------------------------------- reductions
-// Deterministic workgroup sum of one double per thread (fixed tree order).
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double *red, int tid)
+// Deterministic workgroup sums of K doubles per thread: a fixed xor-shuffle
+// tree inside each 64-lane wave, then the per-wave results added in wave
+// order by thread 0.  The sums are valid in thread 0 only.  red must hold
+// K * NT / 64 doubles; the call ends with a barrier so red can be reused.
+template <int NT, int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double *red, int tid)
 {
-    red[tid] = v;
-    __syncthreads();
+    constexpr int NW = NT / 64;
 #pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
     }
-    double r = red[0];
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[k * NW + (tid >> 6)] = v[k];
+    }
     __syncthreads();
-    return r;
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) s += red[k * NW + w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double x, double *red, int tid)
+{
+    double v[1] = {x};
+    block_sums<NT, 1>(v, red, tid);
+    return v[0];
 }
 
 }  // namespace ofdft

@@ -43,11 +43,13 @@ struct Geom {
     double invN;
 };
 
+// k_F knots: the values live in device memory (kernels index them with
+// data-dependent brackets, which must not pull a table into registers)
 struct Knots {
     int nk;
     int log_spacing;
     double inv_span;            // (nk-1)/ln(k_N/k_1)  or  (nk-1)/(k_N-k_1)
-    double k[MAXKNOTS];
+    const double *k;            // device array of nk values
 };
 
 // forward row pass: axis-2 r2c of up to 4 fields derived pointwise from the
@@ -68,6 +70,7 @@ struct RowFwdArgs {
     int pstride;
     const void *twM;            // W_M^n, n < M
     const void *twN;            // W_{n2}^k, k <= M
+    const void *tw1;            // W_{n1}^n (plane kernels)
 };
 
 // strided column pass along axis 1 or 0 (c2c), optionally with a fused
@@ -126,9 +129,16 @@ struct RowInvArgs {
     int pstride;
     int nbatch;
     const void *twM, *twN;
+    const void *tw1;            // W_{n1}^n (plane kernels)
 };
 
 bool length_supported(int L);
+
+// plane kernels (axis-2 and axis-1 fused per (i0, batch) plane) exist for
+// the (n1, n2/2) pairs below when the plane fits in LDS; nblocks = n0
+template <typename T> bool plane_supported(int n1, int m);
+template <typename T> hipError_t launch_plane_fwd(const Geom &g, int nbatch, const RowFwdArgs &a, int &nblocks, hipStream_t s);
+template <typename T> hipError_t launch_plane_inv(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
 
 // launchers (T = float or double)
 template <typename T> hipError_t launch_row_fwd(const Geom &g, int nbatch, const RowFwdArgs &a, int &nblocks, hipStream_t s);

@@ -74,6 +74,15 @@ __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ bool d_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool d_finite(double x) { return isfinite(x); }
+// base-2 logarithm and power: the hardware transcendental instructions for
+// FP32 fields (about 1 ulp), the library functions for FP64
+__device__ __forceinline__ float d_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double d_log2(double x) { return log2(x); }
+__device__ __forceinline__ float d_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double d_exp2(double x) { return exp2(x); }
+template <typename T> __device__ __forceinline__ T neg_inf() { return -__builtin_huge_valf(); }
+template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
+constexpr double LOG2_3PI2 = 4.8879547596657937775;   // log2(3 pi^2)
 
 // Lindhard kernel shape G_NL(eta) = 1/F - 3 eta^2 - 1 with
 // F = 1/2 + (1 - eta^2)/(4 eta) ln|(1 + eta)/(1 - eta)| (the G_NL formula of
@@ -112,10 +121,8 @@ __device__ __forceinline__ T gnl_dev(T eta)
 // weight t on the knots (step s4).  An exact knot belongs to the segment on
 // its right; the last knot to the last segment with t = 1.
 template <typename T>
-__device__ __forceinline__ void knot_bracket(T rho, const Knots &kn, int &j, T &t, bool &inside,
-                                             T &kf)
+__device__ __forceinline__ void knot_bracket_kf(T kf, const Knots &kn, int &j, T &t, bool &inside)
 {
-    kf = d_cbrt(T(THREE_PI2) * rho);
     const int nk = kn.nk;
     const T k1 = T(kn.k[0]), kN = T(kn.k[nk - 1]);
     inside = kf > k1 && kf < kN;
@@ -133,6 +140,28 @@ __device__ __forceinline__ void knot_bracket(T rho, const Knots &kn, int &j, T &
     j = jj;
     const T kj = T(kn.k[jj]), kj1 = T(kn.k[jj + 1]);
     t = (kt - kj) / (kj1 - kj);
+}
+
+// k_F = (3 pi^2 rho)^(1/3) from log2(rho)
+template <typename T>
+__device__ __forceinline__ T kf_from_log2(T lu)
+{
+    return d_exp2((T(LOG2_3PI2) + lu) * T(1.0 / 3.0));
+}
+
+// An opaque copy of the thread index (an empty asm with a register operand,
+// no memory access): index arithmetic derived from it is recomputed where it
+// is used rather than hoisted out of per-field loops and kept live.
+__device__ __forceinline__ int opaque(int t)
+{
+    asm volatile("" : "+v"(t));
+    return t;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> opaque(cpx<T> z)
+{
+    asm volatile("" : "+v"(z.x), "+v"(z.y));
+    return z;
 }
 
 // signed grid frequency of index i on an axis of n points (Nyquist negative)
@@ -153,35 +182,18 @@ __device__ __forceinline__ double *part_ptr(double *part, int b, int slot, int p
 }
 
 // ================================================================ row forward
-template <typename T>
-__device__ __forceinline__ T field_value(int kind, T v, int in_is_phi, T beta, T alpha,
-                                         int knot, const Knots &kn)
-{
-    const T rho = in_is_phi ? v * v : (v > T(0) ? v : T(0));
-    switch (kind) {
-    case FK_RHO: return in_is_phi ? v * v : v;
-    case FK_PHI: return in_is_phi ? v : d_sqrt(rho);
-    case FK_RHOB: return rho > T(0) ? d_pow(rho, beta) : T(0);
-    case FK_KNOT: {
-        int j;
-        T t, kf;
-        bool inside;
-        knot_bracket(rho, kn, j, t, inside, kf);
-        T L = kn.nk == 1 ? T(1) : (j == knot ? T(1) - t : (j + 1 == knot ? t : T(0)));
-        return L == T(0) ? T(0) : L * (rho > T(0) ? d_pow(rho, alpha) : T(0));
-    }
-    default: return v;
-    }
-}
-
+// Axis-2 r2c of P rows per block.  The input is read once into registers;
+// the fields (rho, phi, rho^beta, or rho^alpha L_i(k~) for the EXACT spline)
+// are derived pointwise and transformed one after the other through LDS.
 template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 {
     constexpr int P = row_P<T, M>();
+    constexpr int PS = P + 1;
     constexpr int PAIRS = P * M;
     constexpr int PER = (PAIRS + NT - 1) / NT;
-    __shared__ cpx<T> buf[PAIRS];
-    __shared__ double red[NT];
+    __shared__ cpx<T> buf[M * PS];
+    __shared__ double red[3 * NT / 64];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const long long nrows = (long long)g.n0 * g.n1;
@@ -201,50 +213,88 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             if (row < nrows) x[q] = ((const cpx<T> *)(in + row * g.n2))[n];
         }
     }
-    if (a.partials) {
-        double s_rho = 0.0, s_tf = 0.0, bad = 0.0;
+    // derived values: u = rho, w = phi, z = rho^beta  (or, for knot fields,
+    // u = rho^alpha, w = t, jj = bracket)
+    const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
+    cpx<T> u[PER], w[PER], z[PER];
+    int jj[PER][2];
+    double sums[3] = {0.0, 0.0, 0.0};   // sum rho, sum rho^(5/3), bad count
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int idx = tid + q * NT;
-            if (idx < PAIRS && r0 + idx / M < nrows) {
-                const T vv[2] = {x[q].x, x[q].y};
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NT;
+        const bool live = idx < PAIRS && r0 + idx / M < nrows;
+        const T xv[2] = {x[q].x, x[q].y};
+        T uu[2], ww[2], zz[2];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const T v = vv[c];
-                    const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
-                    if (!ok) {
-                        bad += 1.0;
-                        continue;
-                    }
-                    const T rho = a.in_is_phi ? v * v : v;
-                    const T cr = d_cbrt(rho);
-                    s_rho += (double)rho;
-                    s_tf += (double)(rho * cr * cr);
+        for (int c = 0; c < 2; ++c) {
+            const T v = xv[c];
+            const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
+            const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
+            const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+            if (live && a.partials) {
+                if (!ok) {
+                    sums[2] += 1.0;
+                } else {
+                    sums[0] += (double)rho;
+                    sums[1] += (double)(rho * d_exp2(lu * T(2.0 / 3.0)));
                 }
             }
+            if (knots) {
+                T t;
+                bool inside;
+                knot_bracket_kf(kf_from_log2(lu), a.knots, jj[q][c], t, inside);
+                uu[c] = d_exp2(T(a.alpha) * lu);
+                ww[c] = t;
+                zz[c] = T(0);
+            } else {
+                uu[c] = a.in_is_phi ? v * v : v;
+                ww[c] = a.in_is_phi ? v : d_sqrt(rho);
+                zz[c] = d_exp2(T(a.beta) * lu);
+            }
         }
-        s_rho = block_sum<NT>(s_rho, red, tid);
-        s_tf = block_sum<NT>(s_tf, red, tid);
-        bad = block_sum<NT>(bad, red, tid);
+        u[q] = {uu[0], uu[1]};
+        w[q] = {ww[0], ww[1]};
+        z[q] = {zz[0], zz[1]};
+    }
+    if (a.partials) {
+        block_sums<NT, 3>(sums, red, tid);
         if (tid == 0) {
-            part_ptr(a.part, b, SL_RHO, a.pstride)[blockIdx.x] = s_rho;
-            part_ptr(a.part, b, SL_TF, a.pstride)[blockIdx.x] = s_tf;
-            part_ptr(a.part, b, SL_BAD, a.pstride)[blockIdx.x] = bad;
+            part_ptr(a.part, b, SL_RHO, a.pstride)[blockIdx.x] = sums[0];
+            part_ptr(a.part, b, SL_TF, a.pstride)[blockIdx.x] = sums[1];
+            part_ptr(a.part, b, SL_BAD, a.pstride)[blockIdx.x] = sums[2];
         }
     }
-    const T beta = T(a.beta), alpha = T(a.alpha);
     for (int f = 0; f < a.nfields; ++f) {
         const int kind = a.kind[f];
         const int knot = a.knot0 + f;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NT;
-            if (idx < PAIRS)
-                buf[idx] = {field_value<T>(kind, x[q].x, a.in_is_phi, beta, alpha, knot, a.knots),
-                            field_value<T>(kind, x[q].y, a.in_is_phi, beta, alpha, knot, a.knots)};
+            if (idx < PAIRS) {
+                const int p = idx / M, n = idx % M;
+                cpx<T> val;
+                if (kind == FK_RHO || kind == FK_RAW) val = u[q];
+                else if (kind == FK_PHI) val = w[q];
+                else if (kind == FK_RHOB) val = z[q];
+                else {
+                    const T tv[2] = {w[q].x, w[q].y};
+                    const T uv[2] = {u[q].x, u[q].y};
+                    T o[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int j = jj[q][c];
+                        const T L = a.knots.nk == 1 ? T(1)
+                                                    : (j == knot ? T(1) - tv[c]
+                                                                 : (j + 1 == knot ? tv[c] : T(0)));
+                        o[c] = L * uv[c];
+                    }
+                    val = {o[0], o[1]};
+                }
+                buf[n * PS + p] = val;
+            }
         }
         __syncthreads();
-        lds_fft<T, M, false, P, NT, true>(buf, twM, tid);
+        lds_fft<T, M, false, P, NT, PS>(buf, twM, tid);
         // unpack the half-length complex transform into the r2c half spectrum:
         // X[k] = (Z[k] + conj Z[M-k])/2 - i W^k (Z[k] - conj Z[M-k])/2
         cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh;
@@ -253,8 +303,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             const int p = o / (M + 1), k = o % (M + 1);
             const long long row = r0 + p;
             if (row < nrows) {
-                const cpx<T> zk = buf[p * M + (k == M ? 0 : k)];
-                const cpx<T> zm = cconj(buf[p * M + (k == 0 ? 0 : M - k)]);
+                const cpx<T> zk = buf[(k == M ? 0 : k) * PS + p];
+                const cpx<T> zm = cconj(buf[(k == 0 ? 0 : M - k) * PS + p]);
                 const cpx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
                 const cpx<T> d = {T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y)};
                 const cpx<T> wd = cmul(twN[k], d);
@@ -291,11 +341,11 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a)
     const int b = fb % a.nbatch;
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
     if (op == GO_NONE) {
-        if (a.inv) lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
-        else lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+        if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
+        else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
     } else {
         // axis 0: element n is i0, column c is (i1, k2)
-        lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+        lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
         const Geom &g = a.g;
         const int i1 = cvalid ? (int)(c / g.n2h) : 0;
         const int k2 = cvalid ? (int)(c % g.n2h) : 0;
@@ -335,8 +385,10 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a)
             buf[n * P + p] = o;
         }
         if (op == GO_HEXT || op == GO_VW) {
-            s0 = block_sum<NT>(s0, red, tid);
-            s1 = block_sum<NT>(s1, red, tid);
+            double ss[2] = {s0, s1};
+            block_sums<NT, 2>(ss, red, tid);
+            s0 = ss[0];
+            s1 = ss[1];
             if (tid == 0) {
                 if (op == GO_HEXT) {
                     part_ptr(a.part, b, SL_H, a.pstride)[blockIdx.x] = s0;
@@ -347,7 +399,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a)
             }
         }
         __syncthreads();
-        if (op != GO_SCALE) lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
+        if (op != GO_SCALE) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
     }
     if (cvalid)
         for (int n = tid / P; n < L; n += RSTEP) dst[cbase + n * a.elem_stride] = buf[n * P + p];
@@ -396,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
             if (n < L) buf[n * P + p] = cscale(xs[q], T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k));
         }
         __syncthreads();
-        lds_fft<T, L, true, P, NT, false>(buf, tw, tid);
+        lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
         cpx<T> *dst = (cpx<T> *)a.dst + ((long long)kk * a.nbatch + b) * a.fstride;
         if (cvalid)
             for (int n = tid / P; n < L; n += RSTEP) dst[c + n * es] = buf[n * P + p];
@@ -440,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
         for (int n = tid / P; n < L; n += RSTEP)
             buf[n * P + p] = cvalid ? src[c + n * es] : cpx<T>{T(0), T(0)};
         __syncthreads();
-        lds_fft<T, L, false, P, NT, false>(buf, tw, tid);
+        lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
         const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -469,10 +521,11 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
 }
 
 // ================================================================ row inverse
-// c2r of one half-spectrum row block into buf (z[n] = f[2n] + i f[2n+1]):
+// c2r of one block of half-spectrum rows into buf (z[n] = f[2n] + i f[2n+1],
+// element n of row p at buf[n * PS + p]):
 // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k), k < M, with
 // the imaginary parts of X[0] and X[M] dropped (Re of the inverse).
-template <typename T, int M, int P>
+template <typename T, int M, int P, int PS>
 __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__ spec,
                                          long long r0, long long nrows, int n2h,
                                          const cpx<T> *__restrict__ twM,
@@ -496,20 +549,21 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
             const cpx<T> dw = cmul(d, cconj(twN[k]));
             z = {s.x - dw.y, s.y + dw.x};                  // s + i dw
         }
-        buf[o] = z;
+        buf[k * PS + p] = z;
     }
     __syncthreads();
-    lds_fft<T, M, true, P, NT, true>(buf, twM, tid);
+    lds_fft<T, M, true, P, NT, PS>(buf, twM, tid);
 }
 
 template <typename T, int M>
 __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
 {
     constexpr int P = row_P<T, M>();
+    constexpr int PS = P + 1;
     constexpr int PAIRS = P * M;
     constexpr int PER = (PAIRS + NT - 1) / NT;
-    __shared__ cpx<T> buf[PAIRS];
-    __shared__ double red[NT];
+    __shared__ cpx<T> buf[M * PS];
+    __shared__ double red[4 * NT / 64];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const long long nrows = (long long)g.n0 * g.n1;
@@ -519,25 +573,26 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     auto spec_of = [&](int f) {
         return (const cpx<T> *)a.spec + f * a.spec_fstride + (long long)b * g.Nh;
     };
-    auto pair_of = [&](int q, long long &off) {
+    // pair q of this thread: row p = idx / M, element n = idx % M
+    bool valid[PER];
+    long long offs[PER];
+    int lds_at[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
         const int idx = tid + q * NT;
-        if (idx >= PAIRS) return false;
         const int p = idx / M, n = idx % M;
-        const long long row = r0 + p;
-        if (row >= nrows) return false;
-        off = row * g.n2 + 2 * n;
-        return true;
-    };
+        valid[q] = idx < PAIRS && r0 + p < nrows;
+        offs[q] = valid[q] ? (r0 + p) * g.n2 + 2 * n : 0;
+        lds_at[q] = n * PS + p;
+    }
 
     if (a.mode == EP_STORE) {
         for (int f = 0; f < a.nfields; ++f) {
-            c2r_rows<T, M, P>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
+            c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
             T *out = (T *)a.out + ((long long)f * a.nbatch + b) * g.N;
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                long long off;
-                if (pair_of(q, off)) *(cpx<T> *)(out + off) = buf[tid + q * NT];
-            }
+            for (int q = 0; q < PER; ++q)
+                if (valid[q]) *(cpx<T> *)(out + offs[q]) = buf[lds_at[q]];
             __syncthreads();
         }
         return;
@@ -546,13 +601,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     // input density (rho or phi) for this block's pairs
     const T *in = (const T *)a.in + (long long)b * g.N;
     cpx<T> xin[PER];
-    bool valid[PER];
-    long long offs[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        valid[q] = pair_of(q, offs[q]);
+    for (int q = 0; q < PER; ++q)
         xin[q] = valid[q] ? *(const cpx<T> *)(in + offs[q]) : cpx<T>{T(0), T(0)};
-    }
 
     if (a.mode == EP_KNOTS) {
         // step s4 for this batch of knots: v1 += L_i Phi_i, v2 += L_i' Phi_i
@@ -565,21 +616,28 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const T rho = a.in_is_phi ? vv[c] * vv[c] : (vv[c] > T(0) ? vv[c] : T(0));
-                T kf;
+                const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
                 bool inside;
-                knot_bracket(rho, a.knots, jj[q][c], tt[q][c], inside, kf);
+                knot_bracket_kf(kf_from_log2(lu), a.knots, jj[q][c], tt[q][c], inside);
             }
             v1[q] = {T(0), T(0)};
             v2[q] = {T(0), T(0)};
         }
+        const int nk = a.knots.nk;
         for (int f = 0; f < a.nfields; ++f) {
-            c2r_rows<T, M, P>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
             const int i = a.knot0 + f;
-            const int nk = a.knots.nk;
+            // skip the transform if no point of this block uses knot i
+            bool need = false;
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                need |= valid[q] && (nk == 1 || jj[q][0] == i || jj[q][0] + 1 == i ||
+                                     jj[q][1] == i || jj[q][1] + 1 == i);
+            if (!__syncthreads_or(need)) continue;
+            c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 if (!valid[q]) continue;
-                const cpx<T> z = buf[tid + q * NT];
+                const cpx<T> z = buf[lds_at[q]];
                 const T ph[2] = {z.x, z.y};
                 T w1[2], w2[2];
 #pragma unroll
@@ -626,17 +684,15 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
     for (int s = 0; s < 4; ++s) {
         if (flds[s] < 0) continue;
-        c2r_rows<T, M, P>(buf, spec_of(flds[s]), r0, nrows, g.n2h, twM, twN, tid);
+        c2r_rows<T, M, P, PS>(buf, spec_of(flds[s]), r0, nrows, g.n2h, twM, twN, tid);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int idx = tid + q * NT;
-            if (idx < PAIRS) {
-                const cpx<T> z = buf[idx];
-                if (s == 0) fh[q] = z;
-                else if (s == 1) fl[q] = z;
-                else if (s == 2) fw[q] = z;
-                else fa[q] = z;
-            }
+            if (!valid[q]) continue;
+            const cpx<T> z = buf[lds_at[q]];
+            if (s == 0) fh[q] = z;
+            else if (s == 1) fl[q] = z;
+            else if (s == 2) fw[q] = z;
+            else fa[q] = z;
         }
         __syncthreads();
     }
@@ -646,8 +702,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     T *gout = a.g_out ? (T *)a.g_out + (long long)b * g.N : nullptr;
     const T alpha = T(a.alpha);
     const T floor_rho = T(a.floor);
-    const T floor_phi = d_sqrt(floor_rho);
-    double s_nl = 0.0, s_gphi = 0.0, s_gg = 0.0, s_pp = 0.0;
+    const T lfloor = d_log2(floor_rho);
+    const bool has_wt = a.fld_wt >= 0;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};   // rho^a Phi, g phi, g^2, phi^2
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         if (!valid[q]) continue;
@@ -672,65 +729,542 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
                 rho = xv[c] > T(0) ? xv[c] : T(0);
                 phi = d_sqrt(rho);
             }
-            const T aphi = phi < T(0) ? -phi : phi;
             const T sgn = phi < T(0) ? T(-1) : T(1);
-            const T rho_s = rho > floor_rho ? rho : floor_rho;
-            const T phi_s = sgn * (aphi > floor_phi ? aphi : floor_phi);
-            T v = hv[c];          // v_H + v_ext
+            // one logarithm per point: lu = log2(rho), lr = log2(max(rho, floor))
+            const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+            const T lr = rho >= floor_rho ? lu : lfloor;
+            T v = hv[c];                                   // v_H + v_ext
             T gphi = T(2) * phi * v;
             if (a.use_tf) {
-                const T cr = d_cbrt(rho);
-                const T vt = T(5.0 / 3.0 * C_TF_D) * cr * cr;
+                const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
                 v += vt;
                 gphi += T(2) * phi * vt;
             }
-            // von Weizsaecker: lv = -lambda nabla^2 phi
-            v += T(0.5) * lv[c] / phi_s;
+            // von Weizsaecker: lv = -lambda nabla^2 phi; v = lv / (2 phi_s)
+            v += T(0.5) * lv[c] * sgn * d_exp2(T(-0.5) * lr);
             gphi += lv[c];
-            // nonlocal: rho^(alpha-1) floored in v; phi rho^(alpha-1) = sgn |phi|^(2 alpha - 1) in g
-            const T ra1 = d_pow(rho_s, alpha - T(1));
-            const T fa_ = aphi > T(0) ? sgn * d_pow(aphi, T(2) * alpha - T(1)) : T(0);
-            const T ra = rho > T(0) ? d_pow(rho, alpha) : T(0);
-            if (a.fld_wt >= 0) {
-                v += T(2) * alpha * ra1 * wv[c];
-                gphi += T(4) * alpha * fa_ * wv[c];
-                s_nl += (double)(ra * wv[c]);
-            }
-            if (a.spline) {
-                s_nl += (double)(ra * s1v[c]);
-                if (!a.exact) {
-                    v += T(2) * alpha * ra1 * s1v[c];
-                    gphi += T(4) * alpha * fa_ * s1v[c];
-                } else {
-                    T kf, t;
-                    int j;
-                    bool inside;
-                    knot_bracket(rho, a.knots, j, t, inside, kf);
-                    const T dk = inside ? kf * T(1.0 / 3.0) : T(0);   // rho dk~/drho
-                    v += alpha * ra1 * (s1v[c] + av[c]) + ra * (dk / rho_s) * s2v[c];
-                    gphi += T(2) * (alpha * fa_ * (s1v[c] + av[c]) + fa_ * dk * s2v[c]);
+            if (has_wt || a.spline) {
+                const T ra1 = d_exp2((alpha - T(1)) * lr);          // rho_s^(alpha-1)
+                const T ra = d_exp2(alpha * lu);                    // rho^alpha
+                const T fa_ = sgn * d_exp2((alpha - T(0.5)) * lu);  // phi rho^(alpha-1)
+                if (has_wt) {
+                    v += T(2) * alpha * ra1 * wv[c];
+                    gphi += T(4) * alpha * fa_ * wv[c];
+                    sums[0] += (double)(ra * wv[c]);
+                }
+                if (a.spline) {
+                    sums[0] += (double)(ra * s1v[c]);
+                    if (!a.exact) {
+                        v += T(2) * alpha * ra1 * s1v[c];
+                        gphi += T(4) * alpha * fa_ * s1v[c];
+                    } else {
+                        const T kf = kf_from_log2(lu);
+                        const bool inside = kf > T(a.knots.k[0]) && kf < T(a.knots.k[a.knots.nk - 1]);
+                        const T dk = inside ? kf * T(1.0 / 3.0) : T(0);   // rho dk~/drho
+                        v += alpha * ra1 * (s1v[c] + av[c]) + ra * dk * d_exp2(-lr) * s2v[c];
+                        gphi += T(2) * (alpha * fa_ * (s1v[c] + av[c]) + fa_ * dk * s2v[c]);
+                    }
                 }
             }
             vo[c] = v;
             go[c] = gphi;
-            s_gphi += (double)gphi * (double)phi;
-            s_gg += (double)gphi * (double)gphi;
-            s_pp += (double)phi * (double)phi;
+            sums[1] += (double)gphi * (double)phi;
+            sums[2] += (double)gphi * (double)gphi;
+            sums[3] += (double)phi * (double)phi;
         }
         if (vout) *(cpx<T> *)(vout + offs[q]) = {vo[0], vo[1]};
         if (gout) *(cpx<T> *)(gout + offs[q]) = {go[0], go[1]};
     }
-    s_nl = block_sum<NT>(s_nl, red, tid);
-    s_gphi = block_sum<NT>(s_gphi, red, tid);
-    s_gg = block_sum<NT>(s_gg, red, tid);
-    s_pp = block_sum<NT>(s_pp, red, tid);
+    block_sums<NT, 4>(sums, red, tid);
     if (tid == 0) {
-        part_ptr(a.part, b, SL_NL, a.pstride)[blockIdx.x] = s_nl;
-        part_ptr(a.part, b, SL_GPHI, a.pstride)[blockIdx.x] = s_gphi;
-        part_ptr(a.part, b, SL_GG, a.pstride)[blockIdx.x] = s_gg;
-        part_ptr(a.part, b, SL_PHIPHI, a.pstride)[blockIdx.x] = s_pp;
+        part_ptr(a.part, b, SL_NL, a.pstride)[blockIdx.x] = sums[0];
+        part_ptr(a.part, b, SL_GPHI, a.pstride)[blockIdx.x] = sums[1];
+        part_ptr(a.part, b, SL_GG, a.pstride)[blockIdx.x] = sums[2];
+        part_ptr(a.part, b, SL_PHIPHI, a.pstride)[blockIdx.x] = sums[3];
     }
 }
+
+// ================================================================ plane kernels
+// For grids whose (i1, k2) plane fits in LDS, one block handles a whole
+// i0-plane of one density: the axis-2 r2c of every row and the axis-1 c2c of
+// every column run back to back on the same padded buffer (element (i1, k)
+// at buf[k * A + i1], A odd), so the spectrum needs one HBM round trip less
+// per field; the inverse side mirrors it and ends in the combine or in the
+// spline interpolation.
+template <int N1> constexpr int plane_A() { return (N1 % 2 == 0) ? N1 + 1 : N1; }
+template <int N1, int M> constexpr int plane_NT() { return 1024; }
+template <typename T, int N1, int M> constexpr bool plane_fits()
+{
+    return (long long)(M + 1) * plane_A<N1>() * 2 * sizeof(T) <= 98304;
+}
+
+// X[k] from Z[k] and Z[M-k] (r2c unpack), W^k = twN[k]
+template <typename T>
+__device__ __forceinline__ cpx<T> r2c_unpack(cpx<T> zk, cpx<T> zmk, cpx<T> w)
+{
+    const cpx<T> zm = cconj(zmk);
+    const cpx<T> e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
+    const cpx<T> d = {T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y)};
+    const cpx<T> wd = cmul(w, d);
+    return {e.x + wd.y, e.y - wd.x};
+}
+
+// Z[k] from X[k] and X[M-k] (c2r pack), W^k = twN[k]
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_pack(cpx<T> xk, cpx<T> xm, cpx<T> w)
+{
+    const cpx<T> s = {xk.x + xm.x, xk.y - xm.y};
+    const cpx<T> d = {xk.x - xm.x, xk.y + xm.y};
+    const cpx<T> dw = cmul(d, cconj(w));
+    return {s.x - dw.y, s.y + dw.x};
+}
+
+template <typename T, int N1, int M>
+__global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_fwd(RowFwdArgs a, Geom g)
+{
+    constexpr int NTP = plane_NT<N1, M>();
+    constexpr int A = plane_A<N1>();
+    constexpr int PAIRS = N1 * M;
+    constexpr int PER = (PAIRS + NTP - 1) / NTP;
+    constexpr int HALF = M / 2 + 1;
+    __shared__ cpx<T> buf[(M + 1) * A];
+    __shared__ double red[3 * NTP / 64];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x, b = blockIdx.y;
+    const cpx<T> *in = (const cpx<T> *)((const T *)a.in + (long long)b * g.N +
+                                        (long long)i0 * N1 * g.n2);
+    const cpx<T> *twM = (const cpx<T> *)a.twM;
+    const cpx<T> *twN = (const cpx<T> *)a.twN;
+    const cpx<T> *tw1 = (const cpx<T> *)a.tw1;
+
+    cpx<T> x[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NTP;
+        x[q] = idx < PAIRS ? in[idx] : cpx<T>{T(0), T(0)};
+    }
+    const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
+    if (a.partials) {
+        double sums[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (tid + q * NTP >= PAIRS) continue;
+            const T xv[2] = {x[q].x, x[q].y};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T v = xv[c];
+                const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
+                if (!ok) {
+                    sums[2] += 1.0;
+                    continue;
+                }
+                const T rho = a.in_is_phi ? v * v : v;
+                const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+                sums[0] += (double)rho;
+                sums[1] += (double)(rho * d_exp2(lu * T(2.0 / 3.0)));
+            }
+        }
+        block_sums<NTP, 3>(sums, red, tid);
+        if (tid == 0) {
+            part_ptr(a.part, b, SL_RHO, a.pstride)[i0] = sums[0];
+            part_ptr(a.part, b, SL_TF, a.pstride)[i0] = sums[1];
+            part_ptr(a.part, b, SL_BAD, a.pstride)[i0] = sums[2];
+        }
+    }
+#pragma unroll 1
+    for (int f = 0; f < a.nfields; ++f) {
+        const int t = opaque(tid);
+        const int kind = a.kind[f];
+        const int knot = a.knot0 + f;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = t + q * NTP;
+            if (idx >= PAIRS) continue;
+            const int i1 = idx / M, n = idx % M;
+            const T xv[2] = {x[q].x, x[q].y};
+            T o[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T v = xv[c];
+                const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
+                if (kind == FK_RHO) o[c] = a.in_is_phi ? v * v : v;
+                else if (kind == FK_RAW) o[c] = v;
+                else if (kind == FK_PHI) o[c] = a.in_is_phi ? v : d_sqrt(rho);
+                else {
+                    const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+                    if (kind == FK_RHOB) {
+                        o[c] = d_exp2(T(a.beta) * lu);
+                    } else {
+                        int j;
+                        T t;
+                        bool inside;
+                        knot_bracket_kf(kf_from_log2(lu), a.knots, j, t, inside);
+                        const T L = a.knots.nk == 1 ? T(1)
+                                                    : (j == knot ? T(1) - t
+                                                                 : (j + 1 == knot ? t : T(0)));
+                        o[c] = L == T(0) ? T(0) : L * d_exp2(T(a.alpha) * lu);
+                    }
+                }
+            }
+            buf[n * A + i1] = {o[0], o[1]};
+        }
+        (void)knots;
+        __syncthreads();
+        // axis 2: half-length complex transforms of the N1 rows
+        lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
+        // unpack to the r2c half spectrum, pairs (k, M-k) in place
+        for (int w = t; w < N1 * HALF; w += NTP) {
+            const int i1 = w / HALF, k = w % HALF;
+            if (k == 0) {
+                const cpx<T> z0 = buf[i1];
+                buf[i1] = {z0.x + z0.y, T(0)};
+                buf[M * A + i1] = {z0.x - z0.y, T(0)};
+            } else if (2 * k == M) {
+                const cpx<T> zk = buf[k * A + i1];
+                buf[k * A + i1] = r2c_unpack(zk, zk, twN[k]);
+            } else {
+                const cpx<T> zk = buf[k * A + i1];
+                const cpx<T> zm = buf[(M - k) * A + i1];
+                buf[k * A + i1] = r2c_unpack(zk, zm, twN[k]);
+                buf[(M - k) * A + i1] = r2c_unpack(zm, zk, twN[M - k]);
+            }
+        }
+        __syncthreads();
+        // axis 1: the M + 1 columns
+        lds_fft<T, N1, false, M + 1, NTP, 1, A>(buf, tw1, t);
+        cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh +
+                      (long long)i0 * N1 * (M + 1);
+        for (int o = t; o < N1 * (M + 1); o += NTP) {
+            const int i1 = o / (M + 1), k = o % (M + 1);
+            out[o] = buf[k * A + i1];
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse of one field's (i0, batch) plane into buf: axis-1 c2c of the
+// M + 1 columns, c2r pack, axis-2 transforms; element (i1, n) of the result
+// (f[2n] + i f[2n+1] of row i1) is at buf[n * A + i1].
+template <typename T, int N1, int M, int NTP>
+__device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
+                                              const cpx<T> *tw1,
+                                              const cpx<T> *twM,
+                                              const cpx<T> *twN, int tid)
+{
+    constexpr int A = plane_A<N1>();
+    constexpr int HALF = M / 2 + 1;
+    tid = opaque(tid);
+    for (int o = tid; o < N1 * (M + 1); o += NTP) {
+        const int i1 = o / (M + 1), k = o % (M + 1);
+        buf[k * A + i1] = spec[o];
+    }
+    __syncthreads();
+    lds_fft<T, N1, true, M + 1, NTP, 1, A>(buf, tw1, tid);
+    for (int w = tid; w < N1 * HALF; w += NTP) {
+        const int i1 = w / HALF, k = w % HALF;
+        if (k == 0) {
+            const T x0 = buf[i1].x, xm = buf[M * A + i1].x;
+            buf[i1] = {x0 + xm, x0 - xm};
+        } else if (2 * k == M) {
+            const cpx<T> xk = buf[k * A + i1];
+            buf[k * A + i1] = c2r_pack(xk, xk, twN[k]);
+        } else {
+            const cpx<T> xk = buf[k * A + i1];
+            const cpx<T> xm = buf[(M - k) * A + i1];
+            buf[k * A + i1] = c2r_pack(xk, xm, twN[k]);
+            buf[(M - k) * A + i1] = c2r_pack(xm, xk, twN[M - k]);
+        }
+    }
+    __syncthreads();
+    lds_fft<T, M, true, N1, NTP, A, 1>(buf, twM, tid);
+}
+
+template <typename T, int N1, int M>
+__global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a, Geom g)
+{
+    constexpr int NTP = plane_NT<N1, M>();
+    constexpr int A = plane_A<N1>();
+    constexpr int PAIRS = N1 * M;
+    constexpr int PER = (PAIRS + NTP - 1) / NTP;
+    __shared__ cpx<T> buf[(M + 1) * A];
+    __shared__ double red[4 * NTP / 64];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x, b = blockIdx.y;
+    const cpx<T> *twM = (const cpx<T> *)a.twM;
+    const cpx<T> *twN = (const cpx<T> *)a.twN;
+    const cpx<T> *tw1 = (const cpx<T> *)a.tw1;
+    const long long plane_off = (long long)i0 * N1 * (M + 1);
+    auto spec_of = [&](int f) {
+        return (const cpx<T> *)a.spec + f * a.spec_fstride + (long long)b * g.Nh + plane_off;
+    };
+    const long long real_off = (long long)b * g.N + (long long)i0 * N1 * g.n2;
+    auto at = [&](int t, int q) {
+        const int idx = t + q * NTP;
+        return (idx % M) * A + idx / M;
+    };
+
+    if (a.mode == EP_STORE) {
+#pragma unroll 1
+        for (int f = 0; f < a.nfields; ++f) {
+            const int t = opaque(tid);
+            plane_inverse<T, N1, M, NTP>(buf, spec_of(f), tw1, twM, twN, t);
+            cpx<T> *out = (cpx<T> *)((T *)a.out + (long long)f * a.nbatch * g.N + real_off);
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (t + q * NTP < PAIRS) out[t + q * NTP] = buf[at(t, q)];
+            __syncthreads();
+        }
+        return;
+    }
+
+    const cpx<T> *in = (const cpx<T> *)((const T *)a.in + real_off);
+    cpx<T> xin[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        xin[q] = tid + q * NTP < PAIRS ? in[tid + q * NTP] : cpx<T>{T(0), T(0)};
+
+    if (a.mode == EP_KNOTS) {
+        int jj[PER][2];
+        T tt[PER][2];
+        cpx<T> v1[PER], v2[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const T vv[2] = {xin[q].x, xin[q].y};
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const T rho = a.in_is_phi ? vv[c] * vv[c] : (vv[c] > T(0) ? vv[c] : T(0));
+                const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+                bool inside;
+                knot_bracket_kf(kf_from_log2(lu), a.knots, jj[q][c], tt[q][c], inside);
+            }
+            v1[q] = {T(0), T(0)};
+            v2[q] = {T(0), T(0)};
+        }
+        const int nk = a.knots.nk;
+#pragma unroll 1
+        for (int f = 0; f < a.nfields; ++f) {
+            const int t = opaque(tid);
+            const int i = a.knot0 + f;
+            bool need = false;
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                need |= t + q * NTP < PAIRS &&
+                        (nk == 1 || jj[q][0] == i || jj[q][0] + 1 == i || jj[q][1] == i ||
+                         jj[q][1] + 1 == i);
+            if (!__syncthreads_or(need)) continue;
+            plane_inverse<T, N1, M, NTP>(buf, spec_of(f), tw1, twM, twN, t);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (t + q * NTP >= PAIRS) continue;
+                const cpx<T> z = buf[at(t, q)];
+                const T ph[2] = {z.x, z.y};
+                T w1[2], w2[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int j = jj[q][c];
+                    const T t = tt[q][c];
+                    if (nk == 1) {
+                        w1[c] = T(1);
+                        w2[c] = T(0);
+                    } else {
+                        const T idk = T(1.0 / (a.knots.k[j + 1] - a.knots.k[j]));
+                        w1[c] = (j == i) ? T(1) - t : ((j + 1 == i) ? t : T(0));
+                        w2[c] = (j == i) ? -idk : ((j + 1 == i) ? idk : T(0));
+                    }
+                }
+                v1[q].x += w1[0] * ph[0];
+                v1[q].y += w1[1] * ph[1];
+                v2[q].x += w2[0] * ph[0];
+                v2[q].y += w2[1] * ph[1];
+            }
+            __syncthreads();
+        }
+        cpx<T> *acc1 = (cpx<T> *)((T *)a.acc1 + real_off);
+        cpx<T> *acc2 = a.exact ? (cpx<T> *)((T *)a.acc2 + real_off) : nullptr;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = tid + q * NTP;
+            if (idx >= PAIRS) continue;
+            acc1[idx] = a.acc_init ? v1[q] : cadd(v1[q], acc1[idx]);
+            if (acc2) acc2[idx] = a.acc_init ? v2[q] : cadd(v2[q], acc2[idx]);
+        }
+        return;
+    }
+
+    // EP_COMBINE, one field at a time into v and g
+    const T alpha = T(a.alpha);
+    const T floor_rho = T(a.floor);
+    const T lfloor = d_log2(floor_rho);
+    cpx<T> vacc[PER], gacc[PER];
+    double snl = 0.0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) vacc[q] = gacc[q] = {T(0), T(0)};
+    // point quantities from the input value
+    auto point = [&](T xv, T &phi, T &rho, T &sgn, T &lu, T &lr) {
+        if (a.in_is_phi) {
+            phi = xv;
+            rho = phi * phi;
+        } else {
+            rho = xv > T(0) ? xv : T(0);
+            phi = d_sqrt(rho);
+        }
+        sgn = phi < T(0) ? T(-1) : T(1);
+        lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+        lr = rho >= floor_rho ? lu : lfloor;
+    };
+    const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+        const int t = opaque(tid);
+        if (flds[s] < 0) continue;
+        plane_inverse<T, N1, M, NTP>(buf, spec_of(flds[s]), tw1, twM, twN, t);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (t + q * NTP >= PAIRS) continue;
+            const cpx<T> z = buf[at(t, q)];
+            const T zv[2] = {z.x, z.y};
+            const cpx<T> xq = opaque(xin[q]);
+            const T xv[2] = {xq.x, xq.y};
+            T dv[2], dg[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                T phi, rho, sgn, lu, lr;
+                point(xv[c], phi, rho, sgn, lu, lr);
+                const T f = zv[c];
+                if (s == 0) {                      // v_H + v_ext
+                    dv[c] = f;
+                    dg[c] = T(2) * phi * f;
+                } else if (s == 1) {               // -lambda nabla^2 phi
+                    dv[c] = T(0.5) * f * sgn * d_exp2(T(-0.5) * lr);
+                    dg[c] = f;
+                } else if (s == 2) {               // Wang-Teter Phi
+                    dv[c] = T(2) * alpha * d_exp2((alpha - T(1)) * lr) * f;
+                    dg[c] = T(4) * alpha * sgn * d_exp2((alpha - T(0.5)) * lu) * f;
+                    snl += (double)(d_exp2(alpha * lu) * f);
+                } else {                           // EXACT: F^-1[sum_i omega_i F[rho^a L_i]]
+                    dv[c] = alpha * d_exp2((alpha - T(1)) * lr) * f;
+                    dg[c] = T(2) * alpha * sgn * d_exp2((alpha - T(0.5)) * lu) * f;
+                }
+            }
+            vacc[q].x += dv[0];
+            vacc[q].y += dv[1];
+            gacc[q].x += dg[0];
+            gacc[q].y += dg[1];
+        }
+        __syncthreads();
+    }
+    const cpx<T> *acc1 = a.spline ? (const cpx<T> *)((const T *)a.acc1 + real_off) : nullptr;
+    const cpx<T> *acc2 = (a.spline && a.exact) ? (const cpx<T> *)((const T *)a.acc2 + real_off)
+                                                : nullptr;
+    cpx<T> *vout = a.v_out ? (cpx<T> *)((T *)a.v_out + real_off) : nullptr;
+    cpx<T> *gout = a.g_out ? (cpx<T> *)((T *)a.g_out + real_off) : nullptr;
+    double sums[4] = {snl, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int idx = tid + q * NTP;
+        if (idx >= PAIRS) continue;
+        cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
+        if (acc1) s1 = acc1[idx];
+        if (acc2) s2 = acc2[idx];
+        const T xv[2] = {xin[q].x, xin[q].y};
+        const T s1v[2] = {s1.x, s1.y}, s2v[2] = {s2.x, s2.y};
+        T vv[2] = {vacc[q].x, vacc[q].y};
+        T gg[2] = {gacc[q].x, gacc[q].y};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            T phi, rho, sgn, lu, lr;
+            point(xv[c], phi, rho, sgn, lu, lr);
+            if (a.use_tf) {
+                const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
+                vv[c] += vt;
+                gg[c] += T(2) * phi * vt;
+            }
+            if (a.spline) {
+                const T ra1 = d_exp2((alpha - T(1)) * lr);
+                const T ra = d_exp2(alpha * lu);
+                const T fa_ = sgn * d_exp2((alpha - T(0.5)) * lu);
+                sums[0] += (double)(ra * s1v[c]);
+                if (!a.exact) {
+                    vv[c] += T(2) * alpha * ra1 * s1v[c];
+                    gg[c] += T(4) * alpha * fa_ * s1v[c];
+                } else {
+                    const T kf = kf_from_log2(lu);
+                    const bool inside = kf > T(a.knots.k[0]) && kf < T(a.knots.k[a.knots.nk - 1]);
+                    const T dk = inside ? kf * T(1.0 / 3.0) : T(0);
+                    vv[c] += alpha * ra1 * s1v[c] + ra * dk * d_exp2(-lr) * s2v[c];
+                    gg[c] += T(2) * (alpha * fa_ * s1v[c] + fa_ * dk * s2v[c]);
+                }
+            }
+            sums[1] += (double)gg[c] * (double)phi;
+            sums[2] += (double)gg[c] * (double)gg[c];
+            sums[3] += (double)phi * (double)phi;
+        }
+        if (vout) vout[idx] = {vv[0], vv[1]};
+        if (gout) gout[idx] = {gg[0], gg[1]};
+    }
+    block_sums<NTP, 4>(sums, red, tid);
+    if (tid == 0) {
+        part_ptr(a.part, b, SL_NL, a.pstride)[i0] = sums[0];
+        part_ptr(a.part, b, SL_GPHI, a.pstride)[i0] = sums[1];
+        part_ptr(a.part, b, SL_GG, a.pstride)[i0] = sums[2];
+        part_ptr(a.part, b, SL_PHIPHI, a.pstride)[i0] = sums[3];
+    }
+}
+
+#define OFDFT_PLANES(X) \
+    X(16, 8) X(24, 12) X(32, 16) X(48, 24) X(54, 27) X(64, 32) X(72, 36) X(96, 48) \
+    X(108, 54) X(128, 64)
+
+template <typename T, int N1, int M>
+hipError_t plane_fwd_go(const Geom &g, int nbatch, const RowFwdArgs &a, int &nblocks, hipStream_t s)
+{
+    if constexpr (!plane_fits<T, N1, M>()) {
+        return hipErrorInvalidValue;
+    } else {
+        nblocks = g.n0;
+        if (a.partials && nblocks > a.pstride) return hipErrorInvalidValue;
+        if (a.nfields < 0 || a.nfields > MAXKB) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_plane_fwd<T, N1, M>), dim3(g.n0, nbatch), dim3(plane_NT<N1, M>()),
+                           0, s, a, g);
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int N1, int M>
+hipError_t plane_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s)
+{
+    if constexpr (!plane_fits<T, N1, M>()) {
+        return hipErrorInvalidValue;
+    } else {
+        nblocks = g.n0;
+        if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_plane_inv<T, N1, M>), dim3(g.n0, a.nbatch),
+                           dim3(plane_NT<N1, M>()), 0, s, a, g);
+        return hipGetLastError();
+    }
+}
+
+#define OFDFT_PLANE_CASE_SUP(N1, M) if (n1 == N1 && m == M) return plane_fits<PT, N1, M>();
+#define OFDFT_PLANE_CASE_F(N1, M) if (g.n1 == N1 && g.m == M) return plane_fwd_go<PT, N1, M>(g, nbatch, a, nb, s);
+#define OFDFT_PLANE_CASE_I(N1, M) if (g.n1 == N1 && g.m == M) return plane_inv_go<PT, N1, M>(g, a, nb, s);
+#define OFDFT_INSTANTIATE_PLANES()                                                              \
+    template <> bool plane_supported<PT>(int n1, int m)                                         \
+    {                                                                                           \
+        OFDFT_PLANES(OFDFT_PLANE_CASE_SUP)                                                      \
+        return false;                                                                           \
+    }                                                                                           \
+    template <> hipError_t launch_plane_fwd<PT>(const Geom &g, int nbatch, const RowFwdArgs &a, \
+                                                int &nb, hipStream_t s)                         \
+    {                                                                                           \
+        OFDFT_PLANES(OFDFT_PLANE_CASE_F)                                                        \
+        return hipErrorInvalidValue;                                                            \
+    }                                                                                           \
+    template <> hipError_t launch_plane_inv<PT>(const Geom &g, const RowInvArgs &a, int &nb,    \
+                                                hipStream_t s)                                  \
+    {                                                                                           \
+        OFDFT_PLANES(OFDFT_PLANE_CASE_I)                                                        \
+        return hipErrorInvalidValue;                                                            \
+    }
 
 // ================================================================ launchers
 #define OFDFT_LENGTHS(X) \

@@ -105,6 +105,12 @@ CASES = {
                         dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
     "box_spline_exact": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_SPLINE,
                          dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT)),
+    # (16, 32, 32) and 32^3 run through the fused plane kernels, the others
+    # through the separate row and column passes
+    "plane_spline_s3s4": (lambda: (box((16, 32, 32)), None), LOCAL | ofdft.TERM_SPLINE,
+                          dict(nk=12, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    "plane_spline_exact": (lambda: (box((16, 32, 32)), None), LOCAL | ofdft.TERM_SPLINE,
+                           dict(nk=12, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT)),
     "box_spline_lin_exact": (lambda: (box((18, 16, 24)), None), ofdft.TERM_SPLINE,
                              dict(nk=13, kf_min=0.4, kf_max=1.9, knot_spacing=ofdft.KNOTS_LIN,
                                   nl_mode=ofdft.NL_EXACT)),
