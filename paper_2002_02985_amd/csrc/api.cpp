@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -95,6 +96,7 @@ struct ofdft_grid {
     // device tables
     void *tw0 = nullptr, *tw1 = nullptr, *twM = nullptr, *twN = nullptr;
     void *vext = nullptr;
+    void *gtab = nullptr;    // [1/G^2 | G^2 | omega_WT], 3 x Nh field-type values
     double *ph0 = nullptr, *ph1 = nullptr, *ph2 = nullptr;
     int *d_spec_off = nullptr, *d_atom_species = nullptr;
     double *d_Z = nullptr, *d_rc = nullptr;
@@ -114,6 +116,7 @@ struct ofdft_grid {
     void *opt[9] = {nullptr};
     size_t bytes = 0;
     Timer timer;
+    int tune_col_tile_major = 0;   // block order of the column passes
 };
 
 // ---------------------------------------------------------------- helpers
@@ -414,6 +417,8 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.part = g->part;
     a.pstride = g->pstride;
     a.vext = g->vext;
+    a.gtab = g->gtab;
+    a.tile_major = g->tune_col_tile_major;
     a.use_h = (g->func.terms & OFDFT_TERM_HARTREE) ? 1 : 0;
     a.use_ext = (g->func.terms & OFDFT_TERM_EXT) ? 1 : 0;
     a.lambda_vw = g->func.lambda_vw;
@@ -764,6 +769,7 @@ static void grid_free(ofdft_grid *g)
     dfree(g->twM);
     dfree(g->twN);
     dfree(g->vext);
+    dfree(g->gtab);
     dfree(reinterpret_cast<void *&>(g->ph0));
     dfree(reinterpret_cast<void *&>(g->ph1));
     dfree(reinterpret_cast<void *&>(g->ph2));
@@ -924,6 +930,9 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     } else {
         HIP_TRY(hipMemsetAsync(g->vext, 0, (size_t)G.Nh * 2 * g->fsz, s));
     }
+    ST_TRY(dmalloc(g, &g->gtab, 3 * (size_t)G.Nh * g->fsz));
+    HIP_TRY(g->fp64 ? launch_gtab<double>(G, g->kf_wt, g->gtab, s)
+                    : launch_gtab<float>(G, g->kf_wt, g->gtab, s));
     HIP_TRY(hipStreamSynchronize(s));
     g->e_ion = (f->terms & OFDFT_TERM_EXT) ? ewald_energy_host(g, nullptr) : 0.0;
     ST_TRY(dmalloc(g, &g->rho, (size_t)G.N * g->fsz));
@@ -1228,6 +1237,7 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     ofdft_grid *g = new (std::nothrow) ofdft_grid;
     if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
     g->ctx = ctx;
+    if (const char *e = std::getenv("OFDFT_COL_TILE_MAJOR")) g->tune_col_tile_major = std::atoi(e);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);
     if (st != OFDFT_OK) {
@@ -1262,6 +1272,7 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     uint64_t b = 0;
     b += (uint64_t)(2 * G.n0 + 2 * G.n1 + 2 * G.m + 2 * (G.m + 1)) * grid->fsz;    // twiddles
     b += (uint64_t)G.Nh * 2 * grid->fsz;                                              // v_ext
+    b += (uint64_t)G.Nh * 3 * grid->fsz;                                              // G tables
     b += (uint64_t)grid->natoms * (G.n0 + G.n1 + G.n2h) * 16;                         // phases
     b += (uint64_t)G.N * grid->fsz;                                                   // resident rho
     const uint64_t cap = (uint64_t)grid->cap;

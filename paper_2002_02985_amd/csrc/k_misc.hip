@@ -37,6 +37,34 @@ hipError_t launch_finalize(const double *part, int pstride, const int *count_dev
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- G tables
+// tab[e] = 1/G^2 (0 at G = 0), tab[Nh + e] = G^2,
+// tab[2 Nh + e] = C_WT G_NL(|G| / (2 kf)) for half-spectrum point e, in FP64.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gtab(Geom g, double kf, T *tab)
+{
+    const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+    if (e >= g.Nh) return;
+    const int k2 = (int)(e % g.n2h);
+    const long long row = e / g.n2h;
+    const int i1 = (int)(row % g.n1), i0 = (int)(row / g.n1);
+    const int m2 = (k2 == g.m) ? -g.m : k2;
+    const double G2 = gvec2<double>(g, freq(i0, g.n0), freq(i1, g.n1), m2);
+    tab[e] = T(G2 > 0.0 ? 1.0 / G2 : 0.0);
+    tab[g.Nh + e] = T(G2);
+    tab[2 * g.Nh + e] = T(C_WT_D * gnl_dev<double>(sqrt(G2) / (2.0 * kf)));
+}
+
+template <typename T>
+hipError_t launch_gtab(const Geom &g, double kf_wt, void *gtab, hipStream_t s)
+{
+    const long long nb = (g.Nh + NT - 1) / NT;
+    hipLaunchKernelGGL((k_gtab<T>), dim3((unsigned)nb), dim3(NT), 0, s, g, kf_wt, (T *)gtab);
+    return hipGetLastError();
+}
+template hipError_t launch_gtab<float>(const Geom &, double, void *, hipStream_t);
+template hipError_t launch_gtab<double>(const Geom &, double, void *, hipStream_t);
+
 // ---------------------------------------------------------------- v_ext(G)
 // v_ext(G) = (1/V) sum_s v_s(|G|) sum_{a in s} e^{-i G.R_a}; the phase is the
 // product of per-axis tables ph_d[a][i] = exp(-2 pi i m_d(i) s_{a,d}) (s the

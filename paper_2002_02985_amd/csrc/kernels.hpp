@@ -84,6 +84,8 @@ struct ColArgs {
     int nbatch;                 // field = blockIdx.y / nbatch
     int op[MAXKB];              // per field op (axis 0 only; zero elsewhere)
     const void *vext;           // half spectrum, field type (GO_HEXT)
+    const void *gtab;           // [1/G^2 | G^2 | omega_WT(G)], 3 x Nh values (field type)
+    int tile_major;             // block order: 1 tile-major, 0 array-major
     int use_h, use_ext;
     double lambda_vw;
     double kf_wt;               // GO_WT kernel Fermi wavevector
@@ -148,6 +150,11 @@ template <typename T> hipError_t launch_knot_acc(const KnotArgs &a, hipStream_t 
 template <typename T> hipError_t launch_row_inv(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
 template <typename T> int row_blocks(const Geom &g);
 template <typename T> int col_blocks(int L, long long ncols);
+
+// reciprocal-space tables of a grid: 1/G^2 (0 at G = 0), G^2 and the
+// Wang-Teter kernel C_WT G_NL(|G|/(2 kf)) on the half spectrum, built in FP64
+template <typename T>
+hipError_t launch_gtab(const Geom &g, double kf_wt, void *gtab, hipStream_t s);
 
 // FP64 reductions: sums[b][s] = sum_{i < count[s]} part[b][s][i]
 hipError_t launch_finalize(const double *part, int pstride, const int *count_dev, int nbatch,

@@ -316,30 +316,60 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 }
 
 // ================================================================ columns
+// Block order: array-major (consecutive blocks take adjacent tiles of one
+// array, which keeps DRAM pages open) or tile-major (consecutive blocks take
+// one tile of every (field, density) array, which keeps the tile's share of
+// the reciprocal-space tables in L2).
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_col(ColArgs a)
+__global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
 {
     constexpr int P = col_P<T, L>();
     constexpr int RSTEP = NT / P;
+    constexpr int PER = (L + RSTEP - 1) / RSTEP;
     static_assert(NT % P == 0, "tile width must divide the block");
     __shared__ cpx<T> buf[L * P];
     __shared__ double red[NT];
     const int tid = threadIdx.x;
-    const int fb = blockIdx.y;
+    const int fb = a.tile_major ? (int)(blockIdx.x % (unsigned)nfb)
+                                : (int)(blockIdx.x / (unsigned)ntiles);
+    const int tile = a.tile_major ? (int)(blockIdx.x / (unsigned)nfb)
+                                  : (int)(blockIdx.x % (unsigned)ntiles);
     const int p = tid % P;
-    const long long c = (long long)blockIdx.x * P + p;
+    const long long c = (long long)tile * P + p;
     const bool cvalid = c < a.ncols;
     const long long cbase = cvalid ? (c / a.inner) * a.outer_stride + (c % a.inner) : 0;
     const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
     cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
     const cpx<T> *tw = (const cpx<T> *)a.tw;
-
-    for (int n = tid / P; n < L; n += RSTEP)
-        buf[n * P + p] = cvalid ? src[cbase + n * a.elem_stride] : cpx<T>{T(0), T(0)};
-    __syncthreads();
     const int field = fb / a.nbatch;
     const int b = fb % a.nbatch;
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
+
+    for (int n = tid / P; n < L; n += RSTEP)
+        buf[n * P + p] = cvalid ? src[cbase + n * a.elem_stride] : cpx<T>{T(0), T(0)};
+    // reciprocal-space operands are fetched now so that their latency overlaps
+    // the forward transform: v_ext(G) for the Hartree+ion field, the
+    // Wang-Teter kernel for the nonlocal field (element n of column c is the
+    // half-spectrum point e = n * ncols + c on axis 0)
+    cpx<T> pre[PER];
+    if (op == GO_HEXT || op == GO_WT) {
+        const cpx<T> *vx = (const cpx<T> *)a.vext;
+        const T *om = (const T *)a.gtab + 2 * a.g.Nh;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int n = tid / P + q * RSTEP;
+            pre[q] = {T(0), T(0)};
+            if (n < L && cvalid) {
+                const long long e = (long long)n * a.ncols + c;
+                if (op == GO_HEXT) {
+                    if (a.use_ext) pre[q] = vx[e];
+                } else {
+                    pre[q].x = om[e];
+                }
+            }
+        }
+    }
+    __syncthreads();
     if (op == GO_NONE) {
         if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
         else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
@@ -347,38 +377,37 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a)
         // axis 0: element n is i0, column c is (i1, k2)
         lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
         const Geom &g = a.g;
+        const int t = opaque(tid);
         const int i1 = cvalid ? (int)(c / g.n2h) : 0;
         const int k2 = cvalid ? (int)(c % g.n2h) : 0;
         const int m1 = freq(i1, g.n1);
         const int m2 = (k2 == g.m) ? -g.m : k2;
         const double wgt = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
         const T invN = T(g.invN);
-        const cpx<T> *vx = (const cpx<T> *)a.vext;
         const T fourpi = T(4.0 * PI_D);
         double s0 = 0.0, s1 = 0.0;
-        for (int n = tid / P; n < L; n += RSTEP) {
-            if (!cvalid) continue;
-            const int m0 = freq(n, L);
-            const T G2 = gvec2<T>(g, m0, m1, m2);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int n = t / P + q * RSTEP;
+            if (n >= L || !cvalid) continue;
             const cpx<T> F = cscale(buf[n * P + p], invN);
             cpx<T> o = {T(0), T(0)};
             if (op == GO_HEXT) {
-                const cpx<T> v = vx[(long long)n * g.n1 * g.n2h + c];
-                if (G2 > T(0)) {
-                    const T ih = T(1) / G2;
-                    s0 += wgt * (double)((F.x * F.x + F.y * F.y) * ih);
-                    if (a.use_h) o = cscale(F, fourpi * ih);
-                }
+                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
+                const T ih = G2 > T(0) ? T(1) / G2 : T(0);
+                s0 += wgt * (double)((F.x * F.x + F.y * F.y) * ih);
+                if (a.use_h) o = cscale(F, fourpi * ih);
                 if (a.use_ext) {
+                    const cpx<T> v = pre[q];
                     s1 += wgt * (double)(v.x * F.x + v.y * F.y);
                     o = cadd(o, v);
                 }
             } else if (op == GO_VW) {
+                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
                 s0 += wgt * (double)(G2 * (F.x * F.x + F.y * F.y));
                 o = cscale(F, T(a.lambda_vw) * G2);
             } else if (op == GO_WT) {
-                const T eta = d_sqrt(G2) / (T(2) * T(a.kf_wt));
-                o = cscale(F, T(C_WT_D) * gnl_dev<T>(eta));
+                o = cscale(F, pre[q].x);
             } else {  // GO_SCALE
                 o = F;
             }
@@ -387,14 +416,12 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a)
         if (op == GO_HEXT || op == GO_VW) {
             double ss[2] = {s0, s1};
             block_sums<NT, 2>(ss, red, tid);
-            s0 = ss[0];
-            s1 = ss[1];
             if (tid == 0) {
                 if (op == GO_HEXT) {
-                    part_ptr(a.part, b, SL_H, a.pstride)[blockIdx.x] = s0;
-                    part_ptr(a.part, b, SL_EXT, a.pstride)[blockIdx.x] = s1;
+                    part_ptr(a.part, b, SL_H, a.pstride)[tile] = ss[0];
+                    part_ptr(a.part, b, SL_EXT, a.pstride)[tile] = ss[1];
                 } else {
-                    part_ptr(a.part, b, SL_VW, a.pstride)[blockIdx.x] = s0;
+                    part_ptr(a.part, b, SL_VW, a.pstride)[tile] = ss[0];
                 }
             }
         }
@@ -793,9 +820,13 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
 // spline interpolation.
 template <int N1> constexpr int plane_A() { return (N1 % 2 == 0) ? N1 + 1 : N1; }
 template <int N1, int M> constexpr int plane_NT() { return 1024; }
+// minimum resident waves per SIMD the compiler must allow: two 1024-thread
+// blocks per CU for FP32 (64 VGPRs), one for FP64
+template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? 8 : 4; }
 template <typename T, int N1, int M> constexpr bool plane_fits()
 {
-    return (long long)(M + 1) * plane_A<N1>() * 2 * sizeof(T) <= 98304;
+    // both kernels also stage the input plane (N1 x 2M reals) in LDS
+    return ((long long)(M + 1) * plane_A<N1>() * 2 + (long long)N1 * 2 * M) * sizeof(T) <= 98304;
 }
 
 // X[k] from Z[k] and Z[M-k] (r2c unpack), W^k = twN[k]
@@ -820,7 +851,7 @@ __device__ __forceinline__ cpx<T> c2r_pack(cpx<T> xk, cpx<T> xm, cpx<T> w)
 }
 
 template <typename T, int N1, int M>
-__global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_fwd(RowFwdArgs a, Geom g)
+__global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plane_fwd(RowFwdArgs a, Geom g)
 {
     constexpr int NTP = plane_NT<N1, M>();
     constexpr int A = plane_A<N1>();
@@ -828,6 +859,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_fwd(RowFwdArgs a,
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     constexpr int HALF = M / 2 + 1;
     __shared__ cpx<T> buf[(M + 1) * A];
+    __shared__ cpx<T> xs[N1 * M];   // the input plane, read once from HBM
     __shared__ double red[3 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
@@ -842,7 +874,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_fwd(RowFwdArgs a,
     for (int q = 0; q < PER; ++q) {
         const int idx = tid + q * NTP;
         x[q] = idx < PAIRS ? in[idx] : cpx<T>{T(0), T(0)};
+        if (idx < PAIRS) xs[idx] = x[q];
     }
+    __syncthreads();
     const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
     if (a.partials) {
         double sums[3] = {0.0, 0.0, 0.0};
@@ -881,7 +915,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_fwd(RowFwdArgs a,
             const int idx = t + q * NTP;
             if (idx >= PAIRS) continue;
             const int i1 = idx / M, n = idx % M;
-            const T xv[2] = {x[q].x, x[q].y};
+            const cpx<T> xq = xs[idx];
+            const T xv[2] = {xq.x, xq.y};
             T o[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -979,14 +1014,15 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
     lds_fft<T, M, true, N1, NTP, A, 1>(buf, twM, tid);
 }
 
-template <typename T, int N1, int M>
-__global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a, Geom g)
+template <typename T, int N1, int M, int MODE>
+__global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plane_inv(RowInvArgs a, Geom g)
 {
     constexpr int NTP = plane_NT<N1, M>();
     constexpr int A = plane_A<N1>();
     constexpr int PAIRS = N1 * M;
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     __shared__ cpx<T> buf[(M + 1) * A];
+    __shared__ cpx<T> xsbuf[N1 * M];
     __shared__ double red[4 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
@@ -1003,7 +1039,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         return (idx % M) * A + idx / M;
     };
 
-    if (a.mode == EP_STORE) {
+    if constexpr (MODE == EP_STORE) {
 #pragma unroll 1
         for (int f = 0; f < a.nfields; ++f) {
             const int t = opaque(tid);
@@ -1016,6 +1052,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         }
         return;
     }
+    else {
 
     const cpx<T> *in = (const cpx<T> *)((const T *)a.in + real_off);
     cpx<T> xin[PER];
@@ -1023,7 +1060,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
     for (int q = 0; q < PER; ++q)
         xin[q] = tid + q * NTP < PAIRS ? in[tid + q * NTP] : cpx<T>{T(0), T(0)};
 
-    if (a.mode == EP_KNOTS) {
+    if constexpr (MODE == EP_KNOTS) {
         int jj[PER][2];
         T tt[PER][2];
         cpx<T> v1[PER], v2[PER];
@@ -1090,8 +1127,16 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         }
         return;
     }
+    else {
 
-    // EP_COMBINE, one field at a time into v and g
+    // EP_COMBINE, one field at a time into v and g.  The input plane is kept
+    // in LDS (xs) rather than in registers, so that a thread carries only its
+    // v and g accumulators through the transforms.
+    cpx<T> *xs = (cpx<T> *)xsbuf;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
+    __syncthreads();
     const T alpha = T(a.alpha);
     const T floor_rho = T(a.floor);
     const T lfloor = d_log2(floor_rho);
@@ -1122,8 +1167,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         for (int q = 0; q < PER; ++q) {
             if (t + q * NTP >= PAIRS) continue;
             const cpx<T> z = buf[at(t, q)];
+            const cpx<T> xq = xs[t + q * NTP];
             const T zv[2] = {z.x, z.y};
-            const cpx<T> xq = opaque(xin[q]);
             const T xv[2] = {xq.x, xq.y};
             T dv[2], dg[2];
 #pragma unroll
@@ -1166,7 +1211,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
         if (acc1) s1 = acc1[idx];
         if (acc2) s2 = acc2[idx];
-        const T xv[2] = {xin[q].x, xin[q].y};
+        const cpx<T> xq = xs[idx];
+        const T xv[2] = {xq.x, xq.y};
         const T s1v[2] = {s1.x, s1.y}, s2v[2] = {s2.x, s2.y};
         T vv[2] = {vacc[q].x, vacc[q].y};
         T gg[2] = {gacc[q].x, gacc[q].y};
@@ -1209,6 +1255,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>())) void k_plane_inv(RowInvArgs a,
         part_ptr(a.part, b, SL_GG, a.pstride)[i0] = sums[2];
         part_ptr(a.part, b, SL_PHIPHI, a.pstride)[i0] = sums[3];
     }
+    }
+    }
 }
 
 #define OFDFT_PLANES(X) \
@@ -1238,8 +1286,13 @@ hipError_t plane_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStr
     } else {
         nblocks = g.n0;
         if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_plane_inv<T, N1, M>), dim3(g.n0, a.nbatch),
-                           dim3(plane_NT<N1, M>()), 0, s, a, g);
+        const dim3 grid(g.n0, a.nbatch), block(plane_NT<N1, M>());
+        if (a.mode == EP_STORE)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_STORE>), grid, block, 0, s, a, g);
+        else if (a.mode == EP_KNOTS)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_KNOTS>), grid, block, 0, s, a, g);
+        else
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE>), grid, block, 0, s, a, g);
         return hipGetLastError();
     }
 }
@@ -1305,8 +1358,9 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
     bool has_part = false;
     for (int f = 0; f < MAXKB; ++f) has_part |= (a.op[f] == GO_HEXT || a.op[f] == GO_VW);
     if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
-    dim3 grid(nblocks, nfb);
-    hipLaunchKernelGGL((k_col<T, L>), grid, dim3(NT), 0, s, a);
+    const long long total = (long long)nblocks * nfb;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_col<T, L>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb, nblocks);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libofdft.so")
+LIB_PATH = os.environ.get("OFDFT_LIB", os.path.join(HERE, "libofdft.so"))
 
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOCONV, ECANCELLED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
 TERM_TF, TERM_VW, TERM_HARTREE, TERM_EXT, TERM_WT, TERM_SPLINE = 1, 2, 4, 8, 16, 32
