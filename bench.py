@@ -27,6 +27,85 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 NDENS = 200
 N_GRID = (96, 96, 96)
+CSRC = os.path.join(ROOT, "paper_2002_02985_amd", "csrc")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_al108_96cubed_x200.json")
+COPY_BYTES = 268435456
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources; measured counters are only reported
+    while the kernels they were taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    import json as _json
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    d = _json.load(open(TRAFFIC_JSON))
+    if d.get("source_sha256") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_name)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def ingest_counters(fetch_csv, write_csv, command):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of this benchmark
+    (run with --copy-calibration) into per-launch HBM bytes, calibrated by the
+    counters of the 256 MiB device copy, and write the profile summaries."""
+    import csv
+    import collections
+    import json as _json
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        agg = collections.defaultdict(list)
+        for r in rows:
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return rows, agg
+
+    frows, fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    wrows, write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def copy_value(rows):
+        # the single device-to-device copy of COPY_BYTES bytes
+        best = None
+        for r in rows:
+            if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower():
+                v = float(r["Counter_Value"])
+                if best is None or v > best:
+                    best = v
+        return best
+
+    f_copy = copy_value(frows)
+    w_copy = copy_value(wrows)
+    f_factor = (COPY_BYTES / 1024.0) / f_copy
+    w_factor = (COPY_BYTES / 1024.0) / w_copy
+    kernels = {}
+    for name in fetch:
+        if "ofdft" not in name:
+            continue
+        fk = sum(fetch[name]) / len(fetch[name])
+        wk = sum(write.get(name, [0.0])) / max(1, len(write.get(name, [0.0])))
+        short = name.split("(")[0].replace("void ofdft::", "")
+        kernels[short] = {"fetch_kib": fk, "write_kib": wk,
+                          "bytes_per_launch": (fk * f_factor + wk * w_factor) * 1024.0,
+                          "launches": len(fetch[name])}
+    out = {"source_sha256": kernel_source_hash(), "command": command,
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": f_copy, "write_kib": w_copy,
+                                "fetch_factor": f_factor, "write_factor": w_factor},
+           "kernels": kernels}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as fh:
+        _json.dump(out, fh, indent=1)
+    return out
 
 
 def parse():
@@ -40,6 +119,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary from rocprofv3 counter CSVs and exit")
+    ap.add_argument("--counter-command", default="",
+                    help="the rocprofv3 command line recorded with --ingest-counters")
     return ap.parse_args()
 
 
@@ -128,6 +211,11 @@ def cpu_baseline(cell, dens, nsample):
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        out = ingest_counters(args.ingest_counters[0], args.ingest_counters[1],
+                              args.counter_command)
+        print(json.dumps(out, indent=1))
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
               "(per-GPU throughput is the single-GPU figure)" % args.gpus, file=sys.stderr)
@@ -141,7 +229,7 @@ def main():
         sys.exit(1)
 
     if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -176,9 +264,12 @@ def main():
     avg_ms = ms / n
     nbytes = pass_bytes(name, NDENS, N, Nh, nfields, 4)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+    kname = {"row_fwd": "k_plane_fwd<float, 96, 48>", "row_inv": "k_plane_inv<float, 96, 48, 1>",
+             "col0_g": "k_col<float, 96>"}.get(name)
+    traffic = measured_traffic(kname) if kname else None
+    roof = {"bound": "hbm", "kernel": kname or name, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 4)}
+            "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_ms": round(avg_ms, 4)}
     passes_out = {}
     for k, (pms, pn) in mixed["passes"].items():
         b = pass_bytes(k, NDENS, N, Nh, nfields, 4)
