@@ -50,10 +50,11 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 1
+#define OFDFT_ABI_VERSION 2
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
+typedef struct ofdft_server ofdft_server;
 
 typedef enum {
     OFDFT_OK = 0,
@@ -127,8 +128,20 @@ const char *ofdft_last_error(void);
 /* 1 if n is an FFT length the library has kernels for, else 0. */
 int ofdft_supported_length(int32_t n);
 
+/* A context is one device and one HIP stream (non-blocking, default
+ * priority) on which the grids created from it run. */
 ofdft_status ofdft_ctx_create(int device, ofdft_ctx **out);
 void ofdft_ctx_destroy(ofdft_ctx *ctx);
+
+/* Host-only checks (no device needed): whether a cell and functional are
+ * accepted by ofdft_grid_create, and the device bytes a request of the given
+ * kind (OFDFT_REQ_*) needs on a new grid: fixed tables, workspace for one
+ * density, host-API staging, plus the optimiser vectors (OPTIMIZE) or the
+ * force buffer (FORCES).  These are the figures the server admits by. */
+ofdft_status ofdft_validate(const ofdft_cell_desc *cell, const ofdft_functional_desc *func);
+ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell,
+                                   const ofdft_functional_desc *func, int32_t kind,
+                                   uint64_t *bytes);
 
 /* Builds the grid: reciprocal vectors, twiddle tables, the ionic structure
  * factor and v_ext(G) (exact direct sum over atoms, separable phases), the
@@ -192,7 +205,7 @@ typedef struct {
     double tol;
     int32_t max_iter;
     int32_t method;   /* 0: CG (Polak-Ribiere+) */
-    int32_t warm;     /* reserved */
+    int32_t warm;     /* server requests: start from the resident density */
 } ofdft_opt_params;
 typedef struct {
     ofdft_energy e;
@@ -201,6 +214,79 @@ typedef struct {
 } ofdft_opt_result;
 ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params,
                             ofdft_opt_result *result);
+
+/* ------------------------------------------------------------------ serving
+ * A request server for many cells on one device: energy+potential, force and
+ * optimisation requests (the three operations above) are submitted from any
+ * thread and run by max_inflight worker slots, each with its own stream, so
+ * that requests admitted while others are on the device overlap with them.
+ *
+ * Residency and warm starts: each cell_id keeps its grid, and with it its
+ * density, on the device after a request completes.  A later request with the
+ * same cell_id, lattice, grid, species and functional reuses that grid; if
+ * only the atom positions changed (successive MD frames) the structure factor,
+ * v_ext(G) and E_ion are rebuilt in place and the resident density is the
+ * warm start.  Requests of one cell_id run one at a time in submission order.
+ *
+ * Admission by HBM footprint: a request that needs a new grid is admitted
+ * when its footprint (ofdft_footprint_bytes, OPTIMIZE kind, so a resident
+ * grid never grows) fits in hbm_budget_bytes next to the resident grids;
+ * idle resident grids are evicted least recently used first, those with no
+ * queued request before the others.  A request that cannot fit yet waits, and
+ * no later request that needs new memory overtakes it; requests for resident
+ * grids still run.  A footprint above the whole budget is refused at submit
+ * with OFDFT_ENOMEM.
+ *
+ * Request kinds and results:
+ *   EP        energy and potential of rho_or_null, else of the resident
+ *             density (a cell with none starts from the uniform density
+ *             nelec/V); fills res->e and, at poll, v (N doubles).
+ *   FORCES    energy and forces (natoms x 3, Ha/Bohr) of that density;
+ *             fills res->e and f.
+ *   OPTIMIZE  density optimisation with *opt from rho_or_null if given, else
+ *             from the resident density when opt->warm != 0, else from the
+ *             uniform density; fills res (OFDFT_ENOCONV if max_iter was hit).
+ *   In every kind rho_or_null, when given, becomes the resident density, and
+ *   OPTIMIZE leaves the optimised density resident.
+ * submit deep-copies the request (descriptors, positions, density) and checks
+ * it (OFDFT_EINVAL for a bad descriptor or a non-finite or negative density).
+ * poll returns OFDFT_PENDING until the request has finished, then its final
+ * status (OK, ENOCONV, ECANCELLED or an error, with ofdft_last_error() set),
+ * copies the results into the non-NULL outputs and releases the ticket;
+ * unknown or released tickets give OFDFT_ENOTFOUND.  cancel removes a queued
+ * request, asks a running optimisation to stop at its next iteration and
+ * discards any result: poll then gives OFDFT_ECANCELLED.  submit, poll, wait,
+ * cancel and stats are thread-safe.  destroy cancels what is queued, waits
+ * for what runs and frees every grid. */
+enum { OFDFT_REQ_EP = 0, OFDFT_REQ_FORCES = 1, OFDFT_REQ_OPTIMIZE = 2 };
+typedef struct {
+    uint64_t cell_id;
+    int32_t kind;
+    const ofdft_cell_desc *cell;
+    const ofdft_functional_desc *func;
+    const ofdft_opt_params *opt;   /* OPTIMIZE only */
+    const double *rho_or_null;     /* N doubles or NULL */
+} ofdft_request;
+typedef struct {
+    uint64_t submitted, completed, failed, cancelled;
+    int32_t queued, running, resident_cells, max_inflight;
+    uint64_t resident_bytes, peak_bytes, budget_bytes;
+    double p50_ms, p99_ms;          /* submit-to-finish latency of completed requests */
+    double mean_queue_ms;           /* submit-to-start                                */
+} ofdft_serve_stats;
+ofdft_status ofdft_server_create(ofdft_ctx *ctx, uint64_t hbm_budget_bytes,
+                                 int32_t max_inflight, ofdft_server **out);
+ofdft_status ofdft_serve_submit(ofdft_server *srv, const ofdft_request *req,
+                                uint64_t *ticket);
+ofdft_status ofdft_serve_poll(ofdft_server *srv, uint64_t ticket, ofdft_opt_result *res,
+                              double *v_or_null, double *f_or_null);
+/* Blocks until the request has finished (OFDFT_OK) or timeout_ms has passed
+ * (OFDFT_PENDING); does not release the ticket.  timeout_ms < 0 waits
+ * without limit. */
+ofdft_status ofdft_serve_wait(ofdft_server *srv, uint64_t ticket, int32_t timeout_ms);
+ofdft_status ofdft_serve_cancel(ofdft_server *srv, uint64_t ticket);
+ofdft_status ofdft_serve_stats_get(ofdft_server *srv, ofdft_serve_stats *out);
+void ofdft_server_destroy(ofdft_server *srv);
 
 /* Per-pass timing of the evaluation pipeline (a profiling aid): when
  * enabled, every kernel launch of the passes below is bracketed by HIP events

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ofdft.h"
+#include "internal.hpp"
 #include "kernels.hpp"
 
 using namespace ofdft;
@@ -40,6 +42,7 @@ static ofdft_status fail(ofdft_status st, const std::string &msg)
     } while (0)
 
 static const double PI = 3.14159265358979323846264338327950288;
+static const int NVEC_OPT = 8;   // optimiser vectors per grid
 static const double C_TF = 2.8712340001881918;
 
 // ---------------------------------------------------------------- handles
@@ -87,6 +90,7 @@ struct ofdft_grid {
     bool fp64 = true;
     size_t fsz = 8;
     Geom geom;
+    double frac[3][3];   // fractional coordinates s_j = sum_i frac[j][i] R_i
     double V = 0, dv = 0;
     Knots knots;
     std::vector<double> knot_host;
@@ -115,8 +119,10 @@ struct ofdft_grid {
     void *rho = nullptr;
     void *opt[9] = {nullptr};
     size_t bytes = 0;
+    double *d_forces = nullptr;   // natoms x 3
     Timer timer;
     int tune_col_tile_major = 0;   // block order of the column passes
+    const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
 };
 
 // ---------------------------------------------------------------- helpers
@@ -141,6 +147,15 @@ static void dfree(void *&p)
     p = nullptr;
 }
 
+// synchronous upload on the grid's stream (the stream is non-blocking, so no
+// implicit ordering with other streams of the process)
+static ofdft_status h2d(ofdft_grid *g, void *dst, const void *src, size_t bytes)
+{
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, g->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(g->ctx->stream));
+    return OFDFT_OK;
+}
+
 template <typename T>
 static std::vector<T> to_type(const double *src, size_t n)
 {
@@ -160,10 +175,10 @@ static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt)
     }
     ST_TRY(dmalloc(g, dst, (size_t)cnt * 2 * g->fsz));
     if (g->fp64) {
-        HIP_TRY(hipMemcpy(*dst, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, *dst, t.data(), t.size() * 8));
     } else {
         auto f = to_type<float>(t.data(), t.size());
-        HIP_TRY(hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, *dst, f.data(), f.size() * 4));
     }
     return OFDFT_OK;
 }
@@ -331,11 +346,10 @@ static void timer_collect(ofdft_grid *g)
     } while (0)
 
 // ---------------------------------------------------------------- workspace
-static int max_pstride(const ofdft_grid *g)
+static int max_pstride(const Geom &G, bool fp64)
 {
-    const Geom &G = g->geom;
     int rb, c0, c1;
-    if (g->fp64) {
+    if (fp64) {
         rb = row_blocks<double>(G);
         c0 = col_blocks<double>(G.n0, (long long)G.n1 * G.n2h);
         c1 = col_blocks<double>(G.n1, (long long)G.n0 * G.n2h);
@@ -345,6 +359,38 @@ static int max_pstride(const ofdft_grid *g)
         c1 = col_blocks<float>(G.n1, (long long)G.n0 * G.n2h);
     }
     return std::max({rb, c0, c1, dots_blocks(G.N), G.n0, 1});
+}
+
+// Device bytes of a grid as allocated by this file: fixed tables, workspace
+// for `cap` densities, and optionally the host-API staging fields, the
+// optimiser vectors and the forces buffer.  Used both to report what a grid
+// holds and to size a request before any allocation.
+struct BytesModel {
+    bool stage = false, opt = false, forces = false;
+};
+static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, uint32_t terms,
+                            int nl_mode, int nk, uint64_t cap, BytesModel m)
+{
+    const uint64_t N = (uint64_t)G.N, Nh = (uint64_t)G.Nh, cb = 2 * fsz;
+    uint64_t b = 0;
+    b += (uint64_t)(G.n0 + G.n1 + G.m + (G.m + 1)) * cb;             // twiddles
+    b += Nh * cb;                                                       // v_ext
+    b += Nh * 3 * fsz;                                                  // G tables
+    b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;                 // phase tables
+    b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
+    b += (uint64_t)NSLOT * 4 + (uint64_t)nk * 8;                        // counts, knots
+    b += N * fsz;                                                       // resident rho
+    b += 4 * cap * Nh * cb;                                             // spectra
+    if (terms & OFDFT_TERM_SPLINE) {
+        b += (uint64_t)MAXKB * cap * Nh * cb;                           // knot spectra
+        b += cap * N * fsz;                                             // accumulator
+        if (nl_mode == OFDFT_NL_EXACT) b += cap * N * fsz;
+    }
+    b += cap * NSLOT * (uint64_t)max_pstride(G, fsz == 8) * 8 + cap * NSLOT * 8;   // partials
+    if (m.stage) b += 2 * N * fsz;
+    if (m.opt) b += (uint64_t)NVEC_OPT * N * fsz;
+    if (m.forces) b += (uint64_t)natoms * 3 * 8;
+    return b;
 }
 
 static ofdft_status reserve(ofdft_grid *g, int nb)
@@ -372,7 +418,7 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
         if (g->func.nl_mode == OFDFT_NL_EXACT)
             ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
     }
-    g->pstride = max_pstride(g);
+    g->pstride = max_pstride(G, g->fp64);
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->part),
                    (size_t)nb * NSLOT * g->pstride * sizeof(double)));
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->sums), (size_t)nb * NSLOT * sizeof(double)));
@@ -720,6 +766,22 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
 }
 
 // ---------------------------------------------------------------- grid set-up
+// grid sizes of a cell (reciprocal vectors are filled in by grid_setup)
+static Geom make_geom(const int32_t n[3])
+{
+    Geom G;
+    std::memset(&G, 0, sizeof(G));
+    G.n0 = n[0];
+    G.n1 = n[1];
+    G.n2 = n[2];
+    G.m = n[2] / 2;
+    G.n2h = G.m + 1;
+    G.N = (long long)G.n0 * G.n1 * G.n2;
+    G.Nh = (long long)G.n0 * G.n1 * G.n2h;
+    G.invN = 1.0 / (double)G.N;
+    return G;
+}
+
 static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_desc *f)
 {
     if (!c || !f) return fail(OFDFT_EINVAL, "null descriptor");
@@ -787,6 +849,7 @@ static void grid_free(ofdft_grid *g)
     dfree(g->stage_out);
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
+    dfree(reinterpret_cast<void *&>(g->d_forces));
     dfree(g->rho);
     for (auto &p : g->opt) dfree(p);
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -795,77 +858,14 @@ static void grid_free(ofdft_grid *g)
     g->timer.ev.clear();
 }
 
-static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const ofdft_functional_desc *f)
+// Ionic part of the set-up, also rerun when the atoms move (MD frames of a
+// resident cell): per-axis phase tables exp(-i 2 pi m_d s_d) for every atom,
+// the species-sorted direct sum v_ext(G) = (1/V) sum_a v~(|G|) exp(-iG.R_a)
+// of eq. "ie" and the Ewald energy.  Buffers keep their sizes because the atom
+// count and species are fixed for a grid.
+static ofdft_status setup_ions(ofdft_grid *g)
 {
-    std::memcpy(g->lattice, c->lattice, sizeof(g->lattice));
-    for (int d = 0; d < 3; ++d) g->n[d] = c->n[d];
-    g->natoms = c->natoms;
-    g->pos.assign(c->pos, c->pos + 3 * (size_t)c->natoms);
-    g->species.assign(c->species, c->species + c->natoms);
-    g->Z.assign(c->Z, c->Z + std::max(c->nspecies, 0));
-    g->rc.assign(c->rc, c->rc + std::max(c->nspecies, 0));
-    g->nelec = c->nelec;
-    g->func = *f;
-    g->fp64 = f->precision == OFDFT_FP64;
-    g->fsz = g->fp64 ? 8 : 4;
-
-    // geometry: b_j with a_i . b_j = 2 pi delta_ij  (b = 2 pi inv(A)^T)
-    const double(*A)[3] = g->lattice;
-    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
-                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
-                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
-    if (!(std::fabs(det) > 0)) return fail(OFDFT_EINVAL, "singular lattice");
-    g->V = std::fabs(det);
-    double cof[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
-            cof[i][j] = A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1];
-        }
-    Geom &G = g->geom;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) G.b[i][j] = 2.0 * PI * cof[i][j] / det;
-    G.n0 = c->n[0];
-    G.n1 = c->n[1];
-    G.n2 = c->n[2];
-    G.m = c->n[2] / 2;
-    G.n2h = G.m + 1;
-    G.N = (long long)G.n0 * G.n1 * G.n2;
-    G.Nh = (long long)G.n0 * G.n1 * G.n2h;
-    G.invN = 1.0 / (double)G.N;
-    g->dv = g->V / (double)G.N;
-
-    // knots (step s1): geometric or arithmetic, both ends included
-    std::memset(&g->knots, 0, sizeof(g->knots));
-    if (f->terms & OFDFT_TERM_SPLINE) {
-        Knots &K = g->knots;
-        K.nk = f->nk;
-        K.log_spacing = f->knot_spacing == OFDFT_KNOTS_LOG;
-        std::vector<double> &k = g->knot_host;
-        k.resize(f->nk);
-        for (int i = 0; i < f->nk; ++i) {
-            const double u = f->nk > 1 ? (double)i / (double)(f->nk - 1) : 0.0;
-            k[i] = K.log_spacing ? f->kf_min * std::pow(f->kf_max / f->kf_min, u)
-                                 : f->kf_min + (f->kf_max - f->kf_min) * u;
-        }
-        if (f->nk > 1)
-            K.inv_span = K.log_spacing ? (f->nk - 1) / std::log(k[f->nk - 1] / k[0])
-                                       : (f->nk - 1) / (k[f->nk - 1] - k[0]);
-        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_knots), k.size() * sizeof(double)));
-        HIP_TRY(hipMemcpy(g->d_knots, k.data(), k.size() * sizeof(double), hipMemcpyHostToDevice));
-        K.k = g->d_knots;
-    }
-    g->kf_wt = f->kf_wt > 0 ? f->kf_wt : std::cbrt(3.0 * PI * PI * g->nelec / g->V);
-
-    // twiddles
-    ST_TRY(upload_twiddles(g, &g->tw0, G.n0, G.n0));
-    ST_TRY(upload_twiddles(g, &g->tw1, G.n1, G.n1));
-    ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m));
-    ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1));
-
-    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_count), NSLOT * sizeof(int)));
-
-    // ionic structure factor tables and v_ext(G)
+    const Geom &G = g->geom;
     const int na = g->natoms;
     const int ns = (int)g->Z.size();
     if (na > 0) {
@@ -874,7 +874,7 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
         for (int a = 0; a < na; ++a)
             for (int j = 0; j < 3; ++j) {
                 double s = 0;
-                for (int i = 0; i < 3; ++i) s += g->pos[3 * a + i] * cof[j][i] / det;
+                for (int i = 0; i < 3; ++i) s += g->pos[3 * a + i] * g->frac[j][i];
                 fr[3 * a + j] = s - std::floor(s);
             }
         // atoms sorted by species
@@ -904,20 +904,19 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
                 }
             }
             ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]), t.size() * sizeof(double)));
-            HIP_TRY(hipMemcpy(*tabs[d], t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+            ST_TRY(h2d(g, *tabs[d], t.data(), t.size() * sizeof(double)));
         }
         std::vector<int> sorted_species(na);
         for (int a = 0; a < na; ++a) sorted_species[a] = g->species[order[a]];
         g->species_order = order;
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_spec_off), (ns + 1) * sizeof(int)));
-        HIP_TRY(hipMemcpy(g->d_spec_off, off.data(), (ns + 1) * sizeof(int), hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, g->d_spec_off, off.data(), (ns + 1) * sizeof(int)));
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_atom_species), na * sizeof(int)));
-        HIP_TRY(hipMemcpy(g->d_atom_species, sorted_species.data(), na * sizeof(int),
-                          hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, g->d_atom_species, sorted_species.data(), na * sizeof(int)));
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_Z), ns * sizeof(double)));
-        HIP_TRY(hipMemcpy(g->d_Z, g->Z.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, g->d_Z, g->Z.data(), ns * sizeof(double)));
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_rc), ns * sizeof(double)));
-        HIP_TRY(hipMemcpy(g->d_rc, g->rc.data(), ns * sizeof(double), hipMemcpyHostToDevice));
+        ST_TRY(h2d(g, g->d_rc, g->rc.data(), ns * sizeof(double)));
     }
     ST_TRY(dmalloc(g, &g->vext, (size_t)G.Nh * 2 * g->fsz));
     hipStream_t s = g->ctx->stream;
@@ -930,11 +929,82 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     } else {
         HIP_TRY(hipMemsetAsync(g->vext, 0, (size_t)G.Nh * 2 * g->fsz, s));
     }
+    HIP_TRY(hipStreamSynchronize(s));
+    g->e_ion = (g->func.terms & OFDFT_TERM_EXT) ? ewald_energy_host(g, nullptr) : 0.0;
+    return OFDFT_OK;
+}
+
+static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const ofdft_functional_desc *f)
+{
+    std::memcpy(g->lattice, c->lattice, sizeof(g->lattice));
+    for (int d = 0; d < 3; ++d) g->n[d] = c->n[d];
+    g->natoms = c->natoms;
+    g->pos.assign(c->pos, c->pos + 3 * (size_t)c->natoms);
+    g->species.assign(c->species, c->species + c->natoms);
+    g->Z.assign(c->Z, c->Z + std::max(c->nspecies, 0));
+    g->rc.assign(c->rc, c->rc + std::max(c->nspecies, 0));
+    g->nelec = c->nelec;
+    g->func = *f;
+    g->fp64 = f->precision == OFDFT_FP64;
+    g->fsz = g->fp64 ? 8 : 4;
+
+    // geometry: b_j with a_i . b_j = 2 pi delta_ij  (b = 2 pi inv(A)^T)
+    const double(*A)[3] = g->lattice;
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(std::fabs(det) > 0)) return fail(OFDFT_EINVAL, "singular lattice");
+    g->V = std::fabs(det);
+    double cof[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            cof[i][j] = A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1];
+        }
+    g->geom = make_geom(c->n);
+    Geom &G = g->geom;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G.b[i][j] = 2.0 * PI * cof[i][j] / det;
+    g->dv = g->V / (double)G.N;
+
+    // knots (step s1): geometric or arithmetic, both ends included
+    std::memset(&g->knots, 0, sizeof(g->knots));
+    if (f->terms & OFDFT_TERM_SPLINE) {
+        Knots &K = g->knots;
+        K.nk = f->nk;
+        K.log_spacing = f->knot_spacing == OFDFT_KNOTS_LOG;
+        std::vector<double> &k = g->knot_host;
+        k.resize(f->nk);
+        for (int i = 0; i < f->nk; ++i) {
+            const double u = f->nk > 1 ? (double)i / (double)(f->nk - 1) : 0.0;
+            k[i] = K.log_spacing ? f->kf_min * std::pow(f->kf_max / f->kf_min, u)
+                                 : f->kf_min + (f->kf_max - f->kf_min) * u;
+        }
+        if (f->nk > 1)
+            K.inv_span = K.log_spacing ? (f->nk - 1) / std::log(k[f->nk - 1] / k[0])
+                                       : (f->nk - 1) / (k[f->nk - 1] - k[0]);
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_knots), k.size() * sizeof(double)));
+        ST_TRY(h2d(g, g->d_knots, k.data(), k.size() * sizeof(double)));
+        K.k = g->d_knots;
+    }
+    g->kf_wt = f->kf_wt > 0 ? f->kf_wt : std::cbrt(3.0 * PI * PI * g->nelec / g->V);
+
+    // twiddles
+    ST_TRY(upload_twiddles(g, &g->tw0, G.n0, G.n0));
+    ST_TRY(upload_twiddles(g, &g->tw1, G.n1, G.n1));
+    ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m));
+    ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1));
+
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_count), NSLOT * sizeof(int)));
+
+    for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i) g->frac[j][i] = cof[j][i] / det;
+    ST_TRY(setup_ions(g));
     ST_TRY(dmalloc(g, &g->gtab, 3 * (size_t)G.Nh * g->fsz));
+    hipStream_t s = g->ctx->stream;
     HIP_TRY(g->fp64 ? launch_gtab<double>(G, g->kf_wt, g->gtab, s)
                     : launch_gtab<float>(G, g->kf_wt, g->gtab, s));
     HIP_TRY(hipStreamSynchronize(s));
-    g->e_ion = (f->terms & OFDFT_TERM_EXT) ? ewald_energy_host(g, nullptr) : 0.0;
     ST_TRY(dmalloc(g, &g->rho, (size_t)G.N * g->fsz));
     return OFDFT_OK;
 }
@@ -975,7 +1045,7 @@ static hipStream_t pick_stream(ofdft_grid *g, void *hs)
 // ---------------------------------------------------------------- optimiser
 // Vectors: 0 phi, 1 p (search direction on the sphere), 2 d (raw direction),
 // 3 R (residual), 4 R_prev, 5 g (dE/dphi at phi), 6 phi trial, 7 g trial.
-enum { V_PHI = 0, V_P, V_D, V_R, V_RP, V_G, V_PT, V_GT, NVEC = 8 };
+enum { V_PHI = 0, V_P, V_D, V_R, V_RP, V_G, V_PT, V_GT, NVEC = NVEC_OPT };
 
 struct OptState {
     ofdft_grid *g;
@@ -1064,6 +1134,8 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
             converged = true;
             break;
         }
+        if (g->cancel && g->cancel->load(std::memory_order_relaxed))
+            return fail(OFDFT_ECANCELLED, "optimisation cancelled");
         // R = g - 2 mu phi
         ST_TRY(lincomb<T>(o, v[V_R], 1.0, v[V_G], -2.0 * E.mu, v[V_PHI]));
         double dd[3];
@@ -1189,6 +1261,29 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     return OFDFT_OK;
 }
 
+// ================================================================ internal
+namespace ofdft_internal {
+
+ofdft_status set_positions(ofdft_grid *g, const double *pos)
+{
+    if (!g || (g->natoms > 0 && !pos)) return fail(OFDFT_EINVAL, "null argument");
+    for (int i = 0; i < 3 * g->natoms; ++i)
+        if (!std::isfinite(pos[i])) return fail(OFDFT_EINVAL, "non-finite position");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    g->pos.assign(pos, pos + 3 * (size_t)g->natoms);
+    return setup_ions(g);
+}
+
+void bind_context(ofdft_grid *g, ofdft_ctx *ctx) { g->ctx = ctx; }
+
+void set_cancel(ofdft_grid *g, const std::atomic<int> *flag) { g->cancel = flag; }
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int ctx_device(const ofdft_ctx *ctx) { return ctx->device; }
+
+}  // namespace ofdft_internal
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -1209,10 +1304,10 @@ ofdft_status ofdft_ctx_create(int device, ofdft_ctx **out)
     ofdft_ctx *c = new (std::nothrow) ofdft_ctx;
     if (!c) return fail(OFDFT_ENOMEM, "host allocation failed");
     c->device = device;
-    hipError_t e = hipStreamCreate(&c->stream);
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
-        return fail(OFDFT_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        return fail(OFDFT_EDEVICE, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
     }
     *out = c;
     return OFDFT_OK;
@@ -1268,22 +1363,39 @@ ofdft_status ofdft_grid_reserve(ofdft_grid *grid, int32_t nbatch)
 uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
 {
     if (!grid) return 0;
-    const Geom &G = grid->geom;
-    uint64_t b = 0;
-    b += (uint64_t)(2 * G.n0 + 2 * G.n1 + 2 * G.m + 2 * (G.m + 1)) * grid->fsz;    // twiddles
-    b += (uint64_t)G.Nh * 2 * grid->fsz;                                              // v_ext
-    b += (uint64_t)G.Nh * 3 * grid->fsz;                                              // G tables
-    b += (uint64_t)grid->natoms * (G.n0 + G.n1 + G.n2h) * 16;                         // phases
-    b += (uint64_t)G.N * grid->fsz;                                                   // resident rho
-    const uint64_t cap = (uint64_t)grid->cap;
-    b += 4 * cap * G.Nh * 2 * grid->fsz;
-    if (grid->kspec) b += (uint64_t)MAXKB * cap * G.Nh * 2 * grid->fsz;
-    if (grid->acc1) b += cap * G.N * grid->fsz;
-    if (grid->acc2) b += cap * G.N * grid->fsz;
-    b += cap * NSLOT * (uint64_t)grid->pstride * 8;
-    for (auto p : grid->opt)
-        if (p) b += (uint64_t)G.N * grid->fsz;
+    BytesModel m;
+    m.stage = grid->stage_in != nullptr || grid->stage_out != nullptr;
+    m.opt = grid->opt[0] != nullptr;
+    m.forces = grid->d_forces != nullptr;
+    uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
+                             grid->func.terms, grid->func.nl_mode,
+                             (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
+                             (uint64_t)grid->cap, m);
+    if (m.stage && !(grid->stage_in && grid->stage_out)) b -= (uint64_t)grid->geom.N * grid->fsz;
     return b;
+}
+
+ofdft_status ofdft_validate(const ofdft_cell_desc *cell, const ofdft_functional_desc *func)
+{
+    return validate(cell, func);
+}
+
+ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell, const ofdft_functional_desc *func,
+                                   int32_t kind, uint64_t *bytes)
+{
+    if (!bytes) return fail(OFDFT_EINVAL, "null output pointer");
+    *bytes = 0;
+    ST_TRY(validate(cell, func));
+    if (kind < OFDFT_REQ_EP || kind > OFDFT_REQ_OPTIMIZE) return fail(OFDFT_EINVAL, "bad request kind");
+    const Geom G = make_geom(cell->n);
+    BytesModel m;
+    m.stage = true;
+    m.opt = kind == OFDFT_REQ_OPTIMIZE;
+    m.forces = kind == OFDFT_REQ_FORCES;
+    *bytes = bytes_model(G, func->precision == OFDFT_FP64 ? 8 : 4, cell->natoms, cell->nspecies,
+                         func->terms, func->nl_mode, (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0,
+                         1, m);
+    return OFDFT_OK;
 }
 
 ofdft_status ofdft_set_density(ofdft_grid *grid, const double *rho_host)
@@ -1379,8 +1491,8 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     ofdft_status st = g->fp64 ? fft_impl<double>(g, 1, g->rho, g->spec, true, s)
                               : fft_impl<float>(g, 1, g->rho, g->spec, true, s);
     ST_TRY(st);
-    double *d_f = nullptr;
-    HIP_TRY(hipMalloc((void **)&d_f, 3 * (size_t)na * sizeof(double)));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_forces), 3 * (size_t)na * sizeof(double)));
+    double *d_f = g->d_forces;
     hipError_t e = g->fp64 ? launch_forces<double>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
                                                    g->ph2, g->d_Z, g->d_rc, g->spec, d_f, s)
                            : launch_forces<float>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
@@ -1388,7 +1500,6 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     std::vector<double> fs(3 * (size_t)na);
     if (e == hipSuccess) e = hipMemcpyAsync(fs.data(), d_f, fs.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d_f);
     HIP_TRY(e);
     std::vector<double> fe;
     (void)ewald_energy_host(g, &fe);

@@ -19,6 +19,7 @@ TERM_TF, TERM_VW, TERM_HARTREE, TERM_EXT, TERM_WT, TERM_SPLINE = 1, 2, 4, 8, 16,
 KNOTS_LOG, KNOTS_LIN = 0, 1
 NL_S3S4, NL_EXACT = 0, 1
 FP64, MIXED = 0, 1
+REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
               "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
 
@@ -59,6 +60,25 @@ class OptResult(ctypes.Structure):
                 ("final_resid", ctypes.c_double)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("cell_id", ctypes.c_uint64), ("kind", ctypes.c_int32),
+                ("cell", ctypes.POINTER(CellDesc)), ("func", ctypes.POINTER(FunctionalDesc)),
+                ("opt", ctypes.POINTER(OptParams)), ("rho_or_null", ctypes.POINTER(ctypes.c_double))]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
+                ("queued", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("resident_cells", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("resident_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_queue_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -83,6 +103,19 @@ _SIGS = {
     "ofdft_fft_c2r_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "ofdft_forces": (ctypes.c_int, [_P, _DP]),
     "ofdft_optimize": (ctypes.c_int, [_P, ctypes.POINTER(OptParams), ctypes.POINTER(OptResult)]),
+    "ofdft_validate": (ctypes.c_int, [ctypes.POINTER(CellDesc), ctypes.POINTER(FunctionalDesc)]),
+    "ofdft_footprint_bytes": (ctypes.c_int, [ctypes.POINTER(CellDesc),
+                                             ctypes.POINTER(FunctionalDesc), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
+    "ofdft_server_create": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, _PP]),
+    "ofdft_serve_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "ofdft_serve_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(OptResult), _DP,
+                                        _DP]),
+    "ofdft_serve_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32]),
+    "ofdft_serve_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "ofdft_serve_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServeStats)]),
+    "ofdft_server_destroy": (None, [_P]),
     "ofdft_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_profile_read": (ctypes.c_int, [_P, ctypes.c_int32, _DP,
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -255,6 +288,71 @@ def ofdft_optimize(grid, tol=1e-7, max_iter=1000, method=0, allow_noconv=False):
     if not (st == OK or (allow_noconv and st == ENOCONV)):
         check(st)
     return r, st
+
+
+def ofdft_validate(cell_desc, func_desc):
+    """Host-only: returns the status (OK or EINVAL) without raising."""
+    return load().ofdft_validate(ctypes.byref(cell_desc), ctypes.byref(func_desc))
+
+
+def ofdft_footprint_bytes(cell_desc, func_desc, kind):
+    b = ctypes.c_uint64()
+    check(load().ofdft_footprint_bytes(ctypes.byref(cell_desc), ctypes.byref(func_desc),
+                                       int(kind), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ofdft_server_create(ctx, hbm_budget_bytes=0, max_inflight=4):
+    h = ctypes.c_void_p()
+    check(load().ofdft_server_create(ctx, int(hbm_budget_bytes), int(max_inflight),
+                                     ctypes.byref(h)))
+    return h
+
+
+def ofdft_serve_submit(server, cell_id, kind, cell_desc, func_desc, opt=None, rho=None):
+    """Returns the ticket; raises on a refused request."""
+    q = Request()
+    q.cell_id = int(cell_id)
+    q.kind = int(kind)
+    q.cell = ctypes.pointer(cell_desc)
+    q.func = ctypes.pointer(func_desc)
+    q.opt = ctypes.pointer(opt) if opt is not None else None
+    keep = None
+    if rho is not None:
+        keep = np.ascontiguousarray(rho, dtype=np.float64)
+        q.rho_or_null = _dptr(keep)
+    t = ctypes.c_uint64()
+    check(load().ofdft_serve_submit(server, ctypes.byref(q), ctypes.byref(t)))
+    return int(t.value)
+
+
+def ofdft_serve_poll(server, ticket, v_shape=None, natoms=None):
+    """Returns (status, OptResult, v or None, f or None); status PENDING while running."""
+    r = OptResult()
+    v = np.full(v_shape, np.nan) if v_shape is not None else None
+    f = np.full((natoms, 3), np.nan) if natoms else None
+    st = load().ofdft_serve_poll(server, int(ticket), ctypes.byref(r),
+                                 _dptr(v) if v is not None else None,
+                                 _dptr(f) if f is not None else None)
+    return st, r, v, f
+
+
+def ofdft_serve_wait(server, ticket, timeout_ms=-1):
+    return load().ofdft_serve_wait(server, int(ticket), int(timeout_ms))
+
+
+def ofdft_serve_cancel(server, ticket):
+    return load().ofdft_serve_cancel(server, int(ticket))
+
+
+def ofdft_serve_stats_get(server):
+    st = ServeStats()
+    check(load().ofdft_serve_stats_get(server, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def ofdft_server_destroy(server):
+    load().ofdft_server_destroy(server)
 
 
 def ofdft_profile_enable(grid, on=True):

@@ -156,7 +156,7 @@ def gaussian_superposition(cell, sigma=1.5, floor=0.0):
         sf += z * np.exp(-1j * (G @ p))
     spec = sf * np.exp(-G2 * sigma * sigma / 2.0) / V
     N = n[0] * n[1] * n[2]
-    rho = np.fft.irfftn(spec * N, s=n)
+    rho = np.fft.irfftn(spec * N, s=n, axes=(0, 1, 2))
     rho = np.maximum(rho, 0.0) + floor
     return rho
 
@@ -200,3 +200,40 @@ def config_c3(n=(256, 256, 384)):
     256x256x384 grid; Gaussian superposition plus a 1e-12 floor."""
     cell = mg_hcp_slab((6, 4, 9), n, vacuum=15.0)
     return cell, gaussian_density(cell, sigma=1.5, floor=1e-12)
+
+
+def config_c4(nreq=512, seed=4242, ntraj=64, min_atoms=13, max_atoms=561, grids=BOX_GRIDS,
+              mix=(0.4, 0.3, 0.3), md_step=0.1, h=0.35):
+    """Serving request stream: `ntraj` trajectories, each an Al or Mg cluster
+    (species with p = 1/2, size ~ U{min_atoms..max_atoms}) in a cubic box with
+    8 Bohr of vacuum per side and the smallest grid from `grids` with spacing
+    <= h (the largest one if none is fine enough).  `nreq` requests go to seeded trajectories; each request
+    is one MD frame of its trajectory (positions R_t + N(0, md_step) per
+    step) and is an energy+potential (0), forces (1) or warm-started
+    optimisation (2) request with probabilities `mix`.  The first request of
+    a trajectory carries the Gaussian-superposition starting density.
+
+    Returns a list of dicts {cell_id, kind, cell, rho (or None), frame}."""
+    rng = np.random.default_rng(seed)
+    trajs = []
+    for t in range(ntraj):
+        sp = "Al" if rng.uniform() < 0.5 else "Mg"
+        na = int(rng.integers(min_atoms, max_atoms + 1))
+        base = cluster(na, sp, seed=seed + 1 + t)
+        L = base["lattice"][0, 0]
+        g = box_grid(L, h=h, choices=tuple(grids))
+        trajs.append(cluster(na, sp, seed=seed + 1 + t, grid=g))
+    frames = [0] * ntraj
+    pos = [c["pos"].copy() for c in trajs]
+    out = []
+    for _ in range(nreq):
+        t = int(rng.integers(0, ntraj))
+        kind = int(rng.choice(3, p=np.asarray(mix, dtype=float)))
+        if frames[t] > 0:
+            pos[t] = pos[t] + rng.normal(0.0, md_step, size=pos[t].shape)
+        cell = dict(trajs[t])
+        cell["pos"] = pos[t].copy()
+        rho = gaussian_density(cell, sigma=1.5, floor=1e-8) if frames[t] == 0 else None
+        out.append({"cell_id": t, "kind": kind, "cell": cell, "rho": rho, "frame": frames[t]})
+        frames[t] += 1
+    return out
