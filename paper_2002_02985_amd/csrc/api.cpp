@@ -120,6 +120,9 @@ struct ofdft_grid {
     void *opt[9] = {nullptr};
     size_t bytes = 0;
     double *d_forces = nullptr;   // natoms x 3
+    double *d_frac = nullptr;     // natoms x 3 fractional coordinates, species-sorted
+    double *d_ew_pos = nullptr, *d_ew_q = nullptr, *d_ew_e = nullptr, *d_ew_f = nullptr,
+           *d_ew_sf = nullptr;    // Ewald buffers
     Timer timer;
     int tune_col_tile_major = 0;   // block order of the column passes
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
@@ -183,61 +186,66 @@ static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt)
     return OFDFT_OK;
 }
 
-static int freq_host(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
 
 // ---------------------------------------------------------------- Ewald (host, FP64)
 // E_ion = 1/2 sum' Z_a Z_b erfc(a r)/r + (2 pi / V) sum_{G!=0} e^{-G^2/4a^2}/G^2 |S(G)|^2
 //         - a/sqrt(pi) sum Z^2 - pi Q^2 / (2 V a^2),  S(G) = sum Z_a e^{iG.R_a}
 // and its forces; point charges in a neutralising background.
-struct EwaldSetup {
-    double a, rcut, gcut;
-    std::vector<double> L;   // lattice translations (x,y,z) within reach
-    std::vector<double> G;   // reciprocal vectors (x,y,z,|G|^2), G != 0, |G| <= gcut
-};
-
-static EwaldSetup ewald_setup(const ofdft_grid *g)
+// Ewald parameters of a cell: splitting a = 2 sqrt(pi) (n/V^2)^(1/6), real-
+// and reciprocal-space cut-offs 6.6/a and 13.2 a, and the integer ranges of
+// lattice images and reciprocal vectors that reach them.
+static EwaldGeom ewald_geom(const double lat[3][3], const double b[3][3], double V, int na)
 {
-    EwaldSetup e;
-    const int na = g->natoms;
-    e.a = std::sqrt(PI) * std::pow((double)std::max(na, 1) / (g->V * g->V), 1.0 / 6.0) * 2.0;
-    e.rcut = 6.6 / e.a;
-    e.gcut = 2.0 * e.a * 6.6;
-    // images: planes of lattice points perpendicular to b_d are 2 pi/|b_d| apart
-    int nmax[3], gmax[3];
+    EwaldGeom e;
+    std::memset(&e, 0, sizeof(e));
+    e.a = std::sqrt(PI) * std::pow((double)std::max(na, 1) / (V * V), 1.0 / 6.0) * 2.0;
+    const double rcut = 6.6 / e.a, gcut = 2.0 * e.a * 6.6;
+    e.rcut2 = rcut * rcut;
+    e.gcut2 = gcut * gcut;
     for (int d = 0; d < 3; ++d) {
-        const double bn = std::sqrt(g->geom.b[d][0] * g->geom.b[d][0] + g->geom.b[d][1] * g->geom.b[d][1] +
-                                    g->geom.b[d][2] * g->geom.b[d][2]);
-        const double an = std::sqrt(g->lattice[d][0] * g->lattice[d][0] + g->lattice[d][1] * g->lattice[d][1] +
-                                    g->lattice[d][2] * g->lattice[d][2]);
-        nmax[d] = (int)std::ceil(e.rcut * bn / (2 * PI)) + 1;
-        gmax[d] = (int)std::ceil(e.gcut * an / (2 * PI)) + 1;
+        // planes of lattice points perpendicular to b_d are 2 pi/|b_d| apart
+        const double bn = std::sqrt(b[d][0] * b[d][0] + b[d][1] * b[d][1] + b[d][2] * b[d][2]);
+        const double an = std::sqrt(lat[d][0] * lat[d][0] + lat[d][1] * lat[d][1] + lat[d][2] * lat[d][2]);
+        e.nmax[d] = (int)std::ceil(rcut * bn / (2 * PI)) + 1;
+        e.gmax[d] = (int)std::ceil(gcut * an / (2 * PI)) + 1;
+        for (int c = 0; c < 3; ++c) {
+            e.lat[d][c] = lat[d][c];
+            e.b[d][c] = b[d][c];
+        }
     }
-    for (int i = -nmax[0]; i <= nmax[0]; ++i)
-        for (int j = -nmax[1]; j <= nmax[1]; ++j)
-            for (int k = -nmax[2]; k <= nmax[2]; ++k)
-                for (int c = 0; c < 3; ++c)
-                    e.L.push_back(i * g->lattice[0][c] + j * g->lattice[1][c] + k * g->lattice[2][c]);
-    for (int i = -gmax[0]; i <= gmax[0]; ++i)
-        for (int j = -gmax[1]; j <= gmax[1]; ++j)
-            for (int k = -gmax[2]; k <= gmax[2]; ++k) {
-                if (!i && !j && !k) continue;
-                double v[3];
-                for (int c = 0; c < 3; ++c)
-                    v[c] = i * g->geom.b[0][c] + j * g->geom.b[1][c] + k * g->geom.b[2][c];
-                const double g2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-                if (g2 > e.gcut * e.gcut) continue;
-                e.G.insert(e.G.end(), {v[0], v[1], v[2], g2});
-            }
+    e.volume = V;
     return e;
 }
 
-static double ewald_energy_host(const ofdft_grid *g, std::vector<double> *forces)
+// device bytes of the ionic buffers: sorted fractional coordinates, Ewald
+// positions, charges, per-atom energies and forces, and S(G) on the box
+static uint64_t ion_bytes(const double lat[3][3], int na)
+{
+    if (na <= 0) return 0;
+    const double(*A)[3] = lat;
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    double b[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            b[i][j] = 2.0 * PI * (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;
+        }
+    const EwaldGeom e = ewald_geom(lat, b, std::fabs(det), na);
+    return (uint64_t)na * (3 + 3 + 1 + 1 + 3) * 8 + (uint64_t)ewald_gbox_count(e) * 16;
+}
+
+// E_ion on the device; forces (natoms x 3, original atom order) if asked.
+static ofdft_status ewald_device(ofdft_grid *g, double *e_ion, std::vector<double> *forces)
 {
     const int na = g->natoms;
+    *e_ion = 0.0;
     if (forces) forces->assign(3 * (size_t)na, 0.0);
-    if (na == 0) return 0.0;
-    const EwaldSetup e = ewald_setup(g);
-    const double a = e.a;
+    if (na == 0) return OFDFT_OK;
+    hipStream_t s = g->ctx->stream;
+    const EwaldGeom e = ewald_geom(g->lattice, g->geom.b, g->V, na);
+    const long long nbox = ewald_gbox_count(e);
     std::vector<double> q(na);
     double Q = 0, Q2 = 0;
     for (int i = 0; i < na; ++i) {
@@ -245,57 +253,24 @@ static double ewald_energy_host(const ofdft_grid *g, std::vector<double> *forces
         Q += q[i];
         Q2 += q[i] * q[i];
     }
-    const size_t nL = e.L.size() / 3;
-    double ereal = 0.0;
-    for (int i = 0; i < na; ++i) {
-        for (int j = 0; j < na; ++j) {
-            const double dx0 = g->pos[3 * i] - g->pos[3 * j];
-            const double dy0 = g->pos[3 * i + 1] - g->pos[3 * j + 1];
-            const double dz0 = g->pos[3 * i + 2] - g->pos[3 * j + 2];
-            for (size_t l = 0; l < nL; ++l) {
-                const double dx = dx0 - e.L[3 * l], dy = dy0 - e.L[3 * l + 1], dz = dz0 - e.L[3 * l + 2];
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < 1e-20 || r2 > e.rcut * e.rcut) continue;
-                const double r = std::sqrt(r2);
-                const double ec = std::erfc(a * r);
-                ereal += 0.5 * q[i] * q[j] * ec / r;
-                if (forces) {
-                    const double mag = q[i] * q[j] *
-                                       (ec / r2 + 2.0 * a / std::sqrt(PI) * std::exp(-a * a * r2) / r) / r;
-                    (*forces)[3 * i] += mag * dx;
-                    (*forces)[3 * i + 1] += mag * dy;
-                    (*forces)[3 * i + 2] += mag * dz;
-                }
-            }
-        }
-    }
-    double erec = 0.0;
-    const size_t nG = e.G.size() / 4;
-    std::vector<double> cr(na), ci(na);
-    for (size_t k = 0; k < nG; ++k) {
-        const double *G = &e.G[4 * k];
-        double sr = 0, si = 0;
-        for (int i = 0; i < na; ++i) {
-            const double ph = G[0] * g->pos[3 * i] + G[1] * g->pos[3 * i + 1] + G[2] * g->pos[3 * i + 2];
-            cr[i] = std::cos(ph);
-            ci[i] = std::sin(ph);
-            sr += q[i] * cr[i];
-            si += q[i] * ci[i];
-        }
-        const double w = std::exp(-G[3] / (4 * a * a)) / G[3];
-        erec += 2.0 * PI / g->V * w * (sr * sr + si * si);
-        if (forces) {
-            // F_i = (4 pi / V) w q_i G Im[e^{iG.R_i} conj S]
-            for (int i = 0; i < na; ++i) {
-                const double im = ci[i] * sr - cr[i] * si;
-                const double f = 4.0 * PI / g->V * w * q[i] * im;
-                (*forces)[3 * i] += f * G[0];
-                (*forces)[3 * i + 1] += f * G[1];
-                (*forces)[3 * i + 2] += f * G[2];
-            }
-        }
-    }
-    return ereal + erec - a / std::sqrt(PI) * Q2 - PI * Q * Q / (2 * g->V * a * a);
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_pos), 3 * (size_t)na * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_q), (size_t)na * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_e), (size_t)na * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_f), 3 * (size_t)na * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), (size_t)nbox * 16));
+    HIP_TRY(hipMemcpyAsync(g->d_ew_pos, g->pos.data(), 3 * (size_t)na * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->d_ew_q, q.data(), (size_t)na * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_ewald(e, na, g->d_ew_pos, g->d_ew_q, g->d_ew_sf, g->d_ew_e,
+                         forces ? g->d_ew_f : nullptr, s));
+    std::vector<double> ea(na);
+    HIP_TRY(hipMemcpyAsync(ea.data(), g->d_ew_e, (size_t)na * 8, hipMemcpyDeviceToHost, s));
+    if (forces)
+        HIP_TRY(hipMemcpyAsync(forces->data(), g->d_ew_f, 3 * (size_t)na * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (int i = 0; i < na; ++i) sum += ea[i];
+    *e_ion = sum - e.a / std::sqrt(PI) * Q2 - PI * Q * Q / (2 * g->V * e.a * e.a);
+    return OFDFT_OK;
 }
 
 // ---------------------------------------------------------------- timing
@@ -369,7 +344,7 @@ struct BytesModel {
     bool stage = false, opt = false, forces = false;
 };
 static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, uint32_t terms,
-                            int nl_mode, int nk, uint64_t cap, BytesModel m)
+                            int nl_mode, int nk, uint64_t cap, uint64_t ions, BytesModel m)
 {
     const uint64_t N = (uint64_t)G.N, Nh = (uint64_t)G.Nh, cb = 2 * fsz;
     uint64_t b = 0;
@@ -377,6 +352,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     b += Nh * cb;                                                       // v_ext
     b += Nh * 3 * fsz;                                                  // G tables
     b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;                 // phase tables
+    b += ions;                                                          // coordinates, Ewald
     b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
     b += (uint64_t)NSLOT * 4 + (uint64_t)nk * 8;                        // counts, knots
     b += N * fsz;                                                       // resident rho
@@ -850,6 +826,12 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
     dfree(reinterpret_cast<void *&>(g->d_forces));
+    dfree(reinterpret_cast<void *&>(g->d_frac));
+    dfree(reinterpret_cast<void *&>(g->d_ew_pos));
+    dfree(reinterpret_cast<void *&>(g->d_ew_q));
+    dfree(reinterpret_cast<void *&>(g->d_ew_e));
+    dfree(reinterpret_cast<void *&>(g->d_ew_f));
+    dfree(reinterpret_cast<void *&>(g->d_ew_sf));
     dfree(g->rho);
     for (auto &p : g->opt) dfree(p);
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -868,44 +850,32 @@ static ofdft_status setup_ions(ofdft_grid *g)
     const Geom &G = g->geom;
     const int na = g->natoms;
     const int ns = (int)g->Z.size();
+    hipStream_t s = g->ctx->stream;
     if (na > 0) {
-        // fractional coordinates s = R . inv(A) ; inv(A) = cof^T / det
-        std::vector<double> fr(3 * (size_t)na);
-        for (int a = 0; a < na; ++a)
-            for (int j = 0; j < 3; ++j) {
-                double s = 0;
-                for (int i = 0; i < 3; ++i) s += g->pos[3 * a + i] * g->frac[j][i];
-                fr[3 * a + j] = s - std::floor(s);
-            }
-        // atoms sorted by species
+        // atoms sorted by species: the v_ext kernel sums each species' atoms
+        // together, and the phase tables and forces use this order
         std::vector<int> order(na);
         for (int a = 0; a < na; ++a) order[a] = a;
         std::stable_sort(order.begin(), order.end(),
                          [&](int x, int y) { return g->species[x] < g->species[y]; });
         std::vector<int> off(ns + 1, 0);
         for (int a = 0; a < na; ++a) off[g->species[a] + 1]++;
-        for (int s = 0; s < ns; ++s) off[s + 1] += off[s];
+        for (int k = 0; k < ns; ++k) off[k + 1] += off[k];
+        // fractional coordinates s = inv(A)^T R, wrapped into [0, 1)
+        std::vector<double> fr(3 * (size_t)na);
+        for (int a = 0; a < na; ++a)
+            for (int j = 0; j < 3; ++j) {
+                double x = 0;
+                for (int i = 0; i < 3; ++i) x += g->pos[3 * order[a] + i] * g->frac[j][i];
+                fr[3 * a + j] = x - std::floor(x);
+            }
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_frac), fr.size() * sizeof(double)));
+        ST_TRY(h2d(g, g->d_frac, fr.data(), fr.size() * sizeof(double)));
         const int nax[3] = {G.n0, G.n1, G.n2h};
         double **tabs[3] = {&g->ph0, &g->ph1, &g->ph2};
-        for (int d = 0; d < 3; ++d) {
-            // separate tables in sorted order (for v_ext) are the same tables; forces index
-            // atoms in their original order, so the tables are stored in original order and
-            // the species-sorted v_ext kernel uses the permutation below
-            std::vector<double> t(2 * (size_t)na * nax[d]);
-            for (int a = 0; a < na; ++a) {
-                const int src = order[a];
-                for (int i = 0; i < nax[d]; ++i) {
-                    const int m = (d == 2) ? ((i == G.m) ? -G.m : i) : freq_host(i, nax[d]);
-                    double x = (double)m * fr[3 * src + d];
-                    x -= std::nearbyint(x);
-                    const double ang = -2.0 * PI * x;
-                    t[2 * ((size_t)a * nax[d] + i)] = std::cos(ang);
-                    t[2 * ((size_t)a * nax[d] + i) + 1] = std::sin(ang);
-                }
-            }
-            ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]), t.size() * sizeof(double)));
-            ST_TRY(h2d(g, *tabs[d], t.data(), t.size() * sizeof(double)));
-        }
+        for (int d = 0; d < 3; ++d)
+            ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]), 2 * (size_t)na * nax[d] * sizeof(double)));
+        HIP_TRY(launch_phases(G, na, g->d_frac, g->ph0, g->ph1, g->ph2, s));
         std::vector<int> sorted_species(na);
         for (int a = 0; a < na; ++a) sorted_species[a] = g->species[order[a]];
         g->species_order = order;
@@ -919,7 +889,6 @@ static ofdft_status setup_ions(ofdft_grid *g)
         ST_TRY(h2d(g, g->d_rc, g->rc.data(), ns * sizeof(double)));
     }
     ST_TRY(dmalloc(g, &g->vext, (size_t)G.Nh * 2 * g->fsz));
-    hipStream_t s = g->ctx->stream;
     if (na > 0) {
         hipError_t e = g->fp64 ? launch_vext<double>(G, na, g->d_spec_off, ns, g->ph0, g->ph1, g->ph2,
                                                      g->d_Z, g->d_rc, g->V, g->vext, s)
@@ -929,8 +898,10 @@ static ofdft_status setup_ions(ofdft_grid *g)
     } else {
         HIP_TRY(hipMemsetAsync(g->vext, 0, (size_t)G.Nh * 2 * g->fsz, s));
     }
+    double e_ion = 0.0;
+    ST_TRY(ewald_device(g, &e_ion, nullptr));
+    g->e_ion = (g->func.terms & OFDFT_TERM_EXT) ? e_ion : 0.0;
     HIP_TRY(hipStreamSynchronize(s));
-    g->e_ion = (g->func.terms & OFDFT_TERM_EXT) ? ewald_energy_host(g, nullptr) : 0.0;
     return OFDFT_OK;
 }
 
@@ -1110,14 +1081,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     std::memset(res, 0, sizeof(*res));
 
     // phi = sqrt(rho_resident), normalised to N_e
-    {
-        // square root through the plain kernels: phi = sqrt(max(rho, 0)) is computed by the
-        // forward pass when the input is rho, but the optimiser needs phi as a vector.
-        std::vector<double> h((size_t)G.N);
-        ST_TRY(download_field(g, h.data(), g->rho, (size_t)G.N, s));
-        for (auto &x : h) x = std::sqrt(std::max(x, 0.0));
-        ST_TRY(upload_field(g, v[V_PHI], h.data(), (size_t)G.N, s));
-    }
+    TIMED(PS_OTHER, launch_pointwise<T>(G.N, PW_SQRT, v[V_PHI], g->rho, s));
     double pp;
     ST_TRY(dots<T>(o, 1, v[V_PHI], v[V_PHI], nullptr, nullptr, nullptr, nullptr, &pp));
     if (!(pp > 0)) return fail(OFDFT_EINVAL, "resident density is zero");
@@ -1247,12 +1211,8 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     }
     if (!converged && E.resid_norm < tol) converged = true;
     // leave the optimised density resident: rho = phi^2
-    {
-        std::vector<double> h((size_t)G.N);
-        ST_TRY(download_field(g, h.data(), v[V_PHI], (size_t)G.N, s));
-        for (auto &x : h) x = x * x;
-        ST_TRY(upload_field(g, g->rho, h.data(), (size_t)G.N, s));
-    }
+    TIMED(PS_OTHER, launch_pointwise<T>(G.N, PW_SQUARE, g->rho, v[V_PHI], s));
+    HIP_TRY(hipStreamSynchronize(s));
     res->e = E;
     res->iters = iter;
     res->evals = evals;
@@ -1370,7 +1330,7 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
                              grid->func.terms, grid->func.nl_mode,
                              (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
-                             (uint64_t)grid->cap, m);
+                             (uint64_t)grid->cap, ion_bytes(grid->lattice, grid->natoms), m);
     if (m.stage && !(grid->stage_in && grid->stage_out)) b -= (uint64_t)grid->geom.N * grid->fsz;
     return b;
 }
@@ -1394,7 +1354,7 @@ ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell, const ofdft_func
     m.forces = kind == OFDFT_REQ_FORCES;
     *bytes = bytes_model(G, func->precision == OFDFT_FP64 ? 8 : 4, cell->natoms, cell->nspecies,
                          func->terms, func->nl_mode, (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0,
-                         1, m);
+                         1, ion_bytes(cell->lattice, cell->natoms), m);
     return OFDFT_OK;
 }
 
@@ -1502,7 +1462,8 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     HIP_TRY(e);
     std::vector<double> fe;
-    (void)ewald_energy_host(g, &fe);
+    double e_ion = 0.0;
+    ST_TRY(ewald_device(g, &e_ion, &fe));
     for (int a = 0; a < na; ++a) {
         const int orig = g->species_order[a];
         for (int k = 0; k < 3; ++k) f_out_host[3 * orig + k] = fs[3 * a + k] + fe[3 * orig + k];

@@ -278,4 +278,24 @@ template hipError_t launch_lincomb<float>(long long, void *, double, const void 
 template hipError_t launch_lincomb<double>(long long, void *, double, const void *, double,
                                            const void *, hipStream_t);
 
+template <typename T>
+__global__ __launch_bounds__(NT) void k_pointwise(long long n, int op, T *z, const T *x)
+{
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= n) return;
+    const T v = x[i];
+    z[i] = op == PW_SQRT ? (v > T(0) ? sqrt(v) : T(0)) : v * v;
+}
+
+template <typename T>
+hipError_t launch_pointwise(long long n, int op, void *z, const void *x, hipStream_t s)
+{
+    const long long nb = (n + NT - 1) / NT;
+    hipLaunchKernelGGL((k_pointwise<T>), dim3((unsigned)nb), dim3(NT), 0, s, n, op, (T *)z,
+                       (const T *)x);
+    return hipGetLastError();
+}
+template hipError_t launch_pointwise<float>(long long, int, void *, const void *, hipStream_t);
+template hipError_t launch_pointwise<double>(long long, int, void *, const void *, hipStream_t);
+
 }  // namespace ofdft

@@ -172,6 +172,37 @@ hipError_t launch_forces(const Geom &g, int natoms, const int *atom_species,
                          const double *Z, const double *rc, const void *rho_g, double *f_out,
                          hipStream_t s);
 
+// per-axis phase tables exp(-i 2 pi m_d s_d) of every atom (sorted order),
+// from fractional coordinates frac[3 a + d] in [0, 1): ph_d[a][i], i < n_d
+// (n_2h on axis 2, whose last index is the negative Nyquist frequency)
+hipError_t launch_phases(const Geom &g, int natoms, const double *frac, double *ph0, double *ph1,
+                         double *ph2, hipStream_t s);
+
+// Ewald sum of point ions q_a in a neutralising background.  Real-space
+// images L = sum n_d a_d with |n_d| <= nmax[d] and reciprocal vectors
+// G = sum m_d b_d with |m_d| <= gmax[d], G != 0, G^2 <= gcut2 are enumerated
+// in the kernels; sf holds one complex S(G) per point of that integer box.
+struct EwaldGeom {
+    double a;             // splitting parameter
+    double rcut2, gcut2;
+    int nmax[3], gmax[3];
+    double lat[3][3];     // rows a_d
+    double b[3][3];       // rows b_d
+    double volume;
+};
+__host__ __device__ inline long long ewald_image_count(const EwaldGeom &e)
+{
+    return (long long)(2 * e.nmax[0] + 1) * (2 * e.nmax[1] + 1) * (2 * e.nmax[2] + 1);
+}
+__host__ __device__ inline long long ewald_gbox_count(const EwaldGeom &e)
+{
+    return (long long)(2 * e.gmax[0] + 1) * (2 * e.gmax[1] + 1) * (2 * e.gmax[2] + 1);
+}
+// e_atom[a]: atom a's share of the real- and reciprocal-space energy; f (if
+// not null): natoms x 3 ion-ion forces.  sf: 2 x ewald_gbox_count doubles.
+hipError_t launch_ewald(const EwaldGeom &e, int natoms, const double *pos, const double *q,
+                        double *sf, double *e_atom, double *f, hipStream_t s);
+
 // vector kernels (optimizer): up to 4 dot products into part slots
 template <typename T>
 hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,
@@ -182,5 +213,9 @@ template <typename T>
 hipError_t launch_lincomb(long long n, void *z, double a, const void *x, double b, const void *y,
                           hipStream_t s);
 int dots_blocks(long long n);
+// z = sqrt(max(x, 0)) (op 0) or z = x^2 (op 1)
+enum { PW_SQRT = 0, PW_SQUARE = 1 };
+template <typename T>
+hipError_t launch_pointwise(long long n, int op, void *z, const void *x, hipStream_t s);
 
 }  // namespace ofdft
