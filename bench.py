@@ -131,7 +131,15 @@ def parse():
     ap.add_argument("--serve-qps", default="0.7",
                     help="comma-separated fractions of the closed-loop rate for the "
                          "Poisson phases")
+    ap.add_argument("--c3", action="store_true",
+                    help="spline workload instead: Mg hcp slab (864 atoms) on 256x256x384 "
+                         "with N_k = 32 knots: evaluation throughput of both potential "
+                         "modes in both precisions, then the density optimisation")
+    ap.add_argument("--c3-steps", type=int, default=10)
+    ap.add_argument("--c3-max-iter", type=int, default=1500)
+    ap.add_argument("--c3-no-opt", action="store_true")
     ap.add_argument("--serve-max-iter", type=int, default=50)
+    ap.add_argument("--serve-tol", type=float, default=1e-5)
     return ap.parse_args()
 
 
@@ -250,7 +258,7 @@ def serve_run(ofdft, reqs, slots, arrivals=None):
             if dt > 0:
                 time.sleep(dt)
         cd, k = ofdft.make_cell_desc(q["cell"])
-        op = ofdft.OptParams(tol=1e-5, max_iter=q["max_iter"], method=0, warm=1)
+        op = ofdft.OptParams(tol=q["tol"], max_iter=q["max_iter"], method=ofdft.OPT_PCG, warm=1)
         keep.append((cd, k, op))
         tickets[i] = ofdft.ofdft_serve_submit(srv, q["cell_id"], q["kind"], cd, fd,
                                               op if q["kind"] == ofdft.REQ_OPTIMIZE else None,
@@ -276,6 +284,7 @@ def serve_main(args):
     reqs = W.config_c4(args.serve_requests, seed=4242)
     for q in reqs:
         q["max_iter"] = args.serve_max_iter
+        q["tol"] = args.serve_tol
     npts = [int(np.prod(q["cell"]["n"])) for q in reqs]
     grids = sorted({q["cell"]["n"][0] for q in reqs})
     kinds = [sum(1 for q in reqs if q["kind"] == k) for k in range(3)]
@@ -327,9 +336,10 @@ def serve_main(args):
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "%d requests on 64 Al/Mg cluster trajectories (13-561 atoms, "
                                "8 Bohr vacuum, grids %s), 40%% energy+potential, 30%% forces, "
-                               "30%% warm-started optimisations (tol 1e-5, max %d iterations), "
+                               "30%% warm-started optimisations (preconditioned CG, tol %g, max %d iterations), "
                                "MD frames displaced N(0, 0.1 Bohr), TF+vW+Hartree+local "
-                               "pseudopotential" % (len(reqs), grids, args.serve_max_iter),
+                               "pseudopotential" % (len(reqs), grids, args.serve_tol,
+                                                    args.serve_max_iter),
                    "kinds": kinds, "slots": args.serve_slots},
         "phases": phases,
         "overlap_speedup": round(best["req_per_s"] / phases["closed_1"]["req_per_s"], 3)
@@ -338,8 +348,111 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def c3_main(args):
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
+             ofdft.TERM_SPLINE)
+    spl = dict(nk=32, kf_min=0.1, kf_max=3.0)
+    log("generating the Mg slab and its starting density")
+    cell, rho = W.config_c3()
+    natoms = len(cell["species"])
+    N = int(np.prod(cell["n"]))
+    sh = torch.cuda.current_stream().cuda_stream
+    evals = {}
+    for prec, pname in ((ofdft.MIXED, "mixed"), (ofdft.FP64, "fp64")):
+        dt = torch.float32 if prec == ofdft.MIXED else torch.float64
+        x = torch.from_numpy(rho).to(dtype=dt, device="cuda:0")
+        v = torch.empty_like(x)
+        for nl, mname in ((ofdft.NL_S3S4, "s3s4"), (ofdft.NL_EXACT, "exact")):
+            log("eval %s %s" % (pname, mname))
+            with ofdft.Grid(cell, terms, precision=prec, nl_mode=nl, **spl) as g:
+                for _ in range(2):
+                    e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), v.data_ptr(), sh)
+                ofdft.ofdft_profile_enable(g.handle, True)
+                torch.cuda.synchronize()
+                lat = []
+                for _ in range(args.c3_steps):
+                    t0 = time.perf_counter()
+                    e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), v.data_ptr(), sh)
+                    lat.append(time.perf_counter() - t0)
+                passes = {}
+                for p, nm in enumerate(ofdft.PASS_NAMES):
+                    ms, n = ofdft.ofdft_profile_read(g.handle, p)
+                    if n:
+                        passes[nm] = round(ms / args.c3_steps, 3)
+                ms = float(np.median(lat)) * 1e3
+                evals["%s_%s" % (pname, mname)] = {
+                    "ms_per_eval": round(ms, 3), "Gpts_per_s": round(N / (ms * 1e-3) / 1e9, 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                    "e_total": e.e_total, "e_nl": e.e_nl,
+                    "device_bytes": ofdft.ofdft_grid_device_bytes(g.handle),
+                    "passes_ms": passes}
+        del x, v
+        torch.cuda.empty_cache()
+    for m in ("s3s4", "exact"):
+        evals["mixed_%s" % m]["dE_per_atom_vs_fp64"] = abs(
+            evals["mixed_%s" % m]["e_total"] - evals["fp64_%s" % m]["e_total"]) / natoms
+        evals["mixed_%s" % m]["speedup_vs_fp64"] = round(
+            evals["fp64_%s" % m]["ms_per_eval"] / evals["mixed_%s" % m]["ms_per_eval"], 3)
+    line = {"metric": "energy+potential evals/s (Gpts/s), spline nonlocal KEDF, N_k = 32",
+            "value": evals["mixed_s3s4"]["Gpts_per_s"], "unit": "Gpts/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "Mg hcp slab 6x4x9 orthorhombic cells (864 atoms) + 15 Bohr "
+                                   "vacuum, 256x256x384 grid, TF+vW+Hartree+local "
+                                   "pseudopotential+spline KEDF (32 log knots 0.1-3.0), one "
+                                   "density per evaluation", "grid": list(cell["n"]),
+                       "natoms": natoms},
+            "evals": evals}
+    if not args.c3_no_opt:
+        def run_opt(g, label, budget_s):
+            """Optimises in chunks of 50 iterations (each chunk restarts the
+            conjugate directions from the resident density) and logs progress."""
+            t0 = time.perf_counter()
+            iters = evals = 0
+            r, st = None, ofdft.ENOCONV
+            while iters < args.c3_max_iter and time.perf_counter() - t0 < budget_s:
+                r, st = g.optimize(tol=1e-6, max_iter=min(50, args.c3_max_iter - iters),
+                                   allow_noconv=True, method=ofdft.OPT_PCG)
+                iters += r.iters
+                evals += r.evals
+                log("%s: %d iterations, %d evaluations, resid %.3e, E %.10f, %.1f s" %
+                    (label, iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t0))
+                if st == ofdft.OK or r.iters == 0:
+                    break
+            return {"status": int(st), "iters": iters, "evals": evals,
+                    "final_resid": r.final_resid, "e_total": r.e.e_total,
+                    "wall_s": round(time.perf_counter() - t0, 2)}
+
+        opt = {}
+        log("optimise: mixed precision, EXACT potential, preconditioned CG, tol 1e-6")
+        with ofdft.Grid(cell, terms, precision=ofdft.MIXED, nl_mode=ofdft.NL_EXACT, **spl) as g:
+            g.set_density(rho)
+            opt["mixed"] = run_opt(g, "mixed", 240.0)
+            opt["mixed"]["device_bytes"] = ofdft.ofdft_grid_device_bytes(g.handle)
+            rho_m = g.get_density()
+        if opt["mixed"]["final_resid"] >= 1e-6:
+            log("FP32 residual floor reached: FP64 polish from the mixed result")
+            with ofdft.Grid(cell, terms, precision=ofdft.FP64, nl_mode=ofdft.NL_EXACT, **spl) as g:
+                g.set_density(rho_m)
+                opt["fp64_polish"] = run_opt(g, "fp64", 240.0)
+        line["optimize"] = opt
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.c3:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        c3_main(args)
+        return
     if args.serve:
         if args.gpus != 1:
             print("bench.py: this build runs on one GPU", file=sys.stderr)

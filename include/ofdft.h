@@ -201,10 +201,16 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host);
  * over t in FP64.  Starts from the resident density (warm start) and leaves
  * the optimised density resident.  Converged when sqrt(mean(R^2)) < tol;
  * OFDFT_ENOCONV (with the result filled in) when max_iter is reached. */
+enum {
+    OFDFT_OPT_CG = 0,   /* Polak-Ribiere+ on the residual R                          */
+    OFDFT_OPT_PCG = 1   /* the same on z = K R, K(G) = 1 / (1 + G^2): a reciprocal-space
+                           preconditioner for the -grad^2 of the vW term (two extra
+                           transforms per iteration)                                  */
+};
 typedef struct {
     double tol;
     int32_t max_iter;
-    int32_t method;   /* 0: CG (Polak-Ribiere+) */
+    int32_t method;   /* OFDFT_OPT_CG or OFDFT_OPT_PCG */
     int32_t warm;     /* server requests: start from the resident density */
 } ofdft_opt_params;
 typedef struct {

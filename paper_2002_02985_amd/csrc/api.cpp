@@ -42,7 +42,7 @@ static ofdft_status fail(ofdft_status st, const std::string &msg)
     } while (0)
 
 static const double PI = 3.14159265358979323846264338327950288;
-static const int NVEC_OPT = 8;   // optimiser vectors per grid
+static const int NVEC_OPT = 10;   // optimiser vectors per grid
 static const double C_TF = 2.8712340001881918;
 
 // ---------------------------------------------------------------- handles
@@ -117,7 +117,7 @@ struct ofdft_grid {
     double *h_sums = nullptr;   // pinned
     // resident density and optimiser vectors (N each)
     void *rho = nullptr;
-    void *opt[9] = {nullptr};
+    void *opt[NVEC_OPT] = {nullptr};
     size_t bytes = 0;
     double *d_forces = nullptr;   // natoms x 3
     double *d_frac = nullptr;     // natoms x 3 fractional coordinates, species-sorted
@@ -126,6 +126,7 @@ struct ofdft_grid {
     Timer timer;
     int tune_col_tile_major = 0;   // block order of the column passes
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
+    double precond_q2 = 1.0;                    // optimiser preconditioner q0^2
 };
 
 // ---------------------------------------------------------------- helpers
@@ -445,6 +446,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.use_ext = (g->func.terms & OFDFT_TERM_EXT) ? 1 : 0;
     a.lambda_vw = g->func.lambda_vw;
     a.kf_wt = g->kf_wt;
+    a.precond_q2 = g->precond_q2;
     int L;
     if (axis == 1) {
         L = G.n1;
@@ -1015,8 +1017,9 @@ static hipStream_t pick_stream(ofdft_grid *g, void *hs)
 
 // ---------------------------------------------------------------- optimiser
 // Vectors: 0 phi, 1 p (search direction on the sphere), 2 d (raw direction),
-// 3 R (residual), 4 R_prev, 5 g (dE/dphi at phi), 6 phi trial, 7 g trial.
-enum { V_PHI = 0, V_P, V_D, V_R, V_RP, V_G, V_PT, V_GT, NVEC = NVEC_OPT };
+// 3 R (residual), 4 R_prev, 5 g (dE/dphi at phi), 6 phi trial, 7 g trial,
+// 8 z = K R (preconditioned residual), 9 z_prev.
+enum { V_PHI = 0, V_P, V_D, V_R, V_RP, V_G, V_PT, V_GT, V_Z, V_ZP, NVEC = NVEC_OPT };
 
 struct OptState {
     ofdft_grid *g;
@@ -1053,6 +1056,51 @@ static ofdft_status lincomb(OptState &o, void *z, double a, const void *x, doubl
     return OFDFT_OK;
 }
 
+// out = K in with K(G) = q0^2 / (G^2 + q0^2): forward transform, the
+// multiply inside the axis-0 pass, inverse transform (grid workspace slot 0)
+template <typename T>
+static ofdft_status precondition(OptState &o, const void *in, void *out)
+{
+    ofdft_grid *g = o.g;
+    hipStream_t s = o.s;
+    const Geom &G = g->geom;
+    RowFwdArgs rf;
+    std::memset(&rf, 0, sizeof(rf));
+    rf.in = in;
+    rf.out = g->spec;
+    rf.nfields = 1;
+    rf.kind[0] = FK_RAW;
+    rf.twM = g->twM;
+    rf.twN = g->twN;
+    rf.tw1 = g->tw1;
+    rf.knots = g->knots;
+    int nbk = 0;
+    const bool plane = plane_supported<T>(G.n1, G.m);
+    if (plane) {
+        TIMED(PS_OTHER, launch_plane_fwd<T>(G, 1, rf, nbk, s));
+    } else {
+        TIMED(PS_OTHER, launch_row_fwd<T>(G, 1, rf, nbk, s));
+        ST_TRY(col_pass<T>(g, s, 1, g->spec, 1, 1, 0, nullptr, PS_OTHER));
+    }
+    int ops[4] = {GO_PRECOND, 0, 0, 0};
+    ST_TRY(col_pass<T>(g, s, 0, g->spec, 1, 1, 0, ops, PS_OTHER));
+    if (!plane) ST_TRY(col_pass<T>(g, s, 1, g->spec, 1, 1, 1, nullptr, PS_OTHER));
+    RowInvArgs ri;
+    std::memset(&ri, 0, sizeof(ri));
+    ri.spec = g->spec;
+    ri.nfields = 1;
+    ri.mode = EP_STORE;
+    ri.out = out;
+    ri.nbatch = 1;
+    ri.twM = g->twM;
+    ri.twN = g->twN;
+    ri.tw1 = g->tw1;
+    ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
+    if (plane) TIMED(PS_OTHER, launch_plane_inv<T>(G, ri, nbk, s));
+    else TIMED(PS_OTHER, launch_row_inv<T>(G, ri, nbk, s));
+    return OFDFT_OK;
+}
+
 static double cubic_min(double a, double fa, double da, double b, double fb, double db, bool &ok)
 {
     const double d1 = da + db - 3.0 * (fa - fb) / (a - b);
@@ -1078,6 +1126,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     const double dv = g->dv, ne = g->nelec;
     const int max_iter = prm->max_iter;
     const double tol = prm->tol;
+    const bool precond = prm->method == OFDFT_OPT_PCG;
     std::memset(res, 0, sizeof(*res));
 
     // phi = sqrt(rho_resident), normalised to N_e
@@ -1100,21 +1149,24 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         }
         if (g->cancel && g->cancel->load(std::memory_order_relaxed))
             return fail(OFDFT_ECANCELLED, "optimisation cancelled");
-        // R = g - 2 mu phi
+        // R = g - 2 mu phi; z = K R with the preconditioner, else z = R
         ST_TRY(lincomb<T>(o, v[V_R], 1.0, v[V_G], -2.0 * E.mu, v[V_PHI]));
+        const int Z = precond ? V_Z : V_R, ZP = precond ? V_ZP : V_RP;
+        if (precond) ST_TRY(precondition<T>(o, v[V_R], v[V_Z]));
         double dd[3];
         if (have_prev) {
-            ST_TRY(dots<T>(o, 3, v[V_R], v[V_R], v[V_R], v[V_RP], v[V_RP], v[V_RP], dd));
+            // Polak-Ribiere+: beta = max(0, <z, R - R_prev> / <z_prev, R_prev>)
+            ST_TRY(dots<T>(o, 3, v[Z], v[V_R], v[Z], v[V_RP], v[ZP], v[V_RP], dd));
             const double beta = std::max(0.0, (dd[0] - dd[1]) / dd[2]);
-            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], beta, v[V_D]));
+            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[Z], beta, v[V_D]));
         } else {
-            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], 0.0, nullptr));
+            ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[Z], 0.0, nullptr));
         }
         double q[3];
         for (int attempt = 0; attempt < 2; ++attempt) {
             ST_TRY(dots<T>(o, 3, v[V_D], v[V_R], v[V_D], v[V_PHI], v[V_PHI], v[V_PHI], q));
             if (q[0] >= 0.0 && attempt == 0) {   // not a descent direction: restart
-                ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[V_R], 0.0, nullptr));
+                ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[Z], 0.0, nullptr));
                 continue;
             }
             break;
@@ -1132,7 +1184,9 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         double theta0 = (kappa > 0) ? std::min(1.0, std::max(1e-12, -d0 / kappa))
                                     : (theta_prev > 0 ? theta_prev : 0.1);
         const double f0 = E.e_total;
-        const double eps_f = 1e-14 * std::max(1.0, std::fabs(f0));
+        // energy differences below the evaluation's rounding level are not
+        // trusted: there the search accepts on the derivative conditions
+        const double eps_f = (g->fp64 ? 1e-14 : 1e-8) * std::max(1.0, std::fabs(f0));
         // trial evaluation at theta: phi_t = phi cos + p sin; returns E and dE/dtheta
         double last_theta = -1.0;
         ofdft_energy Et;
@@ -1206,6 +1260,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         std::swap(v[V_PHI], v[V_PT]);
         std::swap(v[V_G], v[V_GT]);
         std::swap(v[V_R], v[V_RP]);
+        if (precond) std::swap(v[V_Z], v[V_ZP]);
         have_prev = true;
         E = Et;
     }
@@ -1475,6 +1530,8 @@ ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, of
 {
     if (!grid || !params || !result) return fail(OFDFT_EINVAL, "null argument");
     if (!(params->tol > 0) || params->max_iter < 0) return fail(OFDFT_EINVAL, "bad parameters");
+    if (params->method != OFDFT_OPT_CG && params->method != OFDFT_OPT_PCG)
+        return fail(OFDFT_EINVAL, "unknown optimisation method");
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return grid->fp64 ? optimize_impl<double>(grid, params, result)
                       : optimize_impl<float>(grid, params, result);

@@ -408,6 +408,10 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
                 o = cscale(F, T(a.lambda_vw) * G2);
             } else if (op == GO_WT) {
                 o = cscale(F, pre[q].x);
+            } else if (op == GO_PRECOND) {
+                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
+                const T q2 = T(a.precond_q2);
+                o = cscale(F, q2 / (G2 + q2));
             } else {  // GO_SCALE
                 o = F;
             }

@@ -20,6 +20,7 @@ KNOTS_LOG, KNOTS_LIN = 0, 1
 NL_S3S4, NL_EXACT = 0, 1
 FP64, MIXED = 0, 1
 REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
+OPT_CG, OPT_PCG = 0, 1
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
               "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
 
@@ -411,5 +412,6 @@ class Grid:
     def forces(self):
         return ofdft_forces(self.handle, self.natoms)
 
-    def optimize(self, tol=1e-7, max_iter=1000, allow_noconv=False):
-        return ofdft_optimize(self.handle, tol, max_iter, allow_noconv=allow_noconv)
+    def optimize(self, tol=1e-7, max_iter=1000, allow_noconv=False, method=OPT_CG):
+        return ofdft_optimize(self.handle, tol, max_iter, method=method,
+                              allow_noconv=allow_noconv)

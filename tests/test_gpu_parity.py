@@ -202,3 +202,42 @@ def test_optimize_c1_fp64_matches_oracle_minimum():
     assert abs(r.e.e_total - ref.result.e_total) < 1e-9
     assert abs(oc.dv * rho_gpu.sum() - cell["nelec"]) < 1e-10
     np.testing.assert_allclose(rho_gpu, ref.phi ** 2, atol=1e-6)
+
+
+def test_optimize_c1_preconditioned_reaches_the_same_minimum():
+    """The preconditioned search direction changes the path, not the
+    minimiser (TF+vW+H+ext is strictly convex in rho)."""
+    from oracle.optimize import optimize as o_opt
+    cell, rho = c1_cell()
+    oc = make_cell(cell)
+    ref = o_opt(oc, OC.Functional(terms=int(LOCAL)), np.sqrt(rho), tol=1e-7, max_iter=500,
+                vext=OF.vext_g(oc), e_ion=ewald_energy(oc))
+    with ofdft.Grid(cell, LOCAL) as g:
+        g.set_density(rho)
+        r, st = g.optimize(tol=1e-7, max_iter=500, method=ofdft.OPT_PCG)
+        assert st == ofdft.OK
+        g.set_density(rho)
+        r0, _ = g.optimize(tol=1e-7, max_iter=500)
+    print("c1 iterations: CG %d (%d evals), PCG %d (%d evals)" % (r0.iters, r0.evals, r.iters,
+                                                                   r.evals), flush=True)
+    assert abs(r.e.e_total - ref.result.e_total) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_preconditioner_speeds_up_a_vacuum_cluster(prec):
+    cell = W.cluster(19, "Al", seed=11, grid=48)
+    rho = W.gaussian_density(cell, sigma=1.5, floor=1e-8)
+    res = {}
+    for m in (ofdft.OPT_CG, ofdft.OPT_PCG):
+        with ofdft.Grid(cell, LOCAL, precision=prec) as g:
+            g.set_density(rho)
+            res[m] = g.optimize(tol=1e-5, max_iter=2000, method=m, allow_noconv=True)
+    (rc, sc), (rp, sp) = res[ofdft.OPT_CG], res[ofdft.OPT_PCG]
+    print("cluster %s: CG %d it %d ev resid %.1e E %.10f; PCG %d it %d ev resid %.1e E %.10f" %
+          ("fp64" if prec == ofdft.FP64 else "mixed", rc.iters, rc.evals, rc.final_resid,
+           rc.e.e_total, rp.iters, rp.evals, rp.final_resid, rp.e.e_total), flush=True)
+    assert sp == ofdft.OK
+    assert rp.iters < rc.iters
+    if sc == ofdft.OK:
+        # both stop at an RMS residual below 1e-5, whose energy error is O(resid^2)
+        assert abs(rp.e.e_total - rc.e.e_total) <= (1e-6 if prec == ofdft.FP64 else 1e-4)

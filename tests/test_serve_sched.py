@@ -35,7 +35,7 @@ def test_footprint_parts():
     fo = ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_FORCES)
     op = ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_OPTIMIZE)
     assert fo - ep == 4 * 3 * 8                 # forces buffer: natoms x 3 doubles
-    assert op - ep == 8 * N * 8                 # eight FP64 optimiser fields
+    assert op - ep == 10 * N * 8                # ten FP64 optimiser fields
     # every field-sized buffer is at least: resident rho, 2 staging fields,
     # 4 half spectra (2 N/2+1 complex), v_ext and 3 G tables
     nh = 32 * 32 * 17
