@@ -163,38 +163,43 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
     // is recomputed here instead of being hoisted out of callers' loops and
     // held in registers across the whole kernel
     asm volatile("" : "+v"(tid));
+    // unsigned index arithmetic: divisions by the compile-time P and NS
+    // become multiply-high and shifts without sign fix-ups
+    const unsigned ut = (unsigned)tid;
     cpx<T> v[PER][R];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int b = tid + q * NT;
-        if (TOT % NT == 0 || b < TOT) {
-            const int j = b / P;
-            const int p = b % P;
+        const unsigned b = ut + (unsigned)(q * NT);
+        if (TOT % NT == 0 || b < (unsigned)TOT) {
+            const unsigned j = b / (unsigned)P;
+            const unsigned p = b % (unsigned)P;
+            const unsigned a0 = j * (unsigned)ES + p * (unsigned)PS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[lidx<ES, PS>(j + r * NBF, p)];
+            for (int r = 0; r < R; ++r) v[q][r] = buf[a0 + (unsigned)(r * NBF * ES)];
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int b = tid + q * NT;
-        if (TOT % NT == 0 || b < TOT) {
-            const int j = b / P;
-            const int p = b % P;
-            const int k = j % NS;
+        const unsigned b = ut + (unsigned)(q * NT);
+        if (TOT % NT == 0 || b < (unsigned)TOT) {
+            const unsigned j = b / (unsigned)P;
+            const unsigned p = b % (unsigned)P;
+            const unsigned k = j % (unsigned)NS;
             if constexpr (NS > 1) {
                 constexpr int STEP = L / (NS * R);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cpx<T> w = tw[r * k * STEP];
+                    cpx<T> w = tw[k * (unsigned)(r * STEP)];
                     if constexpr (INV) w.y = -w.y;
                     v[q][r] = cmul(v[q][r], w);
                 }
             }
             dft<T, R, INV>(v[q]);
-            const int base = (j / NS) * NS * R + k;
+            const unsigned a0 = ((j / (unsigned)NS) * (unsigned)(NS * R) + k) * (unsigned)ES +
+                                p * (unsigned)PS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[lidx<ES, PS>(base + r * NS, p)] = v[q][r];
+            for (int r = 0; r < R; ++r) buf[a0 + (unsigned)(r * NS * ES)] = v[q][r];
         }
     }
     __syncthreads();

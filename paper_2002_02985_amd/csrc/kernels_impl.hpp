@@ -829,8 +829,10 @@ template <int N1, int M> constexpr int plane_NT() { return 1024; }
 template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? 8 : 4; }
 template <typename T, int N1, int M> constexpr bool plane_fits()
 {
-    // both kernels also stage the input plane (N1 x 2M reals) in LDS
-    return ((long long)(M + 1) * plane_A<N1>() * 2 + (long long)N1 * 2 * M) * sizeof(T) <= 98304;
+    // both kernels also stage the input plane (N1 x 2M reals) and the
+    // twiddles (N1 + 2M + 1 complex) in LDS
+    return ((long long)(M + 1) * plane_A<N1>() * 2 + (long long)N1 * 2 * M +
+            2LL * (N1 + 2 * M + 1)) * sizeof(T) <= 98304;
 }
 
 // X[k] from Z[k] and Z[M-k] (r2c unpack), W^k = twN[k]
@@ -854,6 +856,18 @@ __device__ __forceinline__ cpx<T> c2r_pack(cpx<T> xk, cpx<T> xm, cpx<T> w)
     return {s.x - dw.y, s.y + dw.x};
 }
 
+// copies the twiddle tables of both axes and of the r2c (un)pack into LDS:
+// [W_N1^n, n < N1 | W_M^n, n < M | W_2M^k, k <= M]
+template <typename T, int N1, int M, int NTP>
+__device__ __forceinline__ void stage_plane_twiddles(cpx<T> *tws, const void *tw1, const void *twM,
+                                                     const void *twN, int tid)
+{
+    for (int i = tid; i < N1 + 2 * M + 1; i += NTP)
+        tws[i] = i < N1 ? ((const cpx<T> *)tw1)[i]
+                        : (i < N1 + M ? ((const cpx<T> *)twM)[i - N1]
+                                      : ((const cpx<T> *)twN)[i - N1 - M]);
+}
+
 template <typename T, int N1, int M>
 __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plane_fwd(RowFwdArgs a, Geom g)
 {
@@ -864,14 +878,16 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int HALF = M / 2 + 1;
     __shared__ cpx<T> buf[(M + 1) * A];
     __shared__ cpx<T> xs[N1 * M];   // the input plane, read once from HBM
+    __shared__ cpx<T> tws[N1 + 2 * M + 1];   // twiddles of both axes and the r2c unpack
     __shared__ double red[3 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
     const cpx<T> *in = (const cpx<T> *)((const T *)a.in + (long long)b * g.N +
                                         (long long)i0 * N1 * g.n2);
-    const cpx<T> *twM = (const cpx<T> *)a.twM;
-    const cpx<T> *twN = (const cpx<T> *)a.twN;
-    const cpx<T> *tw1 = (const cpx<T> *)a.tw1;
+    stage_plane_twiddles<T, N1, M, NTP>(tws, a.tw1, a.twM, a.twN, tid);
+    const cpx<T> *tw1 = tws;
+    const cpx<T> *twM = tws + N1;
+    const cpx<T> *twN = tws + N1 + M;
 
     cpx<T> x[PER];
 #pragma unroll
@@ -1027,12 +1043,15 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     __shared__ cpx<T> buf[(M + 1) * A];
     __shared__ cpx<T> xsbuf[N1 * M];
+    __shared__ cpx<T> tws[N1 + 2 * M + 1];
     __shared__ double red[4 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
-    const cpx<T> *twM = (const cpx<T> *)a.twM;
-    const cpx<T> *twN = (const cpx<T> *)a.twN;
-    const cpx<T> *tw1 = (const cpx<T> *)a.tw1;
+    stage_plane_twiddles<T, N1, M, NTP>(tws, a.tw1, a.twM, a.twN, tid);
+    __syncthreads();
+    const cpx<T> *tw1 = tws;
+    const cpx<T> *twM = tws + N1;
+    const cpx<T> *twN = tws + N1 + M;
     const long long plane_off = (long long)i0 * N1 * (M + 1);
     auto spec_of = [&](int f) {
         return (const cpx<T> *)a.spec + f * a.spec_fstride + (long long)b * g.Nh + plane_off;
