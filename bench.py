@@ -138,6 +138,8 @@ def parse():
     ap.add_argument("--c3-steps", type=int, default=10)
     ap.add_argument("--c3-max-iter", type=int, default=1500)
     ap.add_argument("--c3-no-opt", action="store_true")
+    ap.add_argument("--c3-opt-mode", default="s3s4", choices=("s3s4", "exact"),
+                    help="spline potential driving the optimisation")
     ap.add_argument("--serve-max-iter", type=int, default=50)
     ap.add_argument("--serve-tol", type=float, default=1e-5)
     return ap.parse_args()
@@ -416,6 +418,7 @@ def c3_main(args):
             t0 = time.perf_counter()
             iters = evals = 0
             r, st = None, ofdft.ENOCONV
+            best = float("inf")
             while iters < args.c3_max_iter and time.perf_counter() - t0 < budget_s:
                 r, st = g.optimize(tol=1e-6, max_iter=min(50, args.c3_max_iter - iters),
                                    allow_noconv=True, method=ofdft.OPT_PCG)
@@ -425,20 +428,24 @@ def c3_main(args):
                     (label, iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t0))
                 if st == ofdft.OK or r.iters == 0:
                     break
+                if r.final_resid > 0.9 * best:
+                    break   # no longer improving: the precision's residual floor
+                best = min(best, r.final_resid)
             return {"status": int(st), "iters": iters, "evals": evals,
                     "final_resid": r.final_resid, "e_total": r.e.e_total,
                     "wall_s": round(time.perf_counter() - t0, 2)}
 
-        opt = {}
-        log("optimise: mixed precision, EXACT potential, preconditioned CG, tol 1e-6")
-        with ofdft.Grid(cell, terms, precision=ofdft.MIXED, nl_mode=ofdft.NL_EXACT, **spl) as g:
+        opt = {"nl_mode": args.c3_opt_mode}
+        nlm = ofdft.NL_S3S4 if args.c3_opt_mode == "s3s4" else ofdft.NL_EXACT
+        log("optimise: mixed precision, %s potential, preconditioned CG, tol 1e-6" % args.c3_opt_mode)
+        with ofdft.Grid(cell, terms, precision=ofdft.MIXED, nl_mode=nlm, **spl) as g:
             g.set_density(rho)
             opt["mixed"] = run_opt(g, "mixed", 240.0)
             opt["mixed"]["device_bytes"] = ofdft.ofdft_grid_device_bytes(g.handle)
             rho_m = g.get_density()
         if opt["mixed"]["final_resid"] >= 1e-6:
             log("FP32 residual floor reached: FP64 polish from the mixed result")
-            with ofdft.Grid(cell, terms, precision=ofdft.FP64, nl_mode=ofdft.NL_EXACT, **spl) as g:
+            with ofdft.Grid(cell, terms, precision=ofdft.FP64, nl_mode=nlm, **spl) as g:
                 g.set_density(rho_m)
                 opt["fp64_polish"] = run_opt(g, "fp64", 240.0)
         line["optimize"] = opt

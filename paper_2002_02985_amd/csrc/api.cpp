@@ -1127,6 +1127,15 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     const int max_iter = prm->max_iter;
     const double tol = prm->tol;
     const bool precond = prm->method == OFDFT_OPT_PCG;
+    // The line search brackets and refines a root of dE/dtheta = <g, dphi/dtheta>
+    // without comparing energies (a) when the potential is not the derivative
+    // of the energy: the S3S4 spline potential interpolates per-knot
+    // potentials, and the search then solves the Euler equation along the
+    // line; (b) on the mixed path, where energy differences near convergence
+    // fall below the FP32 rounding of the large Hartree and electron-ion
+    // terms while the FP64 dot products of the derivative stay reliable.
+    const bool deriv_only =
+        !g->fp64 || ((g->func.terms & OFDFT_TERM_SPLINE) && g->func.nl_mode == OFDFT_NL_S3S4);
     std::memset(res, 0, sizeof(*res));
 
     // phi = sqrt(rho_resident), normalised to N_e
@@ -1202,18 +1211,35 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
             return OFDFT_OK;
         };
         auto decrease_ok = [&](double a, double fa, double da) {
+            if (deriv_only) return true;
             return fa <= f0 + c1 * a * d0 || (fa <= f0 + eps_f && da <= (2 * c1 - 1) * d0);
         };
+        // next trial inside (lo, hi): cubic interpolation of (f, df), or the
+        // secant on df when energies are not compared
+        auto interp = [&](double a0, double f0_, double d0_, double a1, double f1, double d1,
+                          bool &ok) {
+            if (!deriv_only) return cubic_min(a0, f0_, d0_, a1, f1, d1, ok);
+            ok = d1 != d0_;
+            return ok ? a0 - d0_ * (a1 - a0) / (d1 - d0_) : 0.0;
+        };
+        double best_d = 1e300;
         // strong-Wolfe search: bracket, then zoom with safeguarded cubic steps
         double a_lo = 0.0, f_lo = f0, d_lo = d0, a_hi = 0, f_hi = 0, d_hi = 0;
         double a = theta0, best_a = -1, best_f = 1e300;
         bool done = false, zoom = false;
         int budget = 20;
         double fa = 0, da = 0;
+        auto note_best = [&](double a_, double f_, double d_) {
+            if (deriv_only ? std::fabs(d_) < best_d : f_ < best_f) {
+                best_f = f_;
+                best_d = std::fabs(d_);
+                best_a = a_;
+            }
+        };
         for (int k = 0; k < budget && !done && !zoom; ++k) {
             ST_TRY(trial(a, fa, da));
-            if (fa < best_f) { best_f = fa; best_a = a; }
-            if (!decrease_ok(a, fa, da) || (k > 0 && fa > f_lo + eps_f)) {
+            note_best(a, fa, da);
+            if (!decrease_ok(a, fa, da) || (!deriv_only && k > 0 && fa > f_lo + eps_f)) {
                 a_hi = a; f_hi = fa; d_hi = da; zoom = true; break;
             }
             if (std::fabs(da) <= -c2 * d0) { done = true; break; }
@@ -1224,7 +1250,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
                 break;
             }
             bool ok;
-            double an = cubic_min(a_lo, f_lo, d_lo, a, fa, da, ok);
+            double an = interp(a_lo, f_lo, d_lo, a, fa, da, ok);
             if (!ok || an <= a * 1.1 || an > a * 4.0) an = 2.0 * a;
             a_lo = a; f_lo = fa; d_lo = da;
             a = an;
@@ -1233,13 +1259,13 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
             for (int k = 0; k < budget && !done; ++k) {
                 const double lo = std::min(a_lo, a_hi), hi = std::max(a_lo, a_hi);
                 bool ok;
-                double an = cubic_min(a_lo, f_lo, d_lo, a_hi, f_hi, d_hi, ok);
+                double an = interp(a_lo, f_lo, d_lo, a_hi, f_hi, d_hi, ok);
                 if (!ok || !(an > lo && an < hi)) an = 0.5 * (a_lo + a_hi);
                 else an = std::min(std::max(an, lo + 0.01 * (hi - lo)), hi - 0.01 * (hi - lo));
                 a = an;
                 ST_TRY(trial(a, fa, da));
-                if (fa < best_f) { best_f = fa; best_a = a; }
-                if (!decrease_ok(a, fa, da) || fa > f_lo + eps_f) {
+                note_best(a, fa, da);
+                if (!decrease_ok(a, fa, da) || (!deriv_only && fa > f_lo + eps_f)) {
                     a_hi = a; f_hi = fa; d_hi = da;
                 } else {
                     if (std::fabs(da) <= -c2 * d0) { done = true; break; }
@@ -1250,7 +1276,8 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         }
         if (!done) {
             // fall back to the best point seen
-            if (!(best_f <= f0 + eps_f)) break;
+            if (!deriv_only && !(best_f <= f0 + eps_f)) break;
+            if (deriv_only && !(best_d < std::fabs(d0))) break;
             if (best_a != last_theta) ST_TRY(trial(best_a, fa, da));
             a = best_a;
         }

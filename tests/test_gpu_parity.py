@@ -241,3 +241,22 @@ def test_preconditioner_speeds_up_a_vacuum_cluster(prec):
     if sc == ofdft.OK:
         # both stop at an RMS residual below 1e-5, whose energy error is O(resid^2)
         assert abs(rp.e.e_total - rc.e.e_total) <= (1e-6 if prec == ofdft.FP64 else 1e-4)
+
+
+def test_spline_s3s4_optimisation_reaches_the_euler_solution():
+    """With the interpolated (S3S4) potential the search solves the Euler
+    equation: the residual of the returned density is below tol, and a fresh
+    evaluation of that density agrees."""
+    cell = W.mg_hcp_slab((1, 1, 2), (16, 24, 48), vacuum=8.0)
+    rho = W.gaussian_density(cell, sigma=1.5, floor=1e-12)
+    kw = dict(nk=16, kf_min=0.1, kf_max=3.0, nl_mode=ofdft.NL_S3S4)
+    with ofdft.Grid(cell, LOCAL | ofdft.TERM_SPLINE, precision=ofdft.FP64, **kw) as g:
+        g.set_density(rho)
+        r, st = g.optimize(tol=1e-6, max_iter=800, method=ofdft.OPT_PCG)
+        e, _ = g.energy_potential(None, want_v=False)
+    print("slab S3S4: %d iterations, %d evaluations, resid %.2e" % (r.iters, r.evals,
+                                                                    r.final_resid), flush=True)
+    assert st == ofdft.OK and r.final_resid < 1e-6
+    assert e.resid_norm < 1e-6
+    assert abs(e.e_total - r.e.e_total) < 1e-9
+    assert abs(e.nelec_int - cell["nelec"]) < 1e-9
