@@ -140,6 +140,16 @@ def parse():
     ap.add_argument("--c3-no-opt", action="store_true")
     ap.add_argument("--c3-opt-mode", default="s3s4", choices=("s3s4", "exact"),
                     help="spline potential driving the optimisation")
+    ap.add_argument("--c5", action="store_true",
+                    help="large cell instead: fcc Al 63^3 cells (1,000,188 atoms) on 1024^3 "
+                         "with the spline KEDF: set-up, evaluation and optimisation")
+    ap.add_argument("--c5-subsample", type=int, default=1,
+                    help="keep every k-th atom (sizing runs)")
+    ap.add_argument("--c5-jitter", type=float, default=0.0)
+    ap.add_argument("--c5-no-opt", action="store_true")
+    ap.add_argument("--c5-no-polish", action="store_true")
+    ap.add_argument("--c5-budget", type=float, default=420.0,
+                    help="seconds for the mixed optimisation")
     ap.add_argument("--serve-max-iter", type=int, default=50)
     ap.add_argument("--serve-tol", type=float, default=1e-5)
     return ap.parse_args()
@@ -452,8 +462,111 @@ def c3_main(args):
     print(json.dumps(line), flush=True)
 
 
+def c5_main(args):
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
+             ofdft.TERM_SPLINE)
+    spl = dict(nk=32, kf_min=0.1, kf_max=3.0, nl_mode=ofdft.NL_S3S4)
+    cell = W.config_c5(jitter=args.c5_jitter, subsample=args.c5_subsample)
+    natoms = len(cell["species"])
+    N = int(np.prod(cell["n"]))
+    V = W.volume(cell)
+    rho0 = cell["nelec"] / V
+    out = {"metric": "1024^3 spline optimisation: set-up, evaluation and optimisation time",
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "fcc Al %d atoms (63^3 cells%s, a = 482 Bohr), 1024^3 grid, "
+                                  "TF+vW+Hartree+local pseudopotential+spline KEDF (32 log "
+                                  "knots, S3S4), uniform start rho0 = %.6f"
+                                  % (natoms, ", every %d-th atom" % args.c5_subsample
+                                     if args.c5_subsample > 1 else "", rho0),
+                      "natoms": natoms, "grid": list(cell["n"])}}
+    cd, fd = ofdft.make_cell_desc(cell)[0], ofdft.make_functional_desc(terms, precision=ofdft.MIXED, **spl)
+    out["footprint_bytes"] = {"mixed_optimize": ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_OPTIMIZE)}
+    log("creating the mixed-precision grid (structure factor over %d atoms)" % natoms)
+    t0 = time.perf_counter()
+    g = ofdft.Grid(cell, terms, precision=ofdft.MIXED, **spl)
+    out["setup_s"] = round(time.perf_counter() - t0, 2)
+    log("set-up %.1f s" % out["setup_s"])
+    sh = torch.cuda.current_stream().cuda_stream
+    x = torch.full(tuple(cell["n"]), rho0, dtype=torch.float32, device="cuda:0")
+    ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
+        lat.append(time.perf_counter() - t1)
+    ms = float(np.median(lat)) * 1e3
+    out["eval"] = {"ms_per_eval": round(ms, 1), "Gpts_per_s": round(N / (ms * 1e-3) / 1e9, 3),
+                   "e_total": e.e_total, "e_ion": e.e_ion, "nelec_int": e.nelec_int}
+    log("evaluation %.1f ms, E(uniform) = %.6f" % (ms, e.e_total))
+    del x
+    torch.cuda.empty_cache()
+    if not args.c5_no_opt:
+        log("uniform start, preconditioned CG, mixed precision")
+        g.set_density(np.full(tuple(cell["n"]), rho0))
+        t1 = time.perf_counter()
+        iters = evals = 0
+        best = float("inf")
+        r = None
+        while time.perf_counter() - t1 < args.c5_budget:
+            r, st = g.optimize(tol=1e-6, max_iter=20, allow_noconv=True, method=ofdft.OPT_PCG)
+            iters += r.iters
+            evals += r.evals
+            log("mixed: %d iterations, %d evaluations, resid %.3e, E %.8f, %.1f s" %
+                (iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t1))
+            if st == ofdft.OK or r.iters == 0 or r.final_resid > 0.9 * best:
+                break
+            best = min(best, r.final_resid)
+        out["optimize"] = {"mixed": {"iters": iters, "evals": evals, "final_resid": r.final_resid,
+                                     "e_total": r.e.e_total,
+                                     "wall_s": round(time.perf_counter() - t1, 1),
+                                     "device_bytes": ofdft.ofdft_grid_device_bytes(g.handle)}}
+        rho_m = g.get_density() if not args.c5_no_polish else None
+        g.close()
+        if rho_m is not None and r.final_resid >= 1e-6:
+            log("FP64 polish: creating the FP64 grid")
+            t1 = time.perf_counter()
+            g = ofdft.Grid(cell, terms, precision=ofdft.FP64, **spl)
+            su = time.perf_counter() - t1
+            g.set_density(rho_m)
+            del rho_m
+            t1 = time.perf_counter()
+            iters = evals = 0
+            while time.perf_counter() - t1 < args.c5_budget:
+                r, st = g.optimize(tol=1e-6, max_iter=10, allow_noconv=True, method=ofdft.OPT_PCG)
+                iters += r.iters
+                evals += r.evals
+                log("fp64: %d iterations, %d evaluations, resid %.3e, E %.8f, %.1f s" %
+                    (iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t1))
+                if st == ofdft.OK or r.iters == 0:
+                    break
+            out["optimize"]["fp64_polish"] = {
+                "setup_s": round(su, 1), "iters": iters, "evals": evals,
+                "final_resid": r.final_resid, "e_total": r.e.e_total,
+                "converged": bool(r.final_resid < 1e-6),
+                "wall_s": round(time.perf_counter() - t1, 1),
+                "device_bytes": ofdft.ofdft_grid_device_bytes(g.handle)}
+            g.close()
+    else:
+        g.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.c5:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        c5_main(args)
+        return
     if args.c3:
         if args.gpus != 1:
             print("bench.py: this build runs on one GPU", file=sys.stderr)

@@ -43,6 +43,10 @@ static ofdft_status fail(ofdft_status st, const std::string &msg)
 
 static const double PI = 3.14159265358979323846264338327950288;
 static const int NVEC_OPT = 10;   // optimiser vectors per grid
+// From this many atoms on, the structure factor is the tiled direct sum
+// without per-atom phase tables and the Ewald sum uses bins and the FFT box
+// (forces are not offered there: each would cost a full structure factor).
+static const int LARGE_IONS = 8192;
 static const double C_TF = 2.8712340001881918;
 
 // ---------------------------------------------------------------- handles
@@ -127,6 +131,9 @@ struct ofdft_grid {
     int tune_col_tile_major = 0;   // block order of the column passes
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
     double precond_q2 = 1.0;                    // optimiser preconditioner q0^2
+    bool large_ions = false;                    // tiled structure factor, binned Ewald
+    int *d_bin_start = nullptr, *d_bin_of = nullptr;
+    double *d_ew_part = nullptr;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -218,11 +225,71 @@ static EwaldGeom ewald_geom(const double lat[3][3], const double b[3][3], double
     return e;
 }
 
+// Ewald parameters for a large cell: the reciprocal sum is taken over the FFT
+// box, so its cut-off is the radius of the sphere inscribed in the box,
+// min_d pi (n_d - 2) / |a_d|, and a = gcut / 13.2 (or the balanced value if
+// that is smaller); bins for the real-space sum are at least 6.6/a wide.
+struct LargeEwald {
+    EwaldGeom e;
+    int nbin[3];
+};
+static LargeEwald large_ewald(const double lat[3][3], const double b[3][3], double V, int na,
+                              const int n[3])
+{
+    LargeEwald L;
+    L.e = ewald_geom(lat, b, V, na);
+    double gmax = 1e300;
+    for (int d = 0; d < 3; ++d) {
+        const double an = std::sqrt(lat[d][0] * lat[d][0] + lat[d][1] * lat[d][1] + lat[d][2] * lat[d][2]);
+        gmax = std::min(gmax, PI * (n[d] - 2) / an);
+    }
+    const double a = std::min(L.e.a, gmax / 13.2);
+    const double rcut = 6.6 / a;
+    L.e.a = a;
+    L.e.rcut2 = rcut * rcut;
+    L.e.gcut2 = (13.2 * a) * (13.2 * a);
+    for (int d = 0; d < 3; ++d) {
+        // width of the cell across the planes spanned by the other two vectors
+        const double bn = std::sqrt(b[d][0] * b[d][0] + b[d][1] * b[d][1] + b[d][2] * b[d][2]);
+        const double width = 2 * PI / bn;
+        L.nbin[d] = std::max(1, (int)std::floor(width / rcut));
+        // images for the all-pairs fallback; no reciprocal box there
+        L.e.nmax[d] = (int)std::ceil(rcut * bn / (2 * PI)) + 1;
+        L.e.gmax[d] = 0;
+    }
+    return L;
+}
+
+static bool use_large_ions(int na)
+{
+    if (const char *e = std::getenv("OFDFT_LARGE_IONS")) return std::atoi(e) != 0 && na > 0;
+    return na >= LARGE_IONS;
+}
+
 // device bytes of the ionic buffers: sorted fractional coordinates, Ewald
-// positions, charges, per-atom energies and forces, and S(G) on the box
-static uint64_t ion_bytes(const double lat[3][3], int na)
+// positions, charges, per-atom energies and forces, and S(G) on the box; for
+// large cells bins and per-block reciprocal partials instead of S(G) and forces
+static uint64_t ion_bytes(const double lat[3][3], int na, const Geom &G)
 {
     if (na <= 0) return 0;
+    if (use_large_ions(na)) {
+        const double(*A)[3] = lat;
+        const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        double b[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                b[i][j] = 2.0 * PI * (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;
+            }
+        const int n[3] = {G.n0, G.n1, G.n2};
+        const LargeEwald L = large_ewald(lat, b, std::fabs(det), na, n);
+        const bool binned = L.nbin[0] >= 3 && L.nbin[1] >= 3 && L.nbin[2] >= 3;
+        const uint64_t nbins = binned ? (uint64_t)L.nbin[0] * L.nbin[1] * L.nbin[2] : 1;
+        return (uint64_t)na * (3 + 3 + 1 + 1) * 8 + (uint64_t)na * 4 + (nbins + 1) * 4 +
+               (uint64_t)sf_tiled_blocks(G) * 8 + (binned ? 0 : 16);
+    }
     const double(*A)[3] = lat;
     const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
                        A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
@@ -352,7 +419,8 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     b += (uint64_t)(G.n0 + G.n1 + G.m + (G.m + 1)) * cb;             // twiddles
     b += Nh * cb;                                                       // v_ext
     b += Nh * 3 * fsz;                                                  // G tables
-    b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;                 // phase tables
+    if (!use_large_ions(natoms))
+        b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;             // phase tables
     b += ions;                                                          // coordinates, Ewald
     b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
     b += (uint64_t)NSLOT * 4 + (uint64_t)nk * 8;                        // counts, knots
@@ -834,12 +902,106 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_ew_e));
     dfree(reinterpret_cast<void *&>(g->d_ew_f));
     dfree(reinterpret_cast<void *&>(g->d_ew_sf));
+    dfree(reinterpret_cast<void *&>(g->d_bin_start));
+    dfree(reinterpret_cast<void *&>(g->d_bin_of));
+    dfree(reinterpret_cast<void *&>(g->d_ew_part));
     dfree(g->rho);
     for (auto &p : g->opt) dfree(p);
     if (g->h_sums) (void)hipHostFree(g->h_sums);
     g->h_sums = nullptr;
     for (hipEvent_t e : g->timer.ev) (void)hipEventDestroy(e);
     g->timer.ev.clear();
+}
+
+// Large cells: v_ext(G) and the Ewald reciprocal sum from the tiled direct
+// sum, the real-space Ewald sum over bins.  fr: species-sorted fractional
+// coordinates (already on the device in d_frac).
+static ofdft_status setup_ions_large(ofdft_grid *g, const std::vector<int> &order,
+                                     const std::vector<double> &fr)
+{
+    const Geom &G = g->geom;
+    const int na = g->natoms, ns = (int)g->Z.size();
+    hipStream_t s = g->ctx->stream;
+    const LargeEwald L = large_ewald(g->lattice, G.b, g->V, na, g->n);
+    const long long nblk = sf_tiled_blocks(G);
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_part), (size_t)nblk * 8));
+    void *qbuf = nullptr;
+    if (ns > 1) {
+        HIP_TRY(hipMalloc(&qbuf, (size_t)G.Nh * 16));   // released below
+    }
+    hipError_t err = g->fp64
+        ? launch_sf_tiled<double>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V, L.e.a,
+                                  L.e.gcut2, g->vext, qbuf, g->d_ew_part, s)
+        : launch_sf_tiled<float>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V, L.e.a,
+                                 L.e.gcut2, g->vext, qbuf, g->d_ew_part, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (qbuf) (void)hipFree(qbuf);
+    HIP_TRY(err);
+    std::vector<double> part((size_t)nblk);
+    HIP_TRY(hipMemcpyAsync(part.data(), g->d_ew_part, part.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double erec = 0.0;
+    for (double x : part) erec += x;
+    erec *= 2.0 * PI / g->V;
+
+    // real space: atoms binned by fractional coordinate, positions wrapped
+    // into the cell (counting sort, atoms in bin order); a cell less than
+    // three cut-offs wide in some direction sums over images of all pairs
+    int nb0 = L.nbin[0], nb1 = L.nbin[1], nb2 = L.nbin[2];
+    const bool binned = nb0 >= 3 && nb1 >= 3 && nb2 >= 3;
+    if (!binned) nb0 = nb1 = nb2 = 1;
+    const int nbins = nb0 * nb1 * nb2;
+    std::vector<int> bin(na), start(nbins + 1, 0);
+    for (int a = 0; a < na; ++a) {
+        const double *f = &fr[3 * (size_t)a];
+        const int c0 = std::min(nb0 - 1, (int)(f[0] * nb0));
+        const int c1 = std::min(nb1 - 1, (int)(f[1] * nb1));
+        const int c2 = std::min(nb2 - 1, (int)(f[2] * nb2));
+        bin[a] = (c0 * nb1 + c1) * nb2 + c2;
+        start[bin[a] + 1]++;
+    }
+    for (int k = 0; k < nbins; ++k) start[k + 1] += start[k];
+    std::vector<int> fill(start.begin(), start.end() - 1), bin_of(na);
+    std::vector<double> pos(3 * (size_t)na), q(na);
+    double Q = 0, Q2 = 0;
+    for (int a = 0; a < na; ++a) {
+        const int slot = fill[bin[a]]++;
+        const double *f = &fr[3 * (size_t)a];
+        for (int c = 0; c < 3; ++c)
+            pos[3 * (size_t)slot + c] =
+                f[0] * g->lattice[0][c] + f[1] * g->lattice[1][c] + f[2] * g->lattice[2][c];
+        q[slot] = g->Z[g->species[order[a]]];
+        bin_of[slot] = bin[a];
+        Q += q[slot];
+        Q2 += q[slot] * q[slot];
+    }
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_pos), pos.size() * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_q), q.size() * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_e), q.size() * 8));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_bin_start), start.size() * 4));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_bin_of), bin_of.size() * 4));
+    ST_TRY(h2d(g, g->d_ew_pos, pos.data(), pos.size() * 8));
+    ST_TRY(h2d(g, g->d_ew_q, q.data(), q.size() * 8));
+    ST_TRY(h2d(g, g->d_bin_start, start.data(), start.size() * 4));
+    ST_TRY(h2d(g, g->d_bin_of, bin_of.data(), bin_of.size() * 4));
+    const int nbv[3] = {nb0, nb1, nb2};
+    if (binned) {
+        HIP_TRY(launch_ewald_real_cells(L.e, na, g->d_ew_pos, g->d_ew_q, g->d_bin_start,
+                                        g->d_bin_of, nbv, g->d_ew_e, s));
+    } else {
+        // the all-pairs kernel with an empty reciprocal box (gmax = 0: G = 0 only)
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), 16));
+        HIP_TRY(launch_ewald(L.e, na, g->d_ew_pos, g->d_ew_q, g->d_ew_sf, g->d_ew_e, nullptr, s));
+    }
+    std::vector<double> ea(na);
+    HIP_TRY(hipMemcpyAsync(ea.data(), g->d_ew_e, (size_t)na * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double ereal = 0.0;
+    for (double x : ea) ereal += x;
+    const double e_ion = ereal + erec - L.e.a / std::sqrt(PI) * Q2 -
+                         PI * Q * Q / (2 * g->V * L.e.a * L.e.a);
+    g->e_ion = (g->func.terms & OFDFT_TERM_EXT) ? e_ion : 0.0;
+    return OFDFT_OK;
 }
 
 // Ionic part of the set-up, also rerun when the atoms move (MD frames of a
@@ -873,11 +1035,14 @@ static ofdft_status setup_ions(ofdft_grid *g)
             }
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_frac), fr.size() * sizeof(double)));
         ST_TRY(h2d(g, g->d_frac, fr.data(), fr.size() * sizeof(double)));
-        const int nax[3] = {G.n0, G.n1, G.n2h};
-        double **tabs[3] = {&g->ph0, &g->ph1, &g->ph2};
-        for (int d = 0; d < 3; ++d)
-            ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]), 2 * (size_t)na * nax[d] * sizeof(double)));
-        HIP_TRY(launch_phases(G, na, g->d_frac, g->ph0, g->ph1, g->ph2, s));
+        if (!g->large_ions) {
+            const int nax[3] = {G.n0, G.n1, G.n2h};
+            double **tabs[3] = {&g->ph0, &g->ph1, &g->ph2};
+            for (int d = 0; d < 3; ++d)
+                ST_TRY(dmalloc(g, reinterpret_cast<void **>(tabs[d]),
+                               2 * (size_t)na * nax[d] * sizeof(double)));
+            HIP_TRY(launch_phases(G, na, g->d_frac, g->ph0, g->ph1, g->ph2, s));
+        }
         std::vector<int> sorted_species(na);
         for (int a = 0; a < na; ++a) sorted_species[a] = g->species[order[a]];
         g->species_order = order;
@@ -891,6 +1056,17 @@ static ofdft_status setup_ions(ofdft_grid *g)
         ST_TRY(h2d(g, g->d_rc, g->rc.data(), ns * sizeof(double)));
     }
     ST_TRY(dmalloc(g, &g->vext, (size_t)G.Nh * 2 * g->fsz));
+    if (g->large_ions) {
+        // fractional coordinates in the species order, for the bins
+        std::vector<double> frs(3 * (size_t)na);
+        for (int a = 0; a < na; ++a)
+            for (int j = 0; j < 3; ++j) {
+                double x = 0;
+                for (int i = 0; i < 3; ++i) x += g->pos[3 * g->species_order[a] + i] * g->frac[j][i];
+                frs[3 * a + j] = x - std::floor(x);
+            }
+        return setup_ions_large(g, g->species_order, frs);
+    }
     if (na > 0) {
         hipError_t e = g->fp64 ? launch_vext<double>(G, na, g->d_spec_off, ns, g->ph0, g->ph1, g->ph2,
                                                      g->d_Z, g->d_rc, g->V, g->vext, s)
@@ -1375,6 +1551,7 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
     g->ctx = ctx;
     if (const char *e = std::getenv("OFDFT_COL_TILE_MAJOR")) g->tune_col_tile_major = std::atoi(e);
+    g->large_ions = use_large_ions(cell->natoms);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);
     if (st != OFDFT_OK) {
@@ -1412,7 +1589,7 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
                              grid->func.terms, grid->func.nl_mode,
                              (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
-                             (uint64_t)grid->cap, ion_bytes(grid->lattice, grid->natoms), m);
+                             (uint64_t)grid->cap, ion_bytes(grid->lattice, grid->natoms, grid->geom), m);
     if (m.stage && !(grid->stage_in && grid->stage_out)) b -= (uint64_t)grid->geom.N * grid->fsz;
     return b;
 }
@@ -1436,7 +1613,7 @@ ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell, const ofdft_func
     m.forces = kind == OFDFT_REQ_FORCES;
     *bytes = bytes_model(G, func->precision == OFDFT_FP64 ? 8 : 4, cell->natoms, cell->nspecies,
                          func->terms, func->nl_mode, (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0,
-                         1, ion_bytes(cell->lattice, cell->natoms), m);
+                         1, ion_bytes(cell->lattice, cell->natoms, G), m);
     return OFDFT_OK;
 }
 
@@ -1526,6 +1703,9 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     HIP_TRY(hipSetDevice(grid->ctx->device));
     const int na = grid->natoms;
     if (na == 0) return OFDFT_OK;
+    if (grid->large_ions)
+        return fail(OFDFT_EINVAL, "forces are available for cells below " +
+                                      std::to_string(LARGE_IONS) + " atoms");
     ofdft_grid *g = grid;
     hipStream_t s = g->ctx->stream;
     ST_TRY(reserve(g, 1));

@@ -206,6 +206,21 @@ __host__ __device__ inline long long ewald_gbox_count(const EwaldGeom &e)
 hipError_t launch_ewald(const EwaldGeom &e, int natoms, const double *pos, const double *q,
                         double *sf, double *e_atom, double *f, hipStream_t s);
 
+// Large cells: tiled structure-factor direct sum writing v_ext(G) and one
+// Ewald reciprocal partial per block (sf_tiled_blocks of them; ew_part may be
+// null), from species-sorted fractional coordinates; and the real-space Ewald
+// sum over a bin list (nc[d] >= 3 bins per direction, each >= rcut wide).
+long long sf_tiled_blocks(const Geom &g);
+// qbuf: Nh complex FP64 scratch, needed when nspecies > 1
+template <typename T>
+hipError_t launch_sf_tiled(const Geom &g, const int *spec_off, int nspecies, const double *frac,
+                           const double *Z, const double *rc, double volume, double ew_a,
+                           double ew_gcut2, void *vext, void *qbuf, double *ew_part,
+                           hipStream_t s);
+hipError_t launch_ewald_real_cells(const EwaldGeom &e, int natoms, const double *pos,
+                                   const double *q, const int *bin_start, const int *bin_of,
+                                   const int nc[3], double *e_atom, hipStream_t s);
+
 // vector kernels (optimizer): up to 4 dot products into part slots
 template <typename T>
 hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,

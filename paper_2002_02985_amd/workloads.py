@@ -271,3 +271,18 @@ def config_c4(nreq=512, seed=4242, ntraj=64, min_atoms=13, max_atoms=561, grids=
         out.append({"cell_id": t, "kind": kind, "cell": cell, "rho": rho, "frame": frames[t]})
         frames[t] += 1
     return out
+
+
+def config_c5(n=(1024, 1024, 1024), jitter=0.0, seed=5, subsample=1):
+    """fcc Al 63^3 conventional cells (1,000,188 atoms, a = 482 Bohr) on a
+    1024^3 grid, perfect lattice unless jitter > 0; the starting density is
+    uniform (N_e / V) and is not built here (8 GiB as doubles).  subsample
+    keeps every k-th atom with the electron count scaled to match (a cheaper
+    stand-in of the same cell, for sizing the set-up)."""
+    cell = al_fcc_cell(63, n, jitter=jitter, seed=seed)
+    if subsample > 1:
+        keep = np.arange(0, len(cell["species"]), subsample)
+        cell["pos"] = cell["pos"][keep]
+        cell["species"] = cell["species"][keep]
+        cell["nelec"] = AL["Z"] * len(keep)
+    return cell

@@ -63,7 +63,9 @@ def compare(e_gpu, v_gpu, ro, rho, natoms, fp64, label=""):
 
 
 # ------------------------------------------------------------------ FFT
-FFT_SHAPES = [(12, 18, 16), (24, 16, 12), (6, 4, 4), (32, 32, 32), (18, 27, 54), (96, 96, 96)]
+FFT_SHAPES = [(12, 18, 16), (24, 16, 12), (6, 4, 4), (32, 32, 32), (18, 27, 54), (96, 96, 96),
+              # the 1024-point transforms of the 1024^3 cell on each axis
+              (1024, 4, 8), (6, 1024, 4), (8, 6, 1024)]
 
 
 @pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
@@ -260,3 +262,33 @@ def test_spline_s3s4_optimisation_reaches_the_euler_solution():
     assert e.resid_norm < 1e-6
     assert abs(e.e_total - r.e.e_total) < 1e-9
     assert abs(e.nelec_int - cell["nelec"]) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+@pytest.mark.parametrize("which", ["c2", "c3"])
+def test_large_cell_ionic_path_matches(which, prec, monkeypatch):
+    """The tiled structure factor and the binned Ewald sum (used from 8192
+    atoms on) against the phase-table direct sum and the all-pairs Ewald sum
+    on the same cell."""
+    if which == "c2":   # bins for the real-space sum (three cut-offs fit across)
+        cell, dens = W.config_c2((96, 96, 96), 1)
+        rho = dens[0]
+    else:               # narrower than three cut-offs: images of all pairs
+        cell = W.mg_hcp_slab((6, 4, 9), (96, 96, 144), vacuum=15.0, jitter=0.05, seed=7)
+        rho = W.gaussian_density(cell, sigma=1.5, floor=1e-12)
+    res = {}
+    for large in ("0", "1"):
+        monkeypatch.setenv("OFDFT_LARGE_IONS", large)
+        with ofdft.Grid(cell, LOCAL, precision=prec) as g:
+            e, v = g.energy_potential(rho)
+            res[large] = (e.as_dict(), v, ofdft.ofdft_grid_device_bytes(g.handle))
+    e0, v0, b0 = res["0"]
+    e1, v1, b1 = res["1"]
+    print("%s prec %d: e_ext %.3e e_ion %.3e dv %.3e" % (
+        which, prec, e1["e_ext"] - e0["e_ext"], e1["e_ion"] - e0["e_ion"],
+        float(np.abs(v1 - v0).max())), flush=True)
+    tol = 1e-10 if prec == ofdft.FP64 else 1e-5 * len(cell["species"])
+    assert abs(e1["e_ion"] - e0["e_ion"]) <= 1e-10 * abs(e0["e_ion"])
+    assert abs(e1["e_ext"] - e0["e_ext"]) <= tol * (abs(e0["e_ext"]) if prec == ofdft.FP64 else 1)
+    assert float(np.abs(v1 - v0).max()) <= (1e-9 if prec == ofdft.FP64 else 1e-4)
+    assert b1 < b0   # no per-atom phase tables
