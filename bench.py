@@ -514,6 +514,7 @@ def c5_main(args):
         t1 = time.perf_counter()
         iters = evals = 0
         best = float("inf")
+        stale = 0
         r = None
         while time.perf_counter() - t1 < args.c5_budget:
             r, st = g.optimize(tol=1e-6, max_iter=20, allow_noconv=True, method=ofdft.OPT_PCG)
@@ -521,9 +522,13 @@ def c5_main(args):
             evals += r.evals
             log("mixed: %d iterations, %d evaluations, resid %.3e, E %.8f, %.1f s" %
                 (iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t1))
-            if st == ofdft.OK or r.iters == 0 or r.final_resid > 0.9 * best:
+            if st == ofdft.OK or r.iters == 0:
                 break
+            # the FP32 floor: three chunks without a 10% better residual
+            stale = stale + 1 if r.final_resid > 0.9 * best else 0
             best = min(best, r.final_resid)
+            if stale >= 3:
+                break
         out["optimize"] = {"mixed": {"iters": iters, "evals": evals, "final_resid": r.final_resid,
                                      "e_total": r.e.e_total,
                                      "wall_s": round(time.perf_counter() - t1, 1),

@@ -203,9 +203,11 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host);
  * OFDFT_ENOCONV (with the result filled in) when max_iter is reached. */
 enum {
     OFDFT_OPT_CG = 0,   /* Polak-Ribiere+ on the residual R                          */
-    OFDFT_OPT_PCG = 1   /* the same on z = K R, K(G) = 1 / (1 + G^2): a reciprocal-space
-                           preconditioner for the -grad^2 of the vW term (two extra
-                           transforms per iteration)                                  */
+    OFDFT_OPT_PCG = 1   /* the same on z = K R with the reciprocal-space preconditioner
+                           K(G) = 1 / (1 + G^2 + 16 pi rho0 / G^2), rho0 = N_e / V, the
+                           inverse of the phi-Hessian's vW (G^2) and long-wavelength
+                           Hartree (16 pi rho0 / G^2) parts plus a unit shift; K(0) = 1
+                           (two extra transforms per iteration)                       */
 };
 typedef struct {
     double tol;

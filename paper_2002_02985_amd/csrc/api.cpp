@@ -515,6 +515,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.lambda_vw = g->func.lambda_vw;
     a.kf_wt = g->kf_wt;
     a.precond_q2 = g->precond_q2;
+    a.precond_h = 16.0 * PI * g->nelec / g->V;
     int L;
     if (axis == 1) {
         L = G.n1;

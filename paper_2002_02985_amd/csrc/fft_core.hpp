@@ -162,7 +162,9 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
     // an opaque copy of the thread index: the index arithmetic of this stage
     // is recomputed here instead of being hoisted out of callers' loops and
     // held in registers across the whole kernel
+#ifndef OFDFT_STAGE_HOIST
     asm volatile("" : "+v"(tid));
+#endif
     // unsigned index arithmetic: divisions by the compile-time P and NS
     // become multiply-high and shifts without sign fix-ups
     const unsigned ut = (unsigned)tid;

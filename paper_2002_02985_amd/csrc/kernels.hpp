@@ -29,8 +29,8 @@ enum Slot {
 // field kinds of the forward (prologue) kernel
 enum FieldKind { FK_RHO = 0, FK_PHI = 1, FK_RHOB = 2, FK_RAW = 3, FK_KNOT = 4 };
 // reciprocal-space operations of the axis-0 kernel
-// GO_PRECOND: multiply by q0^2 / (G^2 + q0^2) (q0^2 = ColArgs.precond_q2), the
-// optimiser's reciprocal-space preconditioner
+// GO_PRECOND: multiply by q0^2 / (G^2 + q0^2 + h / G^2) (q0^2 = precond_q2,
+// h = precond_h; 1 at G = 0), the optimiser's reciprocal-space preconditioner
 enum GOp { GO_NONE = 0, GO_HEXT = 1, GO_VW = 2, GO_WT = 3, GO_SCALE = 4, GO_PRECOND = 5 };
 // epilogues of the inverse row kernel
 enum EpiMode { EP_STORE = 0, EP_COMBINE = 1, EP_KNOTS = 2 };
@@ -91,7 +91,7 @@ struct ColArgs {
     int use_h, use_ext;
     double lambda_vw;
     double kf_wt;               // GO_WT kernel Fermi wavevector
-    double precond_q2;          // GO_PRECOND
+    double precond_q2, precond_h;   // GO_PRECOND
     double *part;
     int pstride;
     const void *tw;             // W_L^n

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
             } else if (op == GO_PRECOND) {
                 const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
                 const T q2 = T(a.precond_q2);
-                o = cscale(F, q2 / (G2 + q2));
+                o = G2 > T(0) ? cscale(F, q2 / (G2 + q2 + T(a.precond_h) / G2)) : F;
             } else {  // GO_SCALE
                 o = F;
             }
@@ -826,7 +826,10 @@ template <int N1> constexpr int plane_A() { return (N1 % 2 == 0) ? N1 + 1 : N1; 
 template <int N1, int M> constexpr int plane_NT() { return 1024; }
 // minimum resident waves per SIMD the compiler must allow: two 1024-thread
 // blocks per CU for FP32 (64 VGPRs), one for FP64
-template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? 8 : 4; }
+#ifndef OFDFT_PLANE_MINW_F32
+#define OFDFT_PLANE_MINW_F32 8
+#endif
+template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? OFDFT_PLANE_MINW_F32 : 4; }
 template <typename T, int N1, int M> constexpr bool plane_fits()
 {
     // both kernels also stage the input plane (N1 x 2M reals) and the
