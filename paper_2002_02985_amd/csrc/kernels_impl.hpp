@@ -328,6 +328,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     static_assert(NT % P == 0, "tile width must divide the block");
     __shared__ cpx<T> buf[L * P];
+    __shared__ cpx<T> tws[L];     // W_L^n, read by every stage
     __shared__ double red[NT];
     const int tid = threadIdx.x;
     const int fb = a.tile_major ? (int)(blockIdx.x % (unsigned)nfb)
@@ -340,11 +341,12 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
     const long long cbase = cvalid ? (c / a.inner) * a.outer_stride + (c % a.inner) : 0;
     const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
     cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
-    const cpx<T> *tw = (const cpx<T> *)a.tw;
+    const cpx<T> *tw = tws;
     const int field = fb / a.nbatch;
     const int b = fb % a.nbatch;
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
 
+    for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
     for (int n = tid / P; n < L; n += RSTEP)
         buf[n * P + p] = cvalid ? src[cbase + n * a.elem_stride] : cpx<T>{T(0), T(0)};
     // reciprocal-space operands are fetched now so that their latency overlaps
@@ -446,6 +448,7 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     __shared__ cpx<T> buf[L * P];
+    __shared__ cpx<T> tws[L];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const int p = tid % P;
@@ -454,7 +457,8 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
     const Geom &g = a.g;
     const long long es = (long long)g.n1 * g.n2h;
     const cpx<T> *src = (const cpx<T> *)a.src + b * a.fstride;
-    const cpx<T> *tw = (const cpx<T> *)a.tw;
+    for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
+    const cpx<T> *tw = tws;
     const int i1 = cvalid ? (int)(c / g.n2h) : 0;
     const int k2 = cvalid ? (int)(c % g.n2h) : 0;
     const int m1 = freq(i1, g.n1);
@@ -1155,9 +1159,11 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     }
     else {
 
-    // EP_COMBINE, one field at a time into v and g.  The input plane is kept
-    // in LDS (xs) rather than in registers, so that a thread carries only its
-    // v and g accumulators through the transforms.
+    // EP_COMBINE.  The fields come back from reciprocal space one at a time;
+    // a thread keeps the raw values of all but the last in registers (at
+    // most two fields: WT and the EXACT spline field are exclusive) and
+    // forms v and g once, after the last inverse, so that the per-point
+    // powers of rho are evaluated once.  The input plane is kept in LDS (xs).
     cpx<T> *xs = (cpx<T> *)xsbuf;
 #pragma unroll
     for (int q = 0; q < PER; ++q)
@@ -1166,10 +1172,6 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     const T alpha = T(a.alpha);
     const T floor_rho = T(a.floor);
     const T lfloor = d_log2(floor_rho);
-    cpx<T> vacc[PER], gacc[PER];
-    double snl = 0.0;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) vacc[q] = gacc[q] = {T(0), T(0)};
     // point quantities from the input value
     auto point = [&](T xv, T &phi, T &rho, T &sgn, T &lu, T &lr) {
         if (a.in_is_phi) {
@@ -1183,96 +1185,111 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
         lr = rho >= floor_rho ? lu : lfloor;
     };
-    const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+    // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
+    // A are exclusive and come last, so only H+ext and vW are ever held
+    const int all[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+    int last = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (all[k] >= 0) last = k;
+    cpx<T> fh[PER], fv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) fh[q] = fv[q] = {T(0), T(0)};
 #pragma unroll 1
-    for (int s = 0; s < 4; ++s) {
+    for (int k = 0; k < 4; ++k) {
+        if (all[k] < 0) continue;
         const int t = opaque(tid);
-        if (flds[s] < 0) continue;
-        plane_inverse<T, N1, M, NTP>(buf, spec_of(flds[s]), tw1, twM, twN, t);
+        plane_inverse<T, N1, M, NTP>(buf, spec_of(all[k]), tw1, twM, twN, t);
+        if (k == last) break;   // the last field stays in buf
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (t + q * NTP >= PAIRS) continue;
             const cpx<T> z = buf[at(t, q)];
-            const cpx<T> xq = xs[t + q * NTP];
-            const T zv[2] = {z.x, z.y};
-            const T xv[2] = {xq.x, xq.y};
-            T dv[2], dg[2];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                T phi, rho, sgn, lu, lr;
-                point(xv[c], phi, rho, sgn, lu, lr);
-                const T f = zv[c];
-                if (s == 0) {                      // v_H + v_ext
-                    dv[c] = f;
-                    dg[c] = T(2) * phi * f;
-                } else if (s == 1) {               // -lambda nabla^2 phi
-                    dv[c] = T(0.5) * f * sgn * d_exp2(T(-0.5) * lr);
-                    dg[c] = f;
-                } else if (s == 2) {               // Wang-Teter Phi
-                    dv[c] = T(2) * alpha * d_exp2((alpha - T(1)) * lr) * f;
-                    dg[c] = T(4) * alpha * sgn * d_exp2((alpha - T(0.5)) * lu) * f;
-                    snl += (double)(d_exp2(alpha * lu) * f);
-                } else {                           // EXACT: F^-1[sum_i omega_i F[rho^a L_i]]
-                    dv[c] = alpha * d_exp2((alpha - T(1)) * lr) * f;
-                    dg[c] = T(2) * alpha * sgn * d_exp2((alpha - T(0.5)) * lu) * f;
-                }
-            }
-            vacc[q].x += dv[0];
-            vacc[q].y += dv[1];
-            gacc[q].x += dg[0];
-            gacc[q].y += dg[1];
+            if (k == 0) fh[q] = z;
+            else fv[q] = z;
         }
         __syncthreads();
     }
+    const bool has_h = a.fld_hext >= 0, has_vw = a.fld_vw >= 0, has_wt = a.fld_wt >= 0,
+               has_a = a.fld_a >= 0;
+    const bool need_a = a.spline || has_wt || has_a;
     const cpx<T> *acc1 = a.spline ? (const cpx<T> *)((const T *)a.acc1 + real_off) : nullptr;
     const cpx<T> *acc2 = (a.spline && a.exact) ? (const cpx<T> *)((const T *)a.acc2 + real_off)
                                                 : nullptr;
     cpx<T> *vout = a.v_out ? (cpx<T> *)((T *)a.v_out + real_off) : nullptr;
     cpx<T> *gout = a.g_out ? (cpx<T> *)((T *)a.g_out + real_off) : nullptr;
-    double sums[4] = {snl, 0.0, 0.0, 0.0};
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    const int t = opaque(tid);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int idx = tid + q * NTP;
+        const int idx = t + q * NTP;
         if (idx >= PAIRS) continue;
         cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
         if (acc1) s1 = acc1[idx];
         if (acc2) s2 = acc2[idx];
         const cpx<T> xq = xs[idx];
+        const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
+        const cpx<T> zh = last == 0 ? zl : fh[q];
+        const cpx<T> zv = last == 1 ? zl : fv[q];
         const T xv[2] = {xq.x, xq.y};
         const T s1v[2] = {s1.x, s1.y}, s2v[2] = {s2.x, s2.y};
-        T vv[2] = {vacc[q].x, vacc[q].y};
-        T gg[2] = {gacc[q].x, gacc[q].y};
+        const T hv[2] = {zh.x, zh.y}, wv[2] = {zv.x, zv.y}, lv[2] = {zl.x, zl.y};
+        T vout2[2], gout2[2];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             T phi, rho, sgn, lu, lr;
             point(xv[c], phi, rho, sgn, lu, lr);
+            // each power of rho evaluated once per point
+            T ra = T(0), ra1 = T(0), fa_ = T(0);
+            if (need_a) {
+                ra = d_exp2(alpha * lu);                   // rho^a
+                ra1 = d_exp2((alpha - T(1)) * lr);         // rho_s^(a-1)
+                fa_ = sgn * d_exp2((alpha - T(0.5)) * lu); // phi rho^(a-1)
+            }
+            T vv = T(0), gg = T(0);
+            if (has_h) {                               // v_H + v_ext
+                vv += hv[c];
+                gg += T(2) * phi * hv[c];
+            }
+            if (has_vw) {                              // -lambda nabla^2 phi
+                vv += T(0.5) * wv[c] * sgn * d_exp2(T(-0.5) * lr);
+                gg += wv[c];
+            }
+            if (has_wt) {                              // Wang-Teter Phi
+                vv += T(2) * alpha * ra1 * lv[c];
+                gg += T(4) * alpha * fa_ * lv[c];
+                sums[0] += (double)(ra * lv[c]);
+            }
+            if (has_a) {                               // EXACT: F^-1[sum_i omega_i F[rho^a L_i]]
+                vv += alpha * ra1 * lv[c];
+                gg += T(2) * alpha * fa_ * lv[c];
+            }
             if (a.use_tf) {
                 const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
-                vv[c] += vt;
-                gg[c] += T(2) * phi * vt;
+                vv += vt;
+                gg += T(2) * phi * vt;
             }
             if (a.spline) {
-                const T ra1 = d_exp2((alpha - T(1)) * lr);
-                const T ra = d_exp2(alpha * lu);
-                const T fa_ = sgn * d_exp2((alpha - T(0.5)) * lu);
                 sums[0] += (double)(ra * s1v[c]);
                 if (!a.exact) {
-                    vv[c] += T(2) * alpha * ra1 * s1v[c];
-                    gg[c] += T(4) * alpha * fa_ * s1v[c];
+                    vv += T(2) * alpha * ra1 * s1v[c];
+                    gg += T(4) * alpha * fa_ * s1v[c];
                 } else {
                     const T kf = kf_from_log2(lu);
                     const bool inside = kf > T(a.knots.k[0]) && kf < T(a.knots.k[a.knots.nk - 1]);
                     const T dk = inside ? kf * T(1.0 / 3.0) : T(0);
-                    vv[c] += alpha * ra1 * s1v[c] + ra * dk * d_exp2(-lr) * s2v[c];
-                    gg[c] += T(2) * (alpha * fa_ * s1v[c] + fa_ * dk * s2v[c]);
+                    vv += alpha * ra1 * s1v[c] + ra * dk * d_exp2(-lr) * s2v[c];
+                    gg += T(2) * (alpha * fa_ * s1v[c] + fa_ * dk * s2v[c]);
                 }
             }
-            sums[1] += (double)gg[c] * (double)phi;
-            sums[2] += (double)gg[c] * (double)gg[c];
+            sums[1] += (double)gg * (double)phi;
+            sums[2] += (double)gg * (double)gg;
             sums[3] += (double)phi * (double)phi;
+            vout2[c] = vv;
+            gout2[c] = gg;
         }
-        if (vout) vout[idx] = {vv[0], vv[1]};
-        if (gout) gout[idx] = {gg[0], gg[1]};
+        if (vout) vout[idx] = {vout2[0], vout2[1]};
+        if (gout) gout[idx] = {gout2[0], gout2[1]};
     }
     block_sums<NTP, 4>(sums, red, tid);
     if (tid == 0) {
