@@ -1,5 +1,5 @@
-// Device-side FFT building blocks for gfx950: radix-2/3/4/8 butterflies in
-// registers and Stockham autosort stages on pencils staged in LDS.
+// Device-side FFT building blocks for gfx950: radix-2/3/4/6/8/12 butterflies
+// in registers and Stockham autosort stages on pencils staged in LDS.
 //
 // Every reciprocal-space term of the orbital-free energy (Hartree, the
 // von Weizsaecker Laplacian, the nonlocal kernels of eqs. "nl2"/"WT" and the
@@ -50,22 +50,40 @@ struct Plan {
     int r[16];
 };
 
-// radices for a length-L transform: as many 8s as possible (an 8*2 tail is
-// rewritten as 4*4), then 4 or 2, then 3s.
+// Radices for a length-L transform: the fewest Stockham stages (each stage is
+// an LDS round trip and a barrier) over the register butterflies 12, 8, 6,
+// 4, 3, 2; among those, the largest smallest radix (4*4 rather than 8*2);
+// then larger radices first.  Score = stages * 16 - smallest radix.
+constexpr int plan_score(int L, int minr)
+{
+    if (L == 1) return -minr;
+    int best = 1 << 20;
+    const int rs[6] = {12, 8, 6, 4, 3, 2};
+    for (int i = 0; i < 6; ++i)
+        if (L % rs[i] == 0) {
+            const int s = 16 + plan_score(L / rs[i], rs[i] < minr ? rs[i] : minr);
+            if (s < best) best = s;
+        }
+    return best;
+}
+
 constexpr Plan make_plan(int L)
 {
     Plan p{0, {}};
-    int m = L;
-    int twos = 0;
-    while (m % 2 == 0) { m /= 2; ++twos; }
-    int threes = 0;
-    while (m % 3 == 0) { m /= 3; ++threes; }
-    int e8 = twos / 3, rem = twos % 3;
-    if (rem == 1 && e8 > 0) { --e8; p.r[p.n++] = 4; p.r[p.n++] = 4; rem = 0; }
-    for (int i = 0; i < e8; ++i) p.r[p.n++] = 8;
-    if (rem == 2) p.r[p.n++] = 4;
-    if (rem == 1) p.r[p.n++] = 2;
-    for (int i = 0; i < threes; ++i) p.r[p.n++] = 3;
+    int m = L, minr = 64;
+    const int rs[6] = {12, 8, 6, 4, 3, 2};
+    while (m > 1) {
+        const int need = plan_score(m, minr);
+        int pick = 0;
+        for (int i = 0; i < 6 && !pick; ++i)
+            if (m % rs[i] == 0 &&
+                16 + plan_score(m / rs[i], rs[i] < minr ? rs[i] : minr) == need)
+                pick = rs[i];
+        if (!pick) break;
+        p.r[p.n++] = pick;
+        if (pick < minr) minr = pick;
+        m /= pick;
+    }
     return p;
 }
 
@@ -107,6 +125,40 @@ __device__ __forceinline__ void dft(cpx<T> *a)
         a[2] = csub(t0, t2);
         a[1] = cadd(t1, t3);
         a[3] = csub(t1, t3);
+    } else if constexpr (R == 6) {
+        // prime-factor algorithm, 6 = 2 x 3: no internal twiddles.
+        // input n = (3 n1 + 2 n2) mod 6, output k = (3 k1 + 4 k2) mod 6
+        cpx<T> y[3][2];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 2; ++n1) y[n2][n1] = a[(3 * n1 + 2 * n2) % 6];
+            dft<T, 2, INV>(y[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 2; ++k1) {
+            cpx<T> z[3] = {y[0][k1], y[1][k1], y[2][k1]};
+            dft<T, 3, INV>(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) a[(3 * k1 + 4 * k2) % 6] = z[k2];
+        }
+    } else if constexpr (R == 12) {
+        // prime-factor algorithm, 12 = 4 x 3: no internal twiddles.
+        // input n = (3 n1 + 4 n2) mod 12, output k = (9 k1 + 4 k2) mod 12
+        cpx<T> y[3][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = a[(3 * n1 + 4 * n2) % 12];
+            dft<T, 4, INV>(y[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cpx<T> z[3] = {y[0][k1], y[1][k1], y[2][k1]};
+            dft<T, 3, INV>(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) a[(9 * k1 + 4 * k2) % 12] = z[k2];
+        }
     } else if constexpr (R == 8) {
         const T r2 = T(0.70710678118654752440084436210485);
         cpx<T> e[4] = {a[0], a[2], a[4], a[6]};
