@@ -1,4 +1,4 @@
-// Device-side FFT building blocks for gfx950: radix-2/3/4/6/8/12 butterflies
+// Device-side FFT building blocks for gfx950: radix-2/3/4/6/8/12/16 butterflies
 // in registers and Stockham autosort stages on pencils staged in LDS.
 //
 // Every reciprocal-space term of the orbital-free energy (Hartree, the
@@ -51,33 +51,35 @@ struct Plan {
 };
 
 // Radices for a length-L transform: the fewest Stockham stages (each stage is
-// an LDS round trip and a barrier) over the register butterflies 12, 8, 6,
-// 4, 3, 2; among those, the largest smallest radix (4*4 rather than 8*2);
+// an LDS round trip and a barrier) over the register butterflies 16, 12, 8,
+// 6, 4, 3, 2; among those, the largest smallest radix (4*4 rather than 8*2);
 // then larger radices first.  Score = stages * 16 - smallest radix.
-constexpr int plan_score(int L, int minr)
+// Radix 16 holds 32 values per butterfly: used for FP32 only (in FP64 its
+// register footprint costs more than the saved stage).
+constexpr int plan_score(int L, int minr, bool r16)
 {
     if (L == 1) return -minr;
     int best = 1 << 20;
-    const int rs[6] = {12, 8, 6, 4, 3, 2};
-    for (int i = 0; i < 6; ++i)
+    const int rs[7] = {16, 12, 8, 6, 4, 3, 2};
+    for (int i = r16 ? 0 : 1; i < 7; ++i)
         if (L % rs[i] == 0) {
-            const int s = 16 + plan_score(L / rs[i], rs[i] < minr ? rs[i] : minr);
+            const int s = 16 + plan_score(L / rs[i], rs[i] < minr ? rs[i] : minr, r16);
             if (s < best) best = s;
         }
     return best;
 }
 
-constexpr Plan make_plan(int L)
+constexpr Plan make_plan(int L, bool r16 = false)
 {
     Plan p{0, {}};
     int m = L, minr = 64;
-    const int rs[6] = {12, 8, 6, 4, 3, 2};
+    const int rs[7] = {16, 12, 8, 6, 4, 3, 2};
     while (m > 1) {
-        const int need = plan_score(m, minr);
+        const int need = plan_score(m, minr, r16);
         int pick = 0;
-        for (int i = 0; i < 6 && !pick; ++i)
+        for (int i = r16 ? 0 : 1; i < 7 && !pick; ++i)
             if (m % rs[i] == 0 &&
-                16 + plan_score(m / rs[i], rs[i] < minr ? rs[i] : minr) == need)
+                16 + plan_score(m / rs[i], rs[i] < minr ? rs[i] : minr, r16) == need)
                 pick = rs[i];
         if (!pick) break;
         p.r[p.n++] = pick;
@@ -158,6 +160,43 @@ __device__ __forceinline__ void dft(cpx<T> *a)
             dft<T, 3, INV>(z);
 #pragma unroll
             for (int k2 = 0; k2 < 3; ++k2) a[(9 * k1 + 4 * k2) % 12] = z[k2];
+        }
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4 Cooley-Tukey: DFT4 over n1 of x[4 n1 + n2], the twiddle
+        // W16^(n2 k1), DFT4 over n2; output k = k1 + 4 k2
+        constexpr double C1 = 0.92387953251128675613;   // cos(pi/8)
+        constexpr double S1 = 0.38268343236508977173;   // sin(pi/8)
+        constexpr double R2 = 0.70710678118654752440;
+        cpx<T> y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = a[4 * n1 + n2];
+            dft<T, 4, INV>(y[n2]);
+        }
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) {
+                const int m = n2 * k1;   // 1..9
+                // W16^m = cos(2 pi m/16) -/+ i sin(2 pi m/16)
+                const double cr = m == 1 ? C1 : m == 2 ? R2 : m == 3 ? S1 : m == 4 ? 0.0
+                                : m == 6 ? -R2 : m == 9 ? -C1 : 0.0;
+                const double si = m == 1 ? S1 : m == 2 ? R2 : m == 3 ? C1 : m == 4 ? 1.0
+                                : m == 6 ? R2 : m == 9 ? -S1 : 0.0;
+                if (m == 4) {
+                    y[n2][k1] = mul_mi<T, INV>(y[n2][k1]);
+                } else {
+                    const cpx<T> w = {T(cr), INV ? T(si) : T(-si)};
+                    y[n2][k1] = cmul(y[n2][k1], w);
+                }
+            }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cpx<T> z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            dft<T, 4, INV>(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = z[k2];
         }
     } else if constexpr (R == 8) {
         const T r2 = T(0.70710678118654752440084436210485);
@@ -262,7 +301,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
 template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS>
 __device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
-    constexpr Plan pl = make_plan(L);
+    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
     if constexpr (S < pl.n) {
         constexpr int R = pl.r[S];
         stockham_stage<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid);
