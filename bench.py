@@ -117,6 +117,8 @@ def parse():
                     help="densities evaluated by the oracle for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch schedule instead of autotuning it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -173,7 +175,7 @@ def pass_bytes(name, nb, N, Nh, nfields, w):
     return 0
 
 
-def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile):
+def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, tune=True):
     terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
              ofdft.TERM_WT)
     dt = torch.float64 if precision == ofdft.FP64 else torch.float32
@@ -185,6 +187,10 @@ def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile):
     v = torch.empty_like(x)
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
+    tuning = None
+    if tune:
+        # the library's autotuner picks the launch schedule on this batch
+        tuning = ofdft.ofdft_grid_tune_dev(g.handle, NDENS, x.data_ptr(), sh)
     for _ in range(warmup):
         es = ofdft.ofdft_energy_potential_batch_dev(g.handle, NDENS, x.data_ptr(), v.data_ptr(), sh)
     torch.cuda.synchronize()
@@ -217,7 +223,7 @@ def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile):
     del x, v
     torch.cuda.empty_cache()
     return {"wall": wall, "gpu_ms": gpu_ms, "lat": lat, "energies": energies, "passes": passes,
-            "dev_bytes": dev_bytes}
+            "dev_bytes": dev_bytes, "tuning": tuning}
 
 
 def cpu_baseline(cell, dens, nsample):
@@ -616,12 +622,13 @@ def main():
     Nh = N_GRID[0] * N_GRID[1] * (N_GRID[2] // 2 + 1)
 
     log("mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    mixed = run_gpu_batch(ofdft, torch, cell, dens, ofdft.MIXED, args.steps, args.warmup, True)
+    mixed = run_gpu_batch(ofdft, torch, cell, dens, ofdft.MIXED, args.steps, args.warmup, True,
+                          not args.no_tune)
     fp64 = None
     if not args.no_fp64:
         log("fp64 path")
         fp64 = run_gpu_batch(ofdft, torch, cell, dens, ofdft.FP64, max(3, args.steps // 2),
-                             args.warmup, True)
+                             args.warmup, True, not args.no_tune)
 
     ms_step = mixed["wall"] * 1e3 / args.steps
     value = NDENS * N / (ms_step * 1e-3) / 1e9
@@ -637,8 +644,12 @@ def main():
     avg_ms = ms / n
     nbytes = pass_bytes(name, NDENS, N, Nh, nfields, 4)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    kname = {"row_fwd": "k_plane_fwd<float, 96, 48>", "row_inv": "k_plane_inv<float, 96, 48, 1>",
-             "col0_g": "k_col<float, 96>"}.get(name)
+    plane = mixed["tuning"] is None or mixed["tuning"]["plane"]
+    kname = ({"row_fwd": "k_plane_fwd<float, 96, 48>", "row_inv": "k_plane_inv<float, 96, 48, 1>",
+              "col0_g": "k_col<float, 96>"} if plane else
+             {"row_fwd": "k_row_fwd<float, 48>", "row_inv": "k_row_inv<float, 48>",
+              "col0_g": "k_col<float, 96>", "col1_fwd": "k_col<float, 96>",
+              "col1_inv": "k_col<float, 96>"}).get(name)
     traffic = measured_traffic(kname) if kname else None
     roof = {"bound": "hbm", "kernel": kname or name, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -673,6 +684,7 @@ def main():
                        "per_density_p50": round(float(np.percentile(lat, 50)) / NDENS, 4)},
         "passes": passes_out,
         "device_bytes": mixed["dev_bytes"],
+        "tuning": mixed["tuning"],
         "roofline": roof,
     }
     if fp64 is not None:

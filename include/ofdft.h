@@ -296,6 +296,27 @@ ofdft_status ofdft_serve_cancel(ofdft_server *srv, uint64_t ticket);
 ofdft_status ofdft_serve_stats_get(ofdft_server *srv, ofdft_serve_stats *out);
 void ofdft_server_destroy(ofdft_server *srv);
 
+/* Launch schedule.  An evaluation's launch sequence can be replayed from a HIP
+ * graph captured on first use for each argument set (batch size, input,
+ * outputs); at most 8 graphs are kept per grid, and they are dropped when the
+ * grid's workspace is reallocated.  Graphs need a capturable stream (not the
+ * legacy NULL stream) and are not used while per-pass timing is on.
+ * The autotuner times the schedule choices -- fused plane kernels or
+ * separate row and column passes where both apply, the block order of the
+ * column passes, the number of spline knots per batch -- on nbatch densities
+ * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
+ * density, nbatch 1), keeps the fastest for the grid and for every grid of
+ * the same shape, precision, functional and batch size created later in the
+ * process, and reports it. */
+typedef struct {
+    int32_t plane, col_tile_major, knot_batch, candidates;
+    double best_ms, default_ms;   /* per evaluation call */
+} ofdft_tune_result;
+ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
+ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
+                                 void *hip_stream, ofdft_tune_result *result);
+ofdft_status ofdft_grid_tune(ofdft_grid *grid, ofdft_tune_result *result);
+
 /* Per-pass timing of the evaluation pipeline (a profiling aid): when
  * enabled, every kernel launch of the passes below is bracketed by HIP events
  * recorded on the stream it is launched on, and the elapsed times are summed

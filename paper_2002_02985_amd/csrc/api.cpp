@@ -5,6 +5,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -79,6 +83,16 @@ struct Timer {
     long long count[NPASS] = {0};
 };
 
+// one captured evaluation: its arguments and the executable graph
+struct GraphEntry {
+    int nb = 0;
+    const void *in = nullptr;
+    int in_is_phi = 0;
+    void *v = nullptr, *gout = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last = 0;
+};
+
 struct ofdft_grid {
     ofdft_ctx *ctx = nullptr;
     // copies of the descriptors
@@ -117,7 +131,6 @@ struct ofdft_grid {
     double *part = nullptr;
     int pstride = 0;
     double *sums = nullptr;
-    int *d_count = nullptr;
     double *h_sums = nullptr;   // pinned
     // resident density and optimiser vectors (N each)
     void *rho = nullptr;
@@ -128,10 +141,16 @@ struct ofdft_grid {
     double *d_ew_pos = nullptr, *d_ew_q = nullptr, *d_ew_e = nullptr, *d_ew_f = nullptr,
            *d_ew_sf = nullptr;    // Ewald buffers
     Timer timer;
+    // tuned launch schedule (see ofdft_grid_tune)
     int tune_col_tile_major = 0;   // block order of the column passes
+    int tune_plane = 1;            // fused plane kernels where the plane fits in LDS
+    int tune_kb = MAXKB;           // knots per spline batch
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
     double precond_q2 = 1.0;                    // optimiser preconditioner q0^2
     bool large_ions = false;                    // tiled structure factor, binned Ewald
+    bool use_graphs = false;                    // replay evaluations from HIP graphs
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     int *d_bin_start = nullptr, *d_bin_of = nullptr;
     double *d_ew_part = nullptr;
 };
@@ -389,6 +408,12 @@ static void timer_collect(ofdft_grid *g)
     } while (0)
 
 // ---------------------------------------------------------------- workspace
+template <typename T>
+static bool use_plane(const ofdft_grid *g)
+{
+    return g->tune_plane && plane_supported<T>(g->geom.n1, g->geom.m);
+}
+
 static int max_pstride(const Geom &G, bool fp64)
 {
     int rb, c0, c1;
@@ -423,7 +448,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
         b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;             // phase tables
     b += ions;                                                          // coordinates, Ewald
     b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
-    b += (uint64_t)NSLOT * 4 + (uint64_t)nk * 8;                        // counts, knots
+    b += (uint64_t)nk * 8;                                              // knots
     b += N * fsz;                                                       // resident rho
     b += 4 * cap * Nh * cb;                                             // spectra
     if (terms & OFDFT_TERM_SPLINE) {
@@ -438,9 +463,17 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     return b;
 }
 
+// captured evaluations refer to the workspace: dropped when it is reallocated
+static void graphs_clear(ofdft_grid *g)
+{
+    for (auto &e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+    g->graphs.clear();
+}
+
 static ofdft_status reserve(ofdft_grid *g, int nb)
 {
     if (nb <= g->cap) return OFDFT_OK;
+    graphs_clear(g);
     // drop the old workspace
     dfree(g->spec);
     dfree(g->kspec);
@@ -540,10 +573,12 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
 }
 
 template <typename T>
-static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
-                              void *d_g, hipStream_t s, ofdft_energy *e_out, double *bad_out)
+// Enqueues every launch of one evaluation on s and the copy of the FP64 sums
+// to the pinned host array; no allocation, synchronisation or host-to-device
+// copy, so that the sequence can be captured in a HIP graph.
+static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
+                                 void *d_g, hipStream_t s)
 {
-    ST_TRY(reserve(g, nb));
     const Geom &G = g->geom;
     const Layout l = layout_of(g);
     const uint32_t terms = g->func.terms;
@@ -575,7 +610,7 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     rf.twN = g->twN;
     rf.tw1 = g->tw1;
     // grids whose (i1, k2) plane fits in LDS fuse passes 1+2 and 4+5
-    const bool plane = plane_supported<T>(G.n1, G.m);
+    const bool plane = use_plane<T>(g);
     int nb_row = 0;
     if (plane) TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nb_row, s));
     else TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
@@ -597,8 +632,9 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     // spline loop over knot batches (steps s2-s4)
     if (spline) {
         const int nk = g->knots.nk;
-        for (int k0 = 0; k0 < nk; k0 += MAXKB) {
-            const int K = std::min(MAXKB, nk - k0);
+        const int kb = std::max(1, std::min(MAXKB, g->tune_kb));
+        for (int k0 = 0; k0 < nk; k0 += kb) {
+            const int K = std::min(kb, nk - k0);
             KnotArgs ka;
             std::memset(&ka, 0, sizeof(ka));
             ka.src = slot_ptr(l.s_rhob);
@@ -705,15 +741,75 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     else TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));
 
     // 6. fixed-order FP64 sums
-    int cnt[NSLOT] = {0};
-    cnt[SL_RHO] = cnt[SL_TF] = cnt[SL_BAD] = nb_row;
-    cnt[SL_H] = cnt[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
-    cnt[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
-    cnt[SL_NL] = cnt[SL_GPHI] = cnt[SL_GG] = cnt[SL_PHIPHI] = nb_inv;
-    HIP_TRY(hipMemcpyAsync(g->d_count, cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
-    TIMED(PS_FINALIZE, launch_finalize(g->part, g->pstride, g->d_count, nb, g->sums, s));
+    SlotCounts cnt;
+    std::memset(&cnt, 0, sizeof(cnt));
+    cnt.n[SL_RHO] = cnt.n[SL_TF] = cnt.n[SL_BAD] = nb_row;
+    cnt.n[SL_H] = cnt.n[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
+    cnt.n[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
+    cnt.n[SL_NL] = cnt.n[SL_GPHI] = cnt.n[SL_GG] = cnt.n[SL_PHIPHI] = nb_inv;
+    TIMED(PS_FINALIZE, launch_finalize(g->part, g->pstride, cnt, nb, g->sums, s));
     HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, (size_t)nb * NSLOT * sizeof(double),
                            hipMemcpyDeviceToHost, s));
+    return OFDFT_OK;
+}
+
+// Replays (capturing on first use) the evaluation for this argument set.
+template <typename T>
+static ofdft_status eval_graph(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
+                               void *d_g, hipStream_t s)
+{
+    GraphEntry *hit = nullptr;
+    for (auto &e : g->graphs)
+        if (e.nb == nb && e.in == d_in && e.in_is_phi == in_is_phi && e.v == d_v && e.gout == d_g)
+            hit = &e;
+    if (!hit) {
+        if (g->graphs.size() >= 8) {   // drop the least recently used
+            size_t lru = 0;
+            for (size_t i = 1; i < g->graphs.size(); ++i)
+                if (g->graphs[i].last < g->graphs[lru].last) lru = i;
+            (void)hipGraphExecDestroy(g->graphs[lru].exec);
+            g->graphs.erase(g->graphs.begin() + lru);
+        }
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const ofdft_status st = eval_enqueue<T>(g, nb, d_in, in_is_phi, d_v, d_g, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &graph);
+        if (st != OFDFT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        HIP_TRY(e);
+        GraphEntry ge;
+        ge.nb = nb;
+        ge.in = d_in;
+        ge.in_is_phi = in_is_phi;
+        ge.v = d_v;
+        ge.gout = d_g;
+        const hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_TRY(ei);
+        g->graphs.push_back(ge);
+        hit = &g->graphs.back();
+    }
+    hit->last = ++g->graph_clock;
+    HIP_TRY(hipGraphLaunch(hit->exec, s));
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
+                              void *d_g, hipStream_t s, ofdft_energy *e_out, double *bad_out)
+{
+    ST_TRY(reserve(g, nb));
+    const Geom &G = g->geom;
+    const uint32_t terms = g->func.terms;
+    // graphs on streams that can be captured (not the legacy null stream)
+    // and when no per-pass timing is asked for
+    if (g->use_graphs && !g->timer.on && s != nullptr) {
+        ST_TRY(eval_graph<T>(g, nb, d_in, in_is_phi, d_v, d_g, s));
+    } else {
+        ST_TRY(eval_enqueue<T>(g, nb, d_in, in_is_phi, d_v, d_g, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     timer_collect(g);
 
@@ -776,7 +872,7 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         rf.tw1 = g->tw1;
         rf.knots = g->knots;
         int nbk = 0;
-        if (plane_supported<T>(G.n1, G.m)) {
+        if (use_plane<T>(g)) {
             TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nbk, s));
         } else {
             TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nbk, s));
@@ -789,7 +885,7 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         HIP_TRY(hipMemcpyAsync(g->spec, d_in, (size_t)nb * G.Nh * 2 * sizeof(T),
                                hipMemcpyDeviceToDevice, s));
         ST_TRY(col_pass<T>(g, s, 0, g->spec, nb, nb, 1, nullptr, PS_COL0_G));
-        const bool plane = plane_supported<T>(G.n1, G.m);
+        const bool plane = use_plane<T>(g);
         if (!plane) ST_TRY(col_pass<T>(g, s, 1, g->spec, nb, nb, 1, nullptr, PS_COL1_INV));
         RowInvArgs ri;
         std::memset(&ri, 0, sizeof(ri));
@@ -873,6 +969,7 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
 
 static void grid_free(ofdft_grid *g)
 {
+    graphs_clear(g);
     dfree(g->tw0);
     dfree(g->tw1);
     dfree(g->twM);
@@ -886,7 +983,6 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_atom_species));
     dfree(reinterpret_cast<void *&>(g->d_Z));
     dfree(reinterpret_cast<void *&>(g->d_rc));
-    dfree(reinterpret_cast<void *&>(g->d_count));
     dfree(reinterpret_cast<void *&>(g->d_knots));
     dfree(g->spec);
     dfree(g->kspec);
@@ -1145,7 +1241,6 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m));
     ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1));
 
-    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_count), NSLOT * sizeof(int)));
 
     for (int j = 0; j < 3; ++j)
         for (int i = 0; i < 3; ++i) g->frac[j][i] = cof[j][i] / det;
@@ -1213,10 +1308,10 @@ static ofdft_status dots(OptState &o, int nd, const void *x0, const void *y0, co
     int nbk = 0;
     TIMED(PS_OTHER, launch_dots<T>(o.N, nd, x0, y0, x1, y1, x2, y2, nullptr, nullptr, g->part,
                                    g->pstride, nbk, s));
-    int cnt[NSLOT] = {0};
-    for (int d = 0; d < nd; ++d) cnt[SL_AUX0 + d] = nbk;
-    HIP_TRY(hipMemcpyAsync(g->d_count, cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_finalize(g->part, g->pstride, g->d_count, 1, g->sums, s));
+    SlotCounts cnt;
+    std::memset(&cnt, 0, sizeof(cnt));
+    for (int d = 0; d < nd; ++d) cnt.n[SL_AUX0 + d] = nbk;
+    HIP_TRY(launch_finalize(g->part, g->pstride, cnt, 1, g->sums, s));
     HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, NSLOT * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     timer_collect(g);
@@ -1252,7 +1347,7 @@ static ofdft_status precondition(OptState &o, const void *in, void *out)
     rf.tw1 = g->tw1;
     rf.knots = g->knots;
     int nbk = 0;
-    const bool plane = plane_supported<T>(G.n1, G.m);
+    const bool plane = use_plane<T>(g);
     if (plane) {
         TIMED(PS_OTHER, launch_plane_fwd<T>(G, 1, rf, nbk, s));
     } else {
@@ -1480,6 +1575,97 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     return OFDFT_OK;
 }
 
+// ================================================================ autotuner
+// The launch schedule of an evaluation has three free choices: the fused
+// plane kernels or separate row and column passes (where the plane fits in
+// LDS), the block order of the column passes, and the number of spline knots
+// per batch.  The tuner times every combination on the caller's batch and
+// keeps the fastest; results are shared by all grids of the same shape,
+// precision, functional and batch size in the process.
+struct TuneVal {
+    int plane, tile_major, kb;
+};
+using TuneKey = std::tuple<int, int, int, int, uint32_t, int, int, int>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, TuneVal> g_tune_cache;
+
+static TuneKey tune_key(const ofdft_grid *g, int nb)
+{
+    return TuneKey(g->n[0], g->n[1], g->n[2], g->fp64 ? 1 : 0, g->func.terms, g->func.nl_mode,
+                   (g->func.terms & OFDFT_TERM_SPLINE) ? g->func.nk : 0, nb);
+}
+
+static void tune_apply_cached(ofdft_grid *g, int nb)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(g, nb));
+    if (it == g_tune_cache.end()) return;
+    g->tune_plane = it->second.plane;
+    g->tune_col_tile_major = it->second.tile_major;
+    g->tune_kb = it->second.kb;
+    graphs_clear(g);
+}
+
+static ofdft_status eval_dispatch(ofdft_grid *g, int nb, const void *d_in, int in_is_phi,
+                                  void *d_v, void *d_g, hipStream_t s, ofdft_energy *e_out);
+
+static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream_t s,
+                              ofdft_tune_result *out)
+{
+    ST_TRY(reserve(g, nb));
+    const bool plane_ok = g->fp64 ? plane_supported<double>(g->geom.n1, g->geom.m)
+                                  : plane_supported<float>(g->geom.n1, g->geom.m);
+    const bool spline = g->func.terms & OFDFT_TERM_SPLINE;
+    std::vector<TuneVal> cand;
+    for (int pl : {1, 0}) {
+        if (!pl && !plane_ok) continue;
+        for (int tm : {0, 1})
+            for (int kb : {MAXKB, MAXKB / 2}) {
+                if (!spline && kb != MAXKB) continue;
+                cand.push_back({pl, tm, kb});
+            }
+    }
+    std::vector<ofdft_energy> e((size_t)nb);
+    double best = 1e300, dflt = 0.0;
+    TuneVal pick = cand[0];
+    for (size_t c = 0; c < cand.size(); ++c) {
+        g->tune_plane = cand[c].plane;
+        g->tune_col_tile_major = cand[c].tile_major;
+        g->tune_kb = cand[c].kb;
+        graphs_clear(g);
+        ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));   // warm-up
+        double t[3];
+        for (double &x : t) {
+            const auto t0 = std::chrono::steady_clock::now();
+            ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));
+            x = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        std::sort(t, t + 3);
+        if (c == 0) dflt = t[1];
+        if (t[1] < best) {
+            best = t[1];
+            pick = cand[c];
+        }
+    }
+    g->tune_plane = pick.plane;
+    g->tune_col_tile_major = pick.tile_major;
+    g->tune_kb = pick.kb;
+    graphs_clear(g);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[tune_key(g, nb)] = pick;
+    }
+    if (out) {
+        out->plane = pick.plane;
+        out->col_tile_major = pick.tile_major;
+        out->knot_batch = pick.kb;
+        out->candidates = (int32_t)cand.size();
+        out->best_ms = best;
+        out->default_ms = dflt;
+    }
+    return OFDFT_OK;
+}
+
 // ================================================================ internal
 namespace ofdft_internal {
 
@@ -1500,6 +1686,12 @@ void set_cancel(ofdft_grid *g, const std::atomic<int> *flag) { g->cancel = flag;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 int ctx_device(const ofdft_ctx *ctx) { return ctx->device; }
+
+bool has_tuning(const ofdft_grid *g)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune_cache.count(tune_key(g, 1)) > 0;
+}
 
 }  // namespace ofdft_internal
 
@@ -1555,6 +1747,7 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     g->large_ions = use_large_ions(cell->natoms);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);
+    if (st == OFDFT_OK) tune_apply_cached(g, 1);
     if (st != OFDFT_OK) {
         grid_free(g);
         delete g;
@@ -1745,11 +1938,35 @@ ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, of
                       : optimize_impl<float>(grid, params, result);
 }
 
+ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null argument");
+    grid->use_graphs = on != 0;
+    if (!grid->use_graphs) graphs_clear(grid);
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
+                                 void *hip_stream, ofdft_tune_result *result)
+{
+    if (!grid || !d_rho || nbatch < 1 || nbatch > 65535) return fail(OFDFT_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return tune_impl(grid, nbatch, d_rho, pick_stream(grid, hip_stream), result);
+}
+
+ofdft_status ofdft_grid_tune(ofdft_grid *grid, ofdft_tune_result *result)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return tune_impl(grid, 1, grid->rho, grid->ctx->stream, result);
+}
+
 // per-pass timing with HIP events on the launch stream
 ofdft_status ofdft_profile_enable(ofdft_grid *grid, int32_t on)
 {
     if (!grid) return fail(OFDFT_EINVAL, "null argument");
     grid->timer.on = on != 0;
+    graphs_clear(grid);
     for (int i = 0; i < NPASS; ++i) {
         grid->timer.ms[i] = 0;
         grid->timer.count[i] = 0;

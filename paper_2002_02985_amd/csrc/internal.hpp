@@ -19,5 +19,8 @@ void set_cancel(ofdft_grid *g, const std::atomic<int> *flag);
 // Sets the calling thread's ofdft_last_error() message.
 void set_error(const std::string &msg);
 int ctx_device(const ofdft_ctx *ctx);
+// Whether the process already holds a tuned launch schedule for this grid's
+// shape, precision, functional and single-density batches.
+bool has_tuning(const ofdft_grid *g);
 
 }  // namespace ofdft_internal

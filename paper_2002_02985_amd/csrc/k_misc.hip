@@ -16,23 +16,23 @@ bool length_supported(int L)
 }
 
 // ---------------------------------------------------------------- finalize
-__global__ __launch_bounds__(NT) void k_finalize(const double *part, int pstride, const int *count,
+__global__ __launch_bounds__(NT) void k_finalize(const double *part, int pstride, SlotCounts count,
                                                  double *sums)
 {
     __shared__ double red[NT];
     const int s = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
     const double *p = part + ((long long)b * NSLOT + s) * pstride;
-    const int n = count[s];
+    const int n = count.n[s];
     double acc = 0.0;
     for (int i = tid; i < n; i += NT) acc += p[i];
     acc = block_sum<NT>(acc, red, tid);
     if (tid == 0) sums[b * NSLOT + s] = acc;
 }
 
-hipError_t launch_finalize(const double *part, int pstride, const int *count_dev, int nbatch,
+hipError_t launch_finalize(const double *part, int pstride, const SlotCounts &count, int nbatch,
                            double *sums, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(NSLOT, nbatch), dim3(NT), 0, s, part, pstride, count_dev,
+    hipLaunchKernelGGL(k_finalize, dim3(NSLOT, nbatch), dim3(NT), 0, s, part, pstride, count,
                        sums);
     return hipGetLastError();
 }

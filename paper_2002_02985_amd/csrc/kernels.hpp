@@ -159,8 +159,13 @@ template <typename T> int col_blocks(int L, long long ncols);
 template <typename T>
 hipError_t launch_gtab(const Geom &g, double kf_wt, void *gtab, hipStream_t s);
 
-// FP64 reductions: sums[b][s] = sum_{i < count[s]} part[b][s][i]
-hipError_t launch_finalize(const double *part, int pstride, const int *count_dev, int nbatch,
+// FP64 reductions: sums[b][s] = sum_{i < count.n[s]} part[b][s][i]; the
+// counts travel as a kernel argument (the launch sequence of an evaluation
+// has no host-to-device copies, so it can be captured in a HIP graph)
+struct SlotCounts {
+    int n[NSLOT];
+};
+hipError_t launch_finalize(const double *part, int pstride, const SlotCounts &count, int nbatch,
                            double *sums, hipStream_t s);
 
 // ionic structure factor and v_ext(G), electron-ion forces

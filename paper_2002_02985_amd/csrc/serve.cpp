@@ -145,12 +145,16 @@ int find_resident(const ofdft_server *s, uint64_t cell_id)
 void execute(Job &job, Res &r, ofdft_ctx *ctx)
 {
     ofdft_status st = OFDFT_OK;
+    bool fresh = false;
     if (!r.g) {
         st = ofdft_grid_create(ctx, &job.cell.d, &job.func, &r.g);
         if (st == OFDFT_OK) {
             r.cell.assign(job.cell);
             r.func = job.func;
             r.has_density = false;
+            fresh = true;
+            // the worker streams can be captured: evaluations replay graphs
+            (void)ofdft_grid_set_graphs(r.g, 1);
         }
     } else {
         ofdft_internal::bind_context(r.g, ctx);
@@ -177,6 +181,9 @@ void execute(Job &job, Res &r, ofdft_ctx *ctx)
             st = ofdft_set_density(g, u.data());
         }
         if (st == OFDFT_OK) r.has_density = true;
+        // a shape seen for the first time: tune its launch schedule once
+        if (st == OFDFT_OK && fresh && !ofdft_internal::has_tuning(g))
+            st = ofdft_grid_tune(g, nullptr);
     }
     if (st == OFDFT_OK) {
         job.res.evals = 1;

@@ -67,6 +67,15 @@ class Request(ctypes.Structure):
                 ("opt", ctypes.POINTER(OptParams)), ("rho_or_null", ctypes.POINTER(ctypes.c_double))]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("plane", ctypes.c_int32), ("col_tile_major", ctypes.c_int32),
+                ("knot_batch", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("cancelled", ctypes.c_uint64),
@@ -117,6 +126,9 @@ _SIGS = {
     "ofdft_serve_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "ofdft_serve_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServeStats)]),
     "ofdft_server_destroy": (None, [_P]),
+    "ofdft_grid_set_graphs": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
+    "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
     "ofdft_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_profile_read": (ctypes.c_int, [_P, ctypes.c_int32, _DP,
                                           ctypes.POINTER(ctypes.c_int64)]),
@@ -354,6 +366,22 @@ def ofdft_serve_stats_get(server):
 
 def ofdft_server_destroy(server):
     load().ofdft_server_destroy(server)
+
+
+def ofdft_grid_set_graphs(grid, on=True):
+    check(load().ofdft_grid_set_graphs(grid, 1 if on else 0))
+
+
+def ofdft_grid_tune_dev(grid, nbatch, d_rho, stream):
+    r = TuneResult()
+    check(load().ofdft_grid_tune_dev(grid, int(nbatch), d_rho, stream, ctypes.byref(r)))
+    return r.as_dict()
+
+
+def ofdft_grid_tune(grid):
+    r = TuneResult()
+    check(load().ofdft_grid_tune(grid, ctypes.byref(r)))
+    return r.as_dict()
 
 
 def ofdft_profile_enable(grid, on=True):

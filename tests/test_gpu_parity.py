@@ -292,3 +292,56 @@ def test_large_cell_ionic_path_matches(which, prec, monkeypatch):
     assert abs(e1["e_ext"] - e0["e_ext"]) <= tol * (abs(e0["e_ext"]) if prec == ofdft.FP64 else 1)
     assert float(np.abs(v1 - v0).max()) <= (1e-9 if prec == ofdft.FP64 else 1e-4)
     assert b1 < b0   # no per-atom phase tables
+
+
+def test_graph_replay_matches_eager():
+    """Evaluations replayed from captured HIP graphs give the eager results
+    bit for bit, across argument sets and with eager work between replays."""
+    cell, rho = c1_cell()
+    terms = LOCAL | ofdft.TERM_WT
+    xs = [torch.from_numpy(rho).to("cuda:0"), torch.from_numpy(rho * 1.01).to("cuda:0")]
+    v = torch.zeros_like(xs[0])
+    st = torch.cuda.Stream()
+    with ofdft.Grid(cell, terms) as g, torch.cuda.stream(st):
+        h = st.cuda_stream
+        ref = []
+        for x in xs:
+            e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), v.data_ptr(), h)
+            st.synchronize()
+            ref.append((e.e_total, e.mu, v.cpu().numpy().copy()))
+        ofdft.ofdft_grid_set_graphs(g.handle, True)
+        for rep in range(4):
+            for k, x in enumerate(xs):
+                v.zero_()
+                e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), v.data_ptr(), h)
+                st.synchronize()
+                assert e.e_total == ref[k][0] and e.mu == ref[k][1], (rep, k)
+                assert np.array_equal(v.cpu().numpy(), ref[k][2]), (rep, k)
+                xs[1 - k].mul_(1.0)   # eager work between replays
+                st.synchronize()
+        # the optimiser runs its evaluations through the graphs as well
+        g.set_density(rho)
+        r1, s1 = g.optimize(tol=1e-7, max_iter=300, method=ofdft.OPT_PCG)
+        ofdft.ofdft_grid_set_graphs(g.handle, False)
+        g.set_density(rho)
+        r0, s0 = g.optimize(tol=1e-7, max_iter=300, method=ofdft.OPT_PCG)
+    assert s1 == s0 == ofdft.OK
+    assert r1.e.e_total == r0.e.e_total and r1.iters == r0.iters
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_autotuner_keeps_the_result(prec):
+    cell, dens = W.config_c2((96, 96, 96), 2)
+    dt = torch.float64 if prec == ofdft.FP64 else torch.float32
+    x = torch.from_numpy(np.stack(dens)).to(dtype=dt, device="cuda:0")
+    v = torch.zeros_like(x)
+    h = torch.cuda.current_stream().cuda_stream
+    with ofdft.Grid(cell, LOCAL | ofdft.TERM_WT, precision=prec) as g:
+        e0 = ofdft.ofdft_energy_potential_batch_dev(g.handle, 2, x.data_ptr(), v.data_ptr(), h)
+        res = ofdft.ofdft_grid_tune_dev(g.handle, 2, x.data_ptr(), h)
+        e1 = ofdft.ofdft_energy_potential_batch_dev(g.handle, 2, x.data_ptr(), v.data_ptr(), h)
+    print("tuned", prec, res, flush=True)
+    assert res["candidates"] >= 2 and res["best_ms"] <= res["default_ms"] * 1.0001
+    tol = 1e-10 * abs(e0[0].e_total) if prec == ofdft.FP64 else 1e-5 * len(cell["species"])
+    for a, b in zip(e0, e1):
+        assert abs(a.e_total - b.e_total) <= tol
