@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libofdft.so")
-SOURCES = ["k_fp32.hip", "k_fp64.hip", "k_plane_fp32.hip", "k_plane_fp64.hip", "k_misc.hip",
+SOURCES = ["k_row_fp32.hip", "k_row_fp64.hip", "k_col_fp32.hip", "k_col_fp64.hip",
+           "k_rowc_fp32.hip", "k_rowc_fp64.hip", "k_plane_fp32.hip", "k_plane_fp64.hip", "k_misc.hip",
            "k_ions.hip", "api.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("OFDFT_ARCH", "gfx950")

@@ -572,6 +572,23 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     return OFDFT_OK;
 }
 
+// The fixed term set of the final combine matching these arguments, or 0
+// (general combine).  The nonlocal sets assume alpha = 5/6.
+static int combine_flavour(const RowInvArgs &rc)
+{
+    int f = 0;
+    if (rc.fld_hext >= 0) f |= CB_H;
+    if (rc.fld_vw >= 0) f |= CB_VW;
+    if (rc.use_tf) f |= CB_TF;
+    if (rc.fld_wt >= 0) f |= CB_WT;
+    if (rc.spline) f |= CB_SPL;
+    if (rc.exact) f |= CB_EXACT;
+    if (rc.fld_a >= 0) f |= CB_A;
+    if (f != CF_LOCAL && f != CF_WT && f != CF_S3S4 && f != CF_EXACT) return 0;
+    if (f != CF_LOCAL && rc.alpha != 5.0 / 6.0) return 0;
+    return f;
+}
+
 template <typename T>
 // Enqueues every launch of one evaluation on s and the copy of the FP64 sums
 // to the pinned host array; no allocation, synchronisation or host-to-device
@@ -736,6 +753,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rc.twM = g->twM;
     rc.twN = g->twN;
     rc.tw1 = g->tw1;
+    rc.cf = combine_flavour(rc);
     int nb_inv = 0;
     if (plane) TIMED(PS_ROW_INV, launch_plane_inv<T>(G, rc, nb_inv, s));
     else TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));

@@ -135,7 +135,17 @@ struct RowInvArgs {
     int nbatch;
     const void *twM, *twN;
     const void *tw1;            // W_{n1}^n (plane kernels)
+    int cf;                     // EP_COMBINE: a fixed term set CF_* below, or 0
 };
+
+// Term sets of the final combine that have kernels specialised at compile
+// time (a set bit = term present); any other set, or a nonlocal term with
+// alpha != 5/6, runs the general combine (cf = 0).
+enum : int { CB_H = 1, CB_VW = 2, CB_TF = 4, CB_WT = 8, CB_SPL = 16, CB_EXACT = 32, CB_A = 64 };
+constexpr int CF_LOCAL = CB_H | CB_VW | CB_TF;
+constexpr int CF_WT = CF_LOCAL | CB_WT;
+constexpr int CF_S3S4 = CF_LOCAL | CB_SPL;
+constexpr int CF_EXACT = CF_LOCAL | CB_SPL | CB_EXACT | CB_A;
 
 bool length_supported(int L);
 
@@ -151,6 +161,9 @@ template <typename T> hipError_t launch_col(int L, int nfb, const ColArgs &a, in
 template <typename T> hipError_t launch_knot_inv(const KnotArgs &a, hipStream_t s);
 template <typename T> hipError_t launch_knot_acc(const KnotArgs &a, hipStream_t s);
 template <typename T> hipError_t launch_row_inv(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
+// EP_COMBINE with a fixed term set (a.cf != 0) for the row lengths that have
+// it; hipErrorNotSupported for the others (the caller runs the general one)
+template <typename T> hipError_t launch_row_combine_fixed(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
 template <typename T> int row_blocks(const Geom &g);
 template <typename T> int col_blocks(int L, long long ncols);
 

@@ -555,6 +555,192 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
     }
 }
 
+// ================================================================ step s4
+// Interpolation of the knot-i potential Phi_i at a pair of points with
+// brackets j[c] and weights t[c]: v1 += L_i Phi_i with L_i = 1 - t at knot j
+// and t at knot j + 1; for EXACT, v2 collects Phi_{j+1} - Phi_j (the knot
+// slope without its 1/(k_{j+1} - k_j), applied once per knot batch by
+// knot_slope_scale).  One knot (nk = 1): L = 1, no slope.
+template <typename T>
+__device__ __forceinline__ void knot_interp(const int (&j)[2], const T (&t)[2], int i, int nk,
+                                            int exact, cpx<T> z, cpx<T> &v1, cpx<T> &v2)
+{
+    const T ph[2] = {z.x, z.y};
+    T w1[2], d2[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const bool e0 = j[c] == i, e1 = j[c] + 1 == i;
+        w1[c] = nk == 1 ? T(1) : (e0 ? T(1) - t[c] : (e1 ? t[c] : T(0)));
+        d2[c] = nk == 1 ? T(0) : (e0 ? -ph[c] : (e1 ? ph[c] : T(0)));
+    }
+    v1.x += w1[0] * ph[0];
+    v1.y += w1[1] * ph[1];
+    if (exact) {
+        v2.x += d2[0];
+        v2.y += d2[1];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void knot_slope_scale(const Knots &kn, const int (&j)[2], cpx<T> &v2)
+{
+    if (kn.nk == 1) return;
+    v2.x *= T(1.0 / (kn.k[j[0] + 1] - kn.k[j[0]]));
+    v2.y *= T(1.0 / (kn.k[j[1] + 1] - kn.k[j[1]]));
+}
+
+// ================================================================ final combine
+// Per-point combine of the real-space fields into v = dE/drho and
+// g = dE/dphi (eqs. "euler", "euler2"), with the FP64 partial sums of
+// rho^alpha Phi (E_NL), g phi, g^2 and phi^2.  Inputs per point: x (rho or
+// phi), hv = v_H + v_ext, wv = -lambda nabla^2 phi, nl = the WT potential
+// Phi or the EXACT spline field A (exclusive), s1/s2 = the spline
+// accumulators sum_i L_i Phi_i and sum_i L_i' Phi_i.
+//
+// CF = 0 takes the term set from the arguments and any alpha.  A non-zero CF
+// fixes the term set at compile time (CF_* in kernels.hpp; the host picks one
+// when the functional matches it exactly) and, when a nonlocal term is present, alpha
+// = 5/6 (the WT and spline exponents of the paper's kernels), so that every
+// power of rho the terms need comes from two exponentials:
+//   p = rho^(1/6):              phi = p^3, rho^(1/3) = p^2, rho^(2/3) = p^4,
+//                               rho^(5/6) = p^5, k_F = (3 pi^2)^(1/3) p^2
+//   q = max(rho, floor)^(-1/6): rho_s^(-1/6) = q, rho_s^(-1/2) = q^3,
+//                               rho_s^(-1) = q^6
+constexpr double KF_C = 3.0936677262801355;   // (3 pi^2)^(1/3)
+
+template <typename T>
+struct CombineConst {
+    T alpha, floor_rho, lfloor, k_lo, k_hi;
+};
+
+template <typename T>
+__device__ __forceinline__ CombineConst<T> combine_const(const RowInvArgs &a)
+{
+    CombineConst<T> c;
+    c.alpha = T(a.alpha);
+    c.floor_rho = T(a.floor);
+    c.lfloor = d_log2(c.floor_rho);
+    c.k_lo = a.spline ? T(a.knots.k[0]) : T(0);
+    c.k_hi = a.spline ? T(a.knots.k[a.knots.nk - 1]) : T(0);
+    return c;
+}
+
+template <typename T, int CF>
+__device__ __forceinline__ void combine_point(const RowInvArgs &a, const CombineConst<T> &cc, T x,
+                                              T hv, T wv, T nl, T s1, T s2, T &vo, T &go,
+                                              double (&sums)[4])
+{
+    T phi, rho;
+    if (a.in_is_phi) {
+        phi = x;
+        rho = phi * phi;
+    } else {
+        rho = x > T(0) ? x : T(0);
+        phi = T(0);
+    }
+    const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+    const T lr = rho >= cc.floor_rho ? lu : cc.lfloor;
+    T vv = T(0), gg = T(0);
+    if constexpr (CF != 0) {
+        constexpr T AL = T(5.0 / 6.0);
+        const T p = d_exp2(lu * T(1.0 / 6.0));
+        const T q = d_exp2(lr * T(-1.0 / 6.0));
+        const T p2 = p * p;
+        if (!a.in_is_phi) phi = p2 * p;
+        const T sgn = phi < T(0) ? T(-1) : T(1);
+        const T p4 = p2 * p2;
+        const T q3 = q * q * q;
+        if constexpr ((CF & CB_H) != 0) {
+            vv += hv;
+            gg += T(2) * phi * hv;
+        }
+        if constexpr ((CF & CB_VW) != 0) {
+            vv += T(0.5) * wv * sgn * q3;
+            gg += wv;
+        }
+        if constexpr ((CF & CB_TF) != 0) {
+            const T vt = T(5.0 / 3.0 * C_TF_D) * p4;
+            vv += vt;
+            gg += T(2) * phi * vt;
+        }
+        if constexpr ((CF & (CB_WT | CB_A | CB_SPL)) != 0) {
+            const T ra = p4 * p;         // rho^a
+            const T fa_ = sgn * p2;      // phi rho^(a-1)
+            if constexpr ((CF & CB_WT) != 0) {
+                vv += T(2) * AL * q * nl;
+                gg += T(4) * AL * fa_ * nl;
+                sums[0] += (double)(ra * nl);
+            }
+            if constexpr ((CF & CB_A) != 0) {
+                vv += AL * q * nl;
+                gg += T(2) * AL * fa_ * nl;
+            }
+            if constexpr ((CF & CB_SPL) != 0) {
+                sums[0] += (double)(ra * s1);
+                if constexpr ((CF & CB_EXACT) == 0) {
+                    vv += T(2) * AL * q * s1;
+                    gg += T(4) * AL * fa_ * s1;
+                } else {
+                    const T kf = T(KF_C) * p2;
+                    const T dk = (kf > cc.k_lo && kf < cc.k_hi) ? kf * T(1.0 / 3.0) : T(0);
+                    vv += AL * q * s1 + ra * dk * (q3 * q3) * s2;
+                    gg += T(2) * (AL * fa_ * s1 + fa_ * dk * s2);
+                }
+            }
+        }
+    } else {
+        if (!a.in_is_phi) phi = d_sqrt(rho);
+        const T sgn = phi < T(0) ? T(-1) : T(1);
+        const T alpha = cc.alpha;
+        const bool has_wt = a.fld_wt >= 0, has_a = a.fld_a >= 0;
+        T ra = T(0), ra1 = T(0), fa_ = T(0);
+        if (a.spline || has_wt || has_a) {
+            ra = d_exp2(alpha * lu);                   // rho^a
+            ra1 = d_exp2((alpha - T(1)) * lr);         // rho_s^(a-1)
+            fa_ = sgn * d_exp2((alpha - T(0.5)) * lu); // phi rho^(a-1)
+        }
+        if (a.fld_hext >= 0) {                         // v_H + v_ext
+            vv += hv;
+            gg += T(2) * phi * hv;
+        }
+        if (a.fld_vw >= 0) {                           // -lambda nabla^2 phi
+            vv += T(0.5) * wv * sgn * d_exp2(T(-0.5) * lr);
+            gg += wv;
+        }
+        if (has_wt) {                                  // Wang-Teter Phi
+            vv += T(2) * alpha * ra1 * nl;
+            gg += T(4) * alpha * fa_ * nl;
+            sums[0] += (double)(ra * nl);
+        }
+        if (has_a) {                                   // EXACT: F^-1[sum_i omega_i F[rho^a L_i]]
+            vv += alpha * ra1 * nl;
+            gg += T(2) * alpha * fa_ * nl;
+        }
+        if (a.use_tf) {
+            const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
+            vv += vt;
+            gg += T(2) * phi * vt;
+        }
+        if (a.spline) {
+            sums[0] += (double)(ra * s1);
+            if (!a.exact) {
+                vv += T(2) * alpha * ra1 * s1;
+                gg += T(4) * alpha * fa_ * s1;
+            } else {
+                const T kf = kf_from_log2(lu);
+                const T dk = (kf > cc.k_lo && kf < cc.k_hi) ? kf * T(1.0 / 3.0) : T(0);
+                vv += alpha * ra1 * s1 + ra * dk * d_exp2(-lr) * s2;
+                gg += T(2) * (alpha * fa_ * s1 + fa_ * dk * s2);
+            }
+        }
+    }
+    sums[1] += (double)gg * (double)phi;
+    sums[2] += (double)gg * (double)gg;
+    sums[3] += (double)phi * (double)phi;
+    vo = vv;
+    go = gg;
+}
+
 // ================================================================ row inverse
 // c2r of one block of half-spectrum rows into buf (z[n] = f[2n] + i f[2n+1],
 // element n of row p at buf[n * PS + p]):
@@ -590,7 +776,7 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
     lds_fft<T, M, true, P, NT, PS>(buf, twM, tid);
 }
 
-template <typename T, int M>
+template <typename T, int M, int CF>
 __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
 {
     constexpr int P = row_P<T, M>();
@@ -621,7 +807,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
         lds_at[q] = n * PS + p;
     }
 
-    if (a.mode == EP_STORE) {
+    // the fixed-term-set instantiations (CF != 0) hold the combine only
+    if (CF == 0 && a.mode == EP_STORE) {
         for (int f = 0; f < a.nfields; ++f) {
             c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
             T *out = (T *)a.out + ((long long)f * a.nbatch + b) * g.N;
@@ -640,7 +827,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     for (int q = 0; q < PER; ++q)
         xin[q] = valid[q] ? *(const cpx<T> *)(in + offs[q]) : cpx<T>{T(0), T(0)};
 
-    if (a.mode == EP_KNOTS) {
+    if (CF == 0 && a.mode == EP_KNOTS) {
         // step s4 for this batch of knots: v1 += L_i Phi_i, v2 += L_i' Phi_i
         int jj[PER][2];
         T tt[PER][2];
@@ -673,27 +860,13 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
             for (int q = 0; q < PER; ++q) {
                 if (!valid[q]) continue;
                 const cpx<T> z = buf[lds_at[q]];
-                const T ph[2] = {z.x, z.y};
-                T w1[2], w2[2];
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int j = jj[q][c];
-                    const T t = tt[q][c];
-                    if (nk == 1) {
-                        w1[c] = T(1);
-                        w2[c] = T(0);
-                    } else {
-                        const T idk = T(1.0 / (a.knots.k[j + 1] - a.knots.k[j]));
-                        w1[c] = (j == i) ? T(1) - t : ((j + 1 == i) ? t : T(0));
-                        w2[c] = (j == i) ? -idk : ((j + 1 == i) ? idk : T(0));
-                    }
-                }
-                v1[q].x += w1[0] * ph[0];
-                v1[q].y += w1[1] * ph[1];
-                v2[q].x += w2[0] * ph[0];
-                v2[q].y += w2[1] * ph[1];
+                knot_interp(jj[q], tt[q], i, nk, a.exact, z, v1[q], v2[q]);
             }
             __syncthreads();
+        }
+        if (a.exact) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) knot_slope_scale(a.knots, jj[q], v2[q]);
         }
         T *acc1 = (T *)a.acc1 + (long long)b * g.N;
         T *acc2 = a.exact ? (T *)a.acc2 + (long long)b * g.N : nullptr;
@@ -713,9 +886,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     }
 
     // EP_COMBINE: v = dE/drho and g = dE/dphi from all terms
-    cpx<T> fh[PER], fl[PER], fw[PER], fa[PER];
+    cpx<T> fh[PER], fl[PER], fn[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) fh[q] = fl[q] = fw[q] = fa[q] = {T(0), T(0)};
+    for (int q = 0; q < PER; ++q) fh[q] = fl[q] = fn[q] = {T(0), T(0)};
     const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
     for (int s = 0; s < 4; ++s) {
         if (flds[s] < 0) continue;
@@ -726,8 +899,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
             const cpx<T> z = buf[lds_at[q]];
             if (s == 0) fh[q] = z;
             else if (s == 1) fl[q] = z;
-            else if (s == 2) fw[q] = z;
-            else fa[q] = z;
+            else fn[q] = z;   // WT Phi or the EXACT field A (exclusive)
         }
         __syncthreads();
     }
@@ -735,10 +907,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     const T *acc2 = (a.spline && a.exact) ? (const T *)a.acc2 + (long long)b * g.N : nullptr;
     T *vout = a.v_out ? (T *)a.v_out + (long long)b * g.N : nullptr;
     T *gout = a.g_out ? (T *)a.g_out + (long long)b * g.N : nullptr;
-    const T alpha = T(a.alpha);
-    const T floor_rho = T(a.floor);
-    const T lfloor = d_log2(floor_rho);
-    const bool has_wt = a.fld_wt >= 0;
+    const CombineConst<T> cc = combine_const<T>(a);
     double sums[4] = {0.0, 0.0, 0.0, 0.0};   // rho^a Phi, g phi, g^2, phi^2
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -746,69 +915,13 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
         cpx<T> a1 = {T(0), T(0)}, a2 = {T(0), T(0)};
         if (acc1) a1 = *(const cpx<T> *)(acc1 + offs[q]);
         if (acc2) a2 = *(const cpx<T> *)(acc2 + offs[q]);
-        const T xv[2] = {xin[q].x, xin[q].y};
-        const T hv[2] = {fh[q].x, fh[q].y};
-        const T lv[2] = {fl[q].x, fl[q].y};
-        const T wv[2] = {fw[q].x, fw[q].y};
-        const T av[2] = {fa[q].x, fa[q].y};
-        const T s1v[2] = {a1.x, a1.y};
-        const T s2v[2] = {a2.x, a2.y};
-        T vo[2], go[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            T phi, rho;
-            if (a.in_is_phi) {
-                phi = xv[c];
-                rho = phi * phi;
-            } else {
-                rho = xv[c] > T(0) ? xv[c] : T(0);
-                phi = d_sqrt(rho);
-            }
-            const T sgn = phi < T(0) ? T(-1) : T(1);
-            // one logarithm per point: lu = log2(rho), lr = log2(max(rho, floor))
-            const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
-            const T lr = rho >= floor_rho ? lu : lfloor;
-            T v = hv[c];                                   // v_H + v_ext
-            T gphi = T(2) * phi * v;
-            if (a.use_tf) {
-                const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
-                v += vt;
-                gphi += T(2) * phi * vt;
-            }
-            // von Weizsaecker: lv = -lambda nabla^2 phi; v = lv / (2 phi_s)
-            v += T(0.5) * lv[c] * sgn * d_exp2(T(-0.5) * lr);
-            gphi += lv[c];
-            if (has_wt || a.spline) {
-                const T ra1 = d_exp2((alpha - T(1)) * lr);          // rho_s^(alpha-1)
-                const T ra = d_exp2(alpha * lu);                    // rho^alpha
-                const T fa_ = sgn * d_exp2((alpha - T(0.5)) * lu);  // phi rho^(alpha-1)
-                if (has_wt) {
-                    v += T(2) * alpha * ra1 * wv[c];
-                    gphi += T(4) * alpha * fa_ * wv[c];
-                    sums[0] += (double)(ra * wv[c]);
-                }
-                if (a.spline) {
-                    sums[0] += (double)(ra * s1v[c]);
-                    if (!a.exact) {
-                        v += T(2) * alpha * ra1 * s1v[c];
-                        gphi += T(4) * alpha * fa_ * s1v[c];
-                    } else {
-                        const T kf = kf_from_log2(lu);
-                        const bool inside = kf > T(a.knots.k[0]) && kf < T(a.knots.k[a.knots.nk - 1]);
-                        const T dk = inside ? kf * T(1.0 / 3.0) : T(0);   // rho dk~/drho
-                        v += alpha * ra1 * (s1v[c] + av[c]) + ra * dk * d_exp2(-lr) * s2v[c];
-                        gphi += T(2) * (alpha * fa_ * (s1v[c] + av[c]) + fa_ * dk * s2v[c]);
-                    }
-                }
-            }
-            vo[c] = v;
-            go[c] = gphi;
-            sums[1] += (double)gphi * (double)phi;
-            sums[2] += (double)gphi * (double)gphi;
-            sums[3] += (double)phi * (double)phi;
-        }
-        if (vout) *(cpx<T> *)(vout + offs[q]) = {vo[0], vo[1]};
-        if (gout) *(cpx<T> *)(gout + offs[q]) = {go[0], go[1]};
+        cpx<T> vo, go;
+        combine_point<T, CF>(a, cc, xin[q].x, fh[q].x, fl[q].x, fn[q].x, a1.x, a2.x, vo.x, go.x,
+                             sums);
+        combine_point<T, CF>(a, cc, xin[q].y, fh[q].y, fl[q].y, fn[q].y, a1.y, a2.y, vo.y, go.y,
+                             sums);
+        if (vout) *(cpx<T> *)(vout + offs[q]) = vo;
+        if (gout) *(cpx<T> *)(gout + offs[q]) = go;
     }
     block_sums<NT, 4>(sums, red, tid);
     if (tid == 0) {
@@ -974,22 +1087,22 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         __syncthreads();
         // axis 2: half-length complex transforms of the N1 rows
         lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
-        // unpack to the r2c half spectrum, pairs (k, M-k) in place
-        for (int w = t; w < N1 * HALF; w += NTP) {
-            const int i1 = w / HALF, k = w % HALF;
+        // unpack to the r2c half spectrum, pairs (k, M-k) in place, i1 fastest
+        // and the same code for every pair: Z has period M, so k = 0 pairs
+        // Z[0] with itself and yields X[0] and the Nyquist X[M] (real);
+        // k = M/2 writes one value twice
+        for (unsigned w = (unsigned)t; w < (unsigned)(N1 * HALF); w += NTP) {
+            const unsigned k = w / (unsigned)N1, i1 = w % (unsigned)N1;
+            const cpx<T> zk = buf[k * A + i1];
+            const cpx<T> zm = buf[(k == 0 ? 0u : M - k) * A + i1];
+            cpx<T> xk = r2c_unpack(zk, zm, twN[k]);
+            cpx<T> xm = r2c_unpack(zm, zk, twN[M - k]);
             if (k == 0) {
-                const cpx<T> z0 = buf[i1];
-                buf[i1] = {z0.x + z0.y, T(0)};
-                buf[M * A + i1] = {z0.x - z0.y, T(0)};
-            } else if (2 * k == M) {
-                const cpx<T> zk = buf[k * A + i1];
-                buf[k * A + i1] = r2c_unpack(zk, zk, twN[k]);
-            } else {
-                const cpx<T> zk = buf[k * A + i1];
-                const cpx<T> zm = buf[(M - k) * A + i1];
-                buf[k * A + i1] = r2c_unpack(zk, zm, twN[k]);
-                buf[(M - k) * A + i1] = r2c_unpack(zm, zk, twN[M - k]);
+                xk.y = T(0);
+                xm.y = T(0);
             }
+            buf[k * A + i1] = xk;
+            buf[(M - k) * A + i1] = xm;
         }
         __syncthreads();
         // axis 1: the M + 1 columns
@@ -1022,26 +1135,26 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
     }
     __syncthreads();
     lds_fft<T, N1, true, M + 1, NTP, 1, A>(buf, tw1, tid);
-    for (int w = tid; w < N1 * HALF; w += NTP) {
-        const int i1 = w / HALF, k = w % HALF;
+    // c2r pack of the pairs (k, M - k), k = 0..M/2, of every row, i1 fastest
+    // and the same code for every pair: k = 0 pairs the DC element with the
+    // Nyquist one (imaginary parts dropped) and also writes row M, which the
+    // axis-2 transforms do not read; k = M/2 writes one value twice
+    for (unsigned w = (unsigned)tid; w < (unsigned)(N1 * HALF); w += NTP) {
+        const unsigned k = w / (unsigned)N1, i1 = w % (unsigned)N1;
+        cpx<T> xk = buf[k * A + i1];
+        cpx<T> xm = buf[(M - k) * A + i1];
         if (k == 0) {
-            const T x0 = buf[i1].x, xm = buf[M * A + i1].x;
-            buf[i1] = {x0 + xm, x0 - xm};
-        } else if (2 * k == M) {
-            const cpx<T> xk = buf[k * A + i1];
-            buf[k * A + i1] = c2r_pack(xk, xk, twN[k]);
-        } else {
-            const cpx<T> xk = buf[k * A + i1];
-            const cpx<T> xm = buf[(M - k) * A + i1];
-            buf[k * A + i1] = c2r_pack(xk, xm, twN[k]);
-            buf[(M - k) * A + i1] = c2r_pack(xm, xk, twN[M - k]);
+            xk.y = T(0);
+            xm.y = T(0);
         }
+        buf[k * A + i1] = c2r_pack(xk, xm, twN[k]);
+        buf[(M - k) * A + i1] = c2r_pack(xm, xk, twN[M - k]);
     }
     __syncthreads();
     lds_fft<T, M, true, N1, NTP, A, 1>(buf, twM, tid);
 }
 
-template <typename T, int N1, int M, int MODE>
+template <typename T, int N1, int M, int MODE, int CF>
 __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plane_inv(RowInvArgs a, Geom g)
 {
     constexpr int NTP = plane_NT<N1, M>();
@@ -1124,27 +1237,13 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             for (int q = 0; q < PER; ++q) {
                 if (t + q * NTP >= PAIRS) continue;
                 const cpx<T> z = buf[at(t, q)];
-                const T ph[2] = {z.x, z.y};
-                T w1[2], w2[2];
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int j = jj[q][c];
-                    const T t = tt[q][c];
-                    if (nk == 1) {
-                        w1[c] = T(1);
-                        w2[c] = T(0);
-                    } else {
-                        const T idk = T(1.0 / (a.knots.k[j + 1] - a.knots.k[j]));
-                        w1[c] = (j == i) ? T(1) - t : ((j + 1 == i) ? t : T(0));
-                        w2[c] = (j == i) ? -idk : ((j + 1 == i) ? idk : T(0));
-                    }
-                }
-                v1[q].x += w1[0] * ph[0];
-                v1[q].y += w1[1] * ph[1];
-                v2[q].x += w2[0] * ph[0];
-                v2[q].y += w2[1] * ph[1];
+                knot_interp(jj[q], tt[q], i, nk, a.exact, z, v1[q], v2[q]);
             }
             __syncthreads();
+        }
+        if (a.exact) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) knot_slope_scale(a.knots, jj[q], v2[q]);
         }
         cpx<T> *acc1 = (cpx<T> *)((T *)a.acc1 + real_off);
         cpx<T> *acc2 = a.exact ? (cpx<T> *)((T *)a.acc2 + real_off) : nullptr;
@@ -1169,22 +1268,6 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     for (int q = 0; q < PER; ++q)
         if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
     __syncthreads();
-    const T alpha = T(a.alpha);
-    const T floor_rho = T(a.floor);
-    const T lfloor = d_log2(floor_rho);
-    // point quantities from the input value
-    auto point = [&](T xv, T &phi, T &rho, T &sgn, T &lu, T &lr) {
-        if (a.in_is_phi) {
-            phi = xv;
-            rho = phi * phi;
-        } else {
-            rho = xv > T(0) ? xv : T(0);
-            phi = d_sqrt(rho);
-        }
-        sgn = phi < T(0) ? T(-1) : T(1);
-        lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
-        lr = rho >= floor_rho ? lu : lfloor;
-    };
     // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
     // A are exclusive and come last, so only H+ext and vW are ever held
     const int all[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
@@ -1210,14 +1293,12 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         }
         __syncthreads();
     }
-    const bool has_h = a.fld_hext >= 0, has_vw = a.fld_vw >= 0, has_wt = a.fld_wt >= 0,
-               has_a = a.fld_a >= 0;
-    const bool need_a = a.spline || has_wt || has_a;
     const cpx<T> *acc1 = a.spline ? (const cpx<T> *)((const T *)a.acc1 + real_off) : nullptr;
     const cpx<T> *acc2 = (a.spline && a.exact) ? (const cpx<T> *)((const T *)a.acc2 + real_off)
                                                 : nullptr;
     cpx<T> *vout = a.v_out ? (cpx<T> *)((T *)a.v_out + real_off) : nullptr;
     cpx<T> *gout = a.g_out ? (cpx<T> *)((T *)a.g_out + real_off) : nullptr;
+    const CombineConst<T> cc = combine_const<T>(a);
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     const int t = opaque(tid);
 #pragma unroll
@@ -1231,65 +1312,11 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
         const cpx<T> zh = last == 0 ? zl : fh[q];
         const cpx<T> zv = last == 1 ? zl : fv[q];
-        const T xv[2] = {xq.x, xq.y};
-        const T s1v[2] = {s1.x, s1.y}, s2v[2] = {s2.x, s2.y};
-        const T hv[2] = {zh.x, zh.y}, wv[2] = {zv.x, zv.y}, lv[2] = {zl.x, zl.y};
-        T vout2[2], gout2[2];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            T phi, rho, sgn, lu, lr;
-            point(xv[c], phi, rho, sgn, lu, lr);
-            // each power of rho evaluated once per point
-            T ra = T(0), ra1 = T(0), fa_ = T(0);
-            if (need_a) {
-                ra = d_exp2(alpha * lu);                   // rho^a
-                ra1 = d_exp2((alpha - T(1)) * lr);         // rho_s^(a-1)
-                fa_ = sgn * d_exp2((alpha - T(0.5)) * lu); // phi rho^(a-1)
-            }
-            T vv = T(0), gg = T(0);
-            if (has_h) {                               // v_H + v_ext
-                vv += hv[c];
-                gg += T(2) * phi * hv[c];
-            }
-            if (has_vw) {                              // -lambda nabla^2 phi
-                vv += T(0.5) * wv[c] * sgn * d_exp2(T(-0.5) * lr);
-                gg += wv[c];
-            }
-            if (has_wt) {                              // Wang-Teter Phi
-                vv += T(2) * alpha * ra1 * lv[c];
-                gg += T(4) * alpha * fa_ * lv[c];
-                sums[0] += (double)(ra * lv[c]);
-            }
-            if (has_a) {                               // EXACT: F^-1[sum_i omega_i F[rho^a L_i]]
-                vv += alpha * ra1 * lv[c];
-                gg += T(2) * alpha * fa_ * lv[c];
-            }
-            if (a.use_tf) {
-                const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
-                vv += vt;
-                gg += T(2) * phi * vt;
-            }
-            if (a.spline) {
-                sums[0] += (double)(ra * s1v[c]);
-                if (!a.exact) {
-                    vv += T(2) * alpha * ra1 * s1v[c];
-                    gg += T(4) * alpha * fa_ * s1v[c];
-                } else {
-                    const T kf = kf_from_log2(lu);
-                    const bool inside = kf > T(a.knots.k[0]) && kf < T(a.knots.k[a.knots.nk - 1]);
-                    const T dk = inside ? kf * T(1.0 / 3.0) : T(0);
-                    vv += alpha * ra1 * s1v[c] + ra * dk * d_exp2(-lr) * s2v[c];
-                    gg += T(2) * (alpha * fa_ * s1v[c] + fa_ * dk * s2v[c]);
-                }
-            }
-            sums[1] += (double)gg * (double)phi;
-            sums[2] += (double)gg * (double)gg;
-            sums[3] += (double)phi * (double)phi;
-            vout2[c] = vv;
-            gout2[c] = gg;
-        }
-        if (vout) vout[idx] = {vout2[0], vout2[1]};
-        if (gout) gout[idx] = {gout2[0], gout2[1]};
+        cpx<T> vo, go;
+        combine_point<T, CF>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x, sums);
+        combine_point<T, CF>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y, sums);
+        if (vout) vout[idx] = vo;
+        if (gout) gout[idx] = go;
     }
     block_sums<NTP, 4>(sums, red, tid);
     if (tid == 0) {
@@ -1331,11 +1358,19 @@ hipError_t plane_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStr
         if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
         const dim3 grid(g.n0, a.nbatch), block(plane_NT<N1, M>());
         if (a.mode == EP_STORE)
-            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_STORE>), grid, block, 0, s, a, g);
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_STORE, 0>), grid, block, 0, s, a, g);
         else if (a.mode == EP_KNOTS)
-            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_KNOTS>), grid, block, 0, s, a, g);
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_KNOTS, 0>), grid, block, 0, s, a, g);
+        else if (a.cf == CF_LOCAL)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_LOCAL>), grid, block, 0, s, a, g);
+        else if (a.cf == CF_WT)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_WT>), grid, block, 0, s, a, g);
+        else if (a.cf == CF_S3S4)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_S3S4>), grid, block, 0, s, a, g);
+        else if (a.cf == CF_EXACT)
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_EXACT>), grid, block, 0, s, a, g);
         else
-            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE>), grid, block, 0, s, a, g);
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, 0>), grid, block, 0, s, a, g);
         return hipGetLastError();
     }
 }
@@ -1381,7 +1416,7 @@ hipError_t row_fwd_go(const Geom &g, int nbatch, const RowFwdArgs &a, int &nbloc
     return hipGetLastError();
 }
 
-template <typename T, int M>
+template <typename T, int M, int CF = 0>
 hipError_t row_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s)
 {
     constexpr int P = row_P<T, M>();
@@ -1389,8 +1424,21 @@ hipError_t row_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStrea
     nblocks = (int)((nrows + P - 1) / P);
     if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
     dim3 grid(nblocks, a.nbatch);
-    hipLaunchKernelGGL((k_row_inv<T, M>), grid, dim3(NT), 0, s, a, g);
+    hipLaunchKernelGGL((k_row_inv<T, M, CF>), grid, dim3(NT), 0, s, a, g);
     return hipGetLastError();
+}
+
+template <typename T, int M>
+hipError_t row_combine_fixed_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s)
+{
+    if (a.mode != EP_COMBINE) return hipErrorNotSupported;
+    switch (a.cf) {
+    case CF_LOCAL: return row_inv_go<T, M, CF_LOCAL>(g, a, nblocks, s);
+    case CF_WT: return row_inv_go<T, M, CF_WT>(g, a, nblocks, s);
+    case CF_S3S4: return row_inv_go<T, M, CF_S3S4>(g, a, nblocks, s);
+    case CF_EXACT: return row_inv_go<T, M, CF_EXACT>(g, a, nblocks, s);
+    default: return hipErrorNotSupported;
+    }
 }
 
 template <typename T, int L>
@@ -1425,7 +1473,12 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-#define OFDFT_INSTANTIATE_LAUNCHERS(T)                                                          \
+// row lengths with fixed-term-set combine kernels (grids whose planes do not
+// fit in LDS: the larger serving cells, the slab and the 10^6-atom cell)
+#define OFDFT_ROWC_LENGTHS(X) \
+    X(48) X(64) X(72) X(96) X(108) X(128) X(144) X(192) X(216) X(256) X(288) X(384) X(512)
+
+#define OFDFT_INSTANTIATE_ROW(T)                                                               \
     template <> hipError_t launch_row_fwd<T>(const Geom &g, int nbatch, const RowFwdArgs &a,   \
                                              int &nb, hipStream_t s)                           \
     {                                                                                          \
@@ -1437,11 +1490,34 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
     template <> hipError_t launch_row_inv<T>(const Geom &g, const RowInvArgs &a, int &nb,      \
                                              hipStream_t s)                                    \
     {                                                                                          \
+        if (a.mode == EP_COMBINE && a.cf != 0) {                                               \
+            const hipError_t e = launch_row_combine_fixed<T>(g, a, nb, s);                     \
+            if (e != hipErrorNotSupported) return e;                                           \
+        }                                                                                      \
         switch (g.m) {                                                                         \
             OFDFT_LENGTHS(OFDFT_CASE_ROWI_##T)                                                 \
         default: return hipErrorInvalidValue;                                                  \
         }                                                                                      \
     }                                                                                          \
+    template <> int row_blocks<T>(const Geom &g)                                               \
+    {                                                                                          \
+        switch (g.m) {                                                                         \
+            OFDFT_LENGTHS(OFDFT_CASE_RB_##T)                                                   \
+        default: return 0;                                                                     \
+        }                                                                                      \
+    }
+
+#define OFDFT_INSTANTIATE_ROW_FIXED(T)                                                         \
+    template <> hipError_t launch_row_combine_fixed<T>(const Geom &g, const RowInvArgs &a,     \
+                                                       int &nb, hipStream_t s)                 \
+    {                                                                                          \
+        switch (g.m) {                                                                         \
+            OFDFT_ROWC_LENGTHS(OFDFT_CASE_ROWC_##T)                                            \
+        default: return hipErrorNotSupported;                                                  \
+        }                                                                                      \
+    }
+
+#define OFDFT_INSTANTIATE_COL(T)                                                               \
     template <> hipError_t launch_col<T>(int L, int nfb, const ColArgs &a, int &nb,            \
                                          hipStream_t s)                                        \
     {                                                                                          \
@@ -1464,13 +1540,6 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
         default: return hipErrorInvalidValue;                                                  \
         }                                                                                      \
     }                                                                                          \
-    template <> int row_blocks<T>(const Geom &g)                                               \
-    {                                                                                          \
-        switch (g.m) {                                                                         \
-            OFDFT_LENGTHS(OFDFT_CASE_RB_##T)                                                   \
-        default: return 0;                                                                     \
-        }                                                                                      \
-    }                                                                                          \
     template <> int col_blocks<T>(int L, long long ncols)                                      \
     {                                                                                          \
         switch (L) {                                                                           \
@@ -1483,6 +1552,8 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
 #define OFDFT_CASE_ROWF_double(L) case L: return row_fwd_go<double, L>(g, nbatch, a, nb, s);
 #define OFDFT_CASE_ROWI_float(L) case L: return row_inv_go<float, L>(g, a, nb, s);
 #define OFDFT_CASE_ROWI_double(L) case L: return row_inv_go<double, L>(g, a, nb, s);
+#define OFDFT_CASE_ROWC_float(L) case L: return row_combine_fixed_go<float, L>(g, a, nb, s);
+#define OFDFT_CASE_ROWC_double(L) case L: return row_combine_fixed_go<double, L>(g, a, nb, s);
 #define OFDFT_CASE_COL_float(L) case L: return col_go<float, L>(nfb, a, nb, s);
 #define OFDFT_CASE_COL_double(L) case L: return col_go<double, L>(nfb, a, nb, s);
 #define OFDFT_CASE_KI_float(L) case L: return knot_inv_go<float, L>(a, s);
