@@ -32,10 +32,17 @@ constexpr double THREE_PI2 = 29.608813203268075856503472999628;  // 3 pi^2
 constexpr double C_TF_D = 2.8712340001881918;   // (3/10)(3 pi^2)^(2/3)
 constexpr double C_WT_D = 2.2969872001505534;   // (6/25)(3 pi^2)^(2/3)
 
+// complex elements per block of the column and row passes (tile sizes)
+#ifndef OFDFT_COL_ELEMS_F32
+#define OFDFT_COL_ELEMS_F32 4096
+#endif
+#ifndef OFDFT_ROW_ELEMS_F32
+#define OFDFT_ROW_ELEMS_F32 2048
+#endif
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
-    static constexpr int COL_ELEMS = 4096;
-    static constexpr int ROW_ELEMS = 2048;
+    static constexpr int COL_ELEMS = OFDFT_COL_ELEMS_F32;
+    static constexpr int ROW_ELEMS = OFDFT_ROW_ELEMS_F32;
 };
 template <> struct Cfg<double> {
     static constexpr int COL_ELEMS = 2048;
@@ -48,9 +55,16 @@ constexpr int pow2_floor(int x)
     while (p * 2 <= x) p *= 2;
     return p;
 }
+// at most 16 columns per block: smaller tiles keep more blocks in flight per
+// CU, which measured faster than 32-wide tiles on both the 96-point and the
+// 256-point column passes
+#ifndef OFDFT_COL_PMAX
+#define OFDFT_COL_PMAX 16
+#endif
 template <typename T, int L> constexpr int col_P()
 {
     int p = pow2_floor(Cfg<T>::COL_ELEMS / L);
+    if (p > OFDFT_COL_PMAX) p = OFDFT_COL_PMAX;
     if (p < 4) p = 4;
     if (p > NT) p = NT;
     return p;
