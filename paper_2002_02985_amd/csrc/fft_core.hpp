@@ -298,6 +298,86 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
     __syncthreads();
 }
 
+// The first stage of a transform with its inputs taken from src(n, p)
+// (element n of pencil p, read from memory or computed) instead of LDS; the
+// outputs go to buf as in stockham_stage.  NS = 1: no twiddles.
+template <typename T, int L, int R, bool INV, int P, int NT, int ES, int PS, class SRC>
+__device__ __forceinline__ void stockham_stage_src(cpx<T> *buf, int tid, const SRC &src)
+{
+    constexpr int NBF = L / R;
+    constexpr int TOT = NBF * P;
+    constexpr int PER = (TOT + NT - 1) / NT;
+#ifndef OFDFT_STAGE_HOIST
+    asm volatile("" : "+v"(tid));
+#endif
+    const unsigned ut = (unsigned)tid;
+    cpx<T> v[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const unsigned b = ut + (unsigned)(q * NT);
+        if (TOT % NT == 0 || b < (unsigned)TOT) {
+            const unsigned j = b / (unsigned)P;
+            const unsigned p = b % (unsigned)P;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = src(j + (unsigned)(r * NBF), p);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const unsigned b = ut + (unsigned)(q * NT);
+        if (TOT % NT == 0 || b < (unsigned)TOT) {
+            const unsigned j = b / (unsigned)P;
+            const unsigned p = b % (unsigned)P;
+            dft<T, R, INV>(v[q]);
+            const unsigned a0 = j * (unsigned)(R * ES) + p * (unsigned)PS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[a0 + (unsigned)(r * ES)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// The last stage of a transform (NS R = L) with its outputs handed to
+// dst(n, p, value) instead of LDS.
+template <typename T, int L, int R, int NS, bool INV, int P, int NT, int ES, int PS, class DST>
+__device__ __forceinline__ void stockham_stage_dst(const cpx<T> *buf, const cpx<T> *tw, int tid,
+                                                   const DST &dst)
+{
+    static_assert(NS * R == L, "the last stage");
+    constexpr int NBF = L / R;
+    constexpr int TOT = NBF * P;
+    constexpr int PER = (TOT + NT - 1) / NT;
+#ifndef OFDFT_STAGE_HOIST
+    asm volatile("" : "+v"(tid));
+#endif
+    const unsigned ut = (unsigned)tid;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const unsigned b = ut + (unsigned)(q * NT);
+        if (TOT % NT == 0 || b < (unsigned)TOT) {
+            const unsigned j = b / (unsigned)P;   // j < NS
+            const unsigned p = b % (unsigned)P;
+            const unsigned a0 = j * (unsigned)ES + p * (unsigned)PS;
+            cpx<T> v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = buf[a0 + (unsigned)(r * NBF * ES)];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cpx<T> w = tw[j * (unsigned)r];
+                    if constexpr (INV) w.y = -w.y;
+                    v[r] = cmul(v[r], w);
+                }
+            }
+            dft<T, R, INV>(v);
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst(j + (unsigned)(r * NS), p, v[r]);
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS>
 __device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
@@ -317,6 +397,56 @@ __device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
     fft_stages<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid);
+}
+
+// As lds_fft, with the first stage reading element n of pencil p from
+// src(n, p) instead of buf (which need not be filled: the call starts with a
+// barrier so that earlier readers of buf are done).  Returns after a barrier.
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class SRC>
+__device__ __forceinline__ void lds_fft_src(cpx<T> *buf, const cpx<T> *tw, int tid, const SRC &src)
+{
+    static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
+    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    __syncthreads();
+    stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
+    fft_stages<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid);
+}
+
+// As lds_fft, with the outputs of the last stage handed to dst(n, p, value)
+// instead of being written back to buf.  Returns after a barrier.
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS, class DST>
+__device__ __forceinline__ void fft_stages_dst(cpx<T> *buf, const cpx<T> *tw, int tid, const DST &dst)
+{
+    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    constexpr int R = pl.r[S];
+    if constexpr (S + 1 < pl.n) {
+        stockham_stage<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid);
+        fft_stages_dst<T, L, INV, P, NT, ES, PS, S + 1, NS * R>(buf, tw, tid, dst);
+    } else {
+        stockham_stage_dst<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid, dst);
+    }
+}
+
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class DST>
+__device__ __forceinline__ void lds_fft_dst(cpx<T> *buf, const cpx<T> *tw, int tid, const DST &dst)
+{
+    static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
+    fft_stages_dst<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid, dst);
+}
+
+// As lds_fft with both ends in memory: the first stage reads src(n, p), the
+// last stage hands its outputs to dst(n, p, value).  Needs two stages or
+// more.  Starts and returns with a barrier.
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class SRC, class DST>
+__device__ __forceinline__ void lds_fft_io(cpx<T> *buf, const cpx<T> *tw, int tid, const SRC &src,
+                                           const DST &dst)
+{
+    static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
+    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    static_assert(pl.n >= 2, "a single-stage transform cannot read and write memory");
+    __syncthreads();
+    stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
+    fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid, dst);
 }
 
 // ---------------------------------------------------------------- reductions

@@ -86,6 +86,10 @@ __device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+// FP32: the hardware square root (1 ulp) without the correctly rounded
+// fix-up sequence; FP64: the correctly rounded one
+__device__ __forceinline__ float d_sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double d_sqrt_fast(double x) { return sqrt(x); }
 __device__ __forceinline__ bool d_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool d_finite(double x) { return isfinite(x); }
 // base-2 logarithm and power: the hardware transcendental instructions for
@@ -361,8 +365,16 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
 
     for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
-    for (int n = tid / P; n < L; n += RSTEP)
-        buf[n * P + p] = cvalid ? src[cbase + n * a.elem_stride] : cpx<T>{T(0), T(0)};
+    // the first stage of a transform reads element n of this thread's column
+    // from memory and the last one writes it back (the stages assign
+    // pencil p = tid % P to this thread, as NT is a multiple of P)
+    const long long es = a.elem_stride;
+    auto ld = [&](unsigned n, unsigned) {
+        return cvalid ? src[cbase + n * es] : cpx<T>{T(0), T(0)};
+    };
+    auto st = [&](unsigned n, unsigned, cpx<T> v) {
+        if (cvalid) dst[cbase + n * es] = v;
+    };
     // reciprocal-space operands are fetched now so that their latency overlaps
     // the forward transform: v_ext(G) for the Hartree+ion field, the
     // Wang-Teter kernel for the nonlocal field (element n of column c is the
@@ -385,13 +397,21 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
             }
         }
     }
-    __syncthreads();
+    constexpr bool MULTI = make_plan(L, sizeof(T) == 4).n >= 2;
     if (op == GO_NONE) {
-        if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
-        else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
+        if constexpr (MULTI) {
+            if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1>(buf, tw, tid, ld, st);
+            else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tid, ld, st);
+            return;
+        } else {
+            for (int n = tid / P; n < L; n += RSTEP) buf[n * P + p] = ld(n, p);
+            __syncthreads();
+            if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
+            else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
+        }
     } else {
         // axis 0: element n is i0, column c is (i1, k2)
-        lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
+        lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, ld);
         const Geom &g = a.g;
         const int t = opaque(tid);
         const int i1 = cvalid ? (int)(c / g.n2h) : 0;
@@ -446,10 +466,12 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
             }
         }
         __syncthreads();
-        if (op != GO_SCALE) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
+        if (op != GO_SCALE) {
+            lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tid, st);
+            return;
+        }
     }
-    if (cvalid)
-        for (int n = tid / P; n < L; n += RSTEP) dst[cbase + n * a.elem_stride] = buf[n * P + p];
+    for (int n = tid / P; n < L; n += RSTEP) st(n, p, buf[n * P + p]);
 }
 
 // ================================================================ spline, axis 0
@@ -497,11 +519,11 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
             if (n < L) buf[n * P + p] = cscale(xs[q], T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k));
         }
         __syncthreads();
-        lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
+        // the last stage writes this thread's column (pencil p) to memory
         cpx<T> *dst = (cpx<T> *)a.dst + ((long long)kk * a.nbatch + b) * a.fstride;
-        if (cvalid)
-            for (int n = tid / P; n < L; n += RSTEP) dst[c + n * es] = buf[n * P + p];
-        __syncthreads();
+        lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tid, [&](unsigned n, unsigned, cpx<T> v) {
+            if (cvalid) dst[c + n * es] = v;
+        });
     }
 }
 
@@ -537,11 +559,11 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
         gn[q] = (n < L && cvalid) ? d_sqrt(gvec2<T>(g, freq(n, L), m1, m2)) : T(0);
     }
     for (int kk = 0; kk < a.K; ++kk) {
+        // the first stage reads this thread's column (pencil p) from memory
         const cpx<T> *src = (const cpx<T> *)a.src + ((long long)kk * a.nbatch + b) * a.fstride;
-        for (int n = tid / P; n < L; n += RSTEP)
-            buf[n * P + p] = cvalid ? src[c + n * es] : cpx<T>{T(0), T(0)};
-        __syncthreads();
-        lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
+        lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, [&](unsigned n, unsigned) {
+            return cvalid ? src[c + n * es] : cpx<T>{T(0), T(0)};
+        });
         const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -1064,43 +1086,53 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         const int t = opaque(tid);
         const int kind = a.kind[f];
         const int knot = a.knot0 + f;
+        if (kind == FK_KNOT) {
+            // EXACT spline: f_i = rho^a L_i(k_F), written to buf first
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int idx = t + q * NTP;
-            if (idx >= PAIRS) continue;
-            const int i1 = idx / M, n = idx % M;
-            const cpx<T> xq = xs[idx];
-            const T xv[2] = {xq.x, xq.y};
-            T o[2];
+            for (int q = 0; q < PER; ++q) {
+                const int idx = t + q * NTP;
+                if (idx >= PAIRS) continue;
+                const int i1 = idx / M, n = idx % M;
+                const cpx<T> xq = xs[idx];
+                const T xv[2] = {xq.x, xq.y};
+                T o[2];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const T v = xv[c];
-                const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
-                if (kind == FK_RHO) o[c] = a.in_is_phi ? v * v : v;
-                else if (kind == FK_RAW) o[c] = v;
-                else if (kind == FK_PHI) o[c] = a.in_is_phi ? v : d_sqrt(rho);
-                else {
+                for (int c = 0; c < 2; ++c) {
+                    const T v = xv[c];
+                    const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
                     const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
-                    if (kind == FK_RHOB) {
-                        o[c] = d_exp2(T(a.beta) * lu);
-                    } else {
-                        int j;
-                        T t;
-                        bool inside;
-                        knot_bracket_kf(kf_from_log2(lu), a.knots, j, t, inside);
-                        const T L = a.knots.nk == 1 ? T(1)
-                                                    : (j == knot ? T(1) - t
-                                                                 : (j + 1 == knot ? t : T(0)));
-                        o[c] = L == T(0) ? T(0) : L * d_exp2(T(a.alpha) * lu);
-                    }
+                    int j;
+                    T t;
+                    bool inside;
+                    knot_bracket_kf(kf_from_log2(lu), a.knots, j, t, inside);
+                    const T L = a.knots.nk == 1 ? T(1)
+                                                : (j == knot ? T(1) - t
+                                                             : (j + 1 == knot ? t : T(0)));
+                    o[c] = L == T(0) ? T(0) : L * d_exp2(T(a.alpha) * lu);
                 }
+                buf[n * A + i1] = {o[0], o[1]};
             }
-            buf[n * A + i1] = {o[0], o[1]};
+            __syncthreads();
+            // axis 2: half-length complex transforms of the N1 rows
+            lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
+        } else {
+            // axis 2: half-length complex transforms of the N1 rows, the first
+            // stage computing element n of row i1 (rho, phi or rho^beta at the
+            // points 2n, 2n + 1) from the input plane
+            auto field = [&](T v) -> T {
+                if (kind == FK_RAW) return v;
+                if (kind == FK_RHO) return a.in_is_phi ? v * v : v;
+                const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
+                if (kind == FK_PHI) return a.in_is_phi ? v : d_sqrt_fast(rho);
+                return rho > T(0) ? d_exp2(T(a.beta) * d_log2(rho)) : T(0);   // FK_RHOB
+            };
+            lds_fft_src<T, M, false, N1, NTP, A, 1>(
+                buf, twM, t, [&](unsigned n, unsigned p) {
+                    const cpx<T> xq = xs[p * M + n];
+                    return cpx<T>{field(xq.x), field(xq.y)};
+                });
         }
         (void)knots;
-        __syncthreads();
-        // axis 2: half-length complex transforms of the N1 rows
-        lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         // unpack to the r2c half spectrum, pairs (k, M-k) in place, i1 fastest
         // and the same code for every pair: Z has period M, so k = 0 pairs
         // Z[0] with itself and yields X[0] and the Nyquist X[M] (real);
@@ -1119,15 +1151,12 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             buf[(M - k) * A + i1] = xm;
         }
         __syncthreads();
-        // axis 1: the M + 1 columns
-        lds_fft<T, N1, false, M + 1, NTP, 1, A>(buf, tw1, t);
+        // axis 1: the M + 1 columns; the last stage writes element i1 of
+        // column k straight to out[i1 * (M + 1) + k]
         cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh +
                       (long long)i0 * N1 * (M + 1);
-        for (int o = t; o < N1 * (M + 1); o += NTP) {
-            const int i1 = o / (M + 1), k = o % (M + 1);
-            out[o] = buf[k * A + i1];
-        }
-        __syncthreads();
+        lds_fft_dst<T, N1, false, M + 1, NTP, 1, A>(
+            buf, tw1, t, [&](unsigned n, unsigned p, cpx<T> v) { out[n * (M + 1) + p] = v; });
     }
 }
 
@@ -1143,12 +1172,10 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
     constexpr int A = plane_A<N1>();
     constexpr int HALF = M / 2 + 1;
     tid = opaque(tid);
-    for (int o = tid; o < N1 * (M + 1); o += NTP) {
-        const int i1 = o / (M + 1), k = o % (M + 1);
-        buf[k * A + i1] = spec[o];
-    }
-    __syncthreads();
-    lds_fft<T, N1, true, M + 1, NTP, 1, A>(buf, tw1, tid);
+    // axis 1: the first stage reads column k (element i1) straight from the
+    // spectrum, spec[i1 * (M + 1) + k]
+    lds_fft_src<T, N1, true, M + 1, NTP, 1, A>(
+        buf, tw1, tid, [&](unsigned n, unsigned p) { return spec[n * (M + 1) + p]; });
     // c2r pack of the pairs (k, M - k), k = 0..M/2, of every row, i1 fastest
     // and the same code for every pair: k = 0 pairs the DC element with the
     // Nyquist one (imaginary parts dropped) and also writes row M, which the
