@@ -1116,9 +1116,10 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             // axis 2: half-length complex transforms of the N1 rows
             lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         } else {
-            // axis 2: half-length complex transforms of the N1 rows, the first
-            // stage computing element n of row i1 (rho, phi or rho^beta at the
-            // points 2n, 2n + 1) from the input plane
+            // rho, phi or rho^beta at the points 2n, 2n + 1 of row i1 into
+            // element n (computing them in the first FFT stage instead puts the
+            // transcendentals on the fewer threads that hold butterflies:
+            // measured slower), then the axis-2 half-length transforms
             auto field = [&](T v) -> T {
                 if (kind == FK_RAW) return v;
                 if (kind == FK_RHO) return a.in_is_phi ? v * v : v;
@@ -1126,11 +1127,16 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 if (kind == FK_PHI) return a.in_is_phi ? v : d_sqrt_fast(rho);
                 return rho > T(0) ? d_exp2(T(a.beta) * d_log2(rho)) : T(0);   // FK_RHOB
             };
-            lds_fft_src<T, M, false, N1, NTP, A, 1>(
-                buf, twM, t, [&](unsigned n, unsigned p) {
-                    const cpx<T> xq = xs[p * M + n];
-                    return cpx<T>{field(xq.x), field(xq.y)};
-                });
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const unsigned idx = (unsigned)(t + q * NTP);
+                if (idx >= (unsigned)PAIRS) continue;
+                const unsigned i1 = idx / (unsigned)M, n = idx % (unsigned)M;
+                const cpx<T> xq = xs[idx];
+                buf[n * A + i1] = {field(xq.x), field(xq.y)};
+            }
+            __syncthreads();
+            lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         }
         (void)knots;
         // unpack to the r2c half spectrum, pairs (k, M-k) in place, i1 fastest
