@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 2
+#define OFDFT_ABI_VERSION 3
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
@@ -303,7 +303,10 @@ void ofdft_server_destroy(ofdft_server *srv);
  * legacy NULL stream) and are not used while per-pass timing is on.
  * The autotuner times the schedule choices -- fused plane kernels or
  * separate row and column passes where both apply, the block order of the
- * column passes, the number of spline knots per batch -- on nbatch densities
+ * column passes, the number of spline knots per batch, and the number of
+ * sub-batches a batch is split into and pipelined over two HIP streams (the
+ * grid's own second stream, forked from and joined back into the caller's;
+ * results are the same for every split) -- on nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
  * density, nbatch 1), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
@@ -311,6 +314,7 @@ void ofdft_server_destroy(ofdft_server *srv);
 typedef struct {
     int32_t plane, col_tile_major, knot_batch, candidates;
     double best_ms, default_ms;   /* per evaluation call */
+    int32_t pipe, reserved;       /* sub-batches of the pipelined evaluation */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,

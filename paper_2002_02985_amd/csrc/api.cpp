@@ -145,6 +145,12 @@ struct ofdft_grid {
     int tune_col_tile_major = 0;   // block order of the column passes
     int tune_plane = 1;            // fused plane kernels where the plane fits in LDS
     int tune_kb = MAXKB;           // knots per spline batch
+    int tune_pipe = 1;             // sub-batches pipelined over two streams
+    // second stream of the pipelined evaluation and its events (created on
+    // first use)
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_stagger = nullptr;
+    bool stagger_after_fwd = false;
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
     double precond_q2 = 1.0;                    // optimiser preconditioner q0^2
     bool large_ions = false;                    // tiled structure factor, binned Ewald
@@ -527,7 +533,7 @@ static Layout layout_of(const ofdft_grid *g)
 
 template <typename T>
 static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data, int nfb, int nbatch,
-                             int inv, const int *ops, int kind)
+                             int inv, const int *ops, int kind, double *part = nullptr)
 {
     const Geom &G = g->geom;
     ColArgs a;
@@ -538,7 +544,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.nbatch = nbatch;
     a.inv = inv;
     a.g = G;
-    a.part = g->part;
+    a.part = part ? part : g->part;
     a.pstride = g->pstride;
     a.vext = g->vext;
     a.gtab = g->gtab;
@@ -589,12 +595,48 @@ static int combine_flavour(const RowInvArgs &rc)
     return f;
 }
 
+static ofdft_status ensure_lane(ofdft_grid *g)
+{
+    if (g->s2) return OFDFT_OK;
+    HIP_TRY(hipStreamCreateWithFlags(&g->s2, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&g->ev_stagger, hipEventDisableTiming));
+    return OFDFT_OK;
+}
+
+// The workspace of densities b0 .. b0 + nb - 1 of a batch: every per-density
+// buffer offset to density b0 (the spectra slots of the sub-batch are laid
+// out as for a batch of nb, inside its own share of the workspace).
+struct Work {
+    char *spec, *kspec;
+    void *acc1, *acc2;
+    double *part, *sums, *h_sums;
+};
+
 template <typename T>
-// Enqueues every launch of one evaluation on s and the copy of the FP64 sums
-// to the pinned host array; no allocation, synchronisation or host-to-device
-// copy, so that the sequence can be captured in a HIP graph.
+static Work work_of(const ofdft_grid *g, int b0)
+{
+    const Geom &G = g->geom;
+    const size_t cb = 2 * sizeof(T);
+    Work w;
+    w.spec = (char *)g->spec + (size_t)4 * b0 * G.Nh * cb;
+    w.kspec = g->kspec ? (char *)g->kspec + (size_t)MAXKB * b0 * G.Nh * cb : nullptr;
+    w.acc1 = g->acc1 ? (char *)g->acc1 + (size_t)b0 * G.N * sizeof(T) : nullptr;
+    w.acc2 = g->acc2 ? (char *)g->acc2 + (size_t)b0 * G.N * sizeof(T) : nullptr;
+    w.part = g->part + (size_t)b0 * NSLOT * g->pstride;
+    w.sums = g->sums + (size_t)b0 * NSLOT;
+    w.h_sums = g->h_sums + (size_t)b0 * NSLOT;
+    return w;
+}
+
+template <typename T>
+// Enqueues every launch of one evaluation of nb densities on s and the copy
+// of their FP64 sums to the pinned host array; no allocation,
+// synchronisation or host-to-device copy, so that the sequence can be
+// captured in a HIP graph.  d_in, d_v, d_g and w point at the first density.
 static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
-                                 void *d_g, hipStream_t s)
+                                 void *d_g, hipStream_t s, const Work &w)
 {
     const Geom &G = g->geom;
     const Layout l = layout_of(g);
@@ -602,7 +644,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     const bool spline = terms & OFDFT_TERM_SPLINE;
     const bool exact = spline && g->func.nl_mode == OFDFT_NL_EXACT;
     const long long fs = (long long)nb * G.Nh;   // stride between field slots
-    char *spec = (char *)g->spec;
+    char *spec = w.spec;
     const size_t cb = 2 * sizeof(T);
     auto slot_ptr = [&](int sl) { return (void *)(spec + (size_t)sl * fs * cb); };
 
@@ -610,7 +652,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     RowFwdArgs rf;
     std::memset(&rf, 0, sizeof(rf));
     rf.in = d_in;
-    rf.out = g->spec;
+    rf.out = spec;
     rf.out_fstride = fs;
     rf.nfields = l.nfwd;
     if (l.s_rho >= 0) rf.kind[l.s_rho] = FK_RHO;
@@ -621,7 +663,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rf.alpha = g->func.alpha;
     rf.knots = g->knots;
     rf.partials = 1;
-    rf.part = g->part;
+    rf.part = w.part;
     rf.pstride = g->pstride;
     rf.twM = g->twM;
     rf.twN = g->twN;
@@ -631,18 +673,19 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     int nb_row = 0;
     if (plane) TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nb_row, s));
     else TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
+    if (g->stagger_after_fwd) HIP_TRY(hipEventRecord(g->ev_stagger, s));
 
     int nb_col0 = 0;
     if (l.nfwd > 0) {
         // 2. axis 1 forward
         if (!plane)
-            ST_TRY(col_pass<T>(g, s, 1, g->spec, l.nfwd * nb, nb, 0, nullptr, PS_COL1_FWD));
+            ST_TRY(col_pass<T>(g, s, 1, spec, l.nfwd * nb, nb, 0, nullptr, PS_COL1_FWD, w.part));
         // 3. axis 0: forward, reciprocal-space term, inverse
         int ops[4] = {0, 0, 0, 0};
         if (l.s_rho >= 0) ops[l.s_rho] = GO_HEXT;
         if (l.s_phi >= 0) ops[l.s_phi] = GO_VW;
         if (l.s_rhob >= 0) ops[l.s_rhob] = spline ? GO_SCALE : GO_WT;
-        ST_TRY(col_pass<T>(g, s, 0, g->spec, l.nfwd * nb, nb, 0, ops, PS_COL0_G));
+        ST_TRY(col_pass<T>(g, s, 0, spec, l.nfwd * nb, nb, 0, ops, PS_COL0_G, w.part));
         nb_col0 = col_blocks<T>(G.n0, (long long)G.n1 * G.n2h);
     }
 
@@ -655,7 +698,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             KnotArgs ka;
             std::memset(&ka, 0, sizeof(ka));
             ka.src = slot_ptr(l.s_rhob);
-            ka.dst = g->kspec;
+            ka.dst = w.kspec;
             ka.fstride = G.Nh;
             ka.ncols = (long long)G.n1 * G.n2h;
             ka.knot0 = k0;
@@ -666,10 +709,10 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ka.g = G;
             TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
             if (!plane)
-                ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1));
+                ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1, w.part));
             RowInvArgs ri;
             std::memset(&ri, 0, sizeof(ri));
-            ri.spec = g->kspec;
+            ri.spec = w.kspec;
             ri.spec_fstride = fs;
             ri.nfields = K;
             ri.mode = EP_KNOTS;
@@ -677,8 +720,8 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ri.in_is_phi = in_is_phi;
             ri.exact = exact;
             ri.spline = 1;
-            ri.acc1 = g->acc1;
-            ri.acc2 = g->acc2;
+            ri.acc1 = w.acc1;
+            ri.acc2 = w.acc2;
             ri.acc_init = (k0 == 0);
             ri.knot0 = k0;
             ri.knots = g->knots;
@@ -693,7 +736,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             if (exact) {
                 // f_i = rho^a L_i(k~): r2c, axis 1, then axis 0 with omega_i, summed into H
                 RowFwdArgs ef = rf;
-                ef.out = g->kspec;
+                ef.out = w.kspec;
                 ef.out_fstride = fs;
                 ef.nfields = K;
                 for (int f = 0; f < K; ++f) ef.kind[f] = FK_KNOT;
@@ -704,30 +747,30 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
                     TIMED(PS_EXACT_FWD, launch_plane_fwd<T>(G, nb, ef, nbe, s));
                 } else {
                     TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
-                    ST_TRY(col_pass<T>(g, s, 1, g->kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD));
+                    ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD, w.part));
                 }
                 KnotArgs kc = ka;
-                kc.src = g->kspec;
+                kc.src = w.kspec;
                 kc.dst = slot_ptr(l.s_h);
                 kc.accumulate = (k0 > 0);
                 TIMED(PS_EXACT_ACC, launch_knot_acc<T>(kc, s));
             }
         }
         if (exact) {
-            ST_TRY(col_pass<T>(g, s, 0, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
+            ST_TRY(col_pass<T>(g, s, 0, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC, w.part));
             if (!plane)
-                ST_TRY(col_pass<T>(g, s, 1, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC));
+                ST_TRY(col_pass<T>(g, s, 1, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC, w.part));
         }
     }
 
     // 4. axis 1 inverse of the fields that return to real space
     if (l.ninv > 0 && !plane)
-        ST_TRY(col_pass<T>(g, s, 1, g->spec, l.ninv * nb, nb, 1, nullptr, PS_COL1_INV));
+        ST_TRY(col_pass<T>(g, s, 1, spec, l.ninv * nb, nb, 1, nullptr, PS_COL1_INV, w.part));
 
     // 5. axis-2 c2r and the final combine
     RowInvArgs rc;
     std::memset(&rc, 0, sizeof(rc));
-    rc.spec = g->spec;
+    rc.spec = spec;
     rc.spec_fstride = fs;
     rc.mode = EP_COMBINE;
     rc.in = d_in;
@@ -742,12 +785,12 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rc.lambda_vw = g->func.lambda_vw;
     rc.alpha = g->func.alpha;
     rc.floor = g->func.rho_floor;
-    rc.acc1 = g->acc1;
-    rc.acc2 = g->acc2;
+    rc.acc1 = w.acc1;
+    rc.acc2 = w.acc2;
     rc.knots = g->knots;
     rc.v_out = d_v;
     rc.g_out = d_g;
-    rc.part = g->part;
+    rc.part = w.part;
     rc.pstride = g->pstride;
     rc.nbatch = nb;
     rc.twM = g->twM;
@@ -765,9 +808,45 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     cnt.n[SL_H] = cnt.n[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
     cnt.n[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
     cnt.n[SL_NL] = cnt.n[SL_GPHI] = cnt.n[SL_GG] = cnt.n[SL_PHIPHI] = nb_inv;
-    TIMED(PS_FINALIZE, launch_finalize(g->part, g->pstride, cnt, nb, g->sums, s));
-    HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, (size_t)nb * NSLOT * sizeof(double),
+    TIMED(PS_FINALIZE, launch_finalize(w.part, g->pstride, cnt, nb, w.sums, s));
+    HIP_TRY(hipMemcpyAsync(w.h_sums, w.sums, (size_t)nb * NSLOT * sizeof(double),
                            hipMemcpyDeviceToHost, s));
+    return OFDFT_OK;
+}
+
+// Enqueues an evaluation of nb densities as tune_pipe sub-batches that
+// alternate between s and the grid's second stream s2 (forked from s and
+// joined back into it, so the caller sees the whole evaluation on s).  The
+// second lane starts once the first sub-batch's forward pass is done; from
+// then on the memory-bound column passes of one sub-batch run beside the
+// arithmetic-bound plane passes of the other.  Every density goes through
+// the same launches and gives the same results as in one batch.
+template <typename T>
+static ofdft_status eval_enqueue_pipe(ofdft_grid *g, int nb, const void *d_in, int in_is_phi,
+                                      void *d_v, void *d_g, hipStream_t s)
+{
+    const int pipe = std::max(1, std::min(g->tune_pipe, nb));
+    if (pipe == 1 || g->timer.on)
+        return eval_enqueue<T>(g, nb, d_in, in_is_phi, d_v, d_g, s, work_of<T>(g, 0));
+    ST_TRY(ensure_lane(g));
+    const size_t N = (size_t)g->geom.N;
+    const int per = (nb + pipe - 1) / pipe;
+    HIP_TRY(hipEventRecord(g->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(g->s2, g->ev_fork, 0));
+    for (int j = 0, b0 = 0; b0 < nb; ++j, b0 += per) {
+        const int n = std::min(per, nb - b0);
+        hipStream_t sj = (j % 2 == 0) ? s : g->s2;
+        if (j == 1) HIP_TRY(hipStreamWaitEvent(g->s2, g->ev_stagger, 0));
+        const void *in = (const char *)d_in + b0 * N * sizeof(T);
+        void *v = d_v ? (char *)d_v + b0 * N * sizeof(T) : nullptr;
+        void *gv = d_g ? (char *)d_g + b0 * N * sizeof(T) : nullptr;
+        g->stagger_after_fwd = (j == 0);
+        const ofdft_status st = eval_enqueue<T>(g, n, in, in_is_phi, v, gv, sj, work_of<T>(g, b0));
+        g->stagger_after_fwd = false;
+        ST_TRY(st);
+    }
+    HIP_TRY(hipEventRecord(g->ev_join, g->s2));
+    HIP_TRY(hipStreamWaitEvent(s, g->ev_join, 0));
     return OFDFT_OK;
 }
 
@@ -789,7 +868,7 @@ static ofdft_status eval_graph(ofdft_grid *g, int nb, const void *d_in, int in_i
             g->graphs.erase(g->graphs.begin() + lru);
         }
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const ofdft_status st = eval_enqueue<T>(g, nb, d_in, in_is_phi, d_v, d_g, s);
+        const ofdft_status st = eval_enqueue_pipe<T>(g, nb, d_in, in_is_phi, d_v, d_g, s);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(s, &graph);
         if (st != OFDFT_OK) {
@@ -826,7 +905,7 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     if (g->use_graphs && !g->timer.on && s != nullptr) {
         ST_TRY(eval_graph<T>(g, nb, d_in, in_is_phi, d_v, d_g, s));
     } else {
-        ST_TRY(eval_enqueue<T>(g, nb, d_in, in_is_phi, d_v, d_g, s));
+        ST_TRY(eval_enqueue_pipe<T>(g, nb, d_in, in_is_phi, d_v, d_g, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     timer_collect(g);
@@ -1026,6 +1105,15 @@ static void grid_free(ofdft_grid *g)
     g->h_sums = nullptr;
     for (hipEvent_t e : g->timer.ev) (void)hipEventDestroy(e);
     g->timer.ev.clear();
+    for (hipEvent_t *e : {&g->ev_fork, &g->ev_join, &g->ev_stagger})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    if (g->s2) {
+        (void)hipStreamDestroy(g->s2);
+        g->s2 = nullptr;
+    }
 }
 
 // Large cells: v_ext(G) and the Ewald reciprocal sum from the tiled direct
@@ -1601,7 +1689,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
 // keeps the fastest; results are shared by all grids of the same shape,
 // precision, functional and batch size in the process.
 struct TuneVal {
-    int plane, tile_major, kb;
+    int plane, tile_major, kb, pipe;
 };
 using TuneKey = std::tuple<int, int, int, int, uint32_t, int, int, int>;
 static std::mutex g_tune_mu;
@@ -1621,6 +1709,7 @@ static void tune_apply_cached(ofdft_grid *g, int nb)
     g->tune_plane = it->second.plane;
     g->tune_col_tile_major = it->second.tile_major;
     g->tune_kb = it->second.kb;
+    g->tune_pipe = it->second.pipe;
     graphs_clear(g);
 }
 
@@ -1638,10 +1727,12 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
     for (int pl : {1, 0}) {
         if (!pl && !plane_ok) continue;
         for (int tm : {0, 1})
-            for (int kb : {MAXKB, MAXKB / 2}) {
-                if (!spline && kb != MAXKB) continue;
-                cand.push_back({pl, tm, kb});
-            }
+            for (int kb : {MAXKB, MAXKB / 2})
+                for (int pp : {1, 2, 4}) {
+                    if (!spline && kb != MAXKB) continue;
+                    if (pp > nb) continue;
+                    cand.push_back({pl, tm, kb, pp});
+                }
     }
     std::vector<ofdft_energy> e((size_t)nb);
     double best = 1e300, dflt = 0.0;
@@ -1650,6 +1741,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         g->tune_plane = cand[c].plane;
         g->tune_col_tile_major = cand[c].tile_major;
         g->tune_kb = cand[c].kb;
+        g->tune_pipe = cand[c].pipe;
         graphs_clear(g);
         ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));   // warm-up
         double t[3];
@@ -1668,6 +1760,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
     g->tune_plane = pick.plane;
     g->tune_col_tile_major = pick.tile_major;
     g->tune_kb = pick.kb;
+    g->tune_pipe = pick.pipe;
     graphs_clear(g);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1680,6 +1773,8 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         out->candidates = (int32_t)cand.size();
         out->best_ms = best;
         out->default_ms = dflt;
+        out->pipe = pick.pipe;
+        out->reserved = 0;
     }
     return OFDFT_OK;
 }
@@ -1762,6 +1857,7 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
     g->ctx = ctx;
     if (const char *e = std::getenv("OFDFT_COL_TILE_MAJOR")) g->tune_col_tile_major = std::atoi(e);
+    if (const char *e = std::getenv("OFDFT_PIPE")) g->tune_pipe = std::max(1, std::atoi(e));
     g->large_ions = use_large_ions(cell->natoms);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);

@@ -70,10 +70,11 @@ class Request(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("plane", ctypes.c_int32), ("col_tile_major", ctypes.c_int32),
                 ("knot_batch", ctypes.c_int32), ("candidates", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("pipe", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class ServeStats(ctypes.Structure):
