@@ -434,19 +434,27 @@ __device__ __forceinline__ void lds_fft_dst(cpx<T> *buf, const cpx<T> *tw, int t
     fft_stages_dst<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid, dst);
 }
 
-// As lds_fft with both ends in memory: the first stage reads src(n, p), the
-// last stage hands its outputs to dst(n, p, value).  Needs two stages or
-// more.  Starts and returns with a barrier.
+// As lds_fft with both ends outside buf: the first stage reads src(n, p),
+// the last stage hands its outputs to dst(n, p, value) (a single-stage
+// transform writes buf and then hands every element to dst).  Starts and
+// returns with a barrier.
 template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class SRC, class DST>
 __device__ __forceinline__ void lds_fft_io(cpx<T> *buf, const cpx<T> *tw, int tid, const SRC &src,
                                            const DST &dst)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
     constexpr Plan pl = make_plan(L, sizeof(T) == 4);
-    static_assert(pl.n >= 2, "a single-stage transform cannot read and write memory");
     __syncthreads();
     stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
-    fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid, dst);
+    if constexpr (pl.n >= 2) {
+        fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid, dst);
+    } else {
+        for (unsigned o = (unsigned)tid; o < (unsigned)(L * P); o += NT) {
+            const unsigned n = o / (unsigned)P, p = o % (unsigned)P;
+            dst(n, p, buf[n * ES + p * PS]);
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- reductions

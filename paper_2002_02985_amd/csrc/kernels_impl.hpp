@@ -1031,7 +1031,6 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int A = plane_A<N1>();
     constexpr int PAIRS = N1 * M;
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
-    constexpr int HALF = M / 2 + 1;
     __shared__ cpx<T> buf[(M + 1) * A];
     __shared__ cpx<T> xs[N1 * M];   // the input plane, read once from HBM
     __shared__ cpx<T> tws[N1 + 2 * M + 1];   // twiddles of both axes and the r2c unpack
@@ -1139,30 +1138,22 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         }
         (void)knots;
-        // unpack to the r2c half spectrum, pairs (k, M-k) in place, i1 fastest
-        // and the same code for every pair: Z has period M, so k = 0 pairs
-        // Z[0] with itself and yields X[0] and the Nyquist X[M] (real);
-        // k = M/2 writes one value twice
-        for (unsigned w = (unsigned)t; w < (unsigned)(N1 * HALF); w += NTP) {
-            const unsigned k = w / (unsigned)N1, i1 = w % (unsigned)N1;
-            const cpx<T> zk = buf[k * A + i1];
-            const cpx<T> zm = buf[(k == 0 ? 0u : M - k) * A + i1];
-            cpx<T> xk = r2c_unpack(zk, zm, twN[k]);
-            cpx<T> xm = r2c_unpack(zm, zk, twN[M - k]);
-            if (k == 0) {
-                xk.y = T(0);
-                xm.y = T(0);
-            }
-            buf[k * A + i1] = xk;
-            buf[(M - k) * A + i1] = xm;
-        }
-        __syncthreads();
-        // axis 1: the M + 1 columns; the last stage writes element i1 of
-        // column k straight to out[i1 * (M + 1) + k]
+        // axis 1 over the M + 1 columns: the first stage unpacks element i1
+        // of column k of the r2c half spectrum from Z[k] and Z[M-k] of row
+        // i1 (Z has period M; X[0] and X[M] are real), the last stage writes
+        // it straight to out[i1 * (M + 1) + k]
         cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh +
                       (long long)i0 * N1 * (M + 1);
-        lds_fft_dst<T, N1, false, M + 1, NTP, 1, A>(
-            buf, tw1, t, [&](unsigned n, unsigned p, cpx<T> v) { out[n * (M + 1) + p] = v; });
+        lds_fft_io<T, N1, false, M + 1, NTP, 1, A>(
+            buf, tw1, t,
+            [&](unsigned n, unsigned p) {
+                const unsigned k = p == (unsigned)M ? 0u : p;
+                const unsigned km = k == 0 ? 0u : M - k;
+                cpx<T> x = r2c_unpack(buf[k * A + n], buf[km * A + n], twN[p]);
+                if (k == 0) x.y = T(0);
+                return x;
+            },
+            [&](unsigned n, unsigned p, cpx<T> v) { out[n * (M + 1) + p] = v; });
     }
 }
 
@@ -1176,29 +1167,23 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
                                               const cpx<T> *twN, int tid)
 {
     constexpr int A = plane_A<N1>();
-    constexpr int HALF = M / 2 + 1;
     tid = opaque(tid);
     // axis 1: the first stage reads column k (element i1) straight from the
     // spectrum, spec[i1 * (M + 1) + k]
     lds_fft_src<T, N1, true, M + 1, NTP, 1, A>(
         buf, tw1, tid, [&](unsigned n, unsigned p) { return spec[n * (M + 1) + p]; });
-    // c2r pack of the pairs (k, M - k), k = 0..M/2, of every row, i1 fastest
-    // and the same code for every pair: k = 0 pairs the DC element with the
-    // Nyquist one (imaginary parts dropped) and also writes row M, which the
-    // axis-2 transforms do not read; k = M/2 writes one value twice
-    for (unsigned w = (unsigned)tid; w < (unsigned)(N1 * HALF); w += NTP) {
-        const unsigned k = w / (unsigned)N1, i1 = w % (unsigned)N1;
-        cpx<T> xk = buf[k * A + i1];
-        cpx<T> xm = buf[(M - k) * A + i1];
-        if (k == 0) {
+    // axis 2: the first stage forms element n of row i1 of the half-length
+    // input by the c2r pack Z[n] = (X[n] + conj X[M-n]) + i (X[n] - conj
+    // X[M-n]) conj(W^n) (imaginary parts of X[0] and X[M] dropped)
+    lds_fft_src<T, M, true, N1, NTP, A, 1>(buf, twM, tid, [&](unsigned n, unsigned p) {
+        cpx<T> xk = buf[n * A + p];
+        cpx<T> xm = buf[(M - n) * A + p];
+        if (n == 0) {
             xk.y = T(0);
             xm.y = T(0);
         }
-        buf[k * A + i1] = c2r_pack(xk, xm, twN[k]);
-        buf[(M - k) * A + i1] = c2r_pack(xm, xk, twN[M - k]);
-    }
-    __syncthreads();
-    lds_fft<T, M, true, N1, NTP, A, 1>(buf, twM, tid);
+        return c2r_pack(xk, xm, twN[n]);
+    });
 }
 
 template <typename T, int N1, int M, int MODE, int CF>
