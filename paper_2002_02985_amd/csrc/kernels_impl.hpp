@@ -812,8 +812,21 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
     lds_fft<T, M, true, P, NT, PS>(buf, twM, tid);
 }
 
-template <typename T, int M, int CF>
-__global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
+// The knot epilogue is instantiated with CF = CB_SPL (S3S4) or CB_SPL |
+// CB_EXACT and asks for at least 4 resident waves per SIMD (128 VGPRs):
+// measured faster than the 3 its unconstrained allocation allows.
+#ifndef OFDFT_ROW_KNOTS_MINW
+#define OFDFT_ROW_KNOTS_MINW 4
+#endif
+#ifndef OFDFT_ROW_S3S4_MINW
+#define OFDFT_ROW_S3S4_MINW OFDFT_ROW_KNOTS_MINW
+#endif
+template <int MODE, int CF> constexpr int row_inv_minw()
+{
+    return MODE != EP_KNOTS ? 1 : ((CF & CB_EXACT) ? OFDFT_ROW_KNOTS_MINW : OFDFT_ROW_S3S4_MINW);
+}
+template <typename T, int M, int CF, int MODE>
+__global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowInvArgs a, Geom g)
 {
     constexpr int P = row_P<T, M>();
     constexpr int PS = P + 1;
@@ -843,8 +856,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
         lds_at[q] = n * PS + p;
     }
 
-    // the fixed-term-set instantiations (CF != 0) hold the combine only
-    if (CF == 0 && a.mode == EP_STORE) {
+    // one instantiation per mode, so that each holds only the registers its
+    // own epilogue needs (the fixed term sets, CF != 0, are combines)
+    if constexpr (MODE == EP_STORE) {
         for (int f = 0; f < a.nfields; ++f) {
             c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
             T *out = (T *)a.out + ((long long)f * a.nbatch + b) * g.N;
@@ -863,8 +877,10 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
     for (int q = 0; q < PER; ++q)
         xin[q] = valid[q] ? *(const cpx<T> *)(in + offs[q]) : cpx<T>{T(0), T(0)};
 
-    if (CF == 0 && a.mode == EP_KNOTS) {
+    if constexpr (MODE == EP_KNOTS) {
         // step s4 for this batch of knots: v1 += L_i Phi_i, v2 += L_i' Phi_i
+        // (v2 for EXACT only, fixed at compile time by CF)
+        constexpr bool exact = (CF & CB_EXACT) != 0;
         int jj[PER][2];
         T tt[PER][2];
         cpx<T> v1[PER], v2[PER];
@@ -896,16 +912,16 @@ __global__ __launch_bounds__(NT) void k_row_inv(RowInvArgs a, Geom g)
             for (int q = 0; q < PER; ++q) {
                 if (!valid[q]) continue;
                 const cpx<T> z = buf[lds_at[q]];
-                knot_interp(jj[q], tt[q], i, nk, a.exact, z, v1[q], v2[q]);
+                knot_interp(jj[q], tt[q], i, nk, exact, z, v1[q], v2[q]);
             }
             __syncthreads();
         }
-        if (a.exact) {
+        if constexpr (exact) {
 #pragma unroll
             for (int q = 0; q < PER; ++q) knot_slope_scale(a.knots, jj[q], v2[q]);
         }
         T *acc1 = (T *)a.acc1 + (long long)b * g.N;
-        T *acc2 = a.exact ? (T *)a.acc2 + (long long)b * g.N : nullptr;
+        T *acc2 = exact ? (T *)a.acc2 + (long long)b * g.N : nullptr;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (!valid[q]) continue;
@@ -1456,7 +1472,14 @@ hipError_t row_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStrea
     nblocks = (int)((nrows + P - 1) / P);
     if (a.mode == EP_COMBINE && nblocks > a.pstride) return hipErrorInvalidValue;
     dim3 grid(nblocks, a.nbatch);
-    hipLaunchKernelGGL((k_row_inv<T, M, CF>), grid, dim3(NT), 0, s, a, g);
+    if (CF != 0 || a.mode == EP_COMBINE)
+        hipLaunchKernelGGL((k_row_inv<T, M, CF, EP_COMBINE>), grid, dim3(NT), 0, s, a, g);
+    else if (a.mode == EP_KNOTS && a.exact)
+        hipLaunchKernelGGL((k_row_inv<T, M, CB_SPL | CB_EXACT, EP_KNOTS>), grid, dim3(NT), 0, s, a, g);
+    else if (a.mode == EP_KNOTS)
+        hipLaunchKernelGGL((k_row_inv<T, M, CB_SPL, EP_KNOTS>), grid, dim3(NT), 0, s, a, g);
+    else
+        hipLaunchKernelGGL((k_row_inv<T, M, 0, EP_STORE>), grid, dim3(NT), 0, s, a, g);
     return hipGetLastError();
 }
 
