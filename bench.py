@@ -645,9 +645,12 @@ def main():
     nbytes = pass_bytes(name, NDENS, N, Nh, nfields, 4)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     plane = mixed["tuning"] is None or mixed["tuning"]["plane"]
-    kname = ({"row_fwd": "k_plane_fwd<float, 96, 48>", "row_inv": "k_plane_inv<float, 96, 48, 1>",
+    # kernel names as rocprofv3 prints them: the combine is the fixed term set
+    # TF + vW + Hartree/ion + WT (15), epilogue mode 1
+    kname = ({"row_fwd": "k_plane_fwd<float, 96, 48>",
+              "row_inv": "k_plane_inv<float, 96, 48, 1, 15>",
               "col0_g": "k_col<float, 96>"} if plane else
-             {"row_fwd": "k_row_fwd<float, 48>", "row_inv": "k_row_inv<float, 48>",
+             {"row_fwd": "k_row_fwd<float, 48>", "row_inv": "k_row_inv<float, 48, 15, 1>",
               "col0_g": "k_col<float, 96>", "col1_fwd": "k_col<float, 96>",
               "col1_inv": "k_col<float, 96>"}).get(name)
     traffic = measured_traffic(kname) if kname else None

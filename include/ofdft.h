@@ -301,12 +301,14 @@ void ofdft_server_destroy(ofdft_server *srv);
  * outputs); at most 8 graphs are kept per grid, and they are dropped when the
  * grid's workspace is reallocated.  Graphs need a capturable stream (not the
  * legacy NULL stream) and are not used while per-pass timing is on.
+ * ofdft_grid_set_pipeline splits every batch evaluation into nsub
+ * sub-batches (nsub >= 1, default 1) that alternate between the caller's
+ * stream and the grid's own second stream, forked from and joined back into
+ * the caller's; every density's results are the same for any split.  It is
+ * not used while per-pass timing is on.
  * The autotuner times the schedule choices -- fused plane kernels or
  * separate row and column passes where both apply, the block order of the
- * column passes, the number of spline knots per batch, and the number of
- * sub-batches a batch is split into and pipelined over two HIP streams (the
- * grid's own second stream, forked from and joined back into the caller's;
- * results are the same for every split) -- on nbatch densities
+ * column passes, the number of spline knots per batch -- on nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
  * density, nbatch 1), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
@@ -314,9 +316,10 @@ void ofdft_server_destroy(ofdft_server *srv);
 typedef struct {
     int32_t plane, col_tile_major, knot_batch, candidates;
     double best_ms, default_ms;   /* per evaluation call */
-    int32_t pipe, reserved;       /* sub-batches of the pipelined evaluation */
+    int32_t pipe, reserved;       /* the grid's sub-batch split (not tuned) */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
+ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
                                  void *hip_stream, ofdft_tune_result *result);
 ofdft_status ofdft_grid_tune(ofdft_grid *grid, ofdft_tune_result *result);

@@ -1728,11 +1728,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         if (!pl && !plane_ok) continue;
         for (int tm : {0, 1})
             for (int kb : {MAXKB, MAXKB / 2})
-                for (int pp : {1, 2, 4}) {
-                    if (!spline && kb != MAXKB) continue;
-                    if (pp > nb) continue;
-                    cand.push_back({pl, tm, kb, pp});
-                }
+                if (spline || kb == MAXKB) cand.push_back({pl, tm, kb, g->tune_pipe});
     }
     std::vector<ofdft_energy> e((size_t)nb);
     double best = 1e300, dflt = 0.0;
@@ -1857,7 +1853,6 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
     g->ctx = ctx;
     if (const char *e = std::getenv("OFDFT_COL_TILE_MAJOR")) g->tune_col_tile_major = std::atoi(e);
-    if (const char *e = std::getenv("OFDFT_PIPE")) g->tune_pipe = std::max(1, std::atoi(e));
     g->large_ions = use_large_ions(cell->natoms);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);
@@ -2057,6 +2052,15 @@ ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on)
     if (!grid) return fail(OFDFT_EINVAL, "null argument");
     grid->use_graphs = on != 0;
     if (!grid->use_graphs) graphs_clear(grid);
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null grid");
+    if (nsub < 1) return fail(OFDFT_EINVAL, "nsub must be at least 1");
+    grid->tune_pipe = nsub;
+    graphs_clear(grid);
     return OFDFT_OK;
 }
 

@@ -128,6 +128,7 @@ _SIGS = {
     "ofdft_serve_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServeStats)]),
     "ofdft_server_destroy": (None, [_P]),
     "ofdft_grid_set_graphs": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
     "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
     "ofdft_profile_enable": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -371,6 +372,10 @@ def ofdft_server_destroy(server):
 
 def ofdft_grid_set_graphs(grid, on=True):
     check(load().ofdft_grid_set_graphs(grid, 1 if on else 0))
+
+
+def ofdft_grid_set_pipeline(grid, nsub):
+    check(load().ofdft_grid_set_pipeline(grid, int(nsub)))
 
 
 def ofdft_grid_tune_dev(grid, nbatch, d_rho, stream):

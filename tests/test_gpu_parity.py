@@ -334,7 +334,7 @@ PIPE_CASES = ["c1_wt", "box_spline_exact", "plane_spline_s3s4"]
 
 @pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
 @pytest.mark.parametrize("name", PIPE_CASES)
-def test_pipelined_batch_matches_one_batch(name, prec, monkeypatch):
+def test_pipelined_batch_matches_one_batch(name, prec):
     """A batch split into sub-batches over two streams (2 or 4 of them, the
     last one short) gives every density's energy and potential bit for bit as
     one batch does, launched eagerly and replayed from graphs."""
@@ -346,9 +346,9 @@ def test_pipelined_batch_matches_one_batch(name, prec, monkeypatch):
     st = torch.cuda.Stream()
     out = {}
     for pipe in (1, 2, 4):
-        monkeypatch.setenv("OFDFT_PIPE", str(pipe))
         print("case pipe", name, prec, pipe, flush=True)
         with ofdft.Grid(cell, terms, precision=prec, **kw) as g, torch.cuda.stream(st):
+            ofdft.ofdft_grid_set_pipeline(g.handle, pipe)
             h = st.cuda_stream
             for graphs in (False, True, True):
                 ofdft.ofdft_grid_set_graphs(g.handle, graphs)
