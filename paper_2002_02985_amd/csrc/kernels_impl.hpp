@@ -90,6 +90,9 @@ __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 // fix-up sequence; FP64: the correctly rounded one
 __device__ __forceinline__ float d_sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double d_sqrt_fast(double x) { return sqrt(x); }
+// 1/x: FP32 the hardware reciprocal (1 ulp), FP64 the division
+__device__ __forceinline__ float d_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double d_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ bool d_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool d_finite(double x) { return isfinite(x); }
 // base-2 logarithm and power: the hardware transcendental instructions for
@@ -368,12 +371,13 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
     // the first stage of a transform reads element n of this thread's column
     // from memory and the last one writes it back (the stages assign
     // pencil p = tid % P to this thread, as NT is a multiple of P)
-    const long long es = a.elem_stride;
-    auto ld = [&](unsigned n, unsigned) {
-        return cvalid ? src[cbase + n * es] : cpx<T>{T(0), T(0)};
-    };
+    // 32-bit element offsets (a field holds fewer than 2^32 elements); a
+    // column past the end reads column 0 and writes nothing
+    const unsigned cofs = cvalid ? (unsigned)cbase : 0u;
+    const unsigned es = (unsigned)a.elem_stride;
+    auto ld = [&](unsigned n, unsigned) { return src[cofs + n * es]; };
     auto st = [&](unsigned n, unsigned, cpx<T> v) {
-        if (cvalid) dst[cbase + n * es] = v;
+        if (cvalid) dst[cofs + n * es] = v;
     };
     // reciprocal-space operands are fetched now so that their latency overlaps
     // the forward transform: v_ext(G) for the Hartree+ion field, the
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
             cpx<T> o = {T(0), T(0)};
             if (op == GO_HEXT) {
                 const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
-                const T ih = G2 > T(0) ? T(1) / G2 : T(0);
+                const T ih = G2 > T(0) ? d_rcp(G2) : T(0);
                 s0 += wgt * (double)((F.x * F.x + F.y * F.y) * ih);
                 if (a.use_h) o = cscale(F, fourpi * ih);
                 if (a.use_ext) {
@@ -492,6 +496,8 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
     const bool cvalid = c < a.ncols;
     const Geom &g = a.g;
     const long long es = (long long)g.n1 * g.n2h;
+    const unsigned es32 = (unsigned)es;
+    const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
     const cpx<T> *src = (const cpx<T> *)a.src + b * a.fstride;
     for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
     const cpx<T> *tw = tws;
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
         // the last stage writes this thread's column (pencil p) to memory
         cpx<T> *dst = (cpx<T> *)a.dst + ((long long)kk * a.nbatch + b) * a.fstride;
         lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tid, [&](unsigned n, unsigned, cpx<T> v) {
-            if (cvalid) dst[c + n * es] = v;
+            if (cvalid) dst[cofs + n * es32] = v;
         });
     }
 }
@@ -544,6 +550,8 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
     const bool cvalid = c < a.ncols;
     const Geom &g = a.g;
     const long long es = (long long)g.n1 * g.n2h;
+    const unsigned es32 = (unsigned)es;
+    const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
     const cpx<T> *tw = (const cpx<T> *)a.tw;
     const int i1 = cvalid ? (int)(c / g.n2h) : 0;
     const int k2 = cvalid ? (int)(c % g.n2h) : 0;
@@ -561,9 +569,8 @@ __global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
     for (int kk = 0; kk < a.K; ++kk) {
         // the first stage reads this thread's column (pencil p) from memory
         const cpx<T> *src = (const cpx<T> *)a.src + ((long long)kk * a.nbatch + b) * a.fstride;
-        lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, [&](unsigned n, unsigned) {
-            return cvalid ? src[c + n * es] : cpx<T>{T(0), T(0)};
-        });
+        lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid,
+                                              [&](unsigned n, unsigned) { return src[cofs + n * es32]; });
         const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
