@@ -117,25 +117,26 @@ template <typename T>
 __device__ __forceinline__ T gnl_dev(T eta)
 {
     if (!(eta > T(0))) return T(0);
+    // FP32: quotients by the hardware reciprocal (1 ulp); FP64: divisions
     if (eta < T(1)) {
-        T F = T(0.5) + (T(1) - eta) * (T(1) + eta) / (T(4) * eta) *
-                           d_log1p(T(2) * eta / (T(1) - eta));
-        return T(1) / F - T(3) * eta * eta - T(1);
+        T F = T(0.5) + (T(1) - eta) * (T(1) + eta) * d_rcp(T(4) * eta) *
+                           d_log1p(T(2) * eta * d_rcp(T(1) - eta));
+        return d_rcp(F) - T(3) * eta * eta - T(1);
     }
     if (eta == T(1)) return T(-2);
     if (eta < T(1.6)) {
-        T F = T(0.5) - (eta - T(1)) * (eta + T(1)) / (T(4) * eta) *
-                           d_log1p(T(2) / (eta - T(1)));
-        return T(1) / F - T(3) * eta * eta - T(1);
+        T F = T(0.5) - (eta - T(1)) * (eta + T(1)) * d_rcp(T(4) * eta) *
+                           d_log1p(T(2) * d_rcp(eta - T(1)));
+        return d_rcp(F) - T(3) * eta * eta - T(1);
     }
-    const T x = T(1) / (eta * eta);
+    const T x = d_rcp(eta * eta);
     constexpr int NTERM = sizeof(T) == 8 ? 40 : 18;
     T P = T(0), S = T(0);
 #pragma unroll
     for (int n = NTERM; n >= 1; --n) P = P * x + T(1.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
 #pragma unroll
     for (int n = NTERM; n >= 2; --n) S = S * x + T(3.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
-    return T(-1) - S / P;
+    return T(-1) - S * d_rcp(P);
 }
 
 // k_F = (3 pi^2 rho)^(1/3), clamped to the knot range; bracket j and linear
@@ -191,9 +192,11 @@ __device__ __forceinline__ int freq(int i, int n) { return i < (n + 1) / 2 ? i :
 template <typename T>
 __device__ __forceinline__ T gvec2(const Geom &g, int m0, int m1, int m2)
 {
-    const T gx = T(m0) * T(g.b[0][0]) + T(m1) * T(g.b[1][0]) + T(m2) * T(g.b[2][0]);
-    const T gy = T(m0) * T(g.b[0][1]) + T(m1) * T(g.b[1][1]) + T(m2) * T(g.b[2][1]);
-    const T gz = T(m0) * T(g.b[0][2]) + T(m1) * T(g.b[1][2]) + T(m2) * T(g.b[2][2]);
+    // the (m1, m2) part first: in the column passes it is the same for every
+    // element of a column and is computed once
+    const T gx = T(m0) * T(g.b[0][0]) + (T(m1) * T(g.b[1][0]) + T(m2) * T(g.b[2][0]));
+    const T gy = T(m0) * T(g.b[0][1]) + (T(m1) * T(g.b[1][1]) + T(m2) * T(g.b[2][1]));
+    const T gz = T(m0) * T(g.b[0][2]) + (T(m1) * T(g.b[1][2]) + T(m2) * T(g.b[2][2]));
     return gx * gx + gy * gy + gz * gz;
 }
 
