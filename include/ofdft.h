@@ -223,6 +223,29 @@ typedef struct {
 ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params,
                             ofdft_opt_result *result);
 
+/* Multi-step density optimisation (Section "Density optimization
+ * strategies": a full optimisation on a coarse grid, the converged density
+ * interpolated onto a finer grid, and the optimisation continued there).
+ *
+ * ofdft_grid_interpolate_density sets dst's resident density from src's:
+ * phi = sqrt(rho) of src is Fourier interpolated onto dst's grid -- its half
+ * spectrum zero-padded: frequencies strictly inside src's band copied, src's
+ * Nyquist coefficient of an even axis split in halves between +-n/2, nothing
+ * beyond; an axis of equal size copied -- then squared and scaled to dst's
+ * electron count.  Both grids: same device, same precision, the same cell
+ * (lattice within 1e-12), dst at least as fine as src on every axis, src
+ * with a resident density; else OFDFT_EINVAL.  Synchronous.
+ *
+ * ofdft_optimize_multistep runs ofdft_optimize on grids[0] (from its
+ * resident density) with params[0], then for i = 1 .. ngrids-1 interpolates
+ * the result onto grids[i] and optimises there with params[i]; results[i]
+ * receives each step's result.  A step that reaches max_iter (OFDFT_ENOCONV)
+ * still hands its density on; the return value is the last step's status,
+ * or the first other error. */
+ofdft_status ofdft_grid_interpolate_density(ofdft_grid *dst, ofdft_grid *src);
+ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
+                                     const ofdft_opt_params *params, ofdft_opt_result *results);
+
 /* ------------------------------------------------------------------ serving
  * A request server for many cells on one device: energy+potential, force and
  * optimisation requests (the three operations above) are submitted from any

@@ -1681,6 +1681,61 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     return OFDFT_OK;
 }
 
+// Multi-step optimisation (Section "Density optimization strategies"): the
+// resident density of dst from that of src, by Fourier interpolation of
+// phi = sqrt(rho) onto dst's grid (at least as fine on every axis), squared
+// and scaled to dst's electron count.  Runs on src's stream; both grids are
+// idle when it returns.
+template <typename T>
+static ofdft_status interp_impl(ofdft_grid *dst, ofdft_grid *src)
+{
+    hipStream_t s = src->ctx->stream;
+    const Geom &Gs = src->geom, &Gd = dst->geom;
+    HIP_TRY(hipStreamSynchronize(dst->ctx->stream));
+    ST_TRY(dmalloc(src, &src->opt[V_PHI], (size_t)Gs.N * sizeof(T)));
+    ST_TRY(dmalloc(dst, &dst->opt[V_PHI], (size_t)Gd.N * sizeof(T)));
+    ST_TRY(dmalloc(dst, &dst->rho, (size_t)Gd.N * sizeof(T)));
+    ofdft_grid *g = src;   // per-pass timing of the src grid
+    TIMED(PS_OTHER, launch_pointwise<T>(Gs.N, PW_SQRT, src->opt[V_PHI], src->rho, s));
+    ST_TRY(fft_impl<T>(src, 1, src->opt[V_PHI], src->spec, true, s));
+    // the padded spectrum goes to dst's workspace slot 1; the inverse copies
+    // it to slot 0 and transforms there
+    void *slot1 = (char *)dst->spec + (size_t)Gd.Nh * 2 * sizeof(T);
+    TIMED(PS_OTHER, launch_interp_spec<T>(Gs, Gd, src->spec, slot1, s));
+    ST_TRY(fft_impl<T>(dst, 1, slot1, dst->opt[V_PHI], false, s));
+    OptState o{dst, s, Gd.N};
+    double pp = 0.0;
+    ST_TRY(dots<T>(o, 1, dst->opt[V_PHI], dst->opt[V_PHI], nullptr, nullptr, nullptr, nullptr, &pp));
+    if (!(pp > 0)) return fail(OFDFT_EINVAL, "interpolated density is zero");
+    ST_TRY(lincomb<T>(o, dst->opt[V_PHI], std::sqrt(dst->nelec / (dst->dv * pp)), dst->opt[V_PHI],
+                      0.0, nullptr));
+    g = dst;
+    TIMED(PS_OTHER, launch_pointwise<T>(Gd.N, PW_SQUARE, dst->rho, dst->opt[V_PHI], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return OFDFT_OK;
+}
+
+static ofdft_status interpolate_density(ofdft_grid *dst, ofdft_grid *src)
+{
+    if (!dst || !src) return fail(OFDFT_EINVAL, "null grid");
+    if (dst == src) return fail(OFDFT_EINVAL, "source and destination are the same grid");
+    if (src->ctx->device != dst->ctx->device)
+        return fail(OFDFT_EINVAL, "grids on different devices");
+    if (src->fp64 != dst->fp64) return fail(OFDFT_EINVAL, "grids of different precision");
+    for (int i = 0; i < 3; ++i) {
+        if (dst->n[i] < src->n[i])
+            return fail(OFDFT_EINVAL, "destination grid coarser than the source on an axis");
+        for (int j = 0; j < 3; ++j)
+            if (std::fabs(dst->lattice[i][j] - src->lattice[i][j]) >
+                1e-12 * (1.0 + std::fabs(src->lattice[i][j])))
+                return fail(OFDFT_EINVAL, "grids of different cells");
+    }
+    if (!src->rho) return fail(OFDFT_EINVAL, "source grid has no resident density");
+    HIP_TRY(hipSetDevice(src->ctx->device));
+    graphs_clear(dst);
+    return src->fp64 ? interp_impl<double>(dst, src) : interp_impl<float>(dst, src);
+}
+
 // ================================================================ autotuner
 // The launch schedule of an evaluation has three free choices: the fused
 // plane kernels or separate row and column passes (where the plane fits in
@@ -2045,6 +2100,26 @@ ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, of
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return grid->fp64 ? optimize_impl<double>(grid, params, result)
                       : optimize_impl<float>(grid, params, result);
+}
+
+ofdft_status ofdft_grid_interpolate_density(ofdft_grid *dst, ofdft_grid *src)
+{
+    return interpolate_density(dst, src);
+}
+
+ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
+                                     const ofdft_opt_params *params, ofdft_opt_result *results)
+{
+    if (!grids || !params || !results || ngrids < 1) return fail(OFDFT_EINVAL, "null argument");
+    for (int i = 0; i < ngrids; ++i)
+        if (!grids[i]) return fail(OFDFT_EINVAL, "null grid");
+    ofdft_status last = OFDFT_OK;
+    for (int i = 0; i < ngrids; ++i) {
+        if (i > 0) ST_TRY(interpolate_density(grids[i], grids[i - 1]));
+        last = ofdft_optimize(grids[i], &params[i], &results[i]);
+        if (last != OFDFT_OK && last != OFDFT_ENOCONV) return last;
+    }
+    return last;
 }
 
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on)

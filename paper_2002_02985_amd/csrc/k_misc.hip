@@ -298,4 +298,77 @@ hipError_t launch_pointwise(long long n, int op, void *z, const void *x, hipStre
 template hipError_t launch_pointwise<float>(long long, int, void *, const void *, hipStream_t);
 template hipError_t launch_pointwise<double>(long long, int, void *, const void *, hipStream_t);
 
+// ---------------------------------------------------------------- interpolation
+// Fourier interpolation onto a grid at least as fine on every axis (the
+// multi-step optimisation of the section "Density optimization strategies"):
+// coefficient f(G) of the destination is the source's for the frequencies
+// strictly inside the source band, half the source's Nyquist coefficient at
+// each of +-n_s/2 (the band-limited cosine that the Nyquist samples
+// represent), and zero beyond; an axis of equal size is copied as it is.
+// Full axes 0 and 1: frequency m of the destination -> source index and
+// weight; returns false when the source has no such frequency.
+__device__ __forceinline__ bool interp_axis(int m, int ns, int nd, int &is, double &w)
+{
+    w = 1.0;
+    if (nd == ns) {
+        is = m < 0 ? m + ns : m;
+        return true;
+    }
+    if (ns % 2 == 0 && (m == ns / 2 || m == -ns / 2)) {
+        is = ns / 2;   // the source Nyquist frequency -ns/2 sits at index ns/2
+        w = 0.5;
+        return true;
+    }
+    if (2 * m >= ns || -2 * m >= ns) return false;
+    is = m < 0 ? m + ns : m;
+    return true;
+}
+
+// Half axis 2 (k >= 0 stored): source index k and weight.
+__device__ __forceinline__ bool interp_half(int k, int ns, int nd, double &w)
+{
+    w = 1.0;
+    if (nd == ns) return true;
+    if (ns % 2 == 0 && 2 * k == ns) {
+        w = 0.5;
+        return true;
+    }
+    return 2 * k < ns;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_interp_spec(Geom gs, Geom gd, const cpx<T> *src,
+                                                    cpx<T> *dst)
+{
+    const long long e = (long long)blockIdx.x * NT + threadIdx.x;
+    if (e >= gd.Nh) return;
+    const int k2 = (int)(e % gd.n2h);
+    const long long row = e / gd.n2h;
+    const int i1 = (int)(row % gd.n1), i0 = (int)(row / gd.n1);
+    int s0, s1;
+    double w0, w1, w2;
+    cpx<T> v = {T(0), T(0)};
+    if (interp_axis(freq(i0, gd.n0), gs.n0, gd.n0, s0, w0) &&
+        interp_axis(freq(i1, gd.n1), gs.n1, gd.n1, s1, w1) && interp_half(k2, gs.n2, gd.n2, w2)) {
+        const cpx<T> x = src[((long long)s0 * gs.n1 + s1) * gs.n2h + k2];
+        const T w = T(w0 * w1 * w2);
+        v = {w * x.x, w * x.y};
+    }
+    dst[e] = v;
+}
+
+template <typename T>
+hipError_t launch_interp_spec(const Geom &gs, const Geom &gd, const void *src, void *dst,
+                              hipStream_t s)
+{
+    const long long nb = (gd.Nh + NT - 1) / NT;
+    hipLaunchKernelGGL((k_interp_spec<T>), dim3((unsigned)nb), dim3(NT), 0, s, gs, gd,
+                       (const cpx<T> *)src, (cpx<T> *)dst);
+    return hipGetLastError();
+}
+template hipError_t launch_interp_spec<float>(const Geom &, const Geom &, const void *, void *,
+                                              hipStream_t);
+template hipError_t launch_interp_spec<double>(const Geom &, const Geom &, const void *, void *,
+                                               hipStream_t);
+
 }  // namespace ofdft

@@ -253,5 +253,10 @@ int dots_blocks(long long n);
 enum { PW_SQRT = 0, PW_SQUARE = 1 };
 template <typename T>
 hipError_t launch_pointwise(long long n, int op, void *z, const void *x, hipStream_t s);
+// destination half spectrum (gd) from a source half spectrum (gs) of a grid
+// no finer on any axis: Fourier interpolation (see k_misc.hip)
+template <typename T>
+hipError_t launch_interp_spec(const Geom &gs, const Geom &gd, const void *src, void *dst,
+                              hipStream_t s);
 
 }  // namespace ofdft

@@ -128,6 +128,8 @@ _SIGS = {
     "ofdft_serve_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServeStats)]),
     "ofdft_server_destroy": (None, [_P]),
     "ofdft_grid_set_graphs": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_interpolate_density": (ctypes.c_int, [_P, _P]),
+    "ofdft_optimize_multistep": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P, _P]),
     "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
     "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
@@ -303,6 +305,23 @@ def ofdft_optimize(grid, tol=1e-7, max_iter=1000, method=0, allow_noconv=False):
     if not (st == OK or (allow_noconv and st == ENOCONV)):
         check(st)
     return r, st
+
+
+def ofdft_grid_interpolate_density(dst, src):
+    check(load().ofdft_grid_interpolate_density(dst, src))
+
+
+def ofdft_optimize_multistep(grids, params, allow_noconv=False):
+    """grids: grid handles, coarse to fine; params: (tol, max_iter, method)
+    per grid.  Returns ([OptResult per grid], status)."""
+    n = len(grids)
+    hs = (_P * n)(*grids)
+    ps = (OptParams * n)(*[OptParams(tol=t, max_iter=m, method=k, warm=0) for t, m, k in params])
+    rs = (OptResult * n)()
+    st = load().ofdft_optimize_multistep(hs, n, ps, rs)
+    if not (st == OK or (allow_noconv and st == ENOCONV)):
+        check(st)
+    return list(rs), st
 
 
 def ofdft_validate(cell_desc, func_desc):
