@@ -119,6 +119,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch schedule instead of autotuning it")
+    ap.add_argument("--xc", action="store_true",
+                    help="add the LDA exchange-correlation term to the functional")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -181,9 +183,10 @@ def pass_bytes(name, nb, N, Nh, nfields, w):
     return 0
 
 
-def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, tune=True):
+def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, tune=True,
+                  xc=False):
     terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
-             ofdft.TERM_WT)
+             ofdft.TERM_WT | (ofdft.TERM_XC if xc else 0))
     dt = torch.float64 if precision == ofdft.FP64 else torch.float32
     g = ofdft.Grid(cell, terms, precision=precision)
     ofdft.ofdft_grid_reserve(g.handle, NDENS)
@@ -232,13 +235,14 @@ def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, t
             "dev_bytes": dev_bytes, "tuning": tuning}
 
 
-def cpu_baseline(cell, dens, nsample):
+def cpu_baseline(cell, dens, nsample, xc=False):
     from oracle import cell as OC
     from oracle import functionals as OF
     from oracle.ewald import ewald_energy
     from tests.oracle_helpers import make_cell
     oc = make_cell(cell)
-    func = OC.Functional(terms=OC.TF | OC.VW | OC.HARTREE | OC.EXT | OC.WT)
+    func = OC.Functional(terms=OC.TF | OC.VW | OC.HARTREE | OC.EXT | OC.WT |
+                         (OC.XC if xc else 0))
     vx = OF.vext_g(oc)
     ei = ewald_energy(oc)
     out = []
@@ -696,12 +700,12 @@ def main():
 
     log("mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps))
     mixed = run_gpu_batch(ofdft, torch, cell, dens, ofdft.MIXED, args.steps, args.warmup, True,
-                          not args.no_tune)
+                          not args.no_tune, args.xc)
     fp64 = None
     if not args.no_fp64:
         log("fp64 path")
         fp64 = run_gpu_batch(ofdft, torch, cell, dens, ofdft.FP64, max(3, args.steps // 2),
-                             args.warmup, True, not args.no_tune)
+                             args.warmup, True, not args.no_tune, args.xc)
 
     ms_step = mixed["wall"] * 1e3 / args.steps
     value = NDENS * N / (ms_step * 1e-3) / 1e9
@@ -751,8 +755,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "fcc Al 3x3x3 (108 atoms, a=22.95 Bohr), 96^3 grid, "
-                               "WT+vW+TF+Hartree+local pseudopotential, 200 seeded densities "
-                               "per step, mixed precision (FP32 fields, FP64 reductions)",
+                               "WT+vW+TF+Hartree+local pseudopotential%s, 200 seeded densities "
+                               "per step, mixed precision (FP32 fields, FP64 reductions)"
+                               % (" + LDA xc" if args.xc else ""),
                    "grid": list(N_GRID), "densities_per_step": NDENS, "natoms": natoms},
         "evals_per_s": round(NDENS / (ms_step * 1e-3), 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -774,7 +779,7 @@ def main():
 
     if not args.no_cpu:
         log("oracle CPU baseline on %d densities" % args.cpu_sample)
-        t, e_or = cpu_baseline(cell, dens, args.cpu_sample)
+        t, e_or = cpu_baseline(cell, dens, args.cpu_sample, args.xc)
         line["cpu_baseline"] = {"value": round(args.cpu_sample * N / t / 1e9, 6), "unit": "Gpts/s",
                                 "cores": 1, "kind": "oracle",
                                 "sample": "%d of the 200 densities, one FP64 evaluation each "

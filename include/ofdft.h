@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 3
+#define OFDFT_ABI_VERSION 4
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
@@ -74,7 +74,11 @@ enum {
     OFDFT_TERM_HARTREE = 4,   /* 2 pi V sum_{G!=0} |rho(G)|^2 / G^2                  */
     OFDFT_TERM_EXT = 8,       /* int v_ext rho with the local pseudopotential, + E_ion */
     OFDFT_TERM_WT = 16,       /* Wang-Teter nonlocal functional (eqs. "nl2", "WT")    */
-    OFDFT_TERM_SPLINE = 32    /* density-dependent kernel with k_F splines (s1-s4)    */
+    OFDFT_TERM_SPLINE = 32,   /* density-dependent kernel with k_F splines (s1-s4)    */
+    OFDFT_TERM_XC = 64        /* LDA exchange-correlation, E_xc of eq. "efunc": Dirac
+                                 exchange + Perdew-Zunger (1981) correlation of the
+                                 unpolarised electron gas at the local density (the
+                                 parametrisation the paper's applications cite)      */
 };
 enum { OFDFT_KNOTS_LOG = 0, OFDFT_KNOTS_LIN = 1 };
 enum { OFDFT_NL_S3S4 = 0, OFDFT_NL_EXACT = 1 };
@@ -121,6 +125,7 @@ typedef struct {
 typedef struct {
     double e_tf, e_vw, e_h, e_ext, e_nl, e_ion, e_total;
     double mu, nelec_int, resid_norm;
+    double e_xc;   /* included in e_total */
 } ofdft_energy;
 
 int ofdft_abi_version(void);

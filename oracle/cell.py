@@ -17,6 +17,7 @@ HARTREE = 4
 EXT = 8
 WT = 16
 SPLINE = 32
+XC = 64
 
 NL_S3S4 = 0
 NL_EXACT = 1

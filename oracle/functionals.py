@@ -22,6 +22,56 @@ C_WT = 6.0 / 25.0 * (3.0 * PI * PI) ** (2.0 / 3.0)
 
 
 # ---------------------------------------------------------------------------
+# LDA exchange-correlation (E_xc of eq. "efunc"; the applications of Section
+# "Linear scalability" and the TD-OFDFT section use the Perdew-Zunger
+# parametrisation).  Spin-unpolarised homogeneous electron gas at the local
+# density: Dirac exchange and the Perdew-Zunger (1981) fit of the
+# Ceperley-Alder correlation energy, whose parameters are those published by
+# Perdew and Zunger (Phys. Rev. B 23, 5048, Appendix C); the paper cites that
+# work and does not print them.
+# ---------------------------------------------------------------------------
+PZ_GAMMA, PZ_BETA1, PZ_BETA2 = -0.1423, 1.0529, 0.3334      # r_s >= 1
+PZ_A, PZ_B, PZ_C, PZ_D = 0.0311, -0.048, 0.0020, -0.0116    # r_s < 1
+C_X = -0.75 * (3.0 / PI) ** (1.0 / 3.0)                     # eps_x = C_X rho^(1/3)
+
+
+def pz_correlation(rs):
+    """Correlation energy per electron eps_c(r_s) and its potential
+    v_c = eps_c - (r_s/3) d eps_c/d r_s (both Ha), elementwise."""
+    rs = np.asarray(rs, dtype=np.float64)
+    ec = np.empty_like(rs)
+    vc = np.empty_like(rs)
+    lo = rs >= 1.0
+    r = rs[lo]
+    sq = np.sqrt(r)
+    den = 1.0 + PZ_BETA1 * sq + PZ_BETA2 * r
+    ec[lo] = PZ_GAMMA / den
+    vc[lo] = ec[lo] * (1.0 + 7.0 / 6.0 * PZ_BETA1 * sq + 4.0 / 3.0 * PZ_BETA2 * r) / den
+    r = rs[~lo]
+    lr = np.log(r)
+    ec[~lo] = PZ_A * lr + PZ_B + PZ_C * r * lr + PZ_D * r
+    vc[~lo] = (PZ_A * lr + (PZ_B - PZ_A / 3.0) + 2.0 / 3.0 * PZ_C * r * lr +
+               (2.0 * PZ_D - PZ_C) / 3.0 * r)
+    return ec, vc
+
+
+def lda_xc(rho):
+    """eps_xc(rho) (energy per electron) and v_xc = d(rho eps_xc)/d rho;
+    both vanish at rho = 0."""
+    rho = np.asarray(rho, dtype=np.float64)
+    eps = np.zeros_like(rho)
+    v = np.zeros_like(rho)
+    pos = rho > 0.0
+    r3 = np.cbrt(rho[pos])
+    ex = C_X * r3
+    rs = (3.0 / (4.0 * PI)) ** (1.0 / 3.0) / r3
+    ec, vc = pz_correlation(rs)
+    eps[pos] = ex + ec
+    v[pos] = 4.0 / 3.0 * ex + vc
+    return eps, v
+
+
+# ---------------------------------------------------------------------------
 # Lindhard function (Section "New-generation nonlocal KEDFs", the G_NL formula)
 # ---------------------------------------------------------------------------
 _NSER = 64
@@ -160,6 +210,7 @@ class Result:
     e_ext: float = 0.0
     e_nl: float = 0.0
     e_ion: float = 0.0
+    e_xc: float = 0.0
     e_total: float = 0.0
     mu: float = 0.0
     nelec_int: float = 0.0
@@ -178,8 +229,9 @@ def _kf_wt(cell, func):
 def energy_potential(cell, func, rho=None, phi=None, vext=None, e_ion=None):
     """E[rho] and its derivatives for the terms in ``func.terms``.
 
-    The energy is eq. "efunc" without exchange-correlation:
-      E = T_TF + T_vW + T_NL + E_H + int v_ext rho (+ the constant E_ion).
+    The energy is eq. "efunc":
+      E = T_TF + T_vW + T_NL + E_H + E_xc + int v_ext rho (+ the constant E_ion),
+    with E_xc the LDA (term XC, off by default).
     dE/drho - mu = 0 is eq. "euler"; in the psi form (eq. "euler2") the
     residual is R = dE/dphi - 2 mu phi with mu = int v rho / int rho.
     """
@@ -270,7 +322,14 @@ def energy_potential(cell, func, rho=None, phi=None, vext=None, e_ion=None):
         v += vnl
         g += gnl_
 
-    res.e_total = res.e_tf + res.e_vw + res.e_h + res.e_ext + res.e_nl + res.e_ion
+    if terms & C.XC:
+        eps, vxc = lda_xc(rho)
+        res.e_xc = dv * float(np.sum(rho * eps))
+        v += vxc
+        g += 2.0 * phi * vxc
+
+    res.e_total = (res.e_tf + res.e_vw + res.e_h + res.e_ext + res.e_nl + res.e_xc +
+                   res.e_ion)
     # chemical potential and Euler-Lagrange residual in the psi form
     sum_rho = float(np.sum(phi * phi))
     res.mu = float(np.sum(g * phi)) / (2.0 * sum_rho) if sum_rho > 0 else 0.0

@@ -592,7 +592,7 @@ static int combine_flavour(const RowInvArgs &rc)
     if (rc.fld_a >= 0) f |= CB_A;
     if (f != CF_LOCAL && f != CF_WT && f != CF_S3S4 && f != CF_EXACT) return 0;
     if (f != CF_LOCAL && rc.alpha != 5.0 / 6.0) return 0;
-    return f;
+    return rc.use_xc ? (f | CB_XC) : f;
 }
 
 static ofdft_status ensure_lane(ofdft_grid *g)
@@ -780,6 +780,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rc.fld_wt = (terms & OFDFT_TERM_WT) ? l.s_rhob : -1;
     rc.fld_a = l.s_h;
     rc.use_tf = (terms & OFDFT_TERM_TF) ? 1 : 0;
+    rc.use_xc = (terms & OFDFT_TERM_XC) ? 1 : 0;
     rc.spline = spline;
     rc.exact = exact;
     rc.lambda_vw = g->func.lambda_vw;
@@ -808,6 +809,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     cnt.n[SL_H] = cnt.n[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
     cnt.n[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
     cnt.n[SL_NL] = cnt.n[SL_GPHI] = cnt.n[SL_GG] = cnt.n[SL_PHIPHI] = nb_inv;
+    cnt.n[SL_XC] = (terms & OFDFT_TERM_XC) ? nb_inv : 0;   // written by the LDA combines only
     TIMED(PS_FINALIZE, launch_finalize(w.part, g->pstride, cnt, nb, w.sums, s));
     HIP_TRY(hipMemcpyAsync(w.h_sums, w.sums, (size_t)nb * NSLOT * sizeof(double),
                            hipMemcpyDeviceToHost, s));
@@ -924,7 +926,8 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
             e.e_ion = g->e_ion;
         }
         if (terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) e.e_nl = g->dv * S[SL_NL];
-        e.e_total = e.e_tf + e.e_vw + e.e_h + e.e_ext + e.e_nl + e.e_ion;
+        if (terms & OFDFT_TERM_XC) e.e_xc = g->dv * S[SL_XC];
+        e.e_total = e.e_tf + e.e_vw + e.e_h + e.e_ext + e.e_nl + e.e_xc + e.e_ion;
         const double spp = S[SL_PHIPHI];
         e.mu = spp > 0 ? S[SL_GPHI] / (2.0 * spp) : 0.0;
         const double r2 = spp > 0 ? S[SL_GG] - S[SL_GPHI] * S[SL_GPHI] / spp : S[SL_GG];
@@ -1043,7 +1046,7 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
     }
     if (!(c->nelec > 0)) return fail(OFDFT_EINVAL, "nelec must be positive");
     const uint32_t all = OFDFT_TERM_TF | OFDFT_TERM_VW | OFDFT_TERM_HARTREE | OFDFT_TERM_EXT |
-                         OFDFT_TERM_WT | OFDFT_TERM_SPLINE;
+                         OFDFT_TERM_WT | OFDFT_TERM_SPLINE | OFDFT_TERM_XC;
     if (f->terms & ~all) return fail(OFDFT_EINVAL, "unknown term bits");
     if ((f->terms & OFDFT_TERM_WT) && (f->terms & OFDFT_TERM_SPLINE))
         return fail(OFDFT_EINVAL, "WT and SPLINE are exclusive");

@@ -19,6 +19,7 @@ enum Slot {
     SL_GG,          // sum g^2
     SL_PHIPHI,      // sum phi^2
     SL_BAD,         // count of non-finite or negative inputs
+    SL_XC,          // sum rho eps_xc(rho)
     SL_AUX0,        // slots for vector reductions
     SL_AUX1,
     SL_AUX2,
@@ -124,6 +125,7 @@ struct RowInvArgs {
     int in_is_phi;
     int fld_hext, fld_vw, fld_wt, fld_a;   // field index or -1
     int use_tf, spline, exact;
+    int use_xc;                 // LDA exchange-correlation (runtime, any term set)
     double lambda_vw, alpha, floor;
     void *acc1, *acc2;          // spline accumulators sum L_i Phi_i, sum L_i' Phi_i
     int acc_init;               // EP_KNOTS: first knot batch overwrites
@@ -141,7 +143,8 @@ struct RowInvArgs {
 // Term sets of the final combine that have kernels specialised at compile
 // time (a set bit = term present); any other set, or a nonlocal term with
 // alpha != 5/6, runs the general combine (cf = 0).
-enum : int { CB_H = 1, CB_VW = 2, CB_TF = 4, CB_WT = 8, CB_SPL = 16, CB_EXACT = 32, CB_A = 64 };
+enum : int { CB_H = 1, CB_VW = 2, CB_TF = 4, CB_WT = 8, CB_SPL = 16, CB_EXACT = 32, CB_A = 64,
+             CB_XC = 128 };   // CB_XC may be added to any of the sets below
 constexpr int CF_LOCAL = CB_H | CB_VW | CB_TF;
 constexpr int CF_WT = CF_LOCAL | CB_WT;
 constexpr int CF_S3S4 = CF_LOCAL | CB_SPL;

@@ -635,6 +635,45 @@ __device__ __forceinline__ void knot_slope_scale(const Knots &kn, const int (&j)
     v2.y *= T(1.0 / (kn.k[j[1] + 1] - kn.k[j[1]]));
 }
 
+// ================================================================ LDA xc
+// Exchange-correlation of the unpolarised homogeneous electron gas at the
+// local density (E_xc of eq. "efunc"): Dirac exchange eps_x = C_X rho^(1/3)
+// and the Perdew-Zunger (1981) fit of the correlation energy in
+// r_s = (3/(4 pi rho))^(1/3), with the parameters Perdew and Zunger published
+// (the parametrisation the paper's applications use).  r3 = rho^(1/3).
+// eps = eps_x + eps_c, v = d(rho eps)/d rho = (4/3) eps_x + eps_c -
+// (r_s/3) d eps_c/d r_s; both 0 at rho = 0.
+constexpr double XC_CX = -0.7385587663820223;   // -(3/4)(3/pi)^(1/3)
+constexpr double XC_RS = 0.6203504908994001;    // (3/(4 pi))^(1/3)
+constexpr double PZ_G = -0.1423, PZ_B1 = 1.0529, PZ_B2 = 0.3334;             // r_s >= 1
+constexpr double PZ_A = 0.0311, PZ_B = -0.048, PZ_C = 0.0020, PZ_D = -0.0116;  // r_s < 1
+
+template <typename T>
+__device__ __forceinline__ void lda_xc_point(T rho, T r3, T &eps, T &v)
+{
+    if (!(rho > T(0))) {
+        eps = T(0);
+        v = T(0);
+        return;
+    }
+    const T ex = T(XC_CX) * r3;
+    const T rs = T(XC_RS) * d_rcp(r3);
+    T ec, vc;
+    if (rs >= T(1)) {
+        const T sq = d_sqrt_fast(rs);
+        const T iden = d_rcp(T(1) + T(PZ_B1) * sq + T(PZ_B2) * rs);
+        ec = T(PZ_G) * iden;
+        vc = ec * (T(1) + T(7.0 / 6.0 * PZ_B1) * sq + T(4.0 / 3.0 * PZ_B2) * rs) * iden;
+    } else {
+        const T lr = d_log(rs);
+        ec = T(PZ_A) * lr + T(PZ_B) + T(PZ_C) * rs * lr + T(PZ_D) * rs;
+        vc = T(PZ_A) * lr + T(PZ_B - PZ_A / 3.0) + T(2.0 / 3.0 * PZ_C) * rs * lr +
+             T((2.0 * PZ_D - PZ_C) / 3.0) * rs;
+    }
+    eps = ex + ec;
+    v = T(4.0 / 3.0) * ex + vc;
+}
+
 // ================================================================ final combine
 // Per-point combine of the real-space fields into v = dE/drho and
 // g = dE/dphi (eqs. "euler", "euler2"), with the FP64 partial sums of
@@ -671,10 +710,14 @@ __device__ __forceinline__ CombineConst<T> combine_const(const RowInvArgs &a)
     return c;
 }
 
+// partial sums of the combine: rho^a Phi, g phi, g^2, phi^2 and, with the
+// LDA term (always in the general combine), rho eps_xc
+template <int CF> constexpr int combine_nsum() { return (CF == 0 || (CF & CB_XC)) ? 5 : 4; }
+
 template <typename T, int CF>
 __device__ __forceinline__ void combine_point(const RowInvArgs &a, const CombineConst<T> &cc, T x,
                                               T hv, T wv, T nl, T s1, T s2, T &vo, T &go,
-                                              double (&sums)[4])
+                                              double (&sums)[combine_nsum<CF>()])
 {
     T phi, rho;
     if (a.in_is_phi) {
@@ -708,6 +751,13 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
             const T vt = T(5.0 / 3.0 * C_TF_D) * p4;
             vv += vt;
             gg += T(2) * phi * vt;
+        }
+        if constexpr ((CF & CB_XC) != 0) {
+            T eps, vx;
+            lda_xc_point(rho, p2, eps, vx);
+            vv += vx;
+            gg += T(2) * phi * vx;
+            sums[4] += (double)(rho * eps);
         }
         if constexpr ((CF & (CB_WT | CB_A | CB_SPL)) != 0) {
             const T ra = p4 * p;         // rho^a
@@ -766,6 +816,13 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
             const T vt = T(5.0 / 3.0 * C_TF_D) * d_exp2(lu * T(2.0 / 3.0));
             vv += vt;
             gg += T(2) * phi * vt;
+        }
+        if (a.use_xc) {
+            T eps, vx;
+            lda_xc_point(rho, d_exp2(lu * T(1.0 / 3.0)), eps, vx);
+            vv += vx;
+            gg += T(2) * phi * vx;
+            sums[4] += (double)(rho * eps);
         }
         if (a.spline) {
             sums[0] += (double)(ra * s1);
@@ -843,7 +900,7 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     constexpr int PAIRS = P * M;
     constexpr int PER = (PAIRS + NT - 1) / NT;
     __shared__ cpx<T> buf[M * PS];
-    __shared__ double red[4 * NT / 64];
+    __shared__ double red[5 * NT / 64];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const long long nrows = (long long)g.n0 * g.n1;
@@ -970,7 +1027,7 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     T *vout = a.v_out ? (T *)a.v_out + (long long)b * g.N : nullptr;
     T *gout = a.g_out ? (T *)a.g_out + (long long)b * g.N : nullptr;
     const CombineConst<T> cc = combine_const<T>(a);
-    double sums[4] = {0.0, 0.0, 0.0, 0.0};   // rho^a Phi, g phi, g^2, phi^2
+    double sums[combine_nsum<CF>()] = {};   // rho^a Phi, g phi, g^2, phi^2 (, rho eps_xc)
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         if (!valid[q]) continue;
@@ -985,12 +1042,14 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
         if (vout) *(cpx<T> *)(vout + offs[q]) = vo;
         if (gout) *(cpx<T> *)(gout + offs[q]) = go;
     }
-    block_sums<NT, 4>(sums, red, tid);
+    block_sums<NT, combine_nsum<CF>()>(sums, red, tid);
     if (tid == 0) {
         part_ptr(a.part, b, SL_NL, a.pstride)[blockIdx.x] = sums[0];
         part_ptr(a.part, b, SL_GPHI, a.pstride)[blockIdx.x] = sums[1];
         part_ptr(a.part, b, SL_GG, a.pstride)[blockIdx.x] = sums[2];
         part_ptr(a.part, b, SL_PHIPHI, a.pstride)[blockIdx.x] = sums[3];
+        if constexpr (combine_nsum<CF>() == 5)
+            part_ptr(a.part, b, SL_XC, a.pstride)[blockIdx.x] = sums[combine_nsum<CF>() - 1];
     }
 }
 
@@ -1222,7 +1281,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     __shared__ cpx<T> buf[(M + 1) * A];
     __shared__ cpx<T> xsbuf[N1 * M];
     __shared__ cpx<T> tws[N1 + 2 * M + 1];
-    __shared__ double red[4 * NTP / 64];
+    __shared__ double red[5 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
     stage_plane_twiddles<T, N1, M, NTP>(tws, a.tw1, a.twM, a.twN, tid);
@@ -1357,7 +1416,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     cpx<T> *vout = a.v_out ? (cpx<T> *)((T *)a.v_out + real_off) : nullptr;
     cpx<T> *gout = a.g_out ? (cpx<T> *)((T *)a.g_out + real_off) : nullptr;
     const CombineConst<T> cc = combine_const<T>(a);
-    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    double sums[combine_nsum<CF>()] = {};   // rho^a Phi, g phi, g^2, phi^2 (, rho eps_xc)
     const int t = opaque(tid);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -1376,12 +1435,14 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         if (vout) vout[idx] = vo;
         if (gout) gout[idx] = go;
     }
-    block_sums<NTP, 4>(sums, red, tid);
+    block_sums<NTP, combine_nsum<CF>()>(sums, red, tid);
     if (tid == 0) {
         part_ptr(a.part, b, SL_NL, a.pstride)[i0] = sums[0];
         part_ptr(a.part, b, SL_GPHI, a.pstride)[i0] = sums[1];
         part_ptr(a.part, b, SL_GG, a.pstride)[i0] = sums[2];
         part_ptr(a.part, b, SL_PHIPHI, a.pstride)[i0] = sums[3];
+        if constexpr (combine_nsum<CF>() == 5)
+            part_ptr(a.part, b, SL_XC, a.pstride)[i0] = sums[combine_nsum<CF>() - 1];
     }
     }
     }
@@ -1427,6 +1488,14 @@ hipError_t plane_inv_go(const Geom &g, const RowInvArgs &a, int &nblocks, hipStr
             hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_S3S4>), grid, block, 0, s, a, g);
         else if (a.cf == CF_EXACT)
             hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_EXACT>), grid, block, 0, s, a, g);
+        else if (a.cf == (CF_LOCAL | CB_XC))
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_LOCAL | CB_XC>), grid, block, 0, s, a, g);
+        else if (a.cf == (CF_WT | CB_XC))
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_WT | CB_XC>), grid, block, 0, s, a, g);
+        else if (a.cf == (CF_S3S4 | CB_XC))
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_S3S4 | CB_XC>), grid, block, 0, s, a, g);
+        else if (a.cf == (CF_EXACT | CB_XC))
+            hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, CF_EXACT | CB_XC>), grid, block, 0, s, a, g);
         else
             hipLaunchKernelGGL((k_plane_inv<T, N1, M, EP_COMBINE, 0>), grid, block, 0, s, a, g);
         return hipGetLastError();
@@ -1502,6 +1571,10 @@ hipError_t row_combine_fixed_go(const Geom &g, const RowInvArgs &a, int &nblocks
     case CF_WT: return row_inv_go<T, M, CF_WT>(g, a, nblocks, s);
     case CF_S3S4: return row_inv_go<T, M, CF_S3S4>(g, a, nblocks, s);
     case CF_EXACT: return row_inv_go<T, M, CF_EXACT>(g, a, nblocks, s);
+    case CF_LOCAL | CB_XC: return row_inv_go<T, M, CF_LOCAL | CB_XC>(g, a, nblocks, s);
+    case CF_WT | CB_XC: return row_inv_go<T, M, CF_WT | CB_XC>(g, a, nblocks, s);
+    case CF_S3S4 | CB_XC: return row_inv_go<T, M, CF_S3S4 | CB_XC>(g, a, nblocks, s);
+    case CF_EXACT | CB_XC: return row_inv_go<T, M, CF_EXACT | CB_XC>(g, a, nblocks, s);
     default: return hipErrorNotSupported;
     }
 }

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("OFDFT_LIB", os.path.join(HERE, "libofdft.so"))
 
 OK, PENDING, EINVAL, ENOMEM, EDEVICE, ENOCONV, ECANCELLED, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6
 TERM_TF, TERM_VW, TERM_HARTREE, TERM_EXT, TERM_WT, TERM_SPLINE = 1, 2, 4, 8, 16, 32
+TERM_XC = 64
 KNOTS_LOG, KNOTS_LIN = 0, 1
 NL_S3S4, NL_EXACT = 0, 1
 FP64, MIXED = 0, 1
@@ -45,7 +46,7 @@ class FunctionalDesc(ctypes.Structure):
 class Energy(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("e_tf", "e_vw", "e_h", "e_ext", "e_nl", "e_ion", "e_total", "mu", "nelec_int",
-                 "resid_norm")]
+                 "resid_norm", "e_xc")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_host_helpers():
-    assert ofdft.ofdft_abi_version() == 3
+    assert ofdft.ofdft_abi_version() == 4
     for n in (4, 6, 12, 32, 48, 96, 192, 256, 384, 1024):
         assert ofdft.ofdft_supported_length(n)
     for n in (5, 7, 10, 100, 2048):
@@ -44,6 +44,6 @@ def test_host_helpers():
 
 def test_struct_layouts_match_header():
     # field counts of the C structs mirrored in the binding
-    assert ctypes.sizeof(ofdft.Energy) == 10 * 8
+    assert ctypes.sizeof(ofdft.Energy) == 11 * 8
     assert ctypes.sizeof(ofdft.OptParams) == 8 + 3 * 4 + 4
     assert ofdft.CellDesc.nelec.offset == 9 * 8 + 3 * 4 + 4 + 8 + 8 + 8 + 8 + 8

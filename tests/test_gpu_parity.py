@@ -24,7 +24,7 @@ from tests.oracle_helpers import make_cell, smooth_density
 pytestmark = pytest.mark.gpu
 
 LOCAL = ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT
-ENERGY_KEYS = ("e_tf", "e_vw", "e_h", "e_ext", "e_nl", "e_ion", "e_total")
+ENERGY_KEYS = ("e_tf", "e_vw", "e_h", "e_ext", "e_nl", "e_ion", "e_xc", "e_total")
 
 
 def oracle_func(terms, **kw):
@@ -116,6 +116,16 @@ CASES = {
     "box_spline_lin_exact": (lambda: (box((18, 16, 24)), None), ofdft.TERM_SPLINE,
                              dict(nk=13, kf_min=0.4, kf_max=1.9, knot_spacing=ofdft.KNOTS_LIN,
                                   nl_mode=ofdft.NL_EXACT)),
+    # LDA exchange-correlation: with the fixed term sets (plane path) and the
+    # general combine (row path), and a dense box whose r_s spans both
+    # branches of the correlation fit
+    "c1_local_xc": (lambda: c1_cell(), LOCAL | ofdft.TERM_XC, {}),
+    "c1_wt_xc": (lambda: c1_cell(), LOCAL | ofdft.TERM_WT | ofdft.TERM_XC, {}),
+    "box_spline_s3s4_xc": (lambda: (box((24, 16, 12)), None),
+                           LOCAL | ofdft.TERM_SPLINE | ofdft.TERM_XC,
+                           dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    "box_xc_dense": (lambda: (box((12, 18, 16), L=(2.5, 2.7, 3.0)), None),
+                     ofdft.TERM_TF | ofdft.TERM_XC, {}),
 }
 
 
