@@ -519,8 +519,18 @@ def c5_main(args):
         e = ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
         lat.append(time.perf_counter() - t1)
     ms = float(np.median(lat)) * 1e3
+    # one more evaluation with per-pass HIP-event timing
+    ofdft.ofdft_profile_enable(g.handle, True)
+    ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
+    passes = {}
+    for p, nm in enumerate(ofdft.PASS_NAMES):
+        pms, n = ofdft.ofdft_profile_read(g.handle, p)
+        if n:
+            passes[nm] = round(pms, 2)
+    ofdft.ofdft_profile_enable(g.handle, False)
     out["eval"] = {"ms_per_eval": round(ms, 1), "Gpts_per_s": round(N / (ms * 1e-3) / 1e9, 3),
-                   "e_total": e.e_total, "e_ion": e.e_ion, "nelec_int": e.nelec_int}
+                   "e_total": e.e_total, "e_ion": e.e_ion, "nelec_int": e.nelec_int,
+                   "passes_ms": passes}
     log("evaluation %.1f ms, E(uniform) = %.6f" % (ms, e.e_total))
     del x
     torch.cuda.empty_cache()

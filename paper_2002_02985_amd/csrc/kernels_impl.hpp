@@ -34,7 +34,7 @@ constexpr double C_WT_D = 2.2969872001505534;   // (6/25)(3 pi^2)^(2/3)
 
 // complex elements per block of the column and row passes (tile sizes)
 #ifndef OFDFT_COL_ELEMS_F32
-#define OFDFT_COL_ELEMS_F32 4096
+#define OFDFT_COL_ELEMS_F32 8192
 #endif
 #ifndef OFDFT_ROW_ELEMS_F32
 #define OFDFT_ROW_ELEMS_F32 2048
@@ -64,6 +64,19 @@ constexpr int pow2_floor(int x)
 template <typename T, int L> constexpr int col_P()
 {
     int p = pow2_floor(Cfg<T>::COL_ELEMS / L);
+    if (p > OFDFT_COL_PMAX) p = OFDFT_COL_PMAX;
+    if (p < 4) p = 4;
+    if (p > NT) p = NT;
+    return p;
+}
+// column passes with no reciprocal-space operation hold no per-element
+// registers besides the transform and take twice as many columns (the
+// 1024-point passes of the 10^6-atom cell: 128-byte row segments instead of
+// 64-byte ones, measured faster; the other lengths reach the 16-column cap
+// either way)
+template <typename T, int L> constexpr int col_P_plain()
+{
+    int p = pow2_floor(2 * Cfg<T>::COL_ELEMS / L);
     if (p > OFDFT_COL_PMAX) p = OFDFT_COL_PMAX;
     if (p < 4) p = 4;
     if (p > NT) p = NT;
@@ -344,10 +357,9 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 // array, which keeps DRAM pages open) or tile-major (consecutive blocks take
 // one tile of every (field, density) array, which keeps the tile's share of
 // the reciprocal-space tables in L2).
-template <typename T, int L>
+template <typename T, int L, int P>
 __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
 {
-    constexpr int P = col_P<T, L>();
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     static_assert(NT % P == 0, "tile width must divide the block");
@@ -386,8 +398,10 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
     // the forward transform: v_ext(G) for the Hartree+ion field, the
     // Wang-Teter kernel for the nonlocal field (element n of column c is the
     // half-spectrum point e = n * ncols + c on axis 0)
-    cpx<T> pre[PER];
-    if (op == GO_HEXT || op == GO_WT) {
+    // the wide-tile instantiation (P != col_P) serves plain passes only
+    constexpr bool OPS = P == col_P<T, L>();
+    cpx<T> pre[OPS ? PER : 1];
+    if (OPS && (op == GO_HEXT || op == GO_WT)) {
         const cpx<T> *vx = (const cpx<T> *)a.vext;
         const T *om = (const T *)a.gtab + 2 * a.g.Nh;
 #pragma unroll
@@ -405,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
         }
     }
     constexpr bool MULTI = make_plan(L, sizeof(T) == 4).n >= 2;
-    if (op == GO_NONE) {
+    if (!OPS || op == GO_NONE) {
         if constexpr (MULTI) {
             if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1>(buf, tw, tid, ld, st);
             else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tid, ld, st);
@@ -416,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
             if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
             else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
         }
-    } else {
+    } else if constexpr (OPS) {
         // axis 0: element n is i0, column c is (i1, k2)
         lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, ld);
         const Geom &g = a.g;
@@ -1583,13 +1597,27 @@ template <typename T, int L>
 hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
 {
     constexpr int P = col_P<T, L>();
+    constexpr int PP = col_P_plain<T, L>();
+    bool has_part = false, plain = true;
+    for (int f = 0; f < MAXKB; ++f) {
+        has_part |= (a.op[f] == GO_HEXT || a.op[f] == GO_VW);
+        plain &= a.op[f] == GO_NONE;
+    }
+    if constexpr (PP != P) {
+        if (plain) {
+            nblocks = (int)((a.ncols + PP - 1) / PP);
+            const long long total = (long long)nblocks * nfb;
+            if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_col<T, L, PP>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb,
+                               nblocks);
+            return hipGetLastError();
+        }
+    }
     nblocks = (int)((a.ncols + P - 1) / P);
-    bool has_part = false;
-    for (int f = 0; f < MAXKB; ++f) has_part |= (a.op[f] == GO_HEXT || a.op[f] == GO_VW);
     if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
     const long long total = (long long)nblocks * nfb;
     if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_col<T, L>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb, nblocks);
+    hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb, nblocks);
     return hipGetLastError();
 }
 
