@@ -154,6 +154,8 @@ def parse():
     ap.add_argument("--c5-no-polish", action="store_true")
     ap.add_argument("--c5-budget", type=float, default=420.0,
                     help="seconds for the mixed optimisation")
+    ap.add_argument("--opt-methods", action="store_true",
+                    help="optimise the 108-atom cell with CG, preconditioned CG and truncated Newton")
     ap.add_argument("--multistep", action="store_true",
                     help="multi-step (coarse then fine grid) cluster optimisation vs a fine start")
     ap.add_argument("--ms-atoms", type=int, default=561)
@@ -651,8 +653,54 @@ def multistep_main(args):
     print(json.dumps(out), flush=True)
 
 
+def opt_methods_main(args):
+    """Density optimisation of the 108-atom Al cell (96^3, WT + vW + TF +
+    Hartree + local pseudopotential) from a Gaussian guess with the three
+    methods of the library: CG, preconditioned CG and truncated Newton
+    (Section "Density optimization strategies" compares CG, L-BFGS and TN)."""
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    terms = ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT | ofdft.TERM_WT
+    cell, _ = W.config_c2(N_GRID, 1)
+    rho0 = W.gaussian_density(cell, sigma=1.5)
+    out = {"metric": "density optimisation wall time by method", "unit": "s", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "fcc Al 3x3x3 (108 atoms), 96^3, WT+vW+TF+Hartree+local "
+                                  "pseudopotential, Gaussian start; FP64 to RMS residual 1e-7, "
+                                  "mixed to 1e-5", "natoms": len(cell["species"])}}
+    names = {ofdft.OPT_CG: "cg", ofdft.OPT_PCG: "pcg", ofdft.OPT_TN: "tn"}
+    for prec, pname, tol in ((ofdft.FP64, "fp64", 1e-7), (ofdft.MIXED, "mixed", 1e-5)):
+        with ofdft.Grid(cell, terms, precision=prec) as g:
+            for rep in range(2):   # the first pass warms up
+                for m in (ofdft.OPT_CG, ofdft.OPT_PCG, ofdft.OPT_TN):
+                    g.set_density(rho0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r, st = g.optimize(tol=tol, max_iter=3000, method=m, allow_noconv=True)
+                    t = time.perf_counter() - t0
+                    out["%s_%s" % (pname, names[m])] = {
+                        "wall_s": round(t, 3), "iters": r.iters, "evals": r.evals,
+                        "status": st, "final_resid": r.final_resid, "e_total": r.e.e_total}
+                    if rep == 1:
+                        log("%s %s: %d iterations, %d evaluations, %.3f s, resid %.2e, E %.10f" % (
+                            pname, names[m], r.iters, r.evals, t, r.final_resid, r.e.e_total))
+    out["value"] = out["fp64_tn"]["wall_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.opt_methods:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        opt_methods_main(args)
+        return
     if args.multistep:
         if args.gpus != 1:
             print("bench.py: this build runs on one GPU", file=sys.stderr)

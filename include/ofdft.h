@@ -208,16 +208,23 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host);
  * OFDFT_ENOCONV (with the result filled in) when max_iter is reached. */
 enum {
     OFDFT_OPT_CG = 0,   /* Polak-Ribiere+ on the residual R                          */
-    OFDFT_OPT_PCG = 1   /* the same on z = K R with the reciprocal-space preconditioner
+    OFDFT_OPT_PCG = 1,  /* the same on z = K R with the reciprocal-space preconditioner
                            K(G) = 1 / (1 + G^2 + 16 pi rho0 / G^2), rho0 = N_e / V, the
                            inverse of the phi-Hessian's vW (G^2) and long-wavelength
                            Hartree (16 pi rho0 / G^2) parts plus a unit shift; K(0) = 1
                            (two extra transforms per iteration)                       */
+    OFDFT_OPT_TN = 2    /* truncated Newton (the paper's TN): the direction solves
+                           H_T d = -R approximately by CG preconditioned with K, H_T the
+                           Hessian of E on the tangent space of the N_e constraint
+                           applied by finite differences of dE/dphi (one evaluation per
+                           product, at most 20 per iteration, stopped at |r| <=
+                           min(1/2, sqrt(rms R)) |R| or on negative curvature); the
+                           line search starts at the Newton step                     */
 };
 typedef struct {
     double tol;
     int32_t max_iter;
-    int32_t method;   /* OFDFT_OPT_CG or OFDFT_OPT_PCG */
+    int32_t method;   /* OFDFT_OPT_CG, OFDFT_OPT_PCG or OFDFT_OPT_TN */
     int32_t warm;     /* server requests: start from the resident density */
 } ofdft_opt_params;
 typedef struct {

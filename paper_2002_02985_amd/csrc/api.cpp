@@ -1495,6 +1495,68 @@ static double cubic_min(double a, double fa, double da, double b, double fb, dou
     return b - (b - a) * (db + d2 - d1) / den;
 }
 
+// Truncated-Newton direction (Section "Density optimization strategies":
+// the paper's TN, a line-search Newton-CG method) on the tangent space of
+// the constraint <phi, phi> dv = N_e: preconditioned CG on H_T d = -R with
+// H_T v = P[(g(phi + h v) - g(phi)) / h - 2 mu v], P the projector orthogonal
+// to phi and h a finite-difference step relative to |phi| / |v|; stopped at
+// |r| <= min(1/2, sqrt(|R|_rms)) |R| (the forcing sequence of Newton-CG), on
+// negative curvature (the first iteration then returns the preconditioned
+// steepest descent direction) or after max_inner products.  On entry V_R
+// holds R and V_Z holds K R; on return V_D holds d.  Each product is one
+// evaluation.  Vectors: r in V_RP, z in V_Z, p in V_ZP, H p in V_P, the
+// displaced phi and its gradient in V_PT and V_GT.
+template <typename T>
+static ofdft_status tn_direction(OptState &o, void **v, const ofdft_energy &E, int &evals)
+{
+    ofdft_grid *g = o.g;
+    hipStream_t s = o.s;
+    const int max_inner = 20;
+    const double eta_fd = g->fp64 ? 1e-6 : 1e-3;
+    double w[3];
+    ST_TRY(dots<T>(o, 3, v[V_Z], v[V_PHI], v[V_PHI], v[V_PHI], v[V_R], v[V_R], w));
+    const double pp = w[1], rr0 = w[2];
+    if (!(pp > 0) || !(rr0 > 0)) return fail(OFDFT_EINVAL, "degenerate Newton system");
+    ST_TRY(lincomb<T>(o, v[V_Z], -1.0, v[V_Z], w[0] / pp, v[V_PHI]));   // z = P K r, r = -R
+    ST_TRY(lincomb<T>(o, v[V_RP], -1.0, v[V_R], 0.0, nullptr));
+    ST_TRY(lincomb<T>(o, v[V_ZP], 1.0, v[V_Z], 0.0, nullptr));          // p = z
+    ST_TRY(lincomb<T>(o, v[V_D], 0.0, v[V_Z], 0.0, nullptr));           // d = 0
+    ST_TRY(dots<T>(o, 1, v[V_RP], v[V_Z], nullptr, nullptr, nullptr, nullptr, w));
+    double rz = w[0];
+    const double eta = std::min(0.5, std::sqrt(E.resid_norm));
+    for (int j = 0; j < max_inner; ++j) {
+        ST_TRY(dots<T>(o, 1, v[V_ZP], v[V_ZP], nullptr, nullptr, nullptr, nullptr, w));
+        if (!(w[0] > 0)) break;
+        const double h = eta_fd * std::sqrt(pp / w[0]);
+        ST_TRY(lincomb<T>(o, v[V_PT], 1.0, v[V_PHI], h, v[V_ZP]));
+        ofdft_energy Et;
+        ST_TRY(eval_dispatch(g, 1, v[V_PT], 1, nullptr, v[V_GT], s, &Et));
+        ++evals;
+        ST_TRY(lincomb<T>(o, v[V_P], 1.0 / h, v[V_GT], -1.0 / h, v[V_G]));
+        ST_TRY(lincomb<T>(o, v[V_P], 1.0, v[V_P], -2.0 * E.mu, v[V_ZP]));
+        ST_TRY(dots<T>(o, 2, v[V_P], v[V_PHI], v[V_ZP], v[V_P], nullptr, nullptr, w));
+        ST_TRY(lincomb<T>(o, v[V_P], 1.0, v[V_P], -w[0] / pp, v[V_PHI]));   // H_T p
+        const double pAp = w[1];   // p is orthogonal to phi
+        if (!(pAp > 0)) {
+            if (j == 0) ST_TRY(lincomb<T>(o, v[V_D], 1.0, v[V_ZP], 0.0, nullptr));
+            break;
+        }
+        const double alpha = rz / pAp;
+        ST_TRY(lincomb<T>(o, v[V_D], 1.0, v[V_D], alpha, v[V_ZP]));
+        ST_TRY(lincomb<T>(o, v[V_RP], 1.0, v[V_RP], -alpha, v[V_P]));
+        ST_TRY(dots<T>(o, 1, v[V_RP], v[V_RP], nullptr, nullptr, nullptr, nullptr, w));
+        if (std::sqrt(w[0]) <= eta * std::sqrt(rr0)) break;
+        ST_TRY(precondition<T>(o, v[V_RP], v[V_Z]));
+        ST_TRY(dots<T>(o, 1, v[V_Z], v[V_PHI], nullptr, nullptr, nullptr, nullptr, w));
+        ST_TRY(lincomb<T>(o, v[V_Z], 1.0, v[V_Z], -w[0] / pp, v[V_PHI]));
+        ST_TRY(dots<T>(o, 1, v[V_RP], v[V_Z], nullptr, nullptr, nullptr, nullptr, w));
+        const double beta = w[0] / rz;
+        rz = w[0];
+        ST_TRY(lincomb<T>(o, v[V_ZP], 1.0, v[V_Z], beta, v[V_ZP]));
+    }
+    return OFDFT_OK;
+}
+
 template <typename T>
 static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, ofdft_opt_result *res)
 {
@@ -1507,7 +1569,8 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     const double dv = g->dv, ne = g->nelec;
     const int max_iter = prm->max_iter;
     const double tol = prm->tol;
-    const bool precond = prm->method == OFDFT_OPT_PCG;
+    const bool tn = prm->method == OFDFT_OPT_TN;
+    const bool precond = prm->method == OFDFT_OPT_PCG || tn;
     // The line search brackets and refines a root of dE/dtheta = <g, dphi/dtheta>
     // without comparing energies (a) when the potential is not the derivative
     // of the energy: the S3S4 spline potential interpolates per-knot
@@ -1544,7 +1607,9 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         const int Z = precond ? V_Z : V_R, ZP = precond ? V_ZP : V_RP;
         if (precond) ST_TRY(precondition<T>(o, v[V_R], v[V_Z]));
         double dd[3];
-        if (have_prev) {
+        if (tn) {
+            ST_TRY(tn_direction<T>(o, v, E, evals));
+        } else if (have_prev) {
             // Polak-Ribiere+: beta = max(0, <z, R - R_prev> / <z_prev, R_prev>)
             ST_TRY(dots<T>(o, 3, v[Z], v[V_R], v[Z], v[V_RP], v[ZP], v[V_RP], dd));
             const double beta = std::max(0.0, (dd[0] - dd[1]) / dd[2]);
@@ -1556,6 +1621,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         for (int attempt = 0; attempt < 2; ++attempt) {
             ST_TRY(dots<T>(o, 3, v[V_D], v[V_R], v[V_D], v[V_PHI], v[V_PHI], v[V_PHI], q));
             if (q[0] >= 0.0 && attempt == 0) {   // not a descent direction: restart
+                if (tn) ST_TRY(precondition<T>(o, v[V_R], v[V_Z]));   // TN used V_Z
                 ST_TRY(lincomb<T>(o, v[V_D], -1.0, v[Z], 0.0, nullptr));
                 continue;
             }
@@ -1573,6 +1639,8 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
 
         double theta0 = (kappa > 0) ? std::min(1.0, std::max(1e-12, -d0 / kappa))
                                     : (theta_prev > 0 ? theta_prev : 0.1);
+        // TN: the Newton step phi + d is theta = |P d| / |phi| along the rotation
+        if (tn) theta0 = std::min(1.0, std::max(1e-12, std::sqrt(pq[0] / q[2])));
         const double f0 = E.e_total;
         // energy differences below the evaluation's rounding level are not
         // trusted: there the search accepts on the derivative conditions
@@ -2098,7 +2166,8 @@ ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, of
 {
     if (!grid || !params || !result) return fail(OFDFT_EINVAL, "null argument");
     if (!(params->tol > 0) || params->max_iter < 0) return fail(OFDFT_EINVAL, "bad parameters");
-    if (params->method != OFDFT_OPT_CG && params->method != OFDFT_OPT_PCG)
+    if (params->method != OFDFT_OPT_CG && params->method != OFDFT_OPT_PCG &&
+        params->method != OFDFT_OPT_TN)
         return fail(OFDFT_EINVAL, "unknown optimisation method");
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return grid->fp64 ? optimize_impl<double>(grid, params, result)

@@ -21,7 +21,7 @@ KNOTS_LOG, KNOTS_LIN = 0, 1
 NL_S3S4, NL_EXACT = 0, 1
 FP64, MIXED = 0, 1
 REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
-OPT_CG, OPT_PCG = 0, 1
+OPT_CG, OPT_PCG, OPT_TN = 0, 1, 2
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
               "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
 

@@ -235,6 +235,36 @@ def test_optimize_c1_preconditioned_reaches_the_same_minimum():
     assert abs(r.e.e_total - ref.result.e_total) < 1e-9
 
 
+@pytest.mark.parametrize("name", ["c1_local", "c1_wt", "c1_local_xc"])
+def test_truncated_newton_reaches_the_oracle_minimum(name):
+    """The truncated-Newton direction changes the path, not the minimiser:
+    the oracle's CG minimum (TF+vW+H+ext, with WT or LDA) to 1e-9 Ha in FP64,
+    1e-5 Ha/atom mixed."""
+    from oracle.optimize import optimize as o_opt
+    mk, terms, kw = CASES[name]
+    cell, rho = mk()
+    oc = make_cell(cell)
+    ref = o_opt(oc, oracle_func(terms, **kw), np.sqrt(rho), tol=1e-7, max_iter=800,
+                vext=OF.vext_g(oc), e_ion=ewald_energy(oc))
+    assert ref.converged
+    natoms = len(cell["species"])
+    for prec in (ofdft.FP64, ofdft.MIXED):
+        with ofdft.Grid(cell, terms, precision=prec, **kw) as g:
+            g.set_density(rho)
+            tol = 1e-7 if prec == ofdft.FP64 else 2e-5
+            r, st = g.optimize(tol=tol, max_iter=300, method=ofdft.OPT_TN)
+            g.set_density(rho)
+            rp, _ = g.optimize(tol=tol, max_iter=300, method=ofdft.OPT_PCG)
+        print("%s %s: TN %d it %d ev, PCG %d it %d ev, dE %.2e" % (
+            name, "fp64" if prec == ofdft.FP64 else "mixed", r.iters, r.evals, rp.iters,
+            rp.evals, r.e.e_total - ref.result.e_total), flush=True)
+        assert st == ofdft.OK
+        if prec == ofdft.FP64:
+            assert abs(r.e.e_total - ref.result.e_total) < 1e-9
+        else:
+            assert abs(r.e.e_total - ref.result.e_total) <= 1e-5 * natoms
+
+
 @pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
 def test_preconditioner_speeds_up_a_vacuum_cluster(prec):
     cell = W.cluster(19, "Al", seed=11, grid=48)
