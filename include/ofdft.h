@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 4
+#define OFDFT_ABI_VERSION 5
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
@@ -84,10 +84,24 @@ enum { OFDFT_KNOTS_LOG = 0, OFDFT_KNOTS_LIN = 1 };
 enum { OFDFT_NL_S3S4 = 0, OFDFT_NL_EXACT = 1 };
 enum { OFDFT_FP64 = 0, OFDFT_MIXED = 1 };
 
+/* Ionic structure factor S(G) = sum_a exp(-iG.R_a) behind v_ext(G) and the
+ * Ewald reciprocal sum.  DIRECT: the exact sum (per-atom phase tables below
+ * 8192 atoms, a tiled direct sum from there on).  PME: the smooth
+ * particle-mesh Ewald approximation the paper uses for large cells (Sections
+ * "OFDFT software background" and "Leveraging existing techniques"; the
+ * method of Essmann et al. 1995): each species' atoms spread onto the grid
+ * with cardinal B-splines of order pme_order, one forward transform, and the
+ * exponential-spline factors; the Ewald split is chosen so that the
+ * reciprocal sum ends at half the box.  PME takes the large-cell ionic path
+ * at any atom count, where ofdft_forces is not offered. */
+enum { OFDFT_SF_DIRECT = 0, OFDFT_SF_PME = 1 };
+
 /* Cell: lattice vectors as rows (Bohr), grid, atoms.  pos is natoms x 3
  * Cartesian Bohr; species[a] indexes Z[] (valence charge) and rc[] (radius of
  * the local pseudopotential v(G) = -4 pi Z exp(-G^2 rc^2 / 4) / G^2, i.e.
- * -Z erf(r/rc)/r, with the non-Coulomb G = 0 value pi Z rc^2). */
+ * -Z erf(r/rc)/r, with the non-Coulomb G = 0 value pi Z rc^2).  sf_method is
+ * an OFDFT_SF_* value (0, the exact sum, when zero-initialised); pme_order the
+ * even B-spline order 4 .. 16, at most every n[d] (0 selects 10). */
 typedef struct {
     double lattice[3][3];
     int32_t n[3];
@@ -98,6 +112,8 @@ typedef struct {
     const double *Z;
     const double *rc;
     double nelec;
+    int32_t sf_method;
+    int32_t pme_order;
 } ofdft_cell_desc;
 
 /* Functional.  alpha and beta are the exponents of eq. "nl2"; the GPU path

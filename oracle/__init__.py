@@ -21,6 +21,8 @@ simulations", arXiv:2002.02985):
 * the density-dependent-kernel (LWT) functional evaluated with linear splines
   over k_F knots (steps s1-s4 of the same section),
 * Hellmann-Feynman forces and the ion-ion Ewald energy,
+* the smooth particle-mesh Ewald structure factor the paper uses for large
+  cells (``oracle.pme``),
 * the constrained minimisation over psi = sqrt(rho) with the orthogonal
   rotation update (Section "Density optimization strategies").
 

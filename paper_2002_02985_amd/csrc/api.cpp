@@ -159,6 +159,9 @@ struct ofdft_grid {
     uint64_t graph_clock = 0;
     int *d_bin_start = nullptr, *d_bin_of = nullptr;
     double *d_ew_part = nullptr;
+    int sf_method = OFDFT_SF_DIRECT;            // structure factor of the ionic terms
+    int pme_order = 0;                          // B-spline order of the PME spread
+    double2 *d_pme_b = nullptr;                 // conjugated exponential-spline factors
 };
 
 // ---------------------------------------------------------------- helpers
@@ -259,7 +262,7 @@ struct LargeEwald {
     int nbin[3];
 };
 static LargeEwald large_ewald(const double lat[3][3], const double b[3][3], double V, int na,
-                              const int n[3])
+                              const int n[3], bool pme)
 {
     LargeEwald L;
     L.e = ewald_geom(lat, b, V, na);
@@ -268,7 +271,9 @@ static LargeEwald large_ewald(const double lat[3][3], const double b[3][3], doub
         const double an = std::sqrt(lat[d][0] * lat[d][0] + lat[d][1] * lat[d][1] + lat[d][2] * lat[d][2]);
         gmax = std::min(gmax, PI * (n[d] - 2) / an);
     }
-    const double a = std::min(L.e.a, gmax / 13.2);
+    // with PME the reciprocal sum stops at half the box, where the spline
+    // interpolation of S(G) is accurate
+    const double a = std::min(L.e.a, gmax / (pme ? 26.4 : 13.2));
     const double rcut = 6.6 / a;
     L.e.a = a;
     L.e.rcut2 = rcut * rcut;
@@ -285,19 +290,22 @@ static LargeEwald large_ewald(const double lat[3][3], const double b[3][3], doub
     return L;
 }
 
-static bool use_large_ions(int na)
+static bool use_large_ions(int na, int sf_method)
 {
+    if (na > 0 && sf_method == OFDFT_SF_PME) return true;
     if (const char *e = std::getenv("OFDFT_LARGE_IONS")) return std::atoi(e) != 0 && na > 0;
     return na >= LARGE_IONS;
 }
 
+static int pme_order_of(int order) { return order > 0 ? order : 10; }
+
 // device bytes of the ionic buffers: sorted fractional coordinates, Ewald
 // positions, charges, per-atom energies and forces, and S(G) on the box; for
 // large cells bins and per-block reciprocal partials instead of S(G) and forces
-static uint64_t ion_bytes(const double lat[3][3], int na, const Geom &G)
+static uint64_t ion_bytes(const double lat[3][3], int na, int sf_method, const Geom &G)
 {
     if (na <= 0) return 0;
-    if (use_large_ions(na)) {
+    if (use_large_ions(na, sf_method)) {
         const double(*A)[3] = lat;
         const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
                            A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
@@ -309,11 +317,15 @@ static uint64_t ion_bytes(const double lat[3][3], int na, const Geom &G)
                 b[i][j] = 2.0 * PI * (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;
             }
         const int n[3] = {G.n0, G.n1, G.n2};
-        const LargeEwald L = large_ewald(lat, b, std::fabs(det), na, n);
+        const bool pme = sf_method == OFDFT_SF_PME;
+        const LargeEwald L = large_ewald(lat, b, std::fabs(det), na, n, pme);
         const bool binned = L.nbin[0] >= 3 && L.nbin[1] >= 3 && L.nbin[2] >= 3;
         const uint64_t nbins = binned ? (uint64_t)L.nbin[0] * L.nbin[1] * L.nbin[2] : 1;
-        return (uint64_t)na * (3 + 3 + 1 + 1) * 8 + (uint64_t)na * 4 + (nbins + 1) * 4 +
-               (uint64_t)sf_tiled_blocks(G) * 8 + (binned ? 0 : 16);
+        const uint64_t recip = pme ? (uint64_t)pme_finish_blocks(G) * 8 +
+                                         (uint64_t)(G.n0 + G.n1 + G.n2h) * 16
+                                   : (uint64_t)sf_tiled_blocks(G) * 8;
+        return (uint64_t)na * (3 + 3 + 1 + 1) * 8 + (uint64_t)na * 4 + (nbins + 1) * 4 + recip +
+               (binned ? 0 : 16);
     }
     const double(*A)[3] = lat;
     const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
@@ -442,15 +454,16 @@ static int max_pstride(const Geom &G, bool fp64)
 struct BytesModel {
     bool stage = false, opt = false, forces = false;
 };
-static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, uint32_t terms,
-                            int nl_mode, int nk, uint64_t cap, uint64_t ions, BytesModel m)
+static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, int sf_method,
+                            uint32_t terms, int nl_mode, int nk, uint64_t cap, uint64_t ions,
+                            BytesModel m)
 {
     const uint64_t N = (uint64_t)G.N, Nh = (uint64_t)G.Nh, cb = 2 * fsz;
     uint64_t b = 0;
     b += (uint64_t)(G.n0 + G.n1 + G.m + (G.m + 1)) * cb;             // twiddles
     b += Nh * cb;                                                       // v_ext
     b += Nh * 3 * fsz;                                                  // G tables
-    if (!use_large_ions(natoms))
+    if (!use_large_ions(natoms, sf_method))
         b += (uint64_t)natoms * (G.n0 + G.n1 + G.n2h) * 16;             // phase tables
     b += ions;                                                          // coordinates, Ewald
     b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
@@ -1045,6 +1058,15 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
             if (!std::isfinite(c->pos[3 * a + k])) return fail(OFDFT_EINVAL, "non-finite position");
     }
     if (!(c->nelec > 0)) return fail(OFDFT_EINVAL, "nelec must be positive");
+    if (c->sf_method != OFDFT_SF_DIRECT && c->sf_method != OFDFT_SF_PME)
+        return fail(OFDFT_EINVAL, "unknown structure-factor method");
+    if (c->sf_method == OFDFT_SF_PME) {
+        const int P = pme_order_of(c->pme_order);
+        if (P < 4 || P > PME_MAX_ORDER || P % 2 != 0)
+            return fail(OFDFT_EINVAL, "pme_order must be even, 4 to 16");
+        if (P > c->n[0] || P > c->n[1] || P > c->n[2])
+            return fail(OFDFT_EINVAL, "pme_order exceeds a grid dimension");
+    }
     const uint32_t all = OFDFT_TERM_TF | OFDFT_TERM_VW | OFDFT_TERM_HARTREE | OFDFT_TERM_EXT |
                          OFDFT_TERM_WT | OFDFT_TERM_SPLINE | OFDFT_TERM_XC;
     if (f->terms & ~all) return fail(OFDFT_EINVAL, "unknown term bits");
@@ -1102,6 +1124,7 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_bin_start));
     dfree(reinterpret_cast<void *&>(g->d_bin_of));
     dfree(reinterpret_cast<void *&>(g->d_ew_part));
+    dfree(reinterpret_cast<void *&>(g->d_pme_b));
     dfree(g->rho);
     for (auto &p : g->opt) dfree(p);
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -1119,36 +1142,188 @@ static void grid_free(ofdft_grid *g)
     }
 }
 
+// Exponential-spline factors of smooth PME along one axis of K points,
+// conjugated for the exp(-iG.R) sign of the structure factor: out[m] =
+// conj(b(m)), m = 0 .. cnt-1, with b(m) = exp(2 pi i (P-1) m / K) /
+// sum_{k=0}^{P-2} M_P(k+1) exp(2 pi i m k / K).  False if a denominator
+// vanishes.
+template <int P>
+static void bspline_integers(double *out)
+{
+    double w[P];
+    bspline_fill<P>(0.0, w);   // w[j] = M_P(j)
+    for (int j = 0; j < P; ++j) out[j] = w[j];
+}
+static bool pme_bfactors(int order, int K, int cnt, double2 *out)
+{
+    double M[PME_MAX_ORDER];
+    switch (order) {
+    case 4: bspline_integers<4>(M); break;
+    case 6: bspline_integers<6>(M); break;
+    case 8: bspline_integers<8>(M); break;
+    case 10: bspline_integers<10>(M); break;
+    case 12: bspline_integers<12>(M); break;
+    case 14: bspline_integers<14>(M); break;
+    case 16: bspline_integers<16>(M); break;
+    default: return false;
+    }
+    for (int m = 0; m < cnt; ++m) {
+        double dr = 0.0, di = 0.0;
+        for (int k = 0; k <= order - 2; ++k) {
+            const double ang = 2.0 * PI * (double)(((long long)m * k) % K) / K;
+            dr += M[k + 1] * std::cos(ang);
+            di += M[k + 1] * std::sin(ang);
+        }
+        const double den2 = dr * dr + di * di;
+        if (!(den2 > 1e-300)) return false;
+        const double ang = 2.0 * PI * (double)(((long long)m * (order - 1)) % K) / K;
+        const double nr = std::cos(ang), ni = std::sin(ang);
+        out[m] = {(nr * dr + ni * di) / den2, -(ni * dr - nr * di) / den2};
+    }
+    return true;
+}
+
+// Bound on any charge-grid value: atoms contributing to a point have their
+// base index floor(n s) within P consecutive points per axis, so they lie in
+// two adjacent cells of a partition into cells at least P points wide; each
+// atom adds at most 1.
+static double pme_grid_bound(const Geom &G, int P, const std::vector<double> &fr)
+{
+    const int na = (int)(fr.size() / 3);
+    const int n[3] = {G.n0, G.n1, G.n2};
+    int c[3];
+    for (int d = 0; d < 3; ++d) c[d] = std::max(1, n[d] / P);
+    std::vector<int> cnt((size_t)c[0] * c[1] * c[2], 0);
+    for (int a = 0; a < na; ++a) {
+        int ci[3];
+        for (int d = 0; d < 3; ++d) {
+            int b = (int)std::floor(fr[3 * (size_t)a + d] * n[d]);
+            b = std::min(std::max(b, 0), n[d] - 1);
+            ci[d] = std::min(b / P, c[d] - 1);
+        }
+        cnt[((size_t)ci[0] * c[1] + ci[1]) * c[2] + ci[2]]++;
+    }
+    double worst = 0.0;
+    for (int x = 0; x < c[0]; ++x)
+        for (int y = 0; y < c[1]; ++y)
+            for (int z = 0; z < c[2]; ++z) {
+                double t = 0.0;
+                for (int dx = 0; dx < 2; ++dx)
+                    for (int dy = 0; dy < 2; ++dy)
+                        for (int dz = 0; dz < 2; ++dz)
+                            t += cnt[(((size_t)(x + dx) % c[0]) * c[1] + (y + dy) % c[1]) * c[2] +
+                                     (z + dz) % c[2]];
+                worst = std::max(worst, t);
+            }
+    return worst;
+}
+
+// v_ext(G) and the Ewald reciprocal sum by smooth PME: per species, the
+// fixed-point charge grid, the grid's forward transform (in the grid's
+// precision) into the workspace spectrum, and the spline-factor pass.
+template <typename T>
+static ofdft_status pme_reciprocal(ofdft_grid *g, const LargeEwald &L,
+                                   const std::vector<double> &fr, double *erec)
+{
+    const Geom &G = g->geom;
+    const int na = g->natoms, ns = (int)g->Z.size(), P = g->pme_order;
+    hipStream_t s = g->ctx->stream;
+    if (na >= (1 << (64 - PME_FIX_BITS - 1)) &&
+        pme_grid_bound(G, P, fr) >= (double)(1ull << (64 - PME_FIX_BITS - 1)))
+        return fail(OFDFT_EINVAL, "too many atoms within one PME spline window");
+    if (!g->d_pme_b) {
+        std::vector<double2> bt((size_t)G.n0 + G.n1 + G.n2h);
+        if (!pme_bfactors(P, G.n0, G.n0, bt.data()) ||
+            !pme_bfactors(P, G.n1, G.n1, bt.data() + G.n0) ||
+            !pme_bfactors(P, G.n2, G.n2h, bt.data() + G.n0 + G.n1))
+            return fail(OFDFT_EINVAL, "a PME spline factor vanishes");
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_pme_b), bt.size() * sizeof(double2)));
+        ST_TRY(h2d(g, g->d_pme_b, bt.data(), bt.size() * sizeof(double2)));
+    }
+    const int nblk = pme_finish_blocks(G);
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_part), (size_t)nblk * 8));
+    ST_TRY(reserve(g, 1));
+    std::vector<int> off(ns + 1, 0);
+    for (int a = 0; a < na; ++a) off[g->species[a] + 1]++;
+    for (int k = 0; k < ns; ++k) off[k + 1] += off[k];
+    // transient: the fixed-point grid (converted in place for FP64), its
+    // FP32 copy, and sum_s Z_s S_s between species
+    void *qfix = nullptr, *qreal = nullptr, *qbuf = nullptr;
+    hipError_t e = hipMalloc(&qfix, (size_t)G.N * 8);
+    if (e == hipSuccess && !g->fp64) e = hipMalloc(&qreal, (size_t)G.N * sizeof(T));
+    if (e == hipSuccess && ns > 1) e = hipMalloc(&qbuf, (size_t)G.Nh * 16);
+    ofdft_status st = OFDFT_OK;
+    if (e != hipSuccess) st = fail(OFDFT_ENOMEM, "PME charge grid allocation failed");
+    void *qr = g->fp64 ? qfix : qreal;
+    for (int sp = 0; sp < ns && st == OFDFT_OK; ++sp) {
+        e = hipMemsetAsync(qfix, 0, (size_t)G.N * 8, s);
+        if (e == hipSuccess)
+            e = launch_pme_spread(G, P, off[sp], off[sp + 1] - off[sp], g->d_frac,
+                                  (unsigned long long *)qfix, s);
+        if (e == hipSuccess) e = launch_pme_to_real<T>(G, (const unsigned long long *)qfix, qr, s);
+        if (e != hipSuccess) {
+            st = fail(OFDFT_EDEVICE, std::string("PME spread: ") + hipGetErrorString(e));
+            break;
+        }
+        st = fft_impl<T>(g, 1, qr, g->spec, true, s);
+        if (st != OFDFT_OK) break;
+        e = launch_pme_finish<T>(G, g->spec, g->d_pme_b, g->Z[sp], g->rc[sp], g->V, L.e.a,
+                                 L.e.gcut2, sp == 0, sp == ns - 1, g->vext, qbuf, g->d_ew_part, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            st = fail(OFDFT_EDEVICE, std::string("PME finish: ") + hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(s);
+    if (qfix) (void)hipFree(qfix);
+    if (qreal) (void)hipFree(qreal);
+    if (qbuf) (void)hipFree(qbuf);
+    ST_TRY(st);
+    std::vector<double> part((size_t)nblk);
+    HIP_TRY(hipMemcpyAsync(part.data(), g->d_ew_part, part.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (double x : part) sum += x;
+    *erec = sum * 2.0 * PI / g->V;
+    return OFDFT_OK;
+}
+
 // Large cells: v_ext(G) and the Ewald reciprocal sum from the tiled direct
-// sum, the real-space Ewald sum over bins.  fr: species-sorted fractional
-// coordinates (already on the device in d_frac).
+// sum (or smooth PME), the real-space Ewald sum over bins.  fr:
+// species-sorted fractional coordinates (already on the device in d_frac).
 static ofdft_status setup_ions_large(ofdft_grid *g, const std::vector<int> &order,
                                      const std::vector<double> &fr)
 {
     const Geom &G = g->geom;
     const int na = g->natoms, ns = (int)g->Z.size();
     hipStream_t s = g->ctx->stream;
-    const LargeEwald L = large_ewald(g->lattice, G.b, g->V, na, g->n);
-    const long long nblk = sf_tiled_blocks(G);
-    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_part), (size_t)nblk * 8));
-    void *qbuf = nullptr;
-    if (ns > 1) {
-        HIP_TRY(hipMalloc(&qbuf, (size_t)G.Nh * 16));   // released below
-    }
-    hipError_t err = g->fp64
-        ? launch_sf_tiled<double>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V, L.e.a,
-                                  L.e.gcut2, g->vext, qbuf, g->d_ew_part, s)
-        : launch_sf_tiled<float>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V, L.e.a,
-                                 L.e.gcut2, g->vext, qbuf, g->d_ew_part, s);
-    if (err == hipSuccess) err = hipStreamSynchronize(s);
-    if (qbuf) (void)hipFree(qbuf);
-    HIP_TRY(err);
-    std::vector<double> part((size_t)nblk);
-    HIP_TRY(hipMemcpyAsync(part.data(), g->d_ew_part, part.size() * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const bool pme = g->sf_method == OFDFT_SF_PME;
+    const LargeEwald L = large_ewald(g->lattice, G.b, g->V, na, g->n, pme);
     double erec = 0.0;
-    for (double x : part) erec += x;
-    erec *= 2.0 * PI / g->V;
+    if (pme) {
+        ST_TRY(g->fp64 ? pme_reciprocal<double>(g, L, fr, &erec)
+                       : pme_reciprocal<float>(g, L, fr, &erec));
+    } else {
+        const long long nblk = sf_tiled_blocks(G);
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_part), (size_t)nblk * 8));
+        void *qbuf = nullptr;
+        if (ns > 1) {
+            HIP_TRY(hipMalloc(&qbuf, (size_t)G.Nh * 16));   // released below
+        }
+        hipError_t err = g->fp64
+            ? launch_sf_tiled<double>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V,
+                                      L.e.a, L.e.gcut2, g->vext, qbuf, g->d_ew_part, s)
+            : launch_sf_tiled<float>(G, g->d_spec_off, ns, g->d_frac, g->d_Z, g->d_rc, g->V,
+                                     L.e.a, L.e.gcut2, g->vext, qbuf, g->d_ew_part, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (qbuf) (void)hipFree(qbuf);
+        HIP_TRY(err);
+        std::vector<double> part((size_t)nblk);
+        HIP_TRY(hipMemcpyAsync(part.data(), g->d_ew_part, part.size() * 8, hipMemcpyDeviceToHost,
+                               s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (double x : part) erec += x;
+        erec *= 2.0 * PI / g->V;
+    }
 
     // real space: atoms binned by fractional coordinate, positions wrapped
     // into the cell (counting sort, atoms in bin order); a cell less than
@@ -1979,7 +2154,9 @@ ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
     if (!g) return fail(OFDFT_ENOMEM, "host allocation failed");
     g->ctx = ctx;
     if (const char *e = std::getenv("OFDFT_COL_TILE_MAJOR")) g->tune_col_tile_major = std::atoi(e);
-    g->large_ions = use_large_ions(cell->natoms);
+    g->sf_method = cell->sf_method;
+    g->pme_order = pme_order_of(cell->pme_order);
+    g->large_ions = use_large_ions(cell->natoms, cell->sf_method);
     ofdft_status st = grid_setup(g, cell, func);
     if (st == OFDFT_OK) st = reserve(g, 1);
     if (st == OFDFT_OK) tune_apply_cached(g, 1);
@@ -2016,9 +2193,10 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     m.opt = grid->opt[0] != nullptr;
     m.forces = grid->d_forces != nullptr;
     uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
-                             grid->func.terms, grid->func.nl_mode,
+                             grid->sf_method, grid->func.terms, grid->func.nl_mode,
                              (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
-                             (uint64_t)grid->cap, ion_bytes(grid->lattice, grid->natoms, grid->geom), m);
+                             (uint64_t)grid->cap,
+                             ion_bytes(grid->lattice, grid->natoms, grid->sf_method, grid->geom), m);
     if (m.stage && !(grid->stage_in && grid->stage_out)) b -= (uint64_t)grid->geom.N * grid->fsz;
     return b;
 }
@@ -2041,8 +2219,9 @@ ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell, const ofdft_func
     m.opt = kind == OFDFT_REQ_OPTIMIZE;
     m.forces = kind == OFDFT_REQ_FORCES;
     *bytes = bytes_model(G, func->precision == OFDFT_FP64 ? 8 : 4, cell->natoms, cell->nspecies,
-                         func->terms, func->nl_mode, (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0,
-                         1, ion_bytes(cell->lattice, cell->natoms, G), m);
+                         cell->sf_method, func->terms, func->nl_mode,
+                         (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0, 1,
+                         ion_bytes(cell->lattice, cell->natoms, cell->sf_method, G), m);
     return OFDFT_OK;
 }
 
@@ -2134,7 +2313,8 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     if (na == 0) return OFDFT_OK;
     if (grid->large_ions)
         return fail(OFDFT_EINVAL, "forces are available for cells below " +
-                                      std::to_string(LARGE_IONS) + " atoms");
+                                      std::to_string(LARGE_IONS) +
+                                      " atoms with the direct structure factor");
     ofdft_grid *g = grid;
     hipStream_t s = g->ctx->stream;
     ST_TRY(reserve(g, 1));

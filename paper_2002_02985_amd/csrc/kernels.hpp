@@ -242,6 +242,45 @@ hipError_t launch_ewald_real_cells(const EwaldGeom &e, int natoms, const double 
                                    const double *q, const int *bin_start, const int *bin_of,
                                    const int nc[3], double *e_atom, hipStream_t s);
 
+// Smooth PME structure factor.  Cardinal B-spline of order P: w[j] =
+// M_P(t + j) for j = 0 .. P-1, t in [0, 1], from M_2(t) = t, M_2(t + 1) =
+// 1 - t and M_k(x) = (x M_{k-1}(x) + (k - x) M_{k-1}(x - 1)) / (k - 1).
+template <int P>
+__host__ __device__ inline void bspline_fill(double t, double (&w)[P])
+{
+    w[0] = t;
+    w[1] = 1.0 - t;
+#pragma unroll
+    for (int j = 2; j < P; ++j) w[j] = 0.0;
+#pragma unroll
+    for (int k = 3; k <= P; ++k) {
+        const double r = 1.0 / (k - 1);
+#pragma unroll
+        for (int j = k - 1; j >= 1; --j) w[j] = ((t + j) * w[j] + (k - t - j) * w[j - 1]) * r;
+        w[0] = t * w[0] * r;
+    }
+}
+constexpr int PME_FIX_BITS = 48;   // fractional bits of the fixed-point charge grid
+constexpr int PME_MAX_ORDER = 16;
+// charge grid q (N unsigned 64-bit fixed-point values, zeroed by the caller)
+// += the order-P B-splines of atoms [a_beg, a_beg + natoms) of frac
+// (fractional coordinates in [0, 1]); P even, 4 .. 16, at most every n_d
+hipError_t launch_pme_spread(const Geom &g, int order, int a_beg, int natoms, const double *frac,
+                             unsigned long long *q, hipStream_t s);
+// out[i] = q[i] / 2^PME_FIX_BITS as T (out may be q itself when T is double)
+template <typename T>
+hipError_t launch_pme_to_real(const Geom &g, const unsigned long long *q, void *out, hipStream_t s);
+// one species' share of v_ext(G) (and of the Ewald reciprocal sum after the
+// last species, one partial per block: pme_finish_blocks of them) from the
+// normalised forward transform F of its charge grid; bt: conjugated
+// exponential-spline factors b0(0..n0-1), b1(0..n1-1), b2(0..n2/2);
+// qbuf: Nh complex FP64, needed unless first and last
+int pme_finish_blocks(const Geom &g);
+template <typename T>
+hipError_t launch_pme_finish(const Geom &g, const void *F, const double2 *bt, double z, double rc,
+                             double volume, double ew_a, double ew_gcut2, int first, int last,
+                             void *vext, void *qbuf, double *ew_part, hipStream_t s);
+
 // vector kernels (optimizer): up to 4 dot products into part slots
 template <typename T>
 hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,

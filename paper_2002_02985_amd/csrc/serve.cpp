@@ -72,6 +72,7 @@ bool same_shape(const CellCopy &a, const ofdft_functional_desc &fa, const CellCo
     for (int k = 0; k < 3; ++k)
         if (a.d.n[k] != b.d.n[k]) return false;
     return a.d.natoms == b.d.natoms && a.d.nspecies == b.d.nspecies && a.d.nelec == b.d.nelec &&
+           a.d.sf_method == b.d.sf_method && a.d.pme_order == b.d.pme_order &&
            a.species == b.species && a.Z == b.Z && a.rc == b.rc && same_functional(fa, fb);
 }
 

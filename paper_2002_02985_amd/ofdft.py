@@ -22,6 +22,7 @@ NL_S3S4, NL_EXACT = 0, 1
 FP64, MIXED = 0, 1
 REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
 OPT_CG, OPT_PCG, OPT_TN = 0, 1, 2
+SF_DIRECT, SF_PME = 0, 1
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
               "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
 
@@ -31,7 +32,8 @@ class CellDesc(ctypes.Structure):
                 ("natoms", ctypes.c_int32), ("pos", ctypes.POINTER(ctypes.c_double)),
                 ("species", ctypes.POINTER(ctypes.c_int32)), ("nspecies", ctypes.c_int32),
                 ("Z", ctypes.POINTER(ctypes.c_double)), ("rc", ctypes.POINTER(ctypes.c_double)),
-                ("nelec", ctypes.c_double)]
+                ("nelec", ctypes.c_double), ("sf_method", ctypes.c_int32),
+                ("pme_order", ctypes.c_int32)]
 
 
 class FunctionalDesc(ctypes.Structure):
@@ -209,6 +211,8 @@ def make_cell_desc(cell):
     d.Z = _dptr(Z)
     d.rc = _dptr(rc)
     d.nelec = float(cell["nelec"])
+    d.sf_method = int(cell.get("sf_method", SF_DIRECT))
+    d.pme_order = int(cell.get("pme_order", 0))
     return d, (lat, pos, spc, Z, rc)
 
 

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_host_helpers():
-    assert ofdft.ofdft_abi_version() == 4
+    assert ofdft.ofdft_abi_version() == 5
     for n in (4, 6, 12, 32, 48, 96, 192, 256, 384, 1024):
         assert ofdft.ofdft_supported_length(n)
     for n in (5, 7, 10, 100, 2048):
@@ -47,3 +47,27 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ofdft.Energy) == 11 * 8
     assert ctypes.sizeof(ofdft.OptParams) == 8 + 3 * 4 + 4
     assert ofdft.CellDesc.nelec.offset == 9 * 8 + 3 * 4 + 4 + 8 + 8 + 8 + 8 + 8
+
+
+def test_structure_factor_settings_are_validated_on_the_host():
+    import numpy as np
+    cell = {"lattice": np.diag([9.0, 10.0, 11.0]), "n": (12, 12, 16),
+            "pos": np.array([[1.0, 2.0, 3.0]]), "species": np.zeros(1, np.int32),
+            "Z": np.array([3.0]), "rc": np.array([1.0]), "nelec": 3.0}
+    f = ofdft.make_functional_desc(ofdft.TERM_TF | ofdft.TERM_EXT)
+    for sf, order, want in ((ofdft.SF_DIRECT, 0, ofdft.OK), (ofdft.SF_PME, 0, ofdft.OK),
+                            (ofdft.SF_PME, 12, ofdft.OK), (ofdft.SF_PME, 7, ofdft.EINVAL),
+                            (ofdft.SF_PME, 2, ofdft.EINVAL), (ofdft.SF_PME, 18, ofdft.EINVAL),
+                            (ofdft.SF_PME, 14, ofdft.EINVAL),   # above n[0] = 12
+                            (5, 0, ofdft.EINVAL)):
+        d, keep = ofdft.make_cell_desc(dict(cell, sf_method=sf, pme_order=order))
+        assert ofdft.ofdft_validate(d, f) == want, (sf, order)
+    # PME needs no per-atom phase tables: a smaller footprint for many atoms
+    rng = np.random.default_rng(0)
+    big = dict(cell, pos=rng.random((500, 3)) * 9.0, species=np.zeros(500, np.int32),
+               nelec=1500.0)
+    sizes = []
+    for sf in (ofdft.SF_DIRECT, ofdft.SF_PME):
+        d, keep = ofdft.make_cell_desc(dict(big, sf_method=sf))
+        sizes.append(ofdft.ofdft_footprint_bytes(d, f, ofdft.REQ_EP))
+    assert sizes[1] < sizes[0]
