@@ -562,10 +562,11 @@ def c5_main(args):
                 (iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t1))
             if st == ofdft.OK or r.iters == 0:
                 break
-            # the FP32 floor: three chunks without a 10% better residual
-            stale = stale + 1 if r.final_resid > 0.9 * best else 0
+            # the FP32 floor: a chunk that does not lower the best residual by
+            # 30% hands over to the FP64 polish
+            stale = stale + 1 if r.final_resid > 0.7 * best else 0
             best = min(best, r.final_resid)
-            if stale >= 3:
+            if stale >= 1:
                 break
         out["optimize"] = {"mixed": {"iters": iters, "evals": evals, "final_resid": r.final_resid,
                                      "e_total": r.e.e_total,
