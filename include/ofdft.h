@@ -398,6 +398,45 @@ ofdft_status ofdft_profile_enable(ofdft_grid *grid, int32_t on);
 ofdft_status ofdft_profile_read(ofdft_grid *grid, int32_t pass, double *total_ms,
                                 int64_t *launches);
 
+/* Real-time TD-OFDFT (Section "Time-Dependent OFDFT"): the collective
+ * orbital psi, |psi|^2 = rho, obeys i d psi/dt = H psi with
+ * H = -(1/2) nabla^2 + v, v = the functional derivative of every term of the
+ * grid's functional except von Weizsaecker (dT_Pauli/drho + v_s of eq.
+ * "heq", evaluated at the current density; the functional must contain vW
+ * with lambda_vw = 1).  Each step solves the Crank-Nicolson system of eq.
+ * "cn" in the sign of the time-dependent equation,
+ * (1 + i dt/2 H) psi(t + dt) = (1 - i dt/2 H) psi(t), by BiCGSTAB from
+ * psi(t); H is first built from rho(t) (predictor), then n_corrector times
+ * from the midpoint density (rho(t) + |psi_trial|^2) / 2.  The state lives
+ * on the grid (about 23 N field values of device memory).
+ *
+ * ofdft_td_start: psi = sqrt(resident density) exp(-i k.r), the kick of
+ *   strength |k| (Bohr^-1); r = sum_d (i_d / N_d) a_d.
+ * ofdft_td_set_psi / ofdft_td_get_psi: psi as two host arrays of N doubles
+ *   (real and imaginary parts).
+ * ofdft_td_propagate: nsteps steps; dipole_out (may be NULL) receives
+ *   mu = int r |psi|^2 dr (3 doubles, Bohr) after each step, nsteps x 3;
+ *   stats the solver work, the largest final relative residual
+ *   |b - A x| / |b| and int |psi|^2 at the end.  solver_tol <= 0 selects
+ *   1e-11 (FP64) or 1e-6 (mixed), max_solver_iter <= 0 selects 200; a solve
+ *   that stops above its tolerance is counted, not an error. */
+typedef struct {
+    double dt;               /* a.u. of time; may be negative (backwards)       */
+    int32_t n_corrector;     /* 0 .. 16                                          */
+    int32_t max_solver_iter;
+    double solver_tol;
+} ofdft_td_params;
+typedef struct {
+    int32_t steps, solver_iters, unconverged_solves, reserved;
+    double max_solver_resid;
+    double nelec;
+} ofdft_td_stats;
+ofdft_status ofdft_td_start(ofdft_grid *grid, const double k[3]);
+ofdft_status ofdft_td_set_psi(ofdft_grid *grid, const double *re_host, const double *im_host);
+ofdft_status ofdft_td_get_psi(ofdft_grid *grid, double *re_host, double *im_host);
+ofdft_status ofdft_td_propagate(ofdft_grid *grid, const ofdft_td_params *params, int32_t nsteps,
+                                double *dipole_out, ofdft_td_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libofdft.so")
 SOURCES = ["k_row_fp32.hip", "k_row_fp64.hip", "k_col_fp32.hip", "k_col_fp64.hip",
            "k_rowc_fp32.hip", "k_rowc_fp64.hip", "k_plane_fp32.hip", "k_plane_fp64.hip", "k_misc.hip",
-           "k_ions.hip", "k_pme.hip", "api.cpp", "serve.cpp"]
+           "k_ions.hip", "k_pme.hip", "k_td.hip", "api.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("OFDFT_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

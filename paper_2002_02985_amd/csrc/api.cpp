@@ -10,6 +10,7 @@
 #include <mutex>
 #include <tuple>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -162,6 +163,10 @@ struct ofdft_grid {
     int sf_method = OFDFT_SF_DIRECT;            // structure factor of the ionic terms
     int pme_order = 0;                          // B-spline order of the PME spread
     double2 *d_pme_b = nullptr;                 // conjugated exponential-spline factors
+    // real-time TD-OFDFT state (ofdft_td_start): one block of split complex
+    // vectors, real fields and two half spectra, and the dipole partials
+    void *td = nullptr;
+    double *d_td_part = nullptr;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -1092,6 +1097,8 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
 static void grid_free(ofdft_grid *g)
 {
     graphs_clear(g);
+    dfree(g->td);
+    dfree(reinterpret_cast<void *&>(g->d_td_part));
     dfree(g->tw0);
     dfree(g->tw1);
     dfree(g->twM);
@@ -2105,6 +2112,249 @@ bool has_tuning(const ofdft_grid *g)
 
 }  // namespace ofdft_internal
 
+
+// ---------------------------------------------------------------- TD-OFDFT
+// Real-time propagation of the collective orbital (Section "Time-Dependent
+// OFDFT"): i d psi/dt = H psi with H = -(1/2) nabla^2 + v, v the functional
+// derivative of every term but von Weizsaecker (dT_Pauli/drho + v_s of eq.
+// "heq", adiabatic), Crank-Nicolson steps (eq. "cn", with the signs of the
+// time-dependent equation: (1 + i dt/2 H) psi(t+dt) = (1 - i dt/2 H) psi(t))
+// solved by BiCGSTAB, and corrector passes that rebuild H from the midpoint
+// density (rho(t) + |psi_trial|^2) / 2.
+enum { TV_PSI = 0, TV_TRIAL, TV_B, TV_R, TV_RH, TV_P, TV_V, TV_S, TV_T, TV_KIN, NTV };
+struct TdBufs {
+    void *vec[NTV];          // split complex vectors, 2N values each
+    void *rho_n, *rho, *veff;  // real fields, N values each
+    void *spec;              // two half spectra, 2 Nh complex
+};
+static uint64_t td_bytes(const Geom &G, size_t fsz)
+{
+    return ((uint64_t)NTV * 2 * G.N + 3 * (uint64_t)G.N + 4 * (uint64_t)G.Nh) * fsz;
+}
+static TdBufs td_bufs(ofdft_grid *g)
+{
+    const Geom &G = g->geom;
+    char *p = static_cast<char *>(g->td);
+    TdBufs b;
+    for (int k = 0; k < NTV; ++k) {
+        b.vec[k] = p;
+        p += 2 * (size_t)G.N * g->fsz;
+    }
+    b.rho_n = p;
+    p += (size_t)G.N * g->fsz;
+    b.rho = p;
+    p += (size_t)G.N * g->fsz;
+    b.veff = p;
+    p += (size_t)G.N * g->fsz;
+    b.spec = p;
+    return b;
+}
+static const void *im_part(const ofdft_grid *g, const void *x)
+{
+    return static_cast<const char *>(x) + (size_t)g->geom.N * g->fsz;
+}
+
+// complex dot products <a, b> = sum conj(a) b over the split vectors
+template <typename T>
+static ofdft_status td_cdot(ofdft_grid *g, hipStream_t s, const void *a, const void *b,
+                            std::complex<double> *out)
+{
+    int nbk = 0;
+    const void *ai = im_part(g, a), *bi = im_part(g, b);
+    HIP_TRY(launch_dots<T>(g->geom.N, 4, a, b, ai, bi, a, bi, ai, b, g->part, g->pstride, nbk, s));
+    SlotCounts cnt;
+    std::memset(&cnt, 0, sizeof(cnt));
+    for (int d = 0; d < 4; ++d) cnt.n[SL_AUX0 + d] = nbk;
+    HIP_TRY(launch_finalize(g->part, g->pstride, cnt, 1, g->sums, s));
+    HIP_TRY(hipMemcpyAsync(g->h_sums, g->sums, NSLOT * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double *h = g->h_sums + SL_AUX0;
+    *out = {h[0] + h[1], h[2] - h[3]};
+    return OFDFT_OK;
+}
+
+template <typename T>
+static hipError_t td_lin(ofdft_grid *g, hipStream_t s, void *z, std::complex<double> a,
+                         const void *x, std::complex<double> b = 0.0, const void *y = nullptr,
+                         std::complex<double> c = 0.0, const void *w = nullptr)
+{
+    const double ca[2] = {a.real(), a.imag()}, cb[2] = {b.real(), b.imag()},
+                 cc[2] = {c.real(), c.imag()};
+    return launch_td_zlincomb<T>(g->geom.N, z, ca, x, cb, y, cc, w, s);
+}
+
+// out = x + i tau H x with the potential in veff (tau = +-dt/2)
+template <typename T>
+static ofdft_status td_apply(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *x,
+                             void *out, double tau)
+{
+    const Geom &G = g->geom;
+    ST_TRY(fft_impl<T>(g, 2, x, B.spec, true, s));
+    const void *g2 = static_cast<const char *>(g->gtab) + (size_t)G.Nh * g->fsz;
+    HIP_TRY(launch_td_kinetic<T>(G, B.spec, g2, s));
+    ST_TRY(fft_impl<T>(g, 2, B.spec, B.vec[TV_KIN], false, s));
+    HIP_TRY(launch_td_apply<T>(G.N, x, B.vec[TV_KIN], B.veff, tau, out, s));
+    return OFDFT_OK;
+}
+
+// veff = v[rho] of every term but vW (the grid's functional otherwise)
+template <typename T>
+static ofdft_status td_potential(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *rho)
+{
+    const uint32_t terms = g->func.terms;
+    const bool graphs = g->use_graphs;
+    graphs_clear(g);
+    g->use_graphs = false;
+    g->func.terms = terms & ~(uint32_t)OFDFT_TERM_VW;
+    ofdft_energy e;
+    ofdft_status st = eval_dispatch(g, 1, rho, 0, B.veff, nullptr, s, &e);
+    g->func.terms = terms;
+    g->use_graphs = graphs;
+    return st;
+}
+
+// (1 + i tau H) x = b by BiCGSTAB from the guess in x
+template <typename T>
+static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, double tau,
+                             const void *b, void *x, int maxit, double tol, int *iters,
+                             double *relres)
+{
+    using cplx = std::complex<double>;
+    void *r = B.vec[TV_R], *rh = B.vec[TV_RH], *p = B.vec[TV_P], *v = B.vec[TV_V],
+         *sv = B.vec[TV_S], *t = B.vec[TV_T];
+    ST_TRY(td_apply<T>(g, B, s, x, t, tau));
+    HIP_TRY(td_lin<T>(g, s, r, 1.0, b, -1.0, t));
+    HIP_TRY(td_lin<T>(g, s, rh, 1.0, r));
+    HIP_TRY(hipMemsetAsync(p, 0, 2 * (size_t)g->geom.N * g->fsz, s));
+    HIP_TRY(hipMemsetAsync(v, 0, 2 * (size_t)g->geom.N * g->fsz, s));
+    cplx bb, rr;
+    ST_TRY(td_cdot<T>(g, s, b, b, &bb));
+    ST_TRY(td_cdot<T>(g, s, r, r, &rr));
+    const double bnorm = std::sqrt(std::max(bb.real(), 1e-300));
+    double res = std::sqrt(std::max(rr.real(), 0.0)) / bnorm;
+    cplx rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    int it = 0;
+    while (res > tol && it < maxit) {
+        ++it;
+        cplx rho;
+        ST_TRY(td_cdot<T>(g, s, rh, r, &rho));
+        if (std::abs(rho) == 0.0) break;
+        const cplx beta = (rho / rho_prev) * (alpha / omega);
+        HIP_TRY(td_lin<T>(g, s, p, 1.0, r, beta, p, -beta * omega, v));
+        ST_TRY(td_apply<T>(g, B, s, p, v, tau));
+        cplx rv;
+        ST_TRY(td_cdot<T>(g, s, rh, v, &rv));
+        if (std::abs(rv) == 0.0) break;
+        alpha = rho / rv;
+        HIP_TRY(td_lin<T>(g, s, sv, 1.0, r, -alpha, v));
+        cplx ss;
+        ST_TRY(td_cdot<T>(g, s, sv, sv, &ss));
+        if (std::sqrt(std::max(ss.real(), 0.0)) / bnorm <= tol) {
+            HIP_TRY(td_lin<T>(g, s, x, 1.0, x, alpha, p));
+            res = std::sqrt(std::max(ss.real(), 0.0)) / bnorm;
+            break;
+        }
+        ST_TRY(td_apply<T>(g, B, s, sv, t, tau));
+        cplx ts, tt;
+        ST_TRY(td_cdot<T>(g, s, t, sv, &ts));
+        ST_TRY(td_cdot<T>(g, s, t, t, &tt));
+        omega = tt.real() > 0.0 ? ts / tt.real() : cplx(0.0);
+        HIP_TRY(td_lin<T>(g, s, x, 1.0, x, alpha, p, omega, sv));
+        HIP_TRY(td_lin<T>(g, s, r, 1.0, sv, -omega, t));
+        ST_TRY(td_cdot<T>(g, s, r, r, &rr));
+        res = std::sqrt(std::max(rr.real(), 0.0)) / bnorm;
+        if (std::abs(omega) == 0.0) break;
+        rho_prev = rho;
+    }
+    *iters = it;
+    *relres = res;
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status td_dipole(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *rho,
+                              double mu[3])
+{
+    TdLattice L;
+    for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) L.a[3 * i + c] = g->lattice[i][c];
+    const int nb = td_dipole_blocks(g->geom);
+    HIP_TRY(launch_td_dipole<T>(g->geom, L, rho, g->d_td_part, s));
+    std::vector<double> h(3 * (size_t)nb);
+    HIP_TRY(hipMemcpyAsync(h.data(), g->d_td_part, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < nb; ++k) acc += h[3 * (size_t)k + c];
+        mu[c] = acc * g->dv;
+    }
+    return OFDFT_OK;
+}
+
+static ofdft_status td_alloc(ofdft_grid *g)
+{
+    ST_TRY(reserve(g, 2));
+    ST_TRY(dmalloc(g, &g->td, td_bytes(g->geom, g->fsz)));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_td_part),
+                   3 * (size_t)td_dipole_blocks(g->geom) * sizeof(double)));
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status td_start_impl(ofdft_grid *g, const double k[3])
+{
+    hipStream_t s = g->ctx->stream;
+    ST_TRY(td_alloc(g));
+    const TdBufs B = td_bufs(g);
+    TdLattice L;
+    for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) L.a[3 * i + c] = g->lattice[i][c];
+    HIP_TRY(launch_td_kick<T>(g->geom, L, k, g->rho, B.vec[TV_PSI], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return OFDFT_OK;
+}
+
+template <typename T>
+static ofdft_status td_propagate_impl(ofdft_grid *g, const ofdft_td_params *prm, int nsteps,
+                                      double *mu_out, ofdft_td_stats *st)
+{
+    hipStream_t s = g->ctx->stream;
+    const TdBufs B = td_bufs(g);
+    const Geom &G = g->geom;
+    const double tau = 0.5 * prm->dt;
+    const double tol = prm->solver_tol > 0 ? prm->solver_tol : (g->fp64 ? 1e-11 : 1e-6);
+    const int maxit = prm->max_solver_iter > 0 ? prm->max_solver_iter : 200;
+    std::memset(st, 0, sizeof(*st));
+    for (int n = 0; n < nsteps; ++n) {
+        void *psi = B.vec[TV_PSI], *trial = B.vec[TV_TRIAL], *b = B.vec[TV_B];
+        HIP_TRY(launch_td_density<T>(G.N, psi, 1.0, nullptr, 0.0, B.rho_n, s));
+        const void *rho_h = B.rho_n;
+        for (int c = 0; c <= prm->n_corrector; ++c) {
+            if (c > 0) {
+                HIP_TRY(launch_td_density<T>(G.N, psi, 0.5, trial, 0.5, B.rho, s));
+                rho_h = B.rho;
+            }
+            ST_TRY(td_potential<T>(g, B, s, rho_h));
+            ST_TRY(td_apply<T>(g, B, s, psi, b, -tau));                  // (1 - i tau H) psi
+            if (c == 0) HIP_TRY(td_lin<T>(g, s, trial, 1.0, psi));       // guess: psi(t)
+            int it = 0;
+            double res = 0.0;
+            ST_TRY(td_solve<T>(g, B, s, tau, b, trial, maxit, tol, &it, &res));
+            st->solver_iters += it;
+            st->max_solver_resid = std::max(st->max_solver_resid, res);
+            if (res > tol) st->unconverged_solves++;
+        }
+        HIP_TRY(td_lin<T>(g, s, psi, 1.0, trial));
+        HIP_TRY(launch_td_density<T>(G.N, psi, 1.0, nullptr, 0.0, B.rho, s));
+        if (mu_out) ST_TRY(td_dipole<T>(g, B, s, B.rho, mu_out + 3 * (size_t)n));
+        st->steps++;
+    }
+    std::complex<double> nn;
+    ST_TRY(td_cdot<T>(g, s, B.vec[TV_PSI], B.vec[TV_PSI], &nn));
+    st->nelec = nn.real() * g->dv;
+    return OFDFT_OK;
+}
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -2198,6 +2448,9 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
                              (uint64_t)grid->cap,
                              ion_bytes(grid->lattice, grid->natoms, grid->sf_method, grid->geom), m);
     if (m.stage && !(grid->stage_in && grid->stage_out)) b -= (uint64_t)grid->geom.N * grid->fsz;
+    if (grid->td)
+        b += td_bytes(grid->geom, grid->fsz) +
+             3 * (uint64_t)td_dipole_blocks(grid->geom) * sizeof(double);
     return b;
 }
 
@@ -2340,6 +2593,61 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
         for (int k = 0; k < 3; ++k) f_out_host[3 * orig + k] = fs[3 * a + k] + fe[3 * orig + k];
     }
     return OFDFT_OK;
+}
+
+
+ofdft_status ofdft_td_start(ofdft_grid *grid, const double k[3])
+{
+    if (!grid || !k) return fail(OFDFT_EINVAL, "null argument");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(k[c])) return fail(OFDFT_EINVAL, "non-finite kick");
+    if (!(grid->func.terms & OFDFT_TERM_VW) || grid->func.lambda_vw != 1.0)
+        return fail(OFDFT_EINVAL, "TD-OFDFT needs the von Weizsaecker term with lambda = 1 "
+                                  "(the Laplacian of the Hamiltonian)");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return grid->fp64 ? td_start_impl<double>(grid, k) : td_start_impl<float>(grid, k);
+}
+
+ofdft_status ofdft_td_propagate(ofdft_grid *grid, const ofdft_td_params *params, int32_t nsteps,
+                                double *dipole_out, ofdft_td_stats *stats)
+{
+    if (!grid || !params || !stats || nsteps < 0) return fail(OFDFT_EINVAL, "bad argument");
+    if (!grid->td) return fail(OFDFT_EINVAL, "no TD state: call ofdft_td_start first");
+    if (!std::isfinite(params->dt) || params->dt == 0.0 || params->n_corrector < 0 ||
+        params->n_corrector > 16 || params->max_solver_iter < 0 || !(params->solver_tol >= 0))
+        return fail(OFDFT_EINVAL, "bad TD parameters");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    return grid->fp64 ? td_propagate_impl<double>(grid, params, nsteps, dipole_out, stats)
+                      : td_propagate_impl<float>(grid, params, nsteps, dipole_out, stats);
+}
+
+ofdft_status ofdft_td_get_psi(ofdft_grid *grid, double *re_host, double *im_host)
+{
+    if (!grid || !re_host || !im_host) return fail(OFDFT_EINVAL, "null argument");
+    if (!grid->td) return fail(OFDFT_EINVAL, "no TD state: call ofdft_td_start first");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    const size_t N = (size_t)grid->geom.N;
+    const TdBufs B = td_bufs(grid);
+    hipStream_t s = grid->ctx->stream;
+    ST_TRY(download_field(grid, re_host, B.vec[TV_PSI], N, s));
+    return download_field(grid, im_host, im_part(grid, B.vec[TV_PSI]), N, s);
+}
+
+ofdft_status ofdft_td_set_psi(ofdft_grid *grid, const double *re_host, const double *im_host)
+{
+    if (!grid || !re_host || !im_host) return fail(OFDFT_EINVAL, "null argument");
+    const size_t N = (size_t)grid->geom.N;
+    for (size_t i = 0; i < N; ++i)
+        if (!std::isfinite(re_host[i]) || !std::isfinite(im_host[i]))
+            return fail(OFDFT_EINVAL, "non-finite psi");
+    if (!(grid->func.terms & OFDFT_TERM_VW) || grid->func.lambda_vw != 1.0)
+        return fail(OFDFT_EINVAL, "TD-OFDFT needs the von Weizsaecker term with lambda = 1");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    ST_TRY(td_alloc(grid));
+    const TdBufs B = td_bufs(grid);
+    hipStream_t s = grid->ctx->stream;
+    ST_TRY(upload_field(grid, B.vec[TV_PSI], re_host, N, s));
+    return upload_field(grid, const_cast<void *>(im_part(grid, B.vec[TV_PSI])), im_host, N, s);
 }
 
 ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, ofdft_opt_result *result)

@@ -1,0 +1,218 @@
+// Real-time TD-OFDFT (Section "Time-Dependent OFDFT"): pointwise kernels of
+// the Crank-Nicolson propagation of the collective orbital psi.  Complex
+// vectors are stored split, the N real parts followed by the N imaginary
+// parts, so that the pair goes through the real-to-complex transforms as a
+// batch of two fields.
+#include "kernels_impl.hpp"
+
+namespace ofdft {
+
+namespace {
+constexpr int TD_BLOCKS = 2048;     // grid-stride launches
+}
+
+// rho = wa |a|^2 + wb |b|^2 (b may be null)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_density(long long n, const T *a, double wa, const T *b,
+                                                   double wb, T *rho)
+{
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT) {
+        const double ar = a[i], ai = a[n + i];
+        double r = wa * (ar * ar + ai * ai);
+        if (b) {
+            const double br = b[i], bi = b[n + i];
+            r += wb * (br * br + bi * bi);
+        }
+        rho[i] = T(r);
+    }
+}
+
+// Cartesian position of grid point (i0, i1, i2): sum_d (i_d / n_d) a_d
+__device__ __forceinline__ void td_position(const Geom &g, const double *lat, long long i,
+                                            double (&r)[3])
+{
+    const int i2 = (int)(i % g.n2);
+    const long long q = i / g.n2;
+    const int i1 = (int)(q % g.n1), i0 = (int)(q / g.n1);
+    const double f0 = (double)i0 / g.n0, f1 = (double)i1 / g.n1, f2 = (double)i2 / g.n2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = f0 * lat[c] + f1 * lat[3 + c] + f2 * lat[6 + c];
+}
+
+// per-block partial sums of rho x, rho y, rho z (part[3 * block + c])
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_dipole(Geom g, TdLattice L, const T *rho, double *part)
+{
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * NT + tid; i < g.N;
+         i += (long long)gridDim.x * NT) {
+        double r[3];
+        td_position(g, L.a, i, r);
+        const double w = (double)rho[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] += r[c] * w;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double s = block_sum<NT>(acc[c], red, tid);
+        if (tid == 0) part[3 * blockIdx.x + c] = s;
+    }
+}
+
+// psi = sqrt(rho) exp(-i k.r)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_kick(Geom g, TdLattice L, double k0, double k1,
+                                                double k2, const T *rho, T *psi)
+{
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * NT) {
+        double r[3];
+        td_position(g, L.a, i, r);
+        const double ph = k0 * r[0] + k1 * r[1] + k2 * r[2];
+        double sn, cs;
+        sincos(ph, &sn, &cs);
+        const double a = sqrt(fmax((double)rho[i], 0.0));
+        psi[i] = T(a * cs);
+        psi[g.N + i] = T(-a * sn);
+    }
+}
+
+// the kinetic operator on the two half spectra: X *= G^2 / 2
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_kinetic(long long nh, cpx<T> *spec, const T *g2)
+{
+    for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < nh;
+         e += (long long)gridDim.x * NT) {
+        const T h = T(0.5) * g2[e];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            cpx<T> x = spec[f * nh + e];
+            x.x *= h;
+            x.y *= h;
+            spec[f * nh + e] = x;
+        }
+    }
+}
+
+// out = x + sgn i tau (Tx + v x), Tx the kinetic part already applied
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_apply(long long n, const T *x, const T *tx, const T *v,
+                                                 double tau, T *out)
+{
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT) {
+        const double xr = x[i], xi = x[n + i], vv = v[i];
+        const double hr = (double)tx[i] + vv * xr, hi = (double)tx[n + i] + vv * xi;
+        out[i] = T(xr - tau * hi);
+        out[n + i] = T(xi + tau * hr);
+    }
+}
+
+// z = a x + b y + c w with complex coefficients (y, w may be null; z may
+// alias any of them: each element is read before it is written)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_zlincomb(long long n, T *z, double ar, double ai,
+                                                    const T *x, double br, double bi, const T *y,
+                                                    double cr, double ci, const T *w)
+{
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT) {
+        const double xr = x[i], xi = x[n + i];
+        double zr = ar * xr - ai * xi, zi = ar * xi + ai * xr;
+        if (y) {
+            const double yr = y[i], yi = y[n + i];
+            zr += br * yr - bi * yi;
+            zi += br * yi + bi * yr;
+        }
+        if (w) {
+            const double wr = w[i], wi = w[n + i];
+            zr += cr * wr - ci * wi;
+            zi += cr * wi + ci * wr;
+        }
+        z[i] = T(zr);
+        z[n + i] = T(zi);
+    }
+}
+
+static unsigned td_grid(long long n)
+{
+    const long long nb = (n + NT - 1) / NT;
+    return (unsigned)(nb < TD_BLOCKS ? nb : TD_BLOCKS);
+}
+
+int td_dipole_blocks(const Geom &g) { return (int)td_grid(g.N); }
+
+template <typename T>
+hipError_t launch_td_density(long long n, const void *a, double wa, const void *b, double wb,
+                             void *rho, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_density<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (const T *)a, wa,
+                       (const T *)b, wb, (T *)rho);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_dipole(const Geom &g, const TdLattice &L, const void *rho, double *part,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_dipole<T>), dim3(td_grid(g.N)), dim3(NT), 0, s, g, L,
+                       (const T *)rho, part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_kick(const Geom &g, const TdLattice &L, const double k[3], const void *rho,
+                          void *psi, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_kick<T>), dim3(td_grid(g.N)), dim3(NT), 0, s, g, L, k[0], k[1], k[2],
+                       (const T *)rho, (T *)psi);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_kinetic(const Geom &g, void *spec, const void *g2, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_kinetic<T>), dim3(td_grid(g.Nh)), dim3(NT), 0, s, g.Nh,
+                       (cpx<T> *)spec, (const T *)g2);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_apply(long long n, const void *x, const void *tx, const void *v, double tau,
+                           void *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_apply<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (const T *)x,
+                       (const T *)tx, (const T *)v, tau, (T *)out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_zlincomb(long long n, void *z, const double a[2], const void *x,
+                              const double b[2], const void *y, const double c[2], const void *w,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_zlincomb<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (T *)z, a[0], a[1],
+                       (const T *)x, b[0], b[1], (const T *)y, c[0], c[1], (const T *)w);
+    return hipGetLastError();
+}
+
+#define OFDFT_TD_INSTANTIATE(T)                                                                   \
+    template hipError_t launch_td_density<T>(long long, const void *, double, const void *,      \
+                                             double, void *, hipStream_t);                        \
+    template hipError_t launch_td_dipole<T>(const Geom &, const TdLattice &, const void *,        \
+                                            double *, hipStream_t);                               \
+    template hipError_t launch_td_kick<T>(const Geom &, const TdLattice &, const double *,        \
+                                          const void *, void *, hipStream_t);                     \
+    template hipError_t launch_td_kinetic<T>(const Geom &, void *, const void *, hipStream_t);    \
+    template hipError_t launch_td_apply<T>(long long, const void *, const void *, const void *,   \
+                                           double, void *, hipStream_t);                          \
+    template hipError_t launch_td_zlincomb<T>(long long, void *, const double *, const void *,    \
+                                              const double *, const void *, const double *,       \
+                                              const void *, hipStream_t);
+OFDFT_TD_INSTANTIATE(float)
+OFDFT_TD_INSTANTIATE(double)
+
+}  // namespace ofdft

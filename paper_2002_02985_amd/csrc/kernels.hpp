@@ -281,6 +281,37 @@ hipError_t launch_pme_finish(const Geom &g, const void *F, const double2 *bt, do
                              double volume, double ew_a, double ew_gcut2, int first, int last,
                              void *vext, void *qbuf, double *ew_part, hipStream_t s);
 
+// Real-time TD-OFDFT.  Complex vectors are split: n real parts, then n
+// imaginary parts.  lattice vectors a_d as rows (9 doubles)
+struct TdLattice {
+    double a[9];
+};
+int td_dipole_blocks(const Geom &g);
+// rho = wa |a|^2 + wb |b|^2 (b may be null)
+template <typename T>
+hipError_t launch_td_density(long long n, const void *a, double wa, const void *b, double wb,
+                             void *rho, hipStream_t s);
+// part[3 * block + c]: per-block sums of r_c rho (td_dipole_blocks blocks)
+template <typename T>
+hipError_t launch_td_dipole(const Geom &g, const TdLattice &L, const void *rho, double *part,
+                            hipStream_t s);
+// psi = sqrt(rho) exp(-i k.r)
+template <typename T>
+hipError_t launch_td_kick(const Geom &g, const TdLattice &L, const double k[3], const void *rho,
+                          void *psi, hipStream_t s);
+// two half spectra (2 x Nh complex) times G^2 / 2; g2: the grid's G^2 table
+template <typename T>
+hipError_t launch_td_kinetic(const Geom &g, void *spec, const void *g2, hipStream_t s);
+// out = x + i tau (tx + v x)
+template <typename T>
+hipError_t launch_td_apply(long long n, const void *x, const void *tx, const void *v, double tau,
+                           void *out, hipStream_t s);
+// z = a x + b y + c w, complex coefficients {re, im}; y, w may be null
+template <typename T>
+hipError_t launch_td_zlincomb(long long n, void *z, const double a[2], const void *x,
+                              const double b[2], const void *y, const double c[2], const void *w,
+                              hipStream_t s);
+
 // vector kernels (optimizer): up to 4 dot products into part slots
 template <typename T>
 hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,

@@ -64,6 +64,17 @@ class OptResult(ctypes.Structure):
                 ("final_resid", ctypes.c_double)]
 
 
+class TdParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("n_corrector", ctypes.c_int32),
+                ("max_solver_iter", ctypes.c_int32), ("solver_tol", ctypes.c_double)]
+
+
+class TdStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("solver_iters", ctypes.c_int32),
+                ("unconverged_solves", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_solver_resid", ctypes.c_double), ("nelec", ctypes.c_double)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("cell_id", ctypes.c_uint64), ("kind", ctypes.c_int32),
                 ("cell", ctypes.POINTER(CellDesc)), ("func", ctypes.POINTER(FunctionalDesc)),
@@ -133,6 +144,14 @@ _SIGS = {
     "ofdft_grid_set_graphs": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_interpolate_density": (ctypes.c_int, [_P, _P]),
     "ofdft_optimize_multistep": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P, _P]),
+    "ofdft_td_start": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "ofdft_td_set_psi": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "ofdft_td_get_psi": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "ofdft_td_propagate": (ctypes.c_int, [_P, ctypes.POINTER(TdParams), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(TdStats)]),
     "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
     "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
@@ -327,6 +346,36 @@ def ofdft_optimize_multistep(grids, params, allow_noconv=False):
     if not (st == OK or (allow_noconv and st == ENOCONV)):
         check(st)
     return list(rs), st
+
+
+def ofdft_td_start(grid, k):
+    """psi = sqrt(resident density) exp(-i k.r) (the kick)."""
+    kk = (ctypes.c_double * 3)(*[float(x) for x in k])
+    check(load().ofdft_td_start(grid, kk))
+
+
+def ofdft_td_set_psi(grid, psi):
+    re = np.ascontiguousarray(np.real(psi), dtype=np.float64).reshape(-1)
+    im = np.ascontiguousarray(np.imag(psi), dtype=np.float64).reshape(-1)
+    check(load().ofdft_td_set_psi(grid, _dptr(re), _dptr(im)))
+
+
+def ofdft_td_get_psi(grid, shape):
+    n = int(np.prod(shape))
+    re = np.empty(n)
+    im = np.empty(n)
+    check(load().ofdft_td_get_psi(grid, _dptr(re), _dptr(im)))
+    return (re + 1j * im).reshape(shape)
+
+
+def ofdft_td_propagate(grid, dt, nsteps, n_corrector=1, solver_tol=0.0, max_solver_iter=0):
+    """Returns (dipoles nsteps x 3, TdStats)."""
+    p = TdParams(float(dt), int(n_corrector), int(max_solver_iter), float(solver_tol))
+    mu = np.zeros((max(int(nsteps), 1), 3))
+    st = TdStats()
+    check(load().ofdft_td_propagate(grid, ctypes.byref(p), int(nsteps), _dptr(mu),
+                                    ctypes.byref(st)))
+    return mu[:int(nsteps)], st
 
 
 def ofdft_validate(cell_desc, func_desc):

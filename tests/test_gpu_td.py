@@ -1,0 +1,140 @@
+"""GPU parity of real-time TD-OFDFT (Section "Time-Dependent OFDFT",
+eqs. "heq" and "cn") against the oracle's propagator (``oracle.tdofdft``,
+which solves each Crank-Nicolson system exactly), through the C ABI.
+
+Tolerances: FP64 psi within 1e-9 of max |psi| and the dipole within 1e-9
+Bohr after each step (the device solves to a relative residual of 1e-13);
+mixed psi within 1e-4 of max |psi|, the dipole within 1e-4 Bohr (FP32
+fields, solver tolerance 1e-6)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import cell as OC
+from oracle import functionals as OF
+from oracle import tdofdft as TD
+from paper_2002_02985_amd import ofdft
+from tests.oracle_helpers import make_cell
+
+pytestmark = pytest.mark.gpu
+
+LOCAL = ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT
+
+
+def gaussian_case(n=(12, 12, 12), L=(11.0, 11.5, 12.0), sigma=1.1, Z=2.0):
+    L = np.array(L)
+    pos = np.array([L / 2 + np.array([0.3, -0.2, 0.1])])
+    cell = {"lattice": np.diag(L), "n": n, "pos": pos, "species": np.zeros(1, np.int32),
+            "Z": np.array([Z]), "rc": np.array([1.0]), "nelec": Z}
+    oc = make_cell(cell)
+    r = TD.positions(oc) - L / 2
+    rho = np.exp(-np.einsum("...d,...d->...", r, r) / (2 * sigma ** 2)) + 1e-10
+    return cell, oc, rho * Z / (rho.sum() * oc.dv)
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+@pytest.mark.parametrize("ncorr", [0, 1])
+def test_td_matches_the_oracle(prec, ncorr):
+    cell, oc, rho = gaussian_case()
+    k = [0.05, -0.02, 0.03]
+    dt, nsteps = 0.1, 3
+    psi_o, mu_o = TD.propagate(oc, OC.Functional(terms=int(LOCAL)), TD.kick(oc, rho, k), dt,
+                               nsteps, ncorr)
+    tol = 1e-13 if prec == ofdft.FP64 else 1e-6
+    with ofdft.Grid(cell, LOCAL, precision=prec) as g:
+        g.set_density(rho)
+        ofdft.ofdft_td_start(g.handle, k)
+        mu, st = ofdft.ofdft_td_propagate(g.handle, dt, nsteps, n_corrector=ncorr,
+                                          solver_tol=tol)
+        psi = ofdft.ofdft_td_get_psi(g.handle, oc.n)
+    dpsi = float(np.abs(psi - psi_o).max())
+    print("prec %d ncorr %d: dpsi %.3e dmu %.3e iters %d resid %.2e nelec %.12f" % (
+        prec, ncorr, dpsi, float(np.abs(mu - mu_o).max()), st.solver_iters,
+        st.max_solver_resid, st.nelec), flush=True)
+    scale = float(np.abs(psi_o).max())
+    if prec == ofdft.FP64:
+        assert dpsi <= 1e-9 * scale
+        np.testing.assert_allclose(mu, mu_o, rtol=0, atol=1e-9)
+        assert abs(st.nelec - cell["nelec"]) <= 1e-10 * cell["nelec"]
+        assert st.unconverged_solves == 0
+    else:
+        assert dpsi <= 1e-4 * scale
+        np.testing.assert_allclose(mu, mu_o, rtol=0, atol=1e-4)
+        assert abs(st.nelec - cell["nelec"]) <= 1e-5 * cell["nelec"]
+    assert st.steps == nsteps
+
+
+def test_td_plane_wave_phase():
+    """A plane wave on a uniform density: each step multiplies psi by
+    (1 - i E dt/2)/(1 + i E dt/2), E = |G|^2/2 + (5/3) C_TF rho0^(2/3)."""
+    L = np.array([8.0, 9.0, 10.0])
+    n = (8, 12, 12)
+    cell = {"lattice": np.diag(L), "n": n, "pos": np.zeros((0, 3)),
+            "species": np.zeros(0, np.int32), "Z": np.array([2.0]), "rc": np.array([1.0]),
+            "nelec": 4.0}
+    oc = make_cell(cell)
+    rho0 = 4.0 / np.prod(L)
+    G1 = oc.recip[0] + 2 * oc.recip[2]
+    psi0 = np.sqrt(rho0) * np.exp(1j * (TD.positions(oc) @ G1))
+    E = 0.5 * G1 @ G1 + 5.0 / 3.0 * OF.C_TF * rho0 ** (2.0 / 3.0)
+    dt = 0.07
+    with ofdft.Grid(cell, ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE,
+                    precision=ofdft.FP64) as g:
+        ofdft.ofdft_td_set_psi(g.handle, psi0)
+        mu, st = ofdft.ofdft_td_propagate(g.handle, dt, 3, n_corrector=1, solver_tol=1e-14)
+        psi = ofdft.ofdft_td_get_psi(g.handle, n)
+    f = (1 - 0.5j * E * dt) / (1 + 0.5j * E * dt)
+    assert float(np.abs(psi - psi0 * f ** 3).max()) <= 1e-11 * np.sqrt(rho0)
+
+
+def test_td_ground_state_is_stationary():
+    """The optimised density is an eigenstate of H (the Euler equation):
+    without a kick the density and dipole stay put."""
+    cell, oc, rho = gaussian_case(n=(24, 24, 24), sigma=1.3)
+    with ofdft.Grid(cell, LOCAL, precision=ofdft.FP64) as g:
+        g.set_density(rho)
+        r, st = g.optimize(tol=1e-9, max_iter=500, method=ofdft.OPT_PCG)
+        rho_gs = g.get_density()
+        mu0 = TD.dipole(oc, rho_gs)
+        ofdft.ofdft_td_start(g.handle, [0.0, 0.0, 0.0])
+        mu, tst = ofdft.ofdft_td_propagate(g.handle, 0.2, 10, n_corrector=1)
+        psi = ofdft.ofdft_td_get_psi(g.handle, oc.n)
+    drho = float(np.abs(np.abs(psi) ** 2 - rho_gs).max())
+    print("ground state: resid %.2e drho %.3e dmu %.3e" % (
+        r.final_resid, drho, float(np.abs(mu - mu0).max())), flush=True)
+    assert drho <= 1e-7 * float(rho_gs.max())
+    assert float(np.abs(mu - mu0).max()) <= 1e-7
+
+
+def test_td_kick_moves_the_dipole_at_minus_k_ne():
+    """Ehrenfest right after the kick: d mu/dt = -k N_e (Richardson over two
+    step sizes removes the O(dt) term)."""
+    cell, oc, rho = gaussian_case(sigma=1.0)
+    k = np.array([0.02, 0.0, -0.01])
+    mu0 = TD.dipole(oc, rho)
+    slopes = []
+    for dt in (0.02, 0.01):
+        with ofdft.Grid(cell, LOCAL, precision=ofdft.FP64) as g:
+            g.set_density(rho)
+            ofdft.ofdft_td_start(g.handle, k)
+            mu, _ = ofdft.ofdft_td_propagate(g.handle, dt, 1, n_corrector=1, solver_tol=1e-13)
+        slopes.append((mu[0] - mu0) / dt)
+    slope = 2 * slopes[1] - slopes[0]
+    np.testing.assert_allclose(slope, -k * cell["nelec"], rtol=0,
+                               atol=2e-3 * np.abs(k).max() * cell["nelec"])
+
+
+def test_td_refusals():
+    cell, oc, rho = gaussian_case()
+    with ofdft.Grid(cell, ofdft.TERM_TF | ofdft.TERM_HARTREE | ofdft.TERM_EXT) as g:
+        g.set_density(rho)
+        with pytest.raises(ofdft.OfdftError):
+            ofdft.ofdft_td_start(g.handle, [0.1, 0.0, 0.0])
+    with ofdft.Grid(cell, LOCAL) as g:
+        g.set_density(rho)
+        with pytest.raises(ofdft.OfdftError):
+            ofdft.ofdft_td_propagate(g.handle, 0.1, 1)      # no TD state yet
+        ofdft.ofdft_td_start(g.handle, [0.1, 0.0, 0.0])
+        with pytest.raises(ofdft.OfdftError):
+            ofdft.ofdft_td_propagate(g.handle, 0.0, 1)      # dt = 0
