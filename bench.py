@@ -160,6 +160,13 @@ def parse():
     ap.add_argument("--c5-pme-order", type=int, default=10)
     ap.add_argument("--opt-methods", action="store_true",
                     help="optimise the 108-atom cell with CG, preconditioned CG and truncated Newton")
+    ap.add_argument("--td", action="store_true",
+                    help="real-time TD-OFDFT instead: Mg cluster ground state, kick, "
+                         "Crank-Nicolson propagation, dipole spectrum")
+    ap.add_argument("--td-atoms", type=int, default=50)
+    ap.add_argument("--td-steps", type=int, default=2000)
+    ap.add_argument("--td-dt", type=float, default=0.1)
+    ap.add_argument("--td-mixed", action="store_true")
     ap.add_argument("--multistep", action="store_true",
                     help="multi-step (coarse then fine grid) cluster optimisation vs a fine start")
     ap.add_argument("--ms-atoms", type=int, default=561)
@@ -604,6 +611,84 @@ def c5_main(args):
     print(json.dumps(out), flush=True)
 
 
+def td_main(args):
+    """Real-time TD-OFDFT of an Mg cluster (Section "Time-Dependent OFDFT"):
+    TF + vW + Hartree + local pseudopotential + LDA ground state, the kick
+    exp(-i k x), Crank-Nicolson steps with one corrector, the dipole after
+    every step and the oscillator strength sigma(w) = w Im[dmu(w)] / k."""
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
+             ofdft.TERM_XC)
+    cell = dict(W.cluster(args.td_atoms, "Mg", seed=3))
+    n = tuple(cell["n"])
+    prec = ofdft.MIXED if args.td_mixed else ofdft.FP64
+    kick = 1e-3
+    dt, nsteps = args.td_dt, args.td_steps
+    out = {"metric": "TD-OFDFT propagation: Crank-Nicolson steps per second", "unit": "steps/s",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if args.td_mixed else "f64",
+           "data": "synthetic",
+           "config": {"workload": "Mg%d cluster (hcp sites, 8 Bohr vacuum, L = %.2f Bohr), %s "
+                                  "grid, TF+vW+Hartree+local pseudopotential+LDA, kick k = %g "
+                                  "along x, dt = %g a.u., one corrector" % (
+                                      args.td_atoms, float(cell["lattice"][0][0]),
+                                      "x".join(str(x) for x in n), kick, dt),
+                      "natoms": args.td_atoms, "grid": list(n), "dt": dt, "steps": nsteps}}
+    with ofdft.Grid(cell, terms, precision=prec) as g:
+        g.set_density(W.gaussian_density(cell, sigma=1.5, floor=1e-12))
+        t0 = time.perf_counter()
+        r, st = g.optimize(tol=1e-7 if prec == ofdft.FP64 else 1e-5, max_iter=3000,
+                           method=ofdft.OPT_PCG, allow_noconv=True)
+        out["ground_state"] = {"iters": r.iters, "final_resid": r.final_resid,
+                               "e_total": r.e.e_total, "wall_s": round(time.perf_counter() - t0, 2)}
+        log("ground state: %d iterations, resid %.2e" % (r.iters, r.final_resid))
+        rho0 = g.get_density()
+        ofdft.ofdft_td_start(g.handle, [kick, 0.0, 0.0])
+        mu_w, _ = ofdft.ofdft_td_propagate(g.handle, dt, 2, n_corrector=1)
+        ofdft.ofdft_td_start(g.handle, [kick, 0.0, 0.0])
+        torch.cuda.synchronize()
+        mus, its = [], 0
+        t0 = time.perf_counter()
+        chunk = 100
+        done = 0
+        while done < nsteps:
+            m = min(chunk, nsteps - done)
+            mu, tst = ofdft.ofdft_td_propagate(g.handle, dt, m, n_corrector=1)
+            mus.append(mu)
+            its += tst.solver_iters
+            done += m
+            log("%d steps, %.1f s, nelec %.10f, max solver resid %.1e" % (
+                done, time.perf_counter() - t0, tst.nelec, tst.max_solver_resid))
+        wall = time.perf_counter() - t0
+        mu = np.concatenate(mus)
+    # dipole of the ground state (the same sum as the device's, on the host)
+    L = np.asarray(cell["lattice"], dtype=np.float64)
+    fr = [np.arange(k) / k for k in n]
+    x = (fr[0][:, None, None] * L[0][0] + fr[1][None, :, None] * L[1][0] +
+         fr[2][None, None, :] * L[2][0])
+    dv = abs(np.linalg.det(L)) / np.prod(n)
+    mu0x = dv * float(np.sum(x * rho0))
+    dmu = mu[:, 0] - mu0x
+    t = dt * np.arange(1, nsteps + 1)
+    damp = np.exp(-t / (t[-1] / 4.0))
+    w = np.linspace(0.01, 0.5, 2000)                   # Ha
+    dmu_w = (np.exp(1j * np.outer(w, t)) * (dmu * damp)[None, :]).sum(axis=1) * dt
+    sigma = w * np.imag(dmu_w) / kick
+    ipk = int(np.argmax(np.abs(sigma)))
+    out.update({"value": round(nsteps / wall, 2), "ms_per_step": round(wall / nsteps * 1e3, 3),
+                "solver_iters_per_step": round(its / nsteps, 2),
+                "nelec_final": tst.nelec, "nelec_drift": tst.nelec - cell["nelec"],
+                "spectrum": {"peak_eV": round(w[ipk] * 27.211386, 3),
+                             "resolution_eV": round(2 * np.pi / t[-1] * 27.211386, 3)},
+                "dmu_x_first": [float(v) for v in dmu[:5]]})
+    print(json.dumps(out), flush=True)
+
+
 def multistep_main(args):
     """Multi-step optimisation of an Al cluster (Section "Density optimization
     strategies"): the density optimised on a grid of twice the spacing, Fourier
@@ -712,6 +797,12 @@ def main():
             print("bench.py: this build runs on one GPU", file=sys.stderr)
             sys.exit(2)
         opt_methods_main(args)
+        return
+    if args.td:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        td_main(args)
         return
     if args.multistep:
         if args.gpus != 1:

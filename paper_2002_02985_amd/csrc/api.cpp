@@ -973,7 +973,7 @@ static ofdft_status eval_dispatch(ofdft_grid *g, int nb, const void *d_in, int i
 // ---------------------------------------------------------------- FFT pair
 template <typename T>
 static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_out, bool fwd,
-                             hipStream_t s)
+                             hipStream_t s, bool sync = true)
 {
     ST_TRY(reserve(g, nb));
     const Geom &G = g->geom;
@@ -1021,8 +1021,10 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         if (plane) TIMED(PS_ROW_INV, launch_plane_inv<T>(G, ri, nbk, s));
         else TIMED(PS_ROW_INV, launch_row_inv<T>(G, ri, nbk, s));
     }
-    HIP_TRY(hipStreamSynchronize(s));
-    timer_collect(g);
+    if (sync) {
+        HIP_TRY(hipStreamSynchronize(s));
+        timer_collect(g);
+    }
     return OFDFT_OK;
 }
 
@@ -2183,17 +2185,40 @@ static hipError_t td_lin(ofdft_grid *g, hipStream_t s, void *z, std::complex<dou
     return launch_td_zlincomb<T>(g->geom.N, z, ca, x, cb, y, cc, w, s);
 }
 
+// out = c(G) x for a diagonal operator of the complex field (TD_KIN: the
+// kinetic operator; TD_K / TD_KINV: 1 + i tau G^2/2 and its inverse), through
+// the forward and inverse transforms of the two parts (no host wait)
+template <typename T>
+static ofdft_status td_kapply(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *x,
+                              void *out, double tau, int mode)
+{
+    const Geom &G = g->geom;
+    ST_TRY(fft_impl<T>(g, 2, x, B.spec, true, s, false));
+    const void *g2 = static_cast<const char *>(g->gtab) + (size_t)G.Nh * g->fsz;
+    HIP_TRY(launch_td_spectral<T>(G, B.spec, g2, tau, mode, s));
+    ST_TRY(fft_impl<T>(g, 2, B.spec, out, false, s, false));
+    return OFDFT_OK;
+}
+
 // out = x + i tau H x with the potential in veff (tau = +-dt/2)
 template <typename T>
 static ofdft_status td_apply(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *x,
                              void *out, double tau)
 {
-    const Geom &G = g->geom;
-    ST_TRY(fft_impl<T>(g, 2, x, B.spec, true, s));
-    const void *g2 = static_cast<const char *>(g->gtab) + (size_t)G.Nh * g->fsz;
-    HIP_TRY(launch_td_kinetic<T>(G, B.spec, g2, s));
-    ST_TRY(fft_impl<T>(g, 2, B.spec, B.vec[TV_KIN], false, s));
-    HIP_TRY(launch_td_apply<T>(G.N, x, B.vec[TV_KIN], B.veff, tau, out, s));
+    ST_TRY(td_kapply<T>(g, B, s, x, B.vec[TV_KIN], tau, TD_KIN));
+    HIP_TRY(launch_td_apply<T>(g->geom.N, x, B.vec[TV_KIN], B.veff, tau, out, s));
+    return OFDFT_OK;
+}
+
+// out = A K^-1 z = z + i tau veff (K^-1 z), K = 1 + i tau G^2/2: the system
+// matrix A = K + i tau veff right-preconditioned with its kinetic part (one
+// transform pair per product, as for A itself)
+template <typename T>
+static ofdft_status td_apply_pc(ofdft_grid *g, const TdBufs &B, hipStream_t s, const void *z,
+                                void *out, double tau)
+{
+    ST_TRY(td_kapply<T>(g, B, s, z, B.vec[TV_KIN], tau, TD_KINV));
+    HIP_TRY(launch_td_pc_apply<T>(g->geom.N, z, B.vec[TV_KIN], B.veff, tau, out, s));
     return OFDFT_OK;
 }
 
@@ -2213,7 +2238,10 @@ static ofdft_status td_potential(ofdft_grid *g, const TdBufs &B, hipStream_t s, 
     return st;
 }
 
-// (1 + i tau H) x = b by BiCGSTAB from the guess in x
+// (1 + i tau H) x = b by BiCGSTAB on A K^-1 y = b, x = K^-1 y (right
+// preconditioning with the kinetic part K = 1 + i tau G^2/2, exact in
+// reciprocal space): the residual b - A x is the unpreconditioned one, and
+// the iteration starts from the guess in x
 template <typename T>
 static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, double tau,
                              const void *b, void *x, int maxit, double tol, int *iters,
@@ -2222,7 +2250,9 @@ static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, doub
     using cplx = std::complex<double>;
     void *r = B.vec[TV_R], *rh = B.vec[TV_RH], *p = B.vec[TV_P], *v = B.vec[TV_V],
          *sv = B.vec[TV_S], *t = B.vec[TV_T];
-    ST_TRY(td_apply<T>(g, B, s, x, t, tau));
+    void *y = x;                                   // y = K x, in place
+    ST_TRY(td_kapply<T>(g, B, s, x, y, tau, TD_K));
+    ST_TRY(td_apply_pc<T>(g, B, s, y, t, tau));
     HIP_TRY(td_lin<T>(g, s, r, 1.0, b, -1.0, t));
     HIP_TRY(td_lin<T>(g, s, rh, 1.0, r));
     HIP_TRY(hipMemsetAsync(p, 0, 2 * (size_t)g->geom.N * g->fsz, s));
@@ -2241,7 +2271,7 @@ static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, doub
         if (std::abs(rho) == 0.0) break;
         const cplx beta = (rho / rho_prev) * (alpha / omega);
         HIP_TRY(td_lin<T>(g, s, p, 1.0, r, beta, p, -beta * omega, v));
-        ST_TRY(td_apply<T>(g, B, s, p, v, tau));
+        ST_TRY(td_apply_pc<T>(g, B, s, p, v, tau));
         cplx rv;
         ST_TRY(td_cdot<T>(g, s, rh, v, &rv));
         if (std::abs(rv) == 0.0) break;
@@ -2250,22 +2280,23 @@ static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, doub
         cplx ss;
         ST_TRY(td_cdot<T>(g, s, sv, sv, &ss));
         if (std::sqrt(std::max(ss.real(), 0.0)) / bnorm <= tol) {
-            HIP_TRY(td_lin<T>(g, s, x, 1.0, x, alpha, p));
+            HIP_TRY(td_lin<T>(g, s, y, 1.0, y, alpha, p));
             res = std::sqrt(std::max(ss.real(), 0.0)) / bnorm;
             break;
         }
-        ST_TRY(td_apply<T>(g, B, s, sv, t, tau));
+        ST_TRY(td_apply_pc<T>(g, B, s, sv, t, tau));
         cplx ts, tt;
         ST_TRY(td_cdot<T>(g, s, t, sv, &ts));
         ST_TRY(td_cdot<T>(g, s, t, t, &tt));
         omega = tt.real() > 0.0 ? ts / tt.real() : cplx(0.0);
-        HIP_TRY(td_lin<T>(g, s, x, 1.0, x, alpha, p, omega, sv));
+        HIP_TRY(td_lin<T>(g, s, y, 1.0, y, alpha, p, omega, sv));
         HIP_TRY(td_lin<T>(g, s, r, 1.0, sv, -omega, t));
         ST_TRY(td_cdot<T>(g, s, r, r, &rr));
         res = std::sqrt(std::max(rr.real(), 0.0)) / bnorm;
         if (std::abs(omega) == 0.0) break;
         rho_prev = rho;
     }
+    ST_TRY(td_kapply<T>(g, B, s, y, x, tau, TD_KINV));   // x = K^-1 y
     *iters = it;
     *relres = res;
     return OFDFT_OK;

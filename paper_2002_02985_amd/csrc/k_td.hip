@@ -80,24 +80,38 @@ __global__ __launch_bounds__(NT) void k_td_kick(Geom g, TdLattice L, double k0, 
     }
 }
 
-// the kinetic operator on the two half spectra: X *= G^2 / 2
+// A diagonal operator c(G) of the complex field on the half spectra A, B of
+// its real and imaginary parts (psi = a + i b): with c = cr + i ci even in G,
+// the result's parts have spectra cr A - ci B and ci A + cr B.  With
+// q = tau G^2 / 2: TD_KIN c = G^2 / 2 (the kinetic operator), TD_K c = 1 + i q,
+// TD_KINV c = 1 / (1 + i q).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_td_kinetic(long long nh, cpx<T> *spec, const T *g2)
+__global__ __launch_bounds__(NT) void k_td_spectral(long long nh, cpx<T> *spec, const T *g2,
+                                                    double tau, int mode)
 {
     for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < nh;
          e += (long long)gridDim.x * NT) {
-        const T h = T(0.5) * g2[e];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            cpx<T> x = spec[f * nh + e];
-            x.x *= h;
-            x.y *= h;
-            spec[f * nh + e] = x;
+        const double h = 0.5 * (double)g2[e];
+        double cr, ci;
+        if (mode == TD_KIN) {
+            cr = h;
+            ci = 0.0;
+        } else if (mode == TD_K) {
+            cr = 1.0;
+            ci = tau * h;
+        } else {
+            const double q = tau * h, d = 1.0 / (1.0 + q * q);
+            cr = d;
+            ci = -q * d;
         }
+        const cpx<T> A = spec[e], B = spec[nh + e];
+        const double ar = A.x, ai = A.y, br = B.x, bi = B.y;
+        spec[e] = {T(cr * ar - ci * br), T(cr * ai - ci * bi)};
+        spec[nh + e] = {T(ci * ar + cr * br), T(ci * ai + cr * bi)};
     }
 }
 
-// out = x + sgn i tau (Tx + v x), Tx the kinetic part already applied
+// out = x + i tau (Tx + v x), Tx the kinetic part already applied
 template <typename T>
 __global__ __launch_bounds__(NT) void k_td_apply(long long n, const T *x, const T *tx, const T *v,
                                                  double tau, T *out)
@@ -108,6 +122,20 @@ __global__ __launch_bounds__(NT) void k_td_apply(long long n, const T *x, const 
         const double hr = (double)tx[i] + vv * xr, hi = (double)tx[n + i] + vv * xi;
         out[i] = T(xr - tau * hi);
         out[n + i] = T(xi + tau * hr);
+    }
+}
+
+// out = z + i tau v u (the right-preconditioned operator with u = K^-1 z)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_pc_apply(long long n, const T *z, const T *u,
+                                                    const T *v, double tau, T *out)
+{
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT) {
+        const double vv = v[i], ur = u[i], ui = u[n + i];
+        const double zr = z[i], zi = z[n + i];
+        out[i] = T(zr - tau * vv * ui);
+        out[n + i] = T(zi + tau * vv * ur);
     }
 }
 
@@ -173,10 +201,21 @@ hipError_t launch_td_kick(const Geom &g, const TdLattice &L, const double k[3], 
 }
 
 template <typename T>
-hipError_t launch_td_kinetic(const Geom &g, void *spec, const void *g2, hipStream_t s)
+hipError_t launch_td_spectral(const Geom &g, void *spec, const void *g2, double tau, int mode,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL((k_td_kinetic<T>), dim3(td_grid(g.Nh)), dim3(NT), 0, s, g.Nh,
-                       (cpx<T> *)spec, (const T *)g2);
+    if (mode != TD_KIN && mode != TD_K && mode != TD_KINV) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_td_spectral<T>), dim3(td_grid(g.Nh)), dim3(NT), 0, s, g.Nh,
+                       (cpx<T> *)spec, (const T *)g2, tau, mode);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_td_pc_apply(long long n, const void *z, const void *u, const void *v,
+                              double tau, void *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_pc_apply<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (const T *)z,
+                       (const T *)u, (const T *)v, tau, (T *)out);
     return hipGetLastError();
 }
 
@@ -206,7 +245,10 @@ hipError_t launch_td_zlincomb(long long n, void *z, const double a[2], const voi
                                             double *, hipStream_t);                               \
     template hipError_t launch_td_kick<T>(const Geom &, const TdLattice &, const double *,        \
                                           const void *, void *, hipStream_t);                     \
-    template hipError_t launch_td_kinetic<T>(const Geom &, void *, const void *, hipStream_t);    \
+    template hipError_t launch_td_spectral<T>(const Geom &, void *, const void *, double, int,     \
+                                              hipStream_t);                                       \
+    template hipError_t launch_td_pc_apply<T>(long long, const void *, const void *, const void *, \
+                                              double, void *, hipStream_t);                       \
     template hipError_t launch_td_apply<T>(long long, const void *, const void *, const void *,   \
                                            double, void *, hipStream_t);                          \
     template hipError_t launch_td_zlincomb<T>(long long, void *, const double *, const void *,    \

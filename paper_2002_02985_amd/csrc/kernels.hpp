@@ -299,9 +299,18 @@ hipError_t launch_td_dipole(const Geom &g, const TdLattice &L, const void *rho, 
 template <typename T>
 hipError_t launch_td_kick(const Geom &g, const TdLattice &L, const double k[3], const void *rho,
                           void *psi, hipStream_t s);
-// two half spectra (2 x Nh complex) times G^2 / 2; g2: the grid's G^2 table
+// a diagonal operator c(G) of the complex field on the half spectra of its
+// two parts (2 x Nh complex); g2: the grid's G^2 table; q = tau G^2 / 2
+enum { TD_KIN = 0,    // c = G^2 / 2
+       TD_K = 1,      // c = 1 + i q
+       TD_KINV = 2 }; // c = 1 / (1 + i q)
 template <typename T>
-hipError_t launch_td_kinetic(const Geom &g, void *spec, const void *g2, hipStream_t s);
+hipError_t launch_td_spectral(const Geom &g, void *spec, const void *g2, double tau, int mode,
+                              hipStream_t s);
+// out = z + i tau v u
+template <typename T>
+hipError_t launch_td_pc_apply(long long n, const void *z, const void *u, const void *v,
+                              double tau, void *out, hipStream_t s);
 // out = x + i tau (tx + v x)
 template <typename T>
 hipError_t launch_td_apply(long long n, const void *x, const void *tx, const void *v, double tau,
