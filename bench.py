@@ -158,6 +158,8 @@ def parse():
                     help="ionic structure factor: smooth PME (the paper's method for large "
                          "cells) or the exact tiled direct sum")
     ap.add_argument("--c5-pme-order", type=int, default=10)
+    ap.add_argument("--c5-method", default="pcg", choices=("pcg", "tn"),
+                    help="optimiser of both stages: preconditioned CG or truncated Newton")
     ap.add_argument("--opt-methods", action="store_true",
                     help="optimise the 108-atom cell with CG, preconditioned CG and truncated Newton")
     ap.add_argument("--td", action="store_true",
@@ -554,7 +556,8 @@ def c5_main(args):
     del x
     torch.cuda.empty_cache()
     if not args.c5_no_opt:
-        log("uniform start, preconditioned CG, mixed precision")
+        method = ofdft.OPT_TN if args.c5_method == "tn" else ofdft.OPT_PCG
+        log("uniform start, %s, mixed precision" % args.c5_method)
         g.set_density(np.full(tuple(cell["n"]), rho0))
         t1 = time.perf_counter()
         iters = evals = 0
@@ -562,20 +565,22 @@ def c5_main(args):
         stale = 0
         r = None
         while time.perf_counter() - t1 < args.c5_budget:
-            r, st = g.optimize(tol=1e-6, max_iter=20, allow_noconv=True, method=ofdft.OPT_PCG)
+            r, st = g.optimize(tol=1e-6, max_iter=20 if method == ofdft.OPT_PCG else 5,
+                               allow_noconv=True, method=method)
             iters += r.iters
             evals += r.evals
             log("mixed: %d iterations, %d evaluations, resid %.3e, E %.8f, %.1f s" %
                 (iters, evals, r.final_resid, r.e.e_total, time.perf_counter() - t1))
             if st == ofdft.OK or r.iters == 0:
                 break
-            # the FP32 floor: a chunk that does not lower the best residual by
-            # 30% hands over to the FP64 polish
+            # the FP32 floor: a chunk (20 CG or 5 TN iterations) that does not
+            # lower the best residual by 30% hands over to the FP64 polish
             stale = stale + 1 if r.final_resid > 0.7 * best else 0
             best = min(best, r.final_resid)
             if stale >= 1:
                 break
-        out["optimize"] = {"mixed": {"iters": iters, "evals": evals, "final_resid": r.final_resid,
+        out["optimize"] = {"method": args.c5_method,
+                           "mixed": {"iters": iters, "evals": evals, "final_resid": r.final_resid,
                                      "e_total": r.e.e_total,
                                      "wall_s": round(time.perf_counter() - t1, 1),
                                      "device_bytes": ofdft.ofdft_grid_device_bytes(g.handle)}}
@@ -591,7 +596,8 @@ def c5_main(args):
             t1 = time.perf_counter()
             iters = evals = 0
             while time.perf_counter() - t1 < args.c5_budget:
-                r, st = g.optimize(tol=1e-6, max_iter=10, allow_noconv=True, method=ofdft.OPT_PCG)
+                r, st = g.optimize(tol=1e-6, max_iter=10 if method == ofdft.OPT_PCG else 3,
+                                   allow_noconv=True, method=method)
                 iters += r.iters
                 evals += r.evals
                 log("fp64: %d iterations, %d evaluations, resid %.3e, E %.8f, %.1f s" %
