@@ -83,15 +83,29 @@ __global__ __launch_bounds__(NT) void k_td_kick(Geom g, TdLattice L, double k0, 
 // A diagonal operator c(G) of the complex field on the half spectra A, B of
 // its real and imaginary parts (psi = a + i b): with c = cr + i ci even in G,
 // the result's parts have spectra cr A - ci B and ci A + cr B.  With
-// q = tau G^2 / 2: TD_KIN c = G^2 / 2 (the kinetic operator), TD_K c = 1 + i q,
-// TD_KINV c = 1 / (1 + i q).
+// q = tau h, h = G^2 / 2: TD_KIN c = h (the kinetic operator), TD_K
+// c = 1 + i q, TD_KINV c = 1 / (1 + i q).  On the self-conjugate planes
+// (k2 = 0 and n2/2) the inverse real transform keeps the Hermitian part, so
+// a point and its partner ((n0 - i0) % n0, (n1 - i1) % n1) act with the mean
+// of their two h (different for the aliased Nyquist frequencies of a skewed
+// cell): h is taken as that mean there, which keeps c even and makes TD_KINV
+// the exact inverse of TD_K.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_td_spectral(long long nh, cpx<T> *spec, const T *g2,
+__global__ __launch_bounds__(NT) void k_td_spectral(Geom g, cpx<T> *spec, const T *g2,
                                                     double tau, int mode)
 {
+    const long long nh = g.Nh;
     for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < nh;
          e += (long long)gridDim.x * NT) {
-        const double h = 0.5 * (double)g2[e];
+        double h = 0.5 * (double)g2[e];
+        const int k2 = (int)(e % g.n2h);
+        if (k2 == 0 || k2 == g.m) {
+            const long long r = e / g.n2h;
+            const int i1 = (int)(r % g.n1), i0 = (int)(r / g.n1);
+            const int p0 = i0 == 0 ? 0 : g.n0 - i0, p1 = i1 == 0 ? 0 : g.n1 - i1;
+            const long long ep = ((long long)p0 * g.n1 + p1) * g.n2h + k2;
+            h = 0.5 * (h + 0.5 * (double)g2[ep]);
+        }
         double cr, ci;
         if (mode == TD_KIN) {
             cr = h;
@@ -205,7 +219,7 @@ hipError_t launch_td_spectral(const Geom &g, void *spec, const void *g2, double 
                               hipStream_t s)
 {
     if (mode != TD_KIN && mode != TD_K && mode != TD_KINV) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_td_spectral<T>), dim3(td_grid(g.Nh)), dim3(NT), 0, s, g.Nh,
+    hipLaunchKernelGGL((k_td_spectral<T>), dim3(td_grid(g.Nh)), dim3(NT), 0, s, g,
                        (cpx<T> *)spec, (const T *)g2, tau, mode);
     return hipGetLastError();
 }

@@ -139,3 +139,17 @@ def test_pme_many_atoms_against_the_tiled_direct_sum():
     assert abs(ep["e_ext"] - ed["e_ext"]) <= 1e-8 * na
     assert abs(ep["e_ion"] - ed["e_ion"]) <= 1e-9 * abs(ed["e_ion"])
     assert float(np.abs(vp - vd).max()) <= 3e-5
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_pme_triclinic_cell_matches_the_oracle(prec):
+    """A skewed lattice: the spread works on fractional coordinates and the
+    spline factors per axis, so PME holds for any cell."""
+    lat = np.array([[10.0, 0.0, 0.0], [2.5, 11.0, 0.0], [1.0, -1.5, 12.0]])
+    rng = np.random.default_rng(12)
+    frac = rng.random((7, 3))
+    species = np.array([0, 1, 0, 1, 1, 0, 0], np.int32)
+    Z = np.array([3.0, 2.0])
+    cell = {"lattice": lat, "n": (24, 27, 32), "pos": frac @ lat, "species": species,
+            "Z": Z, "rc": np.array([1.0, 0.8]), "nelec": float(Z[species].sum())}
+    check(cell, prec, 0, "triclinic")

@@ -138,3 +138,27 @@ def test_td_refusals():
         ofdft.ofdft_td_start(g.handle, [0.1, 0.0, 0.0])
         with pytest.raises(ofdft.OfdftError):
             ofdft.ofdft_td_propagate(g.handle, 0.0, 1)      # dt = 0
+
+
+def test_td_triclinic_cell_matches_the_oracle():
+    lat = np.array([[11.0, 0.0, 0.0], [2.0, 11.5, 0.0], [-1.0, 1.5, 12.0]])
+    centre = np.array([0.5, 0.5, 0.5]) @ lat
+    cell = {"lattice": lat, "n": (12, 12, 12), "pos": centre[None, :],
+            "species": np.zeros(1, np.int32), "Z": np.array([2.0]), "rc": np.array([1.0]),
+            "nelec": 2.0}
+    oc = make_cell(cell)
+    r = TD.positions(oc) - centre
+    rho = np.exp(-np.einsum("...d,...d->...", r, r) / (2 * 1.1 ** 2)) + 1e-10
+    rho *= 2.0 / (rho.sum() * oc.dv)
+    k = [0.03, 0.02, -0.04]
+    psi_o, mu_o = TD.propagate(oc, OC.Functional(terms=int(LOCAL)), TD.kick(oc, rho, k), 0.1, 2,
+                               1)
+    with ofdft.Grid(cell, LOCAL, precision=ofdft.FP64) as g:
+        g.set_density(rho)
+        ofdft.ofdft_td_start(g.handle, k)
+        mu, st = ofdft.ofdft_td_propagate(g.handle, 0.1, 2, n_corrector=1, solver_tol=1e-13)
+        psi = ofdft.ofdft_td_get_psi(g.handle, oc.n)
+    print("triclinic TD: dpsi %.3e dmu %.3e" % (float(np.abs(psi - psi_o).max()),
+                                                float(np.abs(mu - mu_o).max())), flush=True)
+    assert float(np.abs(psi - psi_o).max()) <= 1e-9 * float(np.abs(psi_o).max())
+    np.testing.assert_allclose(mu, mu_o, rtol=0, atol=1e-9)
