@@ -38,6 +38,16 @@ def box(n, L=(9.0, 10.0, 11.0), natoms=3, seed=0, Z=2.0):
             "Z": np.array([Z]), "rc": np.array([1.0]), "nelec": Z * natoms}
 
 
+def tri(n, natoms=3, seed=0, Z=2.0):
+    """A skewed (triclinic) cell: the aliased Nyquist frequencies of the
+    self-conjugate planes then have partners with a different |G|."""
+    lat = np.array([[9.0, 0.0, 0.0], [-3.5, 9.5, 0.0], [1.2, -0.8, 10.5]])
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, 1, size=(natoms, 3)) @ lat
+    return {"lattice": lat, "n": n, "pos": pos, "species": np.zeros(natoms, np.int32),
+            "Z": np.array([Z]), "rc": np.array([1.0]), "nelec": Z * natoms}
+
+
 def varied_rho(cell_d, seed=1, amp=0.9, rho0=0.03):
     c = make_cell(cell_d)
     return smooth_density(c, seed=seed, amp=amp, nmodes=3, rho0=rho0)
@@ -126,6 +136,12 @@ CASES = {
                            dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
     "box_xc_dense": (lambda: (box((12, 18, 16), L=(2.5, 2.7, 3.0)), None),
                      ofdft.TERM_TF | ofdft.TERM_XC, {}),
+    # triclinic cells, row path and plane path
+    "tri_wt": (lambda: (tri((24, 16, 12)), None), LOCAL | ofdft.TERM_WT, {}),
+    "tri_spline_s3s4": (lambda: (tri((18, 16, 24)), None), LOCAL | ofdft.TERM_SPLINE,
+                        dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    "tri_plane_spline_exact": (lambda: (tri((16, 32, 32)), None), LOCAL | ofdft.TERM_SPLINE,
+                               dict(nk=12, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT)),
 }
 
 
