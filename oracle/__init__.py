@@ -9,8 +9,8 @@ What it computes follows the paper (Shao, Jiang, Mi, Genova, Pavanello,
 "DFTpy: An efficient and object-oriented platform for orbital-free DFT
 simulations", arXiv:2002.02985):
 
-* the energy functional E[rho] = T_s + E_H + int v_ext rho  (Introduction,
-  eq. "efunc"; exchange-correlation is not part of this path),
+* the energy functional E[rho] = T_s + E_H + E_xc + int v_ext rho
+  (Introduction, eq. "efunc"; E_xc the LDA of Perdew and Zunger, optional),
 * its functional derivative v = dE/drho and the Euler-Lagrange residual
   (Introduction, eqs. "euler", "euler2a"; Section "Density optimization
   strategies", eq. "euler2"),
@@ -24,7 +24,11 @@ simulations", arXiv:2002.02985):
 * the smooth particle-mesh Ewald structure factor the paper uses for large
   cells (``oracle.pme``),
 * the constrained minimisation over psi = sqrt(rho) with the orthogonal
-  rotation update (Section "Density optimization strategies").
+  rotation update (Section "Density optimization strategies"), and the
+  coarse-to-fine interpolation of the multi-step scheme (``oracle.multistep``),
+* real-time TD-OFDFT: Crank-Nicolson propagation of the collective orbital
+  with exact linear solves (Section "Time-Dependent OFDFT",
+  ``oracle.tdofdft``).
 
 Conventions used by every module here (and, independently, by the GPU path):
 
