@@ -82,6 +82,19 @@ template <typename T, int L> constexpr int col_P_plain()
     if (p > NT) p = NT;
     return p;
 }
+// threads per block of the column kernel: 256, and more for long columns,
+// whose L x P tile fills so much LDS that one or two blocks fit on a CU (a
+// 1024-point, 16-column tile takes 128 KB): L P / 16 rounded down to a power
+// of two, clamped to 256 .. 1024, keeps about 16 elements per thread.  (The
+// knot kernels stay at 256: with more threads their per-knot registers spill
+// at two blocks per CU, which measured slower.)
+template <typename T, int L, int P> constexpr int col_NT()
+{
+    int t = pow2_floor(L * P / 16);
+    if (t < NT) t = NT;
+    if (t > 1024) t = 1024;
+    return t;
+}
 template <typename T, int M> constexpr int row_P()
 {
     int p = pow2_floor(Cfg<T>::ROW_ELEMS / M);
@@ -358,8 +371,9 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 // one tile of every (field, density) array, which keeps the tile's share of
 // the reciprocal-space tables in L2).
 template <typename T, int L, int P>
-__global__ __launch_bounds__(NT) void k_col(ColArgs a, int nfb, int ntiles)
+__global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb, int ntiles)
 {
+    constexpr int NT = col_NT<T, L, P>();   // this kernel's block size
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     static_assert(NT % P == 0, "tile width must divide the block");
@@ -1608,7 +1622,8 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
             nblocks = (int)((a.ncols + PP - 1) / PP);
             const long long total = (long long)nblocks * nfb;
             if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_col<T, L, PP>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb,
+            hipLaunchKernelGGL((k_col<T, L, PP>), dim3((unsigned)total), dim3(col_NT<T, L, PP>()),
+                               0, s, a, nfb,
                                nblocks);
             return hipGetLastError();
         }
@@ -1617,7 +1632,8 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
     if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
     const long long total = (long long)nblocks * nfb;
     if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(NT), 0, s, a, nfb, nblocks);
+    hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0, s, a,
+                       nfb, nblocks);
     return hipGetLastError();
 }
 

@@ -136,6 +136,19 @@ CASES = {
                            dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
     "box_xc_dense": (lambda: (box((12, 18, 16), L=(2.5, 2.7, 3.0)), None),
                      ofdft.TERM_TF | ofdft.TERM_XC, {}),
+    # 1024-point axes (the million-atom grid's column and knot kernels) at a
+    # realistic spacing (0.29 Bohr; on an over-resolved axis the vW Laplacian
+    # multiplies FP32 rounding by G_max^2, which grows as the square of the
+    # number of points)
+    "spline_1024_axis0_s3s4": (lambda: (box((1024, 4, 8), L=(300.0, 6.0, 7.0), natoms=40), None),
+                               LOCAL | ofdft.TERM_SPLINE,
+                               dict(nk=9, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    "spline_1024_axis0_exact": (lambda: (box((1024, 4, 8), L=(300.0, 6.0, 7.0), natoms=40), None),
+                                LOCAL | ofdft.TERM_SPLINE,
+                                dict(nk=9, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT)),
+    "spline_1024_axis1_s3s4": (lambda: (box((4, 1024, 8), L=(6.0, 300.0, 7.0), natoms=40), None),
+                               LOCAL | ofdft.TERM_SPLINE,
+                               dict(nk=9, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
     # triclinic cells, row path and plane path
     "tri_wt": (lambda: (tri((24, 16, 12)), None), LOCAL | ofdft.TERM_WT, {}),
     "tri_spline_s3s4": (lambda: (tri((18, 16, 24)), None), LOCAL | ofdft.TERM_SPLINE,
