@@ -93,7 +93,12 @@ enum { OFDFT_FP64 = 0, OFDFT_MIXED = 1 };
  * with cardinal B-splines of order pme_order, one forward transform, and the
  * exponential-spline factors; the Ewald split is chosen so that the
  * reciprocal sum ends at half the box.  PME takes the large-cell ionic path
- * at any atom count, where ofdft_forces is not offered. */
+ * at any atom count, where ofdft_forces is not offered.  Its set-up (grid
+ * creation, and each change of positions) also allocates, and frees again,
+ * N x 8 bytes for the fixed-point charge grid, N x 4 more on a mixed grid
+ * and 16 bytes per half-spectrum point with more than one species; these
+ * transient bytes are not part of ofdft_footprint_bytes or
+ * ofdft_grid_device_bytes. */
 enum { OFDFT_SF_DIRECT = 0, OFDFT_SF_PME = 1 };
 
 /* Cell: lattice vectors as rows (Bohr), grid, atoms.  pos is natoms x 3
