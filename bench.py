@@ -162,6 +162,8 @@ def parse():
                     help="optimiser of both stages: preconditioned CG or truncated Newton")
     ap.add_argument("--opt-methods", action="store_true",
                     help="optimise the 108-atom cell with CG, preconditioned CG and truncated Newton")
+    ap.add_argument("--host-path", action="store_true",
+                    help="the host-array entry point on the 108-atom cell (PCIe included)")
     ap.add_argument("--td", action="store_true",
                     help="real-time TD-OFDFT instead: Mg cluster ground state, kick, "
                          "Crank-Nicolson propagation, dipole spectrum")
@@ -796,6 +798,42 @@ def opt_methods_main(args):
     print(json.dumps(out), flush=True)
 
 
+def host_path_main(args):
+    """The host-array entry point (ofdft_energy_potential: FP64 host density
+    in, FP64 host potential out, one density per call) on the 108-atom
+    cell: the PCIe-inclusive rate, beside the device-resident batch."""
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    terms = ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT | ofdft.TERM_WT
+    cell, dens = W.config_c2(N_GRID, 20)
+    N = int(np.prod(cell["n"]))
+    out = {"metric": "energy+potential evals/s through host arrays (PCIe included)",
+           "unit": "Gpts/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "fcc Al 3x3x3 (108 atoms, a=22.95 Bohr), 96^3 grid, "
+                                  "WT+vW+TF+Hartree+local pseudopotential, 20 seeded densities, "
+                                  "one per call, FP64 host arrays in and out"}}
+    for prec, pname in ((ofdft.MIXED, "mixed"), (ofdft.FP64, "fp64")):
+        with ofdft.Grid(cell, terms, precision=prec) as g:
+            for rho in dens[:3]:
+                g.energy_potential(rho)
+            lat = []
+            for rho in dens:
+                t0 = time.perf_counter()
+                g.energy_potential(rho)
+                lat.append(time.perf_counter() - t0)
+        ms = float(np.median(lat)) * 1e3
+        out[pname] = {"ms_per_eval": round(ms, 3), "Gpts_per_s": round(N / (ms * 1e-3) / 1e9, 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+        log("%s: %.3f ms per evaluation through host arrays" % (pname, ms))
+    out["value"] = out["mixed"]["Gpts_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.opt_methods:
@@ -803,6 +841,12 @@ def main():
             print("bench.py: this build runs on one GPU", file=sys.stderr)
             sys.exit(2)
         opt_methods_main(args)
+        return
+    if args.host_path:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        host_path_main(args)
         return
     if args.td:
         if args.gpus != 1:
