@@ -170,6 +170,31 @@ def test_warm_start_across_md_frames():
         s.close()
 
 
+def test_pme_cell_across_md_frames_matches_direct_grid():
+    """A cell whose structure factor is taken by smooth PME: each MD frame
+    re-spreads the charge grid on the resident cell, and the results equal a
+    fresh grid of that frame bit for bit (the fixed-point spread makes PME
+    independent of the order in which atoms land)."""
+    base = dict(W.cluster(19, "Al", seed=11, grid=48), sf_method=ofdft.SF_PME, pme_order=8)
+    rng = np.random.default_rng(9)
+    frames = [base["pos"], base["pos"] + rng.normal(0.0, 0.1, size=base["pos"].shape)]
+    s = Server(max_inflight=2)
+    try:
+        for p in frames:
+            cell = dict(base, pos=p)
+            q = {"cell_id": 0, "kind": ofdft.REQ_EP, "cell": cell,
+                 "rho": W.gaussian_density(cell, sigma=1.5, floor=1e-8)}
+            st, r, v, _ = s.result(s.submit(q), q)
+            assert st == ofdft.OK
+            with ofdft.Grid(cell, TERMS, precision=ofdft.FP64) as g:
+                e, vg = g.energy_potential(q["rho"])
+            assert r.e.e_total == e.e_total and r.e.e_ion == e.e_ion
+            assert np.array_equal(v, vg)
+        assert s.stats()["resident_cells"] == 1
+    finally:
+        s.close()
+
+
 def test_admission_under_a_tight_budget():
     reqs = [q for q in _stream(10)]
     cds = [ofdft.make_cell_desc(q["cell"]) for q in reqs]
