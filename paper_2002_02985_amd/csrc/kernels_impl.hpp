@@ -82,18 +82,30 @@ template <typename T, int L> constexpr int col_P_plain()
     if (p > NT) p = NT;
     return p;
 }
+// columns per block and threads per block of the knot kernels: the column
+// tile, except for 1024-point columns, which take the wide tile of the
+// plain column passes (16 columns: the eight knot spectra are written in
+// 128-byte row segments instead of 64-byte ones) with 1024 threads
+template <typename T, int L> constexpr int knot_P()
+{
+    return L >= 1024 ? col_P_plain<T, L>() : col_P<T, L>();
+}
 // threads per block of the column kernel: 256, and more for long columns,
 // whose L x P tile fills so much LDS that one or two blocks fit on a CU (a
 // 1024-point, 16-column tile takes 128 KB): L P / 16 rounded down to a power
 // of two, clamped to 256 .. 1024, keeps about 16 elements per thread.  (The
-// knot kernels stay at 256: with more threads their per-knot registers spill
-// at two blocks per CU, which measured slower.)
+// knot kernels of 8-column tiles stay at 256: with more threads their
+// per-knot registers spill at two blocks per CU, which measured slower.)
 template <typename T, int L, int P> constexpr int col_NT()
 {
     int t = pow2_floor(L * P / 16);
     if (t < NT) t = NT;
     if (t > 1024) t = 1024;
     return t;
+}
+template <typename T, int L> constexpr int knot_NT()
+{
+    return knot_P<T, L>() != col_P<T, L>() ? col_NT<T, L, knot_P<T, L>()>() : NT;
 }
 template <typename T, int M> constexpr int row_P()
 {
@@ -143,16 +155,18 @@ template <typename T>
 __device__ __forceinline__ T gnl_dev(T eta)
 {
     if (!(eta > T(0))) return T(0);
-    // FP32: quotients by the hardware reciprocal (1 ulp); FP64: divisions
-    if (eta < T(1)) {
-        T F = T(0.5) + (T(1) - eta) * (T(1) + eta) * d_rcp(T(4) * eta) *
-                           d_log1p(T(2) * eta * d_rcp(T(1) - eta));
-        return d_rcp(F) - T(3) * eta * eta - T(1);
-    }
     if (eta == T(1)) return T(-2);
+    // FP32: quotients by the hardware reciprocal (1 ulp); FP64: divisions.
+    // Below 1.6 one expression serves both sides of eta = 1 (the operands
+    // selected per lane, so a wave whose lanes straddle eta = 1 runs one
+    // logarithm): ln|(1 + eta)/(1 - eta)| = log1p(2 eta / (1 - eta)) below 1,
+    // log1p(2 / (eta - 1)) above, and (1 - eta^2) changes sign.
     if (eta < T(1.6)) {
-        T F = T(0.5) - (eta - T(1)) * (eta + T(1)) * d_rcp(T(4) * eta) *
-                           d_log1p(T(2) * d_rcp(eta - T(1)));
+        const bool lo = eta < T(1);
+        const T d = lo ? T(1) - eta : eta - T(1);
+        const T num = lo ? T(2) * eta : T(2);
+        const T m = lo ? (T(1) - eta) * (T(1) + eta) : -((eta - T(1)) * (eta + T(1)));
+        T F = T(0.5) + m * d_rcp(T(4) * eta) * d_log1p(num * d_rcp(d));
         return d_rcp(F) - T(3) * eta * eta - T(1);
     }
     const T x = d_rcp(eta * eta);
@@ -513,9 +527,10 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
 // Step s2/s3: for knots i = knot0 .. knot0+K-1, Phi_i(G) = omega_i(|G|) rho^b(G)
 // with omega_i = C_WT G_NL(|G| / (2 k_i)), then the axis-0 inverse.
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
+__global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
 {
-    constexpr int P = col_P<T, L>();
+    constexpr int P = knot_P<T, L>();
+    constexpr int NT = knot_NT<T, L>();   // this kernel's block size
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     __shared__ cpx<T> buf[L * P];
@@ -568,9 +583,10 @@ __global__ __launch_bounds__(NT) void k_knot_inv(KnotArgs a)
 // K inputs have had the axis-2 r2c and axis-1 forward passes; this kernel does
 // the axis-0 forward transform and the normalisation.
 template <typename T, int L>
-__global__ __launch_bounds__(NT) void k_knot_acc(KnotArgs a)
+__global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
 {
-    constexpr int P = col_P<T, L>();
+    constexpr int P = knot_P<T, L>();
+    constexpr int NT = knot_NT<T, L>();   // this kernel's block size
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     __shared__ cpx<T> buf[L * P];
@@ -1640,18 +1656,18 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
 template <typename T, int L>
 hipError_t knot_inv_go(const KnotArgs &a, hipStream_t s)
 {
-    constexpr int P = col_P<T, L>();
+    constexpr int P = knot_P<T, L>();
     dim3 grid((unsigned)((a.ncols + P - 1) / P), a.nbatch);
-    hipLaunchKernelGGL((k_knot_inv<T, L>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_knot_inv<T, L>), grid, dim3(knot_NT<T, L>()), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T, int L>
 hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
 {
-    constexpr int P = col_P<T, L>();
+    constexpr int P = knot_P<T, L>();
     dim3 grid((unsigned)((a.ncols + P - 1) / P), a.nbatch);
-    hipLaunchKernelGGL((k_knot_acc<T, L>), grid, dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_knot_acc<T, L>), grid, dim3(knot_NT<T, L>()), 0, s, a);
     return hipGetLastError();
 }
 
