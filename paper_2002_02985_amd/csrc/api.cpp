@@ -972,8 +972,10 @@ static ofdft_status eval_dispatch(ofdft_grid *g, int nb, const void *d_in, int i
 
 // ---------------------------------------------------------------- FFT pair
 template <typename T>
+// sync: wait for the stream at the end; consume: the inverse may overwrite
+// d_in (a scratch spectrum) instead of working on a copy in the workspace
 static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_out, bool fwd,
-                             hipStream_t s, bool sync = true)
+                             hipStream_t s, bool sync = true, bool consume = false)
 {
     ST_TRY(reserve(g, nb));
     const Geom &G = g->geom;
@@ -999,15 +1001,18 @@ static ofdft_status fft_impl(ofdft_grid *g, int nb, const void *d_in, void *d_ou
         int ops[4] = {GO_SCALE, 0, 0, 0};
         ST_TRY(col_pass<T>(g, s, 0, d_out, nb, nb, 0, ops, PS_COL0_G));
     } else {
-        // inverse: copy the spectrum into the workspace so the caller's input survives
-        HIP_TRY(hipMemcpyAsync(g->spec, d_in, (size_t)nb * G.Nh * 2 * sizeof(T),
-                               hipMemcpyDeviceToDevice, s));
-        ST_TRY(col_pass<T>(g, s, 0, g->spec, nb, nb, 1, nullptr, PS_COL0_G));
+        // inverse: copy the spectrum into the workspace so the caller's input
+        // survives, unless it may be consumed
+        void *work = consume ? const_cast<void *>(d_in) : g->spec;
+        if (!consume)
+            HIP_TRY(hipMemcpyAsync(g->spec, d_in, (size_t)nb * G.Nh * 2 * sizeof(T),
+                                   hipMemcpyDeviceToDevice, s));
+        ST_TRY(col_pass<T>(g, s, 0, work, nb, nb, 1, nullptr, PS_COL0_G));
         const bool plane = use_plane<T>(g);
-        if (!plane) ST_TRY(col_pass<T>(g, s, 1, g->spec, nb, nb, 1, nullptr, PS_COL1_INV));
+        if (!plane) ST_TRY(col_pass<T>(g, s, 1, work, nb, nb, 1, nullptr, PS_COL1_INV));
         RowInvArgs ri;
         std::memset(&ri, 0, sizeof(ri));
-        ri.spec = g->spec;
+        ri.spec = work;
         ri.spec_fstride = 0;
         ri.nfields = 1;
         ri.mode = EP_STORE;
@@ -2196,7 +2201,7 @@ static ofdft_status td_kapply(ofdft_grid *g, const TdBufs &B, hipStream_t s, con
     ST_TRY(fft_impl<T>(g, 2, x, B.spec, true, s, false));
     const void *g2 = static_cast<const char *>(g->gtab) + (size_t)G.Nh * g->fsz;
     HIP_TRY(launch_td_spectral<T>(G, B.spec, g2, tau, mode, s));
-    ST_TRY(fft_impl<T>(g, 2, B.spec, out, false, s, false));
+    ST_TRY(fft_impl<T>(g, 2, B.spec, out, false, s, false, true));   // B.spec is scratch
     return OFDFT_OK;
 }
 
