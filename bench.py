@@ -162,6 +162,9 @@ def parse():
                     help="optimiser of both stages: preconditioned CG or truncated Newton")
     ap.add_argument("--opt-methods", action="store_true",
                     help="optimise the 108-atom cell with CG, preconditioned CG and truncated Newton")
+    ap.add_argument("--kedf-scaling", action="store_true",
+                    help="nonlocal spline KEDF vs TF+vW evaluation time on Al clusters of "
+                         "13 to 12,195 atoms")
     ap.add_argument("--host-path", action="store_true",
                     help="the host-array entry point on the 108-atom cell (PCIe included)")
     ap.add_argument("--td", action="store_true",
@@ -798,6 +801,63 @@ def opt_methods_main(args):
     print(json.dumps(out), flush=True)
 
 
+def kedf_scaling_main(args):
+    """The shape of the paper's timing table for the density-dependent
+    nonlocal KEDF (Section "New-generation nonlocal KEDFs", Table "tlmgp"):
+    Al clusters of 13 to 12,195 atoms with 15 Angstrom of vacuum, 40
+    arithmetic k_F knots, linear-spline potential (S3S4); one energy+potential
+    evaluation with TF+vW alone and with the spline functional added, mixed
+    precision, grid spacing at most 0.38 Bohr."""
+    import torch
+    from paper_2002_02985_amd import ofdft
+    from paper_2002_02985_amd import workloads as W
+    ofdft.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    lengths = [n for n in range(32, 1025) if n % 2 == 0 and ofdft.ofdft_supported_length(n)
+               and ofdft.ofdft_supported_length(n // 2)]
+    semi = ofdft.TERM_TF | ofdft.TERM_VW
+    spl = dict(nk=40, kf_min=0.1, kf_max=3.0, knot_spacing=ofdft.KNOTS_LIN,
+               nl_mode=ofdft.NL_S3S4)
+    sh = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for natoms in (13, 55, 147, 309, 561, 923, 1415, 2057, 4085, 12195):
+        cell = dict(W.cluster(natoms, "Al", seed=1, vacuum=28.35, grid=48))
+        L = float(cell["lattice"][0][0])
+        n = min(x for x in lengths if x >= L / 0.38)
+        cell["n"] = (n, n, n)
+        rho = W.gaussian_density(cell, sigma=1.5, floor=1e-12)
+        x = torch.from_numpy(rho).to(dtype=torch.float32, device="cuda:0")
+        ts = {}
+        for name, terms, kw in (("tf_vw", semi, {}), ("tf_vw_nl", semi | ofdft.TERM_SPLINE, spl)):
+            with ofdft.Grid(cell, terms, precision=ofdft.MIXED, **kw) as g:
+                for _ in range(2):
+                    ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
+                torch.cuda.synchronize()
+                lat = []
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    ofdft.ofdft_energy_potential_dev(g.handle, x.data_ptr(), None, sh)
+                    lat.append(time.perf_counter() - t0)
+            ts[name] = float(np.median(lat)) * 1e3
+        del x
+        torch.cuda.empty_cache()
+        row = {"natoms": natoms, "grid": n, "L_bohr": round(L, 1),
+               "ms_tf_vw": round(ts["tf_vw"], 3), "ms_tf_vw_nl": round(ts["tf_vw_nl"], 3),
+               "nl_over_semilocal": round((ts["tf_vw_nl"] - ts["tf_vw"]) / ts["tf_vw"], 2)}
+        rows.append(row)
+        log("%5d atoms, %d^3: TF+vW %.3f ms, +NL %.3f ms, NL / semilocal %.1f" % (
+            natoms, n, ts["tf_vw"], ts["tf_vw_nl"], row["nl_over_semilocal"]))
+    out = {"metric": "nonlocal (spline) KEDF cost over TF+vW per evaluation, Al clusters",
+           "unit": "ratio", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "Al clusters (fcc sites nearest a seeded "
+                                                     "centre), 28.35 Bohr vacuum, spacing <= 0.38 "
+                                                     "Bohr, 40 arithmetic knots 0.1-3.0, S3S4"},
+           "rows": rows, "value": max(r["nl_over_semilocal"] for r in rows)}
+    print(json.dumps(out), flush=True)
+
+
 def host_path_main(args):
     """The host-array entry point (ofdft_energy_potential: FP64 host density
     in, FP64 host potential out, one density per call) on the 108-atom
@@ -841,6 +901,12 @@ def main():
             print("bench.py: this build runs on one GPU", file=sys.stderr)
             sys.exit(2)
         opt_methods_main(args)
+        return
+    if args.kedf_scaling:
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            sys.exit(2)
+        kedf_scaling_main(args)
         return
     if args.host_path:
         if args.gpus != 1:
