@@ -12,10 +12,16 @@ from paper_2002_02985_amd import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def test_admission_policy_scenarios(tmp_path):
+# the policy header on its own, and again under AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only, built with the host compiler)
+SANITIZE = [[], ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]]
+
+
+@pytest.mark.parametrize("extra", SANITIZE, ids=["plain", "asan_ubsan"])
+def test_admission_policy_scenarios(tmp_path, extra):
     exe = str(tmp_path / "sched_check")
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-o", exe,
-                    os.path.join(HERE, "sched_check.cpp")], check=True)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall"] + extra +
+                   ["-o", exe, os.path.join(HERE, "sched_check.cpp")], check=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.strip() == "ok"
