@@ -296,7 +296,11 @@ ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
  * when its footprint (ofdft_footprint_bytes, OPTIMIZE kind, so a resident
  * grid never grows) fits in hbm_budget_bytes next to the resident grids;
  * idle resident grids are evicted least recently used first, those with no
- * queued request before the others.  A request that cannot fit yet waits, and
+ * queued request before the others.  An evicted cell's density is kept in
+ * host memory (N doubles per cell, until the server is destroyed) and is the
+ * starting density when that cell's grid is built again with the same grid
+ * shape for a request that brings none (OPTIMIZE with warm = 0 excepted), so
+ * warm starts survive eviction.  A request that cannot fit yet waits, and
  * no later request that needs new memory overtakes it; requests for resident
  * grids still run.  A footprint above the whole budget is refused at submit
  * with OFDFT_ENOMEM.

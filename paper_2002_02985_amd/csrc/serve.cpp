@@ -106,6 +106,11 @@ struct Res {
     ofdft_functional_desc func{};
 };
 
+struct SavedDensity {
+    int32_t n[3] = {0, 0, 0};
+    std::vector<double> rho;
+};
+
 double ms_between(Clock::time_point a, Clock::time_point b)
 {
     return std::chrono::duration<double, std::milli>(b - a).count();
@@ -129,6 +134,9 @@ struct ofdft_server {
     std::vector<double> lat_ms, queue_ms;
     std::vector<ofdft_ctx *> ctxs;
     std::vector<std::thread> workers;
+    // densities of evicted cells, kept in host memory and handed back as the
+    // starting density when the cell's grid is built again (same grid shape)
+    std::unordered_map<uint64_t, SavedDensity> saved;
 };
 
 namespace {
@@ -142,8 +150,9 @@ int find_resident(const ofdft_server *s, uint64_t cell_id)
 
 // Runs one request on resident grid r (created here if it has none) on the
 // worker's context.  Called without the server lock; r is owned by this
-// worker while busy.
-void execute(Job &job, Res &r, ofdft_ctx *ctx)
+// worker while busy.  saved: the density kept for this cell when its grid
+// was evicted (empty if none), the start of a request that brings none.
+void execute(Job &job, Res &r, ofdft_ctx *ctx, const SavedDensity &saved)
 {
     ofdft_status st = OFDFT_OK;
     bool fresh = false;
@@ -170,6 +179,10 @@ void execute(Job &job, Res &r, ofdft_ctx *ctx)
         ofdft_internal::set_cancel(g, &job.cancel);
         if (!job.rho.empty()) {
             st = ofdft_set_density(g, job.rho.data());
+        } else if (!r.has_density && !cold_opt && !saved.rho.empty() &&
+                   saved.n[0] == job.cell.d.n[0] && saved.n[1] == job.cell.d.n[1] &&
+                   saved.n[2] == job.cell.d.n[2]) {
+            st = ofdft_set_density(g, saved.rho.data());
         } else if (!r.has_density || cold_opt) {
             const double V = std::fabs(
                 job.cell.d.lattice[0][0] * (job.cell.d.lattice[1][1] * job.cell.d.lattice[2][2] -
@@ -254,17 +267,32 @@ void worker_loop(ofdft_server *s, int w)
         // take the evicted grids out of the resident set (largest index first)
         std::vector<int> ev = d.evict;
         std::sort(ev.rbegin(), ev.rend());
-        std::vector<ofdft_grid *> to_free;
+        struct Evicted {
+            ofdft_grid *g;
+            uint64_t cell_id;
+            bool keep;          // has a density worth restoring
+            int32_t n[3];
+        };
+        std::vector<Evicted> to_free;
         for (int r : ev) {
             s->used -= s->res[r]->bytes;
-            if (s->res[r]->g) to_free.push_back(s->res[r]->g);
+            const Res &x = *s->res[r];
+            if (x.g)
+                to_free.push_back({x.g, x.cell_id, x.has_density,
+                                   {x.cell.d.n[0], x.cell.d.n[1], x.cell.d.n[2]}});
             s->res.erase(s->res.begin() + r);
         }
         Res *r = nullptr;
+        SavedDensity saved;
         const int ri = find_resident(s, job->cell_id);
         if (ri >= 0) {
             r = s->res[ri].get();
         } else {
+            auto it = s->saved.find(job->cell_id);
+            if (it != s->saved.end()) {
+                saved = std::move(it->second);
+                s->saved.erase(it);
+            }
             std::unique_ptr<Res> nr(new Res);
             nr->cell_id = job->cell_id;
             nr->bytes = job->need;
@@ -279,11 +307,20 @@ void worker_loop(ofdft_server *s, int w)
         job->t_start = Clock::now();
         lk.unlock();
 
-        for (ofdft_grid *g : to_free) {
-            ofdft_internal::bind_context(g, ctx);   // idle: nothing of it is in flight
-            ofdft_grid_destroy(g);
+        for (const Evicted &e : to_free) {
+            ofdft_internal::bind_context(e.g, ctx);   // idle: nothing of it is in flight
+            if (e.keep) {
+                SavedDensity h;
+                std::memcpy(h.n, e.n, sizeof(h.n));
+                h.rho.resize((size_t)e.n[0] * e.n[1] * e.n[2]);
+                if (ofdft_get_density(e.g, h.rho.data()) == OFDFT_OK) {
+                    std::lock_guard<std::mutex> g2(s->mu);
+                    s->saved[e.cell_id] = std::move(h);
+                }
+            }
+            ofdft_grid_destroy(e.g);
         }
-        execute(*job, *r, ctx);
+        execute(*job, *r, ctx, saved);
 
         lk.lock();
         job->t_end = Clock::now();

@@ -281,3 +281,40 @@ def test_destroy_with_work_in_flight():
     for q in reqs:
         s.submit(q)
     s.close()   # cancels what is queued, waits for what runs
+
+
+def test_evicted_density_is_restored():
+    """Under a budget of one grid, cell B evicts cell A; A's density is kept in
+    host memory and is the warm start when A comes back without a density:
+    its optimisation resumes from the converged density (no iterations),
+    where a fresh server starts from the uniform density."""
+    a = W.cluster(19, "Al", seed=11, grid=48)
+    b = W.cluster(13, "Mg", seed=2, grid=48)
+    fd = ofdft.make_functional_desc(TERMS, precision=ofdft.FP64)
+    cd, keep = ofdft.make_cell_desc(a)
+    budget = int(ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_OPTIMIZE) * 1.2)
+    opt = dict(tol=1e-6, max_iter=400)
+
+    def run(s, cid, cell, rho):
+        q = {"cell_id": cid, "kind": ofdft.REQ_OPTIMIZE, "cell": cell, "rho": rho}
+        st, r, _, _ = s.result(s.submit(q, opt=opt, func=fd), q)
+        assert st == ofdft.OK
+        return r
+
+    s = Server(budget=budget, max_inflight=1)
+    try:
+        r1 = run(s, 0, a, W.gaussian_density(a, sigma=1.5, floor=1e-8))
+        run(s, 1, b, W.gaussian_density(b, sigma=1.5, floor=1e-8))
+        assert s.stats()["resident_cells"] == 1          # A was evicted
+        r2 = run(s, 0, a, None)
+    finally:
+        s.close()
+    s = Server(budget=budget, max_inflight=1)
+    try:
+        cold = run(s, 0, a, None)
+    finally:
+        s.close()
+    _say("A: %d iterations, again after eviction %d, uniform start %d" % (
+        r1.iters, r2.iters, cold.iters))
+    assert r2.iters <= 2 < cold.iters
+    assert abs(r2.e.e_total - r1.e.e_total) < 1e-8 * abs(r1.e.e_total)
