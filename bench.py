@@ -898,49 +898,49 @@ def main():
     args = parse()
     if args.opt_methods:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         opt_methods_main(args)
         return
     if args.kedf_scaling:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         kedf_scaling_main(args)
         return
     if args.host_path:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         host_path_main(args)
         return
     if args.td:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         td_main(args)
         return
     if args.multistep:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         multistep_main(args)
         return
     if args.c5:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         c5_main(args)
         return
     if args.c3:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         c3_main(args)
         return
     if args.serve:
         if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            print("bench.py: the benchmark runs on one GPU", file=sys.stderr)
             sys.exit(2)
         serve_main(args)
         return
@@ -950,7 +950,7 @@ def main():
         print(json.dumps(out, indent=1))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+        print("bench.py: the benchmark runs on one GPU; --gpus %d is not supported "
               "(per-GPU throughput is the single-GPU figure)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
