@@ -2540,9 +2540,8 @@ ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host, do
     const size_t N = (size_t)grid->geom.N;
     hipStream_t s = grid->ctx->stream;
     if (rho_host) {
-        for (size_t i = 0; i < N; ++i)
-            if (!std::isfinite(rho_host[i]) || rho_host[i] < 0)
-                return fail(OFDFT_EINVAL, "density has non-finite or negative values");
+        // non-finite or negative values are counted by the evaluation itself
+        // (its prologue partials), which then fails with OFDFT_EINVAL
         ST_TRY(dmalloc(grid, &grid->stage_in, N * grid->fsz));
         ST_TRY(upload_field(grid, grid->stage_in, rho_host, N, s));
     }
