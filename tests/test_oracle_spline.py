@@ -145,3 +145,48 @@ def test_brackets_tie_rules():
     np.testing.assert_array_equal(inside, [False, False, True, True, False, False])
     np.testing.assert_allclose(C.knots(C.Functional(nk=32, kf_min=0.1, kf_max=3.0))[[0, 31]],
                                [0.1, 3.0], rtol=1e-15)
+
+
+def test_log_knots_are_a_geometric_progression():
+    """Step s1 with geometric spacing: every interior knot is pinned, not only
+    the ends.  A geometric progression has a constant ratio and mirror pairs
+    whose product is k_min k_max; an arithmetic progression between the same
+    ends fails both (and the arithmetic variant is checked by the dual
+    properties: constant difference, mirror pairs summing to k_min + k_max)."""
+    for nk, lo, hi in [(32, 0.1, 3.0), (7, 0.25, 4.0), (2, 0.5, 2.0)]:
+        k = C.knots(C.Functional(nk=nk, kf_min=lo, kf_max=hi, knot_spacing=C.KNOTS_LOG))
+        assert len(k) == nk
+        ratio = k[1:] / k[:-1]
+        np.testing.assert_allclose(ratio, (hi / lo) ** (1.0 / (nk - 1)), rtol=1e-13)
+        np.testing.assert_allclose(k * k[::-1], lo * hi, rtol=1e-13)
+        # log k is evenly spaced from log k_min to log k_max
+        np.testing.assert_allclose(np.log(k), np.linspace(np.log(lo), np.log(hi), nk),
+                                   rtol=0, atol=1e-13)
+        kl = C.knots(C.Functional(nk=nk, kf_min=lo, kf_max=hi, knot_spacing=C.KNOTS_LIN))
+        np.testing.assert_allclose(np.diff(kl), (hi - lo) / (nk - 1), rtol=1e-13)
+        np.testing.assert_allclose(kl + kl[::-1], lo + hi, rtol=1e-13)
+        if nk > 2:
+            # the two progressions really differ inside
+            assert np.abs(k[1:-1] - kl[1:-1]).min() > 1e-3
+
+
+def test_brackets_on_log_knots_match_a_linear_search():
+    """Bracket and weight on the 32 geometric knots of the slab workload
+    against a plain linear scan over the segments."""
+    kn = C.knots(C.Functional(nk=32, kf_min=0.1, kf_max=3.0))
+    rng = np.random.default_rng(11)
+    kf = np.concatenate([np.exp(rng.uniform(np.log(0.05), np.log(4.0), 2000)), kn,
+                         [0.1, 3.0, 0.0, 10.0]])
+    kt, j, t, inside = Fn.spline_brackets(kn, kf)
+    for x, jj, tt in zip(kf, j, t):
+        xc = min(max(x, kn[0]), kn[-1])
+        seg = 30
+        for s in range(31):
+            if kn[s] <= xc < kn[s + 1]:
+                seg = s
+                break
+        assert jj == seg
+        assert abs(tt - (xc - kn[seg]) / (kn[seg + 1] - kn[seg])) < 1e-14
+        # the hat weights reproduce k~ itself (linear interpolation is exact
+        # for a function linear in k)
+        assert abs((1 - tt) * kn[seg] + tt * kn[seg + 1] - xc) < 1e-14 * max(1.0, xc)
