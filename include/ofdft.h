@@ -6,9 +6,9 @@
  * efficient and object-oriented platform for orbital-free DFT simulations"
  * (arXiv:2002.02985).  The library evaluates, on a periodic real-space grid,
  *
- *   E[rho] = T_TF + T_vW + T_NL + E_H + int v_ext rho  (+ E_ion)
+ *   E[rho] = T_TF + T_vW + T_NL + E_H + E_xc + int v_ext rho  (+ E_ion)
  *
- * (eq. "efunc" without exchange-correlation) and its functional derivative
+ * (eq. "efunc"; E_xc the optional LDA term) and its functional derivative
  * v = dE/drho (eqs. "euler", "euler2a"), where T_NL is the Wang-Teter
  * functional (eq. "WT") or the density-dependent-kernel functional evaluated
  * with linear splines over k_F knots (steps s1-s4 of Section
@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 5
+#define OFDFT_ABI_VERSION 6
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
@@ -82,7 +82,18 @@ enum {
 };
 enum { OFDFT_KNOTS_LOG = 0, OFDFT_KNOTS_LIN = 1 };
 enum { OFDFT_NL_S3S4 = 0, OFDFT_NL_EXACT = 1 };
-enum { OFDFT_FP64 = 0, OFDFT_MIXED = 1 };
+/* Precision.  FP64: every field, transform and reduction in FP64.
+ * MIXED: FP32 fields, transforms and pointwise terms; FP64 energy
+ * reductions, electron count, chemical potential and optimiser line search.
+ * MIXED_VW64: as MIXED, except that phi's transform pair behind the von
+ * Weizsaecker term runs in FP64 (FP32 input, FP64 spectrum, -lambda nabla^2
+ * phi returned to the FP32 combine).  v_vW divides that Laplacian by phi, so
+ * the FP32 transforms' absolute rounding (about 1e-7 of max |phi|) becomes
+ * a potential error of order 1e-5 / phi Ha: MIXED meets 1e-4 Ha in
+ * max |dE/drho| where rho >~ 1e-3 (bulk cells), MIXED_VW64 down to
+ * rho = 1e-6 (cells with vacuum), at the cost of one FP64 transform pair.
+ * Fields passed as device pointers are FP32 in both mixed modes. */
+enum { OFDFT_FP64 = 0, OFDFT_MIXED = 1, OFDFT_MIXED_VW64 = 2 };
 
 /* Ionic structure factor S(G) = sum_a exp(-iG.R_a) behind v_ext(G) and the
  * Ewald reciprocal sum.  DIRECT: the exact sum (per-atom phase tables below
@@ -121,13 +132,25 @@ typedef struct {
     int32_t pme_order;
 } ofdft_cell_desc;
 
+/* Kernel family of the nonlocal term (WT and SPLINE alike).  WT: eq. "WT",
+ * omega = C_WT G_NL(q / (2 k_F)).  MGP, MGPA, MGPG: eq. "MGP",
+ * omega_{x,y} = omega_WT - x C_WT int_0^1 t^y d/dt G_NL(eta(q, t)) dt with
+ * (x, y) = (1, 5/6), (1/2, 5/6), (1, 5/3), read with eta(q, t) =
+ * q / (2 t^(1/3) k_F) (functional integration along the scaled density
+ * t rho; the paper defers eta(q, t) to a supplement).  As in step s2, the
+ * correction is evaluated once at fixed eta nodes (spacing 1/2048 up to
+ * eta = 4, then 1/16384 in 1/eta^2) and interpolated linearly; with SPLINE
+ * these are the LMGP functionals. */
+enum { OFDFT_KERNEL_WT = 0, OFDFT_KERNEL_MGP = 1, OFDFT_KERNEL_MGPA = 2, OFDFT_KERNEL_MGPG = 3 };
+
 /* Functional.  alpha and beta are the exponents of eq. "nl2"; the GPU path
  * requires alpha == beta.  kf_wt <= 0 selects (3 pi^2 nelec / V)^(1/3) for
  * the Wang-Teter kernel.  Spline knots (step s1): nk values from kf_min to
  * kf_max, geometric (LOG) or arithmetic (LIN), both ends included.
  * nl_mode S3S4 interpolates the per-knot potentials (steps s3, s4 as
  * printed); EXACT returns the functional derivative of the spline energy.
- * rho_floor (default 1e-12) bounds rho^(alpha-1) and 1/sqrt(rho). */
+ * rho_floor (default 1e-12) bounds rho^(alpha-1) and 1/sqrt(rho).
+ * nl_kernel is an OFDFT_KERNEL_* value (0, Wang-Teter, when zero-initialised). */
 typedef struct {
     uint32_t terms;
     double lambda_vw;
@@ -139,6 +162,7 @@ typedef struct {
     int32_t nl_mode;
     int32_t precision;
     double rho_floor;
+    int32_t nl_kernel;
 } ofdft_functional_desc;
 
 /* Energies (Ha).  mu = int v rho / int rho; resid_norm = sqrt(mean(R^2)) with
@@ -170,9 +194,10 @@ ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell,
                                    uint64_t *bytes);
 
 /* Builds the grid: reciprocal vectors, twiddle tables, the ionic structure
- * factor and v_ext(G) (exact direct sum over atoms, separable phases), the
- * Ewald energy E_ion, and device buffers for one density.  The descriptors
- * are copied. */
+ * factor and v_ext(G) (by the cell's sf_method: the exact direct sum --
+ * separable per-atom phases below 8192 atoms, a tiled sum from there on --
+ * or smooth PME), the Ewald energy E_ion, and device buffers for one
+ * density.  The descriptors are copied. */
 ofdft_status ofdft_grid_create(ofdft_ctx *ctx, const ofdft_cell_desc *cell,
                                const ofdft_functional_desc *func, ofdft_grid **out);
 void ofdft_grid_destroy(ofdft_grid *grid);
@@ -216,8 +241,14 @@ ofdft_status ofdft_fft_c2r_dev(ofdft_grid *grid, int32_t nbatch, const void *d_i
                                void *d_out, void *hip_stream);
 
 /* Forces on the ions (Ha/Bohr, natoms x 3 doubles) for the resident density:
- * Hellmann-Feynman electron-ion term -d/dR int v_ext rho at fixed rho plus
- * the Ewald ion-ion term. */
+ * F_a = -d(E_ext + E_ion)/dR_a at fixed rho, i.e. the Hellmann-Feynman
+ * electron-ion term of the int v_ext rho energy of eq. "efunc" (v_ext the
+ * sum of the atoms' local pseudopotentials, Section "DFTpy classes", the
+ * IONS functional) plus the Ewald ion-ion term.  This is the force the
+ * paper's ASE calculator hands to molecular dynamics (Section "Other
+ * Classes and APIs", the DFTpyCalculator; Section "DFTpy+ASE: Dynamics of
+ * liquid aluminum") and is exact at the optimised density.  Not offered from
+ * 8192 atoms on or with sf_method PME (OFDFT_EINVAL). */
 ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host);
 
 /* Density optimisation (Section "Density optimization strategies"):
@@ -401,6 +432,7 @@ enum {
     OFDFT_PASS_EXACT_ACC,     /* spline EXACT: sum_i omega_i F[rho^a L_i]       */
     OFDFT_PASS_FINALIZE,      /* FP64 reductions                                */
     OFDFT_PASS_OTHER,         /* optimiser vector kernels                       */
+    OFDFT_PASS_VW64,          /* the FP64 von Weizsaecker leg of MIXED_VW64     */
     OFDFT_NPASS
 };
 ofdft_status ofdft_profile_enable(ofdft_grid *grid, int32_t on);

@@ -80,6 +80,7 @@ class Functional:
     knot_spacing: int = KNOTS_LOG
     nl_mode: int = NL_S3S4
     rho_floor: float = 1e-12
+    nl_kernel: int = 0             # 0 WT; 1 MGP, 2 MGPA, 3 MGPG (oracle.mgp)
 
 
 def mvals(n):

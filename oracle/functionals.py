@@ -138,6 +138,15 @@ def wt_kernel(gnorm, kf):
     return C_WT * gnl(np.asarray(gnorm) / (2.0 * kf))
 
 
+def nl_kernel(gnorm, kf, kind):
+    """The nonlocal kernel omega(|G|; k_F) of the selected family: Wang-Teter
+    (eq. "WT") or one of MGP / MGPA / MGPG (eq. "MGP", oracle.mgp)."""
+    if kind == 0:
+        return wt_kernel(gnorm, kf)
+    from . import mgp
+    return mgp.kernel(gnorm, kf, kind)
+
+
 # ---------------------------------------------------------------------------
 # External potential through the ionic structure factor
 # ---------------------------------------------------------------------------
@@ -307,8 +316,9 @@ def energy_potential(cell, func, rho=None, phi=None, vext=None, e_ion=None):
     a, b = func.alpha, func.beta
     if terms & C.WT:
         # Wang-Teter: T_NL = int rho^a (omega * rho^b), eqs. "nl2", "WT",
-        # kernel at the average k_F of the cell.
-        w = wt_kernel(gn, _kf_wt(cell, func))
+        # kernel at the average k_F of the cell (or an MGP-family kernel,
+        # eq. "MGP", at the same k_F).
+        w = nl_kernel(gn, _kf_wt(cell, func), func.nl_kernel)
         phib = c2r(w * r2c(rho ** b), shape)
         phia = c2r(w * r2c(rho ** a), shape) if a != b else phib
         res.e_nl += dv * float(np.sum(rho ** a * phib))
@@ -346,7 +356,8 @@ def spline_nl(cell, func, rho, phi, gn, kernel=None):
 
     Energy (both modes):
         E = int rho^a(r) sum_i L_i(k~(r)) Phi_i(r),
-        Phi_i = F^-1[omega_i F[rho^b]],  omega_i(G) = C_WT G_NL(|G|/(2 k_i)),
+        Phi_i = F^-1[omega_i F[rho^b]],  omega_i(G) = C_WT G_NL(|G|/(2 k_i))
+        (or the MGP-family kernel at k_i: the LMGP functionals),
     with k~ = clamp((3 pi^2 rho)^(1/3), k_1, k_Nk) and L_i the piecewise-linear
     hat functions of k on the knots of step s1.
 
@@ -379,7 +390,7 @@ def spline_nl(cell, func, rho, phi, gn, kernel=None):
     v3 = np.zeros(shape)   # sum_i L_i Psi_i (S3S4 with a != b)
     hsum = None
     for i in range(nk):
-        w = C_WT * gnl(gn / (2.0 * kn[i])) if kernel is None else kernel(gn, kn[i])
+        w = nl_kernel(gn, kn[i], func.nl_kernel) if kernel is None else kernel(gn, kn[i])
         phi_i = c2r(w * rb_g, shape)
         if nk == 1:
             L = np.ones(shape)

@@ -73,6 +73,7 @@ enum Pass {
     PS_EXACT_ACC,
     PS_FINALIZE,
     PS_OTHER,
+    PS_VW64,
     NPASS
 };
 
@@ -108,6 +109,12 @@ struct ofdft_grid {
     ofdft_functional_desc func;
     bool fp64 = true;
     size_t fsz = 8;
+    // OFDFT_MIXED_VW64: FP32 fields, with phi's transform pair (the von
+    // Weizsaecker term) in FP64 -- tables and workspace of that leg
+    bool vw64 = false;
+    void *tw0d = nullptr, *tw1d = nullptr, *twMd = nullptr, *twNd = nullptr;
+    void *vwspec = nullptr;   // cap * Nh complex FP64
+    void *vwout = nullptr;    // cap * N FP32: -lambda nabla^2 phi
     Geom geom;
     double frac[3][3];   // fractional coordinates s_j = sum_i frac[j][i] R_i
     double V = 0, dv = 0;
@@ -116,6 +123,11 @@ struct ofdft_grid {
     double *d_knots = nullptr;
     double kf_wt = 0;
     double e_ion = 0;
+    // nonlocal kernel family: x of eq. "MGP" (0 = Wang-Teter) and the J table
+    // (FP64 for the reciprocal-space table, field type for the knot kernels)
+    double mgp_x = 0;
+    double *d_jtab64 = nullptr;
+    void *d_jtab = nullptr;
     // device tables
     void *tw0 = nullptr, *tw1 = nullptr, *twM = nullptr, *twN = nullptr;
     void *vext = nullptr;
@@ -208,8 +220,38 @@ static std::vector<T> to_type(const double *src, size_t n)
     return v;
 }
 
-// twiddle table exp(-2 pi i n / L) for n < cnt, built in FP64, stored as field type
-static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt)
+// The MGP J table of exponent y (mgp_table.hpp), built once per process
+static const std::vector<double> &mgp_table_cached(double y)
+{
+    static std::mutex mu;
+    static std::map<double, std::vector<double>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(y);
+    if (it == cache.end()) it = cache.emplace(y, mgp_build_table(y)).first;
+    return it->second;
+}
+
+static bool mgp_params(int kernel, double &x, double &y)
+{
+    switch (kernel) {
+    case OFDFT_KERNEL_MGP: x = 1.0; y = 5.0 / 6.0; return true;
+    case OFDFT_KERNEL_MGPA: x = 0.5; y = 5.0 / 6.0; return true;
+    case OFDFT_KERNEL_MGPG: x = 1.0; y = 5.0 / 3.0; return true;
+    default: x = 0.0; y = 0.0; return false;
+    }
+}
+
+static NlKern nl_kern(const ofdft_grid *g, bool fp64_table)
+{
+    NlKern k;
+    k.x = g->mgp_x;
+    k.tab = fp64_table ? (const void *)g->d_jtab64 : g->d_jtab;
+    return k;
+}
+
+// twiddle table exp(-2 pi i n / L) for n < cnt, built in FP64, stored as
+// field type (or as FP64 for the von Weizsaecker leg of a mixed grid)
+static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt, bool as_fp64)
 {
     std::vector<double> t(2 * (size_t)cnt);
     for (int i = 0; i < cnt; ++i) {
@@ -217,8 +259,8 @@ static ofdft_status upload_twiddles(ofdft_grid *g, void **dst, int L, int cnt)
         t[2 * i] = std::cos(a);
         t[2 * i + 1] = -std::sin(a);
     }
-    ST_TRY(dmalloc(g, dst, (size_t)cnt * 2 * g->fsz));
-    if (g->fp64) {
+    ST_TRY(dmalloc(g, dst, (size_t)cnt * 2 * (as_fp64 ? 8 : 4)));
+    if (as_fp64) {
         ST_TRY(h2d(g, *dst, t.data(), t.size() * 8));
     } else {
         auto f = to_type<float>(t.data(), t.size());
@@ -458,7 +500,15 @@ static int max_pstride(const Geom &G, bool fp64)
 // holds and to size a request before any allocation.
 struct BytesModel {
     bool stage = false, opt = false, forces = false;
+    bool vw64 = false;   // FP32 grid with the FP64 von Weizsaecker leg
+    bool mgp = false;    // MGP-family kernel table
 };
+// partial-sum rows: the block counts of the grid's own kernels, and of the
+// FP64 passes of a mixed grid's von Weizsaecker leg
+static int pstride_of(const Geom &G, bool fp64, bool vw64)
+{
+    return vw64 ? std::max(max_pstride(G, false), max_pstride(G, true)) : max_pstride(G, fp64);
+}
 static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, int sf_method,
                             uint32_t terms, int nl_mode, int nk, uint64_t cap, uint64_t ions,
                             BytesModel m)
@@ -473,6 +523,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     b += ions;                                                          // coordinates, Ewald
     b += (uint64_t)natoms * 4 + (uint64_t)(nspecies + 1) * 4 + 2 * (uint64_t)nspecies * 8;
     b += (uint64_t)nk * 8;                                              // knots
+    if (m.mgp) b += (uint64_t)MGP_TAB * (fsz == 8 ? 8 : 12);           // J tables
     b += N * fsz;                                                       // resident rho
     b += 4 * cap * Nh * cb;                                             // spectra
     if (terms & OFDFT_TERM_SPLINE) {
@@ -480,7 +531,11 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
         b += cap * N * fsz;                                             // accumulator
         if (nl_mode == OFDFT_NL_EXACT) b += cap * N * fsz;
     }
-    b += cap * NSLOT * (uint64_t)max_pstride(G, fsz == 8) * 8 + cap * NSLOT * 8;   // partials
+    b += cap * NSLOT * (uint64_t)pstride_of(G, fsz == 8, m.vw64) * 8 + cap * NSLOT * 8;   // partials
+    if (m.vw64) {
+        b += (uint64_t)(G.n0 + G.n1 + G.m + (G.m + 1)) * 16;         // FP64 twiddles
+        b += cap * Nh * 16 + cap * N * 4;                              // FP64 spectrum, result
+    }
     if (m.stage) b += 2 * N * fsz;
     if (m.opt) b += (uint64_t)NVEC_OPT * N * fsz;
     if (m.forces) b += (uint64_t)natoms * 3 * 8;
@@ -505,6 +560,8 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
     dfree(g->acc2);
     dfree(g->stage_in);
     dfree(g->stage_out);
+    dfree(g->vwspec);
+    dfree(g->vwout);
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -520,7 +577,11 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
         if (g->func.nl_mode == OFDFT_NL_EXACT)
             ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
     }
-    g->pstride = max_pstride(G, g->fp64);
+    if (g->vw64) {
+        ST_TRY(dmalloc(g, &g->vwspec, (size_t)nb * G.Nh * 16));
+        ST_TRY(dmalloc(g, &g->vwout, (size_t)nb * G.N * 4));
+    }
+    g->pstride = pstride_of(G, g->fp64, g->vw64);
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->part),
                    (size_t)nb * NSLOT * g->pstride * sizeof(double)));
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->sums), (size_t)nb * NSLOT * sizeof(double)));
@@ -541,7 +602,7 @@ static Layout layout_of(const ofdft_grid *g)
     const uint32_t t = g->func.terms;
     int idx = 0;
     if (t & (OFDFT_TERM_HARTREE | OFDFT_TERM_EXT)) l.s_rho = idx++;
-    if (t & OFDFT_TERM_VW) l.s_phi = idx++;
+    if ((t & OFDFT_TERM_VW) && !g->vw64) l.s_phi = idx++;   // else in the FP64 leg
     if (t & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) l.s_rhob = idx++;
     l.nfwd = idx;
     l.ninv = (t & OFDFT_TERM_SPLINE) ? idx - 1 : idx;
@@ -551,7 +612,8 @@ static Layout layout_of(const ofdft_grid *g)
 
 template <typename T>
 static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data, int nfb, int nbatch,
-                             int inv, const int *ops, int kind, double *part = nullptr)
+                             int inv, const int *ops, int kind, double *part = nullptr,
+                             const void *tw = nullptr)
 {
     const Geom &G = g->geom;
     ColArgs a;
@@ -580,14 +642,14 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
         a.inner = G.n2h;
         a.outer_stride = (long long)G.n1 * G.n2h;
         a.elem_stride = G.n2h;
-        a.tw = g->tw1;
+        a.tw = tw ? tw : g->tw1;
     } else {
         L = G.n0;
         a.ncols = (long long)G.n1 * G.n2h;
         a.inner = a.ncols;
         a.outer_stride = 0;
         a.elem_stride = (long long)G.n1 * G.n2h;
-        a.tw = g->tw0;
+        a.tw = tw ? tw : g->tw0;
         if (ops)
             for (int f = 0; f < 4; ++f) a.op[f] = ops[f];   // ops has 4 entries
     }
@@ -629,6 +691,8 @@ static ofdft_status ensure_lane(ofdft_grid *g)
 struct Work {
     char *spec, *kspec;
     void *acc1, *acc2;
+    char *vwspec;     // FP64 von Weizsaecker leg: spectrum and result
+    void *vwout;
     double *part, *sums, *h_sums;
 };
 
@@ -642,10 +706,64 @@ static Work work_of(const ofdft_grid *g, int b0)
     w.kspec = g->kspec ? (char *)g->kspec + (size_t)MAXKB * b0 * G.Nh * cb : nullptr;
     w.acc1 = g->acc1 ? (char *)g->acc1 + (size_t)b0 * G.N * sizeof(T) : nullptr;
     w.acc2 = g->acc2 ? (char *)g->acc2 + (size_t)b0 * G.N * sizeof(T) : nullptr;
+    w.vwspec = g->vwspec ? (char *)g->vwspec + (size_t)b0 * G.Nh * 16 : nullptr;
+    w.vwout = g->vwout ? (char *)g->vwout + (size_t)b0 * G.N * 4 : nullptr;
     w.part = g->part + (size_t)b0 * NSLOT * g->pstride;
     w.sums = g->sums + (size_t)b0 * NSLOT;
     w.h_sums = g->h_sums + (size_t)b0 * NSLOT;
     return w;
+}
+
+// The von Weizsaecker term of a mixed grid in FP64 (OFDFT_MIXED_VW64): phi
+// from the FP32 input (or sqrt of the FP32 rho) through the FP64 row and
+// column passes, lambda G^2 phi(G) with the FP64 energy partial SL_VW on
+// axis 0, the inverse passes, and w = -lambda nabla^2 phi stored as FP32 for
+// the combine, which divides it by phi.  The transforms' rounding then stays
+// about 1e-16 of max |phi| instead of 1e-7, so v_vW = w / (2 phi) keeps its
+// accuracy where phi is small (vacuum).  Returns the axis-0 block count
+// (the number of SL_VW partials).
+static ofdft_status vw_leg(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, hipStream_t s,
+                           const Work &w, int &nb_vw)
+{
+    const Geom &G = g->geom;
+    RowFwdArgs rf;
+    std::memset(&rf, 0, sizeof(rf));
+    rf.in = d_in;
+    rf.in_f32 = 1;
+    rf.out = w.vwspec;
+    rf.out_fstride = (long long)nb * G.Nh;
+    rf.nfields = 1;
+    rf.kind[0] = FK_PHI;
+    rf.in_is_phi = in_is_phi;
+    rf.partials = 0;
+    rf.part = w.part;
+    rf.pstride = g->pstride;
+    rf.twM = g->twMd;
+    rf.twN = g->twNd;
+    rf.tw1 = g->tw1d;
+    int nbr = 0;
+    TIMED(PS_VW64, launch_row_fwd<double>(G, nb, rf, nbr, s));
+    ST_TRY(col_pass<double>(g, s, 1, w.vwspec, nb, nb, 0, nullptr, PS_VW64, w.part, g->tw1d));
+    const int ops[4] = {GO_VW, 0, 0, 0};
+    ST_TRY(col_pass<double>(g, s, 0, w.vwspec, nb, nb, 0, ops, PS_VW64, w.part, g->tw0d));
+    ST_TRY(col_pass<double>(g, s, 1, w.vwspec, nb, nb, 1, nullptr, PS_VW64, w.part, g->tw1d));
+    RowInvArgs ri;
+    std::memset(&ri, 0, sizeof(ri));
+    ri.spec = w.vwspec;
+    ri.spec_fstride = (long long)nb * G.Nh;
+    ri.nfields = 1;
+    ri.mode = EP_STORE;
+    ri.out = w.vwout;
+    ri.out_f32 = 1;
+    ri.nbatch = nb;
+    ri.twM = g->twMd;
+    ri.twN = g->twNd;
+    ri.tw1 = g->tw1d;
+    ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
+    int nbi = 0;
+    TIMED(PS_VW64, launch_row_inv<double>(G, ri, nbi, s));
+    nb_vw = col_blocks<double>(G.n0, (long long)G.n1 * G.n2h);
+    return OFDFT_OK;
 }
 
 template <typename T>
@@ -691,6 +809,8 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     int nb_row = 0;
     if (plane) TIMED(PS_ROW_FWD, launch_plane_fwd<T>(G, nb, rf, nb_row, s));
     else TIMED(PS_ROW_FWD, launch_row_fwd<T>(G, nb, rf, nb_row, s));
+    int nb_vw = 0;
+    if (g->vw64) ST_TRY(vw_leg(g, nb, d_in, in_is_phi, s, w, nb_vw));
     if (g->stagger_after_fwd) HIP_TRY(hipEventRecord(g->ev_stagger, s));
 
     int nb_col0 = 0;
@@ -723,6 +843,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ka.K = K;
             ka.nbatch = nb;
             ka.knots = g->knots;
+            ka.kern = nl_kern(g, false);
             ka.tw = g->tw0;
             ka.g = G;
             TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
@@ -795,6 +916,10 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rc.in_is_phi = in_is_phi;
     rc.fld_hext = l.s_rho;
     rc.fld_vw = l.s_phi;
+    if (g->vw64) {
+        rc.fld_vw = 0;   // present; its values come from the FP64 leg
+        rc.vw_field = w.vwout;
+    }
     rc.fld_wt = (terms & OFDFT_TERM_WT) ? l.s_rhob : -1;
     rc.fld_a = l.s_h;
     rc.use_tf = (terms & OFDFT_TERM_TF) ? 1 : 0;
@@ -815,7 +940,9 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     rc.twM = g->twM;
     rc.twN = g->twN;
     rc.tw1 = g->tw1;
-    rc.cf = combine_flavour(rc);
+    // the fixed term sets have no real-space vW input: the FP64 leg's result
+    // goes through the general combine
+    rc.cf = g->vw64 ? 0 : combine_flavour(rc);
     int nb_inv = 0;
     if (plane) TIMED(PS_ROW_INV, launch_plane_inv<T>(G, rc, nb_inv, s));
     else TIMED(PS_ROW_INV, launch_row_inv<T>(G, rc, nb_inv, s));
@@ -825,7 +952,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     std::memset(&cnt, 0, sizeof(cnt));
     cnt.n[SL_RHO] = cnt.n[SL_TF] = cnt.n[SL_BAD] = nb_row;
     cnt.n[SL_H] = cnt.n[SL_EXT] = (l.s_rho >= 0) ? nb_col0 : 0;
-    cnt.n[SL_VW] = (l.s_phi >= 0) ? nb_col0 : 0;
+    cnt.n[SL_VW] = g->vw64 ? nb_vw : ((l.s_phi >= 0) ? nb_col0 : 0);
     cnt.n[SL_NL] = cnt.n[SL_GPHI] = cnt.n[SL_GG] = cnt.n[SL_PHIPHI] = nb_inv;
     cnt.n[SL_XC] = (terms & OFDFT_TERM_XC) ? nb_inv : 0;   // written by the LDA combines only
     TIMED(PS_FINALIZE, launch_finalize(w.part, g->pstride, cnt, nb, w.sums, s));
@@ -1088,6 +1215,8 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
         return fail(OFDFT_EINVAL, "the GPU path requires alpha == beta");
     if ((f->terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) && !(f->alpha > 0.5))
         return fail(OFDFT_EINVAL, "alpha must exceed 1/2");
+    if (f->nl_kernel < OFDFT_KERNEL_WT || f->nl_kernel > OFDFT_KERNEL_MGPG)
+        return fail(OFDFT_EINVAL, "unknown nl_kernel");
     if (f->terms & OFDFT_TERM_SPLINE) {
         if (f->nk < 1 || f->nk > MAXKNOTS) return fail(OFDFT_EINVAL, "nk out of range");
         if (!(f->kf_min > 0) || !(f->kf_max >= f->kf_min) || (f->nk > 1 && !(f->kf_max > f->kf_min)))
@@ -1095,7 +1224,8 @@ static ofdft_status validate(const ofdft_cell_desc *c, const ofdft_functional_de
         if (f->nl_mode != OFDFT_NL_S3S4 && f->nl_mode != OFDFT_NL_EXACT)
             return fail(OFDFT_EINVAL, "bad nl_mode");
     }
-    if (f->precision != OFDFT_FP64 && f->precision != OFDFT_MIXED)
+    if (f->precision != OFDFT_FP64 && f->precision != OFDFT_MIXED &&
+        f->precision != OFDFT_MIXED_VW64)
         return fail(OFDFT_EINVAL, "bad precision");
     if (!(f->rho_floor > 0)) return fail(OFDFT_EINVAL, "rho_floor must be positive");
     return OFDFT_OK;
@@ -1110,6 +1240,12 @@ static void grid_free(ofdft_grid *g)
     dfree(g->tw1);
     dfree(g->twM);
     dfree(g->twN);
+    dfree(g->tw0d);
+    dfree(g->tw1d);
+    dfree(g->twMd);
+    dfree(g->twNd);
+    dfree(g->vwspec);
+    dfree(g->vwout);
     dfree(g->vext);
     dfree(g->gtab);
     dfree(reinterpret_cast<void *&>(g->ph0));
@@ -1120,6 +1256,9 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_Z));
     dfree(reinterpret_cast<void *&>(g->d_rc));
     dfree(reinterpret_cast<void *&>(g->d_knots));
+    if (g->d_jtab != (void *)g->d_jtab64) dfree(g->d_jtab);
+    g->d_jtab = nullptr;
+    dfree(reinterpret_cast<void *&>(g->d_jtab64));
     dfree(g->spec);
     dfree(g->kspec);
     dfree(g->acc1);
@@ -1491,6 +1630,7 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     g->func = *f;
     g->fp64 = f->precision == OFDFT_FP64;
     g->fsz = g->fp64 ? 8 : 4;
+    g->vw64 = f->precision == OFDFT_MIXED_VW64 && (f->terms & OFDFT_TERM_VW);
 
     // geometry: b_j with a_i . b_j = 2 pi delta_ij  (b = 2 pi inv(A)^T)
     const double(*A)[3] = g->lattice;
@@ -1533,11 +1673,33 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     }
     g->kf_wt = f->kf_wt > 0 ? f->kf_wt : std::cbrt(3.0 * PI * PI * g->nelec / g->V);
 
+    // MGP-family kernel: the J table in FP64 and in the field type
+    double mx = 0.0, my = 0.0;
+    if ((f->terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) && mgp_params(f->nl_kernel, mx, my)) {
+        const std::vector<double> &tab = mgp_table_cached(my);
+        g->mgp_x = mx;
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_jtab64), tab.size() * 8));
+        ST_TRY(h2d(g, g->d_jtab64, tab.data(), tab.size() * 8));
+        if (g->fp64) {
+            g->d_jtab = g->d_jtab64;
+        } else {
+            auto tf = to_type<float>(tab.data(), tab.size());
+            ST_TRY(dmalloc(g, &g->d_jtab, tf.size() * 4));
+            ST_TRY(h2d(g, g->d_jtab, tf.data(), tf.size() * 4));
+        }
+    }
+
     // twiddles
-    ST_TRY(upload_twiddles(g, &g->tw0, G.n0, G.n0));
-    ST_TRY(upload_twiddles(g, &g->tw1, G.n1, G.n1));
-    ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m));
-    ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1));
+    ST_TRY(upload_twiddles(g, &g->tw0, G.n0, G.n0, g->fp64));
+    ST_TRY(upload_twiddles(g, &g->tw1, G.n1, G.n1, g->fp64));
+    ST_TRY(upload_twiddles(g, &g->twM, G.m, G.m, g->fp64));
+    ST_TRY(upload_twiddles(g, &g->twN, G.n2, G.m + 1, g->fp64));
+    if (g->vw64) {
+        ST_TRY(upload_twiddles(g, &g->tw0d, G.n0, G.n0, true));
+        ST_TRY(upload_twiddles(g, &g->tw1d, G.n1, G.n1, true));
+        ST_TRY(upload_twiddles(g, &g->twMd, G.m, G.m, true));
+        ST_TRY(upload_twiddles(g, &g->twNd, G.n2, G.m + 1, true));
+    }
 
 
     for (int j = 0; j < 3; ++j)
@@ -1545,8 +1707,8 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
     ST_TRY(setup_ions(g));
     ST_TRY(dmalloc(g, &g->gtab, 3 * (size_t)G.Nh * g->fsz));
     hipStream_t s = g->ctx->stream;
-    HIP_TRY(g->fp64 ? launch_gtab<double>(G, g->kf_wt, g->gtab, s)
-                    : launch_gtab<float>(G, g->kf_wt, g->gtab, s));
+    HIP_TRY(g->fp64 ? launch_gtab<double>(G, g->kf_wt, nl_kern(g, true), g->gtab, s)
+                    : launch_gtab<float>(G, g->kf_wt, nl_kern(g, true), g->gtab, s));
     HIP_TRY(hipStreamSynchronize(s));
     ST_TRY(dmalloc(g, &g->rho, (size_t)G.N * g->fsz));
     return OFDFT_OK;
@@ -2012,7 +2174,8 @@ static std::map<TuneKey, TuneVal> g_tune_cache;
 
 static TuneKey tune_key(const ofdft_grid *g, int nb)
 {
-    return TuneKey(g->n[0], g->n[1], g->n[2], g->fp64 ? 1 : 0, g->func.terms, g->func.nl_mode,
+    return TuneKey(g->n[0], g->n[1], g->n[2], g->func.precision,
+                   g->func.terms | ((uint32_t)g->func.nl_kernel << 16), g->func.nl_mode,
                    (g->func.terms & OFDFT_TERM_SPLINE) ? g->func.nk : 0, nb);
 }
 
@@ -2478,6 +2641,8 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     m.stage = grid->stage_in != nullptr || grid->stage_out != nullptr;
     m.opt = grid->opt[0] != nullptr;
     m.forces = grid->d_forces != nullptr;
+    m.vw64 = grid->vw64;
+    m.mgp = grid->d_jtab64 != nullptr;
     uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
                              grid->sf_method, grid->func.terms, grid->func.nl_mode,
                              (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
@@ -2507,6 +2672,9 @@ ofdft_status ofdft_footprint_bytes(const ofdft_cell_desc *cell, const ofdft_func
     m.stage = true;
     m.opt = kind == OFDFT_REQ_OPTIMIZE;
     m.forces = kind == OFDFT_REQ_FORCES;
+    m.vw64 = func->precision == OFDFT_MIXED_VW64 && (func->terms & OFDFT_TERM_VW);
+    m.mgp = (func->terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) &&
+            func->nl_kernel != OFDFT_KERNEL_WT;
     *bytes = bytes_model(G, func->precision == OFDFT_FP64 ? 8 : 4, cell->natoms, cell->nspecies,
                          cell->sf_method, func->terms, func->nl_mode,
                          (func->terms & OFDFT_TERM_SPLINE) ? func->nk : 0, 1,

@@ -39,9 +39,10 @@ hipError_t launch_finalize(const double *part, int pstride, const SlotCounts &co
 
 // ---------------------------------------------------------------- G tables
 // tab[e] = 1/G^2 (0 at G = 0), tab[Nh + e] = G^2,
-// tab[2 Nh + e] = C_WT G_NL(|G| / (2 kf)) for half-spectrum point e, in FP64.
+// tab[2 Nh + e] = C_WT K(|G| / (2 kf)) for half-spectrum point e (K = G_NL for
+// Wang-Teter, the MGP-family kernel otherwise), in FP64.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_gtab(Geom g, double kf, T *tab)
+__global__ __launch_bounds__(NT) void k_gtab(Geom g, double kf, NlKern kern, T *tab)
 {
     const long long e = (long long)blockIdx.x * NT + threadIdx.x;
     if (e >= g.Nh) return;
@@ -52,18 +53,18 @@ __global__ __launch_bounds__(NT) void k_gtab(Geom g, double kf, T *tab)
     const double G2 = gvec2<double>(g, freq(i0, g.n0), freq(i1, g.n1), m2);
     tab[e] = T(G2 > 0.0 ? 1.0 / G2 : 0.0);
     tab[g.Nh + e] = T(G2);
-    tab[2 * g.Nh + e] = T(C_WT_D * gnl_dev<double>(sqrt(G2) / (2.0 * kf)));
+    tab[2 * g.Nh + e] = T(C_WT_D * nl_kernel_dev<double>(sqrt(G2) / (2.0 * kf), kern));
 }
 
 template <typename T>
-hipError_t launch_gtab(const Geom &g, double kf_wt, void *gtab, hipStream_t s)
+hipError_t launch_gtab(const Geom &g, double kf_wt, const NlKern &kern, void *gtab, hipStream_t s)
 {
     const long long nb = (g.Nh + NT - 1) / NT;
-    hipLaunchKernelGGL((k_gtab<T>), dim3((unsigned)nb), dim3(NT), 0, s, g, kf_wt, (T *)gtab);
+    hipLaunchKernelGGL((k_gtab<T>), dim3((unsigned)nb), dim3(NT), 0, s, g, kf_wt, kern, (T *)gtab);
     return hipGetLastError();
 }
-template hipError_t launch_gtab<float>(const Geom &, double, void *, hipStream_t);
-template hipError_t launch_gtab<double>(const Geom &, double, void *, hipStream_t);
+template hipError_t launch_gtab<float>(const Geom &, double, const NlKern &, void *, hipStream_t);
+template hipError_t launch_gtab<double>(const Geom &, double, const NlKern &, void *, hipStream_t);
 
 // ---------------------------------------------------------------- v_ext(G)
 // v_ext(G) = (1/V) sum_s v_s(|G|) sum_{a in s} e^{-i G.R_a}; the phase is the

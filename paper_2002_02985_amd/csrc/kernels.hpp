@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "mgp_table.hpp"
+
 namespace ofdft {
 
 // partial-sum slots (FP64), one row of per-workgroup partials per slot
@@ -46,6 +48,15 @@ struct Geom {
     double invN;
 };
 
+// Nonlocal kernel family (eq. "WT" or eq. "MGP"): omega = C_WT K(eta),
+// K = G_NL for Wang-Teter (x = 0), K = (1 - x) G_NL + x J for MGP / MGPA / MGPG,
+// J linearly interpolated on the table built in mgp_table.hpp (device copy in
+// the kernel's field type; k_gtab reads an FP64 copy).
+struct NlKern {
+    double x;                   // 0: Wang-Teter
+    const void *tab;            // MGP_TAB values of J
+};
+
 // k_F knots: the values live in device memory (kernels index them with
 // data-dependent brackets, which must not pull a table into registers)
 struct Knots {
@@ -74,6 +85,8 @@ struct RowFwdArgs {
     const void *twM;            // W_M^n, n < M
     const void *twN;            // W_{n2}^k, k <= M
     const void *tw1;            // W_{n1}^n (plane kernels)
+    int in_f32;                 // FP64 kernels: the input is FP32 (the FP64 von
+                                // Weizsaecker leg of a mixed-precision grid)
 };
 
 // strided column pass along axis 1 or 0 (c2c), optionally with a fused
@@ -87,7 +100,7 @@ struct ColArgs {
     int nbatch;                 // field = blockIdx.y / nbatch
     int op[MAXKB];              // per field op (axis 0 only; zero elsewhere)
     const void *vext;           // half spectrum, field type (GO_HEXT)
-    const void *gtab;           // [1/G^2 | G^2 | omega_WT(G)], 3 x Nh values (field type)
+    const void *gtab;           // [1/G^2 | G^2 | omega(G)], 3 x Nh values (field type)
     int tile_major;             // block order: 1 tile-major, 0 array-major
     int use_h, use_ext;
     double lambda_vw;
@@ -111,6 +124,7 @@ struct KnotArgs {
     Knots knots;
     const void *tw;
     Geom g;
+    NlKern kern;                // kernel family at each knot (tab in field type)
 };
 
 // inverse row pass: axis-2 c2r of up to 4 fields, then a plain store, the
@@ -138,6 +152,10 @@ struct RowInvArgs {
     const void *twM, *twN;
     const void *tw1;            // W_{n1}^n (plane kernels)
     int cf;                     // EP_COMBINE: a fixed term set CF_* below, or 0
+    int out_f32;                // EP_STORE of FP64 kernels: out holds FP32 values
+    const void *vw_field;       // EP_COMBINE with cf = 0: -lambda nabla^2 phi as a real
+                                // field (nbatch x N, field type) computed elsewhere (the
+                                // FP64 leg of a mixed grid); fld_vw's spectrum is then unused
 };
 
 // Term sets of the final combine that have kernels specialised at compile
@@ -171,9 +189,10 @@ template <typename T> int row_blocks(const Geom &g);
 template <typename T> int col_blocks(int L, long long ncols);
 
 // reciprocal-space tables of a grid: 1/G^2 (0 at G = 0), G^2 and the
-// Wang-Teter kernel C_WT G_NL(|G|/(2 kf)) on the half spectrum, built in FP64
+// nonlocal kernel C_WT K(|G|/(2 kf)) on the half spectrum, built in FP64
+// (kern.tab: the FP64 J table)
 template <typename T>
-hipError_t launch_gtab(const Geom &g, double kf_wt, void *gtab, hipStream_t s);
+hipError_t launch_gtab(const Geom &g, double kf_wt, const NlKern &kern, void *gtab, hipStream_t s);
 
 // FP64 reductions: sums[b][s] = sum_{i < count.n[s]} part[b][s][i]; the
 // counts travel as a kernel argument (the launch sequence of an evaluation

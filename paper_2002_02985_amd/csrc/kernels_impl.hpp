@@ -179,6 +179,33 @@ __device__ __forceinline__ T gnl_dev(T eta)
     return T(-1) - S * d_rcp(P);
 }
 
+// K(eta) of the kernel family (omega = C_WT K): G_NL for Wang-Teter; for the
+// MGP family (1 - x) G_NL + x J with J interpolated linearly on its table
+// (in eta up to 4, in w = 1/eta^2 above; the node rule of mgp_table.hpp)
+template <typename T>
+__device__ __forceinline__ T nl_kernel_dev(T eta, const NlKern &k)
+{
+    if (k.x == 0.0) return gnl_dev<T>(eta);
+    const T *tab = (const T *)k.tab;
+    T j;
+    if (eta <= T(4)) {
+        const T s = eta * T(MGP_SA);
+        int i = (int)s;
+        i = i > MGP_NA - 1 ? MGP_NA - 1 : i;
+        const T f = s - T(i);
+        j = tab[i] + f * (tab[i + 1] - tab[i]);
+    } else {
+        const T s = d_rcp(eta * eta) * T(MGP_SB);
+        int i = (int)s;
+        i = i > MGP_NB - 1 ? MGP_NB - 1 : i;
+        const T f = s - T(i);
+        const T *tb = tab + MGP_NA + 1;
+        j = tb[i] + f * (tb[i + 1] - tb[i]);
+    }
+    const T x = T(k.x);
+    return k.x == 1.0 ? j : (T(1) - x) * gnl_dev<T>(eta) + x * j;
+}
+
 // k_F = (3 pi^2 rho)^(1/3), clamped to the knot range; bracket j and linear
 // weight t on the knots (step s4).  An exact knot belongs to the segment on
 // its right; the last knot to the last segment with t = 1.
@@ -274,12 +301,30 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
         if (idx < PAIRS) {
             const int p = idx / M, n = idx % M;
             const long long row = r0 + p;
-            if (row < nrows) x[q] = ((const cpx<T> *)(in + row * g.n2))[n];
+            if (row < nrows) {
+                if constexpr (sizeof(T) == 8) {
+                    if (a.in_f32) {
+                        // FP32 input of the FP64 von Weizsaecker leg
+                        const float2 v = ((const float2 *)((const float *)a.in +
+                                                           (long long)b * g.N + row * g.n2))[n];
+                        x[q] = {T(v.x), T(v.y)};
+                    } else {
+                        x[q] = ((const cpx<T> *)(in + row * g.n2))[n];
+                    }
+                } else {
+                    x[q] = ((const cpx<T> *)(in + row * g.n2))[n];
+                }
+            }
         }
     }
     // derived values: u = rho, w = phi, z = rho^beta  (or, for knot fields,
     // u = rho^alpha, w = t, jj = bracket)
     const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
+    // FP64 passes that need neither the partials nor rho^beta nor the knot
+    // weights (the von Weizsaecker leg: phi only) skip the FP64 logarithm
+    // and exponential; FP32 passes always evaluate them
+    bool need_lu = sizeof(T) == 4 || a.partials || knots;
+    for (int f = 0; f < a.nfields; ++f) need_lu |= a.kind[f] == FK_RHOB;
     cpx<T> u[PER], w[PER], z[PER];
     int jj[PER][2];
     double sums[3] = {0.0, 0.0, 0.0};   // sum rho, sum rho^(5/3), bad count
@@ -294,7 +339,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             const T v = xv[c];
             const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
             const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
-            const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+            const T lu = (need_lu && rho > T(0)) ? d_log2(rho) : neg_inf<T>();
             if (live && a.partials) {
                 if (!ok) {
                     sums[2] += 1.0;
@@ -313,7 +358,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             } else {
                 uu[c] = a.in_is_phi ? v * v : v;
                 ww[c] = a.in_is_phi ? v : d_sqrt(rho);
-                zz[c] = d_exp2(T(a.beta) * lu);
+                zz[c] = need_lu ? d_exp2(T(a.beta) * lu) : T(0);
             }
         }
         u[q] = {uu[0], uu[1]};
@@ -568,7 +613,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int n = tid / P + q * RSTEP;
-            if (n < L) buf[n * P + p] = cscale(xs[q], T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k));
+            if (n < L) buf[n * P + p] = cscale(xs[q], T(C_WT_D) * nl_kernel_dev<T>(gn[q] * inv2k, a.kern));
         }
         __syncthreads();
         // the last stage writes this thread's column (pencil p) to memory
@@ -623,7 +668,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
         for (int q = 0; q < PER; ++q) {
             const int n = tid / P + q * RSTEP;
             if (n < L) {
-                const T w = T(C_WT_D) * gnl_dev<T>(gn[q] * inv2k) * invN;
+                const T w = T(C_WT_D) * nl_kernel_dev<T>(gn[q] * inv2k, a.kern) * invN;
                 const cpx<T> v = buf[n * P + p];
                 acc[q].x += w * v.x;
                 acc[q].y += w * v.y;
@@ -972,10 +1017,28 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     if constexpr (MODE == EP_STORE) {
         for (int f = 0; f < a.nfields; ++f) {
             c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
-            T *out = (T *)a.out + ((long long)f * a.nbatch + b) * g.N;
+            const long long fo = ((long long)f * a.nbatch + b) * g.N;
+            bool done = false;
+            if constexpr (sizeof(T) == 8) {
+                if (a.out_f32) {
+                    // the FP64 von Weizsaecker leg hands its result to the
+                    // FP32 combine
+                    float *outf = (float *)a.out + fo;
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (valid[q]) *(cpx<T> *)(out + offs[q]) = buf[lds_at[q]];
+                    for (int q = 0; q < PER; ++q)
+                        if (valid[q]) {
+                            const cpx<T> v = buf[lds_at[q]];
+                            *(float2 *)(outf + offs[q]) = make_float2((float)v.x, (float)v.y);
+                        }
+                    done = true;
+                }
+            }
+            if (!done) {
+                T *out = (T *)a.out + fo;
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    if (valid[q]) *(cpx<T> *)(out + offs[q]) = buf[lds_at[q]];
+            }
             __syncthreads();
         }
         return;
@@ -1052,7 +1115,10 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     cpx<T> fh[PER], fl[PER], fn[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) fh[q] = fl[q] = fn[q] = {T(0), T(0)};
-    const int flds[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+    // with vw_field set (general combine only: the host picks CF = 0 for it)
+    // the von Weizsaecker term arrives in real space
+    const bool vwf = CF == 0 && a.vw_field != nullptr;
+    const int flds[4] = {a.fld_hext, vwf ? -1 : a.fld_vw, a.fld_wt, a.fld_a};
     for (int s = 0; s < 4; ++s) {
         if (flds[s] < 0) continue;
         c2r_rows<T, M, P, PS>(buf, spec_of(flds[s]), r0, nrows, g.n2h, twM, twN, tid);
@@ -1065,6 +1131,14 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
             else fn[q] = z;   // WT Phi or the EXACT field A (exclusive)
         }
         __syncthreads();
+    }
+    if constexpr (CF == 0) {
+        if (vwf) {
+            const T *vw = (const T *)a.vw_field + (long long)b * g.N;
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (valid[q]) fl[q] = *(const cpx<T> *)(vw + offs[q]);
+        }
     }
     const T *acc1 = a.spline ? (const T *)a.acc1 + (long long)b * g.N : nullptr;
     const T *acc2 = (a.spline && a.exact) ? (const T *)a.acc2 + (long long)b * g.N : nullptr;
@@ -1431,7 +1505,10 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     __syncthreads();
     // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
     // A are exclusive and come last, so only H+ext and vW are ever held
-    const int all[4] = {a.fld_hext, a.fld_vw, a.fld_wt, a.fld_a};
+    // with vw_field set (general combine only: the host picks CF = 0 for it)
+    // the von Weizsaecker term arrives in real space
+    const bool vwf = CF == 0 && a.vw_field != nullptr;
+    const int all[4] = {a.fld_hext, vwf ? -1 : a.fld_vw, a.fld_wt, a.fld_a};
     int last = -1;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -1472,7 +1549,10 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         const cpx<T> xq = xs[idx];
         const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
         const cpx<T> zh = last == 0 ? zl : fh[q];
-        const cpx<T> zv = last == 1 ? zl : fv[q];
+        cpx<T> zv = last == 1 ? zl : fv[q];
+        if constexpr (CF == 0) {
+            if (vwf) zv = ((const cpx<T> *)((const T *)a.vw_field + real_off))[idx];
+        }
         cpx<T> vo, go;
         combine_point<T, CF>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x, sums);
         combine_point<T, CF>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y, sums);

@@ -61,7 +61,8 @@ bool same_functional(const ofdft_functional_desc &a, const ofdft_functional_desc
     return a.terms == b.terms && a.lambda_vw == b.lambda_vw && a.alpha == b.alpha &&
            a.beta == b.beta && a.kf_wt == b.kf_wt && a.nk == b.nk && a.kf_min == b.kf_min &&
            a.kf_max == b.kf_max && a.knot_spacing == b.knot_spacing && a.nl_mode == b.nl_mode &&
-           a.precision == b.precision && a.rho_floor == b.rho_floor;
+           a.precision == b.precision && a.rho_floor == b.rho_floor &&
+           a.nl_kernel == b.nl_kernel;
 }
 
 // Everything but the atom positions: a grid built for one serves the other.

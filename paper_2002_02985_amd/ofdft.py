@@ -19,12 +19,13 @@ TERM_TF, TERM_VW, TERM_HARTREE, TERM_EXT, TERM_WT, TERM_SPLINE = 1, 2, 4, 8, 16,
 TERM_XC = 64
 KNOTS_LOG, KNOTS_LIN = 0, 1
 NL_S3S4, NL_EXACT = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_VW64 = 0, 1, 2
 REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
 OPT_CG, OPT_PCG, OPT_TN = 0, 1, 2
 SF_DIRECT, SF_PME = 0, 1
+KERNEL_WT, KERNEL_MGP, KERNEL_MGPA, KERNEL_MGPG = 0, 1, 2, 3
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
-              "knot_row", "exact_fwd", "exact_acc", "finalize", "other"]
+              "knot_row", "exact_fwd", "exact_acc", "finalize", "other", "vw64"]
 
 
 class CellDesc(ctypes.Structure):
@@ -42,7 +43,7 @@ class FunctionalDesc(ctypes.Structure):
                 ("kf_wt", ctypes.c_double), ("nk", ctypes.c_int32), ("kf_min", ctypes.c_double),
                 ("kf_max", ctypes.c_double), ("knot_spacing", ctypes.c_int32),
                 ("nl_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("rho_floor", ctypes.c_double)]
+                ("rho_floor", ctypes.c_double), ("nl_kernel", ctypes.c_int32)]
 
 
 class Energy(ctypes.Structure):
@@ -237,7 +238,7 @@ def make_cell_desc(cell):
 
 def make_functional_desc(terms, precision=FP64, lambda_vw=1.0, alpha=5.0 / 6.0, beta=5.0 / 6.0,
                          kf_wt=0.0, nk=32, kf_min=0.1, kf_max=3.0, knot_spacing=KNOTS_LOG,
-                         nl_mode=NL_S3S4, rho_floor=1e-12):
+                         nl_mode=NL_S3S4, rho_floor=1e-12, nl_kernel=KERNEL_WT):
     f = FunctionalDesc()
     f.terms = int(terms)
     f.lambda_vw = lambda_vw
@@ -251,6 +252,7 @@ def make_functional_desc(terms, precision=FP64, lambda_vw=1.0, alpha=5.0 / 6.0, 
     f.nl_mode = nl_mode
     f.precision = precision
     f.rho_floor = rho_floor
+    f.nl_kernel = nl_kernel
     return f
 
 

@@ -149,6 +149,23 @@ CASES = {
     "spline_1024_axis1_s3s4": (lambda: (box((4, 1024, 8), L=(6.0, 300.0, 7.0), natoms=40), None),
                                LOCAL | ofdft.TERM_SPLINE,
                                dict(nk=9, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4)),
+    # MGP-family kernels (eq. "MGP"): the Wang-Teter-type functional at the
+    # cell's average k_F (fixed combine, plane path) and the LMGP spline
+    # functionals on the row path and the plane path
+    "c1_mgp": (lambda: c1_cell(), LOCAL | ofdft.TERM_WT, dict(nl_kernel=ofdft.KERNEL_MGP)),
+    "box_wt_mgpa": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_WT,
+                    dict(nl_kernel=ofdft.KERNEL_MGPA)),
+    "box_wt_mgpg": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_WT,
+                    dict(nl_kernel=ofdft.KERNEL_MGPG)),
+    "box_lmgp_s3s4": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_SPLINE,
+                      dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_S3S4,
+                           nl_kernel=ofdft.KERNEL_MGP)),
+    "box_lmgpa_exact": (lambda: (box((24, 16, 12)), None), LOCAL | ofdft.TERM_SPLINE,
+                        dict(nk=10, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT,
+                             nl_kernel=ofdft.KERNEL_MGPA)),
+    "plane_lmgpg_exact": (lambda: (box((16, 32, 32)), None), LOCAL | ofdft.TERM_SPLINE,
+                          dict(nk=12, kf_min=0.3, kf_max=2.0, nl_mode=ofdft.NL_EXACT,
+                               nl_kernel=ofdft.KERNEL_MGPG)),
     # triclinic cells, row path and plane path
     "tri_wt": (lambda: (tri((24, 16, 12)), None), LOCAL | ofdft.TERM_WT, {}),
     "tri_spline_s3s4": (lambda: (tri((18, 16, 24)), None), LOCAL | ofdft.TERM_SPLINE,
@@ -158,7 +175,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED, ofdft.MIXED_VW64])
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_energy_potential_parity(name, prec):
     print("case energy", name, prec, flush=True)
