@@ -223,6 +223,27 @@ ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host,
 ofdft_status ofdft_energy_potential_dev(ofdft_grid *grid, const void *d_rho, void *d_v,
                                         void *hip_stream, ofdft_energy *e_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the device
+ * variant above for one density with the evaluation's whole workspace (the
+ * spectra, the spline knot spectra and accumulators, the FP64 von Weizsaecker
+ * leg's buffers and the partial sums) in a static device array of the library
+ * instead of the grid's buffers.  The call allocates nothing: no hipMalloc,
+ * hipFree, graph or event; the grid (created earlier) provides its tables.
+ * The array holds OFDFT_NOALLOC_SCRATCH_BYTES per device, reserved by the
+ * library on every device it runs on until the process ends; its address on
+ * a device is resolved by ofdft_ctx_create.  A grid whose one-density
+ * workspace is larger (for example a 256x256x384 spline grid: 8 knot spectra
+ * of 101 MB) gives OFDFT_EINVAL before anything is launched.  Results are
+ * those of ofdft_energy_potential_dev without graphs or pipelining (the same
+ * launches).  Every call on a device shares the array, so calls that overlap
+ * on one device (on different streams or threads) race; the call returns
+ * after its stream work has completed.  Non-finite or negative densities
+ * give OFDFT_EINVAL, with e_out left untouched. */
+#define OFDFT_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+ofdft_status ofdft_energy_potential_dev_noalloc(ofdft_grid *grid, const void *d_rho, void *d_v,
+                                                void *hip_stream, ofdft_energy *e_out);
+
 /* Batched device variant: nbatch densities of the same cell, stored
  * back to back (nbatch x N values); d_v likewise (may be NULL);
  * e_out has nbatch entries.  Every step of the evaluation runs for the whole

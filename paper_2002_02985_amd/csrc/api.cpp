@@ -1040,13 +1040,33 @@ static ofdft_status eval_graph(ofdft_grid *g, int nb, const void *d_in, int in_i
     return OFDFT_OK;
 }
 
+// Energies, mu and the residual norm of one density from its FP64 sums
+static void energies_of(const ofdft_grid *g, const double *S, ofdft_energy &e)
+{
+    const uint32_t terms = g->func.terms;
+    std::memset(&e, 0, sizeof(e));
+    e.nelec_int = g->dv * S[SL_RHO];
+    if (terms & OFDFT_TERM_TF) e.e_tf = C_TF * g->dv * S[SL_TF];
+    if (terms & OFDFT_TERM_VW) e.e_vw = 0.5 * g->func.lambda_vw * g->V * S[SL_VW];
+    if (terms & OFDFT_TERM_HARTREE) e.e_h = 2.0 * PI * g->V * S[SL_H];
+    if (terms & OFDFT_TERM_EXT) {
+        e.e_ext = g->V * S[SL_EXT];
+        e.e_ion = g->e_ion;
+    }
+    if (terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) e.e_nl = g->dv * S[SL_NL];
+    if (terms & OFDFT_TERM_XC) e.e_xc = g->dv * S[SL_XC];
+    e.e_total = e.e_tf + e.e_vw + e.e_h + e.e_ext + e.e_nl + e.e_xc + e.e_ion;
+    const double spp = S[SL_PHIPHI];
+    e.mu = spp > 0 ? S[SL_GPHI] / (2.0 * spp) : 0.0;
+    const double r2 = spp > 0 ? S[SL_GG] - S[SL_GPHI] * S[SL_GPHI] / spp : S[SL_GG];
+    e.resid_norm = std::sqrt(std::max(0.0, r2) / (double)g->geom.N);
+}
+
 template <typename T>
 static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
                               void *d_g, hipStream_t s, ofdft_energy *e_out, double *bad_out)
 {
     ST_TRY(reserve(g, nb));
-    const Geom &G = g->geom;
-    const uint32_t terms = g->func.terms;
     // graphs on streams that can be captured (not the legacy null stream)
     // and when no per-pass timing is asked for
     if (g->use_graphs && !g->timer.on && s != nullptr) {
@@ -1061,22 +1081,7 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
     for (int b = 0; b < nb; ++b) {
         const double *S = g->h_sums + (size_t)b * NSLOT;
         ofdft_energy e;
-        std::memset(&e, 0, sizeof(e));
-        e.nelec_int = g->dv * S[SL_RHO];
-        if (terms & OFDFT_TERM_TF) e.e_tf = C_TF * g->dv * S[SL_TF];
-        if (terms & OFDFT_TERM_VW) e.e_vw = 0.5 * g->func.lambda_vw * g->V * S[SL_VW];
-        if (terms & OFDFT_TERM_HARTREE) e.e_h = 2.0 * PI * g->V * S[SL_H];
-        if (terms & OFDFT_TERM_EXT) {
-            e.e_ext = g->V * S[SL_EXT];
-            e.e_ion = g->e_ion;
-        }
-        if (terms & (OFDFT_TERM_WT | OFDFT_TERM_SPLINE)) e.e_nl = g->dv * S[SL_NL];
-        if (terms & OFDFT_TERM_XC) e.e_xc = g->dv * S[SL_XC];
-        e.e_total = e.e_tf + e.e_vw + e.e_h + e.e_ext + e.e_nl + e.e_xc + e.e_ion;
-        const double spp = S[SL_PHIPHI];
-        e.mu = spp > 0 ? S[SL_GPHI] / (2.0 * spp) : 0.0;
-        const double r2 = spp > 0 ? S[SL_GG] - S[SL_GPHI] * S[SL_GPHI] / spp : S[SL_GG];
-        e.resid_norm = std::sqrt(std::max(0.0, r2) / (double)G.N);
+        energies_of(g, S, e);
         bad += S[SL_BAD];
         if (e_out) e_out[b] = e;
     }
@@ -2555,6 +2560,105 @@ static ofdft_status td_propagate_impl(ofdft_grid *g, const ofdft_td_params *prm,
 }
 
 // ================================================================ C ABI
+// ---------------------------------------------------------------- no-allocation evaluation
+// The workspace of ofdft_energy_potential_dev_noalloc (spectra, spline knot
+// spectra and accumulators, the FP64 leg's buffers, partial sums) for callers
+// that cannot allocate device memory.  Host code never uses this array's name
+// as an address: each device's copy is resolved once with hipGetSymbolAddress
+// (in ofdft_ctx_create, with that device current) and only that pointer is
+// passed to kernels.  Every call on a device shares its copy; calls that
+// overlap on one device race.  Nothing in it needs to start at zero: every
+// buffer is written before it is read within one evaluation (the first knot
+// batch overwrites the accumulators, and the final sums read only the partials
+// that the evaluation's own blocks wrote).
+static __device__ __align__(256) unsigned char scratch[OFDFT_NOALLOC_SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+static ofdft_status scratch_resolve(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return fail(OFDFT_EINVAL, "device index beyond the no-allocation scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return OFDFT_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(OFDFT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return OFDFT_OK;
+}
+
+static void *scratch_of(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+// Carves the one-density workspace of a grid out of the scratch array
+// (256-byte aligned pieces); returns the bytes needed, and fills w when they
+// fit.
+template <typename T>
+static size_t scratch_work(const ofdft_grid *g, char *base, Work &w)
+{
+    const Geom &G = g->geom;
+    const size_t cb = 2 * sizeof(T);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    std::memset(&w, 0, sizeof(w));
+    w.spec = take((size_t)4 * G.Nh * cb);
+    if (g->func.terms & OFDFT_TERM_SPLINE) {
+        w.kspec = take((size_t)MAXKB * G.Nh * cb);
+        w.acc1 = take((size_t)G.N * sizeof(T));
+        if (g->func.nl_mode == OFDFT_NL_EXACT) w.acc2 = take((size_t)G.N * sizeof(T));
+    }
+    if (g->vw64) {
+        w.vwspec = take((size_t)G.Nh * 16);
+        w.vwout = take((size_t)G.N * 4);
+    }
+    w.part = (double *)take((size_t)NSLOT * g->pstride * sizeof(double));
+    w.sums = (double *)take((size_t)NSLOT * sizeof(double));
+    return off;
+}
+
+template <typename T>
+static ofdft_status eval_noalloc(ofdft_grid *g, const void *d_rho, void *d_v, hipStream_t s,
+                                 ofdft_energy *e_out)
+{
+    char *base = (char *)scratch_of(g->ctx->device);
+    if (!base)
+        return fail(OFDFT_EDEVICE, "no-allocation scratch not resolved for this device");
+    Work w;
+    const size_t need = scratch_work<T>(g, base, w);
+    if (need > (size_t)OFDFT_NOALLOC_SCRATCH_BYTES)
+        return fail(OFDFT_EINVAL, "the workspace of one evaluation on this grid needs " +
+                                      std::to_string(need) + " bytes; the no-allocation scratch holds " +
+                                      std::to_string((size_t)OFDFT_NOALLOC_SCRATCH_BYTES));
+    double hs[NSLOT];
+    w.h_sums = hs;
+    // no per-pass timing (it creates events) and no graphs or second stream
+    const bool timer = g->timer.on;
+    g->timer.on = false;
+    const ofdft_status st = eval_enqueue<T>(g, 1, d_rho, 0, d_v, nullptr, s, w);
+    g->timer.on = timer;
+    ST_TRY(st);
+    HIP_TRY(hipStreamSynchronize(s));
+    ofdft_energy e;
+    energies_of(g, hs, e);
+    if (hs[SL_BAD] > 0)
+        return fail(OFDFT_EINVAL, "input density has " + std::to_string((long long)hs[SL_BAD]) +
+                                      " non-finite or negative values");
+    *e_out = e;
+    return OFDFT_OK;
+}
+
 extern "C" {
 
 int ofdft_abi_version(void) { return OFDFT_ABI_VERSION; }
@@ -2571,6 +2675,9 @@ ofdft_status ofdft_ctx_create(int device, ofdft_ctx **out)
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(OFDFT_EINVAL, "no such device");
     HIP_TRY(hipSetDevice(device));
+    // library set-up per device: the address of this device's copy of the
+    // no-allocation scratch array
+    ST_TRY(scratch_resolve(device));
     ofdft_ctx *c = new (std::nothrow) ofdft_ctx;
     if (!c) return fail(OFDFT_ENOMEM, "host allocation failed");
     c->device = device;
@@ -2728,6 +2835,16 @@ ofdft_status ofdft_energy_potential_dev(ofdft_grid *grid, const void *d_rho, voi
                                         void *hip_stream, ofdft_energy *e_out)
 {
     return ofdft_energy_potential_batch_dev(grid, 1, d_rho, d_v, hip_stream, e_out);
+}
+
+ofdft_status ofdft_energy_potential_dev_noalloc(ofdft_grid *grid, const void *d_rho, void *d_v,
+                                                void *hip_stream, ofdft_energy *e_out)
+{
+    if (!grid || !d_rho || !e_out) return fail(OFDFT_EINVAL, "bad argument");
+    HIP_TRY(hipSetDevice(grid->ctx->device));
+    hipStream_t s = pick_stream(grid, hip_stream);
+    return grid->fp64 ? eval_noalloc<double>(grid, d_rho, d_v, s, e_out)
+                      : eval_noalloc<float>(grid, d_rho, d_v, s, e_out);
 }
 
 ofdft_status ofdft_energy_potential_batch_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,

@@ -125,6 +125,7 @@ _SIGS = {
     "ofdft_energy_potential_dev": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(Energy)]),
     "ofdft_energy_potential_batch_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P,
                                                         ctypes.POINTER(Energy)]),
+    "ofdft_energy_potential_dev_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(Energy)]),
     "ofdft_fft_r2c_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "ofdft_fft_c2r_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "ofdft_forces": (ctypes.c_int, [_P, _DP]),
@@ -301,6 +302,12 @@ def ofdft_energy_potential(grid, rho=None, want_v=True, shape=None):
 def ofdft_energy_potential_dev(grid, d_rho, d_v, stream):
     e = Energy()
     check(load().ofdft_energy_potential_dev(grid, d_rho, d_v, stream, ctypes.byref(e)))
+    return e
+
+
+def ofdft_energy_potential_dev_noalloc(grid, d_rho, d_v, stream):
+    e = Energy()
+    check(load().ofdft_energy_potential_dev_noalloc(grid, d_rho, d_v, stream, ctypes.byref(e)))
     return e
 
 
