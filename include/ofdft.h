@@ -40,6 +40,14 @@
  *   No function aborts: each returns an ofdft_status, and
  *   ofdft_last_error() gives a message for the calling thread.
  *   Non-finite or negative densities give OFDFT_EINVAL.
+ *
+ * Environment (read when a grid is created; for tests and profiling)
+ *   OFDFT_COL_TILE_MAJOR=0|1  fixes the block order of the column passes
+ *     (array-major or tile-major), the choice ofdft_grid_tune otherwise makes,
+ *     so that a profiled run without the autotuner launches the tuned kernels.
+ *   OFDFT_LARGE_IONS=0|1  forces the small-cell (per-atom phase tables) or the
+ *     large-cell (tiled sum, binned Ewald) ionic set-up regardless of the atom
+ *     count, to compare the two on the same cell.
  */
 #ifndef OFDFT_H
 #define OFDFT_H
@@ -349,10 +357,12 @@ ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
  * grid never grows) fits in hbm_budget_bytes next to the resident grids;
  * idle resident grids are evicted least recently used first, those with no
  * queued request before the others.  An evicted cell's density is kept in
- * host memory (N doubles per cell, until the server is destroyed) and is the
- * starting density when that cell's grid is built again with the same grid
- * shape for a request that brings none (OPTIMIZE with warm = 0 excepted), so
- * warm starts survive eviction.  A request that cannot fit yet waits, and
+ * host memory (N doubles per cell; at most 8 GiB in all, the least recently
+ * saved dropped first) and is the starting density when that cell's grid is
+ * built again with the same grid shape for a request that brings none
+ * (OPTIMIZE with warm = 0 excepted), so warm starts survive eviction.  Until
+ * an evicted grid's density has been saved and the grid freed, the grid stays
+ * counted against the budget and requests of its cell wait.  A request that cannot fit yet waits, and
  * no later request that needs new memory overtakes it; requests for resident
  * grids still run.  A footprint above the whole budget is refused at submit
  * with OFDFT_ENOMEM.
@@ -431,6 +441,13 @@ typedef struct {
     int32_t pipe, reserved;       /* the grid's sub-batch split (not tuned) */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
+/* Spline knot range (step s1 on the device; on by default): before the knot
+ * loop, one pass over the input finds each density's smallest and largest
+ * rho, and with them the knots whose hat functions are non-zero at some
+ * point (one more on each side); the per-knot transforms and the
+ * interpolation skip every other knot, whose contributions are exact zeros.
+ * Off transforms every knot (the same results: a check of the skipping). */
+ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on);
 ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
                                  void *hip_stream, ofdft_tune_result *result);

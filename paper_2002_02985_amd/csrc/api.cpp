@@ -140,6 +140,9 @@ struct ofdft_grid {
     void *spec = nullptr;    // 4 * cap * Nh complex
     void *kspec = nullptr;   // MAXKB * cap * Nh complex (spline)
     void *acc1 = nullptr, *acc2 = nullptr;   // cap * N
+    double *kr_part = nullptr;   // cap * 2 * KR_BLOCKS: knot-range partials (spline)
+    int *kneed = nullptr;        // cap * 2: each density's knot range (spline)
+    bool knot_skip = true;       // spline passes skip knots outside the range
     void *stage_in = nullptr, *stage_out = nullptr;   // cap * N (host API staging)
     double *part = nullptr;
     int pstride = 0;
@@ -530,6 +533,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
         b += (uint64_t)MAXKB * cap * Nh * cb;                           // knot spectra
         b += cap * N * fsz;                                             // accumulator
         if (nl_mode == OFDFT_NL_EXACT) b += cap * N * fsz;
+        b += cap * (2 * (uint64_t)KR_BLOCKS * 8 + 2 * 4);               // knot range
     }
     b += cap * NSLOT * (uint64_t)pstride_of(G, fsz == 8, m.vw64) * 8 + cap * NSLOT * 8;   // partials
     if (m.vw64) {
@@ -562,6 +566,8 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
     dfree(g->stage_out);
     dfree(g->vwspec);
     dfree(g->vwout);
+    dfree(reinterpret_cast<void *&>(g->kr_part));
+    dfree(reinterpret_cast<void *&>(g->kneed));
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -576,6 +582,9 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
         ST_TRY(dmalloc(g, &g->acc1, (size_t)nb * G.N * g->fsz));
         if (g->func.nl_mode == OFDFT_NL_EXACT)
             ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->kr_part),
+                       (size_t)nb * 2 * KR_BLOCKS * sizeof(double)));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->kneed), (size_t)nb * 2 * sizeof(int)));
     }
     if (g->vw64) {
         ST_TRY(dmalloc(g, &g->vwspec, (size_t)nb * G.Nh * 16));
@@ -613,7 +622,7 @@ static Layout layout_of(const ofdft_grid *g)
 template <typename T>
 static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data, int nfb, int nbatch,
                              int inv, const int *ops, int kind, double *part = nullptr,
-                             const void *tw = nullptr)
+                             const void *tw = nullptr, const int *kneed = nullptr, int knot0 = 0)
 {
     const Geom &G = g->geom;
     ColArgs a;
@@ -635,6 +644,8 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.kf_wt = g->kf_wt;
     a.precond_q2 = g->precond_q2;
     a.precond_h = 16.0 * PI * g->nelec / g->V;
+    a.kneed = kneed;
+    a.knot0 = knot0;
     int L;
     if (axis == 1) {
         L = G.n1;
@@ -693,6 +704,8 @@ struct Work {
     void *acc1, *acc2;
     char *vwspec;     // FP64 von Weizsaecker leg: spectrum and result
     void *vwout;
+    double *kr_part;  // spline knot range: partials and the per-density range
+    int *kneed;
     double *part, *sums, *h_sums;
 };
 
@@ -708,6 +721,8 @@ static Work work_of(const ofdft_grid *g, int b0)
     w.acc2 = g->acc2 ? (char *)g->acc2 + (size_t)b0 * G.N * sizeof(T) : nullptr;
     w.vwspec = g->vwspec ? (char *)g->vwspec + (size_t)b0 * G.Nh * 16 : nullptr;
     w.vwout = g->vwout ? (char *)g->vwout + (size_t)b0 * G.N * 4 : nullptr;
+    w.kr_part = g->kr_part ? g->kr_part + (size_t)b0 * 2 * KR_BLOCKS : nullptr;
+    w.kneed = g->kneed ? g->kneed + (size_t)b0 * 2 : nullptr;
     w.part = g->part + (size_t)b0 * NSLOT * g->pstride;
     w.sums = g->sums + (size_t)b0 * NSLOT;
     w.h_sums = g->h_sums + (size_t)b0 * NSLOT;
@@ -831,6 +846,14 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
     if (spline) {
         const int nk = g->knots.nk;
         const int kb = std::max(1, std::min(MAXKB, g->tune_kb));
+        // step s1 on the device: each density's range of knots with a
+        // non-zero hat somewhere; the knot passes skip the others
+        const int *kneed = nullptr;
+        if (g->knot_skip && nk > 1) {
+            TIMED(PS_KNOT_INV, launch_knot_range<T>(G.N, nb, d_in, in_is_phi, g->knots, w.kr_part,
+                                                    w.kneed, s));
+            kneed = w.kneed;
+        }
         for (int k0 = 0; k0 < nk; k0 += kb) {
             const int K = std::min(kb, nk - k0);
             KnotArgs ka;
@@ -844,11 +867,13 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ka.nbatch = nb;
             ka.knots = g->knots;
             ka.kern = nl_kern(g, false);
+            ka.kneed = kneed;
             ka.tw = g->tw0;
             ka.g = G;
             TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
             if (!plane)
-                ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1, w.part));
+                ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1, w.part,
+                                   nullptr, kneed, k0));
             RowInvArgs ri;
             std::memset(&ri, 0, sizeof(ri));
             ri.spec = w.kspec;
@@ -862,6 +887,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ri.acc1 = w.acc1;
             ri.acc2 = w.acc2;
             ri.acc_init = (k0 == 0);
+            ri.kneed = kneed;
             ri.knot0 = k0;
             ri.knots = g->knots;
             ri.nbatch = nb;
@@ -883,10 +909,14 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
                 ef.partials = 0;
                 int nbe = 0;
                 if (plane) {
+                    // (the plane kernel writes every knot's field; those outside
+                    // the range are exact zeros, which knot_acc then skips)
                     TIMED(PS_EXACT_FWD, launch_plane_fwd<T>(G, nb, ef, nbe, s));
                 } else {
+                    ef.kneed = kneed;
                     TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
-                    ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD, w.part));
+                    ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD, w.part,
+                                       nullptr, kneed, k0));
                 }
                 KnotArgs kc = ka;
                 kc.src = w.kspec;
@@ -1092,13 +1122,16 @@ static ofdft_status eval_impl(ofdft_grid *g, int nb, const void *d_in, int in_is
 static ofdft_status eval_dispatch(ofdft_grid *g, int nb, const void *d_in, int in_is_phi,
                                   void *d_v, void *d_g, hipStream_t s, ofdft_energy *e_out)
 {
+    // energies reach e_out only when the input was valid
     double bad = 0.0;
-    ofdft_status st = g->fp64 ? eval_impl<double>(g, nb, d_in, in_is_phi, d_v, d_g, s, e_out, &bad)
-                              : eval_impl<float>(g, nb, d_in, in_is_phi, d_v, d_g, s, e_out, &bad);
+    std::vector<ofdft_energy> e((size_t)nb);
+    ofdft_status st = g->fp64 ? eval_impl<double>(g, nb, d_in, in_is_phi, d_v, d_g, s, e.data(), &bad)
+                              : eval_impl<float>(g, nb, d_in, in_is_phi, d_v, d_g, s, e.data(), &bad);
     if (st != OFDFT_OK) return st;
     if (bad > 0)
         return fail(OFDFT_EINVAL, "input density has " + std::to_string((long long)bad) +
                                       " non-finite or negative values");
+    if (e_out) std::copy(e.begin(), e.end(), e_out);
     return OFDFT_OK;
 }
 
@@ -1251,6 +1284,8 @@ static void grid_free(ofdft_grid *g)
     dfree(g->twNd);
     dfree(g->vwspec);
     dfree(g->vwout);
+    dfree(reinterpret_cast<void *&>(g->kr_part));
+    dfree(reinterpret_cast<void *&>(g->kneed));
     dfree(g->vext);
     dfree(g->gtab);
     dfree(reinterpret_cast<void *&>(g->ph0));
@@ -1720,12 +1755,26 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
 }
 
 // ---------------------------------------------------------------- host<->device fields
-static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, size_t n, hipStream_t s)
+// check_density: refuse non-finite or negative values.  FP64 fields are
+// checked by the evaluation's own prologue; for FP32 fields the conversion
+// loop checks the FP64 values it visits anyway (a negative value too small
+// for FP32 would otherwise arrive as -0 and pass)
+static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, size_t n, hipStream_t s,
+                                 bool check_density = false)
 {
     if (g->fp64) {
         HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, s));
     } else {
-        auto f = to_type<float>(src, n);
+        std::vector<float> f(n);
+        size_t bad = 0;
+        for (size_t i = 0; i < n; ++i) {
+            const double x = src[i];
+            bad += check_density && !(x >= 0.0 && x <= 1.7976931348623157e308);
+            f[i] = (float)x;
+        }
+        if (bad)
+            return fail(OFDFT_EINVAL, "input density has " + std::to_string(bad) +
+                                          " non-finite or negative values");
         HIP_TRY(hipMemcpyAsync(dst, f.data(), n * 4, hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     }
@@ -2618,6 +2667,8 @@ static size_t scratch_work(const ofdft_grid *g, char *base, Work &w)
         w.kspec = take((size_t)MAXKB * G.Nh * cb);
         w.acc1 = take((size_t)G.N * sizeof(T));
         if (g->func.nl_mode == OFDFT_NL_EXACT) w.acc2 = take((size_t)G.N * sizeof(T));
+        w.kr_part = (double *)take((size_t)2 * KR_BLOCKS * sizeof(double));
+        w.kneed = (int *)take((size_t)2 * sizeof(int));
     }
     if (g->vw64) {
         w.vwspec = take((size_t)G.Nh * 16);
@@ -2818,7 +2869,7 @@ ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host, do
         // non-finite or negative values are counted by the evaluation itself
         // (its prologue partials), which then fails with OFDFT_EINVAL
         ST_TRY(dmalloc(grid, &grid->stage_in, N * grid->fsz));
-        ST_TRY(upload_field(grid, grid->stage_in, rho_host, N, s));
+        ST_TRY(upload_field(grid, grid->stage_in, rho_host, N, s, true));
     }
     const void *d_in = rho_host ? grid->stage_in : grid->rho;
     void *d_v = nullptr;
@@ -3007,6 +3058,14 @@ ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on)
     if (!grid) return fail(OFDFT_EINVAL, "null argument");
     grid->use_graphs = on != 0;
     if (!grid->use_graphs) graphs_clear(grid);
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null grid");
+    if ((on != 0) != grid->knot_skip) graphs_clear(grid);
+    grid->knot_skip = on != 0;
     return OFDFT_OK;
 }
 

@@ -253,9 +253,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
     // an opaque copy of the thread index: the index arithmetic of this stage
     // is recomputed here instead of being hoisted out of callers' loops and
     // held in registers across the whole kernel
-#ifndef OFDFT_STAGE_HOIST
     asm volatile("" : "+v"(tid));
-#endif
     // unsigned index arithmetic: divisions by the compile-time P and NS
     // become multiply-high and shifts without sign fix-ups
     const unsigned ut = (unsigned)tid;
@@ -307,9 +305,7 @@ __device__ __forceinline__ void stockham_stage_src(cpx<T> *buf, int tid, const S
     constexpr int NBF = L / R;
     constexpr int TOT = NBF * P;
     constexpr int PER = (TOT + NT - 1) / NT;
-#ifndef OFDFT_STAGE_HOIST
     asm volatile("" : "+v"(tid));
-#endif
     const unsigned ut = (unsigned)tid;
     cpx<T> v[PER][R];
 #pragma unroll
@@ -348,9 +344,7 @@ __device__ __forceinline__ void stockham_stage_dst(const cpx<T> *buf, const cpx<
     constexpr int NBF = L / R;
     constexpr int TOT = NBF * P;
     constexpr int PER = (TOT + NT - 1) / NT;
-#ifndef OFDFT_STAGE_HOIST
     asm volatile("" : "+v"(tid));
-#endif
     const unsigned ut = (unsigned)tid;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {

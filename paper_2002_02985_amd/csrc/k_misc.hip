@@ -37,6 +37,96 @@ hipError_t launch_finalize(const double *part, int pstride, const SlotCounts &co
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- knot range
+template <typename T>
+__global__ __launch_bounds__(NT) void k_knot_range_part(long long N, const T *in, int in_is_phi,
+                                                        double *part)
+{
+    __shared__ double red[2 * NT / 64];
+    const int b = blockIdx.y, tid = threadIdx.x;
+    const T *x = in + (long long)b * N;
+    double lo = 1e300, hi = -1e300;
+    for (long long i = (long long)blockIdx.x * NT + tid; i < N; i += (long long)gridDim.x * NT) {
+        const T v = x[i];
+        const T rho = in_is_phi ? v * v : (v > T(0) ? v : T(0));
+        lo = fmin(lo, (double)rho);
+        hi = fmax(hi, (double)rho);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    constexpr int NW = NT / 64;
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = lo;
+        red[NW + (tid >> 6)] = hi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < NW; ++w) {
+            lo = fmin(lo, red[w]);
+            hi = fmax(hi, red[NW + w]);
+        }
+        part[((long long)b * 2) * KR_BLOCKS + blockIdx.x] = lo;
+        part[((long long)b * 2 + 1) * KR_BLOCKS + blockIdx.x] = hi;
+    }
+}
+
+template <typename T>
+__device__ int knot_bracket_of_rho(T rho, const Knots &kn)
+{
+    const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+    int j;
+    T t;
+    bool inside;
+    knot_bracket_kf(kf_from_log2(lu), kn, j, t, inside);
+    return j;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_knot_range_final(const double *part, Knots kn, int *kneed)
+{
+    const int b = blockIdx.x, tid = threadIdx.x;
+    double lo = 1e300, hi = -1e300;
+    for (int i = tid; i < KR_BLOCKS; i += 64) {
+        lo = fmin(lo, part[((long long)b * 2) * KR_BLOCKS + i]);
+        hi = fmax(hi, part[((long long)b * 2 + 1) * KR_BLOCKS + i]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (tid == 0) {
+        int k0 = 0, k1 = kn.nk - 1;
+        if (kn.nk > 1 && lo <= hi) {
+            // the extremes are values of the field type, bracketed as the grid
+            // points are; knots j .. j + 1 of each bracket, one more each side
+            const int jl = knot_bracket_of_rho<T>(T(lo), kn);
+            const int jh = knot_bracket_of_rho<T>(T(hi), kn);
+            k0 = jl - 1 < 0 ? 0 : jl - 1;
+            k1 = jh + 2 > kn.nk - 1 ? kn.nk - 1 : jh + 2;
+        }
+        kneed[2 * b] = k0;
+        kneed[2 * b + 1] = k1;
+    }
+}
+
+template <typename T>
+hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
+                             const Knots &kn, double *part, int *kneed, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_knot_range_part<T>), dim3(KR_BLOCKS, nbatch), dim3(NT), 0, s, N,
+                       (const T *)in, in_is_phi, part);
+    hipLaunchKernelGGL((k_knot_range_final<T>), dim3(nbatch), dim3(64), 0, s, part, kn, kneed);
+    return hipGetLastError();
+}
+template hipError_t launch_knot_range<float>(long long, int, const void *, int, const Knots &,
+                                             double *, int *, hipStream_t);
+template hipError_t launch_knot_range<double>(long long, int, const void *, int, const Knots &,
+                                              double *, int *, hipStream_t);
+
 // ---------------------------------------------------------------- G tables
 // tab[e] = 1/G^2 (0 at G = 0), tab[Nh + e] = G^2,
 // tab[2 Nh + e] = C_WT K(|G| / (2 kf)) for half-spectrum point e (K = G_NL for

@@ -87,6 +87,8 @@ struct RowFwdArgs {
     const void *tw1;            // W_{n1}^n (plane kernels)
     int in_f32;                 // FP64 kernels: the input is FP32 (the FP64 von
                                 // Weizsaecker leg of a mixed-precision grid)
+    const int *kneed;           // FK_KNOT fields: per-density knot range (see
+                                // launch_knot_range), or null for every knot
 };
 
 // strided column pass along axis 1 or 0 (c2c), optionally with a fused
@@ -110,6 +112,8 @@ struct ColArgs {
     int pstride;
     const void *tw;             // W_L^n
     Geom g;
+    const int *kneed;           // knot spectra: field f is knot knot0 + f; blocks of
+    int knot0;                  // knots outside the density's range return at once
 };
 
 // axis-0 spline kernels: per-knot inverse of omega_i rho^b(G), and the EXACT
@@ -125,6 +129,7 @@ struct KnotArgs {
     const void *tw;
     Geom g;
     NlKern kern;                // kernel family at each knot (tab in field type)
+    const int *kneed;           // per-density knot range, or null for every knot
 };
 
 // inverse row pass: axis-2 c2r of up to 4 fields, then a plain store, the
@@ -156,6 +161,9 @@ struct RowInvArgs {
     const void *vw_field;       // EP_COMBINE with cf = 0: -lambda nabla^2 phi as a real
                                 // field (nbatch x N, field type) computed elsewhere (the
                                 // FP64 leg of a mixed grid); fld_vw's spectrum is then unused
+    const int *kneed;           // EP_KNOTS: per-density knot range, or null for every
+                                // knot (the first batch that meets the range then
+                                // initialises the accumulators instead of acc_init)
 };
 
 // Term sets of the final combine that have kernels specialised at compile
@@ -193,6 +201,19 @@ template <typename T> int col_blocks(int L, long long ncols);
 // (kern.tab: the FP64 J table)
 template <typename T>
 hipError_t launch_gtab(const Geom &g, double kf_wt, const NlKern &kern, void *gtab, hipStream_t s);
+
+// Spline knot range of each density (step s1 on the device): the knots
+// whose hat functions can be non-zero at some grid point, kneed[2 b] = first
+// and kneed[2 b + 1] = last, from the smallest and largest rho of density b
+// (rho = in or in^2 for phi input) bracketed like every grid point and
+// widened by one knot on each side (so that rounding in the monotone map from
+// rho to the bracket cannot drop a knot).  Knots outside the range add exact
+// zeros, so the spline kernels skip them.  part: nbatch x 2 x KR_BLOCKS
+// doubles of scratch.
+constexpr int KR_BLOCKS = 512;
+template <typename T>
+hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
+                             const Knots &kn, double *part, int *kneed, hipStream_t s);
 
 // FP64 reductions: sums[b][s] = sum_{i < count.n[s]} part[b][s][i]; the
 // counts travel as a kernel argument (the launch sequence of an evaluation

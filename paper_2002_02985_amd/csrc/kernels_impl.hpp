@@ -33,16 +33,10 @@ constexpr double C_TF_D = 2.8712340001881918;   // (3/10)(3 pi^2)^(2/3)
 constexpr double C_WT_D = 2.2969872001505534;   // (6/25)(3 pi^2)^(2/3)
 
 // complex elements per block of the column and row passes (tile sizes)
-#ifndef OFDFT_COL_ELEMS_F32
-#define OFDFT_COL_ELEMS_F32 8192
-#endif
-#ifndef OFDFT_ROW_ELEMS_F32
-#define OFDFT_ROW_ELEMS_F32 2048
-#endif
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
-    static constexpr int COL_ELEMS = OFDFT_COL_ELEMS_F32;
-    static constexpr int ROW_ELEMS = OFDFT_ROW_ELEMS_F32;
+    static constexpr int COL_ELEMS = 8192;
+    static constexpr int ROW_ELEMS = 2048;
 };
 template <> struct Cfg<double> {
     static constexpr int COL_ELEMS = 2048;
@@ -58,13 +52,11 @@ constexpr int pow2_floor(int x)
 // at most 16 columns per block: smaller tiles keep more blocks in flight per
 // CU, which measured faster than 32-wide tiles on both the 96-point and the
 // 256-point column passes
-#ifndef OFDFT_COL_PMAX
-#define OFDFT_COL_PMAX 16
-#endif
+constexpr int COL_PMAX = 16;
 template <typename T, int L> constexpr int col_P()
 {
     int p = pow2_floor(Cfg<T>::COL_ELEMS / L);
-    if (p > OFDFT_COL_PMAX) p = OFDFT_COL_PMAX;
+    if (p > COL_PMAX) p = COL_PMAX;
     if (p < 4) p = 4;
     if (p > NT) p = NT;
     return p;
@@ -77,7 +69,7 @@ template <typename T, int L> constexpr int col_P()
 template <typename T, int L> constexpr int col_P_plain()
 {
     int p = pow2_floor(2 * Cfg<T>::COL_ELEMS / L);
-    if (p > OFDFT_COL_PMAX) p = OFDFT_COL_PMAX;
+    if (p > COL_PMAX) p = COL_PMAX;
     if (p < 4) p = 4;
     if (p > NT) p = NT;
     return p;
@@ -292,6 +284,15 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
     const T *in = (const T *)a.in + (long long)b * g.N;
     const cpx<T> *twM = (const cpx<T> *)a.twM;
     const cpx<T> *twN = (const cpx<T> *)a.twN;
+    // EXACT spline fields rho^a L_i: knots outside the density's range are
+    // zero everywhere (their spectra are not needed by the later passes)
+    const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
+    int klo = 0, khi = 1 << 30;
+    if (knots && a.kneed) {
+        klo = a.kneed[2 * b];
+        khi = a.kneed[2 * b + 1];
+        if (a.knot0 > khi || a.knot0 + a.nfields - 1 < klo) return;
+    }
 
     cpx<T> x[PER];
 #pragma unroll
@@ -319,7 +320,6 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
     }
     // derived values: u = rho, w = phi, z = rho^beta  (or, for knot fields,
     // u = rho^alpha, w = t, jj = bracket)
-    const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
     // FP64 passes that need neither the partials nor rho^beta nor the knot
     // weights (the von Weizsaecker leg: phi only) skip the FP64 logarithm
     // and exponential; FP32 passes always evaluate them
@@ -376,6 +376,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
     for (int f = 0; f < a.nfields; ++f) {
         const int kind = a.kind[f];
         const int knot = a.knot0 + f;
+        if (knots && (knot < klo || knot > khi)) continue;   // uniform in the block
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NT;
@@ -454,6 +455,11 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     const int field = fb / a.nbatch;
     const int b = fb % a.nbatch;
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
+    if (a.kneed) {
+        // a knot spectrum outside the density's knot range is not needed
+        const int kn = a.knot0 + field;
+        if (kn < a.kneed[2 * b] || kn > a.kneed[2 * b + 1]) return;
+    }
 
     for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
     // the first stage of a transform reads element n of this thread's column
@@ -582,6 +588,14 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
     __shared__ cpx<T> tws[L];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
+    // knots outside the density's range (their hats vanish at every point)
+    // are not transformed; a batch entirely outside it returns at once
+    int klo = 0, khi = 1 << 30;
+    if (a.kneed) {
+        klo = a.kneed[2 * b];
+        khi = a.kneed[2 * b + 1];
+        if (a.knot0 > khi || a.knot0 + a.K - 1 < klo) return;
+    }
     const int p = tid % P;
     const long long c = (long long)blockIdx.x * P + p;
     const bool cvalid = c < a.ncols;
@@ -609,6 +623,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
         }
     }
     for (int kk = 0; kk < a.K; ++kk) {
+        if (a.knot0 + kk < klo || a.knot0 + kk > khi) continue;   // uniform in the block
         const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -637,6 +652,16 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
     __shared__ cpx<T> buf[L * P];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
+    // knots outside the density's range contribute exact zeros: skipped; the
+    // first batch that meets the range overwrites H
+    int klo = 0, khi = 1 << 30;
+    bool add_to_h = a.accumulate != 0;
+    if (a.kneed) {
+        klo = a.kneed[2 * b];
+        khi = a.kneed[2 * b + 1];
+        if (a.knot0 > khi || a.knot0 + a.K - 1 < klo) return;
+        add_to_h = a.knot0 > klo;
+    }
     const int p = tid % P;
     const long long c = (long long)blockIdx.x * P + p;
     const bool cvalid = c < a.ncols;
@@ -659,6 +684,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
         gn[q] = (n < L && cvalid) ? d_sqrt(gvec2<T>(g, freq(n, L), m1, m2)) : T(0);
     }
     for (int kk = 0; kk < a.K; ++kk) {
+        if (a.knot0 + kk < klo || a.knot0 + kk > khi) continue;   // uniform in the block
         // the first stage reads this thread's column (pencil p) from memory
         const cpx<T> *src = (const cpx<T> *)a.src + ((long long)kk * a.nbatch + b) * a.fstride;
         lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid,
@@ -683,7 +709,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
             const int n = tid / P + q * RSTEP;
             if (n < L) {
                 cpx<T> v = acc[q];
-                if (a.accumulate) v = cadd(v, dst[c + n * es]);
+                if (add_to_h) v = cadd(v, dst[c + n * es]);
                 dst[c + n * es] = v;
             }
         }
@@ -971,15 +997,10 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
 // The knot epilogue is instantiated with CF = CB_SPL (S3S4) or CB_SPL |
 // CB_EXACT and asks for at least 4 resident waves per SIMD (128 VGPRs):
 // measured faster than the 3 its unconstrained allocation allows.
-#ifndef OFDFT_ROW_KNOTS_MINW
-#define OFDFT_ROW_KNOTS_MINW 4
-#endif
-#ifndef OFDFT_ROW_S3S4_MINW
-#define OFDFT_ROW_S3S4_MINW OFDFT_ROW_KNOTS_MINW
-#endif
+constexpr int ROW_KNOTS_MINW = 4;
 template <int MODE, int CF> constexpr int row_inv_minw()
 {
-    return MODE != EP_KNOTS ? 1 : ((CF & CB_EXACT) ? OFDFT_ROW_KNOTS_MINW : OFDFT_ROW_S3S4_MINW);
+    return MODE != EP_KNOTS ? 1 : ROW_KNOTS_MINW;
 }
 template <typename T, int M, int CF, int MODE>
 __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowInvArgs a, Geom g)
@@ -1044,6 +1065,17 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
         return;
     }
 
+    // a knot batch entirely outside the density's knot range adds nothing;
+    // the first batch that meets it initialises the accumulators
+    bool acc_init = a.acc_init != 0;
+    if constexpr (MODE == EP_KNOTS) {
+        if (a.kneed) {
+            const int klo = a.kneed[2 * b], khi = a.kneed[2 * b + 1];
+            if (a.knot0 > khi || a.knot0 + a.nfields - 1 < klo) return;
+            acc_init = a.knot0 <= klo;
+        }
+    }
+
     // input density (rho or phi) for this block's pairs
     const T *in = (const T *)a.in + (long long)b * g.N;
     cpx<T> xin[PER];
@@ -1100,11 +1132,11 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
         for (int q = 0; q < PER; ++q) {
             if (!valid[q]) continue;
             cpx<T> s1 = v1[q];
-            if (!a.acc_init) s1 = cadd(s1, *(cpx<T> *)(acc1 + offs[q]));
+            if (!acc_init) s1 = cadd(s1, *(cpx<T> *)(acc1 + offs[q]));
             *(cpx<T> *)(acc1 + offs[q]) = s1;
             if (acc2) {
                 cpx<T> s2 = v2[q];
-                if (!a.acc_init) s2 = cadd(s2, *(cpx<T> *)(acc2 + offs[q]));
+                if (!acc_init) s2 = cadd(s2, *(cpx<T> *)(acc2 + offs[q]));
                 *(cpx<T> *)(acc2 + offs[q]) = s2;
             }
         }
@@ -1182,10 +1214,7 @@ template <int N1> constexpr int plane_A() { return (N1 % 2 == 0) ? N1 + 1 : N1; 
 template <int N1, int M> constexpr int plane_NT() { return 1024; }
 // minimum resident waves per SIMD the compiler must allow: two 1024-thread
 // blocks per CU for FP32 (64 VGPRs), one for FP64
-#ifndef OFDFT_PLANE_MINW_F32
-#define OFDFT_PLANE_MINW_F32 8
-#endif
-template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? OFDFT_PLANE_MINW_F32 : 4; }
+template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? 8 : 4; }
 template <typename T, int N1, int M> constexpr bool plane_fits()
 {
     // both kernels also stage the input plane (N1 x 2M reals) and the
@@ -1439,6 +1468,12 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         xin[q] = tid + q * NTP < PAIRS ? in[tid + q * NTP] : cpx<T>{T(0), T(0)};
 
     if constexpr (MODE == EP_KNOTS) {
+        bool acc_init = a.acc_init != 0;
+        if (a.kneed) {
+            const int klo = a.kneed[2 * b], khi = a.kneed[2 * b + 1];
+            if (a.knot0 > khi || a.knot0 + a.nfields - 1 < klo) return;
+            acc_init = a.knot0 <= klo;
+        }
         int jj[PER][2];
         T tt[PER][2];
         cpx<T> v1[PER], v2[PER];
@@ -1486,8 +1521,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         for (int q = 0; q < PER; ++q) {
             const int idx = tid + q * NTP;
             if (idx >= PAIRS) continue;
-            acc1[idx] = a.acc_init ? v1[q] : cadd(v1[q], acc1[idx]);
-            if (acc2) acc2[idx] = a.acc_init ? v2[q] : cadd(v2[q], acc2[idx]);
+            acc1[idx] = acc_init ? v1[q] : cadd(v1[q], acc1[idx]);
+            if (acc2) acc2[idx] = acc_init ? v2[q] : cadd(v2[q], acc2[idx]);
         }
         return;
     }

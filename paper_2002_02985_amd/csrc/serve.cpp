@@ -101,6 +101,10 @@ struct Res {
     ofdft_grid *g = nullptr;
     uint64_t bytes = 0;
     bool busy = false;
+    // chosen for eviction: its density is being saved and the grid destroyed
+    // by a worker outside the lock; it stays busy (requests of its cell wait)
+    // and its bytes stay counted until then
+    bool evicting = false;
     uint64_t last_use = 0;
     bool has_density = false;
     CellCopy cell;
@@ -110,7 +114,12 @@ struct Res {
 struct SavedDensity {
     int32_t n[3] = {0, 0, 0};
     std::vector<double> rho;
+    uint64_t stamp = 0;   // order of saving, for the host-memory cap
 };
+
+// host bytes of saved densities kept at most; the least recently saved go
+// first beyond it
+constexpr uint64_t SAVED_CAP_BYTES = 8ull << 30;
 
 double ms_between(Clock::time_point a, Clock::time_point b)
 {
@@ -138,15 +147,52 @@ struct ofdft_server {
     // densities of evicted cells, kept in host memory and handed back as the
     // starting density when the cell's grid is built again (same grid shape)
     std::unordered_map<uint64_t, SavedDensity> saved;
+    uint64_t saved_bytes = 0, saved_clock = 0;
 };
 
 namespace {
 
+// The resident grid of a cell, not counting one that is being evicted
 int find_resident(const ofdft_server *s, uint64_t cell_id)
 {
     for (size_t r = 0; r < s->res.size(); ++r)
-        if (s->res[r]->cell_id == cell_id) return (int)r;
+        if (s->res[r]->cell_id == cell_id && !s->res[r]->evicting) return (int)r;
     return -1;
+}
+
+// For the admission views: the cell's resident grid, else the grid of it that
+// is being evicted (busy, so that the cell's requests wait until its density
+// has been saved), else -1
+int find_resident_or_evicting(const ofdft_server *s, uint64_t cell_id)
+{
+    const int r = find_resident(s, cell_id);
+    if (r >= 0) return r;
+    for (size_t k = 0; k < s->res.size(); ++k)
+        if (s->res[k]->cell_id == cell_id) return (int)k;
+    return -1;
+}
+
+// Keeps an evicted cell's density (under the lock), dropping the least
+// recently saved ones beyond the host-memory cap
+void save_density(ofdft_server *s, uint64_t cell_id, SavedDensity &&h)
+{
+    auto old = s->saved.find(cell_id);
+    if (old != s->saved.end()) {
+        s->saved_bytes -= old->second.rho.size() * sizeof(double);
+        s->saved.erase(old);
+    }
+    const uint64_t bytes = h.rho.size() * sizeof(double);
+    if (bytes > SAVED_CAP_BYTES) return;
+    while (s->saved_bytes + bytes > SAVED_CAP_BYTES && !s->saved.empty()) {
+        auto lru = s->saved.begin();
+        for (auto it = s->saved.begin(); it != s->saved.end(); ++it)
+            if (it->second.stamp < lru->second.stamp) lru = it;
+        s->saved_bytes -= lru->second.rho.size() * sizeof(double);
+        s->saved.erase(lru);
+    }
+    h.stamp = ++s->saved_clock;
+    s->saved_bytes += bytes;
+    s->saved[cell_id] = std::move(h);
 }
 
 // Runs one request on resident grid r (created here if it has none) on the
@@ -246,15 +292,16 @@ void worker_loop(ofdft_server *s, int w)
             rv[r].busy = s->res[r]->busy;
             rv[r].last_use = s->res[r]->last_use;
         }
+        for (size_t r = 0; r < s->res.size(); ++r) rv[r].busy |= s->res[r]->evicting;
         for (size_t i = 0; i < s->queue.size(); ++i) {
             const Job &j = *s->queue[i];
             qv[i].cell_id = j.cell_id;
             qv[i].need = j.need;
-            qv[i].resident = find_resident(s, j.cell_id);
+            qv[i].resident = find_resident_or_evicting(s, j.cell_id);
             if (qv[i].resident >= 0) {
                 const Res &r = *s->res[qv[i].resident];
                 rv[qv[i].resident].pending = true;
-                qv[i].reuse = r.g && same_shape(r.cell, r.func, j.cell, j.func);
+                qv[i].reuse = r.g && !r.evicting && same_shape(r.cell, r.func, j.cell, j.func);
             }
         }
         ofdft_sched::Decision d =
@@ -265,23 +312,22 @@ void worker_loop(ofdft_server *s, int w)
         }
         std::shared_ptr<Job> job = s->queue[d.job];
         s->queue.erase(s->queue.begin() + d.job);
-        // take the evicted grids out of the resident set (largest index first)
-        std::vector<int> ev = d.evict;
-        std::sort(ev.rbegin(), ev.rend());
+        // mark the evicted grids: they stay resident, busy and counted until
+        // this worker has saved their densities and destroyed them below
         struct Evicted {
+            Res *res;
             ofdft_grid *g;
             uint64_t cell_id;
             bool keep;          // has a density worth restoring
             int32_t n[3];
         };
         std::vector<Evicted> to_free;
-        for (int r : ev) {
-            s->used -= s->res[r]->bytes;
-            const Res &x = *s->res[r];
-            if (x.g)
-                to_free.push_back({x.g, x.cell_id, x.has_density,
-                                   {x.cell.d.n[0], x.cell.d.n[1], x.cell.d.n[2]}});
-            s->res.erase(s->res.begin() + r);
+        for (int r : d.evict) {
+            Res &x = *s->res[r];
+            x.evicting = true;
+            x.busy = true;
+            to_free.push_back({&x, x.g, x.cell_id, x.g && x.has_density,
+                               {x.cell.d.n[0], x.cell.d.n[1], x.cell.d.n[2]}});
         }
         Res *r = nullptr;
         SavedDensity saved;
@@ -291,6 +337,7 @@ void worker_loop(ofdft_server *s, int w)
         } else {
             auto it = s->saved.find(job->cell_id);
             if (it != s->saved.end()) {
+                s->saved_bytes -= it->second.rho.size() * sizeof(double);
                 saved = std::move(it->second);
                 s->saved.erase(it);
             }
@@ -300,7 +347,6 @@ void worker_loop(ofdft_server *s, int w)
             r = nr.get();
             s->res.push_back(std::move(nr));
             s->used += job->need;
-            s->peak = std::max(s->peak, s->used);
         }
         r->busy = true;
         s->running++;
@@ -308,18 +354,39 @@ void worker_loop(ofdft_server *s, int w)
         job->t_start = Clock::now();
         lk.unlock();
 
-        for (const Evicted &e : to_free) {
+        // save and free the evicted grids before this request allocates its
+        // own, then retire them from the resident set and the byte count
+        std::vector<SavedDensity> kept(to_free.size());
+        std::vector<bool> ok(to_free.size(), false);
+        for (size_t k = 0; k < to_free.size(); ++k) {
+            const Evicted &e = to_free[k];
+            if (!e.g) continue;
             ofdft_internal::bind_context(e.g, ctx);   // idle: nothing of it is in flight
             if (e.keep) {
-                SavedDensity h;
+                SavedDensity &h = kept[k];
                 std::memcpy(h.n, e.n, sizeof(h.n));
                 h.rho.resize((size_t)e.n[0] * e.n[1] * e.n[2]);
-                if (ofdft_get_density(e.g, h.rho.data()) == OFDFT_OK) {
-                    std::lock_guard<std::mutex> g2(s->mu);
-                    s->saved[e.cell_id] = std::move(h);
-                }
+                ok[k] = ofdft_get_density(e.g, h.rho.data()) == OFDFT_OK;
             }
             ofdft_grid_destroy(e.g);
+        }
+        if (!to_free.empty()) {
+            std::lock_guard<std::mutex> g2(s->mu);
+            for (size_t k = 0; k < to_free.size(); ++k) {
+                const Evicted &e = to_free[k];
+                if (ok[k]) save_density(s, e.cell_id, std::move(kept[k]));
+                for (size_t x = 0; x < s->res.size(); ++x)
+                    if (s->res[x].get() == e.res) {
+                        s->used -= s->res[x]->bytes;
+                        s->res.erase(s->res.begin() + x);
+                        break;
+                    }
+            }
+            s->cv_work.notify_all();
+        }
+        {
+            std::lock_guard<std::mutex> g2(s->mu);
+            s->peak = std::max(s->peak, s->used);
         }
         execute(*job, *r, ctx, saved);
 

@@ -154,6 +154,7 @@ _SIGS = {
     "ofdft_td_propagate": (ctypes.c_int, [_P, ctypes.POINTER(TdParams), ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(TdStats)]),
+    "ofdft_grid_set_knot_skip": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
     "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
@@ -454,6 +455,10 @@ def ofdft_server_destroy(server):
 
 def ofdft_grid_set_graphs(grid, on=True):
     check(load().ofdft_grid_set_graphs(grid, 1 if on else 0))
+
+
+def ofdft_grid_set_knot_skip(grid, on=True):
+    check(load().ofdft_grid_set_knot_skip(grid, 1 if on else 0))
 
 
 def ofdft_grid_set_pipeline(grid, nsub):

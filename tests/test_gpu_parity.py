@@ -209,9 +209,10 @@ def test_batch_matches_single(prec):
                 np.abs(vs[b] - v1).max() == 0.0
 
 
-def test_input_validation():
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_input_validation(prec):
     cell, rho = c1_cell()
-    with ofdft.Grid(cell, LOCAL) as g:
+    with ofdft.Grid(cell, LOCAL, precision=prec) as g:
         bad = rho.copy()
         bad[3, 4, 5] = -1.0
         with pytest.raises(ofdft.OfdftError) as ei:
@@ -220,6 +221,12 @@ def test_input_validation():
         bad[3, 4, 5] = np.nan
         with pytest.raises(ofdft.OfdftError):
             g.energy_potential(bad)
+        # a negative value below the smallest FP32 subnormal (it would round
+        # to -0 in the mixed path) is refused in both precisions
+        bad[3, 4, 5] = -1e-300
+        with pytest.raises(ofdft.OfdftError) as ei:
+            g.energy_potential(bad)
+        assert ei.value.status == ofdft.EINVAL
     bad_cell = dict(cell)
     bad_cell["n"] = (30, 32, 32)
     with pytest.raises(ofdft.OfdftError) as ei:

@@ -318,3 +318,37 @@ def test_evicted_density_is_restored():
         r1.iters, r2.iters, cold.iters))
     assert r2.iters <= 2 < cold.iters
     assert abs(r2.e.e_total - r1.e.e_total) < 1e-8 * abs(r1.e.e_total)
+
+
+def test_eviction_with_two_slots_keeps_the_density():
+    """Two worker slots under a budget of one grid: while cell B's request
+    evicts cell A, an energy request for A (no density of its own) arrives.
+    It must wait until A's density has been saved and then start from it: its
+    energy is the optimised energy of A, not that of the uniform start."""
+    a = W.cluster(19, "Al", seed=11, grid=48)
+    b = W.cluster(13, "Mg", seed=2, grid=48)
+    fd = ofdft.make_functional_desc(TERMS, precision=ofdft.FP64)
+    cd, keep = ofdft.make_cell_desc(a)
+    budget = int(ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_OPTIMIZE) * 1.2)
+    opt = dict(tol=1e-6, max_iter=400)
+    s = Server(budget=budget, max_inflight=2)
+    try:
+        qa = {"cell_id": 0, "kind": ofdft.REQ_OPTIMIZE, "cell": a,
+              "rho": W.gaussian_density(a, sigma=1.5, floor=1e-8)}
+        st, r1, _, _ = s.result(s.submit(qa, opt=opt, func=fd), qa)
+        assert st == ofdft.OK
+        qb = {"cell_id": 1, "kind": ofdft.REQ_OPTIMIZE, "cell": b,
+              "rho": W.gaussian_density(b, sigma=1.5, floor=1e-8)}
+        qe = {"cell_id": 0, "kind": ofdft.REQ_EP, "cell": a, "rho": None}
+        tb = s.submit(qb, opt=opt, func=fd)
+        te = s.submit(qe, func=fd)
+        st_b, _, _, _ = s.result(tb, qb)
+        st_e, re, _, _ = s.result(te, qe)
+        stats = s.stats()
+    finally:
+        s.close()
+    _say("A optimised E %.10f; A again after eviction E %.10f; peak %d of budget %d" % (
+        r1.e.e_total, re.e.e_total, stats["peak_bytes"], budget))
+    assert st_b == ofdft.OK and st_e == ofdft.OK
+    assert abs(re.e.e_total - r1.e.e_total) < 1e-8 * abs(r1.e.e_total)
+    assert stats["peak_bytes"] <= budget
