@@ -479,6 +479,10 @@ static void timer_collect(ofdft_grid *g)
 template <typename T>
 static bool use_plane(const ofdft_grid *g)
 {
+    // (the FP64 spline interpolation epilogue spills registers on planes
+    // above 72 x 36: those grids keep the row passes)
+    if (sizeof(T) == 8 && (g->func.terms & OFDFT_TERM_SPLINE) && g->geom.n1 * g->geom.m > 72 * 36)
+        return false;
     return g->tune_plane && plane_supported<T>(g->geom.n1, g->geom.m);
 }
 

@@ -1215,12 +1215,22 @@ template <int N1, int M> constexpr int plane_NT() { return 1024; }
 // minimum resident waves per SIMD the compiler must allow: two 1024-thread
 // blocks per CU for FP32 (64 VGPRs), one for FP64
 template <typename T> constexpr int plane_minw() { return sizeof(T) == 4 ? 8 : 4; }
+// FP32: the kernels also stage the input plane in LDS (two blocks per CU
+// share its 160 KB, so a block stays within 96 KB); FP64: one block per CU,
+// the input plane is read again from memory where it is needed (it stays in
+// L2 between the reads) and the block may take all 160 KB
+template <typename T> constexpr bool plane_stage_x() { return sizeof(T) == 4; }
 template <typename T, int N1, int M> constexpr bool plane_fits()
 {
-    // both kernels also stage the input plane (N1 x 2M reals) and the
-    // twiddles (N1 + 2M + 1 complex) in LDS
-    return ((long long)(M + 1) * plane_A<N1>() * 2 + (long long)N1 * 2 * M +
-            2LL * (N1 + 2 * M + 1)) * sizeof(T) <= 98304;
+    // the padded plane, the staged input plane (N1 x 2M reals) if any and
+    // the twiddles (N1 + 2M + 1 complex)
+    const long long reals = (long long)(M + 1) * plane_A<N1>() * 2 +
+                            (plane_stage_x<T>() ? (long long)N1 * 2 * M : 0) +
+                            2LL * (N1 + 2 * M + 1);
+    // FP64 planes larger than 96 x 48 spill registers at one 1024-thread
+    // block per CU; those grids keep the row and column passes
+    return reals * (long long)sizeof(T) <= (plane_stage_x<T>() ? 98304 : 155648) &&
+           (plane_stage_x<T>() || N1 * M <= 96 * 48);
 }
 
 // X[k] from Z[k] and Z[M-k] (r2c unpack), W^k = twN[k]
@@ -1264,7 +1274,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int PAIRS = N1 * M;
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     __shared__ cpx<T> buf[(M + 1) * A];
-    __shared__ cpx<T> xs[N1 * M];   // the input plane, read once from HBM
+    constexpr bool STX = plane_stage_x<T>();
+    __shared__ cpx<T> xs[STX ? N1 * M : 1];   // the input plane, read once from HBM
     __shared__ cpx<T> tws[N1 + 2 * M + 1];   // twiddles of both axes and the r2c unpack
     __shared__ double red[3 * NTP / 64];
     const int tid = threadIdx.x;
@@ -1281,7 +1292,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     for (int q = 0; q < PER; ++q) {
         const int idx = tid + q * NTP;
         x[q] = idx < PAIRS ? in[idx] : cpx<T>{T(0), T(0)};
-        if (idx < PAIRS) xs[idx] = x[q];
+        if constexpr (STX) {
+            if (idx < PAIRS) xs[idx] = x[q];
+        }
     }
     __syncthreads();
     const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
@@ -1324,7 +1337,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 const int idx = t + q * NTP;
                 if (idx >= PAIRS) continue;
                 const int i1 = idx / M, n = idx % M;
-                const cpx<T> xq = xs[idx];
+                cpx<T> xq;
+                if constexpr (STX) xq = xs[idx];
+                else xq = in[idx];
                 const T xv[2] = {xq.x, xq.y};
                 T o[2];
 #pragma unroll
@@ -1363,7 +1378,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 const unsigned idx = (unsigned)(t + q * NTP);
                 if (idx >= (unsigned)PAIRS) continue;
                 const unsigned i1 = idx / (unsigned)M, n = idx % (unsigned)M;
-                const cpx<T> xq = xs[idx];
+                cpx<T> xq;
+                if constexpr (STX) xq = xs[idx];
+                else xq = in[idx];
                 buf[n * A + i1] = {field(xq.x), field(xq.y)};
             }
             __syncthreads();
@@ -1426,7 +1443,8 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int PAIRS = N1 * M;
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     __shared__ cpx<T> buf[(M + 1) * A];
-    __shared__ cpx<T> xsbuf[N1 * M];
+    constexpr bool STX = plane_stage_x<T>();
+    __shared__ cpx<T> xsbuf[STX ? N1 * M : 1];
     __shared__ cpx<T> tws[N1 + 2 * M + 1];
     __shared__ double red[5 * NTP / 64];
     const int tid = threadIdx.x;
@@ -1534,9 +1552,11 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     // forms v and g once, after the last inverse, so that the per-point
     // powers of rho are evaluated once.  The input plane is kept in LDS (xs).
     cpx<T> *xs = (cpx<T> *)xsbuf;
+    if constexpr (STX) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q)
-        if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
+        for (int q = 0; q < PER; ++q)
+            if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
+    }
     __syncthreads();
     // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
     // A are exclusive and come last, so only H+ext and vW are ever held
@@ -1581,7 +1601,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
         if (acc1) s1 = acc1[idx];
         if (acc2) s2 = acc2[idx];
-        const cpx<T> xq = xs[idx];
+        cpx<T> xq;
+        if constexpr (STX) xq = xs[idx];
+        else xq = in[idx];
         const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
         const cpx<T> zh = last == 0 ? zl : fh[q];
         cpx<T> zv = last == 1 ? zl : fv[q];
