@@ -260,6 +260,23 @@ ofdft_status ofdft_energy_potential_batch_dev(ofdft_grid *grid, int32_t nbatch,
                                               const void *d_rho, void *d_v,
                                               void *hip_stream, ofdft_energy *e_out);
 
+/* Energy and potential of the resident densities of n different cells in
+ * one batched evaluation (the serving loop's batches of requests): every
+ * kernel launch processes all n densities, the reciprocal-space terms use
+ * each cell's own reciprocal vectors, v_ext(G), kernel table and E_ion.  The
+ * grids must share the grid shape, every field of the functional (precision
+ * included) and the device; the cells may differ in lattice, atoms and
+ * electron count.  grids[0] leads: its workspace (grown to n densities, plus
+ * n densities of staging for inputs and potentials), launch schedule and
+ * stream serve the batch.  v_out_or_null: NULL, or n pointers each NULL or
+ * to N doubles; e_out: n entries.  Each result is the same, bit for bit, as
+ * ofdft_energy_potential(grids[b], NULL, ...) with the leader's schedule.
+ * 1 <= n <= OFDFT_MULTI_MAX; no grid may appear twice; none may be in use
+ * by another thread. */
+#define OFDFT_MULTI_MAX 64
+ofdft_status ofdft_energy_potential_multi(ofdft_grid *const *grids, int32_t n,
+                                          double *const *v_out_or_null, ofdft_energy *e_out);
+
 /* The 3D FFT pair on the grid (the transforms behind every reciprocal-space
  * term): forward d_out = r2c(d_in) as n0 x n1 x (n2/2+1) interleaved complex
  * values, normalised by 1/N; inverse d_out = Re sum_half c X exp(iG.r)
@@ -367,6 +384,14 @@ ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
  * grids still run.  A footprint above the whole budget is refused at submit
  * with OFDFT_ENOMEM.
  *
+ * Continuous batching: when a worker takes an energy+potential request whose
+ * cell's grid is resident, it also takes further queued energy+potential
+ * requests of other resident cells with the same grid shape and functional
+ * (each the earliest queued request of its cell), up to 8, and serves them
+ * in one batched evaluation (ofdft_energy_potential_multi) if the leading
+ * grid's larger workspace fits in the budget; results are the same as
+ * alone.
+ *
  * Request kinds and results:
  *   EP        energy and potential of rho_or_null, else of the resident
  *             density (a cell with none starts from the uniform density
@@ -403,6 +428,8 @@ typedef struct {
     uint64_t resident_bytes, peak_bytes, budget_bytes;
     double p50_ms, p99_ms;          /* submit-to-finish latency of completed requests */
     double mean_queue_ms;           /* submit-to-start                                */
+    uint64_t batches;               /* batched evaluations of several cells           */
+    uint64_t batched_requests;      /* requests served in them                        */
 } ofdft_serve_stats;
 ofdft_status ofdft_server_create(ofdft_ctx *ctx, uint64_t hbm_budget_bytes,
                                  int32_t max_inflight, ofdft_server **out);

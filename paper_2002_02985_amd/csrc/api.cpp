@@ -140,6 +140,15 @@ struct ofdft_grid {
     void *spec = nullptr;    // 4 * cap * Nh complex
     void *kspec = nullptr;   // MAXKB * cap * Nh complex (spline)
     void *acc1 = nullptr, *acc2 = nullptr;   // cap * N
+    // multi-cell batches led by this grid (ofdft_energy_potential_multi): the
+    // per-entry cell records (device and pinned host), the entries' densities
+    // and potentials side by side, and the record array of the batch being
+    // enqueued (null otherwise)
+    CellTab *d_ct = nullptr, *h_ct = nullptr;
+    void *batch_in = nullptr, *batch_out = nullptr;
+    int batch_cap = 0;
+    uint64_t multi_bytes = 0;
+    const CellTab *cur_ct = nullptr;
     double *kr_part = nullptr;   // cap * 2 * KR_BLOCKS: knot-range partials (spline)
     int *kneed = nullptr;        // cap * 2: each density's knot range (spline)
     bool knot_skip = true;       // spline passes skip knots outside the range
@@ -509,6 +518,7 @@ struct BytesModel {
     bool stage = false, opt = false, forces = false;
     bool vw64 = false;   // FP32 grid with the FP64 von Weizsaecker leg
     bool mgp = false;    // MGP-family kernel table
+    uint64_t extra = 0;  // buffers of multi-cell batches led by the grid
 };
 // partial-sum rows: the block counts of the grid's own kernels, and of the
 // FP64 passes of a mixed grid's von Weizsaecker leg
@@ -547,6 +557,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     if (m.stage) b += 2 * N * fsz;
     if (m.opt) b += (uint64_t)NVEC_OPT * N * fsz;
     if (m.forces) b += (uint64_t)natoms * 3 * 8;
+    b += m.extra;
     return b;
 }
 
@@ -650,6 +661,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.precond_h = 16.0 * PI * g->nelec / g->V;
     a.kneed = kneed;
     a.knot0 = knot0;
+    a.ct = (axis == 0 && ops) ? g->cur_ct : nullptr;
     int L;
     if (axis == 1) {
         L = G.n1;
@@ -872,6 +884,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ka.knots = g->knots;
             ka.kern = nl_kern(g, false);
             ka.kneed = kneed;
+            ka.ct = g->cur_ct;
             ka.tw = g->tw0;
             ka.g = G;
             TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
@@ -1322,6 +1335,11 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_bin_of));
     dfree(reinterpret_cast<void *&>(g->d_ew_part));
     dfree(reinterpret_cast<void *&>(g->d_pme_b));
+    dfree(reinterpret_cast<void *&>(g->d_ct));
+    if (g->h_ct) (void)hipHostFree(g->h_ct);
+    g->h_ct = nullptr;
+    dfree(g->batch_in);
+    dfree(g->batch_out);
     dfree(g->rho);
     for (auto &p : g->opt) dfree(p);
     if (g->h_sums) (void)hipHostFree(g->h_sums);
@@ -2613,6 +2631,88 @@ static ofdft_status td_propagate_impl(ofdft_grid *g, const ofdft_td_params *prm,
 }
 
 // ================================================================ C ABI
+// ---------------------------------------------------------------- multi-cell batches
+// Whether two grids can share a launch sequence: the same grid shape,
+// functional (every field) and device.  The cells may differ (lattice, atoms,
+// electron count): the reciprocal-space pass and the knot kernels take each
+// entry's own reciprocal vectors and tables.
+static bool batchable(const ofdft_grid *a, const ofdft_grid *b)
+{
+    const ofdft_functional_desc &x = a->func, &y = b->func;
+    return a->ctx->device == b->ctx->device && a->n[0] == b->n[0] && a->n[1] == b->n[1] &&
+           a->n[2] == b->n[2] && x.terms == y.terms && x.lambda_vw == y.lambda_vw &&
+           x.alpha == y.alpha && x.beta == y.beta && x.nk == y.nk && x.kf_min == y.kf_min &&
+           x.kf_max == y.kf_max && x.knot_spacing == y.knot_spacing && x.nl_mode == y.nl_mode &&
+           x.precision == y.precision && x.rho_floor == y.rho_floor && x.nl_kernel == y.nl_kernel;
+}
+
+// One evaluation of the resident densities of n cells, led by grids[0],
+// whose workspace, twiddles and schedule serve the whole batch; potentials
+// (where v_host[b] is not null) are copied to the host.
+template <typename T>
+static ofdft_status eval_multi(ofdft_grid *const *grids, int n, double *const *v_host,
+                               ofdft_energy *e_out)
+{
+    ofdft_grid *g = grids[0];
+    const Geom &G = g->geom;
+    const size_t fb = (size_t)G.N * sizeof(T);
+    hipStream_t s = g->ctx->stream;
+    ST_TRY(reserve(g, n));
+    if (g->batch_cap < n) {
+        g->bytes -= g->multi_bytes;
+        dfree(reinterpret_cast<void *&>(g->d_ct));
+        dfree(g->batch_in);
+        dfree(g->batch_out);
+        if (g->h_ct) (void)hipHostFree(g->h_ct);
+        g->h_ct = nullptr;
+        g->batch_cap = 0;
+        g->multi_bytes = 0;
+        const uint64_t before = g->bytes;
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ct), (size_t)n * sizeof(CellTab)));
+        ST_TRY(dmalloc(g, &g->batch_in, (size_t)n * fb));
+        ST_TRY(dmalloc(g, &g->batch_out, (size_t)n * fb));
+        HIP_TRY(hipHostMalloc((void **)&g->h_ct, (size_t)n * sizeof(CellTab)));
+        g->multi_bytes = g->bytes - before;
+        g->batch_cap = n;
+    }
+    bool want_v = false;
+    for (int b = 0; b < n; ++b) {
+        const ofdft_grid *x = grids[b];
+        if (!x->rho) return fail(OFDFT_EINVAL, "a grid of the batch has no resident density");
+        CellTab &c = g->h_ct[b];
+        std::memcpy(c.b, x->geom.b, sizeof(c.b));
+        c.vext = x->vext;
+        c.gtab = x->gtab;
+        // a member's density was last written on its own context's stream
+        if (x->ctx->stream != s) HIP_TRY(hipStreamSynchronize(x->ctx->stream));
+        HIP_TRY(hipMemcpyAsync((char *)g->batch_in + b * fb, x->rho, fb, hipMemcpyDeviceToDevice, s));
+        want_v |= v_host && v_host[b];
+    }
+    HIP_TRY(hipMemcpyAsync(g->d_ct, g->h_ct, (size_t)n * sizeof(CellTab), hipMemcpyHostToDevice, s));
+    g->cur_ct = g->d_ct;
+    const ofdft_status st = eval_enqueue<T>(g, n, g->batch_in, 0, want_v ? g->batch_out : nullptr,
+                                            nullptr, s, work_of<T>(g, 0));
+    g->cur_ct = nullptr;
+    ST_TRY(st);
+    HIP_TRY(hipStreamSynchronize(s));
+    timer_collect(g);
+    double bad = 0.0;
+    std::vector<ofdft_energy> e((size_t)n);
+    for (int b = 0; b < n; ++b) {
+        const double *S = g->h_sums + (size_t)b * NSLOT;
+        energies_of(grids[b], S, e[b]);
+        bad += S[SL_BAD];
+    }
+    if (bad > 0)
+        return fail(OFDFT_EINVAL, "a resident density has " + std::to_string((long long)bad) +
+                                      " non-finite or negative values");
+    for (int b = 0; b < n; ++b)
+        if (v_host && v_host[b])
+            ST_TRY(download_field(g, v_host[b], (const char *)g->batch_out + b * fb, (size_t)G.N, s));
+    std::copy(e.begin(), e.end(), e_out);
+    return OFDFT_OK;
+}
+
 // ---------------------------------------------------------------- no-allocation evaluation
 // The workspace of ofdft_energy_potential_dev_noalloc (spectra, spline knot
 // spectra and accumulators, the FP64 leg's buffers, partial sums) for callers
@@ -2805,6 +2905,7 @@ uint64_t ofdft_grid_device_bytes(const ofdft_grid *grid)
     m.forces = grid->d_forces != nullptr;
     m.vw64 = grid->vw64;
     m.mgp = grid->d_jtab64 != nullptr;
+    m.extra = grid->multi_bytes;
     uint64_t b = bytes_model(grid->geom, grid->fsz, grid->natoms, (int)grid->Z.size(),
                              grid->sf_method, grid->func.terms, grid->func.nl_mode,
                              (grid->func.terms & OFDFT_TERM_SPLINE) ? grid->func.nk : 0,
@@ -2900,6 +3001,22 @@ ofdft_status ofdft_energy_potential_dev_noalloc(ofdft_grid *grid, const void *d_
     hipStream_t s = pick_stream(grid, hip_stream);
     return grid->fp64 ? eval_noalloc<double>(grid, d_rho, d_v, s, e_out)
                       : eval_noalloc<float>(grid, d_rho, d_v, s, e_out);
+}
+
+ofdft_status ofdft_energy_potential_multi(ofdft_grid *const *grids, int32_t n,
+                                          double *const *v_out_or_null, ofdft_energy *e_out)
+{
+    if (!grids || !e_out || n < 1 || n > OFDFT_MULTI_MAX) return fail(OFDFT_EINVAL, "bad argument");
+    for (int b = 0; b < n; ++b) {
+        if (!grids[b]) return fail(OFDFT_EINVAL, "null grid in the batch");
+        if (!batchable(grids[0], grids[b]))
+            return fail(OFDFT_EINVAL, "grids of a batch need the same shape, functional and device");
+        for (int c = 0; c < b; ++c)
+            if (grids[c] == grids[b]) return fail(OFDFT_EINVAL, "a grid appears twice in the batch");
+    }
+    HIP_TRY(hipSetDevice(grids[0]->ctx->device));
+    return grids[0]->fp64 ? eval_multi<double>(grids, n, v_out_or_null, e_out)
+                          : eval_multi<float>(grids, n, v_out_or_null, e_out);
 }
 
 ofdft_status ofdft_energy_potential_batch_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,

@@ -91,6 +91,16 @@ struct RowFwdArgs {
                                 // launch_knot_range), or null for every knot
 };
 
+// Per-entry cell data of a batch whose densities belong to different cells
+// of one grid shape and functional (ofdft_energy_potential_multi): the
+// cell's reciprocal vectors and its reciprocal-space tables (device array,
+// one record per batch entry)
+struct CellTab {
+    double b[3][3];
+    const void *vext;           // half spectrum v_ext(G), field type
+    const void *gtab;           // [1/G^2 | G^2 | omega(G)], field type
+};
+
 // strided column pass along axis 1 or 0 (c2c), optionally with a fused
 // reciprocal-space operation between a forward and an inverse transform
 struct ColArgs {
@@ -114,6 +124,8 @@ struct ColArgs {
     Geom g;
     const int *kneed;           // knot spectra: field f is knot knot0 + f; blocks of
     int knot0;                  // knots outside the density's range return at once
+    const CellTab *ct;          // reciprocal-space ops of a multi-cell batch: entry b's
+                                // b-vectors, v_ext and tables (null: g, vext, gtab)
 };
 
 // axis-0 spline kernels: per-knot inverse of omega_i rho^b(G), and the EXACT
@@ -130,6 +142,7 @@ struct KnotArgs {
     Geom g;
     NlKern kern;                // kernel family at each knot (tab in field type)
     const int *kneed;           // per-density knot range, or null for every knot
+    const CellTab *ct;          // multi-cell batch: entry b's reciprocal vectors (or null)
 };
 
 // inverse row pass: axis-2 c2r of up to 4 fields, then a plain store, the

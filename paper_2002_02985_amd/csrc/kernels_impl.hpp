@@ -430,7 +430,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 // array, which keeps DRAM pages open) or tile-major (consecutive blocks take
 // one tile of every (field, density) array, which keeps the tile's share of
 // the reciprocal-space tables in L2).
-template <typename T, int L, int P>
+// MC: a multi-cell batch (per-entry reciprocal vectors and tables from a.ct)
+template <typename T, int L, int P, bool MC = false>
 __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb, int ntiles)
 {
     constexpr int NT = col_NT<T, L, P>();   // this kernel's block size
@@ -480,9 +481,14 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     // the wide-tile instantiation (P != col_P) serves plain passes only
     constexpr bool OPS = P == col_P<T, L>();
     cpx<T> pre[OPS ? PER : 1];
+    const void *vext_b = a.vext, *gtab_b = a.gtab;
+    if constexpr (MC) {
+        vext_b = a.ct[b].vext;
+        gtab_b = a.ct[b].gtab;
+    }
     if (OPS && (op == GO_HEXT || op == GO_WT)) {
-        const cpx<T> *vx = (const cpx<T> *)a.vext;
-        const T *om = (const T *)a.gtab + 2 * a.g.Nh;
+        const cpx<T> *vx = (const cpx<T> *)vext_b;
+        const T *om = (const T *)gtab_b + 2 * a.g.Nh;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int n = tid / P + q * RSTEP;
@@ -512,7 +518,13 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     } else if constexpr (OPS) {
         // axis 0: element n is i0, column c is (i1, k2)
         lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, ld);
-        const Geom &g = a.g;
+        Geom g = a.g;
+        if constexpr (MC) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
+        }
         const int t = opaque(tid);
         const int i1 = cvalid ? (int)(c / g.n2h) : 0;
         const int k2 = cvalid ? (int)(c % g.n2h) : 0;
@@ -599,7 +611,13 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
     const int p = tid % P;
     const long long c = (long long)blockIdx.x * P + p;
     const bool cvalid = c < a.ncols;
-    const Geom &g = a.g;
+    Geom g = a.g;
+    if (a.ct) {   // multi-cell batch: this entry's reciprocal vectors
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
+    }
     const long long es = (long long)g.n1 * g.n2h;
     const unsigned es32 = (unsigned)es;
     const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
@@ -665,7 +683,13 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
     const int p = tid % P;
     const long long c = (long long)blockIdx.x * P + p;
     const bool cvalid = c < a.ncols;
-    const Geom &g = a.g;
+    Geom g = a.g;
+    if (a.ct) {   // multi-cell batch: this entry's reciprocal vectors
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
+    }
     const long long es = (long long)g.n1 * g.n2h;
     const unsigned es32 = (unsigned)es;
     const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
@@ -1785,8 +1809,12 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
     if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
     const long long total = (long long)nblocks * nfb;
     if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0, s, a,
-                       nfb, nblocks);
+    if (a.ct && !plain)
+        hipLaunchKernelGGL((k_col<T, L, P, true>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0,
+                           s, a, nfb, nblocks);
+    else
+        hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0, s,
+                           a, nfb, nblocks);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_set>
 #include <unordered_map>
 #include <vector>
 
@@ -148,6 +149,9 @@ struct ofdft_server {
     // starting density when the cell's grid is built again (same grid shape)
     std::unordered_map<uint64_t, SavedDensity> saved;
     uint64_t saved_bytes = 0, saved_clock = 0;
+    // continuous batching of energy+potential requests across cells
+    int batch_max = 8;
+    uint64_t n_batches = 0, n_batched = 0;
 };
 
 namespace {
@@ -276,6 +280,54 @@ void execute(Job &job, Res &r, ofdft_ctx *ctx, const SavedDensity &saved)
     job.status = st;
 }
 
+// Runs energy+potential requests of several resident cells (one grid shape
+// and functional) as one batched evaluation led by the first one's grid.
+// Called without the server lock; every grid is owned by this worker while
+// busy.  Falls back to one request at a time if the batch cannot run.
+void execute_batch(const std::vector<Job *> &jobs, const std::vector<Res *> &res, ofdft_ctx *ctx)
+{
+    const size_t n = jobs.size();
+    std::vector<ofdft_grid *> grids(n);
+    std::vector<double *> vptr(n);
+    std::vector<ofdft_energy> e(n);
+    ofdft_status st = OFDFT_OK;
+    for (size_t b = 0; b < n && st == OFDFT_OK; ++b) {
+        Job &job = *jobs[b];
+        Res &r = *res[b];
+        ofdft_internal::bind_context(r.g, ctx);
+        if (r.cell.pos != job.cell.pos) {
+            st = ofdft_internal::set_positions(r.g, job.cell.pos.data());
+            if (st == OFDFT_OK) r.cell.assign(job.cell);
+        }
+        if (st == OFDFT_OK && !job.rho.empty()) st = ofdft_set_density(r.g, job.rho.data());
+        if (st == OFDFT_OK) r.has_density = true;
+        grids[b] = r.g;
+        job.v.resize((size_t)job.cell.npoints());
+        vptr[b] = job.v.data();
+    }
+    if (st == OFDFT_OK) st = ofdft_energy_potential_multi(grids.data(), (int32_t)n, vptr.data(), e.data());
+    if (st != OFDFT_OK) {   // one at a time (each request gets its own status)
+        for (size_t b = 0; b < n; ++b) {
+            Job &job = *jobs[b];
+            job.status = ofdft_energy_potential(res[b]->g, nullptr, job.v.data(), &job.res.e);
+            job.res.evals = 1;
+            if (job.status != OFDFT_OK) job.err = ofdft_last_error();
+        }
+    } else {
+        for (size_t b = 0; b < n; ++b) {
+            jobs[b]->res.e = e[b];
+            jobs[b]->res.evals = 1;
+            jobs[b]->status = OFDFT_OK;
+        }
+    }
+    for (Job *job : jobs)
+        if (job->cancel.load()) {
+            job->status = OFDFT_ECANCELLED;
+            job->err = "request cancelled";
+            job->v.clear();
+        }
+}
+
 void worker_loop(ofdft_server *s, int w)
 {
     ofdft_ctx *ctx = s->ctxs[w];
@@ -311,7 +363,55 @@ void worker_loop(ofdft_server *s, int w)
             continue;
         }
         std::shared_ptr<Job> job = s->queue[d.job];
+        // continuous batching: an energy+potential request on a resident grid
+        // takes further queued energy+potential requests of other resident
+        // cells with the same grid shape and functional along (each the
+        // earliest queued request of its cell, its grid idle), as long as
+        // the leader's larger workspace fits in the budget
+        std::vector<std::shared_ptr<Job>> batch;
+        std::vector<Res *> batch_res;
+        if (job->kind == OFDFT_REQ_EP && d.evict.empty() && s->batch_max > 1) {
+            const int lr = find_resident(s, job->cell_id);
+            if (lr >= 0 && s->res[lr]->g && !s->res[lr]->busy &&
+                same_shape(s->res[lr]->cell, s->res[lr]->func, job->cell, job->func)) {
+                const Res &L = *s->res[lr];
+                uint64_t per = 0;   // workspace and staging of one more density
+                if (ofdft_footprint_bytes(&job->cell.d, &job->func, OFDFT_REQ_EP, &per) != OFDFT_OK)
+                    per = ~0ull >> 2;
+                std::unordered_set<uint64_t> seen;
+                seen.insert(job->cell_id);
+                for (size_t i = 0; i < s->queue.size() && (int)batch.size() + 1 < s->batch_max; ++i) {
+                    if ((int)i == d.job) continue;
+                    const Job &j = *s->queue[i];
+                    if (!seen.insert(j.cell_id).second) continue;   // not its cell's earliest
+                    if (j.kind != OFDFT_REQ_EP) continue;
+                    const int r = find_resident(s, j.cell_id);
+                    if (r < 0) continue;
+                    Res &R = *s->res[r];
+                    if (R.busy || R.evicting || !R.g) continue;
+                    if (!same_shape(R.cell, R.func, j.cell, j.func)) continue;
+                    if (j.rho.empty() && !R.has_density) continue;
+                    if (!same_functional(R.func, L.func) || R.cell.d.n[0] != L.cell.d.n[0] ||
+                        R.cell.d.n[1] != L.cell.d.n[1] || R.cell.d.n[2] != L.cell.d.n[2])
+                        continue;
+                    if (s->used + per * (batch.size() + 1) > s->budget) break;
+                    batch.push_back(s->queue[i]);
+                    batch_res.push_back(&R);
+                }
+            }
+        }
         s->queue.erase(s->queue.begin() + d.job);
+        for (const auto &bj : batch)
+            for (size_t i = 0; i < s->queue.size(); ++i)
+                if (s->queue[i] == bj) {
+                    s->queue.erase(s->queue.begin() + i);
+                    break;
+                }
+        for (size_t k = 0; k < batch.size(); ++k) {
+            batch_res[k]->busy = true;
+            batch[k]->state = RUNNING;
+            batch[k]->t_start = Clock::now();
+        }
         // mark the evicted grids: they stay resident, busy and counted until
         // this worker has saved their densities and destroyed them below
         struct Evicted {
@@ -388,9 +488,46 @@ void worker_loop(ofdft_server *s, int w)
             std::lock_guard<std::mutex> g2(s->mu);
             s->peak = std::max(s->peak, s->used);
         }
-        execute(*job, *r, ctx, saved);
+        if (batch.empty()) {
+            execute(*job, *r, ctx, saved);
+        } else {
+            std::vector<Job *> jobs{job.get()};
+            std::vector<Res *> rs{r};
+            for (size_t k = 0; k < batch.size(); ++k) {
+                jobs.push_back(batch[k].get());
+                rs.push_back(batch_res[k]);
+            }
+            execute_batch(jobs, rs, ctx);
+        }
 
         lk.lock();
+        if (!batch.empty()) {
+            // the leader's workspace grew with the batch: count it
+            const uint64_t now = ofdft_grid_device_bytes(r->g);
+            if (now > r->bytes) {
+                s->used += now - r->bytes;
+                r->bytes = now;
+            }
+            s->peak = std::max(s->peak, s->used);
+            s->n_batched += batch.size() + 1;
+            s->n_batches++;
+        }
+        for (size_t k = 0; k < batch.size(); ++k) {
+            Job &bj = *batch[k];
+            bj.t_end = Clock::now();
+            batch_res[k]->busy = false;
+            batch_res[k]->last_use = ++s->clock;
+            bj.state = DONE;
+            if (bj.status == OFDFT_OK) {
+                s->n_done++;
+                s->lat_ms.push_back(ms_between(bj.t_submit, bj.t_end));
+                s->queue_ms.push_back(ms_between(bj.t_submit, bj.t_start));
+            } else if (bj.status == OFDFT_ECANCELLED) {
+                s->n_cancel++;
+            } else {
+                s->n_fail++;
+            }
+        }
         job->t_end = Clock::now();
         r->busy = false;
         r->last_use = ++s->clock;
@@ -606,6 +743,8 @@ ofdft_status ofdft_serve_stats_get(ofdft_server *s, ofdft_serve_stats *out)
     double q = 0;
     for (double x : s->queue_ms) q += x;
     out->mean_queue_ms = s->queue_ms.empty() ? 0.0 : q / (double)s->queue_ms.size();
+    out->batches = s->n_batches;
+    out->batched_requests = s->n_batched;
     return OFDFT_OK;
 }
 

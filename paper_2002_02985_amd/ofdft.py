@@ -99,7 +99,8 @@ class ServeStats(ctypes.Structure):
                 ("resident_cells", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("resident_bytes", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("budget_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
-                ("p99_ms", ctypes.c_double), ("mean_queue_ms", ctypes.c_double)]
+                ("p99_ms", ctypes.c_double), ("mean_queue_ms", ctypes.c_double),
+                ("batches", ctypes.c_uint64), ("batched_requests", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -126,6 +127,9 @@ _SIGS = {
     "ofdft_energy_potential_batch_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P,
                                                         ctypes.POINTER(Energy)]),
     "ofdft_energy_potential_dev_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(Energy)]),
+    "ofdft_energy_potential_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                                    ctypes.POINTER(Energy)]),
     "ofdft_fft_r2c_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "ofdft_fft_c2r_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "ofdft_forces": (ctypes.c_int, [_P, _DP]),
@@ -310,6 +314,22 @@ def ofdft_energy_potential_dev_noalloc(grid, d_rho, d_v, stream):
     e = Energy()
     check(load().ofdft_energy_potential_dev_noalloc(grid, d_rho, d_v, stream, ctypes.byref(e)))
     return e
+
+
+def ofdft_energy_potential_multi(grids, shapes=None, want_v=True):
+    """Batched evaluation of the resident densities of several grids (same
+    shape and functional); returns (energies, potentials or None)."""
+    n = len(grids)
+    harr = (ctypes.c_void_p * n)(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in grids])
+    es = (Energy * n)()
+    vs = None
+    if want_v:
+        vs = [np.empty(tuple(sh), dtype=np.float64) for sh in shapes]
+        varr = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(v) for v in vs])
+    else:
+        varr = None
+    check(load().ofdft_energy_potential_multi(harr, n, varr, es))
+    return list(es), vs
 
 
 def ofdft_energy_potential_batch_dev(grid, nbatch, d_rho, d_v, stream):
