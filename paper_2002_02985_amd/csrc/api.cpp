@@ -568,6 +568,24 @@ static void graphs_clear(ofdft_grid *g)
     g->graphs.clear();
 }
 
+// device bytes of the per-density workspace that reserve(g, nb) allocates
+static uint64_t workspace_bytes(const ofdft_grid *g, int nb)
+{
+    const Geom &G = g->geom;
+    const uint64_t cbytes = 2 * g->fsz;
+    const bool spline = g->func.terms & OFDFT_TERM_SPLINE;
+    uint64_t b = 4ull * nb * G.Nh * cbytes;
+    if (spline) {
+        b += (uint64_t)MAXKB * nb * G.Nh * cbytes + (uint64_t)nb * G.N * g->fsz;
+        if (g->func.nl_mode == OFDFT_NL_EXACT) b += (uint64_t)nb * G.N * g->fsz;
+        b += (uint64_t)nb * 2 * KR_BLOCKS * sizeof(double) + (uint64_t)nb * 2 * sizeof(int);
+    }
+    if (g->vw64) b += (uint64_t)nb * G.Nh * 16 + (uint64_t)nb * G.N * 4;
+    b += (uint64_t)nb * NSLOT * pstride_of(G, g->fp64, g->vw64) * sizeof(double);
+    b += (uint64_t)nb * NSLOT * sizeof(double);
+    return b;
+}
+
 static ofdft_status reserve(ofdft_grid *g, int nb)
 {
     if (nb <= g->cap) return OFDFT_OK;
@@ -2354,6 +2372,17 @@ bool has_tuning(const ofdft_grid *g)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     return g_tune_cache.count(tune_key(g, 1)) > 0;
+}
+
+uint64_t multi_growth_bytes(const ofdft_grid *g, int n)
+{
+    uint64_t grow = 0;
+    if (n > g->cap) grow += workspace_bytes(g, n) - (g->cap > 0 ? workspace_bytes(g, g->cap) : 0);
+    if (n > g->batch_cap) {
+        const uint64_t staging = (uint64_t)n * (2ull * g->geom.N * g->fsz + sizeof(CellTab));
+        if (staging > g->multi_bytes) grow += staging - g->multi_bytes;
+    }
+    return grow;
 }
 
 }  // namespace ofdft_internal

@@ -452,20 +452,44 @@ __device__ __forceinline__ void lds_fft_io(cpx<T> *buf, const cpx<T> *tw, int ti
 }
 
 // ---------------------------------------------------------------- reductions
-// Deterministic workgroup sums of K doubles per thread: a fixed xor-shuffle
-// tree inside each 64-lane wave, then the per-wave results added in wave
-// order by thread 0.  The sums are valid in thread 0 only.  red must hold
-// K * NT / 64 doubles; the call ends with a barrier so red can be reused.
+// One DPP move of a double (both 32-bit halves with the same control);
+// lanes without a source, and rows outside ROWM, read +0.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWM, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWM, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum of v over the 64 lanes of a wave, valid in lane 63, in a fixed order:
+// running sums over 2, 4, 8 and 16 lanes inside each row of 16 (row_shr),
+// then row 0's total added to row 1 and row 2's to row 3 (row_bcast:15),
+// then the total of rows 0-1 added to rows 2-3 (row_bcast:31).
+__device__ __forceinline__ double wave_sum_to_last(double v)
+{
+    v += dpp_f64<0x111, 0xf>(v);
+    v += dpp_f64<0x112, 0xf>(v);
+    v += dpp_f64<0x114, 0xf>(v);
+    v += dpp_f64<0x118, 0xf>(v);
+    v += dpp_f64<0x142, 0xa>(v);
+    v += dpp_f64<0x143, 0xc>(v);
+    return v;
+}
+
+// Deterministic workgroup sums of K doubles per thread: a fixed DPP tree
+// inside each 64-lane wave, then the per-wave results added in wave order by
+// thread 0.  The sums are valid in thread 0 only.  red must hold K * NT / 64
+// doubles; the call ends with a barrier so red can be reused.
 template <int NT, int K>
 __device__ __forceinline__ void block_sums(double (&v)[K], double *red, int tid)
 {
+    static_assert(NT % 64 == 0, "whole waves");
     constexpr int NW = NT / 64;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
-    }
-    if ((tid & 63) == 0) {
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_to_last(v[k]);
+    if ((tid & 63) == 63) {
 #pragma unroll
         for (int k = 0; k < K; ++k) red[k * NW + (tid >> 6)] = v[k];
     }
@@ -480,6 +504,52 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double *red, int tid)
         }
     }
     __syncthreads();
+}
+
+// As block_sums, through LDS, for blocks with a free LDS area of K * NT
+// doubles (lds; the caller's reads of it must be complete, which the first
+// barrier here ensures): every thread stores its K values, then wave k adds
+// the NT values of quantity k (each lane NT / 64 of them, in wave order) and
+// reduces them with the DPP tree.  Valid in thread 0 only; red holds K
+// doubles and is read by thread 0 before any later barrier.
+template <int NT, int K>
+__device__ __forceinline__ void block_sums_lds(double (&v)[K], double *lds, double *red, int tid)
+{
+    static_assert(NT % 64 == 0 && K * 64 <= NT, "one wave per quantity");
+    constexpr int NW = NT / 64;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[k * NT + tid] = v[k];
+    __syncthreads();
+    if (tid < K * 64) {
+        const int k = tid >> 6, l = tid & 63;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += lds[k * NT + w * 64 + l];
+        s = wave_sum_to_last(s);
+        if (l == 63) red[k] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = red[k];
+    }
+}
+
+// element i of an array at a block-uniform base, addressed by a 32-bit byte
+// offset: the load or store then takes the base from scalar registers and one
+// 32-bit offset per lane.  Only for bases whose elements used lie within
+// 4 GiB of them (a plane of a field, not a whole field: a half spectrum of
+// 1024^3 points in FP32 is 4.3 GB)
+template <typename V>
+__device__ __forceinline__ V ld32(const V *base, unsigned i)
+{
+    return *(const V *)((const char *)base + i * (unsigned)sizeof(V));
+}
+template <typename V>
+__device__ __forceinline__ void st32(V *base, unsigned i, V v)
+{
+    *(V *)((char *)base + i * (unsigned)sizeof(V)) = v;
 }
 
 template <int NT>

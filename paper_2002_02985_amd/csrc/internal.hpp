@@ -22,5 +22,9 @@ int ctx_device(const ofdft_ctx *ctx);
 // Whether the process already holds a tuned launch schedule for this grid's
 // shape, precision, functional and single-density batches.
 bool has_tuning(const ofdft_grid *g);
+// Device bytes by which ofdft_energy_potential_multi led by g would grow g's
+// allocations for a batch of n grids (workspace for n densities and the
+// batch staging); 0 when they already suffice.
+uint64_t multi_growth_bytes(const ofdft_grid *g, int n);
 
 }  // namespace ofdft_internal

@@ -20,6 +20,7 @@
 // that interpolates over k_F at every point (steps s2-s4).
 #pragma once
 #include <cmath>
+#include <type_traits>
 
 #include "fft_core.hpp"
 #include "kernels.hpp"
@@ -131,6 +132,8 @@ __device__ __forceinline__ float d_log2(float x) { return __builtin_amdgcn_logf(
 __device__ __forceinline__ double d_log2(double x) { return log2(x); }
 __device__ __forceinline__ float d_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double d_exp2(double x) { return exp2(x); }
+__device__ __forceinline__ float d_fmax(float x, float y) { return __builtin_fmaxf(x, y); }
+__device__ __forceinline__ double d_fmax(double x, double y) { return __builtin_fmax(x, y); }
 template <typename T> __device__ __forceinline__ T neg_inf() { return -__builtin_huge_valf(); }
 template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
 constexpr double LOG2_3PI2 = 4.8879547596657937775;   // log2(3 pi^2)
@@ -257,6 +260,20 @@ __device__ __forceinline__ T gvec2(const Geom &g, int m0, int m1, int m2)
     const T gy = T(m0) * T(g.b[0][1]) + (T(m1) * T(g.b[1][1]) + T(m2) * T(g.b[2][1]));
     const T gz = T(m0) * T(g.b[0][2]) + (T(m1) * T(g.b[1][2]) + T(m2) * T(g.b[2][2]));
     return gx * gx + gy * gy + gz * gz;
+}
+
+// (c / d, c % d) for the column c = c0 + p of a block tile (c0 the tile's
+// first column, block-uniform; 0 <= p < the tile width): the division once
+// per tile in 32 bits, then wrap steps per lane (at most p / d + 1)
+__device__ __forceinline__ void tile_divmod(unsigned c0, unsigned p, unsigned d, unsigned &q,
+                                            unsigned &r)
+{
+    q = c0 / d;
+    r = c0 - q * d + p;
+    while (r >= d) {
+        r -= d;
+        ++q;
+    }
 }
 
 __device__ __forceinline__ double *part_ptr(double *part, int b, int slot, int pstride)
@@ -447,9 +464,13 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     const int tile = a.tile_major ? (int)(blockIdx.x / (unsigned)nfb)
                                   : (int)(blockIdx.x % (unsigned)ntiles);
     const int p = tid % P;
-    const long long c = (long long)tile * P + p;
-    const bool cvalid = c < a.ncols;
-    const long long cbase = cvalid ? (c / a.inner) * a.outer_stride + (c % a.inner) : 0;
+    // column indices in 32 bits (a field holds fewer than 2^32 elements)
+    const unsigned c0 = (unsigned)tile * (unsigned)P;
+    const unsigned c = c0 + (unsigned)p;
+    const bool cvalid = c < (unsigned)a.ncols;
+    unsigned cq, cr;
+    tile_divmod(c0, (unsigned)p, (unsigned)a.inner, cq, cr);
+    const unsigned cbase = cvalid ? cq * (unsigned)a.outer_stride + cr : 0u;
     const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
     cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
     const cpx<T> *tw = tws;
@@ -470,9 +491,9 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     // column past the end reads column 0 and writes nothing
     const unsigned cofs = cvalid ? (unsigned)cbase : 0u;
     const unsigned es = (unsigned)a.elem_stride;
-    auto ld = [&](unsigned n, unsigned) { return src[cofs + n * es]; };
+    auto ld = [&](unsigned n, unsigned) { return src[(size_t)(cofs + n * es)]; };
     auto st = [&](unsigned n, unsigned, cpx<T> v) {
-        if (cvalid) dst[cofs + n * es] = v;
+        if (cvalid) dst[(size_t)(cofs + n * es)] = v;
     };
     // reciprocal-space operands are fetched now so that their latency overlaps
     // the forward transform: v_ext(G) for the Hartree+ion field, the
@@ -494,11 +515,11 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
             const int n = tid / P + q * RSTEP;
             pre[q] = {T(0), T(0)};
             if (n < L && cvalid) {
-                const long long e = (long long)n * a.ncols + c;
+                const unsigned e = (unsigned)n * (unsigned)a.ncols + c;
                 if (op == GO_HEXT) {
-                    if (a.use_ext) pre[q] = vx[e];
+                    if (a.use_ext) pre[q] = vx[(size_t)e];
                 } else {
-                    pre[q].x = om[e];
+                    pre[q].x = om[(size_t)e];
                 }
             }
         }
@@ -526,8 +547,10 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
                 for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
         }
         const int t = opaque(tid);
-        const int i1 = cvalid ? (int)(c / g.n2h) : 0;
-        const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+        unsigned u1, u2;
+        tile_divmod(c0, (unsigned)p, (unsigned)g.n2h, u1, u2);
+        const int i1 = cvalid ? (int)u1 : 0;
+        const int k2 = cvalid ? (int)u2 : 0;
         const int m1 = freq(i1, g.n1);
         const int m2 = (k2 == g.m) ? -g.m : k2;
         const double wgt = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
@@ -609,8 +632,9 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
         if (a.knot0 > khi || a.knot0 + a.K - 1 < klo) return;
     }
     const int p = tid % P;
-    const long long c = (long long)blockIdx.x * P + p;
-    const bool cvalid = c < a.ncols;
+    const unsigned c0 = (unsigned)blockIdx.x * (unsigned)P;
+    const unsigned c = c0 + (unsigned)p;   // 32-bit column index
+    const bool cvalid = c < (unsigned)a.ncols;
     Geom g = a.g;
     if (a.ct) {   // multi-cell batch: this entry's reciprocal vectors
 #pragma unroll
@@ -618,14 +642,15 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
 #pragma unroll
             for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
     }
-    const long long es = (long long)g.n1 * g.n2h;
-    const unsigned es32 = (unsigned)es;
+    const unsigned es32 = (unsigned)g.n1 * (unsigned)g.n2h;
     const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
     const cpx<T> *src = (const cpx<T> *)a.src + b * a.fstride;
     for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
     const cpx<T> *tw = tws;
-    const int i1 = cvalid ? (int)(c / g.n2h) : 0;
-    const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+    unsigned u1, u2;
+    tile_divmod(c0, (unsigned)p, (unsigned)g.n2h, u1, u2);
+    const int i1 = cvalid ? (int)u1 : 0;
+    const int k2 = cvalid ? (int)u2 : 0;
     const int m1 = freq(i1, g.n1);
     const int m2 = (k2 == g.m) ? -g.m : k2;
     cpx<T> xs[PER];
@@ -636,7 +661,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
         xs[q] = {T(0), T(0)};
         gn[q] = T(0);
         if (n < L && cvalid) {
-            xs[q] = src[c + n * es];
+            xs[q] = src[(size_t)(c + (unsigned)n * es32)];
             gn[q] = d_sqrt(gvec2<T>(g, freq(n, L), m1, m2));
         }
     }
@@ -652,7 +677,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_inv(KnotArgs a)
         // the last stage writes this thread's column (pencil p) to memory
         cpx<T> *dst = (cpx<T> *)a.dst + ((long long)kk * a.nbatch + b) * a.fstride;
         lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tid, [&](unsigned n, unsigned, cpx<T> v) {
-            if (cvalid) dst[cofs + n * es32] = v;
+            if (cvalid) dst[(size_t)(cofs + n * es32)] = v;
         });
     }
 }
@@ -681,8 +706,9 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
         add_to_h = a.knot0 > klo;
     }
     const int p = tid % P;
-    const long long c = (long long)blockIdx.x * P + p;
-    const bool cvalid = c < a.ncols;
+    const unsigned c0 = (unsigned)blockIdx.x * (unsigned)P;
+    const unsigned c = c0 + (unsigned)p;   // 32-bit column index
+    const bool cvalid = c < (unsigned)a.ncols;
     Geom g = a.g;
     if (a.ct) {   // multi-cell batch: this entry's reciprocal vectors
 #pragma unroll
@@ -690,12 +716,13 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
 #pragma unroll
             for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
     }
-    const long long es = (long long)g.n1 * g.n2h;
-    const unsigned es32 = (unsigned)es;
+    const unsigned es32 = (unsigned)g.n1 * (unsigned)g.n2h;
     const unsigned cofs = cvalid ? (unsigned)c : 0u;   // past the end: column 0, not written
     const cpx<T> *tw = (const cpx<T> *)a.tw;
-    const int i1 = cvalid ? (int)(c / g.n2h) : 0;
-    const int k2 = cvalid ? (int)(c % g.n2h) : 0;
+    unsigned u1, u2;
+    tile_divmod(c0, (unsigned)p, (unsigned)g.n2h, u1, u2);
+    const int i1 = cvalid ? (int)u1 : 0;
+    const int k2 = cvalid ? (int)u2 : 0;
     const int m1 = freq(i1, g.n1);
     const int m2 = (k2 == g.m) ? -g.m : k2;
     const T invN = T(g.invN);
@@ -712,7 +739,7 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
         // the first stage reads this thread's column (pencil p) from memory
         const cpx<T> *src = (const cpx<T> *)a.src + ((long long)kk * a.nbatch + b) * a.fstride;
         lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid,
-                                              [&](unsigned n, unsigned) { return src[cofs + n * es32]; });
+                                              [&](unsigned n, unsigned) { return src[(size_t)(cofs + n * es32)]; });
         const T inv2k = T(0.5 / a.knots.k[a.knot0 + kk]);
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -733,8 +760,9 @@ __global__ __launch_bounds__((knot_NT<T, L>())) void k_knot_acc(KnotArgs a)
             const int n = tid / P + q * RSTEP;
             if (n < L) {
                 cpx<T> v = acc[q];
-                if (add_to_h) v = cadd(v, dst[c + n * es]);
-                dst[c + n * es] = v;
+                const size_t e = c + (unsigned)n * es32;
+                if (add_to_h) v = cadd(v, dst[e]);
+                dst[e] = v;
             }
         }
     }
@@ -853,29 +881,44 @@ __device__ __forceinline__ CombineConst<T> combine_const(const RowInvArgs &a)
 // LDA term (always in the general combine), rho eps_xc
 template <int CF> constexpr int combine_nsum() { return (CF == 0 || (CF & CB_XC)) ? 5 : 4; }
 
-template <typename T, int CF>
+// PH: 1 = x is phi, 0 = x is rho (both fixed at compile time, fixed term
+// sets only), -1 = taken from the arguments.
+template <typename T, int CF, int PH = -1>
 __device__ __forceinline__ void combine_point(const RowInvArgs &a, const CombineConst<T> &cc, T x,
                                               T hv, T wv, T nl, T s1, T s2, T &vo, T &go,
                                               double (&sums)[combine_nsum<CF>()])
 {
+    static_assert(PH == -1 || CF != 0, "the general combine reads the input kind at run time");
+    const bool in_phi = PH < 0 ? a.in_is_phi != 0 : PH == 1;
     T phi, rho;
-    if (a.in_is_phi) {
+    if (in_phi) {
         phi = x;
         rho = phi * phi;
     } else {
-        rho = x > T(0) ? x : T(0);
+        // with a fixed input kind a negative density is not clamped: the
+        // evaluation's prologue counts it and the call fails
+        rho = PH == 0 ? x : (x > T(0) ? x : T(0));
         phi = T(0);
     }
-    const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
-    const T lr = rho >= cc.floor_rho ? lu : cc.lfloor;
+    T lu, lr;
+    if constexpr (PH >= 0) {
+        // rho >= 0 here and log2(0) = -inf: no branch for empty points;
+        // rho_s = max(rho, floor) in the log domain
+        lu = d_log2(rho);
+        lr = d_fmax(lu, cc.lfloor);
+    } else {
+        lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+        lr = rho >= cc.floor_rho ? lu : cc.lfloor;
+    }
     T vv = T(0), gg = T(0);
     if constexpr (CF != 0) {
         constexpr T AL = T(5.0 / 6.0);
         const T p = d_exp2(lu * T(1.0 / 6.0));
         const T q = d_exp2(lr * T(-1.0 / 6.0));
         const T p2 = p * p;
-        if (!a.in_is_phi) phi = p2 * p;
-        const T sgn = phi < T(0) ? T(-1) : T(1);
+        if (!in_phi) phi = p2 * p;
+        // phi = rho^(1/2) >= 0 when the input is rho
+        const T sgn = PH == 0 ? T(1) : (phi < T(0) ? T(-1) : T(1));
         const T p4 = p2 * p2;
         const T q3 = q * q * q;
         if constexpr ((CF & CB_H) != 0) {
@@ -1202,19 +1245,30 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     T *gout = a.g_out ? (T *)a.g_out + (long long)b * g.N : nullptr;
     const CombineConst<T> cc = combine_const<T>(a);
     double sums[combine_nsum<CF>()] = {};   // rho^a Phi, g phi, g^2, phi^2 (, rho eps_xc)
+    // the input kind (phi or rho) is fixed per launch: compiled in for the
+    // fixed term sets
+    auto points = [&](auto ph) {
+        constexpr int PH = decltype(ph)::value;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        if (!valid[q]) continue;
-        cpx<T> a1 = {T(0), T(0)}, a2 = {T(0), T(0)};
-        if (acc1) a1 = *(const cpx<T> *)(acc1 + offs[q]);
-        if (acc2) a2 = *(const cpx<T> *)(acc2 + offs[q]);
-        cpx<T> vo, go;
-        combine_point<T, CF>(a, cc, xin[q].x, fh[q].x, fl[q].x, fn[q].x, a1.x, a2.x, vo.x, go.x,
-                             sums);
-        combine_point<T, CF>(a, cc, xin[q].y, fh[q].y, fl[q].y, fn[q].y, a1.y, a2.y, vo.y, go.y,
-                             sums);
-        if (vout) *(cpx<T> *)(vout + offs[q]) = vo;
-        if (gout) *(cpx<T> *)(gout + offs[q]) = go;
+        for (int q = 0; q < PER; ++q) {
+            if (!valid[q]) continue;
+            cpx<T> a1 = {T(0), T(0)}, a2 = {T(0), T(0)};
+            if (acc1) a1 = *(const cpx<T> *)(acc1 + offs[q]);
+            if (acc2) a2 = *(const cpx<T> *)(acc2 + offs[q]);
+            cpx<T> vo, go;
+            combine_point<T, CF, PH>(a, cc, xin[q].x, fh[q].x, fl[q].x, fn[q].x, a1.x, a2.x, vo.x,
+                                     go.x, sums);
+            combine_point<T, CF, PH>(a, cc, xin[q].y, fh[q].y, fl[q].y, fn[q].y, a1.y, a2.y, vo.y,
+                                     go.y, sums);
+            if (vout) *(cpx<T> *)(vout + offs[q]) = vo;
+            if (gout) *(cpx<T> *)(gout + offs[q]) = go;
+        }
+    };
+    if constexpr (CF != 0) {
+        if (a.in_is_phi) points(std::integral_constant<int, 1>());
+        else points(std::integral_constant<int, 0>());
+    } else {
+        points(std::integral_constant<int, -1>());
     }
     block_sums<NT, combine_nsum<CF>()>(sums, red, tid);
     if (tid == 0) {
@@ -1314,35 +1368,42 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     cpx<T> x[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int idx = tid + q * NTP;
-        x[q] = idx < PAIRS ? in[idx] : cpx<T>{T(0), T(0)};
+        const unsigned idx = (unsigned)(tid + q * NTP);
+        x[q] = idx < (unsigned)PAIRS ? ld32(in, idx) : cpx<T>{T(0), T(0)};
         if constexpr (STX) {
-            if (idx < PAIRS) xs[idx] = x[q];
+            if (idx < (unsigned)PAIRS) xs[idx] = x[q];
         }
     }
     __syncthreads();
     const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
     if (a.partials) {
         double sums[3] = {0.0, 0.0, 0.0};
+        auto count = [&](auto ph) {
+            constexpr bool P = decltype(ph)::value;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (tid + q * NTP >= PAIRS) continue;
-            const T xv[2] = {x[q].x, x[q].y};
+            for (int q = 0; q < PER; ++q) {
+                if (tid + q * NTP >= PAIRS) continue;
+                const T xv[2] = {x[q].x, x[q].y};
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const T v = xv[c];
-                const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
-                if (!ok) {
-                    sums[2] += 1.0;
-                    continue;
+                for (int c = 0; c < 2; ++c) {
+                    const T v = xv[c];
+                    const bool ok = d_finite(v) && (P || v >= T(0));
+                    if (!ok) {
+                        sums[2] += 1.0;
+                        continue;
+                    }
+                    const T rho = P ? v * v : v;   // >= 0; log2(0) = -inf
+                    sums[0] += (double)rho;
+                    sums[1] += (double)(rho * d_exp2(d_log2(rho) * T(2.0 / 3.0)));
                 }
-                const T rho = a.in_is_phi ? v * v : v;
-                const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
-                sums[0] += (double)rho;
-                sums[1] += (double)(rho * d_exp2(lu * T(2.0 / 3.0)));
             }
-        }
-        block_sums<NTP, 3>(sums, red, tid);
+        };
+        if (a.in_is_phi) count(std::true_type());
+        else count(std::false_type());
+        if constexpr (3 * NTP * sizeof(double) <= sizeof(buf))
+            block_sums_lds<NTP, 3>(sums, (double *)buf, red, tid);
+        else
+            block_sums<NTP, 3>(sums, red, tid);
         if (tid == 0) {
             part_ptr(a.part, b, SL_RHO, a.pstride)[i0] = sums[0];
             part_ptr(a.part, b, SL_TF, a.pstride)[i0] = sums[1];
@@ -1390,22 +1451,43 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             // element n (computing them in the first FFT stage instead puts the
             // transcendentals on the fewer threads that hold butterflies:
             // measured slower), then the axis-2 half-length transforms
-            auto field = [&](T v) -> T {
-                if (kind == FK_RAW) return v;
-                if (kind == FK_RHO) return a.in_is_phi ? v * v : v;
-                const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
-                if (kind == FK_PHI) return a.in_is_phi ? v : d_sqrt_fast(rho);
-                return rho > T(0) ? d_exp2(T(a.beta) * d_log2(rho)) : T(0);   // FK_RHOB
-            };
+            // (the field kind and the input kind are uniform: each pair is
+            // compiled separately so that a point computes only its own field)
+            auto fill = [&](auto kd, auto ph) {
+                constexpr int K = decltype(kd)::value;
+                constexpr bool P = decltype(ph)::value;
+                auto field = [&](T v) -> T {
+                    if constexpr (K == FK_RAW) return v;
+                    else if constexpr (K == FK_RHO) return P ? v * v : v;
+                    // (a negative density is counted by the prologue and
+                    // fails the evaluation: no clamp here)
+                    else if constexpr (K == FK_PHI) return P ? v : d_sqrt_fast(v);
+                    else return d_exp2(T(a.beta) * d_log2(P ? v * v : v));   // FK_RHOB; log2(0) = -inf
+                };
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const unsigned idx = (unsigned)(t + q * NTP);
-                if (idx >= (unsigned)PAIRS) continue;
-                const unsigned i1 = idx / (unsigned)M, n = idx % (unsigned)M;
-                cpx<T> xq;
-                if constexpr (STX) xq = xs[idx];
-                else xq = in[idx];
-                buf[n * A + i1] = {field(xq.x), field(xq.y)};
+                for (int q = 0; q < PER; ++q) {
+                    const unsigned idx = (unsigned)(t + q * NTP);
+                    if (idx >= (unsigned)PAIRS) continue;
+                    const unsigned i1 = idx / (unsigned)M, n = idx % (unsigned)M;
+                    cpx<T> xq;
+                    if constexpr (STX) xq = xs[idx];
+                    else xq = in[idx];
+                    buf[n * A + i1] = {field(xq.x), field(xq.y)};
+                }
+            };
+            using std::integral_constant;
+            using std::true_type;
+            using std::false_type;
+            if (a.in_is_phi) {
+                if (kind == FK_RHO) fill(integral_constant<int, FK_RHO>(), true_type());
+                else if (kind == FK_PHI) fill(integral_constant<int, FK_PHI>(), true_type());
+                else if (kind == FK_RHOB) fill(integral_constant<int, FK_RHOB>(), true_type());
+                else fill(integral_constant<int, FK_RAW>(), true_type());
+            } else {
+                if (kind == FK_RHO) fill(integral_constant<int, FK_RHO>(), false_type());
+                else if (kind == FK_PHI) fill(integral_constant<int, FK_PHI>(), false_type());
+                else if (kind == FK_RHOB) fill(integral_constant<int, FK_RHOB>(), false_type());
+                else fill(integral_constant<int, FK_RAW>(), false_type());
             }
             __syncthreads();
             lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
@@ -1426,7 +1508,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 if (k == 0) x.y = T(0);
                 return x;
             },
-            [&](unsigned n, unsigned p, cpx<T> v) { out[n * (M + 1) + p] = v; });
+            [&](unsigned n, unsigned p, cpx<T> v) { st32(out, n * (M + 1) + p, v); });
     }
 }
 
@@ -1444,7 +1526,7 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
     // axis 1: the first stage reads column k (element i1) straight from the
     // spectrum, spec[i1 * (M + 1) + k]
     lds_fft_src<T, N1, true, M + 1, NTP, 1, A>(
-        buf, tw1, tid, [&](unsigned n, unsigned p) { return spec[n * (M + 1) + p]; });
+        buf, tw1, tid, [&](unsigned n, unsigned p) { return ld32(spec, n * (M + 1) + p); });
     // axis 2: the first stage forms element n of row i1 of the half-length
     // input by the c2r pack Z[n] = (X[n] + conj X[M-n]) + i (X[n] - conj
     // X[M-n]) conj(W^n) (imaginary parts of X[0] and X[M] dropped)
@@ -1507,7 +1589,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     cpx<T> xin[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q)
-        xin[q] = tid + q * NTP < PAIRS ? in[tid + q * NTP] : cpx<T>{T(0), T(0)};
+        xin[q] = tid + q * NTP < PAIRS ? ld32(in, (unsigned)(tid + q * NTP)) : cpx<T>{T(0), T(0)};
 
     if constexpr (MODE == EP_KNOTS) {
         bool acc_init = a.acc_init != 0;
@@ -1582,34 +1664,6 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
     }
     __syncthreads();
-    // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
-    // A are exclusive and come last, so only H+ext and vW are ever held
-    // with vw_field set (general combine only: the host picks CF = 0 for it)
-    // the von Weizsaecker term arrives in real space
-    const bool vwf = CF == 0 && a.vw_field != nullptr;
-    const int all[4] = {a.fld_hext, vwf ? -1 : a.fld_vw, a.fld_wt, a.fld_a};
-    int last = -1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (all[k] >= 0) last = k;
-    cpx<T> fh[PER], fv[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) fh[q] = fv[q] = {T(0), T(0)};
-#pragma unroll 1
-    for (int k = 0; k < 4; ++k) {
-        if (all[k] < 0) continue;
-        const int t = opaque(tid);
-        plane_inverse<T, N1, M, NTP>(buf, spec_of(all[k]), tw1, twM, twN, t);
-        if (k == last) break;   // the last field stays in buf
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (t + q * NTP >= PAIRS) continue;
-            const cpx<T> z = buf[at(t, q)];
-            if (k == 0) fh[q] = z;
-            else fv[q] = z;
-        }
-        __syncthreads();
-    }
     const cpx<T> *acc1 = a.spline ? (const cpx<T> *)((const T *)a.acc1 + real_off) : nullptr;
     const cpx<T> *acc2 = (a.spline && a.exact) ? (const cpx<T> *)((const T *)a.acc2 + real_off)
                                                 : nullptr;
@@ -1617,30 +1671,125 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     cpx<T> *gout = a.g_out ? (cpx<T> *)((T *)a.g_out + real_off) : nullptr;
     const CombineConst<T> cc = combine_const<T>(a);
     double sums[combine_nsum<CF>()] = {};   // rho^a Phi, g phi, g^2, phi^2 (, rho eps_xc)
-    const int t = opaque(tid);
+    // fields in the order H+ext, vW, WT | EXACT-A (the present ones); WT and
+    // A are exclusive and come last, so only H+ext and vW are ever held
+    cpx<T> fh[PER], fv[PER];
+    if constexpr (CF != 0) {
+        // fixed term set: H+ext and vW are always present (the host picks a
+        // fixed set only then), the nonlocal field when NLF.  The transforms
+        // are unrolled, so the held fields need no per-field selects, and
+        // the input kind (phi or rho) is compiled into the point loop.
+        constexpr bool NLF = (CF & (CB_WT | CB_A)) != 0;
+        // LDS slot of pair q of thread t after the inverse: element (i1, n)
+        // at n * A + i1
+        auto uat = [&](int t, int q) {
+            const unsigned idx = (unsigned)(t + q * NTP);
+            return (idx % (unsigned)M) * (unsigned)A + idx / (unsigned)M;
+        };
+        auto hold = [&](cpx<T> (&f)[PER], int t) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int idx = t + q * NTP;
-        if (idx >= PAIRS) continue;
-        cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
-        if (acc1) s1 = acc1[idx];
-        if (acc2) s2 = acc2[idx];
-        cpx<T> xq;
-        if constexpr (STX) xq = xs[idx];
-        else xq = in[idx];
-        const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
-        const cpx<T> zh = last == 0 ? zl : fh[q];
-        cpx<T> zv = last == 1 ? zl : fv[q];
-        if constexpr (CF == 0) {
-            if (vwf) zv = ((const cpx<T> *)((const T *)a.vw_field + real_off))[idx];
+            for (int q = 0; q < PER; ++q)
+                if (t + q * NTP < PAIRS) f[q] = buf[uat(t, q)];
+        };
+        {
+            const int t = opaque(tid);
+            plane_inverse<T, N1, M, NTP>(buf, spec_of(a.fld_hext), tw1, twM, twN, t);
+            hold(fh, t);
+            __syncthreads();
         }
-        cpx<T> vo, go;
-        combine_point<T, CF>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x, sums);
-        combine_point<T, CF>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y, sums);
-        if (vout) vout[idx] = vo;
-        if (gout) gout[idx] = go;
+        {
+            const int t = opaque(tid);
+            plane_inverse<T, N1, M, NTP>(buf, spec_of(a.fld_vw), tw1, twM, twN, t);
+            if constexpr (NLF) {
+                hold(fv, t);
+                __syncthreads();
+            }
+        }
+        if constexpr (NLF) {
+            const int t = opaque(tid);
+            plane_inverse<T, N1, M, NTP>(buf, spec_of((CF & CB_WT) ? a.fld_wt : a.fld_a), tw1,
+                                         twM, twN, t);
+        }
+        auto points = [&](auto ph) {
+            constexpr int PH = decltype(ph)::value;
+            const int t = opaque(tid);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const unsigned idx = (unsigned)(t + q * NTP);
+                if (idx >= (unsigned)PAIRS) continue;
+                cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
+                if (acc1) s1 = ld32(acc1, idx);
+                if (acc2) s2 = ld32(acc2, idx);
+                cpx<T> xq;
+                if constexpr (STX) xq = xs[idx];
+                else xq = ld32(in, idx);
+                const cpx<T> zb = buf[uat(t, q)];
+                const cpx<T> zh = fh[q];
+                const cpx<T> zv = NLF ? fv[q] : zb;
+                const cpx<T> zl = NLF ? zb : cpx<T>{T(0), T(0)};
+                cpx<T> vo, go;
+                combine_point<T, CF, PH>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x,
+                                         sums);
+                combine_point<T, CF, PH>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y,
+                                         sums);
+                if (vout) st32(vout, idx, vo);
+                if (gout) st32(gout, idx, go);
+            }
+        };
+        if (a.in_is_phi) points(std::integral_constant<int, 1>());
+        else points(std::integral_constant<int, 0>());
+    } else {
+        // the von Weizsaecker term may arrive in real space (general combine
+        // only: the host picks CF = 0 for it)
+        const bool vwf = a.vw_field != nullptr;
+        const int all[4] = {a.fld_hext, vwf ? -1 : a.fld_vw, a.fld_wt, a.fld_a};
+        int last = -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (all[k] >= 0) last = k;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) fh[q] = fv[q] = {T(0), T(0)};
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            if (all[k] < 0) continue;
+            const int t = opaque(tid);
+            plane_inverse<T, N1, M, NTP>(buf, spec_of(all[k]), tw1, twM, twN, t);
+            if (k == last) break;   // the last field stays in buf
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                if (t + q * NTP >= PAIRS) continue;
+                const cpx<T> z = buf[at(t, q)];
+                if (k == 0) fh[q] = z;
+                else fv[q] = z;
+            }
+            __syncthreads();
+        }
+        const int t = opaque(tid);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = t + q * NTP;
+            if (idx >= PAIRS) continue;
+            cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
+            if (acc1) s1 = acc1[idx];
+            if (acc2) s2 = acc2[idx];
+            cpx<T> xq;
+            if constexpr (STX) xq = xs[idx];
+            else xq = in[idx];
+            const cpx<T> zl = last >= 0 ? buf[at(t, q)] : cpx<T>{T(0), T(0)};
+            const cpx<T> zh = last == 0 ? zl : fh[q];
+            cpx<T> zv = last == 1 ? zl : fv[q];
+            if (vwf) zv = ((const cpx<T> *)((const T *)a.vw_field + real_off))[idx];
+            cpx<T> vo, go;
+            combine_point<T, CF>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x, sums);
+            combine_point<T, CF>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y, sums);
+            if (vout) vout[idx] = vo;
+            if (gout) gout[idx] = go;
+        }
     }
-    block_sums<NTP, combine_nsum<CF>()>(sums, red, tid);
+    if constexpr (combine_nsum<CF>() * NTP * sizeof(double) <= sizeof(buf))
+        block_sums_lds<NTP, combine_nsum<CF>()>(sums, (double *)buf, red, tid);
+    else
+        block_sums<NTP, combine_nsum<CF>()>(sums, red, tid);
     if (tid == 0) {
         part_ptr(a.part, b, SL_NL, a.pstride)[i0] = sums[0];
         part_ptr(a.part, b, SL_GPHI, a.pstride)[i0] = sums[1];

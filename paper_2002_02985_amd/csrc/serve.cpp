@@ -375,9 +375,6 @@ void worker_loop(ofdft_server *s, int w)
             if (lr >= 0 && s->res[lr]->g && !s->res[lr]->busy &&
                 same_shape(s->res[lr]->cell, s->res[lr]->func, job->cell, job->func)) {
                 const Res &L = *s->res[lr];
-                uint64_t per = 0;   // workspace and staging of one more density
-                if (ofdft_footprint_bytes(&job->cell.d, &job->func, OFDFT_REQ_EP, &per) != OFDFT_OK)
-                    per = ~0ull >> 2;
                 std::unordered_set<uint64_t> seen;
                 seen.insert(job->cell_id);
                 for (size_t i = 0; i < s->queue.size() && (int)batch.size() + 1 < s->batch_max; ++i) {
@@ -394,7 +391,10 @@ void worker_loop(ofdft_server *s, int w)
                     if (!same_functional(R.func, L.func) || R.cell.d.n[0] != L.cell.d.n[0] ||
                         R.cell.d.n[1] != L.cell.d.n[1] || R.cell.d.n[2] != L.cell.d.n[2])
                         continue;
-                    if (s->used + per * (batch.size() + 1) > s->budget) break;
+                    // the leader's allocations grow to the batch (and stay)
+                    if (s->used + ofdft_internal::multi_growth_bytes(L.g, (int)batch.size() + 2) >
+                        s->budget)
+                        break;
                     batch.push_back(s->queue[i]);
                     batch_res.push_back(&R);
                 }
