@@ -457,7 +457,10 @@ void ofdft_server_destroy(ofdft_server *srv);
  * not used while per-pass timing is on.
  * The autotuner times the schedule choices -- fused plane kernels or
  * separate row and column passes where both apply, the block order of the
- * column passes, the number of spline knots per batch -- on nbatch densities
+ * column passes, the number of densities a column block serves (one, or a
+ * group of up to 8 sharing the tile's set-up and operands; batches of
+ * nbatch > 1 on short columns), the number of spline knots per batch -- on
+ * nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
  * density, nbatch 1), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
@@ -465,7 +468,8 @@ void ofdft_server_destroy(ofdft_server *srv);
 typedef struct {
     int32_t plane, col_tile_major, knot_batch, candidates;
     double best_ms, default_ms;   /* per evaluation call */
-    int32_t pipe, reserved;       /* the grid's sub-batch split (not tuned) */
+    int32_t pipe;                 /* the grid's sub-batch split (not tuned) */
+    int32_t col_group;            /* densities per column block (1 or up to 8) */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
 /* Spline knot range (step s1 on the device; on by default): before the knot
@@ -475,6 +479,13 @@ ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
  * interpolation skip every other knot, whose contributions are exact zeros.
  * Off transforms every knot (the same results: a check of the skipping). */
 ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on);
+/* Densities per column block of the reciprocal-space column pass on batches
+ * (the autotuner's choice, set by hand): 1, or up to 8 (a block then takes
+ * one tile for up to n densities, its set-up and per-element operands shared;
+ * used for columns of at most 8 elements per thread and batches that keep
+ * enough blocks).  Results are the same, bit for bit, for every n.
+ * OFDFT_EINVAL outside 1..8. */
+ofdft_status ofdft_grid_set_col_group(ofdft_grid *grid, int32_t n);
 ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
                                  void *hip_stream, ofdft_tune_result *result);

@@ -171,6 +171,7 @@ struct ofdft_grid {
     int tune_plane = 1;            // fused plane kernels where the plane fits in LDS
     int tune_kb = MAXKB;           // knots per spline batch
     int tune_pipe = 1;             // sub-batches pipelined over two streams
+    int tune_col_group = COL_GROUP;   // densities per column block (batches)
     // second stream of the pipelined evaluation and its events (created on
     // first use)
     hipStream_t s2 = nullptr;
@@ -671,6 +672,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.vext = g->vext;
     a.gtab = g->gtab;
     a.tile_major = g->tune_col_tile_major;
+    a.nbb = g->tune_col_group;
     a.use_h = (g->func.terms & OFDFT_TERM_HARTREE) ? 1 : 0;
     a.use_ext = (g->func.terms & OFDFT_TERM_EXT) ? 1 : 0;
     a.lambda_vw = g->func.lambda_vw;
@@ -2260,7 +2262,7 @@ static ofdft_status interpolate_density(ofdft_grid *dst, ofdft_grid *src)
 // keeps the fastest; results are shared by all grids of the same shape,
 // precision, functional and batch size in the process.
 struct TuneVal {
-    int plane, tile_major, kb, pipe;
+    int plane, tile_major, kb, pipe, cgrp;
 };
 using TuneKey = std::tuple<int, int, int, int, uint32_t, int, int, int>;
 static std::mutex g_tune_mu;
@@ -2282,6 +2284,7 @@ static void tune_apply_cached(ofdft_grid *g, int nb)
     g->tune_col_tile_major = it->second.tile_major;
     g->tune_kb = it->second.kb;
     g->tune_pipe = it->second.pipe;
+    g->tune_col_group = it->second.cgrp;
     graphs_clear(g);
 }
 
@@ -2300,7 +2303,9 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         if (!pl && !plane_ok) continue;
         for (int tm : {0, 1})
             for (int kb : {MAXKB, MAXKB / 2})
-                if (spline || kb == MAXKB) cand.push_back({pl, tm, kb, g->tune_pipe});
+                for (int cg : {COL_GROUP, 1})
+                    if ((spline || kb == MAXKB) && (nb > 1 || cg == COL_GROUP))
+                        cand.push_back({pl, tm, kb, g->tune_pipe, cg});
     }
     std::vector<ofdft_energy> e((size_t)nb);
     double best = 1e300, dflt = 0.0;
@@ -2310,6 +2315,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         g->tune_col_tile_major = cand[c].tile_major;
         g->tune_kb = cand[c].kb;
         g->tune_pipe = cand[c].pipe;
+        g->tune_col_group = cand[c].cgrp;
         graphs_clear(g);
         ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));   // warm-up
         double t[3];
@@ -2329,6 +2335,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
     g->tune_col_tile_major = pick.tile_major;
     g->tune_kb = pick.kb;
     g->tune_pipe = pick.pipe;
+    g->tune_col_group = pick.cgrp;
     graphs_clear(g);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2342,7 +2349,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         out->best_ms = best;
         out->default_ms = dflt;
         out->pipe = pick.pipe;
-        out->reserved = 0;
+        out->col_group = pick.cgrp;
     }
     return OFDFT_OK;
 }
@@ -3216,6 +3223,15 @@ ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on)
     if (!grid) return fail(OFDFT_EINVAL, "null grid");
     if ((on != 0) != grid->knot_skip) graphs_clear(grid);
     grid->knot_skip = on != 0;
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_set_col_group(ofdft_grid *grid, int32_t n)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null grid");
+    if (n < 1 || n > COL_GROUP) return fail(OFDFT_EINVAL, "column group outside 1..8");
+    if (n != grid->tune_col_group) graphs_clear(grid);
+    grid->tune_col_group = n;
     return OFDFT_OK;
 }
 

@@ -103,6 +103,9 @@ struct CellTab {
 
 // strided column pass along axis 1 or 0 (c2c), optionally with a fused
 // reciprocal-space operation between a forward and an inverse transform
+// most densities one column block serves (the autotuner's other choice is 1)
+constexpr int COL_GROUP = 8;
+
 struct ColArgs {
     void *data;                 // out; field fb at data + fb * fstride
     const void *src;            // in (may equal data)
@@ -126,6 +129,8 @@ struct ColArgs {
     int knot0;                  // knots outside the density's range return at once
     const CellTab *ct;          // reciprocal-space ops of a multi-cell batch: entry b's
                                 // b-vectors, v_ext and tables (null: g, vext, gtab)
+    int nbb;                    // densities per block: requested (at most
+                                // COL_GROUP; 0 or 1 = one), then as launched
 };
 
 // axis-0 spline kernels: per-knot inverse of omega_i rho^b(G), and the EXACT

@@ -54,6 +54,9 @@ constexpr int pow2_floor(int x)
 // CU, which measured faster than 32-wide tiles on both the 96-point and the
 // 256-point column passes
 constexpr int COL_PMAX = 16;
+// grouped column blocks (COL_GROUP densities, sharing the tile's set-up
+// and operands) only while the launch keeps at least COL_MIN_BLOCKS blocks
+constexpr long long COL_MIN_BLOCKS = 8192;
 template <typename T, int L> constexpr int col_P()
 {
     int p = pow2_floor(Cfg<T>::COL_ELEMS / L);
@@ -95,6 +98,12 @@ template <typename T, int L, int P> constexpr int col_NT()
     if (t < NT) t = NT;
     if (t > 1024) t = 1024;
     return t;
+}
+// grouped column kernels are built for the column lengths whose operands
+// take at most 8 registers per thread (the batched small grids)
+template <typename T, int L> constexpr bool col_grouped()
+{
+    return L * col_P<T, L>() / col_NT<T, L, col_P<T, L>()>() <= 8;
 }
 template <typename T, int L> constexpr int knot_NT()
 {
@@ -240,6 +249,16 @@ __device__ __forceinline__ int opaque(int t)
 {
     asm volatile("" : "+v"(t));
     return t;
+}
+__device__ __forceinline__ float opaque_v(float x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ double opaque_v(double x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
 }
 template <typename T>
 __device__ __forceinline__ cpx<T> opaque(cpx<T> z)
@@ -448,21 +467,30 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 // one tile of every (field, density) array, which keeps the tile's share of
 // the reciprocal-space tables in L2).
 // MC: a multi-cell batch (per-entry reciprocal vectors and tables from a.ct)
-template <typename T, int L, int P, bool MC = false>
+template <typename T, int L, int P, bool MC = false, bool GRP = false>
 __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb, int ntiles)
 {
     constexpr int NT = col_NT<T, L, P>();   // this kernel's block size
     constexpr int RSTEP = NT / P;
     constexpr int PER = (L + RSTEP - 1) / RSTEP;
     static_assert(NT % P == 0, "tile width must divide the block");
+    static_assert(!(GRP && MC), "a multi-cell batch has one density per block");
     __shared__ cpx<T> buf[L * P];
     __shared__ cpx<T> tws[L];     // W_L^n, read by every stage
     __shared__ double red[NT];
     const int tid = threadIdx.x;
-    const int fb = a.tile_major ? (int)(blockIdx.x % (unsigned)nfb)
+    // a block serves one tile of one field for the densities b0 .. b1 - 1
+    // (GRP: a.nbb of them, else one; nfb counts (field, group) pairs): the
+    // tile's set-up and its per-element operands are shared by the group
+    const int nbb = GRP && a.nbb > 1 ? a.nbb : 1;
+    const int nbg = (a.nbatch + nbb - 1) / nbb;
+    const int fg = a.tile_major ? (int)(blockIdx.x % (unsigned)nfb)
                                 : (int)(blockIdx.x / (unsigned)ntiles);
     const int tile = a.tile_major ? (int)(blockIdx.x / (unsigned)nfb)
                                   : (int)(blockIdx.x % (unsigned)ntiles);
+    const int field = fg / nbg;
+    const int b0 = (fg % nbg) * nbb;
+    const int b1 = b0 + nbb < a.nbatch ? b0 + nbb : a.nbatch;
     const int p = tid % P;
     // column indices in 32 bits (a field holds fewer than 2^32 elements)
     const unsigned c0 = (unsigned)tile * (unsigned)P;
@@ -471,142 +499,172 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     unsigned cq, cr;
     tile_divmod(c0, (unsigned)p, (unsigned)a.inner, cq, cr);
     const unsigned cbase = cvalid ? cq * (unsigned)a.outer_stride + cr : 0u;
-    const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
-    cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
     const cpx<T> *tw = tws;
-    const int field = fb / a.nbatch;
-    const int b = fb % a.nbatch;
     const int op = field < MAXKB ? a.op[field] : GO_NONE;
-    if (a.kneed) {
-        // a knot spectrum outside the density's knot range is not needed
-        const int kn = a.knot0 + field;
-        if (kn < a.kneed[2 * b] || kn > a.kneed[2 * b + 1]) return;
-    }
 
     for (int i = tid; i < L; i += NT) tws[i] = ((const cpx<T> *)a.tw)[i];
     // the first stage of a transform reads element n of this thread's column
     // from memory and the last one writes it back (the stages assign
     // pencil p = tid % P to this thread, as NT is a multiple of P)
-    // 32-bit element offsets (a field holds fewer than 2^32 elements); a
-    // column past the end reads column 0 and writes nothing
-    const unsigned cofs = cvalid ? (unsigned)cbase : 0u;
+    // a column past the end reads column 0 and writes nothing
+    const unsigned cofs = cvalid ? cbase : 0u;
     const unsigned es = (unsigned)a.elem_stride;
-    auto ld = [&](unsigned n, unsigned) { return src[(size_t)(cofs + n * es)]; };
-    auto st = [&](unsigned n, unsigned, cpx<T> v) {
-        if (cvalid) dst[(size_t)(cofs + n * es)] = v;
-    };
-    // reciprocal-space operands are fetched now so that their latency overlaps
-    // the forward transform: v_ext(G) for the Hartree+ion field, the
-    // Wang-Teter kernel for the nonlocal field (element n of column c is the
-    // half-spectrum point e = n * ncols + c on axis 0)
     // the wide-tile instantiation (P != col_P) serves plain passes only
     constexpr bool OPS = P == col_P<T, L>();
-    cpx<T> pre[OPS ? PER : 1];
+    Geom g = a.g;
     const void *vext_b = a.vext, *gtab_b = a.gtab;
     if constexpr (MC) {
-        vext_b = a.ct[b].vext;
-        gtab_b = a.ct[b].gtab;
-    }
-    if (OPS && (op == GO_HEXT || op == GO_WT)) {
-        const cpx<T> *vx = (const cpx<T> *)vext_b;
-        const T *om = (const T *)gtab_b + 2 * a.g.Nh;
+        vext_b = a.ct[b0].vext;
+        gtab_b = a.ct[b0].gtab;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int n = tid / P + q * RSTEP;
-            pre[q] = {T(0), T(0)};
-            if (n < L && cvalid) {
-                const unsigned e = (unsigned)n * (unsigned)a.ncols + c;
-                if (op == GO_HEXT) {
-                    if (a.use_ext) pre[q] = vx[(size_t)e];
-                } else {
-                    pre[q].x = om[(size_t)e];
-                }
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b0].b[i][j];
+    }
+    unsigned u1, u2;
+    tile_divmod(c0, (unsigned)p, (unsigned)g.n2h, u1, u2);
+    const int i1 = cvalid ? (int)u1 : 0;
+    const int k2 = cvalid ? (int)u2 : 0;
+    const int m1 = freq(i1, g.n1);
+    const int m2 = (k2 == g.m) ? -g.m : k2;
+    // the per-element operand of the field's reciprocal-space operation
+    // (element n of column c is the half-spectrum point e = n * ncols + c on
+    // axis 0): 1/G^2 (Hartree+ion; 0 at G = 0), G^2 (vW), the Wang-Teter
+    // kernel, the preconditioner factor (1 at G = 0), 1 (scale)
+    auto operand = [&](int q) -> T {
+        const int n = tid / P + q * RSTEP;
+        if (n >= L || !cvalid) return T(0);
+        const unsigned e = (unsigned)n * (unsigned)a.ncols + c;
+        if (op == GO_WT) return ((const T *)gtab_b + 2 * a.g.Nh)[(size_t)e];
+        if (op == GO_SCALE) return T(1);
+        const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
+        if (op == GO_HEXT) return G2 > T(0) ? d_rcp(G2) : T(0);
+        if (op == GO_VW) return G2;
+        const T q2 = T(a.precond_q2);   // GO_PRECOND
+        return G2 > T(0) ? q2 / (G2 + q2 + T(a.precond_h) / G2) : T(1);
+    };
+    // grouped: the operands are kept in LDS (registers held across the
+    // densities would cost occupancy); the first transform's barrier
+    // publishes them
+    __shared__ T opl[GRP && OPS ? L * P : 1];
+    if constexpr (GRP && OPS) {
+        if (op != GO_NONE) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int n = tid / P + q * RSTEP;
+                if (n < L) opl[n * P + p] = operand(q);
             }
         }
     }
     constexpr bool MULTI = make_plan(L, sizeof(T) == 4).n >= 2;
-    if (!OPS || op == GO_NONE) {
-        if constexpr (MULTI) {
-            if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1>(buf, tw, tid, ld, st);
-            else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tid, ld, st);
-            return;
-        } else {
-            for (int n = tid / P; n < L; n += RSTEP) buf[n * P + p] = ld(n, p);
-            __syncthreads();
-            if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tid);
-            else lds_fft<T, L, false, P, NT, P>(buf, tw, tid);
+    const double wgt = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
+    const T invN = T(g.invN);
+    const T fourpi = T(4.0 * PI_D);
+#pragma unroll 1
+    for (int b = b0; b < b1; ++b) {
+        if (a.kneed) {
+            // a knot spectrum outside the density's knot range is not needed
+            const int kn = a.knot0 + field;
+            if (kn < a.kneed[2 * b] || kn > a.kneed[2 * b + 1]) continue;   // uniform
         }
-    } else if constexpr (OPS) {
-        // axis 0: element n is i0, column c is (i1, k2)
-        lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tid, ld);
-        Geom g = a.g;
-        if constexpr (MC) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) g.b[i][j] = a.ct[b].b[i][j];
+        const long long fb = (long long)field * a.nbatch + b;
+        const cpx<T> *src = (const cpx<T> *)a.src + fb * a.fstride;
+        cpx<T> *dst = (cpx<T> *)a.data + fb * a.fstride;
+        // per density, everything that depends on the thread is derived from
+        // an opaque copy of its index: recomputed here rather than hoisted
+        // out of the loop and held in registers
+        const int tl = GRP ? opaque(tid) : tid;
+        const int pl = tl % P;
+        const unsigned cl = c0 + (unsigned)pl;
+        const bool cv = cl < (unsigned)a.ncols;
+        unsigned co = cofs;
+        if constexpr (GRP) {
+            unsigned q1, r1;
+            tile_divmod(c0, (unsigned)pl, (unsigned)a.inner, q1, r1);
+            co = cv ? q1 * (unsigned)a.outer_stride + r1 : 0u;
         }
-        const int t = opaque(tid);
-        unsigned u1, u2;
-        tile_divmod(c0, (unsigned)p, (unsigned)g.n2h, u1, u2);
-        const int i1 = cvalid ? (int)u1 : 0;
-        const int k2 = cvalid ? (int)u2 : 0;
-        const int m1 = freq(i1, g.n1);
-        const int m2 = (k2 == g.m) ? -g.m : k2;
-        const double wgt = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
-        const T invN = T(g.invN);
-        const T fourpi = T(4.0 * PI_D);
-        double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int n = t / P + q * RSTEP;
-            if (n >= L || !cvalid) continue;
-            const cpx<T> F = cscale(buf[n * P + p], invN);
-            cpx<T> o = {T(0), T(0)};
-            if (op == GO_HEXT) {
-                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
-                const T ih = G2 > T(0) ? d_rcp(G2) : T(0);
-                s0 += wgt * (double)((F.x * F.x + F.y * F.y) * ih);
-                if (a.use_h) o = cscale(F, fourpi * ih);
-                if (a.use_ext) {
-                    const cpx<T> v = pre[q];
-                    s1 += wgt * (double)(v.x * F.x + v.y * F.y);
-                    o = cadd(o, v);
-                }
-            } else if (op == GO_VW) {
-                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
-                s0 += wgt * (double)(G2 * (F.x * F.x + F.y * F.y));
-                o = cscale(F, T(a.lambda_vw) * G2);
-            } else if (op == GO_WT) {
-                o = cscale(F, pre[q].x);
-            } else if (op == GO_PRECOND) {
-                const T G2 = gvec2<T>(g, freq(n, L), m1, m2);
-                const T q2 = T(a.precond_q2);
-                o = G2 > T(0) ? cscale(F, q2 / (G2 + q2 + T(a.precond_h) / G2)) : F;
-            } else {  // GO_SCALE
-                o = F;
+        auto ld = [&](unsigned n, unsigned) { return src[(size_t)(co + n * es)]; };
+        auto st = [&](unsigned n, unsigned, cpx<T> v) {
+            if (cv) dst[(size_t)(co + n * es)] = v;
+        };
+        if (!OPS || op == GO_NONE) {
+            if constexpr (MULTI) {
+                // starts and ends with a barrier
+                if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1>(buf, tw, tl, ld, st);
+                else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tl, ld, st);
+                continue;
+            } else {
+                __syncthreads();
+                for (int n = tl / P; n < L; n += RSTEP) buf[n * P + pl] = ld(n, pl);
+                __syncthreads();
+                if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tl);
+                else lds_fft<T, L, false, P, NT, P>(buf, tw, tl);
             }
-            buf[n * P + p] = o;
-        }
-        if (op == GO_HEXT || op == GO_VW) {
-            double ss[2] = {s0, s1};
-            block_sums<NT, 2>(ss, red, tid);
-            if (tid == 0) {
+        } else if constexpr (OPS) {
+            // v_ext(G) of the Hartree+ion field, fetched now so that its
+            // latency overlaps the forward transform
+            cpx<T> pre[PER];
+            if (op == GO_HEXT && a.use_ext) {
+                const cpx<T> *vx = (const cpx<T> *)vext_b;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    const int n = tl / P + q * RSTEP;
+                    pre[q] = (n < L && cv) ? vx[(size_t)((unsigned)n * (unsigned)a.ncols + cl)]
+                                           : cpx<T>{T(0), T(0)};
+                }
+            }
+            // axis 0: element n is i0, column c is (i1, k2)
+            lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tl, ld);
+            const int t = opaque(tl);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int n = t / P + q * RSTEP;
+                if (n >= L || !cv) continue;
+                T w;
+                if constexpr (GRP) w = opl[n * P + pl];
+                else w = operand(q);
+                const cpx<T> F = cscale(buf[n * P + pl], invN);
+                cpx<T> o;
                 if (op == GO_HEXT) {
-                    part_ptr(a.part, b, SL_H, a.pstride)[tile] = ss[0];
-                    part_ptr(a.part, b, SL_EXT, a.pstride)[tile] = ss[1];
-                } else {
-                    part_ptr(a.part, b, SL_VW, a.pstride)[tile] = ss[0];
+                    s0 += wgt * (double)((F.x * F.x + F.y * F.y) * w);
+                    o = a.use_h ? cscale(F, fourpi * w) : cpx<T>{T(0), T(0)};
+                    if (a.use_ext) {
+                        const cpx<T> v = pre[q];
+                        s1 += wgt * (double)(v.x * F.x + v.y * F.y);
+                        o = cadd(o, v);
+                    }
+                } else if (op == GO_VW) {
+                    s0 += wgt * (double)(w * (F.x * F.x + F.y * F.y));
+                    o = cscale(F, T(a.lambda_vw) * w);
+                } else if (op == GO_SCALE) {
+                    o = F;
+                } else {   // GO_WT, GO_PRECOND
+                    o = cscale(F, w);
+                }
+                buf[n * P + pl] = o;
+            }
+            if (op == GO_HEXT || op == GO_VW) {
+                double ss[2] = {s0, s1};
+                block_sums<NT, 2>(ss, red, tl);
+                if (tl == 0) {
+                    if (op == GO_HEXT) {
+                        part_ptr(a.part, b, SL_H, a.pstride)[tile] = ss[0];
+                        part_ptr(a.part, b, SL_EXT, a.pstride)[tile] = ss[1];
+                    } else {
+                        part_ptr(a.part, b, SL_VW, a.pstride)[tile] = ss[0];
+                    }
                 }
             }
+            __syncthreads();
+            if (op != GO_SCALE) {
+                lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tl, st);   // ends with a barrier
+                continue;
+            }
         }
+        for (int n = tl / P; n < L; n += RSTEP) st(n, pl, buf[n * P + pl]);
         __syncthreads();
-        if (op != GO_SCALE) {
-            lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tid, st);
-            return;
-        }
     }
-    for (int n = tid / P; n < L; n += RSTEP) st(n, p, buf[n * P + p]);
 }
 
 // ================================================================ spline, axis 0
@@ -1956,14 +2014,33 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
     }
     nblocks = (int)((a.ncols + P - 1) / P);
     if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
-    const long long total = (long long)nblocks * nfb;
+    // a block takes a tile of the same field for COL_GROUP densities where
+    // that still leaves at least COL_MIN_BLOCKS blocks (not for multi-cell
+    // batches, whose densities have tables of their own)
+    ColArgs ag = a;
+    ag.nbb = 1;
+    const int nfields = nfb / (a.nbatch > 0 ? a.nbatch : 1);
+    if constexpr (col_grouped<T, L>()) {
+        if (!a.ct && !plain && a.nbatch > 1 && a.nbb > 1) {
+            const int want = a.nbb < COL_GROUP ? a.nbb : COL_GROUP;
+            int nbb = want < a.nbatch ? want : a.nbatch;
+            while (nbb > 1 &&
+                   (long long)nblocks * nfields * ((a.nbatch + nbb - 1) / nbb) < COL_MIN_BLOCKS)
+                nbb /= 2;
+            ag.nbb = nbb;
+        }
+    }
+    const int nfg = nfields * ((a.nbatch + ag.nbb - 1) / ag.nbb);
+    const long long total = (long long)nblocks * nfg;
     if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total), block(col_NT<T, L, P>());
     if (a.ct && !plain)
-        hipLaunchKernelGGL((k_col<T, L, P, true>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0,
-                           s, a, nfb, nblocks);
-    else
-        hipLaunchKernelGGL((k_col<T, L, P>), dim3((unsigned)total), dim3(col_NT<T, L, P>()), 0, s,
-                           a, nfb, nblocks);
+        hipLaunchKernelGGL((k_col<T, L, P, true>), grid, block, 0, s, ag, nfg, nblocks);
+    else if (ag.nbb > 1) {
+        if constexpr (col_grouped<T, L>())
+            hipLaunchKernelGGL((k_col<T, L, P, false, true>), grid, block, 0, s, ag, nfg, nblocks);
+    } else
+        hipLaunchKernelGGL((k_col<T, L, P>), grid, block, 0, s, ag, nfg, nblocks);
     return hipGetLastError();
 }
 

@@ -398,6 +398,15 @@ void worker_loop(ofdft_server *s, int w)
                     batch.push_back(s->queue[i]);
                     batch_res.push_back(&R);
                 }
+                if (!batch.empty()) {
+                    // count the growth now, so that admissions and other
+                    // batches made while this one runs see it
+                    const uint64_t grow =
+                        ofdft_internal::multi_growth_bytes(L.g, (int)batch.size() + 1);
+                    s->used += grow;
+                    s->res[lr]->bytes += grow;
+                    s->peak = std::max(s->peak, s->used);
+                }
             }
         }
         s->queue.erase(s->queue.begin() + d.job);
@@ -502,7 +511,8 @@ void worker_loop(ofdft_server *s, int w)
 
         lk.lock();
         if (!batch.empty()) {
-            // the leader's workspace grew with the batch: count it
+            // the leader's growth was counted when the batch was formed; the
+            // device's own count can only confirm it
             const uint64_t now = ofdft_grid_device_bytes(r->g);
             if (now > r->bytes) {
                 s->used += now - r->bytes;
