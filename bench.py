@@ -132,6 +132,9 @@ def parse():
                          "request server (closed loop, then Poisson arrivals)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", default="8,1",
+                    help="largest batch of energy+potential and of optimisation requests "
+                         "(1 = each request alone)")
     ap.add_argument("--serve-qps", default="0.7",
                     help="comma-separated fractions of the closed-loop rate for the "
                          "Poisson phases")
@@ -302,7 +305,7 @@ def cpu_baseline(cell, dens, nsample, xc=False):
     return np.array(walls), np.array(cpus), np.array(es), vs
 
 
-def serve_run(ofdft, reqs, slots, arrivals=None, precision=None):
+def serve_run(ofdft, reqs, slots, arrivals=None, precision=None, batching=(8, 1)):
     """Runs the request stream through a fresh server.  arrivals: submit
     times in s (None: all at once, closed loop).  A poller thread collects
     results as they finish.  Returns (wall s, stats, statuses, evals,
@@ -314,6 +317,7 @@ def serve_run(ofdft, reqs, slots, arrivals=None, precision=None):
     fd = ofdft.make_functional_desc(terms, precision=precision)
     ctx = ofdft.ofdft_ctx_create(0)
     srv = ofdft.ofdft_server_create(ctx, 0, slots)
+    ofdft.ofdft_serve_set_batching(srv, batching[0], batching[1])
     tickets = [None] * len(reqs)
     ready = threading.Semaphore(0)
     out = {"status": [None] * len(reqs), "evals": [0] * len(reqs), "e": [0.0] * len(reqs)}
@@ -381,12 +385,14 @@ def serve_main(args):
         w["kind"] = ofdft.REQ_EP
         w["rho"] = None
         warm.append(w)
-    serve_run(ofdft, warm, args.serve_slots)
-    serve_run(ofdft, warm, args.serve_slots, precision=ofdft.FP64)
+    batching = tuple(int(x) for x in args.serve_batch.split(","))
+    serve_run(ofdft, warm, args.serve_slots, batching=batching)
+    serve_run(ofdft, warm, args.serve_slots, precision=ofdft.FP64, batching=batching)
 
     def closed(slots, precision, tag):
         log("closed loop, %d slot(s), %s" % (slots, tag))
-        wall, st, sts, ev, es = serve_run(ofdft, reqs, slots, precision=precision)
+        wall, st, sts, ev, es = serve_run(ofdft, reqs, slots, precision=precision,
+                                          batching=batching)
         return wall, st, sts, ev, es
 
     def phase(wall, st, sts, ev):
@@ -417,7 +423,7 @@ def serve_main(args):
         arr = np.cumsum(rng.exponential(1.0 / qps, size=len(reqs)))
         arr -= arr[0]
         log("Poisson arrivals at %.2f req/s (%.2f of closed loop)" % (qps, frac))
-        wall, st, sts, ev, _ = serve_run(ofdft, reqs, args.serve_slots, arr)
+        wall, st, sts, ev, _ = serve_run(ofdft, reqs, args.serve_slots, arr, batching=batching)
         phases["poisson_%.2f" % frac] = {
             "qps": round(qps, 2), "wall_s": round(wall, 3),
             "req_per_s": round(len(reqs) / wall, 2),
@@ -459,7 +465,8 @@ def serve_main(args):
                                "MD frames displaced N(0, 0.1 Bohr), TF+vW+Hartree+local "
                                "pseudopotential" % (len(reqs), grids, args.serve_tol,
                                                     args.serve_max_iter),
-                   "kinds": kinds, "slots": args.serve_slots},
+                   "kinds": kinds, "slots": args.serve_slots,
+                   "max_batch_ep_opt": list(batching)},
         "phases": phases,
         "mixed_vs_fp64": versus,
         "overlap_speedup": round(best["req_per_s"] / phases["closed_1"]["req_per_s"], 3)

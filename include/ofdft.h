@@ -333,6 +333,25 @@ typedef struct {
 ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params,
                             ofdft_opt_result *result);
 
+/* Lockstep optimisation of the resident densities of n different cells (the
+ * serving loop's batches of optimisation requests; Section "Density
+ * optimization strategies" per cell): each grid runs ofdft_optimize with its
+ * own params[b] in a host thread of its own on a stream of its own, and the
+ * evaluations the optimisers ask for are merged: an evaluation waits until
+ * every member still optimising has asked for one, and they run as one
+ * batched evaluation (as ofdft_energy_potential_multi, with phi as input
+ * and dE/dphi as output), so every kernel launch serves all members.  Each
+ * result is the same, bit for bit, as ofdft_optimize on that grid alone.
+ * The grids must satisfy the conditions of ofdft_energy_potential_multi and
+ * each hold a resident density; on return each holds its optimised density.
+ * statuses[b] receives the member's ofdft_optimize status (OFDFT_OK,
+ * OFDFT_ENOCONV, ...; ofdft_last_error() then names the first failing
+ * member); the call returns OFDFT_OK when the members ran, OFDFT_EINVAL for
+ * bad arguments.  None of the grids may be in use by another thread. */
+ofdft_status ofdft_optimize_multi(ofdft_grid *const *grids, int32_t n,
+                                  const ofdft_opt_params *params, ofdft_opt_result *results,
+                                  ofdft_status *statuses);
+
 /* Multi-step density optimisation (Section "Density optimization
  * strategies": a full optimisation on a coarse grid, the converged density
  * interpolated onto a finer grid, and the optimisation continued there).
@@ -384,13 +403,16 @@ ofdft_status ofdft_optimize_multistep(ofdft_grid *const *grids, int32_t ngrids,
  * grids still run.  A footprint above the whole budget is refused at submit
  * with OFDFT_ENOMEM.
  *
- * Continuous batching: when a worker takes an energy+potential request whose
- * cell's grid is resident, it also takes further queued energy+potential
- * requests of other resident cells with the same grid shape and functional
- * (each the earliest queued request of its cell), up to 8, and serves them
- * in one batched evaluation (ofdft_energy_potential_multi) if the leading
- * grid's larger workspace fits in the budget; results are the same as
- * alone.
+ * Continuous batching: when a worker takes an energy+potential or (if
+ * enabled, ofdft_serve_set_batching) an optimisation request whose cell's
+ * grid is resident, it also takes further
+ * queued requests of the same kind of other resident cells with the same
+ * grid shape and functional (each the earliest queued request of its cell),
+ * up to 8, and serves them together -- one batched evaluation
+ * (ofdft_energy_potential_multi), or one lockstep optimisation
+ * (ofdft_optimize_multi) -- if the leading grid's larger workspace fits in
+ * the budget (the growth is counted from the moment the batch is formed);
+ * results are the same as alone.
  *
  * Request kinds and results:
  *   EP        energy and potential of rho_or_null, else of the resident
@@ -443,6 +465,14 @@ ofdft_status ofdft_serve_poll(ofdft_server *srv, uint64_t ticket, ofdft_opt_resu
 ofdft_status ofdft_serve_wait(ofdft_server *srv, uint64_t ticket, int32_t timeout_ms);
 ofdft_status ofdft_serve_cancel(ofdft_server *srv, uint64_t ticket);
 ofdft_status ofdft_serve_stats_get(ofdft_server *srv, ofdft_serve_stats *out);
+/* Largest batch of energy+potential requests and of optimisation requests
+ * (continuous batching above; defaults 8 and 1; 1 serves each request alone,
+ * at most OFDFT_MULTI_MAX).  Lockstep optimisation batches are off by
+ * default: on the mixed serving workload several worker slots running
+ * optimisations side by side keep the device busier than one slot running
+ * them in lockstep.  Applies to batches formed after the call.
+ * OFDFT_EINVAL outside 1..OFDFT_MULTI_MAX. */
+ofdft_status ofdft_serve_set_batching(ofdft_server *srv, int32_t max_ep, int32_t max_opt);
 void ofdft_server_destroy(ofdft_server *srv);
 
 /* Launch schedule.  An evaluation's launch sequence can be replayed from a HIP

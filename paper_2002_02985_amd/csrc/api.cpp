@@ -6,6 +6,9 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <thread>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -159,6 +162,7 @@ struct ofdft_grid {
     double *h_sums = nullptr;   // pinned
     // resident density and optimiser vectors (N each)
     void *rho = nullptr;
+    bool rho_set = false;   // the resident density has been written
     void *opt[NVEC_OPT] = {nullptr};
     size_t bytes = 0;
     double *d_forces = nullptr;   // natoms x 3
@@ -178,6 +182,8 @@ struct ofdft_grid {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_stagger = nullptr;
     bool stagger_after_fwd = false;
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
+    struct EvalBatcher *batcher = nullptr;      // lockstep optimisation: evaluations merged
+    hipStream_t opt_stream = nullptr;           // the optimiser's stream (else the context's)
     double precond_q2 = 1.0;                    // optimiser preconditioner q0^2
     bool large_ions = false;                    // tiled structure factor, binned Ewald
     bool use_graphs = false;                    // replay evaluations from HIP graphs
@@ -192,6 +198,9 @@ struct ofdft_grid {
     // vectors, real fields and two half spectra, and the dipole partials
     void *td = nullptr;
     double *d_td_part = nullptr;
+    double *d_td_dots = nullptr;   // 4 x td_dot_blocks partials of the solver's dot products
+    double *d_td_sc = nullptr;     // the solver's scalars (TS_N)
+    double *h_td_sc = nullptr;     // pinned host copy
 };
 
 // ---------------------------------------------------------------- helpers
@@ -1311,6 +1320,10 @@ static void grid_free(ofdft_grid *g)
     graphs_clear(g);
     dfree(g->td);
     dfree(reinterpret_cast<void *&>(g->d_td_part));
+    dfree(reinterpret_cast<void *&>(g->d_td_dots));
+    dfree(reinterpret_cast<void *&>(g->d_td_sc));
+    if (g->h_td_sc) (void)hipHostFree(g->h_td_sc);
+    g->h_td_sc = nullptr;
     dfree(g->tw0);
     dfree(g->tw1);
     dfree(g->twM);
@@ -1942,6 +1955,11 @@ static double cubic_min(double a, double fa, double da, double b, double fb, dou
     return b - (b - a) * (db + d2 - d1) / den;
 }
 
+// The optimiser's evaluation of phi (dE/dphi to gout): directly, or, in a
+// lockstep optimisation, merged with the other members' evaluations
+static ofdft_status opt_eval(ofdft_grid *g, const void *phi, void *gout, hipStream_t s,
+                            ofdft_energy *e);
+
 // Truncated-Newton direction (Section "Density optimization strategies":
 // the paper's TN, a line-search Newton-CG method) on the tangent space of
 // the constraint <phi, phi> dv = N_e: preconditioned CG on H_T d = -R with
@@ -1977,7 +1995,7 @@ static ofdft_status tn_direction(OptState &o, void **v, const ofdft_energy &E, i
         const double h = eta_fd * std::sqrt(pp / w[0]);
         ST_TRY(lincomb<T>(o, v[V_PT], 1.0, v[V_PHI], h, v[V_ZP]));
         ofdft_energy Et;
-        ST_TRY(eval_dispatch(g, 1, v[V_PT], 1, nullptr, v[V_GT], s, &Et));
+        ST_TRY(opt_eval(g, v[V_PT], v[V_GT], s, &Et));
         ++evals;
         ST_TRY(lincomb<T>(o, v[V_P], 1.0 / h, v[V_GT], -1.0 / h, v[V_G]));
         ST_TRY(lincomb<T>(o, v[V_P], 1.0, v[V_P], -2.0 * E.mu, v[V_ZP]));
@@ -2007,7 +2025,7 @@ static ofdft_status tn_direction(OptState &o, void **v, const ofdft_energy &E, i
 template <typename T>
 static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, ofdft_opt_result *res)
 {
-    hipStream_t s = g->ctx->stream;
+    hipStream_t s = g->opt_stream ? g->opt_stream : g->ctx->stream;
     const Geom &G = g->geom;
     OptState o{g, s, G.N};
     ST_TRY(reserve(g, 1));
@@ -2037,7 +2055,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     ST_TRY(lincomb<T>(o, v[V_PHI], std::sqrt(ne / (dv * pp)), v[V_PHI], 0.0, nullptr));
 
     ofdft_energy E;
-    ST_TRY(eval_dispatch(g, 1, v[V_PHI], 1, nullptr, v[V_G], s, &E));
+    ST_TRY(opt_eval(g, v[V_PHI], v[V_G], s, &E));
     int evals = 1, iter = 0;
     bool have_prev = false, converged = false;
     double kappa = -1.0, theta_prev = -1.0;
@@ -2097,7 +2115,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
         ofdft_energy Et;
         auto trial = [&](double th, double &f, double &df) -> ofdft_status {
             ST_TRY(lincomb<T>(o, v[V_PT], std::cos(th), v[V_PHI], std::sin(th), v[V_P]));
-            ST_TRY(eval_dispatch(g, 1, v[V_PT], 1, nullptr, v[V_GT], s, &Et));
+            ST_TRY(opt_eval(g, v[V_PT], v[V_GT], s, &Et));
             ++evals;
             double gd[2];
             ST_TRY(dots<T>(o, 2, v[V_GT], v[V_PHI], v[V_GT], v[V_P], nullptr, nullptr, gd));
@@ -2191,6 +2209,7 @@ static ofdft_status optimize_impl(ofdft_grid *g, const ofdft_opt_params *prm, of
     // leave the optimised density resident: rho = phi^2
     TIMED(PS_OTHER, launch_pointwise<T>(G.N, PW_SQUARE, g->rho, v[V_PHI], s));
     HIP_TRY(hipStreamSynchronize(s));
+    g->rho_set = true;
     res->e = E;
     res->iters = iter;
     res->evals = evals;
@@ -2230,6 +2249,7 @@ static ofdft_status interp_impl(ofdft_grid *dst, ofdft_grid *src)
     g = dst;
     TIMED(PS_OTHER, launch_pointwise<T>(Gd.N, PW_SQUARE, dst->rho, dst->opt[V_PHI], s));
     HIP_TRY(hipStreamSynchronize(s));
+    dst->rho_set = true;
     return OFDFT_OK;
 }
 
@@ -2248,7 +2268,7 @@ static ofdft_status interpolate_density(ofdft_grid *dst, ofdft_grid *src)
                 1e-12 * (1.0 + std::fabs(src->lattice[i][j])))
                 return fail(OFDFT_EINVAL, "grids of different cells");
     }
-    if (!src->rho) return fail(OFDFT_EINVAL, "source grid has no resident density");
+    if (!src->rho_set) return fail(OFDFT_EINVAL, "source grid has no resident density");
     HIP_TRY(hipSetDevice(src->ctx->device));
     graphs_clear(dst);
     return src->fp64 ? interp_impl<double>(dst, src) : interp_impl<float>(dst, src);
@@ -2521,64 +2541,60 @@ static ofdft_status td_potential(ofdft_grid *g, const TdBufs &B, hipStream_t s, 
 // (1 + i tau H) x = b by BiCGSTAB on A K^-1 y = b, x = K^-1 y (right
 // preconditioning with the kinetic part K = 1 + i tau G^2/2, exact in
 // reciprocal space): the residual b - A x is the unpreconditioned one, and
-// the iteration starts from the guess in x
+// the iteration starts from the guess in x.  The scalars stay on the device
+// (k_td_scalars after each pair of dot products; the linear combinations
+// read their coefficients there and stop once the solve is done), and the
+// host reads them once per iteration to decide whether to go on.  Each
+// iteration runs in full (no exit after its first half-step): a residual
+// that vanishes there gives omega = 0 and r = s, and the solve ends at the
+// iteration's end.
 template <typename T>
 static ofdft_status td_solve(ofdft_grid *g, const TdBufs &B, hipStream_t s, double tau,
                              const void *b, void *x, int maxit, double tol, int *iters,
                              double *relres)
 {
-    using cplx = std::complex<double>;
     void *r = B.vec[TV_R], *rh = B.vec[TV_RH], *p = B.vec[TV_P], *v = B.vec[TV_V],
          *sv = B.vec[TV_S], *t = B.vec[TV_T];
+    const long long N = g->geom.N;
+    double *sc = g->d_td_sc, *part = g->d_td_dots, *h = g->h_td_sc;
     void *y = x;                                   // y = K x, in place
     ST_TRY(td_kapply<T>(g, B, s, x, y, tau, TD_K));
     ST_TRY(td_apply_pc<T>(g, B, s, y, t, tau));
     HIP_TRY(td_lin<T>(g, s, r, 1.0, b, -1.0, t));
     HIP_TRY(td_lin<T>(g, s, rh, 1.0, r));
-    HIP_TRY(hipMemsetAsync(p, 0, 2 * (size_t)g->geom.N * g->fsz, s));
-    HIP_TRY(hipMemsetAsync(v, 0, 2 * (size_t)g->geom.N * g->fsz, s));
-    cplx bb, rr;
-    ST_TRY(td_cdot<T>(g, s, b, b, &bb));
-    ST_TRY(td_cdot<T>(g, s, r, r, &rr));
-    const double bnorm = std::sqrt(std::max(bb.real(), 1e-300));
-    double res = std::sqrt(std::max(rr.real(), 0.0)) / bnorm;
-    cplx rho_prev = 1.0, alpha = 1.0, omega = 1.0;
-    int it = 0;
-    while (res > tol && it < maxit) {
-        ++it;
-        cplx rho;
-        ST_TRY(td_cdot<T>(g, s, rh, r, &rho));
-        if (std::abs(rho) == 0.0) break;
-        const cplx beta = (rho / rho_prev) * (alpha / omega);
-        HIP_TRY(td_lin<T>(g, s, p, 1.0, r, beta, p, -beta * omega, v));
+    HIP_TRY(hipMemsetAsync(p, 0, 2 * (size_t)N * g->fsz, s));
+    HIP_TRY(hipMemsetAsync(v, 0, 2 * (size_t)N * g->fsz, s));
+    h[TS_TOL] = tol;
+    h[TS_MAXIT] = maxit;
+    HIP_TRY(hipMemcpyAsync(sc + TS_TOL, h + TS_TOL, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_td_cdots<T>(N, b, b, r, r, part, s));
+    HIP_TRY(launch_td_scalars(TD_STEP_INIT, N, part, sc, s));
+    auto read = [&]() -> ofdft_status {
+        HIP_TRY(hipMemcpyAsync(h, sc, TS_N * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return OFDFT_OK;
+    };
+    ST_TRY(read());
+    while (h[TS_DONE] == 0.0) {
+        HIP_TRY(launch_td_cdots<T>(N, rh, r, nullptr, nullptr, part, s));
+        HIP_TRY(launch_td_scalars(TD_STEP_RHO, N, part, sc, s));
+        HIP_TRY(launch_td_zlincomb_dev<T>(N, p, sc, TS_CP, r, p, v, s));
         ST_TRY(td_apply_pc<T>(g, B, s, p, v, tau));
-        cplx rv;
-        ST_TRY(td_cdot<T>(g, s, rh, v, &rv));
-        if (std::abs(rv) == 0.0) break;
-        alpha = rho / rv;
-        HIP_TRY(td_lin<T>(g, s, sv, 1.0, r, -alpha, v));
-        cplx ss;
-        ST_TRY(td_cdot<T>(g, s, sv, sv, &ss));
-        if (std::sqrt(std::max(ss.real(), 0.0)) / bnorm <= tol) {
-            HIP_TRY(td_lin<T>(g, s, y, 1.0, y, alpha, p));
-            res = std::sqrt(std::max(ss.real(), 0.0)) / bnorm;
-            break;
-        }
+        HIP_TRY(launch_td_cdots<T>(N, rh, v, nullptr, nullptr, part, s));
+        HIP_TRY(launch_td_scalars(TD_STEP_RV, N, part, sc, s));
+        HIP_TRY(launch_td_zlincomb_dev<T>(N, sv, sc, TS_CS, r, v, nullptr, s));
         ST_TRY(td_apply_pc<T>(g, B, s, sv, t, tau));
-        cplx ts, tt;
-        ST_TRY(td_cdot<T>(g, s, t, sv, &ts));
-        ST_TRY(td_cdot<T>(g, s, t, t, &tt));
-        omega = tt.real() > 0.0 ? ts / tt.real() : cplx(0.0);
-        HIP_TRY(td_lin<T>(g, s, y, 1.0, y, alpha, p, omega, sv));
-        HIP_TRY(td_lin<T>(g, s, r, 1.0, sv, -omega, t));
-        ST_TRY(td_cdot<T>(g, s, r, r, &rr));
-        res = std::sqrt(std::max(rr.real(), 0.0)) / bnorm;
-        if (std::abs(omega) == 0.0) break;
-        rho_prev = rho;
+        HIP_TRY(launch_td_cdots<T>(N, t, sv, t, t, part, s));
+        HIP_TRY(launch_td_scalars(TD_STEP_OMEGA, N, part, sc, s));
+        HIP_TRY(launch_td_zlincomb_dev<T>(N, y, sc, TS_CY, y, p, sv, s));
+        HIP_TRY(launch_td_zlincomb_dev<T>(N, r, sc, TS_CR, sv, t, nullptr, s));
+        HIP_TRY(launch_td_cdots<T>(N, r, r, nullptr, nullptr, part, s));
+        HIP_TRY(launch_td_scalars(TD_STEP_RR, N, part, sc, s));
+        ST_TRY(read());
     }
     ST_TRY(td_kapply<T>(g, B, s, y, x, tau, TD_KINV));   // x = K^-1 y
-    *iters = it;
-    *relres = res;
+    *iters = (int)h[TS_IT];
+    *relres = h[TS_RES];
     return OFDFT_OK;
 }
 
@@ -2608,6 +2624,10 @@ static ofdft_status td_alloc(ofdft_grid *g)
     ST_TRY(dmalloc(g, &g->td, td_bytes(g->geom, g->fsz)));
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_td_part),
                    3 * (size_t)td_dipole_blocks(g->geom) * sizeof(double)));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_td_dots),
+                   4 * (size_t)td_dot_blocks(g->geom.N) * sizeof(double)));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_td_sc), TS_N * sizeof(double)));
+    if (!g->h_td_sc) HIP_TRY(hipHostMalloc((void **)&g->h_td_sc, TS_N * sizeof(double)));
     return OFDFT_OK;
 }
 
@@ -2615,6 +2635,7 @@ template <typename T>
 static ofdft_status td_start_impl(ofdft_grid *g, const double k[3])
 {
     hipStream_t s = g->ctx->stream;
+    if (!g->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     ST_TRY(td_alloc(g));
     const TdBufs B = td_bufs(g);
     TdLattice L;
@@ -2682,17 +2703,20 @@ static bool batchable(const ofdft_grid *a, const ofdft_grid *b)
            x.precision == y.precision && x.rho_floor == y.rho_floor && x.nl_kernel == y.nl_kernel;
 }
 
-// One evaluation of the resident densities of n cells, led by grids[0],
-// whose workspace, twiddles and schedule serve the whole batch; potentials
-// (where v_host[b] is not null) are copied to the host.
+// One evaluation of n cells' densities, led by grids[0], whose workspace,
+// twiddles and schedule serve the whole batch, on stream s.  Inputs: in[b]
+// (device, the grid's field type; rho, or phi with in_is_phi) or, with in
+// null, each grid's resident density.  Outputs: potentials copied to the host
+// (v_host[b] not null) or dE/dphi to device arrays (g_dev[b] not null).  The
+// caller has finished all work on the inputs.
 template <typename T>
-static ofdft_status eval_multi(ofdft_grid *const *grids, int n, double *const *v_host,
-                               ofdft_energy *e_out)
+static ofdft_status eval_multi_core(ofdft_grid *const *grids, int n, const void *const *in,
+                                    int in_is_phi, double *const *v_host, void *const *g_dev,
+                                    hipStream_t s, ofdft_energy *e_out)
 {
     ofdft_grid *g = grids[0];
     const Geom &G = g->geom;
     const size_t fb = (size_t)G.N * sizeof(T);
-    hipStream_t s = g->ctx->stream;
     ST_TRY(reserve(g, n));
     if (g->batch_cap < n) {
         g->bytes -= g->multi_bytes;
@@ -2711,25 +2735,30 @@ static ofdft_status eval_multi(ofdft_grid *const *grids, int n, double *const *v
         g->multi_bytes = g->bytes - before;
         g->batch_cap = n;
     }
-    bool want_v = false;
+    bool want_v = false, want_g = false;
     for (int b = 0; b < n; ++b) {
         const ofdft_grid *x = grids[b];
-        if (!x->rho) return fail(OFDFT_EINVAL, "a grid of the batch has no resident density");
+        const void *src = in ? in[b] : (x->rho_set ? x->rho : nullptr);
+        if (!src) return fail(OFDFT_EINVAL, "a grid of the batch has no resident density");
         CellTab &c = g->h_ct[b];
         std::memcpy(c.b, x->geom.b, sizeof(c.b));
         c.vext = x->vext;
         c.gtab = x->gtab;
-        // a member's density was last written on its own context's stream
-        if (x->ctx->stream != s) HIP_TRY(hipStreamSynchronize(x->ctx->stream));
-        HIP_TRY(hipMemcpyAsync((char *)g->batch_in + b * fb, x->rho, fb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync((char *)g->batch_in + b * fb, src, fb, hipMemcpyDeviceToDevice, s));
         want_v |= v_host && v_host[b];
+        want_g |= g_dev && g_dev[b];
     }
     HIP_TRY(hipMemcpyAsync(g->d_ct, g->h_ct, (size_t)n * sizeof(CellTab), hipMemcpyHostToDevice, s));
     g->cur_ct = g->d_ct;
-    const ofdft_status st = eval_enqueue<T>(g, n, g->batch_in, 0, want_v ? g->batch_out : nullptr,
-                                            nullptr, s, work_of<T>(g, 0));
+    const ofdft_status st =
+        eval_enqueue<T>(g, n, g->batch_in, in_is_phi, want_v ? g->batch_out : nullptr,
+                        want_g ? g->batch_out : nullptr, s, work_of<T>(g, 0));
     g->cur_ct = nullptr;
     ST_TRY(st);
+    for (int b = 0; b < n; ++b)
+        if (g_dev && g_dev[b])
+            HIP_TRY(hipMemcpyAsync(g_dev[b], (const char *)g->batch_out + b * fb, fb,
+                                   hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     timer_collect(g);
     double bad = 0.0;
@@ -2740,12 +2769,122 @@ static ofdft_status eval_multi(ofdft_grid *const *grids, int n, double *const *v
         bad += S[SL_BAD];
     }
     if (bad > 0)
-        return fail(OFDFT_EINVAL, "a resident density has " + std::to_string((long long)bad) +
+        return fail(OFDFT_EINVAL, "a density of the batch has " + std::to_string((long long)bad) +
                                       " non-finite or negative values");
     for (int b = 0; b < n; ++b)
         if (v_host && v_host[b])
             ST_TRY(download_field(g, v_host[b], (const char *)g->batch_out + b * fb, (size_t)G.N, s));
     std::copy(e.begin(), e.end(), e_out);
+    return OFDFT_OK;
+}
+
+// The resident densities of n cells (ofdft_energy_potential_multi): the
+// members' densities were last written on their own contexts' streams
+template <typename T>
+static ofdft_status eval_multi(ofdft_grid *const *grids, int n, double *const *v_host,
+                               ofdft_energy *e_out)
+{
+    hipStream_t s = grids[0]->ctx->stream;
+    for (int b = 0; b < n; ++b)
+        if (grids[b]->ctx->stream != s) HIP_TRY(hipStreamSynchronize(grids[b]->ctx->stream));
+    return eval_multi_core<T>(grids, n, nullptr, 0, v_host, nullptr, s, e_out);
+}
+
+// ---------------------------------------------------------------- lockstep optimisation
+// Several grids optimised together (ofdft_optimize_multi), each in a host
+// thread of its own on a stream of its own: the optimisers are unchanged, and
+// each evaluation a member asks for waits until every member still optimising
+// has asked for one; the last to arrive runs them all as one batched
+// evaluation (the kernels of one evaluation then serve every member) and
+// wakes the others.  A member that finishes leaves the group (which may
+// complete a waiting batch).  The results are those of each grid optimised
+// alone: the batched evaluation is the same, bit for bit, per density.
+struct EvalBatcher {
+    struct Req {
+        ofdft_grid *g;
+        const void *in;
+        void *gout;
+        ofdft_energy *e;
+        ofdft_status st;
+        std::string err;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    int active = 0;
+    uint64_t generation = 0;
+    std::vector<Req *> waiting;
+    uint64_t batches = 0, merged = 0;
+    // runs the waiting requests (lock held); every member waiting is blocked,
+    // so the leader's workspace and stream are free
+    void run()
+    {
+        const int n = (int)waiting.size();
+        std::vector<ofdft_grid *> gs((size_t)n);
+        std::vector<const void *> in((size_t)n);
+        std::vector<void *> out((size_t)n);
+        std::vector<ofdft_energy> e((size_t)n);
+        for (int b = 0; b < n; ++b) {
+            gs[b] = waiting[b]->g;
+            in[b] = waiting[b]->in;
+            out[b] = waiting[b]->gout;
+        }
+        ofdft_grid *L = gs[0];
+        hipStream_t s = L->opt_stream ? L->opt_stream : L->ctx->stream;
+        ofdft_status st;
+        if (n == 1) {
+            st = eval_dispatch(L, 1, in[0], 1, nullptr, out[0], s, e.data());
+        } else {
+            st = L->fp64 ? eval_multi_core<double>(gs.data(), n, in.data(), 1, nullptr, out.data(),
+                                                   s, e.data())
+                         : eval_multi_core<float>(gs.data(), n, in.data(), 1, nullptr, out.data(),
+                                                  s, e.data());
+        }
+        const std::string err = st == OFDFT_OK ? std::string() : std::string(ofdft_last_error());
+        for (int b = 0; b < n; ++b) {
+            waiting[b]->st = st;
+            waiting[b]->err = err;
+            if (st == OFDFT_OK) *waiting[b]->e = e[b];
+        }
+        batches++;
+        merged += n;
+        waiting.clear();
+        generation++;
+        cv.notify_all();
+    }
+    ofdft_status eval(ofdft_grid *g, const void *in, void *gout, ofdft_energy *e)
+    {
+        Req r{g, in, gout, e, OFDFT_OK, std::string()};
+        std::unique_lock<std::mutex> lk(mu);
+        waiting.push_back(&r);
+        const uint64_t gen = generation;
+        if ((int)waiting.size() == active) run();
+        else cv.wait(lk, [&] { return generation != gen; });
+        if (r.st != OFDFT_OK) return fail(r.st, r.err);
+        return OFDFT_OK;
+    }
+    void leave()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        active--;
+        if (!waiting.empty() && (int)waiting.size() == active) run();
+    }
+};
+
+static ofdft_status opt_eval(ofdft_grid *g, const void *phi, void *gout, hipStream_t s,
+                             ofdft_energy *e)
+{
+    if (!g->batcher) return eval_dispatch(g, 1, phi, 1, nullptr, gout, s, e);
+    // the member's vector is complete before another thread's stream reads it
+    HIP_TRY(hipStreamSynchronize(s));
+    return g->batcher->eval(g, phi, gout, e);
+}
+
+static ofdft_status check_opt_params(const ofdft_opt_params *params)
+{
+    if (!(params->tol > 0) || params->max_iter < 0) return fail(OFDFT_EINVAL, "bad parameters");
+    if (params->method != OFDFT_OPT_CG && params->method != OFDFT_OPT_PCG &&
+        params->method != OFDFT_OPT_TN)
+        return fail(OFDFT_EINVAL, "unknown optimisation method");
     return OFDFT_OK;
 }
 
@@ -2989,12 +3128,15 @@ ofdft_status ofdft_set_density(ofdft_grid *grid, const double *rho_host)
         if (!std::isfinite(rho_host[i]) || rho_host[i] < 0)
             return fail(OFDFT_EINVAL, "density has non-finite or negative values");
     HIP_TRY(hipSetDevice(grid->ctx->device));
-    return upload_field(grid, grid->rho, rho_host, (size_t)N, grid->ctx->stream);
+    ST_TRY(upload_field(grid, grid->rho, rho_host, (size_t)N, grid->ctx->stream));
+    grid->rho_set = true;
+    return OFDFT_OK;
 }
 
 ofdft_status ofdft_get_density(ofdft_grid *grid, double *rho_host)
 {
     if (!grid || !rho_host) return fail(OFDFT_EINVAL, "null argument");
+    if (!grid->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return download_field(grid, rho_host, grid->rho, (size_t)grid->geom.N, grid->ctx->stream);
 }
@@ -3012,6 +3154,7 @@ ofdft_status ofdft_energy_potential(ofdft_grid *grid, const double *rho_host, do
         ST_TRY(dmalloc(grid, &grid->stage_in, N * grid->fsz));
         ST_TRY(upload_field(grid, grid->stage_in, rho_host, N, s, true));
     }
+    if (!rho_host && !grid->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     const void *d_in = rho_host ? grid->stage_in : grid->rho;
     void *d_v = nullptr;
     if (v_out_host) {
@@ -3097,6 +3240,7 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
                                       std::to_string(LARGE_IONS) +
                                       " atoms with the direct structure factor");
     ofdft_grid *g = grid;
+    if (!g->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     hipStream_t s = g->ctx->stream;
     ST_TRY(reserve(g, 1));
     // rho(G) of the resident density into the workspace spectrum
@@ -3181,13 +3325,73 @@ ofdft_status ofdft_td_set_psi(ofdft_grid *grid, const double *re_host, const dou
 ofdft_status ofdft_optimize(ofdft_grid *grid, const ofdft_opt_params *params, ofdft_opt_result *result)
 {
     if (!grid || !params || !result) return fail(OFDFT_EINVAL, "null argument");
-    if (!(params->tol > 0) || params->max_iter < 0) return fail(OFDFT_EINVAL, "bad parameters");
-    if (params->method != OFDFT_OPT_CG && params->method != OFDFT_OPT_PCG &&
-        params->method != OFDFT_OPT_TN)
-        return fail(OFDFT_EINVAL, "unknown optimisation method");
+    ST_TRY(check_opt_params(params));
+    if (!grid->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return grid->fp64 ? optimize_impl<double>(grid, params, result)
                       : optimize_impl<float>(grid, params, result);
+}
+
+ofdft_status ofdft_optimize_multi(ofdft_grid *const *grids, int32_t n,
+                                  const ofdft_opt_params *params, ofdft_opt_result *results,
+                                  ofdft_status *statuses)
+{
+    if (!grids || !params || !results || !statuses || n < 1 || n > OFDFT_MULTI_MAX)
+        return fail(OFDFT_EINVAL, "bad argument");
+    for (int b = 0; b < n; ++b) {
+        if (!grids[b]) return fail(OFDFT_EINVAL, "null grid in the batch");
+        if (!batchable(grids[0], grids[b]))
+            return fail(OFDFT_EINVAL, "grids of a batch need the same shape, functional and device");
+        for (int c = 0; c < b; ++c)
+            if (grids[c] == grids[b]) return fail(OFDFT_EINVAL, "a grid appears twice in the batch");
+        if (!grids[b]->rho_set)
+            return fail(OFDFT_EINVAL, "a grid of the batch has no resident density");
+        ST_TRY(check_opt_params(&params[b]));
+    }
+    const int dev = grids[0]->ctx->device;
+    HIP_TRY(hipSetDevice(dev));
+    for (int b = 0; b < n; ++b) HIP_TRY(hipStreamSynchronize(grids[b]->ctx->stream));
+    std::vector<hipStream_t> streams((size_t)n, nullptr);
+    for (int b = 0; b < n; ++b) {
+        const hipError_t e = hipStreamCreateWithFlags(&streams[b], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (int c = 0; c < b; ++c) (void)hipStreamDestroy(streams[c]);
+            return fail(OFDFT_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        }
+    }
+    EvalBatcher B;
+    B.active = n;
+    std::vector<std::string> errs((size_t)n);
+    for (int b = 0; b < n; ++b) {
+        grids[b]->batcher = &B;
+        grids[b]->opt_stream = streams[b];
+    }
+    auto member = [&](int b) {
+        (void)hipSetDevice(dev);
+        ofdft_grid *g = grids[b];
+        const ofdft_status st = g->fp64 ? optimize_impl<double>(g, &params[b], &results[b])
+                                        : optimize_impl<float>(g, &params[b], &results[b]);
+        statuses[b] = st;
+        if (st != OFDFT_OK) errs[b] = ofdft_last_error();
+        B.leave();
+    };
+    std::vector<std::thread> threads;
+    threads.reserve((size_t)n - 1);
+    for (int b = 1; b < n; ++b) threads.emplace_back(member, b);
+    member(0);
+    for (auto &t : threads) t.join();
+    for (int b = 0; b < n; ++b) {
+        (void)hipStreamSynchronize(streams[b]);
+        (void)hipStreamDestroy(streams[b]);
+        grids[b]->batcher = nullptr;
+        grids[b]->opt_stream = nullptr;
+    }
+    for (int b = 0; b < n; ++b)
+        if (statuses[b] != OFDFT_OK) {
+            g_last_error = "member " + std::to_string(b) + ": " + errs[b];
+            break;
+        }
+    return OFDFT_OK;
 }
 
 ofdft_status ofdft_grid_interpolate_density(ofdft_grid *dst, ofdft_grid *src)
@@ -3255,6 +3459,7 @@ ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d
 ofdft_status ofdft_grid_tune(ofdft_grid *grid, ofdft_tune_result *result)
 {
     if (!grid) return fail(OFDFT_EINVAL, "null argument");
+    if (!grid->rho_set) return fail(OFDFT_EINVAL, "the grid has no resident density");
     HIP_TRY(hipSetDevice(grid->ctx->device));
     return tune_impl(grid, 1, grid->rho, grid->ctx->stream, result);
 }

@@ -252,7 +252,171 @@ hipError_t launch_td_zlincomb(long long n, void *z, const double a[2], const voi
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- device-side BiCGSTAB
+int td_dot_blocks(long long n) { return (int)td_grid(n); }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_cdots(long long n, const T *a, const T *b, const T *c,
+                                                 const T *d, double *part, int rows)
+{
+    __shared__ double red[4 * NT / 64];
+    const int tid = threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * NT + tid; i < n; i += (long long)gridDim.x * NT) {
+        const double ar = a[i], ai = a[n + i], br = b[i], bi = b[n + i];
+        v[0] += ar * br + ai * bi;
+        v[1] += ar * bi - ai * br;
+        if (c) {
+            const double cr = c[i], ci = c[n + i], dr = d[i], di = d[n + i];
+            v[2] += cr * dr + ci * di;
+            v[3] += cr * di - ci * dr;
+        }
+    }
+    block_sums<NT, 4>(v, red, tid);
+    if (tid == 0)
+        for (int k = 0; k < rows; ++k) part[(long long)k * gridDim.x + blockIdx.x] = v[k];
+}
+
+template <typename T>
+hipError_t launch_td_cdots(long long n, const void *a, const void *b, const void *c,
+                           const void *d, double *part, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_cdots<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (const T *)a,
+                       (const T *)b, (const T *)c, (const T *)d, part, c ? 4 : 2);
+    return hipGetLastError();
+}
+
+namespace {
+struct zc {
+    double r, i;
+};
+__device__ __forceinline__ zc zmul(zc a, zc b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ zc zdiv(zc a, zc b)
+{
+    const double d = b.r * b.r + b.i * b.i;
+    return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+__device__ __forceinline__ zc zget(const double *sc, int k) { return {sc[k], sc[k + 1]}; }
+__device__ __forceinline__ void zput(double *sc, int k, zc v)
+{
+    sc[k] = v.r;
+    sc[k + 1] = v.i;
+}
+}  // namespace
+
+// one block: the dot products in fixed order, then the step's scalars
+__global__ __launch_bounds__(NT) void k_td_scalars(int step, int nblk, const double *part,
+                                                   double *sc)
+{
+    __shared__ double red[4 * NT / 64];
+    const int tid = threadIdx.x;
+    const int rows = (step == TD_STEP_INIT || step == TD_STEP_OMEGA) ? 4 : 2;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < rows; ++k)
+        for (int i = tid; i < nblk; i += NT) v[k] += part[(long long)k * nblk + i];
+    block_sums<NT, 4>(v, red, tid);
+    if (tid != 0) return;
+    const zc d0 = {v[0], v[1]}, d1 = {v[2], v[3]};
+    if (step == TD_STEP_INIT) {
+        const double bnorm = sqrt(fmax(d0.r, 1e-300));
+        sc[TS_BNORM] = bnorm;
+        sc[TS_RES] = sqrt(fmax(d1.r, 0.0)) / bnorm;
+        sc[TS_DONE] = sc[TS_RES] > sc[TS_TOL] && sc[TS_MAXIT] > 0 ? 0.0 : 1.0;
+        sc[TS_IT] = 0.0;
+        zput(sc, TS_RHOP, {1.0, 0.0});
+        zput(sc, TS_ALPHA, {1.0, 0.0});
+        zput(sc, TS_OMEGA, {1.0, 0.0});
+        return;
+    }
+    if (sc[TS_DONE] != 0.0) return;
+    if (step == TD_STEP_RHO) {
+        sc[TS_IT] += 1.0;
+        if (d0.r == 0.0 && d0.i == 0.0) {   // breakdown: stop with the current iterate
+            sc[TS_DONE] = 1.0;
+            return;
+        }
+        zput(sc, TS_RHO, d0);
+        const zc beta = zmul(zdiv(d0, zget(sc, TS_RHOP)), zdiv(zget(sc, TS_ALPHA), zget(sc, TS_OMEGA)));
+        const zc bw = zmul(beta, zget(sc, TS_OMEGA));
+        zput(sc, TS_CP, {1.0, 0.0});
+        zput(sc, TS_CP + 2, beta);
+        zput(sc, TS_CP + 4, {-bw.r, -bw.i});
+    } else if (step == TD_STEP_RV) {
+        if (d0.r == 0.0 && d0.i == 0.0) {
+            sc[TS_DONE] = 1.0;
+            return;
+        }
+        const zc alpha = zdiv(zget(sc, TS_RHO), d0);
+        zput(sc, TS_ALPHA, alpha);
+        zput(sc, TS_CS, {1.0, 0.0});
+        zput(sc, TS_CS + 2, {-alpha.r, -alpha.i});
+    } else if (step == TD_STEP_OMEGA) {
+        // d0 = <t,s>, d1 = <t,t> (real)
+        const zc omega = d1.r > 0.0 ? zc{d0.r / d1.r, d0.i / d1.r} : zc{0.0, 0.0};
+        zput(sc, TS_OMEGA, omega);
+        zput(sc, TS_CY, {1.0, 0.0});
+        zput(sc, TS_CY + 2, zget(sc, TS_ALPHA));
+        zput(sc, TS_CY + 4, omega);
+        zput(sc, TS_CR, {1.0, 0.0});
+        zput(sc, TS_CR + 2, {-omega.r, -omega.i});
+    } else {   // TD_STEP_RR
+        sc[TS_RES] = sqrt(fmax(d0.r, 0.0)) / sc[TS_BNORM];
+        const zc om = zget(sc, TS_OMEGA);
+        if (sc[TS_RES] <= sc[TS_TOL] || (om.r == 0.0 && om.i == 0.0) || sc[TS_IT] >= sc[TS_MAXIT])
+            sc[TS_DONE] = 1.0;
+        zput(sc, TS_RHOP, zget(sc, TS_RHO));
+    }
+}
+
+hipError_t launch_td_scalars(int step, long long n, const double *part, double *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_td_scalars, dim3(1), dim3(NT), 0, s, step, (int)td_grid(n), part, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_td_zlincomb_dev(long long n, T *z, const double *sc,
+                                                        int coef, const T *x, const T *y,
+                                                        const T *w)
+{
+    if (sc[TS_DONE] != 0.0) return;
+    const double ar = sc[coef], ai = sc[coef + 1];
+    const double br = y ? sc[coef + 2] : 0.0, bi = y ? sc[coef + 3] : 0.0;
+    const double cr = w ? sc[coef + 4] : 0.0, ci = w ? sc[coef + 5] : 0.0;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n;
+         i += (long long)gridDim.x * NT) {
+        const double xr = x[i], xi = x[n + i];
+        double zr = ar * xr - ai * xi, zi = ar * xi + ai * xr;
+        if (y) {
+            const double yr = y[i], yi = y[n + i];
+            zr += br * yr - bi * yi;
+            zi += br * yi + bi * yr;
+        }
+        if (w) {
+            const double wr = w[i], wi = w[n + i];
+            zr += cr * wr - ci * wi;
+            zi += cr * wi + ci * wr;
+        }
+        z[i] = T(zr);
+        z[n + i] = T(zi);
+    }
+}
+
+template <typename T>
+hipError_t launch_td_zlincomb_dev(long long n, void *z, const double *sc, int coef, const void *x,
+                                  const void *y, const void *w, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_td_zlincomb_dev<T>), dim3(td_grid(n)), dim3(NT), 0, s, n, (T *)z, sc,
+                       coef, (const T *)x, (const T *)y, (const T *)w);
+    return hipGetLastError();
+}
+
 #define OFDFT_TD_INSTANTIATE(T)                                                                   \
+    template hipError_t launch_td_cdots<T>(long long, const void *, const void *, const void *,   \
+                                           const void *, double *, hipStream_t);                  \
+    template hipError_t launch_td_zlincomb_dev<T>(long long, void *, const double *, int,         \
+                                                  const void *, const void *, const void *,       \
+                                                  hipStream_t);                                   \
     template hipError_t launch_td_density<T>(long long, const void *, double, const void *,      \
                                              double, void *, hipStream_t);                        \
     template hipError_t launch_td_dipole<T>(const Geom &, const TdLattice &, const void *,        \

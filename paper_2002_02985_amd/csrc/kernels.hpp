@@ -379,6 +379,38 @@ hipError_t launch_td_zlincomb(long long n, void *z, const double a[2], const voi
                               const double b[2], const void *y, const double c[2], const void *w,
                               hipStream_t s);
 
+// BiCGSTAB on the device (no host read per dot product).  The solver's
+// scalars live in one FP64 array sc[TS_N]; complex numbers are {re, im}.
+enum {
+    TS_RHO = 0, TS_RHOP = 2, TS_ALPHA = 4, TS_OMEGA = 6,   // complex
+    TS_BNORM = 8, TS_RES = 9, TS_DONE = 10, TS_IT = 11, TS_TOL = 12, TS_MAXIT = 13,
+    TS_CP = 14,   // p = CP0 r + CP1 p + CP2 v   (3 complex)
+    TS_CS = 20,   // s = CS0 r + CS1 v           (2 complex)
+    TS_CY = 24,   // y = CY0 y + CY1 p + CY2 s   (3 complex)
+    TS_CR = 30,   // r = CR0 s + CR1 t           (2 complex)
+    TS_N = 34
+};
+// the update that follows each pair of dot products
+enum { TD_STEP_INIT = 0,   // <b,b>, <r,r>: |b|, the relative residual, done
+       TD_STEP_RHO = 1,    // <rh,r>: rho, beta, CP
+       TD_STEP_RV = 2,     // <rh,v>: alpha, CS
+       TD_STEP_OMEGA = 3,  // <t,s>, <t,t>: omega, CY, CR
+       TD_STEP_RR = 4 };   // <r,r>: residual, iteration count, done
+int td_dot_blocks(long long n);
+// part rows 0, 1 (2, 3): per-block partials of Re, Im <a,b> (<c,d>);
+// c, d may be null
+template <typename T>
+hipError_t launch_td_cdots(long long n, const void *a, const void *b, const void *c,
+                           const void *d, double *part, hipStream_t s);
+// reduces the partials (td_dot_blocks(n) per row, fixed order) and applies
+// step to sc (nothing once sc[TS_DONE] is set)
+hipError_t launch_td_scalars(int step, long long n, const double *part, double *sc, hipStream_t s);
+// z = c0 x + c1 y + c2 w with the complex coefficients sc[coef ..], skipped
+// once sc[TS_DONE] is set; y, w may be null
+template <typename T>
+hipError_t launch_td_zlincomb_dev(long long n, void *z, const double *sc, int coef, const void *x,
+                                  const void *y, const void *w, hipStream_t s);
+
 // vector kernels (optimizer): up to 4 dot products into part slots
 template <typename T>
 hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, const void *x1,

@@ -150,7 +150,9 @@ struct ofdft_server {
     std::unordered_map<uint64_t, SavedDensity> saved;
     uint64_t saved_bytes = 0, saved_clock = 0;
     // continuous batching of energy+potential requests across cells
-    int batch_max = 8;
+    int batch_max = 8;       // energy+potential requests per batch
+    int opt_batch_max = 1;   // optimisation requests per lockstep batch (off: measured
+                             // slower than running them on separate worker slots)
     uint64_t n_batches = 0, n_batched = 0;
 };
 
@@ -203,6 +205,40 @@ void save_density(ofdft_server *s, uint64_t cell_id, SavedDensity &&h)
 // worker's context.  Called without the server lock; r is owned by this
 // worker while busy.  saved: the density kept for this cell when its grid
 // was evicted (empty if none), the start of a request that brings none.
+// rho0 = N_e / V at every point of the request's grid
+std::vector<double> uniform_density(const Job &job)
+{
+    const double(&a)[3][3] = job.cell.d.lattice;
+    const double V = std::fabs(a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                               a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                               a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]));
+    return std::vector<double>((size_t)job.cell.npoints(), job.cell.d.nelec / V);
+}
+
+// A resident grid brought to a batched request on this worker's context:
+// the atoms moved in place, the density given with the request, else the
+// resident one (a cold optimisation, or a grid without one: the uniform one)
+ofdft_status prepare_resident(Job &job, Res &r, ofdft_ctx *ctx)
+{
+    ofdft_internal::bind_context(r.g, ctx);
+    ofdft_status st = OFDFT_OK;
+    if (r.cell.pos != job.cell.pos) {
+        st = ofdft_internal::set_positions(r.g, job.cell.pos.data());
+        if (st == OFDFT_OK) r.cell.assign(job.cell);
+    }
+    const bool cold_opt = job.kind == OFDFT_REQ_OPTIMIZE && !job.opt.warm;
+    if (st == OFDFT_OK) {
+        if (!job.rho.empty()) {
+            st = ofdft_set_density(r.g, job.rho.data());
+        } else if (!r.has_density || cold_opt) {
+            const std::vector<double> u = uniform_density(job);
+            st = ofdft_set_density(r.g, u.data());
+        }
+    }
+    if (st == OFDFT_OK) r.has_density = true;
+    return st;
+}
+
 void execute(Job &job, Res &r, ofdft_ctx *ctx, const SavedDensity &saved)
 {
     ofdft_status st = OFDFT_OK;
@@ -235,14 +271,7 @@ void execute(Job &job, Res &r, ofdft_ctx *ctx, const SavedDensity &saved)
                    saved.n[2] == job.cell.d.n[2]) {
             st = ofdft_set_density(g, saved.rho.data());
         } else if (!r.has_density || cold_opt) {
-            const double V = std::fabs(
-                job.cell.d.lattice[0][0] * (job.cell.d.lattice[1][1] * job.cell.d.lattice[2][2] -
-                                            job.cell.d.lattice[1][2] * job.cell.d.lattice[2][1]) -
-                job.cell.d.lattice[0][1] * (job.cell.d.lattice[1][0] * job.cell.d.lattice[2][2] -
-                                            job.cell.d.lattice[1][2] * job.cell.d.lattice[2][0]) +
-                job.cell.d.lattice[0][2] * (job.cell.d.lattice[1][0] * job.cell.d.lattice[2][1] -
-                                            job.cell.d.lattice[1][1] * job.cell.d.lattice[2][0]));
-            std::vector<double> u((size_t)job.cell.npoints(), job.cell.d.nelec / V);
+            const std::vector<double> u = uniform_density(job);
             st = ofdft_set_density(g, u.data());
         }
         if (st == OFDFT_OK) r.has_density = true;
@@ -294,13 +323,7 @@ void execute_batch(const std::vector<Job *> &jobs, const std::vector<Res *> &res
     for (size_t b = 0; b < n && st == OFDFT_OK; ++b) {
         Job &job = *jobs[b];
         Res &r = *res[b];
-        ofdft_internal::bind_context(r.g, ctx);
-        if (r.cell.pos != job.cell.pos) {
-            st = ofdft_internal::set_positions(r.g, job.cell.pos.data());
-            if (st == OFDFT_OK) r.cell.assign(job.cell);
-        }
-        if (st == OFDFT_OK && !job.rho.empty()) st = ofdft_set_density(r.g, job.rho.data());
-        if (st == OFDFT_OK) r.has_density = true;
+        st = prepare_resident(job, r, ctx);
         grids[b] = r.g;
         job.v.resize((size_t)job.cell.npoints());
         vptr[b] = job.v.data();
@@ -325,6 +348,56 @@ void execute_batch(const std::vector<Job *> &jobs, const std::vector<Res *> &res
             job->status = OFDFT_ECANCELLED;
             job->err = "request cancelled";
             job->v.clear();
+        }
+}
+
+// Runs optimisation requests of several resident cells (one grid shape and
+// functional) as one lockstep optimisation (their evaluations batched).
+// Called without the server lock; every grid is owned by this worker while
+// busy.  Falls back to one request at a time if the batch cannot run.
+void execute_opt_batch(const std::vector<Job *> &jobs, const std::vector<Res *> &res,
+                       ofdft_ctx *ctx)
+{
+    std::vector<ofdft_grid *> grids;
+    std::vector<ofdft_opt_params> prm;
+    std::vector<size_t> idx;
+    for (size_t b = 0; b < jobs.size(); ++b) {
+        Job &job = *jobs[b];
+        job.status = prepare_resident(job, *res[b], ctx);
+        if (job.status != OFDFT_OK) {
+            job.err = ofdft_last_error();
+            continue;
+        }
+        ofdft_internal::set_cancel(res[b]->g, &job.cancel);
+        grids.push_back(res[b]->g);
+        prm.push_back(job.opt);
+        idx.push_back(b);
+    }
+    const size_t n = grids.size();
+    std::vector<ofdft_opt_result> out(n);
+    std::vector<ofdft_status> sts(n, OFDFT_OK);
+    ofdft_status st = OFDFT_EINVAL;
+    if (n > 0)
+        st = ofdft_optimize_multi(grids.data(), (int32_t)n, prm.data(), out.data(), sts.data());
+    const std::string err = ofdft_last_error();
+    for (size_t k = 0; k < n; ++k) {
+        Job &job = *jobs[idx[k]];
+        if (st == OFDFT_OK) {
+            job.res = out[k];
+            job.status = sts[k];
+            if (job.status != OFDFT_OK)
+                job.err = job.status == OFDFT_ENOCONV ? "optimisation did not reach the tolerance"
+                                                      : err;
+        } else {   // one at a time (each request gets its own status)
+            job.status = ofdft_optimize(grids[k], &job.opt, &job.res);
+            if (job.status != OFDFT_OK) job.err = ofdft_last_error();
+        }
+        ofdft_internal::set_cancel(grids[k], nullptr);
+    }
+    for (Job *job : jobs)
+        if (job->cancel.load()) {
+            job->status = OFDFT_ECANCELLED;
+            job->err = "request cancelled";
         }
 }
 
@@ -363,31 +436,35 @@ void worker_loop(ofdft_server *s, int w)
             continue;
         }
         std::shared_ptr<Job> job = s->queue[d.job];
-        // continuous batching: an energy+potential request on a resident grid
-        // takes further queued energy+potential requests of other resident
-        // cells with the same grid shape and functional along (each the
-        // earliest queued request of its cell, its grid idle), as long as
-        // the leader's larger workspace fits in the budget
+        // continuous batching: an energy+potential (or optimisation) request
+        // on a resident grid takes further queued requests of the same kind
+        // of other resident cells with the same grid shape and functional
+        // along (each the earliest queued request of its cell, its grid
+        // idle), as long as the leader's larger workspace fits in the
+        // budget: one batched evaluation, or one lockstep optimisation whose
+        // evaluations are batched
         std::vector<std::shared_ptr<Job>> batch;
         std::vector<Res *> batch_res;
-        if (job->kind == OFDFT_REQ_EP && d.evict.empty() && s->batch_max > 1) {
+        const int bmax = job->kind == OFDFT_REQ_EP ? s->batch_max
+                         : job->kind == OFDFT_REQ_OPTIMIZE ? s->opt_batch_max : 1;
+        if (bmax > 1 && d.evict.empty()) {
             const int lr = find_resident(s, job->cell_id);
             if (lr >= 0 && s->res[lr]->g && !s->res[lr]->busy &&
                 same_shape(s->res[lr]->cell, s->res[lr]->func, job->cell, job->func)) {
                 const Res &L = *s->res[lr];
                 std::unordered_set<uint64_t> seen;
                 seen.insert(job->cell_id);
-                for (size_t i = 0; i < s->queue.size() && (int)batch.size() + 1 < s->batch_max; ++i) {
+                for (size_t i = 0; i < s->queue.size() && (int)batch.size() + 1 < bmax; ++i) {
                     if ((int)i == d.job) continue;
                     const Job &j = *s->queue[i];
                     if (!seen.insert(j.cell_id).second) continue;   // not its cell's earliest
-                    if (j.kind != OFDFT_REQ_EP) continue;
+                    if (j.kind != job->kind) continue;
                     const int r = find_resident(s, j.cell_id);
                     if (r < 0) continue;
                     Res &R = *s->res[r];
                     if (R.busy || R.evicting || !R.g) continue;
                     if (!same_shape(R.cell, R.func, j.cell, j.func)) continue;
-                    if (j.rho.empty() && !R.has_density) continue;
+                    if (j.kind == OFDFT_REQ_EP && j.rho.empty() && !R.has_density) continue;
                     if (!same_functional(R.func, L.func) || R.cell.d.n[0] != L.cell.d.n[0] ||
                         R.cell.d.n[1] != L.cell.d.n[1] || R.cell.d.n[2] != L.cell.d.n[2])
                         continue;
@@ -506,7 +583,8 @@ void worker_loop(ofdft_server *s, int w)
                 jobs.push_back(batch[k].get());
                 rs.push_back(batch_res[k]);
             }
-            execute_batch(jobs, rs, ctx);
+            if (job->kind == OFDFT_REQ_EP) execute_batch(jobs, rs, ctx);
+            else execute_opt_batch(jobs, rs, ctx);
         }
 
         lk.lock();
@@ -528,7 +606,7 @@ void worker_loop(ofdft_server *s, int w)
             batch_res[k]->busy = false;
             batch_res[k]->last_use = ++s->clock;
             bj.state = DONE;
-            if (bj.status == OFDFT_OK) {
+            if (bj.status == OFDFT_OK || bj.status == OFDFT_ENOCONV) {
                 s->n_done++;
                 s->lat_ms.push_back(ms_between(bj.t_submit, bj.t_end));
                 s->queue_ms.push_back(ms_between(bj.t_submit, bj.t_start));
@@ -729,6 +807,17 @@ ofdft_status ofdft_serve_cancel(ofdft_server *s, uint64_t ticket)
         j.v.clear();
         j.f.clear();
     }
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_serve_set_batching(ofdft_server *s, int32_t max_ep, int32_t max_opt)
+{
+    if (!s) return fail(OFDFT_EINVAL, "null server");
+    if (max_ep < 1 || max_ep > OFDFT_MULTI_MAX || max_opt < 1 || max_opt > OFDFT_MULTI_MAX)
+        return fail(OFDFT_EINVAL, "batch size outside 1..OFDFT_MULTI_MAX");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->batch_max = max_ep;
+    s->opt_batch_max = max_opt;
     return OFDFT_OK;
 }
 

@@ -24,6 +24,7 @@ REQ_EP, REQ_FORCES, REQ_OPTIMIZE = 0, 1, 2
 OPT_CG, OPT_PCG, OPT_TN = 0, 1, 2
 SF_DIRECT, SF_PME = 0, 1
 KERNEL_WT, KERNEL_MGP, KERNEL_MGPA, KERNEL_MGPG = 0, 1, 2, 3
+MULTI_MAX = 64   # OFDFT_MULTI_MAX: grids per batched call
 PASS_NAMES = ["row_fwd", "col1_fwd", "col0_g", "col1_inv", "row_inv", "knot_inv", "knot_col1",
               "knot_row", "exact_fwd", "exact_acc", "finalize", "other", "vw64"]
 
@@ -127,6 +128,8 @@ _SIGS = {
     "ofdft_energy_potential_batch_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P,
                                                         ctypes.POINTER(Energy)]),
     "ofdft_energy_potential_dev_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(Energy)]),
+    "ofdft_optimize_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "ofdft_energy_potential_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                                     ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
                                                     ctypes.POINTER(Energy)]),
@@ -146,6 +149,7 @@ _SIGS = {
     "ofdft_serve_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32]),
     "ofdft_serve_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "ofdft_serve_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServeStats)]),
+    "ofdft_serve_set_batching": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "ofdft_server_destroy": (None, [_P]),
     "ofdft_grid_set_graphs": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_interpolate_density": (ctypes.c_int, [_P, _P]),
@@ -362,6 +366,20 @@ def ofdft_optimize(grid, tol=1e-7, max_iter=1000, method=0, allow_noconv=False):
     return r, st
 
 
+def ofdft_optimize_multi(grids, params):
+    """Lockstep optimisation of several grids' resident densities; params:
+    (tol, max_iter, method) per grid.  Returns ([OptResult], [status])."""
+    n = len(grids)
+    harr = (ctypes.c_void_p * n)(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in grids])
+    ps = (OptParams * n)(*[OptParams(tol=t, max_iter=m, method=k, warm=0) for t, m, k in params])
+    rs = (OptResult * n)()
+    sts = (ctypes.c_int32 * n)()
+    check(load().ofdft_optimize_multi(harr, n, ctypes.cast(ps, ctypes.c_void_p),
+                                      ctypes.cast(rs, ctypes.c_void_p),
+                                      ctypes.cast(sts, ctypes.c_void_p)))
+    return list(rs), list(sts)
+
+
 def ofdft_grid_interpolate_density(dst, src):
     check(load().ofdft_grid_interpolate_density(dst, src))
 
@@ -462,6 +480,10 @@ def ofdft_serve_wait(server, ticket, timeout_ms=-1):
 
 def ofdft_serve_cancel(server, ticket):
     return load().ofdft_serve_cancel(server, int(ticket))
+
+
+def ofdft_serve_set_batching(server, max_ep, max_opt):
+    check(load().ofdft_serve_set_batching(server, int(max_ep), int(max_opt)))
 
 
 def ofdft_serve_stats_get(server):

@@ -148,3 +148,66 @@ def test_server_batches_energy_requests_across_cells():
             e, v_ref = g.energy_potential(q0["rho"])
         assert r.e.e_total == e.e_total
         assert np.array_equal(v, v_ref)
+
+
+def test_server_batches_optimisation_requests_across_cells():
+    """One worker slot: warm-started optimisation requests of six resident
+    cells queue behind a long request and are served as lockstep
+    optimisations; each result equals ofdft_optimize on the same cell and
+    starting density alone."""
+    from tests.test_gpu_serve import Server
+    base = cells()
+    cs = []
+    for i in range(6):
+        c = dict(base[i % 2])
+        c["pos"] = base[i % 2]["pos"] + 0.05 * i
+        cs.append(c)
+    fd = ofdft.make_functional_desc(LOCAL | ofdft.TERM_WT, precision=ofdft.MIXED_VW64)
+    opt = dict(tol=2e-5, max_iter=40)
+    s = Server(max_inflight=1)
+    ofdft.ofdft_serve_set_batching(s.h, 8, 8)   # lockstep optimisation batches are off by default
+    try:
+        first = []
+        for i, c in enumerate(cs):
+            q = {"cell_id": 200 + i, "kind": ofdft.REQ_EP, "cell": c,
+                 "rho": W.gaussian_density(c, sigma=1.5 + 0.05 * i, floor=1e-9)}
+            first.append((s.submit(q, func=fd), q))
+        for t, q in first:
+            assert s.result(t, q)[0] == ofdft.OK
+        big = {"cell_id": 998, "kind": ofdft.REQ_OPTIMIZE, "cell": cs[0],
+               "rho": W.gaussian_density(cs[0], sigma=1.5, floor=1e-9)}
+        tb = s.submit(big, opt=dict(tol=1e-6, max_iter=200), func=fd)
+        later = []
+        for i, c in enumerate(cs):
+            q = {"cell_id": 200 + i, "kind": ofdft.REQ_OPTIMIZE, "cell": c, "rho": None}
+            later.append((s.submit(q, opt=opt, func=fd), q))
+        res = [s.result(t, q) for t, q in later]
+        s.result(tb, big)
+        stats = s.stats()
+    finally:
+        s.close()
+    print("batches %d, batched requests %d" % (stats["batches"], stats["batched_requests"]),
+          flush=True)
+    assert stats["batches"] >= 1 and stats["batched_requests"] >= 2
+    for (st, r, _, _), c, (t, q0) in zip(res, cs, first):
+        assert st in (ofdft.OK, ofdft.ENOCONV)
+        with ofdft.Grid(c, LOCAL | ofdft.TERM_WT, precision=ofdft.MIXED_VW64) as g:
+            g.set_density(q0["rho"])
+            ra, sa = ofdft.ofdft_optimize(g.handle, opt["tol"], opt["max_iter"],
+                                          method=ofdft.OPT_CG, allow_noconv=True)
+        assert st == sa
+        assert r.iters == ra.iters and r.evals == ra.evals
+        assert r.e.e_total == ra.e.e_total and r.final_resid == ra.final_resid
+
+
+def test_serve_set_batching_checks_its_range():
+    from tests.test_gpu_serve import Server
+    s = Server(max_inflight=1)
+    try:
+        for bad in ((0, 8), (8, 0), (ofdft.MULTI_MAX + 1, 1)):
+            with pytest.raises(ofdft.OfdftError) as ei:
+                ofdft.ofdft_serve_set_batching(s.h, *bad)
+            assert ei.value.status == ofdft.EINVAL
+        ofdft.ofdft_serve_set_batching(s.h, 1, 1)
+    finally:
+        s.close()
