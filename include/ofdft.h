@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define OFDFT_ABI_VERSION 6
+#define OFDFT_ABI_VERSION 7
 
 typedef struct ofdft_ctx ofdft_ctx;
 typedef struct ofdft_grid ofdft_grid;
@@ -489,8 +489,8 @@ void ofdft_server_destroy(ofdft_server *srv);
  * separate row and column passes where both apply, the block order of the
  * column passes, the number of densities a column block serves (one, or a
  * group of up to 8 sharing the tile's set-up and operands; batches of
- * nbatch > 1 on short columns), the number of spline knots per batch -- on
- * nbatch densities
+ * nbatch > 1 on short columns), the number of spline knots per batch, the
+ * knot pipeline (below) -- on nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
  * density, nbatch 1), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
@@ -500,6 +500,7 @@ typedef struct {
     double best_ms, default_ms;   /* per evaluation call */
     int32_t pipe;                 /* the grid's sub-batch split (not tuned) */
     int32_t col_group;            /* densities per column block (1 or up to 8) */
+    int32_t knot_pipe, reserved;  /* knot pipeline on (1) or off */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
 /* Spline knot range (step s1 on the device; on by default): before the knot
@@ -516,6 +517,13 @@ ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on);
  * enough blocks).  Results are the same, bit for bit, for every n.
  * OFDFT_EINVAL outside 1..8. */
 ofdft_status ofdft_grid_set_col_group(ofdft_grid *grid, int32_t n);
+/* Knot pipeline (spline grids with more than 8 knots whose knot spectra take
+ * at most 4 GiB, where the grid holds a second knot-spectrum buffer; on by
+ * default): knot batch i's transforms run on the grid's second stream into
+ * buffer i % 2 while the row pass of batch i - 1 runs on the caller's stream
+ * (forked from it and joined back; not used while per-pass timing is on or
+ * with a sub-batch split).  Results are the same, bit for bit, either way. */
+ofdft_status ofdft_grid_set_knot_pipeline(ofdft_grid *grid, int32_t on);
 ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
                                  void *hip_stream, ofdft_tune_result *result);

@@ -180,6 +180,12 @@ struct ofdft_grid {
     // first use)
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_stagger = nullptr;
+    // knot pipeline: a second knot-spectrum buffer (allocated by the rule
+    // in knot_pipe_fits) lets a batch's knot transforms run on s2 beside
+    // the previous batch's row pass; events fork, ready[2], free[2]
+    void *kspec2 = nullptr;
+    int tune_knot_pipe = 1;
+    hipEvent_t kev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     bool stagger_after_fwd = false;
     const std::atomic<int> *cancel = nullptr;   // checked once per optimiser iteration
     struct EvalBatcher *batcher = nullptr;      // lockstep optimisation: evaluations merged
@@ -536,6 +542,15 @@ static int pstride_of(const Geom &G, bool fp64, bool vw64)
 {
     return vw64 ? std::max(max_pstride(G, false), max_pstride(G, true)) : max_pstride(G, fp64);
 }
+// the knot pipeline's second buffer: spline grids with more than one knot
+// batch whose knot spectra take at most 4 GiB (a 256 x 256 x 384 grid: 0.8 GB
+// in FP32; the 1024^3 grid's 34 GB are not doubled)
+constexpr uint64_t KNOT_PIPE_MAX_BYTES = 4ull << 30;
+static bool knot_pipe_fits(int nk, uint64_t kspec_bytes)
+{
+    return nk > MAXKB && kspec_bytes <= KNOT_PIPE_MAX_BYTES;
+}
+
 static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies, int sf_method,
                             uint32_t terms, int nl_mode, int nk, uint64_t cap, uint64_t ions,
                             BytesModel m)
@@ -555,6 +570,8 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     b += 4 * cap * Nh * cb;                                             // spectra
     if (terms & OFDFT_TERM_SPLINE) {
         b += (uint64_t)MAXKB * cap * Nh * cb;                           // knot spectra
+        if (knot_pipe_fits(nk, (uint64_t)MAXKB * cap * Nh * cb))
+            b += (uint64_t)MAXKB * cap * Nh * cb;                       // second knot buffer
         b += cap * N * fsz;                                             // accumulator
         if (nl_mode == OFDFT_NL_EXACT) b += cap * N * fsz;
         b += cap * (2 * (uint64_t)KR_BLOCKS * 8 + 2 * 4);               // knot range
@@ -587,6 +604,8 @@ static uint64_t workspace_bytes(const ofdft_grid *g, int nb)
     uint64_t b = 4ull * nb * G.Nh * cbytes;
     if (spline) {
         b += (uint64_t)MAXKB * nb * G.Nh * cbytes + (uint64_t)nb * G.N * g->fsz;
+        if (knot_pipe_fits(g->knots.nk, (uint64_t)MAXKB * nb * G.Nh * cbytes))
+            b += (uint64_t)MAXKB * nb * G.Nh * cbytes;
         if (g->func.nl_mode == OFDFT_NL_EXACT) b += (uint64_t)nb * G.N * g->fsz;
         b += (uint64_t)nb * 2 * KR_BLOCKS * sizeof(double) + (uint64_t)nb * 2 * sizeof(int);
     }
@@ -603,6 +622,7 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
     // drop the old workspace
     dfree(g->spec);
     dfree(g->kspec);
+    dfree(g->kspec2);
     dfree(g->acc1);
     dfree(g->acc2);
     dfree(g->stage_in);
@@ -622,6 +642,8 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
     ST_TRY(dmalloc(g, &g->spec, 4 * (size_t)nb * G.Nh * cbytes));
     if (spline) {
         ST_TRY(dmalloc(g, &g->kspec, (size_t)MAXKB * nb * G.Nh * cbytes));
+        if (knot_pipe_fits(g->knots.nk, (uint64_t)MAXKB * nb * G.Nh * cbytes))
+            ST_TRY(dmalloc(g, &g->kspec2, (size_t)MAXKB * nb * G.Nh * cbytes));
         ST_TRY(dmalloc(g, &g->acc1, (size_t)nb * G.N * g->fsz));
         if (g->func.nl_mode == OFDFT_NL_EXACT)
             ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
@@ -738,6 +760,7 @@ static ofdft_status ensure_lane(ofdft_grid *g)
     HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&g->ev_stagger, hipEventDisableTiming));
+    for (hipEvent_t &e : g->kev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return OFDFT_OK;
 }
 
@@ -745,7 +768,7 @@ static ofdft_status ensure_lane(ofdft_grid *g)
 // buffer offset to density b0 (the spectra slots of the sub-batch are laid
 // out as for a batch of nb, inside its own share of the workspace).
 struct Work {
-    char *spec, *kspec;
+    char *spec, *kspec, *kspec2;
     void *acc1, *acc2;
     char *vwspec;     // FP64 von Weizsaecker leg: spectrum and result
     void *vwout;
@@ -762,6 +785,7 @@ static Work work_of(const ofdft_grid *g, int b0)
     Work w;
     w.spec = (char *)g->spec + (size_t)4 * b0 * G.Nh * cb;
     w.kspec = g->kspec ? (char *)g->kspec + (size_t)MAXKB * b0 * G.Nh * cb : nullptr;
+    w.kspec2 = g->kspec2 ? (char *)g->kspec2 + (size_t)MAXKB * b0 * G.Nh * cb : nullptr;
     w.acc1 = g->acc1 ? (char *)g->acc1 + (size_t)b0 * G.N * sizeof(T) : nullptr;
     w.acc2 = g->acc2 ? (char *)g->acc2 + (size_t)b0 * G.N * sizeof(T) : nullptr;
     w.vwspec = g->vwspec ? (char *)g->vwspec + (size_t)b0 * G.Nh * 16 : nullptr;
@@ -832,7 +856,7 @@ template <typename T>
 // synchronisation or host-to-device copy, so that the sequence can be
 // captured in a HIP graph.  d_in, d_v, d_g and w point at the first density.
 static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in_is_phi, void *d_v,
-                                 void *d_g, hipStream_t s, const Work &w)
+                                 void *d_g, hipStream_t s, const Work &w, bool knot_lane = true)
 {
     const Geom &G = g->geom;
     const Layout l = layout_of(g);
@@ -899,12 +923,26 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
                                                     w.kneed, s));
             kneed = w.kneed;
         }
-        for (int k0 = 0; k0 < nk; k0 += kb) {
+        // knot pipeline: batch i's knot transforms (inverse of omega_i
+        // rho^beta along axis 0 and axis 1) go to the second stream into
+        // buffer i % 2, the row pass (and the EXACT passes) of batch i stay
+        // on s and accumulate in order; s waits for the batch's transforms,
+        // the second stream for the row pass that last read its buffer
+        const bool kpipe = knot_lane && w.kspec2 && g->tune_knot_pipe && !g->timer.on && nk > kb;
+        if (kpipe) {
+            ST_TRY(ensure_lane(g));
+            HIP_TRY(hipEventRecord(g->kev[0], s));
+            HIP_TRY(hipStreamWaitEvent(g->s2, g->kev[0], 0));
+        }
+        for (int k0 = 0, bi = 0; k0 < nk; k0 += kb, ++bi) {
             const int K = std::min(kb, nk - k0);
+            char *ks = (kpipe && (bi & 1)) ? w.kspec2 : w.kspec;
+            hipStream_t sf = kpipe ? g->s2 : s;
+            if (kpipe && bi >= 2) HIP_TRY(hipStreamWaitEvent(sf, g->kev[3 + (bi & 1)], 0));
             KnotArgs ka;
             std::memset(&ka, 0, sizeof(ka));
             ka.src = slot_ptr(l.s_rhob);
-            ka.dst = w.kspec;
+            ka.dst = ks;
             ka.fstride = G.Nh;
             ka.ncols = (long long)G.n1 * G.n2h;
             ka.knot0 = k0;
@@ -916,13 +954,17 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             ka.ct = g->cur_ct;
             ka.tw = g->tw0;
             ka.g = G;
-            TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, s));
+            TIMED(PS_KNOT_INV, launch_knot_inv<T>(ka, sf));
             if (!plane)
-                ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 1, nullptr, PS_KNOT_COL1, w.part,
+                ST_TRY(col_pass<T>(g, sf, 1, ks, K * nb, nb, 1, nullptr, PS_KNOT_COL1, w.part,
                                    nullptr, kneed, k0));
+            if (kpipe) {
+                HIP_TRY(hipEventRecord(g->kev[1 + (bi & 1)], sf));
+                HIP_TRY(hipStreamWaitEvent(s, g->kev[1 + (bi & 1)], 0));
+            }
             RowInvArgs ri;
             std::memset(&ri, 0, sizeof(ri));
-            ri.spec = w.kspec;
+            ri.spec = ks;
             ri.spec_fstride = fs;
             ri.nfields = K;
             ri.mode = EP_KNOTS;
@@ -947,7 +989,7 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
             if (exact) {
                 // f_i = rho^a L_i(k~): r2c, axis 1, then axis 0 with omega_i, summed into H
                 RowFwdArgs ef = rf;
-                ef.out = w.kspec;
+                ef.out = ks;
                 ef.out_fstride = fs;
                 ef.nfields = K;
                 for (int f = 0; f < K; ++f) ef.kind[f] = FK_KNOT;
@@ -961,15 +1003,16 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
                 } else {
                     ef.kneed = kneed;
                     TIMED(PS_EXACT_FWD, launch_row_fwd<T>(G, nb, ef, nbe, s));
-                    ST_TRY(col_pass<T>(g, s, 1, w.kspec, K * nb, nb, 0, nullptr, PS_EXACT_FWD, w.part,
+                    ST_TRY(col_pass<T>(g, s, 1, ks, K * nb, nb, 0, nullptr, PS_EXACT_FWD, w.part,
                                        nullptr, kneed, k0));
                 }
                 KnotArgs kc = ka;
-                kc.src = w.kspec;
+                kc.src = ks;
                 kc.dst = slot_ptr(l.s_h);
                 kc.accumulate = (k0 > 0);
                 TIMED(PS_EXACT_ACC, launch_knot_acc<T>(kc, s));
             }
+            if (kpipe) HIP_TRY(hipEventRecord(g->kev[3 + (bi & 1)], s));
         }
         if (exact) {
             ST_TRY(col_pass<T>(g, s, 0, slot_ptr(l.s_h), nb, nb, 1, nullptr, PS_EXACT_ACC, w.part));
@@ -1064,7 +1107,8 @@ static ofdft_status eval_enqueue_pipe(ofdft_grid *g, int nb, const void *d_in, i
         void *v = d_v ? (char *)d_v + b0 * N * sizeof(T) : nullptr;
         void *gv = d_g ? (char *)d_g + b0 * N * sizeof(T) : nullptr;
         g->stagger_after_fwd = (j == 0);
-        const ofdft_status st = eval_enqueue<T>(g, n, in, in_is_phi, v, gv, sj, work_of<T>(g, b0));
+        const ofdft_status st =
+            eval_enqueue<T>(g, n, in, in_is_phi, v, gv, sj, work_of<T>(g, b0), false);
         g->stagger_after_fwd = false;
         ST_TRY(st);
     }
@@ -1351,6 +1395,7 @@ static void grid_free(ofdft_grid *g)
     dfree(reinterpret_cast<void *&>(g->d_jtab64));
     dfree(g->spec);
     dfree(g->kspec);
+    dfree(g->kspec2);
     dfree(g->acc1);
     dfree(g->acc2);
     dfree(g->stage_in);
@@ -1379,6 +1424,11 @@ static void grid_free(ofdft_grid *g)
     g->h_sums = nullptr;
     for (hipEvent_t e : g->timer.ev) (void)hipEventDestroy(e);
     g->timer.ev.clear();
+    for (hipEvent_t &e : g->kev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     for (hipEvent_t *e : {&g->ev_fork, &g->ev_join, &g->ev_stagger})
         if (*e) {
             (void)hipEventDestroy(*e);
@@ -2282,7 +2332,7 @@ static ofdft_status interpolate_density(ofdft_grid *dst, ofdft_grid *src)
 // keeps the fastest; results are shared by all grids of the same shape,
 // precision, functional and batch size in the process.
 struct TuneVal {
-    int plane, tile_major, kb, pipe, cgrp;
+    int plane, tile_major, kb, pipe, cgrp, kpipe;
 };
 using TuneKey = std::tuple<int, int, int, int, uint32_t, int, int, int>;
 static std::mutex g_tune_mu;
@@ -2305,6 +2355,7 @@ static void tune_apply_cached(ofdft_grid *g, int nb)
     g->tune_kb = it->second.kb;
     g->tune_pipe = it->second.pipe;
     g->tune_col_group = it->second.cgrp;
+    g->tune_knot_pipe = it->second.kpipe;
     graphs_clear(g);
 }
 
@@ -2324,8 +2375,10 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         for (int tm : {0, 1})
             for (int kb : {MAXKB, MAXKB / 2})
                 for (int cg : {COL_GROUP, 1})
-                    if ((spline || kb == MAXKB) && (nb > 1 || cg == COL_GROUP))
-                        cand.push_back({pl, tm, kb, g->tune_pipe, cg});
+                    for (int kp : {1, 0})
+                        if ((spline || kb == MAXKB) && (nb > 1 || cg == COL_GROUP) &&
+                            (g->kspec2 || kp == 1))
+                            cand.push_back({pl, tm, kb, g->tune_pipe, cg, kp});
     }
     std::vector<ofdft_energy> e((size_t)nb);
     double best = 1e300, dflt = 0.0;
@@ -2336,6 +2389,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         g->tune_kb = cand[c].kb;
         g->tune_pipe = cand[c].pipe;
         g->tune_col_group = cand[c].cgrp;
+        g->tune_knot_pipe = cand[c].kpipe;
         graphs_clear(g);
         ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));   // warm-up
         double t[3];
@@ -2356,6 +2410,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
     g->tune_kb = pick.kb;
     g->tune_pipe = pick.pipe;
     g->tune_col_group = pick.cgrp;
+    g->tune_knot_pipe = pick.kpipe;
     graphs_clear(g);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2370,6 +2425,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         out->default_ms = dflt;
         out->pipe = pick.pipe;
         out->col_group = pick.cgrp;
+        out->knot_pipe = pick.kpipe;
     }
     return OFDFT_OK;
 }
@@ -3427,6 +3483,14 @@ ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on)
     if (!grid) return fail(OFDFT_EINVAL, "null grid");
     if ((on != 0) != grid->knot_skip) graphs_clear(grid);
     grid->knot_skip = on != 0;
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_set_knot_pipeline(ofdft_grid *grid, int32_t on)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null grid");
+    if ((on != 0) != (grid->tune_knot_pipe != 0)) graphs_clear(grid);
+    grid->tune_knot_pipe = on != 0;
     return OFDFT_OK;
 }
 

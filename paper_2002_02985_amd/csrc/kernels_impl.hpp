@@ -1119,6 +1119,55 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
     lds_fft<T, M, true, P, NT, PS>(buf, twM, tid);
 }
 
+// c2r of the same block of rows of two spectra (knots i and i + 1) at once:
+// pencil p < P is row r0 + p of sa, pencil P + p the same row of sb (zeros
+// without sb), element n of pencil p at buf[n * PS2 + p], PS2 = 2P + 1.
+// Twice the butterflies per Stockham stage of a one-spectrum pass, so that
+// the stages of a 192-point knot row keep more waves busy between barriers.
+template <typename T, int M, int P>
+__device__ __forceinline__ void c2r_rows2(cpx<T> *buf, const cpx<T> *__restrict__ sa,
+                                          const cpx<T> *__restrict__ sb, long long r0,
+                                          long long nrows, int n2h,
+                                          const cpx<T> *__restrict__ twM,
+                                          const cpx<T> *__restrict__ twN, int tid)
+{
+    constexpr int P2 = 2 * P, PS2 = P2 + 1;
+    // k = 0 .. M/2: each load pair (X[k], X[M-k]) gives Z[k] and Z[M-k]
+    // (Z[M-k] for 0 < k, k != M - k)
+    constexpr int H = M / 2 + 1;
+    constexpr int ITEMS = P2 * H;
+    for (int o = tid; o < ITEMS; o += NT) {
+        const int pp = o / H, k = o % H;
+        const int p = pp < P ? pp : pp - P;
+        const cpx<T> *spec = pp < P ? sa : sb;
+        const long long row = r0 + p;
+        cpx<T> z0 = {T(0), T(0)}, z1 = {T(0), T(0)};
+        if (spec && row < nrows) {
+            const cpx<T> *x = spec + row * n2h;
+            cpx<T> xk = x[k];
+            cpx<T> xm = x[M - k];
+            if (k == 0) {
+                xk.y = T(0);
+                xm.y = T(0);
+            }
+            // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k)
+            const cpx<T> s0 = {xk.x + xm.x, xk.y - xm.y};
+            const cpx<T> d0 = {xk.x - xm.x, xk.y + xm.y};
+            const cpx<T> w0 = cmul(d0, cconj(twN[k]));
+            z0 = {s0.x - w0.y, s0.y + w0.x};
+            // Z[M-k] from the same pair, X[M-k] and X[k] exchanged
+            const cpx<T> s1 = {xm.x + xk.x, xm.y - xk.y};
+            const cpx<T> d1 = {xm.x - xk.x, xm.y + xk.y};
+            const cpx<T> w1 = cmul(d1, cconj(twN[M - k]));
+            z1 = {s1.x - w1.y, s1.y + w1.x};
+        }
+        buf[k * PS2 + pp] = z0;
+        if (k > 0 && 2 * k != M) buf[(M - k) * PS2 + pp] = z1;
+    }
+    __syncthreads();
+    lds_fft<T, M, true, P2, NT, PS2>(buf, twM, tid);
+}
+
 // The knot epilogue is instantiated with CF = CB_SPL (S3S4) or CB_SPL |
 // CB_EXACT and asks for at least 4 resident waves per SIMD (128 VGPRs):
 // measured faster than the 3 its unconstrained allocation allows.
@@ -1134,7 +1183,11 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     constexpr int PS = P + 1;
     constexpr int PAIRS = P * M;
     constexpr int PER = (PAIRS + NT - 1) / NT;
-    __shared__ cpx<T> buf[M * PS];
+    // the knot epilogue transforms two knots' rows at once (c2r_rows2) for
+    // rows of up to 256 complex points (longer rows have enough butterflies
+    // per stage, and the pair's registers would spill)
+    constexpr bool PAIR = MODE == EP_KNOTS && M <= 256;
+    __shared__ cpx<T> buf[M * (PAIR ? 2 * P + 1 : PS)];
     __shared__ double red[5 * NT / 64];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
@@ -1229,21 +1282,37 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
             v2[q] = {T(0), T(0)};
         }
         const int nk = a.knots.nk;
-        for (int f = 0; f < a.nfields; ++f) {
+        constexpr int PS2 = 2 * P + 1;
+        // knots f and f + 1 per pass (PAIR, else one); a pass is skipped if
+        // no point of this block uses its knots (a knot used by none adds
+        // exact zeros)
+        for (int f = 0; f < a.nfields; f += PAIR ? 2 : 1) {
             const int i = a.knot0 + f;
-            // skip the transform if no point of this block uses knot i
+            const bool two = PAIR && f + 1 < a.nfields;
             bool need = false;
 #pragma unroll
             for (int q = 0; q < PER; ++q)
-                need |= valid[q] && (nk == 1 || jj[q][0] == i || jj[q][0] + 1 == i ||
-                                     jj[q][1] == i || jj[q][1] + 1 == i);
+                need |= valid[q] && (nk == 1 || (jj[q][0] >= i - 1 && jj[q][0] <= i + (two ? 1 : 0)) ||
+                                     (jj[q][1] >= i - 1 && jj[q][1] <= i + (two ? 1 : 0)));
             if (!__syncthreads_or(need)) continue;
-            c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
+            if constexpr (PAIR) {
+                c2r_rows2<T, M, P>(buf, spec_of(f), two ? spec_of(f + 1) : nullptr, r0, nrows,
+                                   g.n2h, twM, twN, tid);
 #pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                if (!valid[q]) continue;
-                const cpx<T> z = buf[lds_at[q]];
-                knot_interp(jj[q], tt[q], i, nk, exact, z, v1[q], v2[q]);
+                for (int q = 0; q < PER; ++q) {
+                    if (!valid[q]) continue;
+                    const int at2 = (lds_at[q] / PS) * PS2 + lds_at[q] % PS;
+                    knot_interp(jj[q], tt[q], i, nk, exact, buf[at2], v1[q], v2[q]);
+                    if (two)
+                        knot_interp(jj[q], tt[q], i + 1, nk, exact, buf[at2 + P], v1[q], v2[q]);
+                }
+            } else {
+                c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    if (!valid[q]) continue;
+                    knot_interp(jj[q], tt[q], i, nk, exact, buf[lds_at[q]], v1[q], v2[q]);
+                }
             }
             __syncthreads();
         }

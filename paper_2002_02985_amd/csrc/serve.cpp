@@ -139,6 +139,10 @@ struct ofdft_server {
     std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;   // unreleased tickets
     std::vector<std::unique_ptr<Res>> res;
     uint64_t used = 0, peak = 0, clock = 0, next_ticket = 1;
+    // bytes of admitted new grids not yet allocated: their worker first saves
+    // and frees the grids it evicts (still counted in used meanwhile), so the
+    // device holds at most used - unalloc bytes; the peak records that
+    uint64_t unalloc = 0;
     int running = 0;
     bool stop = false;
     uint64_t n_sub = 0, n_done = 0, n_fail = 0, n_cancel = 0;
@@ -482,7 +486,7 @@ void worker_loop(ofdft_server *s, int w)
                         ofdft_internal::multi_growth_bytes(L.g, (int)batch.size() + 1);
                     s->used += grow;
                     s->res[lr]->bytes += grow;
-                    s->peak = std::max(s->peak, s->used);
+                    s->peak = std::max(s->peak, s->used - s->unalloc);
                 }
             }
         }
@@ -516,6 +520,7 @@ void worker_loop(ofdft_server *s, int w)
                                {x.cell.d.n[0], x.cell.d.n[1], x.cell.d.n[2]}});
         }
         Res *r = nullptr;
+        uint64_t new_bytes = 0;   // a new grid admitted for this request
         SavedDensity saved;
         const int ri = find_resident(s, job->cell_id);
         if (ri >= 0) {
@@ -533,6 +538,8 @@ void worker_loop(ofdft_server *s, int w)
             r = nr.get();
             s->res.push_back(std::move(nr));
             s->used += job->need;
+            s->unalloc += job->need;
+            new_bytes = job->need;
         }
         r->busy = true;
         s->running++;
@@ -572,7 +579,8 @@ void worker_loop(ofdft_server *s, int w)
         }
         {
             std::lock_guard<std::mutex> g2(s->mu);
-            s->peak = std::max(s->peak, s->used);
+            s->unalloc -= new_bytes;   // the evictions are done: the new grid may now allocate
+            s->peak = std::max(s->peak, s->used - s->unalloc);
         }
         if (batch.empty()) {
             execute(*job, *r, ctx, saved);
@@ -596,7 +604,7 @@ void worker_loop(ofdft_server *s, int w)
                 s->used += now - r->bytes;
                 r->bytes = now;
             }
-            s->peak = std::max(s->peak, s->used);
+            s->peak = std::max(s->peak, s->used - s->unalloc);
             s->n_batched += batch.size() + 1;
             s->n_batches++;
         }

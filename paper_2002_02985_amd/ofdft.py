@@ -87,7 +87,8 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("plane", ctypes.c_int32), ("col_tile_major", ctypes.c_int32),
                 ("knot_batch", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
-                ("pipe", ctypes.c_int32), ("col_group", ctypes.c_int32)]
+                ("pipe", ctypes.c_int32), ("col_group", ctypes.c_int32),
+                ("knot_pipe", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -164,6 +165,7 @@ _SIGS = {
                                           ctypes.POINTER(TdStats)]),
     "ofdft_grid_set_knot_skip": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_col_group": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_set_knot_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
     "ofdft_grid_tune": (ctypes.c_int, [_P, ctypes.POINTER(TuneResult)]),
@@ -506,6 +508,10 @@ def ofdft_grid_set_knot_skip(grid, on=True):
 
 def ofdft_grid_set_col_group(grid, n):
     check(load().ofdft_grid_set_col_group(grid, int(n)))
+
+
+def ofdft_grid_set_knot_pipeline(grid, on=True):
+    check(load().ofdft_grid_set_knot_pipeline(grid, 1 if on else 0))
 
 
 def ofdft_grid_set_pipeline(grid, nsub):

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_host_helpers():
-    assert ofdft.ofdft_abi_version() == 6
+    assert ofdft.ofdft_abi_version() == 7
     for n in (4, 6, 12, 32, 48, 96, 192, 256, 384, 1024):
         assert ofdft.ofdft_supported_length(n)
     for n in (5, 7, 10, 100, 2048):

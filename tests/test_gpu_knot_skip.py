@@ -86,3 +86,29 @@ def test_knot_skip_on_the_slab_grid():
         e_off, v_off = run(g, [rho], False)
     assert e_on[0]["e_total"] == e_off[0]["e_total"]
     assert np.array_equal(v_on, v_off)
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED, ofdft.MIXED_VW64])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_knot_pipeline_matches_one_stream(case, prec):
+    """24 knots = 3 batches: with the knot pipeline the knot transforms of a
+    batch run on the grid's second stream into alternating buffers; the
+    energies and potentials are the same, bit for bit, as on one stream."""
+    n, mode = CASES[case]
+    cell = box(n)
+    rhos = densities(cell)
+    print("case knot pipeline", case, prec, flush=True)
+    with ofdft.Grid(cell, LOCAL | ofdft.TERM_SPLINE, precision=prec, nk=24, kf_min=0.1,
+                    kf_max=3.0, nl_mode=mode) as g:
+        ofdft.ofdft_grid_set_knot_pipeline(g.handle, True)
+        e_on, v_on = run(g, rhos, True)
+        ofdft.ofdft_grid_set_knot_pipeline(g.handle, False)
+        e_off, v_off = run(g, rhos, True)
+        ofdft.ofdft_grid_set_knot_pipeline(g.handle, True)
+        e_on2, v_on2 = run(g, rhos, True)
+    for b in range(len(rhos)):
+        for k in e_on[b]:
+            assert e_on[b][k] == e_off[b][k], (case, b, k)
+            assert e_on2[b][k] == e_on[b][k]
+    assert np.array_equal(v_on, v_off)
+    assert np.array_equal(v_on2, v_on)
