@@ -15,8 +15,25 @@
 // host and rounded to the field type.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace ofdft {
+
+// A workgroup barrier for data exchanged through LDS: the wave's LDS
+// operations complete (s_waitcnt lgkmcnt(0)) before the barrier, and the
+// empty asm statements with a memory clobber keep the compiler from moving
+// memory accesses across it.  Global loads, stores and asynchronous LDS
+// copies in flight are not waited for (__syncthreads, whose workgroup fence
+// also covers global memory and LDS copies, would wait for them).  Every
+// barrier of the transforms below exchanges data through LDS alone.
+constexpr int WAIT_LGKM0 = 0xC07F;   // s_waitcnt lgkmcnt(0), other counters at their maximum
+__device__ __forceinline__ void lds_sync()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <typename T>
 struct cpx {
@@ -269,7 +286,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
             for (int r = 0; r < R; ++r) v[q][r] = buf[a0 + (unsigned)(r * NBF * ES)];
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const unsigned b = ut + (unsigned)(q * NT);
@@ -293,18 +310,34 @@ __device__ __forceinline__ void stockham_stage(cpx<T> *buf, const cpx<T> *tw,
             for (int r = 0; r < R; ++r) buf[a0 + (unsigned)(r * NS * ES)] = v[q][r];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // The first stage of a transform with its inputs taken from src(n, p)
 // (element n of pencil p, read from memory or computed) instead of LDS; the
 // outputs go to buf as in stockham_stage.  NS = 1: no twiddles.
+// A source src(n, p) takes element n of pencil p.  A source that also takes
+// three arguments is called as src(nb, dn, p) with n = nb + dn, where dn is
+// the same for every lane (a constant of the unrolled loops): it can form
+// one per-lane offset from nb and hand dn to the scalar part of the address.
+// Destinations likewise: dst(n, p, v), or dst(nb, dn, p, v).
+template <class SRC>
+constexpr bool src_split() { return std::is_invocable_v<const SRC &, unsigned, unsigned, unsigned>; }
+template <class DST, typename T>
+constexpr bool dst_split()
+{
+    return std::is_invocable_v<const DST &, unsigned, unsigned, unsigned, cpx<T>>;
+}
+
 template <typename T, int L, int R, bool INV, int P, int NT, int ES, int PS, class SRC>
 __device__ __forceinline__ void stockham_stage_src(cpx<T> *buf, int tid, const SRC &src)
 {
     constexpr int NBF = L / R;
     constexpr int TOT = NBF * P;
     constexpr int PER = (TOT + NT - 1) / NT;
+    // with NT a multiple of P a lane keeps its pencil across q and its
+    // element index moves by the constant q NT / P
+    constexpr bool EVEN = NT % P == 0;
     asm volatile("" : "+v"(tid));
     const unsigned ut = (unsigned)tid;
     cpx<T> v[PER][R];
@@ -314,11 +347,19 @@ __device__ __forceinline__ void stockham_stage_src(cpx<T> *buf, int tid, const S
         if (TOT % NT == 0 || b < (unsigned)TOT) {
             const unsigned j = b / (unsigned)P;
             const unsigned p = b % (unsigned)P;
+            if constexpr (src_split<SRC>()) {
+                const unsigned jb = EVEN ? ut / (unsigned)P : j;
+                const unsigned pb = EVEN ? ut % (unsigned)P : p;
+                const unsigned DQ = EVEN ? (unsigned)(q * (NT / P)) : 0u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = src(j + (unsigned)(r * NBF), p);
+                for (int r = 0; r < R; ++r) v[q][r] = src(jb, DQ + (unsigned)(r * NBF), pb);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[q][r] = src(j + (unsigned)(r * NBF), p);
+            }
         }
     }
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const unsigned b = ut + (unsigned)(q * NT);
@@ -331,7 +372,7 @@ __device__ __forceinline__ void stockham_stage_src(cpx<T> *buf, int tid, const S
             for (int r = 0; r < R; ++r) buf[a0 + (unsigned)(r * ES)] = v[q][r];
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // The last stage of a transform (NS R = L) with its outputs handed to
@@ -365,11 +406,20 @@ __device__ __forceinline__ void stockham_stage_dst(const cpx<T> *buf, const cpx<
                 }
             }
             dft<T, R, INV>(v);
+            if constexpr (dst_split<DST, T>()) {
+                constexpr bool EVEN = NT % P == 0;
+                const unsigned jb = EVEN ? ut / (unsigned)P : j;
+                const unsigned pb = EVEN ? ut % (unsigned)P : p;
+                const unsigned DQ = EVEN ? (unsigned)(q * (NT / P)) : 0u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst(j + (unsigned)(r * NS), p, v[r]);
+                for (int r = 0; r < R; ++r) dst(jb, DQ + (unsigned)(r * NS), pb, v[r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) dst(j + (unsigned)(r * NS), p, v[r]);
+            }
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS>
@@ -384,7 +434,7 @@ __device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *tw, int ti
 }
 
 // Transform P pencils of length L held in LDS (buf[n * ES + p * PS]), in
-// place.  Caller must __syncthreads() after filling buf; returns after a
+// place.  Caller must lds_sync() after filling buf; returns after a
 // barrier.
 template <typename T, int L, bool INV, int P, int NT, int ES, int PS = 1>
 __device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *tw, int tid)
@@ -401,7 +451,7 @@ __device__ __forceinline__ void lds_fft_src(cpx<T> *buf, const cpx<T> *tw, int t
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
     constexpr Plan pl = make_plan(L, sizeof(T) == 4);
-    __syncthreads();
+    lds_sync();
     stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
     fft_stages<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid);
 }
@@ -438,16 +488,17 @@ __device__ __forceinline__ void lds_fft_io(cpx<T> *buf, const cpx<T> *tw, int ti
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
     constexpr Plan pl = make_plan(L, sizeof(T) == 4);
-    __syncthreads();
+    lds_sync();
     stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
     if constexpr (pl.n >= 2) {
         fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid, dst);
     } else {
         for (unsigned o = (unsigned)tid; o < (unsigned)(L * P); o += NT) {
             const unsigned n = o / (unsigned)P, p = o % (unsigned)P;
-            dst(n, p, buf[n * ES + p * PS]);
+            if constexpr (dst_split<DST, T>()) dst(n, 0u, p, buf[n * ES + p * PS]);
+            else dst(n, p, buf[n * ES + p * PS]);
         }
-        __syncthreads();
+        lds_sync();
     }
 }
 
@@ -493,7 +544,7 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double *red, int tid)
 #pragma unroll
         for (int k = 0; k < K; ++k) red[k * NW + (tid >> 6)] = v[k];
     }
-    __syncthreads();
+    lds_sync();
     if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -503,7 +554,7 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double *red, int tid)
             v[k] = s;
         }
     }
-    __syncthreads();
+    lds_sync();
 }
 
 // As block_sums, through LDS, for blocks with a free LDS area of K * NT
@@ -517,10 +568,10 @@ __device__ __forceinline__ void block_sums_lds(double (&v)[K], double *lds, doub
 {
     static_assert(NT % 64 == 0 && K * 64 <= NT, "one wave per quantity");
     constexpr int NW = NT / 64;
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int k = 0; k < K; ++k) lds[k * NT + tid] = v[k];
-    __syncthreads();
+    lds_sync();
     if (tid < K * 64) {
         const int k = tid >> 6, l = tid & 63;
         double s = 0.0;
@@ -529,7 +580,7 @@ __device__ __forceinline__ void block_sums_lds(double (&v)[K], double *lds, doub
         s = wave_sum_to_last(s);
         if (l == 63) red[k] = s;
     }
-    __syncthreads();
+    lds_sync();
     if (tid == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = red[k];
@@ -551,6 +602,64 @@ __device__ __forceinline__ void st32(V *base, unsigned i, V v)
 {
     *(V *)((char *)base + i * (unsigned)sizeof(V)) = v;
 }
+
+// Loads and stores through a buffer resource over a region of `bytes` bytes
+// (under 4 GiB) at `base`: the address is base + soff + voff, with voff a
+// 32-bit per-lane byte offset and soff a wave-uniform one, which the
+// hardware takes from a scalar register, so that the constant strides
+// between a lane's elements cost no vector instruction.  Callers keep every
+// access inside the region.
+struct BufRes {
+    __amdgpu_buffer_rsrc_t r;
+};
+// word 3 of a gfx9 buffer resource: 32-bit data format, no swizzle
+constexpr int BUF_RES_WORD3 = 0x00020000;
+__device__ __forceinline__ BufRes buf_res(const void *base, unsigned bytes)
+{
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                              BUF_RES_WORD3)};
+}
+typedef unsigned buf_u32x2 __attribute__((vector_size(8)));
+typedef unsigned buf_u32x4 __attribute__((vector_size(16)));
+template <typename V>
+__device__ __forceinline__ V bld(const BufRes &b, unsigned voff, unsigned soff)
+{
+    static_assert(sizeof(V) == 8 || sizeof(V) == 16, "8- or 16-byte elements");
+    if constexpr (sizeof(V) == 8)
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(b.r, voff, soff, 0));
+    else
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(b.r, voff, soff, 0));
+}
+template <typename V>
+__device__ __forceinline__ void bst(const BufRes &b, unsigned voff, unsigned soff, V v)
+{
+    static_assert(sizeof(V) == 8 || sizeof(V) == 16, "8- or 16-byte elements");
+    if constexpr (sizeof(V) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u32x2, v), b.r, voff, soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(buf_u32x4, v), b.r, voff, soff, 0);
+}
+
+// Copy `bytes` (a multiple of 16; both addresses 16-byte aligned) from
+// global memory straight into LDS, without registers: the waves of an
+// NT-thread block take 1 KB chunks in turn, lane l of a wave moving the 16
+// bytes at offset 16 l of its chunk (global_load_lds_dwordx4).  The copy is
+// asynchronous: lds_copy_wait() and a barrier come before any read of dst.
+template <int NT>
+__device__ __forceinline__ void lds_copy_async(void *dst, const void *src, unsigned bytes, int tid)
+{
+    const unsigned w = (unsigned)tid / 64u, l = (unsigned)tid % 64u;
+    const unsigned nchunk = (bytes + 1023u) / 1024u;
+    for (unsigned c = w; c < nchunk; c += (unsigned)(NT / 64)) {
+        const unsigned off = c * 1024u + l * 16u;
+        if (off < bytes)
+            __builtin_amdgcn_global_load_lds(
+                (const char *)src + off,
+                (__attribute__((address_space(3))) char *)((char *)dst + c * 1024u), 16, 0, 0);
+    }
+}
+// waits for this wave's outstanding memory operations (the copies above)
+__device__ __forceinline__ void lds_copy_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 template <int NT>
 __device__ __forceinline__ double block_sum(double x, double *red, int tid)

@@ -141,7 +141,9 @@ __device__ __forceinline__ float d_log2(float x) { return __builtin_amdgcn_logf(
 __device__ __forceinline__ double d_log2(double x) { return log2(x); }
 __device__ __forceinline__ float d_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double d_exp2(double x) { return exp2(x); }
-__device__ __forceinline__ float d_fmax(float x, float y) { return __builtin_fmaxf(x, y); }
+// max for operands that are never NaN: the IEEE-754 2019 maximum (one
+// instruction; fmaxf would first quiet both operands)
+__device__ __forceinline__ float d_fmax(float x, float y) { return __builtin_elementwise_maximum(x, y); }
 __device__ __forceinline__ double d_fmax(double x, double y) { return __builtin_fmax(x, y); }
 template <typename T> __device__ __forceinline__ T neg_inf() { return -__builtin_huge_valf(); }
 template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
@@ -940,13 +942,16 @@ __device__ __forceinline__ CombineConst<T> combine_const(const RowInvArgs &a)
 template <int CF> constexpr int combine_nsum() { return (CF == 0 || (CF & CB_XC)) ? 5 : 4; }
 
 // PH: 1 = x is phi, 0 = x is rho (both fixed at compile time, fixed term
-// sets only), -1 = taken from the arguments.
-template <typename T, int CF, int PH = -1>
+// sets only), -1 = taken from the arguments.  S: the type of the partial
+// sums (double; the fixed term sets also take T, a thread's own few points,
+// which the caller adds to its FP64 sums).
+template <typename T, int CF, int PH = -1, typename S = double>
 __device__ __forceinline__ void combine_point(const RowInvArgs &a, const CombineConst<T> &cc, T x,
                                               T hv, T wv, T nl, T s1, T s2, T &vo, T &go,
-                                              double (&sums)[combine_nsum<CF>()])
+                                              S (&sums)[combine_nsum<CF>()])
 {
     static_assert(PH == -1 || CF != 0, "the general combine reads the input kind at run time");
+    static_assert(CF != 0 || sizeof(S) == 8, "the general combine sums in FP64");
     const bool in_phi = PH < 0 ? a.in_is_phi != 0 : PH == 1;
     T phi, rho;
     if (in_phi) {
@@ -979,25 +984,34 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
         const T sgn = PH == 0 ? T(1) : (phi < T(0) ? T(-1) : T(1));
         const T p4 = p2 * p2;
         const T q3 = q * q * q;
-        if constexpr ((CF & CB_H) != 0) {
-            vv += hv;
-            gg += T(2) * phi * hv;
-        }
-        if constexpr ((CF & CB_VW) != 0) {
-            vv += T(0.5) * wv * sgn * q3;
-            gg += wv;
-        }
-        if constexpr ((CF & CB_TF) != 0) {
+        // every fixed set the host picks holds H+ext, vW and TF: the sums
+        // start from them
+        if constexpr ((CF & CB_H) && (CF & CB_VW) && (CF & CB_TF)) {
             const T vt = T(5.0 / 3.0 * C_TF_D) * p4;
-            vv += vt;
-            gg += T(2) * phi * vt;
+            const T ht = hv + vt;
+            vv = ht + (PH == 0 ? T(0.5) : T(0.5) * sgn) * wv * q3;
+            gg = wv + T(2) * phi * ht;
+        } else {
+            if constexpr ((CF & CB_H) != 0) {
+                vv += hv;
+                gg += T(2) * phi * hv;
+            }
+            if constexpr ((CF & CB_VW) != 0) {
+                vv += T(0.5) * wv * sgn * q3;
+                gg += wv;
+            }
+            if constexpr ((CF & CB_TF) != 0) {
+                const T vt = T(5.0 / 3.0 * C_TF_D) * p4;
+                vv += vt;
+                gg += T(2) * phi * vt;
+            }
         }
         if constexpr ((CF & CB_XC) != 0) {
             T eps, vx;
             lda_xc_point(rho, p2, eps, vx);
             vv += vx;
             gg += T(2) * phi * vx;
-            sums[4] += (double)(rho * eps);
+            sums[4] += (S)(rho * eps);
         }
         if constexpr ((CF & (CB_WT | CB_A | CB_SPL)) != 0) {
             const T ra = p4 * p;         // rho^a
@@ -1005,14 +1019,14 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
             if constexpr ((CF & CB_WT) != 0) {
                 vv += T(2) * AL * q * nl;
                 gg += T(4) * AL * fa_ * nl;
-                sums[0] += (double)(ra * nl);
+                sums[0] += (S)(ra * nl);
             }
             if constexpr ((CF & CB_A) != 0) {
                 vv += AL * q * nl;
                 gg += T(2) * AL * fa_ * nl;
             }
             if constexpr ((CF & CB_SPL) != 0) {
-                sums[0] += (double)(ra * s1);
+                sums[0] += (S)(ra * s1);
                 if constexpr ((CF & CB_EXACT) == 0) {
                     vv += T(2) * AL * q * s1;
                     gg += T(4) * AL * fa_ * s1;
@@ -1077,9 +1091,9 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
             }
         }
     }
-    sums[1] += (double)gg * (double)phi;
-    sums[2] += (double)gg * (double)gg;
-    sums[3] += (double)phi * (double)phi;
+    sums[1] += (S)gg * (S)phi;
+    sums[2] += (S)gg * (S)gg;
+    sums[3] += (S)phi * (S)phi;
     vo = vv;
     go = gg;
 }
@@ -1376,6 +1390,9 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     // fixed term sets
     auto points = [&](auto ph) {
         constexpr int PH = decltype(ph)::value;
+        // a fixed term set sums a thread's few points in T first
+        using S = std::conditional_t<CF != 0, T, double>;
+        S ts[combine_nsum<CF>()] = {};
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             if (!valid[q]) continue;
@@ -1383,13 +1400,15 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
             if (acc1) a1 = *(const cpx<T> *)(acc1 + offs[q]);
             if (acc2) a2 = *(const cpx<T> *)(acc2 + offs[q]);
             cpx<T> vo, go;
-            combine_point<T, CF, PH>(a, cc, xin[q].x, fh[q].x, fl[q].x, fn[q].x, a1.x, a2.x, vo.x,
-                                     go.x, sums);
-            combine_point<T, CF, PH>(a, cc, xin[q].y, fh[q].y, fl[q].y, fn[q].y, a1.y, a2.y, vo.y,
-                                     go.y, sums);
+            combine_point<T, CF, PH, S>(a, cc, xin[q].x, fh[q].x, fl[q].x, fn[q].x, a1.x, a2.x,
+                                        vo.x, go.x, ts);
+            combine_point<T, CF, PH, S>(a, cc, xin[q].y, fh[q].y, fl[q].y, fn[q].y, a1.y, a2.y,
+                                        vo.y, go.y, ts);
             if (vout) *(cpx<T> *)(vout + offs[q]) = vo;
             if (gout) *(cpx<T> *)(gout + offs[q]) = go;
         }
+#pragma unroll
+        for (int k = 0; k < combine_nsum<CF>(); ++k) sums[k] = (double)ts[k];
     };
     if constexpr (CF != 0) {
         if (a.in_is_phi) points(std::integral_constant<int, 1>());
@@ -1430,7 +1449,7 @@ template <typename T, int N1, int M> constexpr bool plane_fits()
     // the padded plane, the staged input plane (N1 x 2M reals) if any and
     // the twiddles (N1 + 2M + 1 complex)
     const long long reals = (long long)(M + 1) * plane_A<N1>() * 2 +
-                            (plane_stage_x<T>() ? (long long)N1 * 2 * M : 0) +
+                            (plane_stage_x<T>() ? (long long)N1 * 2 * (M + 1) : 0) +
                             2LL * (N1 + 2 * M + 1);
     // FP64 planes larger than 96 x 48 spill registers at one 1024-thread
     // block per CU; those grids keep the row and column passes
@@ -1492,21 +1511,25 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     const cpx<T> *twM = tws + N1;
     const cpx<T> *twN = tws + N1 + M;
 
+    constexpr unsigned S = sizeof(cpx<T>);
+    const BufRes rin = buf_res(in, PAIRS * S);
     cpx<T> x[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
         const unsigned idx = (unsigned)(tid + q * NTP);
-        x[q] = idx < (unsigned)PAIRS ? ld32(in, idx) : cpx<T>{T(0), T(0)};
+        x[q] = idx < (unsigned)PAIRS ? bld<cpx<T>>(rin, (unsigned)tid * S, (unsigned)(q * NTP) * S)
+                                     : cpx<T>{T(0), T(0)};
         if constexpr (STX) {
             if (idx < (unsigned)PAIRS) xs[idx] = x[q];
         }
     }
-    __syncthreads();
+    lds_sync();
     const bool knots = a.nfields > 0 && a.kind[0] == FK_KNOT;
     if (a.partials) {
         double sums[3] = {0.0, 0.0, 0.0};
         auto count = [&](auto ph) {
             constexpr bool P = decltype(ph)::value;
+            T ts[2] = {T(0), T(0)};   // a thread's few points, summed in T
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 if (tid + q * NTP >= PAIRS) continue;
@@ -1520,10 +1543,12 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                         continue;
                     }
                     const T rho = P ? v * v : v;   // >= 0; log2(0) = -inf
-                    sums[0] += (double)rho;
-                    sums[1] += (double)(rho * d_exp2(d_log2(rho) * T(2.0 / 3.0)));
+                    ts[0] += rho;
+                    ts[1] += rho * d_exp2(d_log2(rho) * T(2.0 / 3.0));
                 }
             }
+            sums[0] = (double)ts[0];
+            sums[1] = (double)ts[1];
         };
         if (a.in_is_phi) count(std::true_type());
         else count(std::false_type());
@@ -1570,7 +1595,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 }
                 buf[n * A + i1] = {o[0], o[1]};
             }
-            __syncthreads();
+            lds_sync();
             // axis 2: half-length complex transforms of the N1 rows
             lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         } else {
@@ -1616,7 +1641,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 else if (kind == FK_RHOB) fill(integral_constant<int, FK_RHOB>(), false_type());
                 else fill(integral_constant<int, FK_RAW>(), false_type());
             }
-            __syncthreads();
+            lds_sync();
             lds_fft<T, M, false, N1, NTP, A, 1>(buf, twM, t);
         }
         (void)knots;
@@ -1626,6 +1651,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
         // it straight to out[i1 * (M + 1) + k]
         cpx<T> *out = (cpx<T> *)a.out + f * a.out_fstride + (long long)b * g.Nh +
                       (long long)i0 * N1 * (M + 1);
+        const BufRes ro = buf_res(out, (unsigned)(N1 * (M + 1)) * S);
         lds_fft_io<T, N1, false, M + 1, NTP, 1, A>(
             buf, tw1, t,
             [&](unsigned n, unsigned p) {
@@ -1635,7 +1661,9 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 if (k == 0) x.y = T(0);
                 return x;
             },
-            [&](unsigned n, unsigned p, cpx<T> v) { st32(out, n * (M + 1) + p, v); });
+            [&](unsigned nb, unsigned dn, unsigned p, cpx<T> v) {
+                bst(ro, (nb * (M + 1) + p) * S, dn * (unsigned)(M + 1) * S, v);
+            });
     }
 }
 
@@ -1649,18 +1677,64 @@ __device__ __forceinline__ void plane_inverse(cpx<T> *buf, const cpx<T> *spec,
                                               const cpx<T> *twN, int tid)
 {
     constexpr int A = plane_A<N1>();
+    constexpr unsigned S = sizeof(cpx<T>);
     tid = opaque(tid);
     // axis 1: the first stage reads column k (element i1) straight from the
     // spectrum, spec[i1 * (M + 1) + k]
+    const BufRes rs = buf_res(spec, (unsigned)(N1 * (M + 1)) * S);
     lds_fft_src<T, N1, true, M + 1, NTP, 1, A>(
-        buf, tw1, tid, [&](unsigned n, unsigned p) { return ld32(spec, n * (M + 1) + p); });
+        buf, tw1, tid, [&](unsigned nb, unsigned dn, unsigned p) {
+            return bld<cpx<T>>(rs, (nb * (M + 1) + p) * S, dn * (unsigned)(M + 1) * S);
+        });
     // axis 2: the first stage forms element n of row i1 of the half-length
     // input by the c2r pack Z[n] = (X[n] + conj X[M-n]) + i (X[n] - conj
-    // X[M-n]) conj(W^n) (imaginary parts of X[0] and X[M] dropped)
-    lds_fft_src<T, M, true, N1, NTP, A, 1>(buf, twM, tid, [&](unsigned n, unsigned p) {
+    // X[M-n]) conj(W^n) (imaginary parts of X[0] and X[M] dropped).  A lane
+    // holds n = nb + dn for dn = 0, NB, .., DNMAX (NB = M / R, R the first
+    // radix): X[M - n] is addressed from the lane's lowest row, M - nb - DNMAX
+    // (>= 1), so that every offset is a positive constant.
+    constexpr Plan pm = make_plan(M, sizeof(T) == 4);
+    constexpr unsigned DNMAX = (unsigned)((pm.r[0] - 1) * (M / pm.r[0]));
+    lds_fft_src<T, M, true, N1, NTP, A, 1>(buf, twM, tid, [&](unsigned nb, unsigned dn, unsigned p) {
+        const unsigned n = nb + dn;
         cpx<T> xk = buf[n * A + p];
-        cpx<T> xm = buf[(M - n) * A + p];
-        if (n == 0) {
+        // the base is kept opaque (folded back into M - n, every element
+        // would cost a subtraction and a multiply-add); the same asm on the
+        // same operands is formed once for all dn
+        unsigned lo = ((unsigned)M - nb - DNMAX) * A + p;
+        asm("" : "+v"(lo));
+        cpx<T> xm = buf[lo + (DNMAX - dn) * A];
+        if (dn == 0 && nb == 0) {
+            xk.y = T(0);
+            xm.y = T(0);
+        }
+        return c2r_pack(xk, xm, twN[n]);
+    });
+}
+
+// As plane_inverse with the field's spectrum plane already in LDS (pre,
+// element (i1, k) at pre[i1 * (M + 1) + k]); next() is called once the
+// axis-1 transform has read pre (after a barrier), so that it can start the
+// copy of the next plane into it.
+template <typename T, int N1, int M, int NTP, class NEXT>
+__device__ __forceinline__ void plane_inverse_pre(cpx<T> *buf, const cpx<T> *pre,
+                                                  const cpx<T> *tw1, const cpx<T> *twM,
+                                                  const cpx<T> *twN, int tid, const NEXT &next)
+{
+    constexpr int A = plane_A<N1>();
+    tid = opaque(tid);
+    lds_copy_wait();   // this wave's part of pre; lds_fft_src starts with a barrier
+    lds_fft_src<T, N1, true, M + 1, NTP, 1, A>(
+        buf, tw1, tid, [&](unsigned n, unsigned p) { return pre[n * (M + 1) + p]; });
+    next();
+    constexpr Plan pm = make_plan(M, sizeof(T) == 4);
+    constexpr unsigned DNMAX = (unsigned)((pm.r[0] - 1) * (M / pm.r[0]));
+    lds_fft_src<T, M, true, N1, NTP, A, 1>(buf, twM, tid, [&](unsigned nb, unsigned dn, unsigned p) {
+        const unsigned n = nb + dn;
+        cpx<T> xk = buf[n * A + p];
+        unsigned lo = ((unsigned)M - nb - DNMAX) * A + p;
+        asm("" : "+v"(lo));
+        cpx<T> xm = buf[lo + (DNMAX - dn) * A];
+        if (dn == 0 && nb == 0) {
             xk.y = T(0);
             xm.y = T(0);
         }
@@ -1677,13 +1751,17 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     constexpr int PER = (PAIRS + NTP - 1) / NTP;
     __shared__ cpx<T> buf[(M + 1) * A];
     constexpr bool STX = plane_stage_x<T>();
-    __shared__ cpx<T> xsbuf[STX ? N1 * M : 1];
+    // the staged input plane; with a fixed term set (PRE) the same array
+    // first takes each field's spectrum plane, copied in while the previous
+    // field is transformed, and then the input plane
+    constexpr bool PRE = STX && CF != 0 && MODE == EP_COMBINE;
+    __shared__ cpx<T> xsbuf[STX ? N1 * (M + 1) : 1];
     __shared__ cpx<T> tws[N1 + 2 * M + 1];
     __shared__ double red[5 * NTP / 64];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.x, b = blockIdx.y;
     stage_plane_twiddles<T, N1, M, NTP>(tws, a.tw1, a.twM, a.twN, tid);
-    __syncthreads();
+    lds_sync();
     const cpx<T> *tw1 = tws;
     const cpx<T> *twM = tws + N1;
     const cpx<T> *twN = tws + N1 + M;
@@ -1706,17 +1784,22 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
 #pragma unroll
             for (int q = 0; q < PER; ++q)
                 if (t + q * NTP < PAIRS) out[t + q * NTP] = buf[at(t, q)];
-            __syncthreads();
+            lds_sync();
         }
         return;
     }
     else {
 
     const cpx<T> *in = (const cpx<T> *)((const T *)a.in + real_off);
+    constexpr unsigned S = sizeof(cpx<T>);
+    // pair q of thread t is element t + q NTP of the plane: byte offset t S
+    // per lane plus the constant q NTP S
+    const BufRes rin = buf_res(in, PAIRS * S);
     cpx<T> xin[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q)
-        xin[q] = tid + q * NTP < PAIRS ? ld32(in, (unsigned)(tid + q * NTP)) : cpx<T>{T(0), T(0)};
+        xin[q] = tid + q * NTP < PAIRS ? bld<cpx<T>>(rin, (unsigned)tid * S, (unsigned)(q * NTP) * S)
+                                       : cpx<T>{T(0), T(0)};
 
     if constexpr (MODE == EP_KNOTS) {
         bool acc_init = a.acc_init != 0;
@@ -1760,7 +1843,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 const cpx<T> z = buf[at(t, q)];
                 knot_interp(jj[q], tt[q], i, nk, a.exact, z, v1[q], v2[q]);
             }
-            __syncthreads();
+            lds_sync();
         }
         if (a.exact) {
 #pragma unroll
@@ -1785,12 +1868,17 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
     // forms v and g once, after the last inverse, so that the per-point
     // powers of rho are evaluated once.  The input plane is kept in LDS (xs).
     cpx<T> *xs = (cpx<T> *)xsbuf;
-    if constexpr (STX) {
+    constexpr unsigned PLANE_BYTES = (unsigned)(N1 * (M + 1)) * S;
+    // the input plane is copied into LDS asynchronously when 16-byte aligned
+    const bool xasync = PRE && (((size_t)in) & 15) == 0;
+    if constexpr (STX && !PRE) {
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             if (tid + q * NTP < PAIRS) xs[tid + q * NTP] = xin[q];
     }
-    __syncthreads();
+    if constexpr (PRE)
+        lds_copy_async<NTP>(xs, spec_of(a.fld_hext), PLANE_BYTES, tid);
+    lds_sync();
     const cpx<T> *acc1 = a.spline ? (const cpx<T> *)((const T *)a.acc1 + real_off) : nullptr;
     const cpx<T> *acc2 = (a.spline && a.exact) ? (const cpx<T> *)((const T *)a.acc2 + real_off)
                                                 : nullptr;
@@ -1818,50 +1906,76 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             for (int q = 0; q < PER; ++q)
                 if (t + q * NTP < PAIRS) f[q] = buf[uat(t, q)];
         };
+        const int fld_nl = (CF & CB_WT) ? a.fld_wt : a.fld_a;
+        // PRE: the next plane (a spectrum, or the input plane after the
+        // last) streams into xs while this field's axis-2 transforms run
+        auto copy_x = [&]() {
+            if (xasync) lds_copy_async<NTP>(xs, in, (unsigned)PAIRS * S, opaque(tid));
+        };
+        auto inverse = [&](int fld, int t, auto next) {
+            if constexpr (PRE) plane_inverse_pre<T, N1, M, NTP>(buf, xs, tw1, twM, twN, t, next);
+            else plane_inverse<T, N1, M, NTP>(buf, spec_of(fld), tw1, twM, twN, t);
+        };
         {
             const int t = opaque(tid);
-            plane_inverse<T, N1, M, NTP>(buf, spec_of(a.fld_hext), tw1, twM, twN, t);
+            inverse(a.fld_hext, t, [&]() {
+                lds_copy_async<NTP>(xs, spec_of(a.fld_vw), PLANE_BYTES, opaque(tid));
+            });
             hold(fh, t);
-            __syncthreads();
+            lds_sync();
         }
         {
             const int t = opaque(tid);
-            plane_inverse<T, N1, M, NTP>(buf, spec_of(a.fld_vw), tw1, twM, twN, t);
+            inverse(a.fld_vw, t, [&]() {
+                if constexpr (NLF) lds_copy_async<NTP>(xs, spec_of(fld_nl), PLANE_BYTES, opaque(tid));
+                else copy_x();
+            });
             if constexpr (NLF) {
                 hold(fv, t);
-                __syncthreads();
+                lds_sync();
             }
         }
         if constexpr (NLF) {
             const int t = opaque(tid);
-            plane_inverse<T, N1, M, NTP>(buf, spec_of((CF & CB_WT) ? a.fld_wt : a.fld_a), tw1,
-                                         twM, twN, t);
+            inverse(fld_nl, t, copy_x);
         }
+        if constexpr (PRE) {
+            lds_copy_wait();
+            lds_sync();
+        }
+        const BufRes ra1 = buf_res(acc1, PAIRS * S), ra2 = buf_res(acc2, PAIRS * S);
+        const BufRes rvo = buf_res(vout, PAIRS * S), rgo = buf_res(gout, PAIRS * S);
         auto points = [&](auto ph) {
             constexpr int PH = decltype(ph)::value;
             const int t = opaque(tid);
+            const unsigned vo_ = (unsigned)t * S;
+            T ts[combine_nsum<CF>()] = {};   // a thread's few points, summed in T
 #pragma unroll
             for (int q = 0; q < PER; ++q) {
                 const unsigned idx = (unsigned)(t + q * NTP);
                 if (idx >= (unsigned)PAIRS) continue;
+                const unsigned so = (unsigned)(q * NTP) * S;
                 cpx<T> s1 = {T(0), T(0)}, s2 = {T(0), T(0)};
-                if (acc1) s1 = ld32(acc1, idx);
-                if (acc2) s2 = ld32(acc2, idx);
+                if (acc1) s1 = bld<cpx<T>>(ra1, vo_, so);
+                if (acc2) s2 = bld<cpx<T>>(ra2, vo_, so);
                 cpx<T> xq;
-                if constexpr (STX) xq = xs[idx];
-                else xq = ld32(in, idx);
+                if constexpr (PRE) xq = xasync ? xs[idx] : bld<cpx<T>>(rin, vo_, so);
+                else if constexpr (STX) xq = xs[idx];
+                else xq = bld<cpx<T>>(rin, vo_, so);
                 const cpx<T> zb = buf[uat(t, q)];
                 const cpx<T> zh = fh[q];
                 const cpx<T> zv = NLF ? fv[q] : zb;
                 const cpx<T> zl = NLF ? zb : cpx<T>{T(0), T(0)};
                 cpx<T> vo, go;
-                combine_point<T, CF, PH>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x,
-                                         sums);
-                combine_point<T, CF, PH>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y,
-                                         sums);
-                if (vout) st32(vout, idx, vo);
-                if (gout) st32(gout, idx, go);
+                combine_point<T, CF, PH, T>(a, cc, xq.x, zh.x, zv.x, zl.x, s1.x, s2.x, vo.x, go.x,
+                                            ts);
+                combine_point<T, CF, PH, T>(a, cc, xq.y, zh.y, zv.y, zl.y, s1.y, s2.y, vo.y, go.y,
+                                            ts);
+                if (vout) bst(rvo, vo_, so, vo);
+                if (gout) bst(rgo, vo_, so, go);
             }
+#pragma unroll
+            for (int k = 0; k < combine_nsum<CF>(); ++k) sums[k] = (double)ts[k];
         };
         if (a.in_is_phi) points(std::integral_constant<int, 1>());
         else points(std::integral_constant<int, 0>());
@@ -1889,7 +2003,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                 if (k == 0) fh[q] = z;
                 else fv[q] = z;
             }
-            __syncthreads();
+            lds_sync();
         }
         const int t = opaque(tid);
 #pragma unroll
