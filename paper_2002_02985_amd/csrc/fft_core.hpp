@@ -630,14 +630,25 @@ __device__ __forceinline__ V bld(const BufRes &b, unsigned voff, unsigned soff)
     else
         return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(b.r, voff, soff, 0));
 }
+// Stores of more than 8 bytes need a wait state before a vector instruction
+// overwrites their data registers; for buffer stores the compiler does not
+// always leave one (16-byte stores followed at once by a write of their
+// first data registers were found in the FP64 kernels, and stored wrong low
+// halves now and then), so a 16-byte element is stored as two 8-byte halves.
 template <typename V>
 __device__ __forceinline__ void bst(const BufRes &b, unsigned voff, unsigned soff, V v)
 {
     static_assert(sizeof(V) == 8 || sizeof(V) == 16, "8- or 16-byte elements");
-    if constexpr (sizeof(V) == 8)
+    if constexpr (sizeof(V) == 8) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(buf_u32x2, v), b.r, voff, soff, 0);
-    else
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(buf_u32x4, v), b.r, voff, soff, 0);
+    } else {
+        const buf_u32x4 w = __builtin_bit_cast(buf_u32x4, v);
+        const buf_u32x2 lo = {w[0], w[1]}, hi = {w[2], w[3]};
+        __builtin_amdgcn_raw_buffer_store_b64(lo, b.r, voff, soff, 0);
+        // (keeps the two halves from being merged back into one store)
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_raw_buffer_store_b64(hi, b.r, voff + 8u, soff, 0);
+    }
 }
 
 // Copy `bytes` (a multiple of 16; both addresses 16-byte aligned) from

@@ -148,6 +148,7 @@ __device__ __forceinline__ double d_fmax(double x, double y) { return __builtin_
 template <typename T> __device__ __forceinline__ T neg_inf() { return -__builtin_huge_valf(); }
 template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_huge_val(); }
 constexpr double LOG2_3PI2 = 4.8879547596657937775;   // log2(3 pi^2)
+constexpr double KF_C = 3.0936677262801355;   // (3 pi^2)^(1/3)
 
 // Lindhard kernel shape G_NL(eta) = 1/F - 3 eta^2 - 1 with
 // F = 1/2 + (1 - eta^2)/(4 eta) ln|(1 + eta)/(1 - eta)| (the G_NL formula of
@@ -235,6 +236,31 @@ __device__ __forceinline__ void knot_bracket_kf(T kf, const Knots &kn, int &j, T
     j = jj;
     const T kj = T(kn.k[jj]), kj1 = T(kn.k[jj + 1]);
     t = (kt - kj) / (kj1 - kj);
+}
+
+// rho^(-1/6) in FP64 without the FP64 logarithm and exponential (dozens of
+// instructions each), in integer and FP64 multiply-add instructions only.
+// The estimate takes log2 rho as linear in the high word of its bits
+// (exponent and top 20 mantissa bits; off by at most 0.086) and forms the
+// high word of y from -log2(rho)/6, shifted by 0.05 so that the estimate is
+// within 3.5% of rho^(-1/6); five Newton steps on f(y) = y^-6 - rho,
+// y <- y (7 - rho y^6) / 6, each taking a relative error e to about
+// -3.5 e^2, leave the FP64 rounding (3.5e-2 -> 4.3e-3 -> 6.5e-5 -> 1.5e-8 ->
+// 7.6e-16).  rho must be >= 0; below the smallest normal double the result
+// is 0 (every power of rho the terms use is then below 1e-51).
+__device__ __forceinline__ double rsixth(double rho)
+{
+    constexpr int B = 1023 << 20;                 // high word of 1.0
+    constexpr int SHIFT = 52429;                  // 0.05 * 2^20
+    const int hi = (int)(__double_as_longlong(rho) >> 32);
+    const int yh = B - (hi - B) / 6 - SHIFT;
+    double y = __longlong_as_double((long long)yh << 32);
+#pragma unroll
+    for (int it = 0; it < 5; ++it) {
+        const double y2 = y * y;
+        y = y * (7.0 - rho * (y2 * y2 * y2)) * (1.0 / 6.0);
+    }
+    return rho >= 0x1p-1022 ? y : 0.0;
 }
 
 // k_F = (3 pi^2 rho)^(1/3) from log2(rho)
@@ -363,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
     // and exponential; FP32 passes always evaluate them
     bool need_lu = sizeof(T) == 4 || a.partials || knots;
     for (int f = 0; f < a.nfields; ++f) need_lu |= a.kind[f] == FK_RHOB;
+    const bool sixth = sizeof(T) == 8 && a.alpha == 5.0 / 6.0 && a.beta == 5.0 / 6.0;
     cpx<T> u[PER], w[PER], z[PER];
     int jj[PER][2];
     double sums[3] = {0.0, 0.0, 0.0};   // sum rho, sum rho^(5/3), bad count
@@ -377,6 +404,33 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             const T v = xv[c];
             const bool ok = d_finite(v) && (a.in_is_phi || v >= T(0));
             const T rho = a.in_is_phi ? v * v : (v > T(0) ? v : T(0));
+            if (sixth) {
+                // FP64, alpha = beta = 5/6: every power from y = rho^(-1/6)
+                // (rho^(2/3) = rho y^2, k_F = KF_C rho y^4, rho^(5/6) = rho y)
+                const T y = need_lu ? T(rsixth((double)rho)) : T(0);
+                if (live && a.partials) {
+                    if (!ok) {
+                        sums[2] += 1.0;
+                    } else {
+                        sums[0] += (double)rho;
+                        sums[1] += (double)(rho * (rho * (y * y)));
+                    }
+                }
+                if (knots) {
+                    T t;
+                    bool inside;
+                    const T y2 = y * y;
+                    knot_bracket_kf(T(KF_C) * rho * (y2 * y2), a.knots, jj[q][c], t, inside);
+                    uu[c] = rho * y;
+                    ww[c] = t;
+                    zz[c] = T(0);
+                } else {
+                    uu[c] = a.in_is_phi ? v * v : v;
+                    ww[c] = a.in_is_phi ? v : d_sqrt(rho);
+                    zz[c] = rho * y;
+                }
+                continue;
+            }
             const T lu = (need_lu && rho > T(0)) ? d_log2(rho) : neg_inf<T>();
             if (live && a.partials) {
                 if (!ok) {
@@ -596,9 +650,9 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
                 else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tl, ld, st);
                 continue;
             } else {
-                __syncthreads();
+                lds_sync();
                 for (int n = tl / P; n < L; n += RSTEP) buf[n * P + pl] = ld(n, pl);
-                __syncthreads();
+                lds_sync();
                 if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tl);
                 else lds_fft<T, L, false, P, NT, P>(buf, tw, tl);
             }
@@ -658,14 +712,14 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
                     }
                 }
             }
-            __syncthreads();
+            lds_sync();
             if (op != GO_SCALE) {
                 lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tl, st);   // ends with a barrier
                 continue;
             }
         }
         for (int n = tl / P; n < L; n += RSTEP) st(n, pl, buf[n * P + pl]);
-        __syncthreads();
+        lds_sync();
     }
 }
 
@@ -918,11 +972,11 @@ __device__ __forceinline__ void lda_xc_point(T rho, T r3, T &eps, T &v)
 //                               rho^(5/6) = p^5, k_F = (3 pi^2)^(1/3) p^2
 //   q = max(rho, floor)^(-1/6): rho_s^(-1/6) = q, rho_s^(-1/2) = q^3,
 //                               rho_s^(-1) = q^6
-constexpr double KF_C = 3.0936677262801355;   // (3 pi^2)^(1/3)
 
 template <typename T>
 struct CombineConst {
     T alpha, floor_rho, lfloor, k_lo, k_hi;
+    T yfloor;   // floor^(-1/6) (FP64 fixed term sets)
 };
 
 template <typename T>
@@ -932,6 +986,7 @@ __device__ __forceinline__ CombineConst<T> combine_const(const RowInvArgs &a)
     c.alpha = T(a.alpha);
     c.floor_rho = T(a.floor);
     c.lfloor = d_log2(c.floor_rho);
+    c.yfloor = c.floor_rho > T(0) ? d_exp2(c.lfloor * T(-1.0 / 6.0)) : __builtin_huge_val();
     c.k_lo = a.spline ? T(a.knots.k[0]) : T(0);
     c.k_hi = a.spline ? T(a.knots.k[a.knots.nk - 1]) : T(0);
     return c;
@@ -963,8 +1018,12 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
         rho = PH == 0 ? x : (x > T(0) ? x : T(0));
         phi = T(0);
     }
-    T lu, lr;
-    if constexpr (PH >= 0) {
+    // FP64 fixed term sets take p and q from rho^(-1/6) (rsixth) instead
+    // of the FP64 logarithm and exponentials
+    constexpr bool NEWTON = CF != 0 && sizeof(T) == 8;
+    T lu = T(0), lr = T(0);
+    if constexpr (NEWTON) {
+    } else if constexpr (PH >= 0) {
         // rho >= 0 here and log2(0) = -inf: no branch for empty points;
         // rho_s = max(rho, floor) in the log domain
         lu = d_log2(rho);
@@ -976,8 +1035,17 @@ __device__ __forceinline__ void combine_point(const RowInvArgs &a, const Combine
     T vv = T(0), gg = T(0);
     if constexpr (CF != 0) {
         constexpr T AL = T(5.0 / 6.0);
-        const T p = d_exp2(lu * T(1.0 / 6.0));
-        const T q = d_exp2(lr * T(-1.0 / 6.0));
+        T p, q;
+        if constexpr (NEWTON) {
+            // p = rho^(1/6) = rho y^5, q = max(rho, floor)^(-1/6)
+            const double y = rsixth((double)rho);
+            const double y2 = y * y;
+            p = T(rho * (y2 * y2 * y));
+            q = T(rho >= cc.floor_rho && y > 0.0 ? y : cc.yfloor);
+        } else {
+            p = d_exp2(lu * T(1.0 / 6.0));
+            q = d_exp2(lr * T(-1.0 / 6.0));
+        }
         const T p2 = p * p;
         if (!in_phi) phi = p2 * p;
         // phi = rho^(1/2) >= 0 when the input is rho
@@ -1544,7 +1612,12 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                     }
                     const T rho = P ? v * v : v;   // >= 0; log2(0) = -inf
                     ts[0] += rho;
-                    ts[1] += rho * d_exp2(d_log2(rho) * T(2.0 / 3.0));
+                    if constexpr (sizeof(T) == 8) {
+                        const double y = rsixth(rho);   // rho^(2/3) = rho y^2
+                        ts[1] += rho * (rho * (y * y));
+                    } else {
+                        ts[1] += rho * d_exp2(d_log2(rho) * T(2.0 / 3.0));
+                    }
                 }
             }
             sums[0] = (double)ts[0];
@@ -1605,6 +1678,7 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
             // measured slower), then the axis-2 half-length transforms
             // (the field kind and the input kind are uniform: each pair is
             // compiled separately so that a point computes only its own field)
+            const bool b56 = a.beta == 5.0 / 6.0;
             auto fill = [&](auto kd, auto ph) {
                 constexpr int K = decltype(kd)::value;
                 constexpr bool P = decltype(ph)::value;
@@ -1614,7 +1688,11 @@ __global__ __launch_bounds__((plane_NT<N1, M>()), (plane_minw<T>())) void k_plan
                     // (a negative density is counted by the prologue and
                     // fails the evaluation: no clamp here)
                     else if constexpr (K == FK_PHI) return P ? v : d_sqrt_fast(v);
-                    else return d_exp2(T(a.beta) * d_log2(P ? v * v : v));   // FK_RHOB; log2(0) = -inf
+                    else if constexpr (sizeof(T) == 8) {
+                        // FK_RHOB; FP64 with beta = 5/6: rho^(5/6) = rho rho^(-1/6)
+                        const T r = P ? v * v : v;
+                        return b56 ? r * rsixth(r) : d_exp2(T(a.beta) * d_log2(r));
+                    } else return d_exp2(T(a.beta) * d_log2(P ? v * v : v));   // FK_RHOB; log2(0) = -inf
                 };
 #pragma unroll
                 for (int q = 0; q < PER; ++q) {
