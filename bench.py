@@ -1086,13 +1086,16 @@ def main():
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     plane = mixed["tuning"] is None or mixed["tuning"]["plane"]
     # kernel names as rocprofv3 prints them: the combine is the fixed term set
-    # TF + vW + Hartree/ion + WT (15), epilogue mode 1
+    # TF + vW + Hartree/ion + WT (15), epilogue mode 1; the column pass runs
+    # 16-column tiles, grouped (8 densities per block) unless the schedule
+    # serves one density per block
+    grouped = mixed["tuning"] is None or mixed["tuning"].get("col_group", 8) > 1
+    kcol = "k_col<float, 96, 16, false, %s>" % ("true" if grouped else "false")
     kname = ({"row_fwd": "k_plane_fwd<float, 96, 48>",
               "row_inv": "k_plane_inv<float, 96, 48, 1, 15>",
-              "col0_g": "k_col<float, 96>"} if plane else
+              "col0_g": kcol} if plane else
              {"row_fwd": "k_row_fwd<float, 48>", "row_inv": "k_row_inv<float, 48, 15, 1>",
-              "col0_g": "k_col<float, 96>", "col1_fwd": "k_col<float, 96>",
-              "col1_inv": "k_col<float, 96>"}).get(name)
+              "col0_g": kcol, "col1_fwd": kcol, "col1_inv": kcol}).get(name)
     traffic = measured_traffic(kname) if kname else None
     roof = {"bound": "hbm", "kernel": kname or name, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -66,3 +66,20 @@ def test_col_group_setter_checks_its_range():
                 ofdft.ofdft_grid_set_col_group(g.handle, bad)
             assert ei.value.status == ofdft.EINVAL
         ofdft.ofdft_grid_set_col_group(g.handle, 4)
+
+
+@pytest.mark.parametrize("prec", [ofdft.FP64, ofdft.MIXED])
+def test_repeated_batches_are_bit_identical(prec):
+    """The same batch evaluated three times gives the same bits (the 96^3
+    plane path, with the Wang-Teter combine that ends in 16-byte stores in
+    FP64: stores whose data registers were overwritten too soon once left
+    wrong low halves in a few thousand points per batch)."""
+    nb = 32 if prec == ofdft.FP64 else 64
+    cell, dens = W.config_c2((96, 96, 96), nb)
+    print("case repeat", prec, nb, flush=True)
+    with ofdft.Grid(cell, LOCAL | ofdft.TERM_WT, precision=prec) as g:
+        x = dev_tensor(np.stack(dens), torch_dtype(g))
+        runs = [run(g, x, 8) for _ in range(3)]
+    for e, v in runs[1:]:
+        assert np.array_equal(v, runs[0][1]), prec
+        assert [d["e_total"] for d in e] == [d["e_total"] for d in runs[0][0]]
