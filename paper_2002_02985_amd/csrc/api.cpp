@@ -583,7 +583,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
     }
     if (m.stage) b += 2 * N * fsz;
     if (m.opt) b += (uint64_t)NVEC_OPT * N * fsz;
-    if (m.forces) b += (uint64_t)natoms * 3 * 8;
+    if (m.forces) b += ((uint64_t)natoms * 3 + (uint64_t)forces_part_doubles(G, natoms)) * 8;
     b += m.extra;
     return b;
 }
@@ -3303,12 +3303,15 @@ ofdft_status ofdft_forces(ofdft_grid *grid, double *f_out_host)
     ofdft_status st = g->fp64 ? fft_impl<double>(g, 1, g->rho, g->spec, true, s)
                               : fft_impl<float>(g, 1, g->rho, g->spec, true, s);
     ST_TRY(st);
-    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_forces), 3 * (size_t)na * sizeof(double)));
-    double *d_f = g->d_forces;
-    hipError_t e = g->fp64 ? launch_forces<double>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
-                                                   g->ph2, g->d_Z, g->d_rc, g->spec, d_f, s)
-                           : launch_forces<float>(g->geom, na, g->d_atom_species, g->ph0, g->ph1,
-                                                  g->ph2, g->d_Z, g->d_rc, g->spec, d_f, s);
+    // the forces and the partial-force table of the tiled kernel
+    const size_t nfd = 3 * (size_t)na + (size_t)forces_part_doubles(g->geom, na);
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_forces), nfd * sizeof(double)));
+    double *d_f = g->d_forces, *d_part = g->d_forces + 3 * (size_t)na;
+    const int ns = (int)g->Z.size();
+    hipError_t e = g->fp64 ? launch_forces<double>(g->geom, na, g->d_spec_off, ns, g->ph0, g->ph1,
+                                                   g->ph2, g->d_Z, g->d_rc, g->spec, d_part, d_f, s)
+                           : launch_forces<float>(g->geom, na, g->d_spec_off, ns, g->ph0, g->ph1,
+                                                  g->ph2, g->d_Z, g->d_rc, g->spec, d_part, d_f, s);
     std::vector<double> fs(3 * (size_t)na);
     if (e == hipSuccess) e = hipMemcpyAsync(fs.data(), d_f, fs.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

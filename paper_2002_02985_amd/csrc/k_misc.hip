@@ -158,41 +158,76 @@ template hipError_t launch_gtab<double>(const Geom &, double, const NlKern &, vo
 
 // ---------------------------------------------------------------- v_ext(G)
 // v_ext(G) = (1/V) sum_s v_s(|G|) sum_{a in s} e^{-i G.R_a}; the phase is the
-// product of per-axis tables ph_d[a][i] = exp(-2 pi i m_d(i) s_{a,d}) (s the
+// product of per-axis tables ph_d[a][i] = exp(-2 pi i m_d(i) s_d) (s the
 // fractional coordinates), built in FP64 with exact argument reduction.
-// One block per (i0, i1) row of the half spectrum; atoms are grouped by species.
+// A lane takes VS consecutive k2 of one (i0, i1) row (a segment) and sums
+// each species' structure factor at its points, the phase of an atom
+// advanced along k2 by one complex multiplication per point (times
+// ph2[a][1]); the negative Nyquist point, which breaks the progression, takes
+// its table entry.  Atoms are grouped by species.
+constexpr int VS = 8;
 template <typename T>
 __global__ __launch_bounds__(NT) void k_vext(Geom g, int natoms, const int *spec_off,
                                              int nspecies, const double *ph0, const double *ph1,
                                              const double *ph2, const double *Z,
-                                             const double *rc, double inv_vol, cpx<T> *vext)
+                                             const double *rc, double inv_vol, long long nseg,
+                                             int segs_row, cpx<T> *vext)
 {
-    const int row = blockIdx.x;
-    const int i0 = row / g.n1, i1 = row % g.n1;
+    (void)natoms;
+    const long long sg = (long long)blockIdx.x * NT + threadIdx.x;
+    if (sg >= nseg) return;
+    const long long row = sg / segs_row;
+    const int k0 = (int)(sg % segs_row) * VS;
+    const int cnt = min(VS, g.n2h - k0);
+    const int i1 = (int)(row % g.n1), i0 = (int)(row / g.n1);
     const int m0 = freq(i0, g.n0), m1 = freq(i1, g.n1);
-    for (int k2 = threadIdx.x; k2 < g.n2h; k2 += NT) {
-        const int m2 = (k2 == g.m) ? -g.m : k2;
-        const double G2 = gvec2<double>(g, m0, m1, m2);
-        double vr = 0.0, vi = 0.0;
-        for (int s = 0; s < nspecies; ++s) {
-            double sr = 0.0, si = 0.0;
-            for (int a = spec_off[s]; a < spec_off[s + 1]; ++a) {
-                const double *p0 = ph0 + 2 * ((long long)a * g.n0 + i0);
-                const double *p1 = ph1 + 2 * ((long long)a * g.n1 + i1);
-                const double *p2 = ph2 + 2 * ((long long)a * g.n2h + k2);
-                const double ar = p0[0] * p1[0] - p0[1] * p1[1];
-                const double ai = p0[0] * p1[1] + p0[1] * p1[0];
-                sr += ar * p2[0] - ai * p2[1];
-                si += ar * p2[1] + ai * p2[0];
+    const bool nyq_even = g.m > 0 && 2 * g.m == g.n2;
+    const int kn = (nyq_even && k0 + cnt - 1 == g.m) ? cnt - 1 : -1;
+    double vr[VS], vi[VS];
+#pragma unroll
+    for (int j = 0; j < VS; ++j) vr[j] = vi[j] = 0.0;
+    for (int s = 0; s < nspecies; ++s) {
+        double sr[VS], si[VS];
+#pragma unroll
+        for (int j = 0; j < VS; ++j) sr[j] = si[j] = 0.0;
+        double snr = 0.0, sni = 0.0;   // the Nyquist point
+        for (int a = spec_off[s]; a < spec_off[s + 1]; ++a) {
+            const double *p0 = ph0 + 2 * ((long long)a * g.n0 + i0);
+            const double *p1 = ph1 + 2 * ((long long)a * g.n1 + i1);
+            const double *p2 = ph2 + 2 * ((long long)a * g.n2h);   // uniform
+            const double qr = p0[0] * p1[0] - p0[1] * p1[1];
+            const double qi = p0[0] * p1[1] + p0[1] * p1[0];
+            const double dr = p2[2], di = p2[3];
+            double tr = qr * p2[2 * k0] - qi * p2[2 * k0 + 1];
+            double ti = qr * p2[2 * k0 + 1] + qi * p2[2 * k0];
+#pragma unroll
+            for (int j = 0; j < VS; ++j) {
+                sr[j] += tr;
+                si[j] += ti;
+                const double t2 = tr * dr - ti * di;
+                ti = tr * di + ti * dr;
+                tr = t2;
             }
-            const double z = Z[s], r = rc[s];
+            const int mq = g.m > 0 ? g.m : 0;
+            snr += qr * p2[2 * mq] - qi * p2[2 * mq + 1];
+            sni += qr * p2[2 * mq + 1] + qi * p2[2 * mq];
+        }
+        const double z = Z[s], r = rc[s];
+#pragma unroll
+        for (int j = 0; j < VS; ++j) {
+            const bool nq = j == kn;
+            const int m2 = nq ? -g.m : k0 + j;
+            const double G2 = gvec2<double>(g, m0, m1, m2);
             const double vs = G2 > 0.0 ? -4.0 * PI_D * z * exp(-G2 * r * r * 0.25) / G2
                                        : PI_D * z * r * r;
-            vr += vs * sr;
-            vi += vs * si;
+            vr[j] += vs * (nq ? snr : sr[j]);
+            vi[j] += vs * (nq ? sni : si[j]);
         }
-        vext[(long long)row * g.n2h + k2] = {T(vr * inv_vol), T(vi * inv_vol)};
     }
+    cpx<T> *out = vext + row * g.n2h + k0;
+#pragma unroll
+    for (int j = 0; j < VS; ++j)
+        if (j < cnt) out[j] = {T(vr[j] * inv_vol), T(vi[j] * inv_vol)};
 }
 
 template <typename T>
@@ -200,9 +235,11 @@ hipError_t launch_vext(const Geom &g, int natoms, const int *spec_off, int nspec
                        const double *ph0, const double *ph1, const double *ph2, const double *Z,
                        const double *rc, double volume, void *vext, hipStream_t s)
 {
-    (void)natoms;
-    hipLaunchKernelGGL((k_vext<T>), dim3(g.n0 * g.n1), dim3(NT), 0, s, g, natoms, spec_off,
-                       nspecies, ph0, ph1, ph2, Z, rc, 1.0 / volume, (cpx<T> *)vext);
+    const int segs_row = (g.n2h + VS - 1) / VS;
+    const long long nseg = (long long)g.n0 * g.n1 * segs_row;
+    hipLaunchKernelGGL((k_vext<T>), dim3((unsigned)((nseg + NT - 1) / NT)), dim3(NT), 0, s, g,
+                       natoms, spec_off, nspecies, ph0, ph1, ph2, Z, rc, 1.0 / volume, nseg,
+                       segs_row, (cpx<T> *)vext);
     return hipGetLastError();
 }
 template hipError_t launch_vext<float>(const Geom &, int, const int *, int, const double *,
@@ -215,99 +252,222 @@ template hipError_t launch_vext<double>(const Geom &, int, const int *, int, con
 // ---------------------------------------------------------------- forces
 // F_a = sum_half c(m2) G v_{s(a)}(|G|) Im[e^{i G.R_a} rho(G)], the exact
 // derivative -d/dR_a of int v_ext rho = V sum_half c Re[conj(v_ext(G)) rho(G)].
-// One block per atom; its phase tables are staged in LDS.
-constexpr int FORCE_MAXTAB = 2 * 1024 + 513;
+//
+// A lane takes FS consecutive k2 of one (i0, i1) row of the half spectrum
+// (a segment).  For each species it forms w(G) = c(m2) v_s(|G|) rho(G) of its
+// points once; for each atom of a chunk of at most FATOMS it sums
+// im = Im[e^{i G.R_a} w(G)] over the segment, the phase advanced along k2 by
+// one complex multiplication per point (e^{-i G.R} = ph0 ph1 ph2, times
+// ph2[a][1] per step; the negative Nyquist point, which breaks the
+// progression, from its table entry).  G is linear along the segment,
+// G = G_0 + j b_2, so the lane keeps S0 = sum im_j and S1 = sum j im_j and
+// its force is G_0 S0 + b_2 S1.  Wave sums of each atom's force go to LDS;
+// a block's partial forces go to part[block][atom][3], and k_forces_sum adds
+// them in block order (deterministic).
+constexpr int FS = 8;
+constexpr int FATOMS = 512;
+constexpr int FBLOCKS = 1024;
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_forces(Geom g, const int *atom_species,
-                                               const double *ph0, const double *ph1,
-                                               const double *ph2, const double *Z,
-                                               const double *rc, const cpx<T> *rho_g,
-                                               double *f_out)
+__global__ __launch_bounds__(NT) void k_forces_part(Geom g, int a0, int a1, const int *spec_off,
+                                                    int nspecies, const double *ph0,
+                                                    const double *ph1, const double *ph2,
+                                                    const double *Z, const double *rc,
+                                                    const cpx<T> *rho_g, long long nseg,
+                                                    int segs_row, double *part)
 {
-    __shared__ double tab[2 * FORCE_MAXTAB];
-    __shared__ double red[NT];
-    const int a = blockIdx.x, tid = threadIdx.x;
-    const int ntab = g.n0 + g.n1 + g.n2h;
-    for (int i = tid; i < g.n0; i += NT) {
-        tab[2 * i] = ph0[2 * ((long long)a * g.n0 + i)];
-        tab[2 * i + 1] = ph0[2 * ((long long)a * g.n0 + i) + 1];
-    }
-    for (int i = tid; i < g.n1; i += NT) {
-        tab[2 * (g.n0 + i)] = ph1[2 * ((long long)a * g.n1 + i)];
-        tab[2 * (g.n0 + i) + 1] = ph1[2 * ((long long)a * g.n1 + i) + 1];
-    }
-    for (int i = tid; i < g.n2h; i += NT) {
-        tab[2 * (g.n0 + g.n1 + i)] = ph2[2 * ((long long)a * g.n2h + i)];
-        tab[2 * (g.n0 + g.n1 + i) + 1] = ph2[2 * ((long long)a * g.n2h + i) + 1];
-    }
-    (void)ntab;
+    constexpr int NW = NT / 64;
+    __shared__ double acc[FATOMS * 3 * NW];
+    const int tid = threadIdx.x, wv = tid >> 6;
+    const int na = a1 - a0;
+    for (int i = tid; i < na * 3 * NW; i += NT) acc[i] = 0.0;
     __syncthreads();
-    const int s = atom_species[a];
-    const double z = Z[s], r = rc[s];
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (long long e = tid; e < g.Nh; e += NT) {
-        const int k2 = (int)(e % g.n2h);
-        const long long row = e / g.n2h;
+    const bool nyq_even = g.m > 0 && 2 * g.m == g.n2;   // the last k2 is -m
+    for (long long sg0 = (long long)blockIdx.x * NT; sg0 < nseg; sg0 += (long long)gridDim.x * NT) {
+        const long long sg = sg0 + tid;
+        const bool live = sg < nseg;
+        const long long row = live ? sg / segs_row : 0;
+        const int k0 = live ? (int)(sg % segs_row) * FS : 0;
+        const int cnt = live ? min(FS, g.n2h - k0) : 0;
         const int i1 = (int)(row % g.n1), i0 = (int)(row / g.n1);
         const int m0 = freq(i0, g.n0), m1 = freq(i1, g.n1);
-        const int m2 = (k2 == g.m) ? -g.m : k2;
-        const double gx = m0 * g.b[0][0] + m1 * g.b[1][0] + m2 * g.b[2][0];
-        const double gy = m0 * g.b[0][1] + m1 * g.b[1][1] + m2 * g.b[2][1];
-        const double gz = m0 * g.b[0][2] + m1 * g.b[1][2] + m2 * g.b[2][2];
-        const double G2 = gx * gx + gy * gy + gz * gz;
-        if (G2 == 0.0) continue;
-        const double *p0 = tab + 2 * i0;
-        const double *p1 = tab + 2 * (g.n0 + i1);
-        const double *p2 = tab + 2 * (g.n0 + g.n1 + k2);
-        // tables hold exp(-i G.R); the force needs exp(+i G.R) = conj
-        const double ar = p0[0] * p1[0] - p0[1] * p1[1];
-        const double ai = p0[0] * p1[1] + p0[1] * p1[0];
-        const double er = ar * p2[0] - ai * p2[1];
-        const double ei = -(ar * p2[1] + ai * p2[0]);
-        const cpx<T> rg = rho_g[e];
-        const double im = er * (double)rg.y + ei * (double)rg.x;
-        const double vs = -4.0 * PI_D * z * exp(-G2 * r * r * 0.25) / G2;
-        const double w = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
-        const double sc = w * vs * im;
-        fx += sc * gx;
-        fy += sc * gy;
-        fz += sc * gz;
+        // the segment's points: k2 = k0 + j; the Nyquist point (if any) apart
+        const int kn = (nyq_even && k0 + cnt - 1 == g.m) ? cnt - 1 : -1;
+        const double G0x = m0 * g.b[0][0] + m1 * g.b[1][0] + k0 * g.b[2][0];
+        const double G0y = m0 * g.b[0][1] + m1 * g.b[1][1] + k0 * g.b[2][1];
+        const double G0z = m0 * g.b[0][2] + m1 * g.b[1][2] + k0 * g.b[2][2];
+        const double GNx = m0 * g.b[0][0] + m1 * g.b[1][0] - g.m * g.b[2][0];
+        const double GNy = m0 * g.b[0][1] + m1 * g.b[1][1] - g.m * g.b[2][1];
+        const double GNz = m0 * g.b[0][2] + m1 * g.b[1][2] - g.m * g.b[2][2];
+        const cpx<T> *rrow = rho_g + row * g.n2h + k0;
+        for (int s = 0; s < nspecies; ++s) {
+            const int lo = max(spec_off[s], a0), hi = min(spec_off[s + 1], a1);
+            if (lo >= hi) continue;   // uniform
+            const double z = Z[s], r2 = rc[s] * rc[s] * 0.25;
+            // w(G) of the segment's points (0 past the row's end and at
+            // G = 0); the Nyquist point's w apart (wn), 0 in the progression.
+            // Along the segment G^2 = G0^2 + 2 j G0.b2 + j^2 b2^2, so the form
+            // factor exp(-r2 G^2) = E0 A^j B^(j^2) advances by C_j = A B^(2j+1)
+            // (three exponentials per segment; every factor is at most
+            // exp(2 r2 |G0| |b2|), and terms below e^-700 round to 0)
+            const double b2x = g.b[2][0], b2y = g.b[2][1], b2z = g.b[2][2];
+            const double G00 = G0x * G0x + G0y * G0y + G0z * G0z;
+            const double gb = G0x * b2x + G0y * b2y + G0z * b2z;
+            const double bb = b2x * b2x + b2y * b2y + b2z * b2z;
+            const double Bq = exp(-r2 * bb);
+            double E = exp(-r2 * G00), C = exp(-2.0 * r2 * gb) * Bq;
+            const double B2 = Bq * Bq, K = -4.0 * PI_D * z;
+            double wr[FS], wi[FS];
+#pragma unroll
+            for (int j = 0; j < FS; ++j) {
+                const int k2 = k0 + j;
+                const double G2 = G00 + (double)j * (2.0 * gb + (double)j * bb);
+                const bool on = j < cnt && j != kn && G2 > 0.0;
+                const double c = (k2 == 0 || k2 == g.m) ? 1.0 : 2.0;
+                const double w = on ? c * K * E / G2 : 0.0;
+                double rx = 0.0, ry = 0.0;
+                if (j < cnt) {
+                    const cpx<T> rg = rrow[j];
+                    rx = (double)rg.x;
+                    ry = (double)rg.y;
+                }
+                wr[j] = w * rx;
+                wi[j] = w * ry;
+                E *= C;
+                C *= B2;
+                // one point at a time: interleaving the points' divisions
+                // costs registers, not time
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            double wnr = 0.0, wni = 0.0;
+            if (kn >= 0) {
+                const double GN2 = GNx * GNx + GNy * GNy + GNz * GNz;
+                const double w = GN2 > 0.0 ? K * exp(-r2 * GN2) / GN2 : 0.0;   // c = 1
+                const cpx<T> rg = rrow[kn];
+                wnr = w * (double)rg.x;
+                wni = w * (double)rg.y;
+            }
+            for (int a = lo; a < hi; ++a) {
+                double fx = 0.0, fy = 0.0, fz = 0.0;
+                if (live) {
+                    const double *p0 = ph0 + 2 * ((long long)a * g.n0 + i0);
+                    const double *p1 = ph1 + 2 * ((long long)a * g.n1 + i1);
+                    const double *p2 = ph2 + 2 * ((long long)a * g.n2h);   // uniform
+                    const double qr = p0[0] * p1[0] - p0[1] * p1[1];
+                    const double qi = p0[0] * p1[1] + p0[1] * p1[0];
+                    const double dr = p2[2], di = p2[3];   // e^{-i b_2.R_a}
+                    double tr = qr * p2[2 * k0] - qi * p2[2 * k0 + 1];
+                    double ti = qr * p2[2 * k0 + 1] + qi * p2[2 * k0];
+                    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < FS; ++j) {
+                        // Im[conj(t) w] with t = e^{-i G.R}
+                        const double im = tr * wi[j] - ti * wr[j];
+                        s0 += im;
+                        s1 += (double)j * im;
+                        const double t2 = tr * dr - ti * di;
+                        ti = tr * di + ti * dr;
+                        tr = t2;
+                    }
+                    // the Nyquist point (wn = 0 on lanes without one)
+                    const int mq = g.m > 0 ? g.m : 0;
+                    const double nr = qr * p2[2 * mq] - qi * p2[2 * mq + 1];
+                    const double ni = qr * p2[2 * mq + 1] + qi * p2[2 * mq];
+                    const double imn = nr * wni - ni * wnr;
+                    fx = G0x * s0 + g.b[2][0] * s1 + GNx * imn;
+                    fy = G0y * s0 + g.b[2][1] * s1 + GNy * imn;
+                    fz = G0z * s0 + g.b[2][2] * s1 + GNz * imn;
+                }
+                fx = wave_sum_to_last(fx);
+                fy = wave_sum_to_last(fy);
+                fz = wave_sum_to_last(fz);
+                if ((tid & 63) == 63) {
+                    double *o = acc + ((a - a0) * 3) * NW + wv;
+                    o[0] += fx;
+                    o[NW] += fy;
+                    o[2 * NW] += fz;
+                }
+            }
+        }
     }
-    fx = block_sum<NT>(fx, red, tid);
-    fy = block_sum<NT>(fy, red, tid);
-    fz = block_sum<NT>(fz, red, tid);
-    if (tid == 0) {
-        f_out[3 * a + 0] = fx;
-        f_out[3 * a + 1] = fy;
-        f_out[3 * a + 2] = fz;
+    __syncthreads();
+    for (int i = tid; i < na * 3; i += NT) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += acc[i * NW + w];
+        part[(long long)blockIdx.x * na * 3 + i] = v;
     }
 }
 
-template <typename T>
-hipError_t launch_forces(const Geom &g, int natoms, const int *atom_species, const double *ph0,
-                         const double *ph1, const double *ph2, const double *Z, const double *rc,
-                         const void *rho_g, double *f_out, hipStream_t s)
+// 16 lanes per force component: lane l adds blocks l, l + 16, .. in order,
+// then the 16 sums are added by a fixed butterfly (deterministic)
+constexpr int FSUM = 16;
+__global__ __launch_bounds__(NT) void k_forces_sum(int na, int nblk, const double *part,
+                                                   double *f_out)
 {
-    if (g.n0 + g.n1 + g.n2h > FORCE_MAXTAB) return hipErrorInvalidValue;
+    const int l = threadIdx.x % FSUM;
+    const int i = (int)((blockIdx.x * NT + threadIdx.x) / FSUM);
+    const bool ok = i < na * 3;
+    double v = 0.0;
+    if (ok)
+        for (int b = l; b < nblk; b += FSUM) v += part[(long long)b * na * 3 + i];
+#pragma unroll
+    for (int off = FSUM / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, FSUM);
+    if (ok && l == 0) f_out[i] = v;
+}
+
+// blocks of the partial-force kernel and the doubles of its partial table
+long long forces_blocks(const Geom &g)
+{
+    const long long nseg = (long long)g.n0 * g.n1 * ((g.n2h + FS - 1) / FS);
+    const long long nb = (nseg + NT - 1) / NT;
+    return nb < FBLOCKS ? nb : FBLOCKS;
+}
+long long forces_part_doubles(const Geom &g, int natoms)
+{
+    return forces_blocks(g) * (long long)(natoms < FATOMS ? natoms : FATOMS) * 3;
+}
+
+template <typename T>
+hipError_t launch_forces(const Geom &g, int natoms, const int *spec_off, int nspecies,
+                         const double *ph0, const double *ph1, const double *ph2, const double *Z,
+                         const double *rc, const void *rho_g, double *part, double *f_out,
+                         hipStream_t s)
+{
     if (natoms <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_forces<T>), dim3(natoms), dim3(NT), 0, s, g, atom_species, ph0, ph1, ph2,
-                       Z, rc, (const cpx<T> *)rho_g, f_out);
+    const int segs_row = (g.n2h + FS - 1) / FS;
+    const long long nseg = (long long)g.n0 * g.n1 * segs_row;
+    const int nblk = (int)forces_blocks(g);
+    for (int a0 = 0; a0 < natoms; a0 += FATOMS) {
+        const int a1 = a0 + FATOMS < natoms ? a0 + FATOMS : natoms;
+        hipLaunchKernelGGL((k_forces_part<T>), dim3(nblk), dim3(NT), 0, s, g, a0, a1, spec_off,
+                           nspecies, ph0, ph1, ph2, Z, rc, (const cpx<T> *)rho_g, nseg, segs_row,
+                           part);
+        const int n3 = (a1 - a0) * 3;
+        hipLaunchKernelGGL(k_forces_sum, dim3((n3 * FSUM + NT - 1) / NT), dim3(NT), 0, s, a1 - a0,
+                           nblk, (const double *)part, f_out + 3 * (long long)a0);
+    }
     return hipGetLastError();
 }
-template hipError_t launch_forces<float>(const Geom &, int, const int *, const double *,
+template hipError_t launch_forces<float>(const Geom &, int, const int *, int, const double *,
                                          const double *, const double *, const double *,
-                                         const double *, const void *, double *, hipStream_t);
-template hipError_t launch_forces<double>(const Geom &, int, const int *, const double *,
+                                         const double *, const void *, double *, double *,
+                                         hipStream_t);
+template hipError_t launch_forces<double>(const Geom &, int, const int *, int, const double *,
                                           const double *, const double *, const double *,
-                                          const double *, const void *, double *, hipStream_t);
+                                          const double *, const void *, double *, double *,
+                                          hipStream_t);
 
 // ---------------------------------------------------------------- vectors
 constexpr int DOT_ITEMS = 8;
 
 int dots_blocks(long long n) { return (int)((n + (long long)NT * DOT_ITEMS - 1) / (NT * DOT_ITEMS)); }
 
-template <typename T>
+// Up to four dot products over the same index range, each block adding its
+// NT * DOT_ITEMS elements; with AL (16-byte aligned vectors, n a multiple of
+// the group) every load takes 16 bytes.  All products go through one
+// block reduction.
+template <typename T, bool AL>
 __global__ __launch_bounds__(NT) void k_dots(long long n, int nd, const T *x0, const T *y0,
                                              const T *x1, const T *y1, const T *x2, const T *y2,
                                              const T *x3, const T *y3, double *part, int pstride)
@@ -317,15 +477,36 @@ __global__ __launch_bounds__(NT) void k_dots(long long n, int nd, const T *x0, c
     const long long base = (long long)blockIdx.x * NT * DOT_ITEMS;
     const T *xs[4] = {x0, x1, x2, x3};
     const T *ys[4] = {y0, y1, y2, y3};
-    for (int d = 0; d < nd; ++d) {
-        double acc = 0.0;
-        for (int it = 0; it < DOT_ITEMS; ++it) {
-            const long long i = base + (long long)it * NT + tid;
-            if (i < n) acc += (double)xs[d][i] * (double)ys[d][i];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (AL) {
+        constexpr int E = 16 / sizeof(T);
+        struct alignas(16) V { T v[E]; };
+        static_assert(DOT_ITEMS % E == 0, "whole groups");
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            if (d >= nd) break;
+            for (int it = 0; it < DOT_ITEMS / E; ++it) {
+                const long long g = base / E + (long long)it * NT + tid;
+                if (g * E < n) {
+                    const V xv = ((const V *)xs[d])[g], yv = ((const V *)ys[d])[g];
+#pragma unroll
+                    for (int k = 0; k < E; ++k) acc[d] += (double)xv.v[k] * (double)yv.v[k];
+                }
+            }
         }
-        acc = block_sum<NT>(acc, red, tid);
-        if (tid == 0) part[(long long)(SL_AUX0 + d) * pstride + blockIdx.x] = acc;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            if (d >= nd) break;
+            for (int it = 0; it < DOT_ITEMS; ++it) {
+                const long long i = base + (long long)it * NT + tid;
+                if (i < n) acc[d] += (double)xs[d][i] * (double)ys[d][i];
+            }
+        }
     }
+    block_sums<NT, 4>(acc, red, tid);
+    if (tid == 0)
+        for (int d = 0; d < nd; ++d) part[(long long)(SL_AUX0 + d) * pstride + blockIdx.x] = acc[d];
 }
 
 template <typename T>
@@ -335,9 +516,18 @@ hipError_t launch_dots(long long n, int nd, const void *x0, const void *y0, cons
 {
     nblocks = dots_blocks(n);
     if (nblocks > pstride || nd < 1 || nd > 4) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_dots<T>), dim3(nblocks), dim3(NT), 0, s, n, nd, (const T *)x0,
-                       (const T *)y0, (const T *)x1, (const T *)y1, (const T *)x2, (const T *)y2,
-                       (const T *)x3, (const T *)y3, part, pstride);
+    constexpr int E = 16 / sizeof(T);
+    const bool al = n % E == 0 &&
+                    ((size_t)x0 | (size_t)y0 | (size_t)x1 | (size_t)y1 | (size_t)x2 | (size_t)y2 |
+                     (size_t)x3 | (size_t)y3) % 16 == 0;
+    if (al)
+        hipLaunchKernelGGL((k_dots<T, true>), dim3(nblocks), dim3(NT), 0, s, n, nd, (const T *)x0,
+                           (const T *)y0, (const T *)x1, (const T *)y1, (const T *)x2,
+                           (const T *)y2, (const T *)x3, (const T *)y3, part, pstride);
+    else
+        hipLaunchKernelGGL((k_dots<T, false>), dim3(nblocks), dim3(NT), 0, s, n, nd, (const T *)x0,
+                           (const T *)y0, (const T *)x1, (const T *)y1, (const T *)x2,
+                           (const T *)y2, (const T *)x3, (const T *)y3, part, pstride);
     return hipGetLastError();
 }
 template hipError_t launch_dots<float>(long long, int, const void *, const void *, const void *,
@@ -355,10 +545,37 @@ __global__ __launch_bounds__(NT) void k_lincomb(long long n, T *z, double a, con
     if (i < n) z[i] = T(a * (double)x[i] + (y ? b * (double)y[i] : 0.0));
 }
 
+// 16 bytes per thread (4 floats or 2 doubles) for 16-byte aligned vectors
+// whose length is a multiple of the group; the same arithmetic per element
+template <typename T>
+__global__ __launch_bounds__(NT) void k_lincomb16(long long ng, T *z, double a, const T *x,
+                                                  double b, const T *y)
+{
+    constexpr int E = 16 / sizeof(T);
+    struct alignas(16) V { T v[E]; };
+    const long long i = (long long)blockIdx.x * NT + threadIdx.x;
+    if (i >= ng) return;
+    const V xv = ((const V *)x)[i];
+    V yv{};
+    if (y) yv = ((const V *)y)[i];
+    V zv;
+#pragma unroll
+    for (int k = 0; k < E; ++k) zv.v[k] = T(a * (double)xv.v[k] + (y ? b * (double)yv.v[k] : 0.0));
+    ((V *)z)[i] = zv;
+}
+
 template <typename T>
 hipError_t launch_lincomb(long long n, void *z, double a, const void *x, double b, const void *y,
                           hipStream_t s)
 {
+    constexpr int E = 16 / sizeof(T);
+    const bool al = n % E == 0 && ((size_t)z | (size_t)x | (size_t)y) % 16 == 0;
+    if (al) {
+        const long long ng = n / E, nb = (ng + NT - 1) / NT;
+        hipLaunchKernelGGL((k_lincomb16<T>), dim3((unsigned)nb), dim3(NT), 0, s, ng, (T *)z, a,
+                           (const T *)x, b, (const T *)y);
+        return hipGetLastError();
+    }
     const long long nb = (n + NT - 1) / NT;
     hipLaunchKernelGGL((k_lincomb<T>), dim3((unsigned)nb), dim3(NT), 0, s, n, (T *)z, a,
                        (const T *)x, b, (const T *)y);

@@ -248,11 +248,14 @@ hipError_t launch_vext(const Geom &g, int natoms, const int *spec_off, int nspec
                        const double *ph0, const double *ph1, const double *ph2,
                        const double *Z, const double *rc, double volume, void *vext,
                        hipStream_t s);
+// atoms sorted by species (spec_off); part: forces_part_doubles(g, natoms)
+// doubles of scratch; f_out: 3 natoms doubles
 template <typename T>
-hipError_t launch_forces(const Geom &g, int natoms, const int *atom_species,
+hipError_t launch_forces(const Geom &g, int natoms, const int *spec_off, int nspecies,
                          const double *ph0, const double *ph1, const double *ph2,
-                         const double *Z, const double *rc, const void *rho_g, double *f_out,
-                         hipStream_t s);
+                         const double *Z, const double *rc, const void *rho_g, double *part,
+                         double *f_out, hipStream_t s);
+long long forces_part_doubles(const Geom &g, int natoms);
 
 // per-axis phase tables exp(-i 2 pi m_d s_d) of every atom (sorted order),
 // from fractional coordinates frac[3 a + d] in [0, 1): ph_d[a][i], i < n_d

@@ -40,7 +40,9 @@ def test_footprint_parts():
     ep = ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_EP)
     fo = ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_FORCES)
     op = ofdft.ofdft_footprint_bytes(cd, fd, ofdft.REQ_OPTIMIZE)
-    assert fo - ep == 4 * 3 * 8                 # forces buffer: natoms x 3 doubles
+    # forces: natoms x 3 doubles and the force kernel's per-block partials
+    # (32 x 32 rows of 3 segments of 8 k2, 256 per block: 12 blocks)
+    assert fo - ep == (4 * 3 + 12 * 4 * 3) * 8
     assert op - ep == 10 * N * 8                # ten FP64 optimiser fields
     # every field-sized buffer is at least: resident rho, 2 staging fields,
     # 4 half spectra (2 N/2+1 complex), v_ext and 3 G tables
