@@ -400,7 +400,7 @@ static uint64_t ion_bytes(const double lat[3][3], int na, int sf_method, const G
                                          (uint64_t)(G.n0 + G.n1 + G.n2h) * 16
                                    : (uint64_t)sf_tiled_blocks(G) * 8;
         return (uint64_t)na * (3 + 3 + 1 + 1) * 8 + (uint64_t)na * 4 + (nbins + 1) * 4 + recip +
-               (binned ? 0 : 16);
+               (binned ? 0 : 24);
     }
     const double(*A)[3] = lat;
     const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
@@ -413,7 +413,7 @@ static uint64_t ion_bytes(const double lat[3][3], int na, int sf_method, const G
             b[i][j] = 2.0 * PI * (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;
         }
     const EwaldGeom e = ewald_geom(lat, b, std::fabs(det), na);
-    return (uint64_t)na * (3 + 3 + 1 + 1 + 3) * 8 + (uint64_t)ewald_gbox_count(e) * 16;
+    return (uint64_t)na * (3 + 3 + 1 + 1 + 3) * 8 + (uint64_t)ewald_gbox_count(e) * 24;
 }
 
 // E_ion on the device; forces (natoms x 3, original atom order) if asked.
@@ -437,7 +437,7 @@ static ofdft_status ewald_device(ofdft_grid *g, double *e_ion, std::vector<doubl
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_q), (size_t)na * 8));
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_e), (size_t)na * 8));
     ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_f), 3 * (size_t)na * 8));
-    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), (size_t)nbox * 16));
+    ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), (size_t)nbox * 24));   // S(G), w(G)
     HIP_TRY(hipMemcpyAsync(g->d_ew_pos, g->pos.data(), 3 * (size_t)na * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(g->d_ew_q, q.data(), (size_t)na * 8, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_ewald(e, na, g->d_ew_pos, g->d_ew_q, g->d_ew_sf, g->d_ew_e,
@@ -1669,7 +1669,7 @@ static ofdft_status setup_ions_large(ofdft_grid *g, const std::vector<int> &orde
                                         g->d_bin_of, nbv, g->d_ew_e, s));
     } else {
         // the all-pairs kernel with an empty reciprocal box (gmax = 0: G = 0 only)
-        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), 16));
+        ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->d_ew_sf), 24));
         HIP_TRY(launch_ewald(L.e, na, g->d_ew_pos, g->d_ew_q, g->d_ew_sf, g->d_ew_e, nullptr, s));
     }
     std::vector<double> ea(na);

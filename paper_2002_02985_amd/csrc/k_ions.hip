@@ -67,30 +67,70 @@ __device__ __forceinline__ void ewald_gvec(const EwaldGeom &e, long long t, doub
     if (i == 0 && j == 0 && k == 0) g2 = 0.0;
 }
 
-// S(G) = sum_a q_a exp(i G.R_a), one thread per point of the integer box,
-// atoms summed in order
+// S(G) = sum_a q_a exp(i G.R_a) over the integer box of reciprocal vectors,
+// and w(G) = exp(-G^2 / 4a^2) / G^2 (0 at G = 0 and beyond the cut-off,
+// where S is 0 too): sf[2t], sf[2t + 1] = S, sf[2 nbox + t] = w.  A thread
+// takes EW_K consecutive k of one (i, j) row; per atom it evaluates one sine
+// and cosine and advances the phase along k by exp(i b_2.R) (one complex
+// multiplication per point); atoms are summed in order.
+constexpr int EW_K = 8;
 __global__ __launch_bounds__(NT) void k_ewald_sf(EwaldGeom e, int natoms, const double *pos,
                                                  const double *q, double *sf)
 {
-    const long long t = (long long)blockIdx.x * NT + threadIdx.x;
-    if (t >= ewald_gbox_count(e)) return;
-    double G[3], g2;
-    ewald_gvec(e, t, G, g2);
-    double sr = 0.0, si = 0.0;
-    if (g2 > 0.0 && g2 <= e.gcut2) {
-        for (int a = 0; a < natoms; ++a) {
-            double sn, cs;
-            sincos(G[0] * pos[3 * a] + G[1] * pos[3 * a + 1] + G[2] * pos[3 * a + 2], &sn, &cs);
-            sr += q[a] * cs;
-            si += q[a] * sn;
+    const int w0 = 2 * e.gmax[0] + 1, w1 = 2 * e.gmax[1] + 1, w2 = 2 * e.gmax[2] + 1;
+    const int segs = (w2 + EW_K - 1) / EW_K;
+    const long long sg = (long long)blockIdx.x * NT + threadIdx.x;
+    if (sg >= (long long)w0 * w1 * segs) return;
+    const int row = (int)(sg / segs), k0 = (int)(sg % segs) * EW_K;
+    const int i = row / w1 - e.gmax[0], j = row % w1 - e.gmax[1];
+    const int cnt = min(EW_K, w2 - k0);
+    const long long nbox = ewald_gbox_count(e);
+    double G0[3], B2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        G0[c] = i * e.b[0][c] + j * e.b[1][c] + (k0 - e.gmax[2]) * e.b[2][c];
+        B2[c] = e.b[2][c];
+    }
+    double sr[EW_K], si[EW_K];
+    bool on[EW_K];
+#pragma unroll
+    for (int kk = 0; kk < EW_K; ++kk) {
+        sr[kk] = si[kk] = 0.0;
+        const double gx = G0[0] + kk * B2[0], gy = G0[1] + kk * B2[1], gz = G0[2] + kk * B2[2];
+        const double g2 = gx * gx + gy * gy + gz * gz;
+        const bool zero = i == 0 && j == 0 && k0 + kk == e.gmax[2];
+        on[kk] = kk < cnt && !zero && g2 > 0.0 && g2 <= e.gcut2;
+        if (kk < cnt)
+            sf[2 * nbox + (long long)row * w2 + k0 + kk] =
+                on[kk] ? exp(-g2 / (4.0 * e.a * e.a)) / g2 : 0.0;
+    }
+    for (int a = 0; a < natoms; ++a) {
+        const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2], qa = q[a];
+        double tr, ti, dr, di;
+        sincos(G0[0] * x + G0[1] * y + G0[2] * z, &ti, &tr);
+        sincos(B2[0] * x + B2[1] * y + B2[2] * z, &di, &dr);
+#pragma unroll
+        for (int kk = 0; kk < EW_K; ++kk) {
+            sr[kk] += qa * tr;
+            si[kk] += qa * ti;
+            const double t2 = tr * dr - ti * di;
+            ti = tr * di + ti * dr;
+            tr = t2;
         }
     }
-    sf[2 * t] = sr;
-    sf[2 * t + 1] = si;
+#pragma unroll
+    for (int kk = 0; kk < EW_K; ++kk) {
+        if (kk >= cnt) continue;
+        const long long t = (long long)row * w2 + k0 + kk;
+        sf[2 * t] = on[kk] ? sr[kk] : 0.0;
+        sf[2 * t + 1] = on[kk] ? si[kk] : 0.0;
+    }
 }
 
 // One block per atom i: real-space pairs (j, image) with r < rcut, and the
-// reciprocal sum over G of Re/Im[exp(i G.R_i) conj S(G)].
+// reciprocal sum over G of Re/Im[exp(i G.R_i) conj S(G)] w(G), a thread
+// taking whole (i, j) rows of the box with the phase advanced along k (G is
+// linear along a row, so the force needs two running sums per row).
 __global__ __launch_bounds__(NT) void k_ewald_atoms(EwaldGeom e, int natoms, const double *pos,
                                                     const double *q, const double *sf,
                                                     double *e_atom, double *f)
@@ -98,47 +138,76 @@ __global__ __launch_bounds__(NT) void k_ewald_atoms(EwaldGeom e, int natoms, con
     __shared__ double red[4 * NT / 64];
     const int i = blockIdx.x, tid = threadIdx.x;
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2], qi = q[i];
-    const int w1 = 2 * e.nmax[1] + 1, w2 = 2 * e.nmax[2] + 1;
-    const long long nimg = ewald_image_count(e);
     const double a = e.a;
     const double two_a_sqrtpi = 2.0 * a / sqrt(PI_D);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};   // energy, fx, fy, fz
-    for (long long p = tid; p < (long long)natoms * nimg; p += NT) {
-        const int j = (int)(p / nimg);
-        const long long l = p % nimg;
-        const int kk = (int)(l % w2) - e.nmax[2];
-        const long long r1 = l / w2;
-        const int jj = (int)(r1 % w1) - e.nmax[1];
-        const int ii = (int)(r1 / w1) - e.nmax[0];
-        const double dx = xi - pos[3 * j] - (ii * e.lat[0][0] + jj * e.lat[1][0] + kk * e.lat[2][0]);
-        const double dy = yi - pos[3 * j + 1] - (ii * e.lat[0][1] + jj * e.lat[1][1] + kk * e.lat[2][1]);
-        const double dz = zi - pos[3 * j + 2] - (ii * e.lat[0][2] + jj * e.lat[1][2] + kk * e.lat[2][2]);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < 1e-20 || r2 > e.rcut2) continue;
-        const double r = sqrt(r2);
-        const double ec = erfc(a * r);
+    // real space: for atom j the displacement d = R_i - R_j has fractional
+    // coordinates f_c = b_c.d / 2 pi; an image d - sum_c n_c a_c lies within
+    // rcut only if |f_c - n_c| <= rcut |b_c| / 2 pi, so each j visits the
+    // few n in those ranges (inside e.nmax) instead of the whole image box
+    const double rcut = sqrt(e.rcut2);
+    double rcf[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        rcf[c] = rcut * sqrt(e.b[c][0] * e.b[c][0] + e.b[c][1] * e.b[c][1] + e.b[c][2] * e.b[c][2]) /
+                 (2.0 * PI_D);
+    for (int j = tid; j < natoms; j += NT) {
+        const double d0x = xi - pos[3 * j], d0y = yi - pos[3 * j + 1], d0z = zi - pos[3 * j + 2];
+        int lo[3], hi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double fc = (e.b[c][0] * d0x + e.b[c][1] * d0y + e.b[c][2] * d0z) / (2.0 * PI_D);
+            lo[c] = max((int)ceil(fc - rcf[c]), -e.nmax[c]);
+            hi[c] = min((int)floor(fc + rcf[c]), e.nmax[c]);
+        }
         const double qq = qi * q[j];
-        acc[0] += 0.5 * qq * ec / r;
-        const double mag = qq * (ec / r2 + two_a_sqrtpi * exp(-a * a * r2) / r) / r;
-        acc[1] += mag * dx;
-        acc[2] += mag * dy;
-        acc[3] += mag * dz;
+        for (int ii = lo[0]; ii <= hi[0]; ++ii)
+            for (int jj = lo[1]; jj <= hi[1]; ++jj)
+                for (int kk = lo[2]; kk <= hi[2]; ++kk) {
+                    const double dx = d0x - (ii * e.lat[0][0] + jj * e.lat[1][0] + kk * e.lat[2][0]);
+                    const double dy = d0y - (ii * e.lat[0][1] + jj * e.lat[1][1] + kk * e.lat[2][1]);
+                    const double dz = d0z - (ii * e.lat[0][2] + jj * e.lat[1][2] + kk * e.lat[2][2]);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < 1e-20 || r2 > e.rcut2) continue;
+                    const double r = sqrt(r2);
+                    const double ec = erfc(a * r);
+                    acc[0] += 0.5 * qq * ec / r;
+                    const double mag = qq * (ec / r2 + two_a_sqrtpi * exp(-a * a * r2) / r) / r;
+                    acc[1] += mag * dx;
+                    acc[2] += mag * dy;
+                    acc[3] += mag * dz;
+                }
     }
+    const int g0 = 2 * e.gmax[0] + 1, g1 = 2 * e.gmax[1] + 1, g2w = 2 * e.gmax[2] + 1;
     const long long nbox = ewald_gbox_count(e);
     const double pre = 2.0 * PI_D / e.volume;
-    for (long long t = tid; t < nbox; t += NT) {
-        double G[3], g2;
-        ewald_gvec(e, t, G, g2);
-        if (!(g2 > 0.0 && g2 <= e.gcut2)) continue;
-        double sn, cs;
-        sincos(G[0] * xi + G[1] * yi + G[2] * zi, &sn, &cs);
-        const double sr = sf[2 * t], si = sf[2 * t + 1];
-        const double w = exp(-g2 / (4.0 * a * a)) / g2;
-        acc[0] += pre * w * qi * (cs * sr + sn * si);
-        const double fm = 2.0 * pre * w * qi * (sn * sr - cs * si);
-        acc[1] += fm * G[0];
-        acc[2] += fm * G[1];
-        acc[3] += fm * G[2];
+    const double *wg = sf + 2 * nbox;
+    double dr, di;   // exp(i b_2.R_i)
+    sincos(e.b[2][0] * xi + e.b[2][1] * yi + e.b[2][2] * zi, &di, &dr);
+    for (int row = tid; row < g0 * g1; row += NT) {
+        const int gi = row / g1 - e.gmax[0], gj = row % g1 - e.gmax[1];
+        double Gs[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Gs[c] = gi * e.b[0][c] + gj * e.b[1][c] - e.gmax[2] * e.b[2][c];
+        double tr, ti;
+        sincos(Gs[0] * xi + Gs[1] * yi + Gs[2] * zi, &ti, &tr);
+        double en = 0.0, f0 = 0.0, f1 = 0.0;
+        const long long t0 = (long long)row * g2w;
+        for (int k = 0; k < g2w; ++k) {
+            const double w = wg[t0 + k];
+            const double sr = sf[2 * (t0 + k)], si = sf[2 * (t0 + k) + 1];
+            en += w * (tr * sr + ti * si);
+            const double fm = w * (ti * sr - tr * si);
+            f0 += fm;
+            f1 += (double)k * fm;
+            const double t2 = tr * dr - ti * di;
+            ti = tr * di + ti * dr;
+            tr = t2;
+        }
+        acc[0] += pre * qi * en;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[1 + c] += 2.0 * pre * qi * (Gs[c] * f0 + e.b[2][c] * f1);
     }
     block_sums<NT, 4>(acc, red, tid);
     if (tid == 0) {
@@ -155,9 +224,10 @@ hipError_t launch_ewald(const EwaldGeom &e, int natoms, const double *pos, const
                         double *sf, double *e_atom, double *f, hipStream_t s)
 {
     if (natoms <= 0) return hipSuccess;
-    const long long nbox = ewald_gbox_count(e);
-    hipLaunchKernelGGL(k_ewald_sf, dim3((unsigned)((nbox + NT - 1) / NT)), dim3(NT), 0, s, e, natoms,
-                       pos, q, sf);
+    const long long nseg = (long long)(2 * e.gmax[0] + 1) * (2 * e.gmax[1] + 1) *
+                           ((2 * e.gmax[2] + 1 + EW_K - 1) / EW_K);
+    hipLaunchKernelGGL(k_ewald_sf, dim3((unsigned)((nseg + NT - 1) / NT)), dim3(NT), 0, s, e,
+                       natoms, pos, q, sf);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_ewald_atoms, dim3(natoms), dim3(NT), 0, s, e, natoms, pos, q, sf, e_atom, f);
