@@ -215,12 +215,13 @@ __device__ __forceinline__ T nl_kernel_dev(T eta, const NlKern &k)
 
 // k_F = (3 pi^2 rho)^(1/3), clamped to the knot range; bracket j and linear
 // weight t on the knots (step s4).  An exact knot belongs to the segment on
-// its right; the last knot to the last segment with t = 1.
-template <typename T>
-__device__ __forceinline__ void knot_bracket_kf(T kf, const Knots &kn, int &j, T &t, bool &inside)
+// its right; the last knot to the last segment with t = 1.  kat(i) is knot i
+// in T.
+template <typename T, class KAT>
+__device__ __forceinline__ void knot_bracket_at(T kf, int nk, int log_spacing, double inv_span,
+                                                const KAT &kat, int &j, T &t, bool &inside)
 {
-    const int nk = kn.nk;
-    const T k1 = T(kn.k[0]), kN = T(kn.k[nk - 1]);
+    const T k1 = kat(0), kN = kat(nk - 1);
     inside = kf > k1 && kf < kN;
     const T kt = kf < k1 ? k1 : (kf > kN ? kN : kf);
     if (nk == 1) {
@@ -228,14 +229,28 @@ __device__ __forceinline__ void knot_bracket_kf(T kf, const Knots &kn, int &j, T
         t = T(0);
         return;
     }
-    T s = kn.log_spacing ? T(kn.inv_span) * d_log(kt / k1) : T(kn.inv_span) * (kt - k1);
+    T s = log_spacing ? T(inv_span) * d_log(kt / k1) : T(inv_span) * (kt - k1);
     int jj = (int)floor(s);
     jj = jj < 0 ? 0 : (jj > nk - 2 ? nk - 2 : jj);
-    if (kt < T(kn.k[jj]) && jj > 0) jj -= 1;
-    else if (jj < nk - 2 && kt >= T(kn.k[jj + 1])) jj += 1;
+    if (kt < kat(jj) && jj > 0) jj -= 1;
+    else if (jj < nk - 2 && kt >= kat(jj + 1)) jj += 1;
     j = jj;
-    const T kj = T(kn.k[jj]), kj1 = T(kn.k[jj + 1]);
+    const T kj = kat(jj), kj1 = kat(jj + 1);
     t = (kt - kj) / (kj1 - kj);
+}
+// knots read from the device array
+template <typename T>
+__device__ __forceinline__ void knot_bracket_kf(T kf, const Knots &kn, int &j, T &t, bool &inside)
+{
+    knot_bracket_at(kf, kn.nk, kn.log_spacing, kn.inv_span, [&](int i) { return T(kn.k[i]); }, j,
+                    t, inside);
+}
+// knots already converted to T, in LDS
+template <typename T>
+__device__ __forceinline__ void knot_bracket_tab(T kf, int nk, int log_spacing, double inv_span,
+                                                 const T *ktab, int &j, T &t, bool &inside)
+{
+    knot_bracket_at(kf, nk, log_spacing, inv_span, [&](int i) { return ktab[i]; }, j, t, inside);
 }
 
 // rho^(-1/6) in FP64 without the FP64 logarithm and exponential (dozens of
@@ -1201,53 +1216,79 @@ __device__ __forceinline__ void c2r_rows(cpx<T> *buf, const cpx<T> *__restrict__
     lds_fft<T, M, true, P, NT, PS>(buf, twM, tid);
 }
 
-// c2r of the same block of rows of two spectra (knots i and i + 1) at once:
-// pencil p < P is row r0 + p of sa, pencil P + p the same row of sb (zeros
-// without sb), element n of pencil p at buf[n * PS2 + p], PS2 = 2P + 1.
-// Twice the butterflies per Stockham stage of a one-spectrum pass, so that
-// the stages of a 192-point knot row keep more waves busy between barriers.
-template <typename T, int M, int P>
-__device__ __forceinline__ void c2r_rows2(cpx<T> *buf, const cpx<T> *__restrict__ sa,
-                                          const cpx<T> *__restrict__ sb, long long r0,
-                                          long long nrows, int n2h,
-                                          const cpx<T> *__restrict__ twM,
-                                          const cpx<T> *__restrict__ twN, int tid)
+// c2r of the knot passes: NPEN pencils, pencil pp < P row r0 + pp of sa,
+// pencil P <= pp < 2P the same row of sb (zeros without sb); element n of
+// pencil pp at buf[n * ES + pp].  With NPEN = 2P two knots' rows go through
+// one transform, twice the butterflies per Stockham stage of a one-spectrum
+// pass, so that the stages of short rows keep more waves busy between
+// barriers.  Each load pair (X[k], X[M-k]), k = 0 .. M/2, gives Z[k] and
+// Z[M-k]; every load of the pass is issued before the first is used (one
+// memory latency per pass rather than one per item), and twN is read from
+// LDS.
+template <typename T, int M, int P, int NPEN, int ES, int CH>
+__device__ __forceinline__ void c2r_knot_chunk(cpx<T> *buf, const cpx<T> *__restrict__ sa,
+                                               const cpx<T> *__restrict__ sb, long long r0,
+                                               long long nrows, int n2h, const cpx<T> *twN,
+                                               int tid, int q0)
 {
-    constexpr int P2 = 2 * P, PS2 = P2 + 1;
-    // k = 0 .. M/2: each load pair (X[k], X[M-k]) gives Z[k] and Z[M-k]
-    // (Z[M-k] for 0 < k, k != M - k)
     constexpr int H = M / 2 + 1;
-    constexpr int ITEMS = P2 * H;
-    for (int o = tid; o < ITEMS; o += NT) {
+    constexpr int ITEMS = NPEN * H;
+    cpx<T> xk[CH], xm[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int o = tid + (q0 + c) * NT;
         const int pp = o / H, k = o % H;
         const int p = pp < P ? pp : pp - P;
         const cpx<T> *spec = pp < P ? sa : sb;
-        const long long row = r0 + p;
-        cpx<T> z0 = {T(0), T(0)}, z1 = {T(0), T(0)};
-        if (spec && row < nrows) {
-            const cpx<T> *x = spec + row * n2h;
-            cpx<T> xk = x[k];
-            cpx<T> xm = x[M - k];
-            if (k == 0) {
-                xk.y = T(0);
-                xm.y = T(0);
-            }
-            // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k)
-            const cpx<T> s0 = {xk.x + xm.x, xk.y - xm.y};
-            const cpx<T> d0 = {xk.x - xm.x, xk.y + xm.y};
-            const cpx<T> w0 = cmul(d0, cconj(twN[k]));
-            z0 = {s0.x - w0.y, s0.y + w0.x};
-            // Z[M-k] from the same pair, X[M-k] and X[k] exchanged
-            const cpx<T> s1 = {xm.x + xk.x, xm.y - xk.y};
-            const cpx<T> d1 = {xm.x - xk.x, xm.y + xk.y};
-            const cpx<T> w1 = cmul(d1, cconj(twN[M - k]));
-            z1 = {s1.x - w1.y, s1.y + w1.x};
+        xk[c] = {T(0), T(0)};
+        xm[c] = {T(0), T(0)};
+        if ((ITEMS % NT == 0 || o < ITEMS) && spec && r0 + p < nrows) {
+            const cpx<T> *x = spec + (r0 + p) * n2h;
+            xk[c] = x[k];
+            xm[c] = x[M - k];
         }
-        buf[k * PS2 + pp] = z0;
-        if (k > 0 && 2 * k != M) buf[(M - k) * PS2 + pp] = z1;
     }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int o = tid + (q0 + c) * NT;
+        if (ITEMS % NT != 0 && o >= ITEMS) continue;
+        const int pp = o / H, k = o % H;
+        cpx<T> xa = xk[c], xb = xm[c];
+        if (k == 0) {
+            xa.y = T(0);
+            xb.y = T(0);
+        }
+        // Z[k] = (X[k] + conj X[M-k]) + i (X[k] - conj X[M-k]) conj(W^k)
+        const cpx<T> s0 = {xa.x + xb.x, xa.y - xb.y};
+        const cpx<T> d0 = {xa.x - xb.x, xa.y + xb.y};
+        const cpx<T> w0 = cmul(d0, cconj(twN[k]));
+        buf[k * ES + pp] = {s0.x - w0.y, s0.y + w0.x};
+        // Z[M-k] from the same pair, X[M-k] and X[k] exchanged
+        if (k > 0 && 2 * k != M) {
+            const cpx<T> s1 = {xb.x + xa.x, xb.y - xa.y};
+            const cpx<T> d1 = {xb.x - xa.x, xb.y + xa.y};
+            const cpx<T> w1 = cmul(d1, cconj(twN[M - k]));
+            buf[(M - k) * ES + pp] = {s1.x - w1.y, s1.y + w1.x};
+        }
+    }
+}
+// The loads of a pass go out in NCH chunks (one for the S3S4 epilogue; two
+// where the EXACT epilogue's second accumulator leaves fewer registers).
+template <typename T, int M, int P, int NPEN, int ES, int NCH>
+__device__ __forceinline__ void c2r_knot_rows(cpx<T> *buf, const cpx<T> *__restrict__ sa,
+                                              const cpx<T> *__restrict__ sb, long long r0,
+                                              long long nrows, int n2h, const cpx<T> *twM,
+                                              const cpx<T> *twN, int tid)
+{
+    constexpr int PI = (NPEN * (M / 2 + 1) + NT - 1) / NT;
+    constexpr int CH = (PI + NCH - 1) / NCH;
+    // per-item indices recomputed per pass, not hoisted out of the pass loop
+    tid = opaque(tid);
+    c2r_knot_chunk<T, M, P, NPEN, ES, CH>(buf, sa, sb, r0, nrows, n2h, twN, tid, 0);
+    if constexpr (PI > CH)
+        c2r_knot_chunk<T, M, P, NPEN, ES, PI - CH>(buf, sa, sb, r0, nrows, n2h, twN, tid, CH);
     __syncthreads();
-    lds_fft<T, M, true, P2, NT, PS2>(buf, twM, tid);
+    lds_fft<T, M, true, NPEN, NT, ES>(buf, twM, tid);
 }
 
 // The knot epilogue is instantiated with CF = CB_SPL (S3S4) or CB_SPL |
@@ -1265,12 +1306,18 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     constexpr int PS = P + 1;
     constexpr int PAIRS = P * M;
     constexpr int PER = (PAIRS + NT - 1) / NT;
-    // the knot epilogue transforms two knots' rows at once (c2r_rows2) for
-    // rows of up to 256 complex points (longer rows have enough butterflies
-    // per stage, and the pair's registers would spill)
+    // the knot epilogue transforms two knots' rows at once (c2r_knot_rows)
+    // for rows of up to 256 complex points (longer rows have enough
+    // butterflies per stage, and the pair's registers would spill)
     constexpr bool PAIR = MODE == EP_KNOTS && M <= 256;
+    constexpr bool KN = MODE == EP_KNOTS;
     __shared__ cpx<T> buf[M * (PAIR ? 2 * P + 1 : PS)];
     __shared__ double red[5 * NT / 64];
+    // knot passes: twM and twN (M + 1 entries) and the knots in LDS, and the
+    // passes some point of the block needs, one bit per pass and wave
+    __shared__ cpx<T> twl[KN ? 2 * M + 1 : 1];
+    __shared__ T knl[KN ? MAXKNOTS : 1];
+    __shared__ unsigned needw[KN ? NT / 64 : 1];
     const int tid = threadIdx.x;
     const int b = blockIdx.y;
     const long long nrows = (long long)g.n0 * g.n1;
@@ -1347,74 +1394,145 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
         // step s4 for this batch of knots: v1 += L_i Phi_i, v2 += L_i' Phi_i
         // (v2 for EXACT only, fixed at compile time by CF)
         constexpr bool exact = (CF & CB_EXACT) != 0;
-        int jj[PER][2];
+        const int nk = a.knots.nk;
+        constexpr int TWQ = (2 * M + 1 + NT - 1) / NT;
+#pragma unroll
+        for (int q = 0; q < TWQ; ++q) {
+            const int i = tid + q * NT;
+            if (i < 2 * M + 1) twl[i] = i < M ? twM[i] : twN[i - M];
+        }
+        if (tid < nk) knl[tid] = T(a.knots.k[tid]);   // nk <= MAXKNOTS <= NT
+        __syncthreads();
+        // per point: knot brackets (two 8-bit fields per pair, nk <= 64) and
+        // weights.  The pair's row, element and validity are recomputed
+        // from an opaque copy of the thread index where they are used
+        // instead of being held in registers across the passes.
+        auto pair_at = [&](int q, int t, int &p, int &n) {
+            const int idx = t + q * NT;
+            p = idx / M;
+            n = idx % M;
+            return idx < PAIRS && r0 + p < nrows;
+        };
+        unsigned jp[PER];
         T tt[PER][2];
         cpx<T> v1[PER], v2[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const T vv[2] = {xin[q].x, xin[q].y};
+            int jq[2];
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const T rho = a.in_is_phi ? vv[c] * vv[c] : (vv[c] > T(0) ? vv[c] : T(0));
                 const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
                 bool inside;
-                knot_bracket_kf(kf_from_log2(lu), a.knots, jj[q][c], tt[q][c], inside);
+                knot_bracket_tab(kf_from_log2(lu), nk, a.knots.log_spacing, a.knots.inv_span, knl,
+                                 jq[c], tt[q][c], inside);
             }
+            jp[q] = (unsigned)jq[0] | ((unsigned)jq[1] << 8);
             v1[q] = {T(0), T(0)};
             v2[q] = {T(0), T(0)};
         }
-        const int nk = a.knots.nk;
-        constexpr int PS2 = 2 * P + 1;
+        auto jj_of = [&](int q, int (&j)[2]) {
+            j[0] = (int)(jp[q] & 0xffu);
+            j[1] = (int)(jp[q] >> 8);
+        };
         // knots f and f + 1 per pass (PAIR, else one); a pass is skipped if
         // no point of this block uses its knots (a knot used by none adds
-        // exact zeros)
-        for (int f = 0; f < a.nfields; f += PAIR ? 2 : 1) {
+        // exact zeros).  Bit f / KS of need: pass f, for the whole block
+        // after one reduction.
+        constexpr int KS = PAIR ? 2 : 1;
+        constexpr int NCH = exact ? 2 : 1;
+        unsigned need = 0;
+        {
+            const int t = opaque(tid);
+            for (int f = 0; f < a.nfields; f += KS) {
+                const int i = a.knot0 + f;
+                const int ihi = i + (PAIR && f + 1 < a.nfields ? 1 : 0);
+                bool nf = false;
+#pragma unroll
+                for (int q = 0; q < PER; ++q) {
+                    int p, n, j[2];
+                    jj_of(q, j);
+                    nf |= pair_at(q, t, p, n) &&
+                          (nk == 1 || (j[0] >= i - 1 && j[0] <= ihi) || (j[1] >= i - 1 && j[1] <= ihi));
+                }
+                need |= nf ? 1u << (f / KS) : 0u;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) need |= (unsigned)__shfl_xor((int)need, off);
+        if ((tid & 63) == 0) needw[tid >> 6] = need;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) need |= needw[w];
+        constexpr int PS2 = 2 * P + 1;
+        for (int f = 0; f < a.nfields; f += KS) {
+            if (!((need >> (f / KS)) & 1u)) continue;
             const int i = a.knot0 + f;
             const bool two = PAIR && f + 1 < a.nfields;
-            bool need = false;
+            if constexpr (PAIR)
+                c2r_knot_rows<T, M, P, 2 * P, PS2, NCH>(buf, spec_of(f),
+                                                        two ? spec_of(f + 1) : nullptr, r0, nrows,
+                                                        g.n2h, twl, twl + M, tid);
+            else
+                c2r_knot_rows<T, M, P, P, PS, NCH>(buf, spec_of(f), nullptr, r0, nrows, g.n2h,
+                                                   twl, twl + M, tid);
+            const int t = opaque(tid);
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                need |= valid[q] && (nk == 1 || (jj[q][0] >= i - 1 && jj[q][0] <= i + (two ? 1 : 0)) ||
-                                     (jj[q][1] >= i - 1 && jj[q][1] <= i + (two ? 1 : 0)));
-            if (!__syncthreads_or(need)) continue;
-            if constexpr (PAIR) {
-                c2r_rows2<T, M, P>(buf, spec_of(f), two ? spec_of(f + 1) : nullptr, r0, nrows,
-                                   g.n2h, twM, twN, tid);
-#pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    if (!valid[q]) continue;
-                    const int at2 = (lds_at[q] / PS) * PS2 + lds_at[q] % PS;
-                    knot_interp(jj[q], tt[q], i, nk, exact, buf[at2], v1[q], v2[q]);
-                    if (two)
-                        knot_interp(jj[q], tt[q], i + 1, nk, exact, buf[at2 + P], v1[q], v2[q]);
-                }
-            } else {
-                c2r_rows<T, M, P, PS>(buf, spec_of(f), r0, nrows, g.n2h, twM, twN, tid);
-#pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    if (!valid[q]) continue;
-                    knot_interp(jj[q], tt[q], i, nk, exact, buf[lds_at[q]], v1[q], v2[q]);
+            for (int q = 0; q < PER; ++q) {
+                int p, n, j[2];
+                if (!pair_at(q, t, p, n)) continue;
+                jj_of(q, j);
+                if constexpr (PAIR) {
+                    const int at2 = n * PS2 + p;
+                    knot_interp(j, tt[q], i, nk, exact, buf[at2], v1[q], v2[q]);
+                    if (two) knot_interp(j, tt[q], i + 1, nk, exact, buf[at2 + P], v1[q], v2[q]);
+                } else {
+                    knot_interp(j, tt[q], i, nk, exact, buf[n * PS + p], v1[q], v2[q]);
                 }
             }
             __syncthreads();
         }
         if constexpr (exact) {
 #pragma unroll
-            for (int q = 0; q < PER; ++q) knot_slope_scale(a.knots, jj[q], v2[q]);
+            for (int q = 0; q < PER; ++q) {
+                int j[2];
+                jj_of(q, j);
+                knot_slope_scale(a.knots, j, v2[q]);
+            }
         }
+        // accumulators: every load issued before the first add
         T *acc1 = (T *)a.acc1 + (long long)b * g.N;
         T *acc2 = exact ? (T *)a.acc2 + (long long)b * g.N : nullptr;
+        const int t = opaque(tid);
+        long long po[PER];
+        bool ok[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            if (!valid[q]) continue;
-            cpx<T> s1 = v1[q];
-            if (!acc_init) s1 = cadd(s1, *(cpx<T> *)(acc1 + offs[q]));
-            *(cpx<T> *)(acc1 + offs[q]) = s1;
-            if (acc2) {
-                cpx<T> s2 = v2[q];
-                if (!acc_init) s2 = cadd(s2, *(cpx<T> *)(acc2 + offs[q]));
-                *(cpx<T> *)(acc2 + offs[q]) = s2;
+            int p, n;
+            ok[q] = pair_at(q, t, p, n);
+            po[q] = ok[q] ? (r0 + p) * g.n2 + 2 * n : 0;
+        }
+        if (!acc_init) {
+            cpx<T> o1[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                o1[q] = ok[q] ? *(const cpx<T> *)(acc1 + po[q]) : cpx<T>{T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < PER; ++q) v1[q] = cadd(v1[q], o1[q]);
+            if constexpr (exact) {
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    o1[q] = ok[q] ? *(const cpx<T> *)(acc2 + po[q]) : cpx<T>{T(0), T(0)};
+#pragma unroll
+                for (int q = 0; q < PER; ++q) v2[q] = cadd(v2[q], o1[q]);
             }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (!ok[q]) continue;
+            *(cpx<T> *)(acc1 + po[q]) = v1[q];
+            if constexpr (exact) *(cpx<T> *)(acc2 + po[q]) = v2[q];
         }
         return;
     }
