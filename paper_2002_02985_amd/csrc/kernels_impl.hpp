@@ -23,6 +23,7 @@
 #include <type_traits>
 
 #include "fft_core.hpp"
+#include "gnl_poly.hpp"
 #include "kernels.hpp"
 
 namespace ofdft {
@@ -153,11 +154,11 @@ constexpr double KF_C = 3.0936677262801355;   // (3 pi^2)^(1/3)
 // Lindhard kernel shape G_NL(eta) = 1/F - 3 eta^2 - 1 with
 // F = 1/2 + (1 - eta^2)/(4 eta) ln|(1 + eta)/(1 - eta)| (the G_NL formula of
 // the nonlocal-KEDF section).  The logarithm is taken as log1p of
-// 2 eta/(1 - eta) or 2/(eta - 1); from eta = 1.6 on, 1/F - 3 eta^2 is summed
-// as a series in x = 1/eta^2 so that nothing cancels:
-//   F = x P(x),  P = sum_{n>=1} x^(n-1)/((2n-1)(2n+1)),
-//   3 eta^2 F = 1 + x S(x),  S = sum_{n>=2} 3 x^(n-2)/((2n-1)(2n+1)),
-//   G = -1 - S/P.
+// 2 eta/(1 - eta) or 2/(eta - 1); from eta = 1.6 on, where 1/F - 3 eta^2
+// would cancel, G_NL is a polynomial in x = 1/eta^2 (gnl_poly.hpp: the
+// Chebyshev economisation of G = -1 - S/P with F = x P(x) and
+// 3 eta^2 F = 1 + x S(x), P and S the series of the logarithm in 1/eta;
+// degree 7 in FP32, 16 in FP64, each within its precision's rounding).
 template <typename T>
 __device__ __forceinline__ T gnl_dev(T eta)
 {
@@ -168,7 +169,7 @@ __device__ __forceinline__ T gnl_dev(T eta)
     // selected per lane, so a wave whose lanes straddle eta = 1 runs one
     // logarithm): ln|(1 + eta)/(1 - eta)| = log1p(2 eta / (1 - eta)) below 1,
     // log1p(2 / (eta - 1)) above, and (1 - eta^2) changes sign.
-    if (eta < T(1.6)) {
+    if (eta < T(GNL_POLY_ETA)) {
         const bool lo = eta < T(1);
         const T d = lo ? T(1) - eta : eta - T(1);
         const T num = lo ? T(2) * eta : T(2);
@@ -177,13 +178,12 @@ __device__ __forceinline__ T gnl_dev(T eta)
         return d_rcp(F) - T(3) * eta * eta - T(1);
     }
     const T x = d_rcp(eta * eta);
-    constexpr int NTERM = sizeof(T) == 8 ? 40 : 18;
-    T P = T(0), S = T(0);
+    constexpr const double *C = sizeof(T) == 8 ? GNL_X64 : GNL_X32;
+    constexpr int DEG = sizeof(T) == 8 ? GNL_X64_DEG : GNL_X32_DEG;
+    T h = T(C[DEG]);
 #pragma unroll
-    for (int n = NTERM; n >= 1; --n) P = P * x + T(1.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
-#pragma unroll
-    for (int n = NTERM; n >= 2; --n) S = S * x + T(3.0 / ((2.0 * n - 1.0) * (2.0 * n + 1.0)));
-    return T(-1) - S * d_rcp(P);
+    for (int k = DEG - 1; k >= 0; --k) h = h * x + T(C[k]);
+    return h;
 }
 
 // K(eta) of the kernel family (omega = C_WT K): G_NL for Wang-Teter; for the
@@ -372,6 +372,12 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
         khi = a.kneed[2 * b + 1];
         if (a.knot0 > khi || a.knot0 + a.nfields - 1 < klo) return;
     }
+    // knot fields: the knots in T, in LDS for the per-point brackets
+    __shared__ T knl[MAXKNOTS];
+    if (knots) {
+        if (tid < a.knots.nk) knl[tid] = T(a.knots.k[tid]);   // nk <= MAXKNOTS <= NT
+        __syncthreads();
+    }
 
     cpx<T> x[PER];
 #pragma unroll
@@ -435,7 +441,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
                     T t;
                     bool inside;
                     const T y2 = y * y;
-                    knot_bracket_kf(T(KF_C) * rho * (y2 * y2), a.knots, jj[q][c], t, inside);
+                    knot_bracket_tab(T(KF_C) * rho * (y2 * y2), a.knots.nk, a.knots.log_spacing,
+                                     a.knots.inv_span, knl, jj[q][c], t, inside);
                     uu[c] = rho * y;
                     ww[c] = t;
                     zz[c] = T(0);
@@ -458,7 +465,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
             if (knots) {
                 T t;
                 bool inside;
-                knot_bracket_kf(kf_from_log2(lu), a.knots, jj[q][c], t, inside);
+                knot_bracket_tab(kf_from_log2(lu), a.knots.nk, a.knots.log_spacing,
+                                 a.knots.inv_span, knl, jj[q][c], t, inside);
                 uu[c] = d_exp2(T(a.alpha) * lu);
                 ww[c] = t;
                 zz[c] = T(0);
@@ -1299,6 +1307,7 @@ template <int MODE, int CF> constexpr int row_inv_minw()
 {
     return MODE != EP_KNOTS ? 1 : ROW_KNOTS_MINW;
 }
+static_assert(MAXKNOTS <= NT, "the knot tables are filled by one load per thread");
 template <typename T, int M, int CF, int MODE>
 __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowInvArgs a, Geom g)
 {
