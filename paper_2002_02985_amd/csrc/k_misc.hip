@@ -38,20 +38,58 @@ hipError_t launch_finalize(const double *part, int pstride, const SlotCounts &co
 }
 
 // ---------------------------------------------------------------- knot range
+// One pass over each density for its smallest and largest rho: 16-byte
+// loads, KR_U of them in flight per thread (when N is a multiple of the
+// vector width, so that every density starts aligned), the extremes taken in
+// the field type (exact) and widened once.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+constexpr int KR_U = 4;
 template <typename T>
 __global__ __launch_bounds__(NT) void k_knot_range_part(long long N, const T *in, int in_is_phi,
                                                         double *part)
 {
+    using V = typename Vec16<T>::type;
+    constexpr int VN = Vec16<T>::n;
     __shared__ double red[2 * NT / 64];
     const int b = blockIdx.y, tid = threadIdx.x;
     const T *x = in + (long long)b * N;
-    double lo = 1e300, hi = -1e300;
-    for (long long i = (long long)blockIdx.x * NT + tid; i < N; i += (long long)gridDim.x * NT) {
-        const T v = x[i];
+    T tlo = __builtin_huge_valf(), thi = -__builtin_huge_valf();
+    auto upd = [&](T v) {
         const T rho = in_is_phi ? v * v : (v > T(0) ? v : T(0));
-        lo = fmin(lo, (double)rho);
-        hi = fmax(hi, (double)rho);
+        tlo = fmin(tlo, rho);
+        thi = fmax(thi, rho);
+    };
+    const long long stride = (long long)gridDim.x * NT;
+    const long long nv = N % VN == 0 ? N / VN : 0;
+    const V *xv = (const V *)x;
+    long long i = (long long)blockIdx.x * NT + tid;
+    for (; i + (KR_U - 1) * stride < nv; i += KR_U * stride) {
+        V a[KR_U];
+#pragma unroll
+        for (int u = 0; u < KR_U; ++u) a[u] = xv[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < KR_U; ++u) {
+            const T *e = (const T *)&a[u];
+#pragma unroll
+            for (int c = 0; c < VN; ++c) upd(e[c]);
+        }
     }
+    for (; i < nv; i += stride) {
+        const V a = xv[i];
+        const T *e = (const T *)&a;
+#pragma unroll
+        for (int c = 0; c < VN; ++c) upd(e[c]);
+    }
+    for (long long k = nv * VN + (long long)blockIdx.x * NT + tid; k < N; k += stride) upd(x[k]);
+    double lo = fmin(1e300, (double)tlo), hi = fmax(-1e300, (double)thi);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, off, 64));
@@ -85,11 +123,12 @@ __device__ int knot_bracket_of_rho(T rho, const Knots &kn)
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_knot_range_final(const double *part, Knots kn, int *kneed)
+__global__ __launch_bounds__(64) void k_knot_range_final(const double *part, int nblk, Knots kn,
+                                                         int *kneed)
 {
     const int b = blockIdx.x, tid = threadIdx.x;
     double lo = 1e300, hi = -1e300;
-    for (int i = tid; i < KR_BLOCKS; i += 64) {
+    for (int i = tid; i < nblk; i += 64) {
         lo = fmin(lo, part[((long long)b * 2) * KR_BLOCKS + i]);
         hi = fmax(hi, part[((long long)b * 2 + 1) * KR_BLOCKS + i]);
     }
@@ -117,9 +156,13 @@ template <typename T>
 hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
                              const Knots &kn, double *part, int *kneed, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_knot_range_part<T>), dim3(KR_BLOCKS, nbatch), dim3(NT), 0, s, N,
+    // blocks: one KR_U-vector sweep each, at most KR_BLOCKS
+    const long long per = (long long)NT * Vec16<T>::n * KR_U;
+    const int nblk = (int)std::max(1LL, std::min((long long)KR_BLOCKS, (N + per - 1) / per));
+    hipLaunchKernelGGL((k_knot_range_part<T>), dim3(nblk, nbatch), dim3(NT), 0, s, N,
                        (const T *)in, in_is_phi, part);
-    hipLaunchKernelGGL((k_knot_range_final<T>), dim3(nbatch), dim3(64), 0, s, part, kn, kneed);
+    hipLaunchKernelGGL((k_knot_range_final<T>), dim3(nbatch), dim3(64), 0, s, part, nblk, kn,
+                       kneed);
     return hipGetLastError();
 }
 template hipError_t launch_knot_range<float>(long long, int, const void *, int, const Knots &,

@@ -228,7 +228,7 @@ hipError_t launch_gtab(const Geom &g, double kf_wt, const NlKern &kern, void *gt
 // rho to the bracket cannot drop a knot).  Knots outside the range add exact
 // zeros, so the spline kernels skip them.  part: nbatch x 2 x KR_BLOCKS
 // doubles of scratch.
-constexpr int KR_BLOCKS = 512;
+constexpr int KR_BLOCKS = 2048;
 template <typename T>
 hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
                              const Knots &kn, double *part, int *kneed, hipStream_t s);
