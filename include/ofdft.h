@@ -490,7 +490,9 @@ void ofdft_server_destroy(ofdft_server *srv);
  * column passes, the number of densities a column block serves (one, or a
  * group of up to 8 sharing the tile's set-up and operands; batches of
  * nbatch > 1 on short columns), the number of spline knots per batch, the
- * knot pipeline (below) -- on nbatch densities
+ * knot pipeline (below) -- and then, on the fastest of those, the launch
+ * shapes the reciprocal-space column pass offers for the axis-0 length
+ * (ofdft_grid_set_col_variant) -- on nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
  * density, nbatch 1), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
@@ -500,7 +502,8 @@ typedef struct {
     double best_ms, default_ms;   /* per evaluation call */
     int32_t pipe;                 /* the grid's sub-batch split (not tuned) */
     int32_t col_group;            /* densities per column block (1 or up to 8) */
-    int32_t knot_pipe, reserved;  /* knot pipeline on (1) or off */
+    int32_t knot_pipe;            /* knot pipeline on (1) or off */
+    int32_t col_variant;          /* reciprocal-space column pass shape (0..3) */
 } ofdft_tune_result;
 ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
 /* Spline knot range (step s1 on the device; on by default): before the knot
@@ -524,6 +527,16 @@ ofdft_status ofdft_grid_set_col_group(ofdft_grid *grid, int32_t n);
  * (forked from it and joined back; not used while per-pass timing is on or
  * with a sub-batch split).  Results are the same, bit for bit, either way. */
 ofdft_status ofdft_grid_set_knot_pipeline(ofdft_grid *grid, int32_t on);
+/* Launch shape of the reciprocal-space column pass (the autotuner's choice,
+ * set by hand): bit 0 half the columns per block (twice the blocks), bit 1
+ * the transform's radices in reverse order (another Stockham factorisation
+ * of the same DFT).  Offered for FP32 passes of lengths 64, 96, 128, 192 and
+ * 256 where the shape differs from the default (ofdft_tune_result's
+ * col_variant reports what was kept); other lengths, FP64 passes and
+ * multi-cell batches use the default shape whatever is set.  Results agree
+ * with the default shape to the precision's rounding (the radix order
+ * changes the order of the butterflies' sums).  OFDFT_EINVAL outside 0..3. */
+ofdft_status ofdft_grid_set_col_variant(ofdft_grid *grid, int32_t variant);
 ofdft_status ofdft_grid_set_pipeline(ofdft_grid *grid, int32_t nsub);
 ofdft_status ofdft_grid_tune_dev(ofdft_grid *grid, int32_t nbatch, const void *d_rho,
                                  void *hip_stream, ofdft_tune_result *result);

@@ -176,6 +176,7 @@ struct ofdft_grid {
     int tune_kb = MAXKB;           // knots per spline batch
     int tune_pipe = 1;             // sub-batches pipelined over two streams
     int tune_col_group = COL_GROUP;   // densities per column block (batches)
+    int tune_col_variant = 0;         // reciprocal-space column pass shape (col_variants)
     // second stream of the pipelined evaluation and its events (created on
     // first use)
     hipStream_t s2 = nullptr;
@@ -519,8 +520,10 @@ static int max_pstride(const Geom &G, bool fp64)
         c0 = col_blocks<double>(G.n0, (long long)G.n1 * G.n2h);
         c1 = col_blocks<double>(G.n1, (long long)G.n0 * G.n2h);
     } else {
+        // the narrow-tile variant of the axis-0 pass (where offered) has the most blocks
         rb = row_blocks<float>(G);
-        c0 = col_blocks<float>(G.n0, (long long)G.n1 * G.n2h);
+        c0 = std::max(col_blocks<float>(G.n0, (long long)G.n1 * G.n2h),
+                      col_blocks<float>(G.n0, (long long)G.n1 * G.n2h, 1));
         c1 = col_blocks<float>(G.n1, (long long)G.n0 * G.n2h);
     }
     return std::max({rb, c0, c1, dots_blocks(G.N), G.n0, 1});
@@ -687,7 +690,8 @@ static Layout layout_of(const ofdft_grid *g)
 template <typename T>
 static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data, int nfb, int nbatch,
                              int inv, const int *ops, int kind, double *part = nullptr,
-                             const void *tw = nullptr, const int *kneed = nullptr, int knot0 = 0)
+                             const void *tw = nullptr, const int *kneed = nullptr, int knot0 = 0,
+                             int *nblocks = nullptr)
 {
     const Geom &G = g->geom;
     ColArgs a;
@@ -704,6 +708,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     a.gtab = g->gtab;
     a.tile_major = g->tune_col_tile_major;
     a.nbb = g->tune_col_group;
+    a.variant = g->tune_col_variant;
     a.use_h = (g->func.terms & OFDFT_TERM_HARTREE) ? 1 : 0;
     a.use_ext = (g->func.terms & OFDFT_TERM_EXT) ? 1 : 0;
     a.lambda_vw = g->func.lambda_vw;
@@ -733,6 +738,7 @@ static ofdft_status col_pass(ofdft_grid *g, hipStream_t s, int axis, void *data,
     }
     int nbk = 0;
     TIMED(kind, launch_col<T>(L, nfb, a, nbk, s));
+    if (nblocks) *nblocks = nbk;
     return OFDFT_OK;
 }
 
@@ -829,7 +835,8 @@ static ofdft_status vw_leg(ofdft_grid *g, int nb, const void *d_in, int in_is_ph
     TIMED(PS_VW64, launch_row_fwd<double>(G, nb, rf, nbr, s));
     ST_TRY(col_pass<double>(g, s, 1, w.vwspec, nb, nb, 0, nullptr, PS_VW64, w.part, g->tw1d));
     const int ops[4] = {GO_VW, 0, 0, 0};
-    ST_TRY(col_pass<double>(g, s, 0, w.vwspec, nb, nb, 0, ops, PS_VW64, w.part, g->tw0d));
+    ST_TRY(col_pass<double>(g, s, 0, w.vwspec, nb, nb, 0, ops, PS_VW64, w.part, g->tw0d, nullptr,
+                            0, &nb_vw));
     ST_TRY(col_pass<double>(g, s, 1, w.vwspec, nb, nb, 1, nullptr, PS_VW64, w.part, g->tw1d));
     RowInvArgs ri;
     std::memset(&ri, 0, sizeof(ri));
@@ -846,7 +853,6 @@ static ofdft_status vw_leg(ofdft_grid *g, int nb, const void *d_in, int in_is_ph
     ri.fld_hext = ri.fld_vw = ri.fld_wt = ri.fld_a = -1;
     int nbi = 0;
     TIMED(PS_VW64, launch_row_inv<double>(G, ri, nbi, s));
-    nb_vw = col_blocks<double>(G.n0, (long long)G.n1 * G.n2h);
     return OFDFT_OK;
 }
 
@@ -907,8 +913,8 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
         if (l.s_rho >= 0) ops[l.s_rho] = GO_HEXT;
         if (l.s_phi >= 0) ops[l.s_phi] = GO_VW;
         if (l.s_rhob >= 0) ops[l.s_rhob] = spline ? GO_SCALE : GO_WT;
-        ST_TRY(col_pass<T>(g, s, 0, spec, l.nfwd * nb, nb, 0, ops, PS_COL0_G, w.part));
-        nb_col0 = col_blocks<T>(G.n0, (long long)G.n1 * G.n2h);
+        ST_TRY(col_pass<T>(g, s, 0, spec, l.nfwd * nb, nb, 0, ops, PS_COL0_G, w.part, nullptr,
+                           nullptr, 0, &nb_col0));
     }
 
     // spline loop over knot batches (steps s2-s4)
@@ -2325,14 +2331,17 @@ static ofdft_status interpolate_density(ofdft_grid *dst, ofdft_grid *src)
 }
 
 // ================================================================ autotuner
-// The launch schedule of an evaluation has three free choices: the fused
-// plane kernels or separate row and column passes (where the plane fits in
-// LDS), the block order of the column passes, and the number of spline knots
-// per batch.  The tuner times every combination on the caller's batch and
-// keeps the fastest; results are shared by all grids of the same shape,
-// precision, functional and batch size in the process.
+// The launch schedule of an evaluation has free choices: the fused plane
+// kernels or separate row and column passes (where the plane fits in LDS),
+// the block order of the column passes, densities per column block, the
+// number of spline knots per batch and the knot pipeline.  The tuner times
+// every combination on the caller's batch, then, on the fastest, the shapes
+// the reciprocal-space column pass offers for its length (half the columns
+// per block, the reversed radix order, both), and keeps the fastest; results
+// are shared by all grids of the same shape, precision, functional and batch
+// size in the process.
 struct TuneVal {
-    int plane, tile_major, kb, pipe, cgrp, kpipe;
+    int plane, tile_major, kb, pipe, cgrp, kpipe, cvar;
 };
 using TuneKey = std::tuple<int, int, int, int, uint32_t, int, int, int>;
 static std::mutex g_tune_mu;
@@ -2356,6 +2365,7 @@ static void tune_apply_cached(ofdft_grid *g, int nb)
     g->tune_pipe = it->second.pipe;
     g->tune_col_group = it->second.cgrp;
     g->tune_knot_pipe = it->second.kpipe;
+    g->tune_col_variant = it->second.cvar;
     graphs_clear(g);
 }
 
@@ -2381,17 +2391,20 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
                             cand.push_back({pl, tm, kb, g->tune_pipe, cg, kp});
     }
     std::vector<ofdft_energy> e((size_t)nb);
-    double best = 1e300, dflt = 0.0;
-    TuneVal pick = cand[0];
-    for (size_t c = 0; c < cand.size(); ++c) {
-        g->tune_plane = cand[c].plane;
-        g->tune_col_tile_major = cand[c].tile_major;
-        g->tune_kb = cand[c].kb;
-        g->tune_pipe = cand[c].pipe;
-        g->tune_col_group = cand[c].cgrp;
-        g->tune_knot_pipe = cand[c].kpipe;
+    auto apply = [&](const TuneVal &c) {
+        g->tune_plane = c.plane;
+        g->tune_col_tile_major = c.tile_major;
+        g->tune_kb = c.kb;
+        g->tune_pipe = c.pipe;
+        g->tune_col_group = c.cgrp;
+        g->tune_knot_pipe = c.kpipe;
+        g->tune_col_variant = c.cvar;
         graphs_clear(g);
-        ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));   // warm-up
+    };
+    // median of three timed calls after one warm-up
+    auto time_of = [&](const TuneVal &c, double &ms) -> ofdft_status {
+        apply(c);
+        ST_TRY(eval_dispatch(g, nb, d_in, 0, nullptr, nullptr, s, e.data()));
         double t[3];
         for (double &x : t) {
             const auto t0 = std::chrono::steady_clock::now();
@@ -2399,19 +2412,37 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
             x = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
         std::sort(t, t + 3);
-        if (c == 0) dflt = t[1];
-        if (t[1] < best) {
-            best = t[1];
+        ms = t[1];
+        return OFDFT_OK;
+    };
+    double best = 1e300, dflt = 0.0;
+    TuneVal pick = cand[0];
+    for (size_t c = 0; c < cand.size(); ++c) {
+        double ms;
+        ST_TRY(time_of(cand[c], ms));
+        if (c == 0) dflt = ms;
+        if (ms < best) {
+            best = ms;
             pick = cand[c];
         }
     }
-    g->tune_plane = pick.plane;
-    g->tune_col_tile_major = pick.tile_major;
-    g->tune_kb = pick.kb;
-    g->tune_pipe = pick.pipe;
-    g->tune_col_group = pick.cgrp;
-    g->tune_knot_pipe = pick.kpipe;
-    graphs_clear(g);
+    // the column pass's shapes, on the fastest schedule
+    const int vm = g->fp64 ? col_variants<double>(g->geom.n0) : col_variants<float>(g->geom.n0);
+    int ncand = (int)cand.size();
+    const TuneVal base = pick;
+    for (int v = 1; v <= 3; ++v) {
+        if ((v & vm) != v) continue;
+        TuneVal c = base;
+        c.cvar = v;
+        double ms;
+        ST_TRY(time_of(c, ms));
+        ++ncand;
+        if (ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    apply(pick);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[tune_key(g, nb)] = pick;
@@ -2420,12 +2451,13 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         out->plane = pick.plane;
         out->col_tile_major = pick.tile_major;
         out->knot_batch = pick.kb;
-        out->candidates = (int32_t)cand.size();
+        out->candidates = (int32_t)ncand;
         out->best_ms = best;
         out->default_ms = dflt;
         out->pipe = pick.pipe;
         out->col_group = pick.cgrp;
         out->knot_pipe = pick.kpipe;
+        out->col_variant = pick.cvar;
     }
     return OFDFT_OK;
 }
@@ -3503,6 +3535,15 @@ ofdft_status ofdft_grid_set_col_group(ofdft_grid *grid, int32_t n)
     if (n < 1 || n > COL_GROUP) return fail(OFDFT_EINVAL, "column group outside 1..8");
     if (n != grid->tune_col_group) graphs_clear(grid);
     grid->tune_col_group = n;
+    return OFDFT_OK;
+}
+
+ofdft_status ofdft_grid_set_col_variant(ofdft_grid *grid, int32_t variant)
+{
+    if (!grid) return fail(OFDFT_EINVAL, "null grid");
+    if (variant < 0 || variant > 3) return fail(OFDFT_EINVAL, "column variant outside 0..3");
+    if (variant != grid->tune_col_variant) graphs_clear(grid);
+    grid->tune_col_variant = variant;
     return OFDFT_OK;
 }
 

@@ -106,6 +106,29 @@ constexpr Plan make_plan(int L, bool r16 = false)
     return p;
 }
 
+// Plan variants, a choice of the autotuner: 0 is make_plan's order, 1 the
+// same radices in reverse order (another Stockham factorisation of the same
+// transform: different twiddle strides and LDS access patterns).
+constexpr Plan plan_variant(int L, bool r16, int pv)
+{
+    Plan p = make_plan(L, r16);
+    if (pv == 1)
+        for (int i = 0; i < p.n / 2; ++i) {
+            const int t = p.r[i];
+            p.r[i] = p.r[p.n - 1 - i];
+            p.r[p.n - 1 - i] = t;
+        }
+    return p;
+}
+// whether variant 1 differs from variant 0
+constexpr bool plan_reversible(int L, bool r16)
+{
+    const Plan a = plan_variant(L, r16, 0), b = plan_variant(L, r16, 1);
+    for (int i = 0; i < a.n; ++i)
+        if (a.r[i] != b.r[i]) return true;
+    return false;
+}
+
 constexpr bool plan_ok(int L)
 {
     // only lengths made of 2s and 3s
@@ -422,76 +445,78 @@ __device__ __forceinline__ void stockham_stage_dst(const cpx<T> *buf, const cpx<
     lds_sync();
 }
 
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS, int PV = 0>
 __device__ __forceinline__ void fft_stages(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
-    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    constexpr Plan pl = plan_variant(L, sizeof(T) == 4, PV);
     if constexpr (S < pl.n) {
         constexpr int R = pl.r[S];
         stockham_stage<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid);
-        fft_stages<T, L, INV, P, NT, ES, PS, S + 1, NS * R>(buf, tw, tid);
+        fft_stages<T, L, INV, P, NT, ES, PS, S + 1, NS * R, PV>(buf, tw, tid);
     }
 }
 
 // Transform P pencils of length L held in LDS (buf[n * ES + p * PS]), in
 // place.  Caller must lds_sync() after filling buf; returns after a
 // barrier.
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS = 1>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS = 1, int PV = 0>
 __device__ __forceinline__ void lds_fft(cpx<T> *buf, const cpx<T> *tw, int tid)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
-    fft_stages<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid);
+    fft_stages<T, L, INV, P, NT, ES, PS, 0, 1, PV>(buf, tw, tid);
 }
 
 // As lds_fft, with the first stage reading element n of pencil p from
 // src(n, p) instead of buf (which need not be filled: the call starts with a
 // barrier so that earlier readers of buf are done).  Returns after a barrier.
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class SRC>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int PV = 0, class SRC>
 __device__ __forceinline__ void lds_fft_src(cpx<T> *buf, const cpx<T> *tw, int tid, const SRC &src)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
-    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    constexpr Plan pl = plan_variant(L, sizeof(T) == 4, PV);
     lds_sync();
     stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
-    fft_stages<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid);
+    fft_stages<T, L, INV, P, NT, ES, PS, 1, pl.r[0], PV>(buf, tw, tid);
 }
 
 // As lds_fft, with the outputs of the last stage handed to dst(n, p, value)
 // instead of being written back to buf.  Returns after a barrier.
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS, class DST>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int S, int NS, int PV = 0,
+          class DST>
 __device__ __forceinline__ void fft_stages_dst(cpx<T> *buf, const cpx<T> *tw, int tid, const DST &dst)
 {
-    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    constexpr Plan pl = plan_variant(L, sizeof(T) == 4, PV);
     constexpr int R = pl.r[S];
     if constexpr (S + 1 < pl.n) {
         stockham_stage<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid);
-        fft_stages_dst<T, L, INV, P, NT, ES, PS, S + 1, NS * R>(buf, tw, tid, dst);
+        fft_stages_dst<T, L, INV, P, NT, ES, PS, S + 1, NS * R, PV>(buf, tw, tid, dst);
     } else {
         stockham_stage_dst<T, L, R, NS, INV, P, NT, ES, PS>(buf, tw, tid, dst);
     }
 }
 
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class DST>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int PV = 0, class DST>
 __device__ __forceinline__ void lds_fft_dst(cpx<T> *buf, const cpx<T> *tw, int tid, const DST &dst)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
-    fft_stages_dst<T, L, INV, P, NT, ES, PS, 0, 1>(buf, tw, tid, dst);
+    fft_stages_dst<T, L, INV, P, NT, ES, PS, 0, 1, PV>(buf, tw, tid, dst);
 }
 
 // As lds_fft with both ends outside buf: the first stage reads src(n, p),
 // the last stage hands its outputs to dst(n, p, value) (a single-stage
 // transform writes buf and then hands every element to dst).  Starts and
 // returns with a barrier.
-template <typename T, int L, bool INV, int P, int NT, int ES, int PS, class SRC, class DST>
+template <typename T, int L, bool INV, int P, int NT, int ES, int PS, int PV = 0, class SRC,
+          class DST>
 __device__ __forceinline__ void lds_fft_io(cpx<T> *buf, const cpx<T> *tw, int tid, const SRC &src,
                                            const DST &dst)
 {
     static_assert(plan_ok(L), "FFT length must be 2^a 3^b");
-    constexpr Plan pl = make_plan(L, sizeof(T) == 4);
+    constexpr Plan pl = plan_variant(L, sizeof(T) == 4, PV);
     lds_sync();
     stockham_stage_src<T, L, pl.r[0], INV, P, NT, ES, PS>(buf, tid, src);
     if constexpr (pl.n >= 2) {
-        fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0]>(buf, tw, tid, dst);
+        fft_stages_dst<T, L, INV, P, NT, ES, PS, 1, pl.r[0], PV>(buf, tw, tid, dst);
     } else {
         for (unsigned o = (unsigned)tid; o < (unsigned)(L * P); o += NT) {
             const unsigned n = o / (unsigned)P, p = o % (unsigned)P;

@@ -131,6 +131,9 @@ struct ColArgs {
                                 // b-vectors, v_ext and tables (null: g, vext, gtab)
     int nbb;                    // densities per block: requested (at most
                                 // COL_GROUP; 0 or 1 = one), then as launched
+    int variant;                // reciprocal-space passes of lengths with variants
+                                // (col_variants): bit 0 half the columns per block,
+                                // bit 1 the radix order reversed; others ignore it
 };
 
 // axis-0 spline kernels: per-knot inverse of omega_i rho^b(G), and the EXACT
@@ -212,7 +215,10 @@ template <typename T> hipError_t launch_row_inv(const Geom &g, const RowInvArgs 
 // it; hipErrorNotSupported for the others (the caller runs the general one)
 template <typename T> hipError_t launch_row_combine_fixed(const Geom &g, const RowInvArgs &a, int &nblocks, hipStream_t s);
 template <typename T> int row_blocks(const Geom &g);
-template <typename T> int col_blocks(int L, long long ncols);
+template <typename T> int col_blocks(int L, long long ncols, int variant = 0);
+// the column-pass variants a length offers (bit 0 narrow tile, bit 1 reversed
+// radix order; 0 for none), an autotuner choice
+template <typename T> int col_variants(int L);
 
 // reciprocal-space tables of a grid: 1/G^2 (0 at G = 0), G^2 and the
 // nonlocal kernel C_WT K(|G|/(2 kf)) on the half spectrum, built in FP64

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(RowFwdArgs a, Geom g)
 // one tile of every (field, density) array, which keeps the tile's share of
 // the reciprocal-space tables in L2).
 // MC: a multi-cell batch (per-entry reciprocal vectors and tables from a.ct)
-template <typename T, int L, int P, bool MC = false, bool GRP = false>
+template <typename T, int L, int P, bool MC = false, bool GRP = false, int PV = 0>
 __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb, int ntiles)
 {
     constexpr int NT = col_NT<T, L, P>();   // this kernel's block size
@@ -588,8 +588,9 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
     // a column past the end reads column 0 and writes nothing
     const unsigned cofs = cvalid ? cbase : 0u;
     const unsigned es = (unsigned)a.elem_stride;
-    // the wide-tile instantiation (P != col_P) serves plain passes only
-    constexpr bool OPS = P == col_P<T, L>();
+    // the wide-tile instantiation (P > col_P) serves plain passes only; the
+    // default and the narrow (autotuner variant) tiles carry the operations
+    constexpr bool OPS = P <= col_P<T, L>();
     Geom g = a.g;
     const void *vext_b = a.vext, *gtab_b = a.gtab;
     if constexpr (MC) {
@@ -669,15 +670,15 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
         if (!OPS || op == GO_NONE) {
             if constexpr (MULTI) {
                 // starts and ends with a barrier
-                if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1>(buf, tw, tl, ld, st);
-                else lds_fft_io<T, L, false, P, NT, P, 1>(buf, tw, tl, ld, st);
+                if (a.inv) lds_fft_io<T, L, true, P, NT, P, 1, PV>(buf, tw, tl, ld, st);
+                else lds_fft_io<T, L, false, P, NT, P, 1, PV>(buf, tw, tl, ld, st);
                 continue;
             } else {
                 lds_sync();
                 for (int n = tl / P; n < L; n += RSTEP) buf[n * P + pl] = ld(n, pl);
                 lds_sync();
-                if (a.inv) lds_fft<T, L, true, P, NT, P>(buf, tw, tl);
-                else lds_fft<T, L, false, P, NT, P>(buf, tw, tl);
+                if (a.inv) lds_fft<T, L, true, P, NT, P, 1, PV>(buf, tw, tl);
+                else lds_fft<T, L, false, P, NT, P, 1, PV>(buf, tw, tl);
             }
         } else if constexpr (OPS) {
             // v_ext(G) of the Hartree+ion field, fetched now so that its
@@ -693,7 +694,7 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
                 }
             }
             // axis 0: element n is i0, column c is (i1, k2)
-            lds_fft_src<T, L, false, P, NT, P, 1>(buf, tw, tl, ld);
+            lds_fft_src<T, L, false, P, NT, P, 1, PV>(buf, tw, tl, ld);
             const int t = opaque(tl);
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -737,7 +738,7 @@ __global__ __launch_bounds__((col_NT<T, L, P>())) void k_col(ColArgs a, int nfb,
             }
             lds_sync();
             if (op != GO_SCALE) {
-                lds_fft_dst<T, L, true, P, NT, P, 1>(buf, tw, tl, st);   // ends with a barrier
+                lds_fft_dst<T, L, true, P, NT, P, 1, PV>(buf, tw, tl, st);   // ends with a barrier
                 continue;
             }
         }
@@ -2379,6 +2380,68 @@ hipError_t row_combine_fixed_go(const Geom &g, const RowInvArgs &a, int &nblocks
     }
 }
 
+// Column lengths whose reciprocal-space passes offer the autotuner two more
+// launch shapes (FP32): half the columns per block (more, smaller blocks)
+// and the reversed radix order (plan_variant).
+template <typename T, int L> constexpr int col_variant_mask()
+{
+    if constexpr (sizeof(T) != 4 || !(L == 64 || L == 96 || L == 128 || L == 192 || L == 256)) {
+        return 0;
+    } else {
+        int m = 0;
+        if (col_P<T, L>() / 2 >= 4) m |= 1;
+        if (plan_reversible(L, true)) m |= 2;
+        return m;
+    }
+}
+template <typename T, int L> constexpr int col_tile_of(int variant)
+{
+    return (variant & col_variant_mask<T, L>() & 1) ? col_P<T, L>() / 2 : col_P<T, L>();
+}
+
+// the reciprocal-space (non-plain) column pass with tile P and plan variant PV
+template <typename T, int L, int P, int PV>
+hipError_t col_go_tile(int nfb, const ColArgs &a, bool plain, bool has_part, int &nblocks,
+                       hipStream_t s)
+{
+    nblocks = (int)((a.ncols + P - 1) / P);
+    if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
+    // a block takes a tile of the same field for COL_GROUP densities where
+    // that still leaves at least COL_MIN_BLOCKS blocks (not for multi-cell
+    // batches, whose densities have tables of their own)
+    constexpr bool grp_ok = L * P / col_NT<T, L, P>() <= 8;
+    ColArgs ag = a;
+    ag.nbb = 1;
+    const int nfields = nfb / (a.nbatch > 0 ? a.nbatch : 1);
+    if constexpr (grp_ok && col_grouped<T, L>()) {
+        if (!a.ct && !plain && a.nbatch > 1 && a.nbb > 1) {
+            const int want = a.nbb < COL_GROUP ? a.nbb : COL_GROUP;
+            int nbb = want < a.nbatch ? want : a.nbatch;
+            while (nbb > 1 &&
+                   (long long)nblocks * nfields * ((a.nbatch + nbb - 1) / nbb) < COL_MIN_BLOCKS)
+                nbb /= 2;
+            ag.nbb = nbb;
+        }
+    }
+    const int nfg = nfields * ((a.nbatch + ag.nbb - 1) / ag.nbb);
+    const long long total = (long long)nblocks * nfg;
+    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total), block(col_NT<T, L, P>());
+    if (a.ct && !plain) {
+        if constexpr (PV == 0 && P == col_P<T, L>())
+            hipLaunchKernelGGL((k_col<T, L, P, true>), grid, block, 0, s, ag, nfg, nblocks);
+        else
+            return hipErrorInvalidValue;   // multi-cell batches take the default shape
+    } else if (ag.nbb > 1) {
+        if constexpr (grp_ok && col_grouped<T, L>())
+            hipLaunchKernelGGL((k_col<T, L, P, false, true, PV>), grid, block, 0, s, ag, nfg,
+                               nblocks);
+    } else {
+        hipLaunchKernelGGL((k_col<T, L, P, false, false, PV>), grid, block, 0, s, ag, nfg, nblocks);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int L>
 hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
 {
@@ -2400,36 +2463,17 @@ hipError_t col_go(int nfb, const ColArgs &a, int &nblocks, hipStream_t s)
             return hipGetLastError();
         }
     }
-    nblocks = (int)((a.ncols + P - 1) / P);
-    if (has_part && nblocks > a.pstride) return hipErrorInvalidValue;
-    // a block takes a tile of the same field for COL_GROUP densities where
-    // that still leaves at least COL_MIN_BLOCKS blocks (not for multi-cell
-    // batches, whose densities have tables of their own)
-    ColArgs ag = a;
-    ag.nbb = 1;
-    const int nfields = nfb / (a.nbatch > 0 ? a.nbatch : 1);
-    if constexpr (col_grouped<T, L>()) {
-        if (!a.ct && !plain && a.nbatch > 1 && a.nbb > 1) {
-            const int want = a.nbb < COL_GROUP ? a.nbb : COL_GROUP;
-            int nbb = want < a.nbatch ? want : a.nbatch;
-            while (nbb > 1 &&
-                   (long long)nblocks * nfields * ((a.nbatch + nbb - 1) / nbb) < COL_MIN_BLOCKS)
-                nbb /= 2;
-            ag.nbb = nbb;
-        }
+    constexpr int VM = col_variant_mask<T, L>();
+    if constexpr (VM != 0) {
+        const int v = (plain || a.ct) ? 0 : (a.variant & VM);
+        if constexpr ((VM & 1) != 0)
+            if (v == 1) return col_go_tile<T, L, P / 2, 0>(nfb, a, plain, has_part, nblocks, s);
+        if constexpr ((VM & 2) != 0)
+            if (v == 2) return col_go_tile<T, L, P, 1>(nfb, a, plain, has_part, nblocks, s);
+        if constexpr (VM == 3)
+            if (v == 3) return col_go_tile<T, L, P / 2, 1>(nfb, a, plain, has_part, nblocks, s);
     }
-    const int nfg = nfields * ((a.nbatch + ag.nbb - 1) / ag.nbb);
-    const long long total = (long long)nblocks * nfg;
-    if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)total), block(col_NT<T, L, P>());
-    if (a.ct && !plain)
-        hipLaunchKernelGGL((k_col<T, L, P, true>), grid, block, 0, s, ag, nfg, nblocks);
-    else if (ag.nbb > 1) {
-        if constexpr (col_grouped<T, L>())
-            hipLaunchKernelGGL((k_col<T, L, P, false, true>), grid, block, 0, s, ag, nfg, nblocks);
-    } else
-        hipLaunchKernelGGL((k_col<T, L, P>), grid, block, 0, s, ag, nfg, nblocks);
-    return hipGetLastError();
+    return col_go_tile<T, L, P, 0>(nfb, a, plain, has_part, nblocks, s);
 }
 
 template <typename T, int L>
@@ -2517,10 +2561,17 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
         default: return hipErrorInvalidValue;                                                  \
         }                                                                                      \
     }                                                                                          \
-    template <> int col_blocks<T>(int L, long long ncols)                                      \
+    template <> int col_blocks<T>(int L, long long ncols, int variant)                         \
     {                                                                                          \
         switch (L) {                                                                           \
             OFDFT_LENGTHS(OFDFT_CASE_CB_##T)                                                   \
+        default: return 0;                                                                     \
+        }                                                                                      \
+    }                                                                                          \
+    template <> int col_variants<T>(int L)                                                     \
+    {                                                                                          \
+        switch (L) {                                                                           \
+            OFDFT_LENGTHS(OFDFT_CASE_CV_##T)                                                   \
         default: return 0;                                                                     \
         }                                                                                      \
     }
@@ -2539,7 +2590,9 @@ hipError_t knot_acc_go(const KnotArgs &a, hipStream_t s)
 #define OFDFT_CASE_KA_double(L) case L: return knot_acc_go<double, L>(a, s);
 #define OFDFT_CASE_RB_float(L) case L: return (int)(((long long)g.n0 * g.n1 + row_P<float, L>() - 1) / row_P<float, L>());
 #define OFDFT_CASE_RB_double(L) case L: return (int)(((long long)g.n0 * g.n1 + row_P<double, L>() - 1) / row_P<double, L>());
-#define OFDFT_CASE_CB_float(L) case L: return (int)((ncols + col_P<float, L>() - 1) / col_P<float, L>());
-#define OFDFT_CASE_CB_double(L) case L: return (int)((ncols + col_P<double, L>() - 1) / col_P<double, L>());
+#define OFDFT_CASE_CB_float(L) case L: return (int)((ncols + col_tile_of<float, L>(variant) - 1) / col_tile_of<float, L>(variant));
+#define OFDFT_CASE_CB_double(L) case L: return (int)((ncols + col_tile_of<double, L>(variant) - 1) / col_tile_of<double, L>(variant));
+#define OFDFT_CASE_CV_float(L) case L: return col_variant_mask<float, L>();
+#define OFDFT_CASE_CV_double(L) case L: return col_variant_mask<double, L>();
 
 }  // namespace ofdft

@@ -88,7 +88,7 @@ class TuneResult(ctypes.Structure):
                 ("knot_batch", ctypes.c_int32), ("candidates", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
                 ("pipe", ctypes.c_int32), ("col_group", ctypes.c_int32),
-                ("knot_pipe", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("knot_pipe", ctypes.c_int32), ("col_variant", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -165,6 +165,7 @@ _SIGS = {
                                           ctypes.POINTER(TdStats)]),
     "ofdft_grid_set_knot_skip": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_col_group": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "ofdft_grid_set_col_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_knot_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_set_pipeline": (ctypes.c_int, [_P, ctypes.c_int32]),
     "ofdft_grid_tune_dev": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.POINTER(TuneResult)]),
@@ -508,6 +509,10 @@ def ofdft_grid_set_knot_skip(grid, on=True):
 
 def ofdft_grid_set_col_group(grid, n):
     check(load().ofdft_grid_set_col_group(grid, int(n)))
+
+
+def ofdft_grid_set_col_variant(grid, variant):
+    check(load().ofdft_grid_set_col_variant(grid, int(variant)))
 
 
 def ofdft_grid_set_knot_pipeline(grid, on=True):

@@ -223,3 +223,60 @@ def test_vacuum_cluster_potential(cluster13, prec):
     with ofdft.Grid(cell, LOCAL, precision=prec) as g:
         e, v = g.energy_potential(rho)
     check(e.as_dict(), v, ro, rho, len(cell["species"]), prec, 1e-6, "cluster13")
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_c2_96cubed_column_variants_against_oracle(c2_96, variant):
+    """The autotuner's column-pass shapes (half the columns per block, the
+    reversed radix order 8 x 12, both) on the benchmark's 96^3 WT batch in
+    MIXED: every energy term and v against the oracle, as the default shape."""
+    cell, dens, terms, refs = c2_96
+    print("case c2 96^3 column variant", variant, flush=True)
+    nb = len(dens)
+    with ofdft.Grid(cell, terms, precision=ofdft.MIXED) as g:
+        ofdft.ofdft_grid_set_col_variant(g.handle, variant)
+        x = dev_tensor(np.stack(dens), torch_dtype(g))
+        v = torch.zeros_like(x)
+        es = ofdft.ofdft_energy_potential_batch_dev(g.handle, nb, x.data_ptr(), v.data_ptr(),
+                                                    stream_handle())
+        vv = v.cpu().double().numpy()
+    for b, ro in refs.items():
+        check(es[b].as_dict(), vv[b], ro, dens[b], len(cell["species"]), ofdft.MIXED, 0.0,
+              "c2 variant %d density %d" % (variant, b))
+
+
+@pytest.mark.parametrize("n0", [64, 128, 192, 256])
+def test_column_variants_on_longer_columns(n0):
+    """Axis-0 lengths with column-pass variants (64 and 256: the narrow tile;
+    128 and 192: also the reversed radix order 8 x 16, 12 x 16): a batch of
+    two densities in every shape, each against the oracle."""
+    rng = np.random.default_rng(n0)
+    L = np.array([0.25 * n0, 14.0, 15.0])
+    cell = {"lattice": np.diag(L), "n": (n0, 48, 54), "pos": rng.uniform(0, 1, (4, 3)) * L,
+            "species": np.zeros(4, np.int32), "Z": np.array([3.0]), "rc": np.array([1.0]),
+            "nelec": 0.03 * float(np.prod(L))}
+    dens = [smooth_density(make_cell(cell), seed=n0 + k, amp=0.9, nmodes=3, rho0=0.03)
+            for k in range(2)]
+    terms = LOCAL | ofdft.TERM_WT
+    refs = [OF.energy_potential(make_cell(cell), OC.Functional(terms=int(terms)), rho=d)
+            for d in dens]
+    for variant in (0, 1, 2, 3):
+        print("case column variant n0", n0, "variant", variant, flush=True)
+        with ofdft.Grid(cell, terms, precision=ofdft.MIXED) as g:
+            ofdft.ofdft_grid_set_col_variant(g.handle, variant)
+            x = dev_tensor(np.stack(dens), torch_dtype(g))
+            v = torch.zeros_like(x)
+            es = ofdft.ofdft_energy_potential_batch_dev(g.handle, 2, x.data_ptr(), v.data_ptr(),
+                                                        stream_handle())
+            vv = v.cpu().double().numpy()
+        for b in range(2):
+            check(es[b].as_dict(), vv[b], refs[b], dens[b], 4, ofdft.MIXED, 0.0,
+                  "n0 %d variant %d density %d" % (n0, variant, b))
+
+
+def test_set_col_variant_rejects_out_of_range():
+    cell = thin_box((16, 16, 16))
+    with ofdft.Grid(cell, ofdft.TERM_TF, precision=ofdft.MIXED) as g:
+        for bad in (-1, 4):
+            with pytest.raises(ofdft.OfdftError):
+                ofdft.ofdft_grid_set_col_variant(g.handle, bad)
