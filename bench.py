@@ -1087,10 +1087,15 @@ def main():
     plane = mixed["tuning"] is None or mixed["tuning"]["plane"]
     # kernel names as rocprofv3 prints them: the combine is the fixed term set
     # TF + vW + Hartree/ion + WT (15), epilogue mode 1; the column pass runs
-    # 16-column tiles, grouped (8 densities per block) unless the schedule
-    # serves one density per block
-    grouped = mixed["tuning"] is None or mixed["tuning"].get("col_group", 8) > 1
-    kcol = "k_col<float, 96, 16, false, %s>" % ("true" if grouped else "false")
+    # 16-column tiles (8 with the narrow shape), grouped (8 densities per
+    # block) unless the schedule serves one density per block, with the
+    # default (0) or reversed (1) radix order
+    tun = mixed["tuning"] or {}
+    grouped = tun.get("col_group", 8) > 1
+    cvar = tun.get("col_variant", 0)
+    kcol = "k_col<float, 96, %d, false, %s, %d>" % (8 if cvar & 1 else 16,
+                                                   "true" if grouped else "false",
+                                                   1 if cvar & 2 else 0)
     kname = ({"row_fwd": "k_plane_fwd<float, 96, 48>",
               "row_inv": "k_plane_inv<float, 96, 48, 1, 15>",
               "col0_g": kcol} if plane else

@@ -2426,10 +2426,15 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
             pick = cand[c];
         }
     }
-    // the column pass's shapes, on the fastest schedule
+    // the column pass's shapes, on the fastest schedule; a shape replaces
+    // the default one only if it is faster by TUNE_SHAPE_MARGIN (short
+    // calls time within a few percent of each other, and a shape picked on
+    // noise alone measured slower under concurrent streams)
+    constexpr double TUNE_SHAPE_MARGIN = 0.97;
     const int vm = g->fp64 ? col_variants<double>(g->geom.n0) : col_variants<float>(g->geom.n0);
     int ncand = (int)cand.size();
     const TuneVal base = pick;
+    const double base_ms = best;
     for (int v = 1; v <= 3; ++v) {
         if ((v & vm) != v) continue;
         TuneVal c = base;
@@ -2437,7 +2442,7 @@ static ofdft_status tune_impl(ofdft_grid *g, int nb, const void *d_in, hipStream
         double ms;
         ST_TRY(time_of(c, ms));
         ++ncand;
-        if (ms < best) {
+        if (ms < best && ms < base_ms * TUNE_SHAPE_MARGIN) {
             best = ms;
             pick = c;
         }
