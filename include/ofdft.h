@@ -494,7 +494,8 @@ void ofdft_server_destroy(ofdft_server *srv);
  * shapes the reciprocal-space column pass offers for the axis-0 length
  * (ofdft_grid_set_col_variant) -- on nbatch densities
  * at d_rho (device, the grid's field type; ofdft_grid_tune: the resident
- * density, nbatch 1), keeps the fastest for the grid and for every grid of
+ * density, nbatch 1; a column-pass shape is kept only if it times at least
+ * 3% faster than the default one), keeps the fastest for the grid and for every grid of
  * the same shape, precision, functional and batch size created later in the
  * process, and reports it. */
 typedef struct {
