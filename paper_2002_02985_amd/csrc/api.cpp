@@ -156,6 +156,8 @@ struct ofdft_grid {
     int *kneed = nullptr;        // cap * 2: each density's knot range (spline)
     bool knot_skip = true;       // spline passes skip knots outside the range
     void *stage_in = nullptr, *stage_out = nullptr;   // cap * N (host API staging)
+    float *pin_in = nullptr, *pin_out = nullptr;      // N floats each, pinned host memory:
+                                                      // the FP32 host API's converted fields
     double *part = nullptr;
     int pstride = 0;
     double *sums = nullptr;
@@ -1406,6 +1408,9 @@ static void grid_free(ofdft_grid *g)
     dfree(g->acc2);
     dfree(g->stage_in);
     dfree(g->stage_out);
+    if (g->pin_in) (void)hipHostFree(g->pin_in);
+    if (g->pin_out) (void)hipHostFree(g->pin_out);
+    g->pin_in = g->pin_out = nullptr;
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
     dfree(reinterpret_cast<void *&>(g->d_forces));
@@ -1870,13 +1875,28 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
 // checked by the evaluation's own prologue; for FP32 fields the conversion
 // loop checks the FP64 values it visits anyway (a negative value too small
 // for FP32 would otherwise arrive as -0 and pass)
+// Host fields of an FP32 grid are converted in pinned host memory (one
+// buffer of N floats per direction, allocated at first use and kept with the
+// grid; DMA straight from and to it), other sizes through a pageable vector.
+static float *host_stage(ofdft_grid *g, float *&pin, size_t n, std::vector<float> &fallback)
+{
+    if (n == (size_t)g->geom.N) {
+        if (!pin && hipHostMalloc((void **)&pin, n * sizeof(float), hipHostMallocDefault) != hipSuccess)
+            pin = nullptr;
+        if (pin) return pin;
+    }
+    fallback.resize(n);
+    return fallback.data();
+}
+
 static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, size_t n, hipStream_t s,
                                  bool check_density = false)
 {
     if (g->fp64) {
         HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, s));
     } else {
-        std::vector<float> f(n);
+        std::vector<float> fb;
+        float *f = host_stage(g, g->pin_in, n, fb);
         size_t bad = 0;
         for (size_t i = 0; i < n; ++i) {
             const double x = src[i];
@@ -1886,8 +1906,7 @@ static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, si
         if (bad)
             return fail(OFDFT_EINVAL, "input density has " + std::to_string(bad) +
                                           " non-finite or negative values");
-        HIP_TRY(hipMemcpyAsync(dst, f.data(), n * 4, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpyAsync(dst, f, n * 4, hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     return OFDFT_OK;
@@ -1899,8 +1918,9 @@ static ofdft_status download_field(ofdft_grid *g, double *dst, const void *src, 
         HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
     } else {
-        std::vector<float> f(n);
-        HIP_TRY(hipMemcpyAsync(f.data(), src, n * 4, hipMemcpyDeviceToHost, s));
+        std::vector<float> fb;
+        float *f = host_stage(g, g->pin_out, n, fb);
+        HIP_TRY(hipMemcpyAsync(f, src, n * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (size_t i = 0; i < n; ++i) dst[i] = f[i];
     }
