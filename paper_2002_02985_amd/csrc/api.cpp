@@ -156,8 +156,6 @@ struct ofdft_grid {
     int *kneed = nullptr;        // cap * 2: each density's knot range (spline)
     bool knot_skip = true;       // spline passes skip knots outside the range
     void *stage_in = nullptr, *stage_out = nullptr;   // cap * N (host API staging)
-    float *pin_in = nullptr, *pin_out = nullptr;      // N floats each, pinned host memory:
-                                                      // the FP32 host API's converted fields
     double *part = nullptr;
     int pstride = 0;
     double *sums = nullptr;
@@ -1408,9 +1406,6 @@ static void grid_free(ofdft_grid *g)
     dfree(g->acc2);
     dfree(g->stage_in);
     dfree(g->stage_out);
-    if (g->pin_in) (void)hipHostFree(g->pin_in);
-    if (g->pin_out) (void)hipHostFree(g->pin_out);
-    g->pin_in = g->pin_out = nullptr;
     dfree(reinterpret_cast<void *&>(g->part));
     dfree(reinterpret_cast<void *&>(g->sums));
     dfree(reinterpret_cast<void *&>(g->d_forces));
@@ -1875,15 +1870,33 @@ static ofdft_status grid_setup(ofdft_grid *g, const ofdft_cell_desc *c, const of
 // checked by the evaluation's own prologue; for FP32 fields the conversion
 // loop checks the FP64 values it visits anyway (a negative value too small
 // for FP32 would otherwise arrive as -0 and pass)
-// Host fields of an FP32 grid are converted in pinned host memory (one
-// buffer of N floats per direction, allocated at first use and kept with the
-// grid; DMA straight from and to it), other sizes through a pageable vector.
-static float *host_stage(ofdft_grid *g, float *&pin, size_t n, std::vector<float> &fallback)
+// Host fields of an FP32 grid are converted in pinned host memory and copied
+// by DMA from and to it: one buffer per direction and calling thread, grown
+// to a power of two as larger fields come (at most PIN_MAX floats; larger
+// fields go through a pageable vector) and kept for the thread's life, so
+// that grids built and dropped by a serving worker reuse its buffers.
+constexpr size_t PIN_MAX = size_t(1) << 24;
+struct PinStage {
+    float *buf[2] = {nullptr, nullptr};
+    size_t cap[2] = {0, 0};
+};
+static thread_local PinStage t_pin;
+static float *host_stage(int dir, size_t n, std::vector<float> &fallback)
 {
-    if (n == (size_t)g->geom.N) {
-        if (!pin && hipHostMalloc((void **)&pin, n * sizeof(float), hipHostMallocDefault) != hipSuccess)
-            pin = nullptr;
-        if (pin) return pin;
+    if (n <= PIN_MAX) {
+        if (t_pin.cap[dir] < n) {
+            if (t_pin.buf[dir]) (void)hipHostFree(t_pin.buf[dir]);
+            t_pin.buf[dir] = nullptr;
+            t_pin.cap[dir] = 0;
+            size_t c = 1;
+            while (c < n) c <<= 1;
+            void *p = nullptr;
+            if (hipHostMalloc(&p, c * sizeof(float), hipHostMallocDefault) == hipSuccess) {
+                t_pin.buf[dir] = (float *)p;
+                t_pin.cap[dir] = c;
+            }
+        }
+        if (t_pin.buf[dir]) return t_pin.buf[dir];
     }
     fallback.resize(n);
     return fallback.data();
@@ -1896,7 +1909,7 @@ static ofdft_status upload_field(ofdft_grid *g, void *dst, const double *src, si
         HIP_TRY(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, s));
     } else {
         std::vector<float> fb;
-        float *f = host_stage(g, g->pin_in, n, fb);
+        float *f = host_stage(0, n, fb);
         size_t bad = 0;
         for (size_t i = 0; i < n; ++i) {
             const double x = src[i];
@@ -1919,7 +1932,7 @@ static ofdft_status download_field(ofdft_grid *g, double *dst, const void *src, 
         HIP_TRY(hipStreamSynchronize(s));
     } else {
         std::vector<float> fb;
-        float *f = host_stage(g, g->pin_out, n, fb);
+        float *f = host_stage(1, n, fb);
         HIP_TRY(hipMemcpyAsync(f, src, n * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (size_t i = 0; i < n; ++i) dst[i] = f[i];
