@@ -123,6 +123,9 @@ def parse():
                     help="add the LDA exchange-correlation term to the functional")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 256 MiB first (counter calibration)")
+    ap.add_argument("--counter-shapes", action="store_true",
+                    help="after the timed steps, two untimed steps with one density per "
+                         "column block (counter runs: that schedule's column kernel too)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary from rocprofv3 counter CSVs and exit")
     ap.add_argument("--counter-command", default="",
@@ -209,7 +212,7 @@ def pass_bytes(name, nb, N, Nh, nfields, w):
 
 
 def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, tune=True,
-                  xc=False, keep_v=0):
+                  xc=False, keep_v=0, extra_shapes=False):
     terms = (ofdft.TERM_TF | ofdft.TERM_VW | ofdft.TERM_HARTREE | ofdft.TERM_EXT |
              ofdft.TERM_WT | (ofdft.TERM_XC if xc else 0))
     dt = torch.float64 if precision == ofdft.FP64 else torch.float32
@@ -251,6 +254,13 @@ def run_gpu_batch(ofdft, torch, cell, dens, precision, steps, warmup, profile, t
             if n:
                 passes[name] = (ms, n)
         ofdft.ofdft_profile_enable(g.handle, False)
+    if extra_shapes:
+        # untimed: two steps with one density per column block, so that a
+        # counter run also records the column kernel of that schedule
+        ofdft.ofdft_grid_set_col_group(g.handle, 1)
+        for _ in range(2):
+            ofdft.ofdft_energy_potential_batch_dev(g.handle, NDENS, x.data_ptr(), v.data_ptr(), sh)
+        torch.cuda.synchronize()
     energies = np.array([e.e_total for e in es])
     v_kept = v[:keep_v].double().cpu().numpy() if keep_v else None
     dev_bytes = ofdft.ofdft_grid_device_bytes(g.handle)
@@ -1063,7 +1073,7 @@ def main():
     log("mixed path: %d warmup + %d timed steps" % (args.warmup, args.steps))
     keep = 0 if args.no_cpu else args.cpu_sample
     mixed = run_gpu_batch(ofdft, torch, cell, dens, ofdft.MIXED, args.steps, args.warmup, True,
-                          not args.no_tune, args.xc, keep_v=keep)
+                          not args.no_tune, args.xc, keep_v=keep, extra_shapes=args.counter_shapes)
     fp64 = None
     if not args.no_fp64:
         log("fp64 path")
