@@ -152,7 +152,7 @@ struct ofdft_grid {
     int batch_cap = 0;
     uint64_t multi_bytes = 0;
     const CellTab *cur_ct = nullptr;
-    double *kr_part = nullptr;   // cap * 2 * KR_BLOCKS: knot-range partials (spline)
+    double *kr_part = nullptr;   // cap * KR_SLOTS * KR_BLOCKS: knot-range partials (spline)
     int *kneed = nullptr;        // cap * 2: each density's knot range (spline)
     bool knot_skip = true;       // spline passes skip knots outside the range
     void *stage_in = nullptr, *stage_out = nullptr;   // cap * N (host API staging)
@@ -577,7 +577,7 @@ static uint64_t bytes_model(const Geom &G, size_t fsz, int natoms, int nspecies,
             b += (uint64_t)MAXKB * cap * Nh * cb;                       // second knot buffer
         b += cap * N * fsz;                                             // accumulator
         if (nl_mode == OFDFT_NL_EXACT) b += cap * N * fsz;
-        b += cap * (2 * (uint64_t)KR_BLOCKS * 8 + 2 * 4);               // knot range
+        b += cap * (KR_SLOTS * (uint64_t)KR_BLOCKS * 8 + 2 * 4);        // knot range
     }
     b += cap * NSLOT * (uint64_t)pstride_of(G, fsz == 8, m.vw64) * 8 + cap * NSLOT * 8;   // partials
     if (m.vw64) {
@@ -610,7 +610,7 @@ static uint64_t workspace_bytes(const ofdft_grid *g, int nb)
         if (knot_pipe_fits(g->knots.nk, (uint64_t)MAXKB * nb * G.Nh * cbytes))
             b += (uint64_t)MAXKB * nb * G.Nh * cbytes;
         if (g->func.nl_mode == OFDFT_NL_EXACT) b += (uint64_t)nb * G.N * g->fsz;
-        b += (uint64_t)nb * 2 * KR_BLOCKS * sizeof(double) + (uint64_t)nb * 2 * sizeof(int);
+        b += (uint64_t)nb * KR_SLOTS * KR_BLOCKS * sizeof(double) + (uint64_t)nb * 2 * sizeof(int);
     }
     if (g->vw64) b += (uint64_t)nb * G.Nh * 16 + (uint64_t)nb * G.N * 4;
     b += (uint64_t)nb * NSLOT * pstride_of(G, g->fp64, g->vw64) * sizeof(double);
@@ -651,7 +651,7 @@ static ofdft_status reserve(ofdft_grid *g, int nb)
         if (g->func.nl_mode == OFDFT_NL_EXACT)
             ST_TRY(dmalloc(g, &g->acc2, (size_t)nb * G.N * g->fsz));
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->kr_part),
-                       (size_t)nb * 2 * KR_BLOCKS * sizeof(double)));
+                       (size_t)nb * KR_SLOTS * KR_BLOCKS * sizeof(double)));
         ST_TRY(dmalloc(g, reinterpret_cast<void **>(&g->kneed), (size_t)nb * 2 * sizeof(int)));
     }
     if (g->vw64) {
@@ -796,7 +796,7 @@ static Work work_of(const ofdft_grid *g, int b0)
     w.acc2 = g->acc2 ? (char *)g->acc2 + (size_t)b0 * G.N * sizeof(T) : nullptr;
     w.vwspec = g->vwspec ? (char *)g->vwspec + (size_t)b0 * G.Nh * 16 : nullptr;
     w.vwout = g->vwout ? (char *)g->vwout + (size_t)b0 * G.N * 4 : nullptr;
-    w.kr_part = g->kr_part ? g->kr_part + (size_t)b0 * 2 * KR_BLOCKS : nullptr;
+    w.kr_part = g->kr_part ? g->kr_part + (size_t)b0 * KR_SLOTS * KR_BLOCKS : nullptr;
     w.kneed = g->kneed ? g->kneed + (size_t)b0 * 2 : nullptr;
     w.part = g->part + (size_t)b0 * NSLOT * g->pstride;
     w.sums = g->sums + (size_t)b0 * NSLOT;
@@ -925,7 +925,8 @@ static ofdft_status eval_enqueue(ofdft_grid *g, int nb, const void *d_in, int in
         // non-zero hat somewhere; the knot passes skip the others
         const int *kneed = nullptr;
         if (g->knot_skip && nk > 1) {
-            TIMED(PS_KNOT_INV, launch_knot_range<T>(G.N, nb, d_in, in_is_phi, g->knots, w.kr_part,
+            TIMED(PS_KNOT_INV, launch_knot_range<T>(G.N, nb, d_in, in_is_phi, g->knots, !exact,
+                                                    w.kr_part,
                                                     w.kneed, s));
             kneed = w.kneed;
         }
@@ -3072,7 +3073,7 @@ static size_t scratch_work(const ofdft_grid *g, char *base, Work &w)
         w.kspec = take((size_t)MAXKB * G.Nh * cb);
         w.acc1 = take((size_t)G.N * sizeof(T));
         if (g->func.nl_mode == OFDFT_NL_EXACT) w.acc2 = take((size_t)G.N * sizeof(T));
-        w.kr_part = (double *)take((size_t)2 * KR_BLOCKS * sizeof(double));
+        w.kr_part = (double *)take((size_t)KR_SLOTS * KR_BLOCKS * sizeof(double));
         w.kneed = (int *)take((size_t)2 * sizeof(int));
     }
     if (g->vw64) {

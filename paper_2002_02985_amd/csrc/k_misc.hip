@@ -52,20 +52,39 @@ template <> struct Vec16<double> {
     static constexpr int n = 2;
 };
 constexpr int KR_U = 4;
-template <typename T>
+// With BR (the S3S4 interpolation's knots), each point's bracket is also
+// taken exactly as the interpolation takes it (rho -> log2 -> k_F -> knot
+// segment, knots in T from LDS), and its smallest and largest reduced.
+template <typename T, bool BR>
 __global__ __launch_bounds__(NT) void k_knot_range_part(long long N, const T *in, int in_is_phi,
-                                                        double *part)
+                                                        Knots kn, double *part)
 {
     using V = typename Vec16<T>::type;
     constexpr int VN = Vec16<T>::n;
-    __shared__ double red[2 * NT / 64];
+    __shared__ double red[4 * NT / 64];
+    __shared__ T knl[BR ? MAXKNOTS : 1];
     const int b = blockIdx.y, tid = threadIdx.x;
     const T *x = in + (long long)b * N;
+    if constexpr (BR) {
+        if (tid < kn.nk) knl[tid] = T(kn.k[tid]);   // nk <= MAXKNOTS <= NT
+        __syncthreads();
+    }
     T tlo = __builtin_huge_valf(), thi = -__builtin_huge_valf();
+    int jlo = 1 << 30, jhi = -1;
     auto upd = [&](T v) {
         const T rho = in_is_phi ? v * v : (v > T(0) ? v : T(0));
         tlo = fmin(tlo, rho);
         thi = fmax(thi, rho);
+        if constexpr (BR) {
+            const T lu = rho > T(0) ? d_log2(rho) : neg_inf<T>();
+            int j;
+            T t;
+            bool inside;
+            knot_bracket_tab(kf_from_log2(lu), kn.nk, kn.log_spacing, kn.inv_span, knl, j, t,
+                             inside);
+            jlo = j < jlo ? j : jlo;
+            jhi = j > jhi ? j : jhi;
+        }
     };
     const long long stride = (long long)gridDim.x * NT;
     const long long nv = N % VN == 0 ? N / VN : 0;
@@ -90,24 +109,33 @@ __global__ __launch_bounds__(NT) void k_knot_range_part(long long N, const T *in
     }
     for (long long k = nv * VN + (long long)blockIdx.x * NT + tid; k < N; k += stride) upd(x[k]);
     double lo = fmin(1e300, (double)tlo), hi = fmax(-1e300, (double)thi);
+    double dj0 = (double)jlo, dj1 = (double)jhi;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, off, 64));
         hi = fmax(hi, __shfl_xor(hi, off, 64));
+        dj0 = fmin(dj0, __shfl_xor(dj0, off, 64));
+        dj1 = fmax(dj1, __shfl_xor(dj1, off, 64));
     }
     constexpr int NW = NT / 64;
     if ((tid & 63) == 0) {
         red[tid >> 6] = lo;
         red[NW + (tid >> 6)] = hi;
+        red[2 * NW + (tid >> 6)] = dj0;
+        red[3 * NW + (tid >> 6)] = dj1;
     }
     __syncthreads();
     if (tid == 0) {
         for (int w = 1; w < NW; ++w) {
             lo = fmin(lo, red[w]);
             hi = fmax(hi, red[NW + w]);
+            dj0 = fmin(dj0, red[2 * NW + w]);
+            dj1 = fmax(dj1, red[3 * NW + w]);
         }
-        part[((long long)b * 2) * KR_BLOCKS + blockIdx.x] = lo;
-        part[((long long)b * 2 + 1) * KR_BLOCKS + blockIdx.x] = hi;
+        part[((long long)b * KR_SLOTS) * KR_BLOCKS + blockIdx.x] = lo;
+        part[((long long)b * KR_SLOTS + 1) * KR_BLOCKS + blockIdx.x] = hi;
+        part[((long long)b * KR_SLOTS + 2) * KR_BLOCKS + blockIdx.x] = dj0;
+        part[((long long)b * KR_SLOTS + 3) * KR_BLOCKS + blockIdx.x] = dj1;
     }
 }
 
@@ -124,28 +152,41 @@ __device__ int knot_bracket_of_rho(T rho, const Knots &kn)
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_knot_range_final(const double *part, int nblk, Knots kn,
-                                                         int *kneed)
+                                                         int exact_brackets, int *kneed)
 {
     const int b = blockIdx.x, tid = threadIdx.x;
-    double lo = 1e300, hi = -1e300;
+    double lo = 1e300, hi = -1e300, dj0 = 1e300, dj1 = -1e300;
     for (int i = tid; i < nblk; i += 64) {
-        lo = fmin(lo, part[((long long)b * 2) * KR_BLOCKS + i]);
-        hi = fmax(hi, part[((long long)b * 2 + 1) * KR_BLOCKS + i]);
+        lo = fmin(lo, part[((long long)b * KR_SLOTS) * KR_BLOCKS + i]);
+        hi = fmax(hi, part[((long long)b * KR_SLOTS + 1) * KR_BLOCKS + i]);
+        dj0 = fmin(dj0, part[((long long)b * KR_SLOTS + 2) * KR_BLOCKS + i]);
+        dj1 = fmax(dj1, part[((long long)b * KR_SLOTS + 3) * KR_BLOCKS + i]);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, off, 64));
         hi = fmax(hi, __shfl_xor(hi, off, 64));
+        dj0 = fmin(dj0, __shfl_xor(dj0, off, 64));
+        dj1 = fmax(dj1, __shfl_xor(dj1, off, 64));
     }
     if (tid == 0) {
         int k0 = 0, k1 = kn.nk - 1;
         if (kn.nk > 1 && lo <= hi) {
-            // the extremes are values of the field type, bracketed as the grid
-            // points are; knots j .. j + 1 of each bracket, one more each side
-            const int jl = knot_bracket_of_rho<T>(T(lo), kn);
-            const int jh = knot_bracket_of_rho<T>(T(hi), kn);
-            k0 = jl - 1 < 0 ? 0 : jl - 1;
-            k1 = jh + 2 > kn.nk - 1 ? kn.nk - 1 : jh + 2;
+            if (exact_brackets) {
+                // every point's bracket j: its hat functions are knots j, j + 1
+                const int jl = (int)dj0, jh = (int)dj1;
+                k0 = jl;
+                k1 = jh + 1 > kn.nk - 1 ? kn.nk - 1 : jh + 1;
+            } else {
+                // the extremes are values of the field type, bracketed as the
+                // grid points are; knots j .. j + 1 of each bracket, one more
+                // each side (a pass that brackets by another formula, the FP64
+                // EXACT forward fields, may differ by one near a knot)
+                const int jl = knot_bracket_of_rho<T>(T(lo), kn);
+                const int jh = knot_bracket_of_rho<T>(T(hi), kn);
+                k0 = jl - 1 < 0 ? 0 : jl - 1;
+                k1 = jh + 2 > kn.nk - 1 ? kn.nk - 1 : jh + 2;
+            }
         }
         kneed[2 * b] = k0;
         kneed[2 * b + 1] = k1;
@@ -154,20 +195,25 @@ __global__ __launch_bounds__(64) void k_knot_range_final(const double *part, int
 
 template <typename T>
 hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
-                             const Knots &kn, double *part, int *kneed, hipStream_t s)
+                             const Knots &kn, int exact_brackets, double *part, int *kneed,
+                             hipStream_t s)
 {
     // blocks: one KR_U-vector sweep each, at most KR_BLOCKS
     const long long per = (long long)NT * Vec16<T>::n * KR_U;
     const int nblk = (int)std::max(1LL, std::min((long long)KR_BLOCKS, (N + per - 1) / per));
-    hipLaunchKernelGGL((k_knot_range_part<T>), dim3(nblk, nbatch), dim3(NT), 0, s, N,
-                       (const T *)in, in_is_phi, part);
+    if (exact_brackets)
+        hipLaunchKernelGGL((k_knot_range_part<T, true>), dim3(nblk, nbatch), dim3(NT), 0, s, N,
+                           (const T *)in, in_is_phi, kn, part);
+    else
+        hipLaunchKernelGGL((k_knot_range_part<T, false>), dim3(nblk, nbatch), dim3(NT), 0, s, N,
+                           (const T *)in, in_is_phi, kn, part);
     hipLaunchKernelGGL((k_knot_range_final<T>), dim3(nbatch), dim3(64), 0, s, part, nblk, kn,
-                       kneed);
+                       exact_brackets, kneed);
     return hipGetLastError();
 }
-template hipError_t launch_knot_range<float>(long long, int, const void *, int, const Knots &,
+template hipError_t launch_knot_range<float>(long long, int, const void *, int, const Knots &, int,
                                              double *, int *, hipStream_t);
-template hipError_t launch_knot_range<double>(long long, int, const void *, int, const Knots &,
+template hipError_t launch_knot_range<double>(long long, int, const void *, int, const Knots &, int,
                                               double *, int *, hipStream_t);
 
 // ---------------------------------------------------------------- G tables

@@ -228,16 +228,20 @@ hipError_t launch_gtab(const Geom &g, double kf_wt, const NlKern &kern, void *gt
 
 // Spline knot range of each density (step s1 on the device): the knots
 // whose hat functions can be non-zero at some grid point, kneed[2 b] = first
-// and kneed[2 b + 1] = last, from the smallest and largest rho of density b
-// (rho = in or in^2 for phi input) bracketed like every grid point and
-// widened by one knot on each side (so that rounding in the monotone map from
-// rho to the bracket cannot drop a knot).  Knots outside the range add exact
-// zeros, so the spline kernels skip them.  part: nbatch x 2 x KR_BLOCKS
-// doubles of scratch.
+// and kneed[2 b + 1] = last.  exact_brackets (the S3S4 interpolation, whose
+// passes all bracket a point the same way): every grid point's bracket j is
+// computed as the interpolation computes it and the range is [min j,
+// max j + 1].  Otherwise (EXACT, whose FP64 forward fields bracket through
+// another formula): the smallest and largest rho of density b (rho = in or
+// in^2 for phi input) bracketed like every grid point and widened by one knot
+// on each side.  Knots outside the range add exact zeros, so the spline
+// kernels skip them.  part: nbatch x KR_SLOTS x KR_BLOCKS doubles of scratch.
 constexpr int KR_BLOCKS = 2048;
+constexpr int KR_SLOTS = 4;
 template <typename T>
 hipError_t launch_knot_range(long long N, int nbatch, const void *in, int in_is_phi,
-                             const Knots &kn, double *part, int *kneed, hipStream_t s);
+                             const Knots &kn, int exact_brackets, double *part, int *kneed,
+                             hipStream_t s);
 
 // FP64 reductions: sums[b][s] = sum_{i < count.n[s]} part[b][s][i]; the
 // counts travel as a kernel argument (the launch sequence of an evaluation

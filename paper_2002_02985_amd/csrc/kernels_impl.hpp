@@ -1385,9 +1385,11 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
     // a knot batch entirely outside the density's knot range adds nothing;
     // the first batch that meets it initialises the accumulators
     bool acc_init = a.acc_init != 0;
+    int klo = 0, khi = 1 << 30;   // knots transformed for this density
     if constexpr (MODE == EP_KNOTS) {
         if (a.kneed) {
-            const int klo = a.kneed[2 * b], khi = a.kneed[2 * b + 1];
+            klo = a.kneed[2 * b];
+            khi = a.kneed[2 * b + 1];
             if (a.knot0 > khi || a.knot0 + a.nfields - 1 < klo) return;
             acc_init = a.knot0 <= klo;
         }
@@ -1480,10 +1482,13 @@ __global__ __launch_bounds__(NT, (row_inv_minw<MODE, CF>())) void k_row_inv(RowI
             if (!((need >> (f / KS)) & 1u)) continue;
             const int i = a.knot0 + f;
             const bool two = PAIR && f + 1 < a.nfields;
+            // a pass's partner knot outside the transformed range reads as
+            // zeros (its weight is zero at every point of this density)
+            const bool ina = i >= klo && i <= khi, inb = two && i + 1 >= klo && i + 1 <= khi;
             if constexpr (PAIR)
-                c2r_knot_rows<T, M, P, 2 * P, PS2, NCH>(buf, spec_of(f),
-                                                        two ? spec_of(f + 1) : nullptr, r0, nrows,
-                                                        g.n2h, twl, twl + M, tid);
+                c2r_knot_rows<T, M, P, 2 * P, PS2, NCH>(buf, ina ? spec_of(f) : nullptr,
+                                                        inb ? spec_of(f + 1) : nullptr, r0,
+                                                        nrows, g.n2h, twl, twl + M, tid);
             else
                 c2r_knot_rows<T, M, P, P, PS, NCH>(buf, spec_of(f), nullptr, r0, nrows, g.n2h,
                                                    twl, twl + M, tid);
