@@ -510,7 +510,9 @@ ofdft_status ofdft_grid_set_graphs(ofdft_grid *grid, int32_t on);
 /* Spline knot range (step s1 on the device; on by default): before the knot
  * loop, one pass over the input finds each density's smallest and largest
  * rho, and with them the knots whose hat functions are non-zero at some
- * point (one more on each side); the per-knot transforms and the
+ * point (S3S4: every point's bracket, taken as the interpolation takes it;
+ * EXACT: the extremes' brackets and one more knot on each side); the
+ * per-knot transforms and the
  * interpolation skip every other knot, whose contributions are exact zeros.
  * Off transforms every knot (the same results: a check of the skipping). */
 ofdft_status ofdft_grid_set_knot_skip(ofdft_grid *grid, int32_t on);
